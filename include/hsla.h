@@ -1,0 +1,173 @@
+/*
+ * hsla -- differentiable sparse Krylov solves on one MI355X (gfx950).
+ *
+ * C ABI of libhsla.so.  Plain pointers and sizes only.  Every `d_*`
+ * argument is a device pointer on the handle's device, owned by the caller
+ * (the library never frees it and keeps no reference past the call unless
+ * stated).  Host pointers are named without the prefix.  Device work is
+ * ordered after everything already enqueued on the `stream` argument (a
+ * hipStream_t passed as void*; NULL means the legacy default stream): the
+ * library runs it on a private stream of default priority that waits on an
+ * event recorded on `stream`, and every call returns only after its device
+ * work has completed, so outputs are valid for later work on any stream.
+ *
+ * Errors: every entry point returns hsla_status.  0 = success; > 0 =
+ * warning with valid output; < 0 = error, outputs undefined.  A message for
+ * the last error on a handle is available from hsla_last_error().  No C++
+ * exception crosses this boundary.  A handle is not thread-safe; patterns
+ * are immutable after creation and may be shared by handles on one device.
+ *
+ * The problem statement is the paper's x = A.solve(b) with A given by a
+ * sparsity pattern and values, differentiable in both the values and b
+ * (arXiv 2601.13994, Sec. "API" and the API listing of the appendix).
+ */
+#ifndef HSLA_H
+#define HSLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hsla_status {
+    HSLA_OK = 0,
+    HSLA_NOT_CONVERGED = 1, /* max_iter reached; x holds the last iterate       */
+    HSLA_BREAKDOWN = 2,     /* p^T A p <= 0 (CG) or a BiCGStab breakdown after
+                               its one restart; x holds the last iterate        */
+    HSLA_FELL_BACK = 3,     /* learned preconditioner rejected, Jacobi used     */
+    HSLA_ERR_INVALID_ARG = -1,
+    HSLA_ERR_INVALID_CSR = -2, /* pattern not canonical CSR (see hsla_pattern_create) */
+    HSLA_ERR_NONFINITE = -3,   /* NaN/Inf met in b, values or a recurrence      */
+    HSLA_ERR_HIP = -4,         /* HIP runtime error                              */
+    HSLA_ERR_NO_MEMORY = -5,
+    HSLA_ERR_ZERO_DIAGONAL = -6, /* Jacobi requested but a diagonal is missing or 0 */
+    HSLA_ERR_INTERNAL = -7
+} hsla_status;
+
+typedef enum hsla_method { HSLA_METHOD_AUTO = 0, HSLA_METHOD_CG = 1, HSLA_METHOD_BICGSTAB = 2 } hsla_method;
+typedef enum hsla_precond { HSLA_PRECOND_NONE = 0, HSLA_PRECOND_JACOBI = 1, HSLA_PRECOND_FSAI = 2 } hsla_precond;
+
+typedef struct hsla_handle hsla_handle;
+typedef struct hsla_pattern hsla_pattern;
+
+/* Solver options.  hsla_opts_default() fills the defaults noted here. */
+typedef struct hsla_opts {
+    int32_t method;      /* hsla_method; AUTO = CG if A equals A^T bit for bit, else BiCGStab */
+    int32_t precond;     /* hsla_precond; default JACOBI                                        */
+    double rtol;         /* stop when ||r_k||_2 <= max(rtol*||b||_2, atol); default 1e-8         */
+    double atol;         /* default 0                                                           */
+    int64_t max_iter;    /* <= 0: min(10 n, 100000)                                             */
+    int32_t check_every; /* iterations between host convergence checks; <= 0: automatic          */
+    int32_t use_x0;      /* 1: d_x holds the initial guess on input; default 0 (x0 = 0)          */
+    int32_t use_graph;   /* 1: replay iteration chunks as HIP graphs; default 1                  */
+    int32_t profile;     /* 1: time every SpMV(+dot) launch of the iteration with HIP events
+                            (graphs off); results in hsla_info.spmv_ms / spmv_launches          */
+    const float *d_G;    /* FSAI: G values on the lower pattern (float32, [B][nnz_L]); else NULL */
+    const float *d_GT;   /* FSAI: the same values in G^T's CSR order ([B][nnz_L])               */
+} hsla_opts;
+
+/* Per-system result information. */
+typedef struct hsla_info {
+    int64_t iters;        /* iterations run (one SpMV per CG iteration, two per BiCGStab)  */
+    int32_t status;       /* hsla_status of this system                                    */
+    int32_t method;       /* method actually used                                          */
+    double rel_residual;  /* recursive ||r_k|| / ||b|| (||r_k|| if b = 0)                   */
+    double true_residual; /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at the end         */
+    double spmv_ms;       /* profile mode: summed duration of the SpMV(+dot) launches that
+                             did work (all systems of a batch share one launch)            */
+    int64_t spmv_launches;/* profile mode: number of those launches                        */
+} hsla_info;
+
+void hsla_opts_default(hsla_opts *opts);
+const char *hsla_status_string(int status);
+
+/* ---------------------------------------------------------------- handle */
+/* Creates a handle bound to `device` (a HIP device ordinal).  The handle owns
+ * its workspace (grown on demand, released by hsla_destroy). */
+hsla_status hsla_create(hsla_handle **out, int device);
+void hsla_destroy(hsla_handle *h);
+const char *hsla_last_error(const hsla_handle *h);
+
+/* --------------------------------------------------------------- pattern */
+/* Validates and copies a CSR sparsity pattern (row_ptr int32[n+1], col
+ * int32[nnz], device memory) and derives the per-pattern data every solve
+ * reuses: diagonal positions, the transpose permutation, symmetry of the
+ * pattern, and the SpMV tile schedule.  Canonical CSR means: 0-based,
+ * row_ptr[0] = 0, row_ptr nondecreasing, row_ptr[n] = nnz, 0 <= col < n,
+ * columns strictly increasing within a row, nnz < 2^31.  Explicit zeros are
+ * legal; empty rows are legal for SpMV but a solve rejects a missing
+ * diagonal under Jacobi.  Returns HSLA_ERR_INVALID_CSR (with the first bad
+ * row in hsla_last_error) otherwise.  The caller's buffers are not retained. */
+hsla_status hsla_pattern_create(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *d_row_ptr,
+                                const int32_t *d_col, void *stream, hsla_pattern **out);
+void hsla_pattern_destroy(hsla_pattern *p);
+/* n, nnz, nnz of the lower triangle (incl. diagonal), and 1 if the pattern
+ * equals its transpose. */
+hsla_status hsla_pattern_info(const hsla_pattern *p, int32_t *n, int64_t *nnz, int64_t *nnz_lower,
+                              int32_t *pattern_symmetric);
+/* Device copies of the transpose: row_ptr_T int32[n+1], col_T int32[nnz] and
+ * src int32[nnz] with src[k'] = position in A of the entry stored at k' of
+ * A^T (a bijection).  Host-visible only through the copy. */
+hsla_status hsla_pattern_transpose(hsla_handle *h, const hsla_pattern *p, int32_t *d_row_ptr_T,
+                                   int32_t *d_col_T, int32_t *d_src, void *stream);
+
+/* ------------------------------------------------------------ operations */
+/* y = A x for B systems sharing the pattern: values [B][nnz], x and y
+ * [B][n] (Eq. forward_spmv with one process).  Each row sums its products
+ * in ascending column order. */
+hsla_status hsla_spmv(hsla_handle *h, const hsla_pattern *p, int32_t B, const double *d_values,
+                      const double *d_x, double *d_y, void *stream);
+
+/* Solves A x = b (the paper's A.solve(b)).  CG (Hestenes-Stiefel, the
+ * recurrence of the paper's Algorithm "Distributed CG" on one device) or
+ * right-preconditioned BiCGStab (van der Vorst), with Jacobi, FSAI
+ * (M^{-1} = G^T G) or no preconditioner.  All recurrences are FP64; only
+ * stored FSAI factors are float32.  `info` (host, may be NULL) receives one
+ * record.  Status is the system's status. */
+hsla_status hsla_solve(hsla_handle *h, const hsla_pattern *p, const double *d_values,
+                       const double *d_b, double *d_x, const hsla_opts *opts, hsla_info *info,
+                       void *stream);
+
+/* B independent systems on one pattern (values [B][nnz], b and x [B][n]),
+ * iterated in lock step with a per-system convergence mask: a system stops
+ * when its own test passes, and its result does not depend on the others.
+ * `infos` (host, may be NULL) receives B records.  Returns the worst status
+ * (an error < 0 if any system errs, else the largest warning). */
+hsla_status hsla_solve_batched(hsla_handle *h, const hsla_pattern *p, int32_t B,
+                               const double *d_values, const double *d_b, double *d_x,
+                               const hsla_opts *opts, hsla_info *infos, void *stream);
+
+/* Adjoint of the solve (Eq. adjoint_linear): solves A^T lambda = gx with the
+ * options' method/preconditioner/tolerance (relative to ||gx||), then
+ * gb = lambda (float64[n]) and gA[k] = -lambda[row(k)] * x[col(k)] for every
+ * stored entry k, in the pattern's entry order (float64[nnz]).  Either
+ * output may be NULL.  x must be the converged forward solution.  AUTO uses
+ * CG on A when A is symmetric, otherwise BiCGStab on A^T. */
+hsla_status hsla_adjoint(hsla_handle *h, const hsla_pattern *p, const double *d_values,
+                         const double *d_x, const double *d_gx, double *d_gA, double *d_gb,
+                         const hsla_opts *opts, hsla_info *info, void *stream);
+
+/* Batched adjoint over a shared pattern: values [B][nnz], x, gx, gb [B][n],
+ * gA [B][nnz]. */
+hsla_status hsla_adjoint_batched(hsla_handle *h, const hsla_pattern *p, int32_t B,
+                                 const double *d_values, const double *d_x, const double *d_gx,
+                                 double *d_gA, double *d_gb, const hsla_opts *opts,
+                                 hsla_info *infos, void *stream);
+
+/* The gradient assembly alone: gA[k] = -lambda[row(k)] * x[col(k)] for B
+ * systems ([B][n] inputs, [B][nnz] output). */
+hsla_status hsla_outer_on_pattern(hsla_handle *h, const hsla_pattern *p, int32_t B,
+                                  const double *d_lambda, const double *d_x, double *d_gA,
+                                  void *stream);
+
+/* ||b - A x||_2 and ||b||_2 per system (host outputs, B doubles each). */
+hsla_status hsla_residual_norms(hsla_handle *h, const hsla_pattern *p, int32_t B,
+                                const double *d_values, const double *d_b, const double *d_x,
+                                double *res_norm, double *b_norm, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSLA_H */

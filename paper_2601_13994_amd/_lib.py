@@ -1,0 +1,289 @@
+"""ctypes binding of libhsla.so (the C ABI declared in include/hsla.h).
+
+Argument marshalling only: torch tensors are checked for device, dtype and
+contiguity and passed as raw device pointers together with the current
+stream.  There is no fallback path: if the library is missing or no GPU is
+present, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhsla.so")
+
+OK, NOT_CONVERGED, BREAKDOWN, FELL_BACK = 0, 1, 2, 3
+ERR_INVALID_ARG, ERR_INVALID_CSR, ERR_NONFINITE, ERR_HIP = -1, -2, -3, -4
+ERR_NO_MEMORY, ERR_ZERO_DIAGONAL, ERR_INTERNAL = -5, -6, -7
+
+METHODS = {"auto": 0, "cg": 1, "bicgstab": 2}
+METHOD_NAMES = {v: k for k, v in METHODS.items()}
+PRECONDS = {"none": 0, "jacobi": 1, "fsai": 2}
+
+# every symbol include/hsla.h declares
+EXPORTS = [
+    "hsla_opts_default", "hsla_status_string", "hsla_create", "hsla_destroy", "hsla_last_error",
+    "hsla_pattern_create", "hsla_pattern_destroy", "hsla_pattern_info", "hsla_pattern_transpose",
+    "hsla_spmv", "hsla_solve", "hsla_solve_batched", "hsla_adjoint", "hsla_adjoint_batched",
+    "hsla_outer_on_pattern", "hsla_residual_norms",
+]
+
+
+class HslaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hsla status {status}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("method", ctypes.c_int32), ("precond", ctypes.c_int32),
+        ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+        ("max_iter", ctypes.c_int64), ("check_every", ctypes.c_int32),
+        ("use_x0", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32),
+        ("d_G", ctypes.c_void_p), ("d_GT", ctypes.c_void_p),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int64), ("status", ctypes.c_int32), ("method", ctypes.c_int32),
+        ("rel_residual", ctypes.c_double), ("true_residual", ctypes.c_double),
+        ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {"iters": self.iters, "status": self.status, "method": METHOD_NAMES.get(self.method, "?"),
+                "rel_residual": self.rel_residual, "true_residual": self.true_residual,
+                "spmv_ms": self.spmv_ms, "spmv_launches": self.spmv_launches}
+
+
+_lib = None
+_lock = threading.Lock()
+_handles: dict[int, ctypes.c_void_p] = {}
+
+
+def load() -> ctypes.CDLL:
+    """Loads libhsla.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2601_13994_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        P = ctypes.POINTER
+        L.hsla_opts_default.argtypes = [P(Opts)]
+        L.hsla_opts_default.restype = None
+        L.hsla_status_string.argtypes = [ctypes.c_int]
+        L.hsla_status_string.restype = ctypes.c_char_p
+        L.hsla_create.argtypes = [P(vp), ctypes.c_int]
+        L.hsla_destroy.argtypes = [vp]
+        L.hsla_destroy.restype = None
+        L.hsla_last_error.argtypes = [vp]
+        L.hsla_last_error.restype = ctypes.c_char_p
+        L.hsla_pattern_create.argtypes = [vp, i32, i64, vp, vp, vp, P(vp)]
+        L.hsla_pattern_destroy.argtypes = [vp]
+        L.hsla_pattern_destroy.restype = None
+        L.hsla_pattern_info.argtypes = [vp, P(i32), P(i64), P(i64), P(i32)]
+        L.hsla_pattern_transpose.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.hsla_spmv.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+        L.hsla_solve.argtypes = [vp, vp, vp, vp, vp, P(Opts), P(Info), vp]
+        L.hsla_solve_batched.argtypes = [vp, vp, i32, vp, vp, vp, P(Opts), P(Info), vp]
+        L.hsla_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, P(Opts), P(Info), vp]
+        L.hsla_adjoint_batched.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, P(Opts), P(Info), vp]
+        L.hsla_outer_on_pattern.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+        L.hsla_residual_norms.argtypes = [vp, vp, i32, vp, vp, vp, P(f64), P(f64), vp]
+        _lib = L
+    return _lib
+
+
+def status_string(st: int) -> str:
+    return load().hsla_status_string(st).decode()
+
+
+def handle(device: int | None = None) -> ctypes.c_void_p:
+    if not torch.cuda.is_available():
+        raise RuntimeError("hsla needs a ROCm GPU; none is visible")
+    dev = torch.cuda.current_device() if device is None else int(device)
+    h = _handles.get(dev)
+    if h is None:
+        L = load()
+        h = ctypes.c_void_p()
+        st = L.hsla_create(ctypes.byref(h), dev)
+        if st != 0:
+            raise HslaError(st, f"hsla_create(device={dev}) failed: {status_string(st)}")
+        _handles[dev] = h
+    return h
+
+
+def check(st: int, h, what: str, warn_ok: bool = True) -> int:
+    if st < 0 or (st > 0 and not warn_ok):
+        msg = load().hsla_last_error(h).decode() if h else ""
+        raise HslaError(st, f"{what}: {status_string(st)} {msg}")
+    return st
+
+
+def stream_ptr(device=None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def ptr(t: torch.Tensor | None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def need(t: torch.Tensor, dtype: torch.dtype, name: str, device: torch.device) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    return t.contiguous()
+
+
+def make_opts(method="auto", precond="jacobi", rtol=1e-8, atol=0.0, max_iter=0, check_every=0,
+              x0=False, graph=True, profile=False, G=None, GT=None) -> Opts:
+    o = Opts()
+    load().hsla_opts_default(ctypes.byref(o))
+    o.method = METHODS[method]
+    o.precond = PRECONDS[precond]
+    o.rtol = float(rtol)
+    o.atol = float(atol)
+    o.max_iter = int(max_iter or 0)
+    o.check_every = int(check_every or 0)
+    o.use_x0 = int(bool(x0))
+    o.use_graph = int(bool(graph))
+    o.profile = int(bool(profile))
+    o.d_G = G.data_ptr() if G is not None else None
+    o.d_GT = GT.data_ptr() if GT is not None else None
+    return o
+
+
+class Pattern:
+    """A validated CSR pattern resident on one device (hsla_pattern)."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor):
+        if not row_ptr.is_cuda:
+            raise ValueError("row_ptr must be on a GPU")
+        self.device = row_ptr.device
+        self.row_ptr = need(row_ptr, torch.int32, "row_ptr", self.device)
+        self.col = need(col, torch.int32, "col", self.device)
+        self.n = self.row_ptr.numel() - 1
+        self.nnz = self.col.numel()
+        with torch.cuda.device(self.device):
+            self.h = handle(self.device.index)
+            p = ctypes.c_void_p()
+            st = load().hsla_pattern_create(self.h, self.n, self.nnz, ptr(self.row_ptr), ptr(self.col),
+                                            stream_ptr(self.device), ctypes.byref(p))
+            check(st, self.h, "hsla_pattern_create")
+        self.p = p
+        n_ = ctypes.c_int32()
+        nnz_ = ctypes.c_int64()
+        nl = ctypes.c_int64()
+        sym = ctypes.c_int32()
+        load().hsla_pattern_info(self.p, ctypes.byref(n_), ctypes.byref(nnz_), ctypes.byref(nl), ctypes.byref(sym))
+        self.nnz_lower = nl.value
+        self.pattern_symmetric = bool(sym.value)
+
+    def __del__(self):
+        p = getattr(self, "p", None)
+        if p is not None and _lib is not None:
+            try:
+                _lib.hsla_pattern_destroy(p)
+            except Exception:
+                pass
+            self.p = None
+
+    def transpose(self):
+        """(row_ptr_T, col_T, src) of the transpose (device int32 tensors)."""
+        rpT = torch.empty(self.n + 1, dtype=torch.int32, device=self.device)
+        colT = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.device)
+        src = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            st = load().hsla_pattern_transpose(self.h, self.p, ptr(rpT), ptr(colT), ptr(src), stream_ptr(self.device))
+            check(st, self.h, "hsla_pattern_transpose")
+        return rpT, colT[:self.nnz], src[:self.nnz]
+
+
+def _batch(values: torch.Tensor, nnz: int) -> int:
+    if values.dim() == 1:
+        return 1
+    if values.dim() == 2 and values.shape[1] == nnz:
+        return values.shape[0]
+    raise ValueError(f"values must have shape (nnz,) or (B, nnz), got {tuple(values.shape)}")
+
+
+def spmv(pat: Pattern, values: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    values = need(values, torch.float64, "values", pat.device)
+    x = need(x, torch.float64, "x", pat.device)
+    B = _batch(values, pat.nnz)
+    y = torch.empty_like(x)
+    with torch.cuda.device(pat.device):
+        st = load().hsla_spmv(pat.h, pat.p, B, ptr(values), ptr(x), ptr(y), stream_ptr(pat.device))
+        check(st, pat.h, "hsla_spmv")
+    return y
+
+
+def solve(pat: Pattern, values: torch.Tensor, b: torch.Tensor, opts: Opts, x0: torch.Tensor | None = None):
+    """Returns (x, [info dicts], status)."""
+    values = need(values, torch.float64, "values", pat.device)
+    b = need(b, torch.float64, "b", pat.device)
+    B = _batch(values, pat.nnz)
+    if b.numel() != B * pat.n:
+        raise ValueError("b does not match the batch and pattern")
+    x = torch.empty_like(b) if x0 is None else need(x0, torch.float64, "x0", pat.device).clone()
+    infos = (Info * max(B, 1))()
+    with torch.cuda.device(pat.device):
+        st = load().hsla_solve_batched(pat.h, pat.p, B, ptr(values), ptr(b), ptr(x), ctypes.byref(opts),
+                                       infos, stream_ptr(pat.device))
+        check(st, pat.h, "hsla_solve")
+    return x, [infos[i].as_dict() for i in range(B)], st
+
+
+def adjoint(pat: Pattern, values: torch.Tensor, x: torch.Tensor, gx: torch.Tensor, opts: Opts,
+            want_gA: bool = True, want_gb: bool = True):
+    """Returns (gA or None, gb (lambda), [info dicts], status)."""
+    values = need(values, torch.float64, "values", pat.device)
+    x = need(x, torch.float64, "x", pat.device)
+    gx = need(gx, torch.float64, "gx", pat.device)
+    B = _batch(values, pat.nnz)
+    gA = torch.empty_like(values) if want_gA else None
+    gb = torch.empty_like(gx)
+    infos = (Info * max(B, 1))()
+    with torch.cuda.device(pat.device):
+        st = load().hsla_adjoint_batched(pat.h, pat.p, B, ptr(values), ptr(x), ptr(gx), ptr(gA), ptr(gb),
+                                         ctypes.byref(opts), infos, stream_ptr(pat.device))
+        check(st, pat.h, "hsla_adjoint")
+    return gA, gb, [infos[i].as_dict() for i in range(B)], st
+
+
+def outer_on_pattern(pat: Pattern, lam: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    lam = need(lam, torch.float64, "lambda", pat.device)
+    x = need(x, torch.float64, "x", pat.device)
+    B = lam.numel() // max(pat.n, 1) if pat.n else 1
+    gA = torch.empty((B, pat.nnz) if lam.dim() == 2 else (pat.nnz,), dtype=torch.float64, device=pat.device)
+    with torch.cuda.device(pat.device):
+        st = load().hsla_outer_on_pattern(pat.h, pat.p, B, ptr(lam), ptr(x), ptr(gA), stream_ptr(pat.device))
+        check(st, pat.h, "hsla_outer_on_pattern")
+    return gA
+
+
+def residual_norms(pat: Pattern, values: torch.Tensor, b: torch.Tensor, x: torch.Tensor):
+    values = need(values, torch.float64, "values", pat.device)
+    b = need(b, torch.float64, "b", pat.device)
+    x = need(x, torch.float64, "x", pat.device)
+    B = _batch(values, pat.nnz)
+    rn = (ctypes.c_double * B)()
+    bn = (ctypes.c_double * B)()
+    with torch.cuda.device(pat.device):
+        st = load().hsla_residual_norms(pat.h, pat.p, B, ptr(values), ptr(b), ptr(x), rn, bn, stream_ptr(pat.device))
+        check(st, pat.h, "hsla_residual_norms")
+    return list(rn), list(bn)

@@ -1,0 +1,298 @@
+// Internal declarations shared by the hsla HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "hsla.h"
+
+namespace hsla {
+
+constexpr int kBlock = 256;             // threads per block for every kernel
+constexpr int kWave = 64;               // CDNA wavefront width
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kTileRows = 64;           // rows per SpMV tile: one lane per row
+constexpr int kTileCap = 512;           // max stored entries staged per tile (LDS, per wave)
+constexpr int kXcds = 8;                // MI355X: 8 XCDs, blocks dispatched round-robin
+
+// Per-system solver state (device memory, one record per system).
+struct alignas(128) SysState {
+    double rho;      // CG: r.z ; BiCGStab: rho = r_hat.r of the previous step
+    double rho_new;  // BiCGStab: r_hat.r of the current step
+    double alpha, beta, omega;
+    double rnorm2;   // last ||r||^2
+    double bnorm;    // ||b||
+    double tol;      // max(rtol ||b||, atol)
+    double snorm2;
+    int64_t iters;
+    int64_t max_iter;
+    int32_t status;  // hsla_status of the system
+    int32_t done;    // 1 once the system stopped (converged, failed, exhausted)
+    int32_t restarts;
+    int32_t s_exit;  // BiCGStab: ||s|| <= tol, finish with x += alpha p_hat
+    int32_t restart_pending;
+    int32_t bad_diag;  // set when Jacobi finds a missing or zero diagonal
+    int32_t pad[2];
+};
+
+struct DevInfo {
+    int num_cu = 256;
+};
+
+}  // namespace hsla
+
+struct hsla_pattern {
+    int device = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t *row_ptr = nullptr;  // [n+1]
+    int32_t *col = nullptr;      // [nnz]
+    int32_t *diag = nullptr;     // [n] position of the diagonal entry, -1 if absent
+    int32_t *tiles = nullptr;    // [ntiles+1] first row of each SpMV tile
+    int32_t ntiles = 0;
+    int32_t *rpT = nullptr, *colT = nullptr, *srcT = nullptr;  // transpose
+    int32_t *tilesT = nullptr;
+    int32_t ntilesT = 0;
+    int32_t *diagT = nullptr;
+    int32_t pattern_symmetric = 0;
+    int64_t nnz_lower = 0;
+    // lower triangle (incl. diagonal) for factorized approximate inverses
+    int32_t *rpL = nullptr, *colL = nullptr, *posL = nullptr;   // posL: position in A
+    int32_t *tilesL = nullptr;
+    int32_t ntilesL = 0;
+    int32_t *rpU = nullptr, *colU = nullptr, *srcU = nullptr;   // L^T (upper) + perm into L order
+    int32_t *tilesU = nullptr;
+    int32_t ntilesU = 0;
+};
+
+struct hsla_handle {
+    int device = 0;
+    hsla::DevInfo dev;
+    std::string last_error;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    hsla::SysState *h_state = nullptr;  // pinned host mirror
+    size_t h_state_cap = 0;
+    // cached HIP graphs of iteration chunks (small LRU by launch arguments)
+    static constexpr int kGraphCache = 4;
+    hipGraphExec_t graph_exec[kGraphCache] = {};
+    uint64_t graph_key[kGraphCache] = {};
+    uint64_t graph_use[kGraphCache] = {};
+    uint64_t graph_clock = 0;
+    // private stream (default priority) ordered after the caller's stream
+    hipStream_t stream = nullptr;
+    hipEvent_t entry_event = nullptr;
+    int32_t *d_flags = nullptr;  // small device scratch for yes/no flags
+    // profile mode: event pairs around the timed kernel
+    hipEvent_t *prof_ev = nullptr;
+    int prof_cap = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+namespace hsla {
+
+hsla_status set_error(hsla_handle *h, hsla_status st, const char *fmt, ...);
+
+#define HSLA_HIP(h, expr)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return ::hsla::set_error((h), HSLA_ERR_HIP, "%s failed: %s (%s:%d)", #expr,         \
+                                     hipGetErrorString(e_), __FILE__, __LINE__);               \
+    } while (0)
+
+// Sets the device, and orders the handle's stream after the caller's.
+hsla_status enter(hsla_handle *h, hipStream_t user);
+
+// Grows the handle's workspace to at least `bytes` (contents not preserved).
+hsla_status ensure_workspace(hsla_handle *h, size_t bytes);
+hsla_status ensure_host_state(hsla_handle *h, size_t nsys);
+
+// Blocks per system for grid-stride kernels: a multiple of kXcds.
+inline int grid_blocks(const hsla_handle *h, int64_t work_items_per_block_unit, int64_t units, int nsys) {
+    int64_t want = (units + work_items_per_block_unit - 1) / work_items_per_block_unit;
+    int64_t cap = (int64_t)h->dev.num_cu * 8 / (nsys > 0 ? nsys : 1);
+    if (cap < kXcds) cap = kXcds;
+    if (want > cap) want = cap;
+    if (want < 1) want = 1;
+    want = (want + kXcds - 1) / kXcds * kXcds;
+    return (int)want;
+}
+
+// Kernel launch helpers implemented in the .hip files.
+hsla_status launch_spmv(hsla_handle *h, const hsla_pattern *p, int B, const double *values,
+                        const double *x, double *y, hipStream_t s);
+
+}  // namespace hsla
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+namespace hsla {
+
+// Butterfly sum over the 64 lanes; every lane ends with the same value and
+// the association order is fixed, so the result is deterministic.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Sum over the block of NV values; the result is valid in thread 0.
+// `sh` must hold NV * kWavesPerBlock doubles.  Ends with a barrier, so `sh`
+// may be reused right after.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *sh) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) sh[j * kWavesPerBlock + w] = v[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < kWavesPerBlock; ++q) s += sh[j * kWavesPerBlock + q];
+            v[j] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Single-pass deterministic grid reduction.  Every block of the system's
+// grid (gridDim.x blocks) calls this with its thread-local partial values.
+// Block partials go to part[j * G + block]; a ticket counter elects the
+// last block to arrive, which sums the G partials in a fixed order
+// (independent of arrival order) and returns true with the totals in
+// thread 0's `tot`.  The counter is reset for the next use.
+template <int NV>
+__device__ __forceinline__ bool grid_sum(double (&v)[NV], double *part, unsigned *counter,
+                                         double (&tot)[NV]) {
+    __shared__ double sh[NV * kWavesPerBlock];
+    __shared__ int is_last;
+    const unsigned G = gridDim.x;
+    block_sum<NV>(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            __hip_atomic_store(&part[(size_t)j * G + blockIdx.x], v[j], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (t == G - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    for (unsigned i = threadIdx.x; i < G; i += blockDim.x) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            acc[j] += __hip_atomic_load(&part[(size_t)j * G + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    block_sum<NV>(acc, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) tot[j] = acc[j];
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return true;
+}
+
+// XCD-aware tile walk.  Blocks are dispatched round-robin over the 8 XCDs,
+// so block b runs on XCD b % 8.  Each XCD gets a contiguous range of tiles,
+// and the waves of that XCD sweep it together, keeping the x-gather window
+// in that XCD's L2.  Returns the number of rounds; tile(round) gives the
+// tile of this wave in that round or -1.
+struct TileWalk {
+    int32_t lo, hi, first, stride;
+    __device__ __forceinline__ TileWalk(int32_t ntiles) {
+        const int G = gridDim.x;
+        const int wave = threadIdx.x / kWave;
+        if (G % kXcds == 0) {
+            const int xcd = blockIdx.x % kXcds;
+            const int per = G / kXcds;
+            lo = (int32_t)((int64_t)ntiles * xcd / kXcds);
+            hi = (int32_t)((int64_t)ntiles * (xcd + 1) / kXcds);
+            first = lo + (blockIdx.x / kXcds) * kWavesPerBlock + wave;
+            stride = per * kWavesPerBlock;
+        } else {
+            lo = 0;
+            hi = ntiles;
+            first = blockIdx.x * kWavesPerBlock + wave;
+            stride = G * kWavesPerBlock;
+        }
+    }
+    __device__ __forceinline__ int rounds() const {
+        // identical for all waves of a block (same XCD range)
+        const int32_t base = first - (threadIdx.x / kWave);
+        const int32_t span = hi - base;
+        return span <= 0 ? 0 : (span + stride - 1) / stride;
+    }
+    __device__ __forceinline__ int32_t tile(int r) const {
+        const int32_t t = first + r * stride;
+        return t < hi ? t : -1;
+    }
+};
+
+// y_row = sum_k val[k] * x[col[k]] for the rows of one tile, one lane per
+// row.  Products are staged in LDS (`lds`: kTileCap doubles owned by this
+// wave) and each row adds its products in ascending k, so the row sum
+// associates exactly like the sequential definition.  A tile with more than
+// kTileCap entries holds a single row; the wave then splits it lane-strided
+// and combines with a butterfly.  Returns true on the lane that owns a row.
+template <typename VT>
+__device__ __forceinline__ bool tile_spmv(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                          const VT *__restrict__ val, const double *__restrict__ x,
+                                          int32_t r0, int32_t r1, double *lds, int32_t &row, double &y) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int32_t k0 = rp[r0];
+    const int32_t cnt = rp[r1] - k0;
+    if (cnt <= kTileCap) {
+#pragma unroll
+        for (int u = 0; u < kTileCap / kWave; ++u) {
+            const int e = u * kWave + lane;
+            if (e < cnt) {
+                const int32_t k = k0 + e;
+                lds[e] = (double)val[k] * x[col[k]];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        row = r0 + lane;
+        bool own = row < r1;
+        double s = 0.0;
+        if (own) {
+            const int32_t a = rp[row] - k0, b = rp[row + 1] - k0;
+            for (int32_t k = a; k < b; ++k) s += lds[k];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        y = s;
+        return own;
+    }
+    // one long row
+    double s = 0.0;
+    for (int32_t e = lane; e < cnt; e += kWave) {
+        const int32_t k = k0 + e;
+        s += (double)val[k] * x[col[k]];
+    }
+    s = wave_sum(s);
+    row = r0;
+    y = s;
+    return lane == 0;
+}
+
+}  // namespace hsla

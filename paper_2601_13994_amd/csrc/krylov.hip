@@ -1,0 +1,1186 @@
+// Krylov solvers on CSR for MI355X: tile SpMV, Jacobi/FSAI-preconditioned CG
+// and right-Jacobi BiCGStab, the true-residual check and the adjoint
+// gradient assembly.  All recurrences run in FP64.
+//
+// One iteration is a short chain of kernels on one stream; every dot
+// product is folded into the kernel that produces its operands and reduced
+// in a single pass (block partials + ticket, fixed summation order), and
+// the block that completes a reduction also advances the scalar recurrence
+// (alpha, beta, omega, stop test) in device memory.  Kernels of a stopped
+// system return at entry, so chunks of K iterations are enqueued (and
+// replayed as a HIP graph) with one host check per chunk.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace hsla {
+
+// ---------------------------------------------------------------------------
+// Kernel argument bundles
+// ---------------------------------------------------------------------------
+struct Pat {
+    const int32_t *rp, *col, *diag, *tiles;
+    int32_t ntiles, n;
+    int64_t nnz;
+};
+
+struct FPat {  // pattern + values of one FSAI factor (float32 values)
+    const int32_t *rp, *col, *tiles;
+    int32_t ntiles;
+    int64_t nnz;
+    const float *val;
+};
+
+struct Sys {
+    const double *val;  // [B][nnz]
+    const double *b;    // [B][n]
+    double *x;          // [B][n]
+    // work vectors, [B][n] each
+    double *r, *p, *q, *dinv, *z, *w;
+    double *rh, *ph, *v, *s, *sh, *t;
+    SysState *st;       // [B]
+    double *part;       // [B][3][G]
+    unsigned *cnt;      // [B] (64-byte stride)
+    int32_t G;          // blocks per system of the launch that uses `part`
+};
+
+#define SYS_OFFSETS(S, A)                                               \
+    const int sidx = blockIdx.y;                                        \
+    const int64_t vo = (int64_t)sidx * (A).n;                           \
+    SysState &st = (S).st[sidx];                                        \
+    double *part = (S).part + (int64_t)sidx * 3 * gridDim.x;            \
+    unsigned *cnt = (S).cnt + (int64_t)sidx * 16;
+
+__device__ __forceinline__ bool stopped(const SysState &st) { return st.done != 0; }
+
+// ---------------------------------------------------------------------------
+// State reset
+// ---------------------------------------------------------------------------
+__global__ void k_reset(SysState *st, unsigned *cnt, int B, int64_t max_iter) {
+    for (int i = threadIdx.x; i < B; i += blockDim.x) {
+        SysState z;
+        memset(&z, 0, sizeof z);
+        z.max_iter = max_iter;
+        z.rho = z.alpha = z.omega = 1.0;
+        st[i] = z;
+        cnt[(int64_t)i * 16] = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SpMV
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_spmv(Pat A, const double *__restrict__ val, const double *__restrict__ x,
+                                                 double *__restrict__ y) {
+    __shared__ double lds[kWavesPerBlock][kTileCap];
+    const int64_t sidx = blockIdx.y;
+    val += sidx * A.nnz;
+    x += sidx * A.n;
+    y += sidx * A.n;
+    const TileWalk tw(A.ntiles);
+    const int R = tw.rounds();
+    double *my = lds[threadIdx.x / kWave];
+    for (int r = 0; r < R; ++r) {
+        const int32_t t = tw.tile(r);
+        if (t < 0) break;
+        int32_t row;
+        double yv;
+        if (tile_spmv(A.rp, A.col, val, x, A.tiles[t], A.tiles[t + 1], my, row, yv)) y[row] = yv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CG / PCG
+// ---------------------------------------------------------------------------
+enum { PRE_NONE = 0, PRE_JACOBI = 1, PRE_FSAI = 2 };
+
+// x = 0 or x0, r = b - A x0 (q holds A x0), z = M^{-1} r (Jacobi / none),
+// p = z, rho = r.z; stop test against max(rtol ||b||, atol).
+template <int PRE>
+__global__ __launch_bounds__(kBlock) void k_cg_init(Pat A, Sys S, int use_x0, double rtol, double atol) {
+    SYS_OFFSETS(S, A)
+    const double *val = S.val + sidx * A.nnz;
+    double acc[3] = {0.0, 0.0, 0.0};  // b.b, r.r, r.z
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
+        const double bi = S.b[vo + i];
+        const double ri = use_x0 ? bi - S.q[vo + i] : bi;
+        if (!use_x0) S.x[vo + i] = 0.0;
+        S.r[vo + i] = ri;
+        double zi = ri;
+        if (PRE == PRE_JACOBI) {
+            const int32_t d = A.diag[i];
+            const double a = d >= 0 ? val[d] : 0.0;
+            if (a == 0.0) bad = true;
+            const double di = 1.0 / a;
+            S.dinv[vo + i] = di;
+            zi = di * ri;
+        }
+        if (PRE == PRE_FSAI)
+            S.p[vo + i] = 0.0;
+        else
+            S.p[vo + i] = zi;
+        acc[0] += bi * bi;
+        acc[1] += ri * ri;
+        acc[2] += ri * zi;
+    }
+    if (bad) __hip_atomic_store(&st.bad_diag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double tot[3];
+    if (grid_sum<3>(acc, part, cnt, tot) && threadIdx.x == 0) {
+        const double bn = sqrt(tot[0]);
+        double tol = rtol * bn;
+        if (atol > tol) tol = atol;
+        st.bnorm = bn;
+        st.tol = tol;
+        st.rnorm2 = tot[1];
+        st.iters = 0;
+        const double rn = sqrt(tot[1]);
+        if (__hip_atomic_load(&st.bad_diag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            st.status = HSLA_ERR_ZERO_DIAGONAL;
+            st.done = 1;
+        } else if (!isfinite(rn) || !isfinite(bn)) {
+            st.status = HSLA_ERR_NONFINITE;
+            st.done = 1;
+        } else if (rn <= tol) {
+            st.status = HSLA_OK;
+            st.done = 1;
+        } else if (st.max_iter <= 0) {
+            st.status = HSLA_NOT_CONVERGED;
+            st.done = 1;
+        } else {
+            st.rho = (PRE == PRE_FSAI) ? 0.0 : tot[2];
+            st.beta = 0.0;
+        }
+    }
+}
+
+// q = A p and sigma = p.q; alpha = rho / sigma, or breakdown if sigma <= 0.
+template <int PRE>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(Pat A, Sys S) {
+    __shared__ double lds[kWavesPerBlock][kTileCap];
+    SYS_OFFSETS(S, A)
+    if (stopped(st)) return;
+    const double *val = S.val + sidx * A.nnz;
+    const double *p = S.p + vo;
+    double *q = S.q + vo;
+    const TileWalk tw(A.ntiles);
+    const int R = tw.rounds();
+    double *my = lds[threadIdx.x / kWave];
+    double acc[1] = {0.0};
+    for (int r = 0; r < R; ++r) {
+        const int32_t t = tw.tile(r);
+        if (t < 0) break;
+        int32_t row;
+        double yv;
+        if (tile_spmv(A.rp, A.col, val, p, A.tiles[t], A.tiles[t + 1], my, row, yv)) {
+            q[row] = yv;
+            acc[0] += p[row] * yv;
+        }
+    }
+    double tot[1];
+    if (grid_sum<1>(acc, part, cnt, tot) && threadIdx.x == 0) {
+        const double sigma = tot[0];
+        if (!isfinite(sigma)) {
+            st.status = HSLA_ERR_NONFINITE;
+            st.done = 1;
+        } else if (!(sigma > 0.0)) {
+            st.status = HSLA_BREAKDOWN;
+            st.done = 1;
+        } else {
+            st.alpha = st.rho / sigma;
+        }
+    }
+}
+
+// x += alpha p, r -= alpha q, stop test on ||r||, then (Jacobi / none)
+// rho' = r.M^{-1}r, beta = rho'/rho.
+template <int PRE>
+__global__ __launch_bounds__(kBlock) void k_cg_update(Pat A, Sys S) {
+    SYS_OFFSETS(S, A)
+    if (stopped(st)) return;
+    const double alpha = st.alpha;
+    double acc[2] = {0.0, 0.0};  // r.r, r.z
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t j = vo + i;
+        S.x[j] = S.x[j] + alpha * S.p[j];
+        const double ri = S.r[j] - alpha * S.q[j];
+        S.r[j] = ri;
+        acc[0] += ri * ri;
+        if (PRE == PRE_JACOBI) acc[1] += ri * (S.dinv[j] * ri);
+    }
+    if (PRE == PRE_NONE) acc[1] = acc[0];
+    double tot[2];
+    if (grid_sum<2>(acc, part, cnt, tot) && threadIdx.x == 0) {
+        st.iters += 1;
+        st.rnorm2 = tot[0];
+        const double rn = sqrt(tot[0]);
+        if (!isfinite(rn)) {
+            st.status = HSLA_ERR_NONFINITE;
+            st.done = 1;
+        } else if (rn <= st.tol) {
+            st.status = HSLA_OK;
+            st.done = 1;
+        } else if (st.iters >= st.max_iter) {
+            st.status = HSLA_NOT_CONVERGED;
+            st.done = 1;
+        } else if (PRE != PRE_FSAI) {
+            st.beta = tot[1] / st.rho;
+            st.rho = tot[1];
+        }
+    }
+}
+
+// p = z + beta p with z = D^{-1} r (Jacobi), r (none) or the stored z (FSAI).
+template <int PRE>
+__global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
+    SYS_OFFSETS(S, A)
+    if (stopped(st)) return;
+    (void)part;
+    (void)cnt;
+    const double beta = st.beta;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t j = vo + i;
+        double zi;
+        if (PRE == PRE_JACOBI)
+            zi = S.dinv[j] * S.r[j];
+        else if (PRE == PRE_NONE)
+            zi = S.r[j];
+        else
+            zi = S.z[j];
+        S.p[j] = zi + beta * S.p[j];
+    }
+}
+
+// FSAI apply, first half: w = G r (G lower, float32 values, FP64 products).
+__global__ __launch_bounds__(kBlock) void k_fsai_lower(Pat A, FPat L, Sys S) {
+    __shared__ double lds[kWavesPerBlock][kTileCap];
+    SYS_OFFSETS(S, A)
+    (void)part;
+    (void)cnt;
+    if (stopped(st)) return;
+    const float *g = L.val + sidx * L.nnz;
+    const double *r = S.r + vo;
+    double *w = S.w + vo;
+    const TileWalk tw(L.ntiles);
+    const int R = tw.rounds();
+    double *my = lds[threadIdx.x / kWave];
+    for (int rr = 0; rr < R; ++rr) {
+        const int32_t t = tw.tile(rr);
+        if (t < 0) break;
+        int32_t row;
+        double yv;
+        if (tile_spmv(L.rp, L.col, g, r, L.tiles[t], L.tiles[t + 1], my, row, yv)) w[row] = yv;
+    }
+}
+
+// FSAI apply, second half: z = G^T w and rho' = r.z; in the set-up phase
+// rho = rho' (p = z follows from beta = 0 and p = 0), in an iteration
+// beta = rho'/rho, rho = rho'.
+__global__ __launch_bounds__(kBlock) void k_fsai_upper_dot(Pat A, FPat U, Sys S, int setup) {
+    __shared__ double lds[kWavesPerBlock][kTileCap];
+    SYS_OFFSETS(S, A)
+    if (stopped(st)) return;
+    const float *g = U.val + sidx * U.nnz;
+    const double *w = S.w + vo;
+    const double *r = S.r + vo;
+    double *z = S.z + vo;
+    const TileWalk tw(U.ntiles);
+    const int R = tw.rounds();
+    double *my = lds[threadIdx.x / kWave];
+    double acc[1] = {0.0};
+    for (int rr = 0; rr < R; ++rr) {
+        const int32_t t = tw.tile(rr);
+        if (t < 0) break;
+        int32_t row;
+        double yv;
+        if (tile_spmv(U.rp, U.col, g, w, U.tiles[t], U.tiles[t + 1], my, row, yv)) {
+            z[row] = yv;
+            acc[0] += r[row] * yv;
+        }
+    }
+    double tot[1];
+    if (grid_sum<1>(acc, part, cnt, tot) && threadIdx.x == 0) {
+        if (!isfinite(tot[0])) {
+            st.status = HSLA_ERR_NONFINITE;
+            st.done = 1;
+        } else if (setup) {
+            st.rho = tot[0];
+            st.beta = 0.0;
+        } else {
+            st.beta = tot[0] / st.rho;
+            st.rho = tot[0];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab (right preconditioning with D^{-1} or none)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void bicg_breakdown(SysState &st) {
+    if (st.restarts == 0) {
+        // restart from the current iterate: r_hat = r, p = v = 0,
+        // rho = alpha = omega = 1, so rho' = r.r and p = r next
+        st.restarts = 1;
+        st.restart_pending = 1;
+        st.rho = 1.0;
+        st.alpha = 1.0;
+        st.omega = 1.0;
+        st.rho_new = st.rnorm2;
+        if (st.rho_new == 0.0) {
+            st.status = HSLA_BREAKDOWN;
+            st.done = 1;
+        }
+    } else {
+        st.status = HSLA_BREAKDOWN;
+        st.done = 1;
+    }
+}
+
+template <int PRE>
+__global__ __launch_bounds__(kBlock) void k_bicg_init(Pat A, Sys S, int use_x0, double rtol, double atol) {
+    SYS_OFFSETS(S, A)
+    const double *val = S.val + sidx * A.nnz;
+    double acc[2] = {0.0, 0.0};  // b.b, r.r
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t j = vo + i;
+        const double bi = S.b[j];
+        const double ri = use_x0 ? bi - S.q[j] : bi;
+        if (!use_x0) S.x[j] = 0.0;
+        S.r[j] = ri;
+        S.rh[j] = ri;
+        S.p[j] = 0.0;
+        S.v[j] = 0.0;
+        if (PRE == PRE_JACOBI) {
+            const int32_t d = A.diag[i];
+            const double a = d >= 0 ? val[d] : 0.0;
+            if (a == 0.0) bad = true;
+            S.dinv[j] = 1.0 / a;
+        }
+        acc[0] += bi * bi;
+        acc[1] += ri * ri;
+    }
+    if (bad) __hip_atomic_store(&st.bad_diag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double tot[2];
+    if (grid_sum<2>(acc, part, cnt, tot) && threadIdx.x == 0) {
+        const double bn = sqrt(tot[0]);
+        double tol = rtol * bn;
+        if (atol > tol) tol = atol;
+        st.bnorm = bn;
+        st.tol = tol;
+        st.rnorm2 = tot[1];
+        const double rn = sqrt(tot[1]);
+        if (__hip_atomic_load(&st.bad_diag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            st.status = HSLA_ERR_ZERO_DIAGONAL;
+            st.done = 1;
+        } else if (!isfinite(rn) || !isfinite(bn)) {
+            st.status = HSLA_ERR_NONFINITE;
+            st.done = 1;
+        } else if (rn <= tol) {
+            st.status = HSLA_OK;
+            st.done = 1;
+        } else if (st.max_iter <= 0) {
+            st.status = HSLA_NOT_CONVERGED;
+            st.done = 1;
+        } else {
+            st.rho_new = tot[1];  // r_hat.r with r_hat = r
+            st.beta = (st.rho_new / st.rho) * (st.alpha / st.omega);
+        }
+    }
+}
+
+// p = r + beta (p - omega v), p_hat = M^{-1} p (after a restart: r_hat = r,
+// p = r).
+template <int PRE>
+__global__ __launch_bounds__(kBlock) void k_bicg_dir(Pat A, Sys S) {
+    SYS_OFFSETS(S, A)
+    (void)part;
+    (void)cnt;
+    if (stopped(st)) return;
+    const double beta = st.beta, omega = st.omega;
+    const int restart = st.restart_pending;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t j = vo + i;
+        const double ri = S.r[j];
+        double pi;
+        if (restart) {
+            S.rh[j] = ri;
+            pi = ri;
+        } else {
+            pi = ri + beta * (S.p[j] - omega * S.v[j]);
+        }
+        S.p[j] = pi;
+        S.ph[j] = PRE == PRE_JACOBI ? S.dinv[j] * pi : pi;
+    }
+}
+
+// v = A p_hat and r_hat.v; alpha = rho' / (r_hat.v).
+__global__ __launch_bounds__(kBlock) void k_bicg_spmv_v(Pat A, Sys S) {
+    __shared__ double lds[kWavesPerBlock][kTileCap];
+    SYS_OFFSETS(S, A)
+    if (stopped(st)) return;
+    const double *val = S.val + sidx * A.nnz;
+    const double *ph = S.ph + vo;
+    const double *rh = S.rh + vo;
+    double *v = S.v + vo;
+    const TileWalk tw(A.ntiles);
+    const int R = tw.rounds();
+    double *my = lds[threadIdx.x / kWave];
+    double acc[1] = {0.0};
+    for (int r = 0; r < R; ++r) {
+        const int32_t t = tw.tile(r);
+        if (t < 0) break;
+        int32_t row;
+        double yv;
+        if (tile_spmv(A.rp, A.col, val, ph, A.tiles[t], A.tiles[t + 1], my, row, yv)) {
+            v[row] = yv;
+            acc[0] += rh[row] * yv;
+        }
+    }
+    double tot[1];
+    if (grid_sum<1>(acc, part, cnt, tot) && threadIdx.x == 0) {
+        st.restart_pending = 0;
+        const double rv = tot[0];
+        if (!isfinite(rv)) {
+            st.status = HSLA_ERR_NONFINITE;
+            st.done = 1;
+        } else if (rv == 0.0) {
+            bicg_breakdown(st);
+        } else {
+            st.alpha = st.rho_new / rv;
+        }
+    }
+}
+
+// s = r - alpha v, s_hat = M^{-1} s, ||s||; ||s|| <= tol finishes the
+// solve in the update kernel with x += alpha p_hat.
+template <int PRE>
+__global__ __launch_bounds__(kBlock) void k_bicg_s(Pat A, Sys S) {
+    SYS_OFFSETS(S, A)
+    if (stopped(st) || st.restart_pending) return;
+    const double alpha = st.alpha;
+    double acc[1] = {0.0};
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t j = vo + i;
+        const double si = S.r[j] - alpha * S.v[j];
+        S.s[j] = si;
+        S.sh[j] = PRE == PRE_JACOBI ? S.dinv[j] * si : si;
+        acc[0] += si * si;
+    }
+    double tot[1];
+    if (grid_sum<1>(acc, part, cnt, tot) && threadIdx.x == 0) {
+        st.iters += 1;
+        st.snorm2 = tot[0];
+        const double sn = sqrt(tot[0]);
+        if (!isfinite(sn)) {
+            st.status = HSLA_ERR_NONFINITE;
+            st.done = 1;
+        } else if (sn <= st.tol) {
+            st.s_exit = 1;
+        }
+    }
+}
+
+// t = A s_hat, t.s and t.t; omega = t.s / t.t.
+__global__ __launch_bounds__(kBlock) void k_bicg_spmv_t(Pat A, Sys S) {
+    __shared__ double lds[kWavesPerBlock][kTileCap];
+    SYS_OFFSETS(S, A)
+    if (stopped(st) || st.restart_pending || st.s_exit) return;
+    const double *val = S.val + sidx * A.nnz;
+    const double *sh = S.sh + vo;
+    const double *s = S.s + vo;
+    double *t = S.t + vo;
+    const TileWalk tw(A.ntiles);
+    const int R = tw.rounds();
+    double *my = lds[threadIdx.x / kWave];
+    double acc[2] = {0.0, 0.0};
+    for (int r = 0; r < R; ++r) {
+        const int32_t tl = tw.tile(r);
+        if (tl < 0) break;
+        int32_t row;
+        double yv;
+        if (tile_spmv(A.rp, A.col, val, sh, A.tiles[tl], A.tiles[tl + 1], my, row, yv)) {
+            t[row] = yv;
+            acc[0] += yv * s[row];
+            acc[1] += yv * yv;
+        }
+    }
+    double tot[2];
+    if (grid_sum<2>(acc, part, cnt, tot) && threadIdx.x == 0) {
+        if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+            st.status = HSLA_ERR_NONFINITE;
+            st.done = 1;
+        } else if (tot[1] == 0.0) {
+            bicg_breakdown(st);
+        } else {
+            st.omega = tot[0] / tot[1];
+        }
+    }
+}
+
+// x += alpha p_hat + omega s_hat, r = s - omega t, stop test on ||r||, then
+// rho' = r_hat.r and beta = (rho'/rho)(alpha/omega) for the next step.
+__global__ __launch_bounds__(kBlock) void k_bicg_update(Pat A, Sys S) {
+    SYS_OFFSETS(S, A)
+    if (stopped(st) || st.restart_pending) return;
+    const double alpha = st.alpha, omega = st.omega;
+    const int sx = st.s_exit;
+    double acc[2] = {0.0, 0.0};  // r.r, r_hat.r
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t j = vo + i;
+        double ri;
+        if (sx) {
+            S.x[j] = S.x[j] + alpha * S.ph[j];
+            ri = S.s[j];
+        } else {
+            S.x[j] = S.x[j] + (alpha * S.ph[j] + omega * S.sh[j]);
+            ri = S.s[j] - omega * S.t[j];
+        }
+        S.r[j] = ri;
+        acc[0] += ri * ri;
+        acc[1] += S.rh[j] * ri;
+    }
+    double tot[2];
+    if (grid_sum<2>(acc, part, cnt, tot) && threadIdx.x == 0) {
+        st.rnorm2 = tot[0];
+        const double rn = sqrt(tot[0]);
+        if (sx) {
+            st.status = HSLA_OK;
+            st.done = 1;
+            st.rnorm2 = st.snorm2;
+        } else if (!isfinite(rn)) {
+            st.status = HSLA_ERR_NONFINITE;
+            st.done = 1;
+        } else if (rn <= st.tol) {
+            st.status = HSLA_OK;
+            st.done = 1;
+        } else if (omega == 0.0) {
+            bicg_breakdown(st);
+        } else if (st.iters >= st.max_iter) {
+            st.status = HSLA_NOT_CONVERGED;
+            st.done = 1;
+        } else {
+            st.rho = st.rho_new;
+            st.rho_new = tot[1];
+            if (!isfinite(st.rho_new)) {
+                st.status = HSLA_ERR_NONFINITE;
+                st.done = 1;
+            } else if (st.rho_new == 0.0) {
+                bicg_breakdown(st);
+            } else {
+                st.beta = (st.rho_new / st.rho) * (st.alpha / st.omega);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Residual, symmetry and adjoint helpers
+// ---------------------------------------------------------------------------
+
+// ||b - A x||^2 and ||b||^2 per system into out[2*s], out[2*s+1].
+__global__ __launch_bounds__(kBlock) void k_residual(Pat A, Sys S, double *out) {
+    __shared__ double lds[kWavesPerBlock][kTileCap];
+    SYS_OFFSETS(S, A)
+    (void)st;
+    const double *val = S.val + sidx * A.nnz;
+    const double *x = S.x + vo;
+    const double *b = S.b + vo;
+    const TileWalk tw(A.ntiles);
+    const int R = tw.rounds();
+    double *my = lds[threadIdx.x / kWave];
+    double acc[2] = {0.0, 0.0};
+    for (int r = 0; r < R; ++r) {
+        const int32_t t = tw.tile(r);
+        if (t < 0) break;
+        int32_t row;
+        double yv;
+        if (tile_spmv(A.rp, A.col, val, x, A.tiles[t], A.tiles[t + 1], my, row, yv)) {
+            const double e = b[row] - yv;
+            acc[0] += e * e;
+            acc[1] += b[row] * b[row];
+        }
+    }
+    double tot[2];
+    if (grid_sum<2>(acc, part, cnt, tot) && threadIdx.x == 0) {
+        out[2 * sidx] = tot[0];
+        out[2 * sidx + 1] = tot[1];
+    }
+}
+
+// flag = 1 if val[s][src[k]] != val[s][k] for some system and entry.
+__global__ __launch_bounds__(kBlock) void k_value_asym(int64_t nnz, int B, const double *__restrict__ val,
+                                                       const int32_t *__restrict__ src, int32_t *flag) {
+    const int64_t total = nnz * B;
+    bool diff = false;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
+        const int64_t s = e / nnz, k = e - s * nnz;
+        if (!(val[s * nnz + src[k]] == val[e])) diff = true;
+    }
+    if (diff) *flag = 1;
+}
+
+// out[s][k] = in[s][src[k]]
+__global__ __launch_bounds__(kBlock) void k_gather_values(int64_t nnz, int B, const double *__restrict__ in,
+                                                          const int32_t *__restrict__ src, double *__restrict__ out) {
+    const int64_t total = nnz * B;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
+        const int64_t s = e / nnz, k = e - s * nnz;
+        out[e] = in[s * nnz + src[k]];
+    }
+}
+
+// Eq. adjoint_linear on the pattern: gA[s][k] = -lambda[s][row(k)] * x[s][col(k)].
+__global__ __launch_bounds__(kBlock) void k_outer(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ lam,
+                                                  const double *__restrict__ x, double *__restrict__ gA) {
+    const int64_t sidx = blockIdx.y;
+    lam += sidx * n;
+    x += sidx * n;
+    gA += sidx * nnz;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double li = -lam[i];
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) gA[k] = li * x[col[k]];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host drivers
+// ---------------------------------------------------------------------------
+
+struct Layout {
+    size_t off_state, off_cnt, off_part, off_vec, off_res, total;
+};
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+static Layout make_layout(int B, int64_t n, int nvec, int G) {
+    Layout L{};
+    size_t o = 0;
+    L.off_state = o;
+    o = align_up(o + sizeof(SysState) * B, 256);
+    L.off_cnt = o;
+    o = align_up(o + 64 * (size_t)B, 256);
+    L.off_part = o;
+    o = align_up(o + sizeof(double) * 3 * (size_t)G * B, 256);
+    L.off_res = o;
+    o = align_up(o + sizeof(double) * 2 * (size_t)B, 256);
+    L.off_vec = o;
+    o = align_up(o + sizeof(double) * (size_t)nvec * B * (size_t)n, 256);
+    L.total = o;
+    return L;
+}
+
+hsla_status launch_spmv(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *x,
+                        double *y, hipStream_t s) {
+    if (p->n == 0 || B == 0) return HSLA_OK;
+    Pat A{p->row_ptr, p->col, p->diag, p->tiles, p->ntiles, p->n, p->nnz};
+    const int G = grid_blocks(h, kWavesPerBlock, p->ntiles, 1);
+    k_spmv<<<dim3(G, B), kBlock, 0, s>>>(A, values, x, y);
+    HSLA_HIP(h, hipGetLastError());
+    return HSLA_OK;
+}
+
+struct SolveCall {
+    Pat A;
+    FPat L, U;
+    Sys S;
+    int B;
+    int method;   // HSLA_METHOD_CG / BICGSTAB
+    int precond;  // PRE_*
+    int G;        // blocks per system, shared by every kernel (partial stride)
+};
+
+// Enqueues `iters` iterations.  With `ev` (profile mode) the SpMV(+dot)
+// launch of iteration k is bracketed by ev[2k], ev[2k+1].
+static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hipEvent_t *ev) {
+    const dim3 g(c.G, c.B);
+    for (int k = 0; k < iters; ++k) {
+        if (c.method == HSLA_METHOD_CG) {
+            if (ev) (void)hipEventRecord(ev[2 * k], s);
+            switch (c.precond) {
+                case PRE_NONE: k_cg_spmv_dot<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S); break;
+                case PRE_JACOBI: k_cg_spmv_dot<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S); break;
+                default: k_cg_spmv_dot<PRE_FSAI><<<g, kBlock, 0, s>>>(c.A, c.S); break;
+            }
+            if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
+            switch (c.precond) {
+                case PRE_NONE:
+                    k_cg_update<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S);
+                    k_cg_direction<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S);
+                    break;
+                case PRE_JACOBI:
+                    k_cg_update<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S);
+                    k_cg_direction<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S);
+                    break;
+                default:
+                    k_cg_update<PRE_FSAI><<<g, kBlock, 0, s>>>(c.A, c.S);
+                    k_fsai_lower<<<g, kBlock, 0, s>>>(c.A, c.L, c.S);
+                    k_fsai_upper_dot<<<g, kBlock, 0, s>>>(c.A, c.U, c.S, 0);
+                    k_cg_direction<PRE_FSAI><<<g, kBlock, 0, s>>>(c.A, c.S);
+                    break;
+            }
+        } else {
+            if (c.precond == PRE_JACOBI)
+                k_bicg_dir<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S);
+            else
+                k_bicg_dir<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S);
+            if (ev) (void)hipEventRecord(ev[2 * k], s);
+            k_bicg_spmv_v<<<g, kBlock, 0, s>>>(c.A, c.S);
+            if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
+            if (c.precond == PRE_JACOBI)
+                k_bicg_s<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S);
+            else
+                k_bicg_s<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S);
+            k_bicg_spmv_t<<<g, kBlock, 0, s>>>(c.A, c.S);
+            k_bicg_update<<<g, kBlock, 0, s>>>(c.A, c.S);
+        }
+    }
+}
+
+static uint64_t fnv(const void *data, size_t len, uint64_t hsh = 1469598103934665603ull) {
+    const unsigned char *b = (const unsigned char *)data;
+    for (size_t i = 0; i < len; ++i) hsh = (hsh ^ b[i]) * 1099511628211ull;
+    return hsh;
+}
+
+// Runs `iters` iterations.  Without profiling they are replayed from a
+// cached graph of `unit` iterations (8 when `iters` is a multiple of 8), so
+// every chunk length of a solve reuses one captured graph.
+static hsla_status run_chunk(hsla_handle *h, const SolveCall &c, int iters, bool use_graph, hipStream_t s,
+                             hipEvent_t *ev) {
+    if (!use_graph || ev) {
+        enqueue_iterations(c, iters, s, ev);
+        HSLA_HIP(h, hipGetLastError());
+        return HSLA_OK;
+    }
+    const int unit = iters % 8 == 0 ? 8 : iters;
+    uint64_t key = fnv(&c, sizeof c);
+    key = fnv(&unit, sizeof unit, key);
+    int slot = -1;
+    for (int i = 0; i < hsla_handle::kGraphCache; ++i)
+        if (h->graph_exec[i] && h->graph_key[i] == key) slot = i;
+    if (slot < 0) {
+        slot = 0;
+        for (int i = 1; i < hsla_handle::kGraphCache; ++i)
+            if (h->graph_use[i] < h->graph_use[slot]) slot = i;
+        if (h->graph_exec[slot]) {
+            HSLA_HIP(h, hipGraphExecDestroy(h->graph_exec[slot]));
+            h->graph_exec[slot] = nullptr;
+            h->graph_key[slot] = 0;
+        }
+        hipGraph_t g = nullptr;
+        HSLA_HIP(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        enqueue_iterations(c, unit, s, nullptr);
+        const hipError_t le = hipGetLastError();
+        const hipError_t ce = hipStreamEndCapture(s, &g);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return set_error(h, HSLA_ERR_HIP, "graph capture failed: %s",
+                             hipGetErrorString(le != hipSuccess ? le : ce));
+        }
+        const hipError_t ie = hipGraphInstantiate(&h->graph_exec[slot], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            h->graph_exec[slot] = nullptr;
+            return set_error(h, HSLA_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(ie));
+        }
+        h->graph_key[slot] = key;
+    }
+    h->graph_use[slot] = ++h->graph_clock;
+    for (int done = 0; done < iters; done += unit) HSLA_HIP(h, hipGraphLaunch(h->graph_exec[slot], s));
+    return HSLA_OK;
+}
+
+static hsla_status ensure_prof_events(hsla_handle *h, int pairs) {
+    if (2 * pairs <= h->prof_cap) return HSLA_OK;
+    for (int i = 0; i < h->prof_cap; ++i) (void)hipEventDestroy(h->prof_ev[i]);
+    delete[] h->prof_ev;
+    h->prof_ev = new hipEvent_t[2 * pairs];
+    h->prof_cap = 0;
+    for (int i = 0; i < 2 * pairs; ++i) {
+        HSLA_HIP(h, hipEventCreate(&h->prof_ev[i]));
+        h->prof_cap = i + 1;
+    }
+    return HSLA_OK;
+}
+
+static int worst_status(int a, int b) {
+    if (a < 0 || b < 0) return a < b ? a : b;
+    return a > b ? a : b;
+}
+
+// Shared solve driver for the single, batched and transposed (adjoint)
+// paths.  `A` is the operator actually iterated on.
+static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const FPat *U, int B, const double *values,
+                              const double *b, double *x, const hsla_opts &o, int method, hsla_info *infos,
+                              hipStream_t s) {
+    const int64_t n = A.n;
+    const int pre = o.precond == HSLA_PRECOND_NONE ? PRE_NONE : o.precond == HSLA_PRECOND_FSAI ? PRE_FSAI : PRE_JACOBI;
+    if (method == HSLA_METHOD_BICGSTAB && pre == PRE_FSAI)
+        return set_error(h, HSLA_ERR_INVALID_ARG, "FSAI preconditioning is for CG only");
+    const int nvec = method == HSLA_METHOD_CG ? 6 : 10;
+    const int G = grid_blocks(h, kWavesPerBlock, A.ntiles, 1);
+    const Layout lay = make_layout(B, n, nvec, G);
+    hsla_status st = ensure_workspace(h, lay.total);
+    if (st != HSLA_OK) return st;
+    st = ensure_host_state(h, B);
+    if (st != HSLA_OK) return st;
+    char *ws = (char *)h->ws;
+    SolveCall c{};
+    c.A = A;
+    if (L) c.L = *L;
+    if (U) c.U = *U;
+    c.B = B;
+    c.method = method;
+    c.precond = pre;
+    c.G = G;
+    Sys &S = c.S;
+    S.val = values;
+    S.b = b;
+    S.x = x;
+    S.st = (SysState *)(ws + lay.off_state);
+    S.cnt = (unsigned *)(ws + lay.off_cnt);
+    S.part = (double *)(ws + lay.off_part);
+    S.G = G;
+    double *vec = (double *)(ws + lay.off_vec);
+    const size_t vs = (size_t)B * n;
+    double **slots[] = {&S.r, &S.p, &S.q, &S.dinv, &S.z, &S.w, &S.rh, &S.ph, &S.v, &S.s};
+    for (int k = 0; k < nvec; ++k) *slots[k] = vec + k * vs;
+    if (method == HSLA_METHOD_BICGSTAB) {
+        S.sh = S.z;  // s_hat
+        S.t = S.w;
+    }
+    const int64_t max_iter = o.max_iter > 0 ? o.max_iter : (10 * n < 100000 ? 10 * n : 100000);
+    const dim3 g(G, B);
+    k_reset<<<1, kBlock, 0, s>>>(S.st, S.cnt, B, max_iter);
+    if (o.use_x0) k_spmv<<<g, kBlock, 0, s>>>(A, values, x, S.q);
+    if (method == HSLA_METHOD_CG) {
+        switch (pre) {
+            case PRE_NONE: k_cg_init<PRE_NONE><<<g, kBlock, 0, s>>>(A, S, o.use_x0, o.rtol, o.atol); break;
+            case PRE_JACOBI: k_cg_init<PRE_JACOBI><<<g, kBlock, 0, s>>>(A, S, o.use_x0, o.rtol, o.atol); break;
+            default:
+                k_cg_init<PRE_FSAI><<<g, kBlock, 0, s>>>(A, S, o.use_x0, o.rtol, o.atol);
+                k_fsai_lower<<<g, kBlock, 0, s>>>(A, c.L, S);
+                k_fsai_upper_dot<<<g, kBlock, 0, s>>>(A, c.U, S, 1);
+                k_cg_direction<PRE_FSAI><<<g, kBlock, 0, s>>>(A, S);
+                break;
+        }
+    } else {
+        if (pre == PRE_JACOBI)
+            k_bicg_init<PRE_JACOBI><<<g, kBlock, 0, s>>>(A, S, o.use_x0, o.rtol, o.atol);
+        else
+            k_bicg_init<PRE_NONE><<<g, kBlock, 0, s>>>(A, S, o.use_x0, o.rtol, o.atol);
+    }
+    HSLA_HIP(h, hipGetLastError());
+
+    // chunks of iterations, one host check per chunk
+    int chunk = o.check_every > 0 ? o.check_every : 8;
+    const int chunk_cap = o.check_every > 0 ? o.check_every : 64;
+    hipEvent_t *ev = nullptr;
+    if (o.profile) {
+        st = ensure_prof_events(h, chunk_cap > chunk ? chunk_cap : chunk);
+        if (st != HSLA_OK) return st;
+        ev = h->prof_ev;
+    }
+    double prof_ms = 0.0;
+    int64_t prof_n = 0;
+    SysState *hs = h->h_state;
+    int64_t run = 0, last_iters = 0;
+    int pending = 0;  // launches of the previous chunk not yet accounted
+    for (;;) {
+        HSLA_HIP(h, hipMemcpyAsync(hs, S.st, sizeof(SysState) * B, hipMemcpyDeviceToHost, s));
+        HSLA_HIP(h, hipStreamSynchronize(s));
+        if (ev && pending > 0) {
+            // launches that did work: the largest per-system iteration advance
+            int64_t most = 0;
+            for (int i = 0; i < B; ++i) most = hs[i].iters > most ? hs[i].iters : most;
+            const int64_t worked = most - last_iters;
+            last_iters = most;
+            for (int64_t k = 0; k < worked && k < pending; ++k) {
+                float ms = 0.f;
+                HSLA_HIP(h, hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+                prof_ms += ms;
+                ++prof_n;
+            }
+            pending = 0;
+        }
+        bool all_done = true;
+        for (int i = 0; i < B; ++i)
+            if (!hs[i].done) {
+                all_done = false;
+                break;
+            }
+        if (all_done || run >= max_iter + 2) break;
+        if (chunk > chunk_cap) chunk = chunk_cap;
+        st = run_chunk(h, c, chunk, o.use_graph != 0, s, ev);
+        if (st != HSLA_OK) return st;
+        run += chunk;
+        pending = chunk;
+        if (chunk < chunk_cap) chunk *= 2;
+    }
+    // true residual ||b - A x|| / ||b||
+    double *res = (double *)(ws + lay.off_res);
+    k_residual<<<g, kBlock, 0, s>>>(A, S, res);
+    HSLA_HIP(h, hipGetLastError());
+    std::vector<double> hres(2 * (size_t)B);
+    HSLA_HIP(h, hipMemcpyAsync(hres.data(), res, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s));
+    HSLA_HIP(h, hipStreamSynchronize(s));
+    int worst = HSLA_OK;
+    for (int i = 0; i < B; ++i) {
+        const int sst = hs[i].done ? hs[i].status : HSLA_ERR_INTERNAL;
+        worst = worst_status(worst, sst);
+        if (infos) {
+            hsla_info &f = infos[i];
+            f.iters = hs[i].iters;
+            f.status = sst;
+            f.method = method;
+            const double bn = hs[i].bnorm;
+            const double rn = std::sqrt(hs[i].rnorm2);
+            f.rel_residual = bn > 0 ? rn / bn : rn;
+            const double tr = std::sqrt(hres[2 * i]), tb = std::sqrt(hres[2 * i + 1]);
+            f.true_residual = tb > 0 ? tr / tb : tr;
+            f.spmv_ms = prof_ms;
+            f.spmv_launches = prof_n;
+        }
+    }
+    return (hsla_status)worst;
+}
+
+static hsla_status check_common(hsla_handle *h, const hsla_pattern *p, int B, hipStream_t user) {
+    if (!h) return HSLA_ERR_INVALID_ARG;
+    if (!p) return set_error(h, HSLA_ERR_INVALID_ARG, "null pattern");
+    if (p->device != h->device) return set_error(h, HSLA_ERR_INVALID_ARG, "pattern on another device");
+    if (B < 0) return set_error(h, HSLA_ERR_INVALID_ARG, "negative batch");
+    return enter(h, user);
+}
+
+// True when the pattern equals its transpose and every system's values are
+// symmetric bit for bit (the paper detects symmetry on the values).
+static hsla_status values_symmetric(hsla_handle *h, const hsla_pattern *p, int B, const double *values, hipStream_t s,
+                                    bool *sym) {
+    if (!p->pattern_symmetric) {
+        *sym = false;
+        return HSLA_OK;
+    }
+    HSLA_HIP(h, hipMemsetAsync(h->d_flags, 0, sizeof(int32_t), s));
+    if (p->nnz > 0 && B > 0) {
+        const int64_t tot = p->nnz * B;
+        int blocks = (int)((tot + kBlock - 1) / kBlock);
+        if (blocks > 8192) blocks = 8192;
+        k_value_asym<<<blocks, kBlock, 0, s>>>(p->nnz, B, values, p->srcT, h->d_flags);
+        HSLA_HIP(h, hipGetLastError());
+    }
+    int32_t hf = 0;
+    HSLA_HIP(h, hipMemcpyAsync(&hf, h->d_flags, sizeof hf, hipMemcpyDeviceToHost, s));
+    HSLA_HIP(h, hipStreamSynchronize(s));
+    *sym = hf == 0;
+    return HSLA_OK;
+}
+
+static hsla_status read_opts(hsla_handle *h, const hsla_opts *opts, hsla_opts *o) {
+    if (opts)
+        *o = *opts;
+    else
+        hsla_opts_default(o);
+    if (!(o->rtol >= 0) || !(o->atol >= 0)) return set_error(h, HSLA_ERR_INVALID_ARG, "negative or NaN tolerance");
+    if (o->method < HSLA_METHOD_AUTO || o->method > HSLA_METHOD_BICGSTAB)
+        return set_error(h, HSLA_ERR_INVALID_ARG, "unknown method %d", o->method);
+    if (o->precond < HSLA_PRECOND_NONE || o->precond > HSLA_PRECOND_FSAI)
+        return set_error(h, HSLA_ERR_INVALID_ARG, "unknown preconditioner %d", o->precond);
+    return HSLA_OK;
+}
+
+static void trivial_infos(hsla_info *infos, int B) {
+    for (int i = 0; infos && i < B; ++i) {
+        std::memset(&infos[i], 0, sizeof infos[i]);
+        infos[i].method = HSLA_METHOD_CG;
+    }
+}
+
+hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *b, double *x,
+                        const hsla_opts *opts, hsla_info *infos, hipStream_t user) {
+    hsla_status st = check_common(h, p, B, user);
+    if (st != HSLA_OK) return st;
+    hipStream_t s = h->stream;
+    hsla_opts o;
+    st = read_opts(h, opts, &o);
+    if (st != HSLA_OK) return st;
+    if (B == 0) return HSLA_OK;
+    if (p->n == 0) {
+        trivial_infos(infos, B);
+        return HSLA_OK;
+    }
+    if (!values || !b || !x) return set_error(h, HSLA_ERR_INVALID_ARG, "null values, b or x");
+    int method = o.method;
+    if (method == HSLA_METHOD_AUTO) {
+        bool sym = false;
+        st = values_symmetric(h, p, B, values, s, &sym);
+        if (st != HSLA_OK) return st;
+        method = sym ? HSLA_METHOD_CG : HSLA_METHOD_BICGSTAB;
+    }
+    Pat A{p->row_ptr, p->col, p->diag, p->tiles, p->ntiles, p->n, p->nnz};
+    FPat L{}, U{};
+    if (o.precond == HSLA_PRECOND_FSAI) {
+        if (!o.d_G || !o.d_GT) return set_error(h, HSLA_ERR_INVALID_ARG, "FSAI needs d_G and d_GT");
+        L = FPat{p->rpL, p->colL, p->tilesL, p->ntilesL, p->nnz_lower, o.d_G};
+        U = FPat{p->rpU, p->colU, p->tilesU, p->ntilesU, p->nnz_lower, o.d_GT};
+    }
+    return solve_core(h, A, &L, &U, B, values, b, x, o, method, infos, s);
+}
+
+// Eq. adjoint_linear: A^T lambda = gx, gb = lambda, gA = -lambda x^T on the
+// pattern.  A symmetric A is iterated on directly; otherwise the values are
+// permuted into the transpose's entry order and the transpose's pattern is
+// iterated on.
+hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *x,
+                          const double *gx, double *gA, double *gb, const hsla_opts *opts, hsla_info *infos,
+                          hipStream_t user) {
+    hsla_status st = check_common(h, p, B, user);
+    if (st != HSLA_OK) return st;
+    hipStream_t s = h->stream;
+    hsla_opts o;
+    st = read_opts(h, opts, &o);
+    if (st != HSLA_OK) return st;
+    if (o.use_x0) return set_error(h, HSLA_ERR_INVALID_ARG, "use_x0 is not supported by the adjoint");
+    if (o.precond == HSLA_PRECOND_FSAI) return set_error(h, HSLA_ERR_INVALID_ARG, "the adjoint uses Jacobi or none");
+    if (B == 0) return HSLA_OK;
+    if (p->n == 0) {
+        trivial_infos(infos, B);
+        return HSLA_OK;
+    }
+    if (!values || !x || !gx) return set_error(h, HSLA_ERR_INVALID_ARG, "null values, x or gx");
+    bool sym = false;
+    st = values_symmetric(h, p, B, values, s, &sym);
+    if (st != HSLA_OK) return st;
+    const int method = o.method != HSLA_METHOD_AUTO ? o.method : (sym ? HSLA_METHOD_CG : HSLA_METHOD_BICGSTAB);
+    const int64_t n = p->n;
+    double *lam = gb, *lam_own = nullptr, *valT = nullptr;
+    if (!lam) {
+        HSLA_HIP(h, hipMalloc((void **)&lam_own, sizeof(double) * (size_t)B * n));
+        lam = lam_own;
+    }
+    hsla_status res;
+    if (sym) {
+        Pat A{p->row_ptr, p->col, p->diag, p->tiles, p->ntiles, p->n, p->nnz};
+        res = solve_core(h, A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s);
+    } else {
+        if (hipMalloc((void **)&valT, sizeof(double) * (size_t)B * (p->nnz > 0 ? p->nnz : 1)) != hipSuccess) {
+            if (lam_own) (void)hipFree(lam_own);
+            return set_error(h, HSLA_ERR_NO_MEMORY, "transposed values");
+        }
+        const int64_t tot = p->nnz * B;
+        int blocks = (int)((tot + kBlock - 1) / kBlock);
+        if (blocks > 8192) blocks = 8192;
+        if (tot > 0) k_gather_values<<<blocks, kBlock, 0, s>>>(p->nnz, B, values, p->srcT, valT);
+        Pat AT{p->rpT, p->colT, p->diagT, p->tilesT, p->ntilesT, p->n, p->nnz};
+        res = solve_core(h, AT, nullptr, nullptr, B, valT, gx, lam, o, method, infos, s);
+    }
+    if (res >= 0 && gA) {
+        int Gr = (int)((n + kBlock - 1) / kBlock);
+        if (Gr > 4096) Gr = 4096;
+        k_outer<<<dim3(Gr, B), kBlock, 0, s>>>(p->n, p->nnz, p->row_ptr, p->col, lam, x, gA);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) res = set_error(h, HSLA_ERR_HIP, "outer product: %s", hipGetErrorString(e));
+    }
+    const hipError_t se = hipStreamSynchronize(s);
+    if (valT) (void)hipFree(valT);
+    if (lam_own) (void)hipFree(lam_own);
+    if (se != hipSuccess) return set_error(h, HSLA_ERR_HIP, "adjoint: %s", hipGetErrorString(se));
+    return res;
+}
+
+}  // namespace hsla
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+hsla_status hsla_spmv(hsla_handle *h, const hsla_pattern *p, int32_t B, const double *d_values, const double *d_x,
+                      double *d_y, void *stream) {
+    hsla_status st = hsla::check_common(h, p, B, (hipStream_t)stream);
+    if (st != HSLA_OK) return st;
+    if (B > 0 && p->n > 0 && (!d_values || !d_x || !d_y))
+        return hsla::set_error(h, HSLA_ERR_INVALID_ARG, "null pointer");
+    st = hsla::launch_spmv(h, p, B, d_values, d_x, d_y, h->stream);
+    if (st != HSLA_OK) return st;
+    HSLA_HIP(h, hipStreamSynchronize(h->stream));
+    return HSLA_OK;
+}
+
+hsla_status hsla_solve(hsla_handle *h, const hsla_pattern *p, const double *d_values, const double *d_b, double *d_x,
+                       const hsla_opts *opts, hsla_info *info, void *stream) {
+    return hsla::solve_entry(h, p, 1, d_values, d_b, d_x, opts, info, (hipStream_t)stream);
+}
+
+hsla_status hsla_solve_batched(hsla_handle *h, const hsla_pattern *p, int32_t B, const double *d_values,
+                               const double *d_b, double *d_x, const hsla_opts *opts, hsla_info *infos, void *stream) {
+    return hsla::solve_entry(h, p, B, d_values, d_b, d_x, opts, infos, (hipStream_t)stream);
+}
+
+hsla_status hsla_adjoint(hsla_handle *h, const hsla_pattern *p, const double *d_values, const double *d_x,
+                         const double *d_gx, double *d_gA, double *d_gb, const hsla_opts *opts, hsla_info *info,
+                         void *stream) {
+    return hsla::adjoint_entry(h, p, 1, d_values, d_x, d_gx, d_gA, d_gb, opts, info, (hipStream_t)stream);
+}
+
+hsla_status hsla_adjoint_batched(hsla_handle *h, const hsla_pattern *p, int32_t B, const double *d_values,
+                                 const double *d_x, const double *d_gx, double *d_gA, double *d_gb,
+                                 const hsla_opts *opts, hsla_info *infos, void *stream) {
+    return hsla::adjoint_entry(h, p, B, d_values, d_x, d_gx, d_gA, d_gb, opts, infos, (hipStream_t)stream);
+}
+
+hsla_status hsla_outer_on_pattern(hsla_handle *h, const hsla_pattern *p, int32_t B, const double *d_lambda,
+                                  const double *d_x, double *d_gA, void *stream) {
+    hsla_status st = hsla::check_common(h, p, B, (hipStream_t)stream);
+    if (st != HSLA_OK) return st;
+    if (B == 0 || p->n == 0) return HSLA_OK;
+    if (!d_lambda || !d_x || !d_gA) return hsla::set_error(h, HSLA_ERR_INVALID_ARG, "null pointer");
+    int G = (int)((p->n + hsla::kBlock - 1) / hsla::kBlock);
+    if (G > 4096) G = 4096;
+    hsla::k_outer<<<dim3(G, B), hsla::kBlock, 0, h->stream>>>(p->n, p->nnz, p->row_ptr, p->col, d_lambda, d_x, d_gA);
+    HSLA_HIP(h, hipGetLastError());
+    HSLA_HIP(h, hipStreamSynchronize(h->stream));
+    return HSLA_OK;
+}
+
+hsla_status hsla_residual_norms(hsla_handle *h, const hsla_pattern *p, int32_t B, const double *d_values,
+                                const double *d_b, const double *d_x, double *res_norm, double *b_norm, void *stream) {
+    hsla_status st = hsla::check_common(h, p, B, (hipStream_t)stream);
+    if (st != HSLA_OK) return st;
+    if (B == 0) return HSLA_OK;
+    if (p->n > 0 && (!d_values || !d_b || !d_x)) return hsla::set_error(h, HSLA_ERR_INVALID_ARG, "null pointer");
+    hipStream_t s = h->stream;
+    const int G = hsla::grid_blocks(h, hsla::kWavesPerBlock, p->ntiles, 1);
+    const hsla::Layout lay = hsla::make_layout(B, p->n, 0, G);
+    st = hsla::ensure_workspace(h, lay.total);
+    if (st != HSLA_OK) return st;
+    char *ws = (char *)h->ws;
+    hsla::Sys S{};
+    S.val = d_values;
+    S.b = d_b;
+    S.x = const_cast<double *>(d_x);
+    S.st = (hsla::SysState *)(ws + lay.off_state);
+    S.cnt = (unsigned *)(ws + lay.off_cnt);
+    S.part = (double *)(ws + lay.off_part);
+    hsla::k_reset<<<1, hsla::kBlock, 0, s>>>(S.st, S.cnt, B, 1);
+    const hsla::Pat A{p->row_ptr, p->col, p->diag, p->tiles, p->ntiles, p->n, p->nnz};
+    double *res = (double *)(ws + lay.off_res);
+    std::vector<double> hr(2 * (size_t)B, 0.0);
+    if (p->n > 0) {
+        hsla::k_residual<<<dim3(G, B), hsla::kBlock, 0, s>>>(A, S, res);
+        HSLA_HIP(h, hipGetLastError());
+        HSLA_HIP(h, hipMemcpyAsync(hr.data(), res, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s));
+    }
+    HSLA_HIP(h, hipStreamSynchronize(s));
+    for (int i = 0; i < B; ++i) {
+        if (res_norm) res_norm[i] = std::sqrt(hr[2 * i]);
+        if (b_norm) b_norm[i] = std::sqrt(hr[2 * i + 1]);
+    }
+    return HSLA_OK;
+}
+
+}  // extern "C"

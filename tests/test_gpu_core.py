@@ -1,0 +1,311 @@
+"""GPU parity of the core path (SpMV, pattern ingest, CG/PCG, BiCGStab,
+adjoint) against the CPU oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from gpu_common import dev, iters_close, pattern, rel, solve, t32, t64  # noqa: E402
+from paper_2601_13994_amd import _lib  # noqa: E402
+
+
+def _rand_csr(n, density, seed, long_rows=(), int_vals=False):
+    r = np.random.default_rng(seed)
+    m = r.random((n, n)) < density
+    for i in long_rows:
+        m[i, :] = True
+    np.fill_diagonal(m, True)
+    a = W.from_dense(np.where(m, 1.0, 0.0), keep=m)
+    a.val = (r.integers(-1000, 1000, a.nnz).astype(np.float64) if int_vals else r.standard_normal(a.nnz))
+    return a
+
+
+# ---------------------------------------------------------------- pattern ingest
+
+def test_pattern_rejects_invalid_csr():
+    good = W.poisson2d(5)
+    cases = []
+    rp = good.row_ptr.copy(); rp[3], rp[4] = rp[4], rp[3]; cases.append((rp, good.col))   # decreasing
+    c = good.col.copy(); c[7] = good.n; cases.append((good.row_ptr, c))                     # out of range
+    c = good.col.copy(); c[0], c[1] = c[1], c[0]; cases.append((good.row_ptr, c))           # unsorted
+    c = good.col.copy(); c[1] = c[0]; cases.append((good.row_ptr, c))                       # duplicate
+    rp = good.row_ptr.copy(); rp[-1] -= 1; cases.append((rp, good.col))                     # rp[n] != nnz
+    c = good.col.copy(); c[5] = -3; cases.append((good.row_ptr, c))                         # negative
+    for rp, c in cases:
+        with pytest.raises(_lib.HslaError) as e:
+            _lib.Pattern(t32(rp), t32(c))
+        assert e.value.status == _lib.ERR_INVALID_CSR
+
+
+def test_pattern_transpose_exact(orc):
+    for seed, (n, d) in enumerate([(1, 1.0), (57, 0.08), (700, 0.01)]):
+        a = _rand_csr(n, d, seed)
+        pat = pattern(a)
+        rpT, colT, src = pat.transpose()
+        t, srco = orc.transpose(a)
+        assert np.array_equal(rpT.cpu().numpy(), t.row_ptr)
+        assert np.array_equal(colT.cpu().numpy(), t.col)
+        assert np.array_equal(src.cpu().numpy(), srco)
+        assert pat.nnz_lower == int(np.sum(a.col <= a.rows()))
+    assert pattern(W.poisson2d(6)).pattern_symmetric
+    assert not pattern(_rand_csr(40, 0.1, 9)).pattern_symmetric
+
+
+# ---------------------------------------------------------------- SpMV
+
+@pytest.mark.parametrize("n,density,seed", [(1, 1.0, 0), (63, 0.1, 1), (64, 0.1, 2), (1000, 0.005, 3),
+                                            (4097, 0.001, 4)])
+def test_spmv_bitwise(orc, n, density, seed):
+    """Each row adds its rounded products in ascending column order, exactly
+    as the oracle does, so the results agree bit for bit for any values."""
+    a = _rand_csr(n, density, seed)
+    x = np.random.default_rng(seed + 7).standard_normal(n)
+    y = _lib.spmv(pattern(a), t64(a.val), t64(x)).cpu().numpy()
+    assert np.array_equal(y, orc.spmv(a, x))
+
+
+def test_spmv_long_rows_and_empty_rows(orc):
+    """Rows longer than one LDS tile (split across lanes) with integer data
+    (exact under any order), and empty rows."""
+    a = _rand_csr(1500, 0.002, 5, long_rows=(3, 700, 1499), int_vals=True)
+    x = np.random.default_rng(1).integers(-1000, 1000, a.n).astype(np.float64)
+    y = _lib.spmv(pattern(a), t64(a.val), t64(x)).cpu().numpy()
+    assert np.array_equal(y, orc.spmv(a, x))
+    e = W.Csr(4, np.array([0, 0, 2, 2, 3], np.int32), np.array([0, 3, 1], np.int32), np.array([2.0, 3.0, 5.0]))
+    y = _lib.spmv(pattern(e), t64(e.val), t64(np.array([1.0, 2.0, 3.0, 4.0]))).cpu().numpy()
+    assert np.array_equal(y, np.array([0.0, 14.0, 0.0, 10.0]))
+
+
+def test_spmv_batched(orc):
+    a = W.diffusion3d(7, W.diffusion3d_kappa(7))
+    r = np.random.default_rng(3)
+    V = np.stack([a.val * r.uniform(0.5, 2.0) for _ in range(3)])
+    X = r.standard_normal((3, a.n))
+    Y = _lib.spmv(pattern(a), t64(V), t64(X)).cpu().numpy()
+    for s in range(3):
+        assert np.array_equal(Y[s], orc.spmv(a.with_values(V[s]), X[s]))
+
+
+# ---------------------------------------------------------------- CG / PCG
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_cg_poisson2d_parity(orc, precond):
+    """2D 5-point Poisson 64 x 64 (n = 4096), the small adjoint-check problem
+    of the paper: ||x_gpu - x_oracle|| / ||x_oracle|| <= 1e-8 at rtol 1e-12."""
+    a, b = W.poisson2d_workload(64)
+    x, info, st = solve(a, b, method="cg", precond=precond, rtol=1e-12)
+    ref = orc.cg(a, b, precond=precond, rtol=1e-12)
+    assert st == 0 and info[0]["status"] == 0
+    assert rel(x, ref.x) <= 1e-8
+    assert iters_close(info[0]["iters"], ref.iters)
+    assert info[0]["true_residual"] <= 2e-12
+
+
+def test_pcg_diffusion3d_parity(orc):
+    """3D log-normal diffusion (the large workload's operator) at m = 24."""
+    m = 24
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m))
+    b = W.rng(2, 1).standard_normal(a.n)
+    x, info, st = solve(a, b, precond="jacobi", rtol=1e-12)
+    ref = orc.cg(a, b, precond="jacobi", rtol=1e-12)
+    assert st == 0 and info[0]["method"] == "cg"
+    assert rel(x, ref.x) <= 1e-8
+    assert iters_close(info[0]["iters"], ref.iters)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_cg_random_spd_parity(orc, seed):
+    r = np.random.default_rng(seed)
+    a = W.random_spd(300, 0.02, r)
+    b = r.standard_normal(a.n)
+    x, info, st = solve(a, b, precond="jacobi", rtol=1e-12)
+    ref = orc.cg(a, b, precond="jacobi", rtol=1e-12)
+    assert st == 0 and rel(x, ref.x) <= 1e-8
+
+
+def test_cg_finite_termination():
+    n = 300
+    b = np.random.default_rng(1).standard_normal(n)
+    x, info, st = solve(W.from_dense(np.eye(n)), b, method="cg", precond="none", rtol=1e-14)
+    assert info[0]["iters"] == 1 and np.array_equal(x, b)
+    d = np.random.default_rng(2).uniform(1, 100, n)
+    x, info, _ = solve(W.from_dense(np.diag(d)), b, precond="jacobi", rtol=1e-14)
+    assert info[0]["iters"] == 1 and rel(x, b / d) < 1e-15
+
+
+# ---------------------------------------------------------------- BiCGStab
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_bicgstab_upwind_parity(orc, precond):
+    m = 12
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m), velocity=10.0)
+    b = W.rng(2, 1).standard_normal(a.n)
+    x, info, st = solve(a, b, precond=precond, rtol=1e-12)
+    ref = orc.bicgstab(a, b, precond=precond, rtol=1e-12)
+    assert st == 0 and info[0]["method"] == "bicgstab"
+    assert rel(x, ref.x) <= 1e-8
+    assert iters_close(info[0]["iters"], ref.iters)
+
+
+def test_bicgstab_pure_upwind_exact():
+    """Triangular operator: the solution from forward substitution."""
+    import scipy.linalg
+
+    a = W.diffusion3d(10, velocity=10.0, diffusion=False)
+    b = np.random.default_rng(7).standard_normal(a.n)
+    xe = scipy.linalg.solve_triangular(a.to_dense(), b, lower=True)
+    x, info, st = solve(a, b, precond="jacobi", rtol=1e-14)
+    assert rel(x, xe) <= 1e-10
+
+
+def test_bicgstab_random_nonsym(orc):
+    r = np.random.default_rng(5)
+    a = W.random_nonsym(400, 0.02, r)
+    b = r.standard_normal(a.n)
+    x, info, st = solve(a, b, precond="jacobi", rtol=1e-12)
+    ref = orc.bicgstab(a, b, precond="jacobi", rtol=1e-12)
+    assert st == 0 and rel(x, ref.x) <= 1e-8
+
+
+def test_bicgstab_breakdown_reported():
+    a = W.from_dense(np.array([[0.0, 1.0], [1.0, 0.0]]), keep=np.ones((2, 2), bool))
+    x, info, st = solve(a, np.array([1.0, 0.0]), method="bicgstab", precond="none")
+    assert st == _lib.BREAKDOWN and np.all(np.isfinite(x))
+
+
+# ---------------------------------------------------------------- status codes
+
+def test_status_codes():
+    a, b = W.poisson2d_workload(16)
+    pat = pattern(a)
+    x, info, st = solve(a, b, pat=pat, max_iter=1)
+    assert st == _lib.NOT_CONVERGED and info[0]["iters"] == 1
+    x, info, st = solve(a, np.zeros(a.n), pat=pat)
+    assert st == 0 and info[0]["iters"] == 0 and not x.any()
+    bad = b.copy()
+    bad[3] = np.nan
+    with pytest.raises(_lib.HslaError) as e:
+        solve(a, bad, pat=pat)
+    assert e.value.status == _lib.ERR_NONFINITE
+    x, info, st = solve(a, b, pat=pat, values=t64(-a.val), method="cg")
+    assert st == _lib.BREAKDOWN
+    nodiag = W.Csr(2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0, 1.0]))
+    with pytest.raises(_lib.HslaError) as e:
+        solve(nodiag, np.ones(2), precond="jacobi")
+    assert e.value.status == _lib.ERR_ZERO_DIAGONAL
+
+
+def test_empty_system():
+    e = W.Csr(0, np.array([0], np.int32), np.zeros(0, np.int32), np.zeros(0))
+    x, info, st = solve(e, np.zeros(0))
+    assert st == 0 and x.size == 0
+
+
+# ---------------------------------------------------------------- determinism, graphs, batches
+
+def test_deterministic_and_graph_equal():
+    m = 20
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m))
+    b = W.rng(2, 1).standard_normal(a.n)
+    pat = pattern(a)
+    x1, i1, _ = solve(a, b, pat=pat, rtol=1e-10, graph=True)
+    x2, i2, _ = solve(a, b, pat=pat, rtol=1e-10, graph=True)
+    x3, i3, _ = solve(a, b, pat=pat, rtol=1e-10, graph=False)
+    x4, i4, _ = solve(a, b, pat=pat, rtol=1e-10, graph=False, check_every=5)
+    assert np.array_equal(x1, x2) and np.array_equal(x1, x3) and np.array_equal(x1, x4)
+    assert i1[0]["iters"] == i3[0]["iters"] == i4[0]["iters"]
+
+
+def test_batched_masks_and_independence(orc):
+    """Systems with very different iteration counts, a zero right-hand side
+    and an easy one, iterated in lock step: each equals its own solve bit for
+    bit and matches the oracle."""
+    m = 14
+    base = W.diffusion3d(m)
+    r = np.random.default_rng(11)
+    vals, bs = [], []
+    for s in range(5):
+        if s == 3:
+            vals.append(W.diffusion3d(m, np.full(m ** 3, 5.0)).val)  # constant coefficient
+        else:
+            vals.append(W.diffusion3d(m, np.exp((s + 0.5) * r.standard_normal(m ** 3))).val)
+        bs.append(np.zeros(base.n) if s == 2 else r.standard_normal(base.n))
+    V, Bm = np.stack(vals), np.stack(bs)
+    pat = pattern(base)
+    opts = _lib.make_opts(precond="jacobi", rtol=1e-11)
+    X, infos, st = _lib.solve(pat, t64(V), t64(Bm), opts)
+    X = X.cpu().numpy()
+    assert st == 0
+    its = [f["iters"] for f in infos]
+    assert its[2] == 0 and not X[2].any()
+    assert len(set(its)) >= 3
+    for s in range(5):
+        xs, inf, _ = _lib.solve(pat, t64(V[s]), t64(Bm[s]), opts)
+        assert np.array_equal(xs.cpu().numpy(), X[s])
+        assert inf[0]["iters"] == its[s]
+        if s != 2:
+            ref = orc.cg(base.with_values(V[s]), Bm[s], precond="jacobi", rtol=1e-11)
+            assert rel(X[s], ref.x) <= 1e-7
+
+
+# ---------------------------------------------------------------- adjoint
+
+def test_outer_on_pattern_bitwise(orc):
+    a = _rand_csr(500, 0.01, 3)
+    r = np.random.default_rng(0)
+    lam = r.integers(-1000, 1000, a.n).astype(np.float64)
+    x = r.standard_normal(a.n)
+    g = _lib.outer_on_pattern(pattern(a), t64(lam), t64(x)).cpu().numpy()
+    assert np.array_equal(g, orc.adjoint_grad(a, lam, x))
+
+
+@pytest.mark.parametrize("kind", ["spd", "nonsym"])
+def test_adjoint_parity(orc, kind):
+    m = 10
+    if kind == "spd":
+        a = W.diffusion3d(m, W.diffusion3d_kappa(m, cfg=4))
+    else:
+        a = W.diffusion3d(m, W.diffusion3d_kappa(m, cfg=4), velocity=10.0)
+    r = np.random.default_rng(2)
+    b, xs = r.standard_normal(a.n), r.standard_normal(a.n)
+    x = orc.solve(a, b, precond="jacobi", rtol=1e-13).x
+    gx = x - xs
+    pat = pattern(a)
+    opts = _lib.make_opts(precond="jacobi", rtol=1e-13)
+    gA, gb, infos, st = _lib.adjoint(pat, t64(a.val), t64(x), t64(gx), opts)
+    gA_o, gb_o, _ = orc.adjoint(a, x, gx, precond="jacobi", rtol=1e-13)
+    assert st == 0
+    assert rel(gb.cpu().numpy(), gb_o) <= 1e-6
+    assert rel(gA.cpu().numpy(), gA_o) <= 1e-6
+    # dense brute force
+    lam = np.linalg.solve(a.to_dense().T, gx)
+    assert rel(gb.cpu().numpy(), lam) <= 1e-8
+
+
+def test_autograd_one_node_and_gradients(orc):
+    import paper_2601_13994_amd as hs
+
+    m = 8
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m, cfg=4))
+    r = np.random.default_rng(4)
+    b_np, xs_np = r.standard_normal(a.n), r.standard_normal(a.n)
+    vals = t64(a.val).requires_grad_(True)
+    b = t64(b_np).requires_grad_(True)
+    A = hs.SparseCSR(vals, t32(a.row_ptr), t32(a.col), shape=(a.n, a.n))
+    x = A.solve(b, rtol=1e-13)
+    assert type(x.grad_fn).__name__ == "SolveFnBackward"
+    assert all(f[0] is None or "AccumulateGrad" in type(f[0]).__name__ for f in x.grad_fn.next_functions)
+    loss = 0.5 * ((x - t64(xs_np)) ** 2).sum()
+    loss.backward()
+    xo = orc.cg(a, b_np, precond="jacobi", rtol=1e-13).x
+    gA_o, gb_o, _ = orc.adjoint(a, xo, xo - xs_np, precond="jacobi", rtol=1e-13)
+    assert rel(vals.grad.cpu().numpy(), gA_o) <= 1e-6
+    assert rel(b.grad.cpu().numpy(), gb_o) <= 1e-6
