@@ -246,8 +246,10 @@ struct TileWalk {
 };
 
 // y_row = sum_k val[k] * x[col[k]] for the rows of one tile, one lane per
-// row.  Products are staged in LDS (`lds`: kTileCap doubles owned by this
-// wave) and each row adds its products in ascending k, so the row sum
+// row.  All value/column loads of the tile are issued first (clamped
+// indices, no branches), then all x gathers, so a wave keeps ~2 KB of loads
+// in flight.  Products are staged in LDS (`lds`: kTileCap doubles owned by
+// this wave) and each row adds its products in ascending k, so the row sum
 // associates exactly like the sequential definition.  A tile with more than
 // kTileCap entries holds a single row; the wave then splits it lane-strided
 // and combines with a butterfly.  Returns true on the lane that owns a row.
@@ -258,25 +260,37 @@ __device__ __forceinline__ bool tile_spmv(const int32_t *__restrict__ rp, const 
     const int lane = threadIdx.x & (kWave - 1);
     const int32_t k0 = rp[r0];
     const int32_t cnt = rp[r1] - k0;
+    row = r0 + lane;
+    const bool own = row < r1;
     if (cnt <= kTileCap) {
+        const int32_t rr = own ? row : r0;
+        const int32_t ra = rp[rr] - k0, rb = rp[rr + 1] - k0;
+        if (cnt > 0) {
+            constexpr int U = kTileCap / kWave;
+            VT v[U];
+            int32_t c[U];
 #pragma unroll
-        for (int u = 0; u < kTileCap / kWave; ++u) {
-            const int e = u * kWave + lane;
-            if (e < cnt) {
-                const int32_t k = k0 + e;
-                lds[e] = (double)val[k] * x[col[k]];
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = u * kWave + lane;
+                const int32_t k = k0 + (e < cnt ? e : cnt - 1);
+                v[u] = val[k];
+                c[u] = col[k];
+            }
+            double xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = u * kWave + lane;
+                if (e < cnt) lds[e] = (double)v[u] * xv[u];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        row = r0 + lane;
-        bool own = row < r1;
         double s = 0.0;
-        if (own) {
-            const int32_t a = rp[row] - k0, b = rp[row + 1] - k0;
-            for (int32_t k = a; k < b; ++k) s += lds[k];
-        }
+        if (own)
+            for (int32_t k = ra; k < rb; ++k) s += lds[k];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

@@ -194,6 +194,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(Pat A, Sys S) {
     }
 }
 
+// Grid-stride element loops: each thread takes 4 elements per trip
+// (i, i+S, i+2S, i+3S with S the grid's thread count) so that all their
+// loads are in flight together; the per-thread summation order is the
+// plain grid-stride order.
+#define GRID_LOOP_BEGIN(n)                                                           \
+    {                                                                                \
+        const int64_t n_ = (n);                                                      \
+        const int64_t S_ = (int64_t)gridDim.x * kBlock;                              \
+        int64_t i_ = (int64_t)blockIdx.x * kBlock + threadIdx.x;                     \
+        for (; i_ + 3 * S_ < n_; i_ += 4 * S_) {
+#define GRID_LOOP_TAIL \
+        }              \
+        for (; i_ < n_; i_ += S_) {
+#define GRID_LOOP_END \
+        }             \
+    }
+
 // x += alpha p, r -= alpha q, stop test on ||r||, then (Jacobi / none)
 // rho' = r.M^{-1}r, beta = rho'/rho.
 template <int PRE>
@@ -201,15 +218,36 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
     if (stopped(st)) return;
     const double alpha = st.alpha;
+    double *__restrict__ x = S.x + vo;
+    double *__restrict__ r = S.r + vo;
+    const double *__restrict__ p = S.p + vo;
+    const double *__restrict__ q = S.q + vo;
+    const double *__restrict__ dinv = S.dinv + vo;
     double acc[2] = {0.0, 0.0};  // r.r, r.z
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
-        const int64_t j = vo + i;
-        S.x[j] = S.x[j] + alpha * S.p[j];
-        const double ri = S.r[j] - alpha * S.q[j];
-        S.r[j] = ri;
-        acc[0] += ri * ri;
-        if (PRE == PRE_JACOBI) acc[1] += ri * (S.dinv[j] * ri);
-    }
+    GRID_LOOP_BEGIN(A.n)
+            double xv[4], pv[4], rv[4], qv[4], dv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t e = i_ + j * S_;
+                xv[j] = x[e]; pv[j] = p[e]; rv[j] = r[e]; qv[j] = q[e];
+                dv[j] = PRE == PRE_JACOBI ? dinv[e] : 1.0;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t e = i_ + j * S_;
+                x[e] = xv[j] + alpha * pv[j];
+                const double ri = rv[j] - alpha * qv[j];
+                r[e] = ri;
+                acc[0] += ri * ri;
+                if (PRE == PRE_JACOBI) acc[1] += ri * (dv[j] * ri);
+            }
+            GRID_LOOP_TAIL
+            x[i_] = x[i_] + alpha * p[i_];
+            const double ri = r[i_] - alpha * q[i_];
+            r[i_] = ri;
+            acc[0] += ri * ri;
+            if (PRE == PRE_JACOBI) acc[1] += ri * (dinv[i_] * ri);
+            GRID_LOOP_END
     if (PRE == PRE_NONE) acc[1] = acc[0];
     double tot[2];
     if (grid_sum<2>(acc, part, cnt, tot) && threadIdx.x == 0) {
@@ -240,17 +278,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
     (void)part;
     (void)cnt;
     const double beta = st.beta;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
-        const int64_t j = vo + i;
-        double zi;
-        if (PRE == PRE_JACOBI)
-            zi = S.dinv[j] * S.r[j];
-        else if (PRE == PRE_NONE)
-            zi = S.r[j];
-        else
-            zi = S.z[j];
-        S.p[j] = zi + beta * S.p[j];
-    }
+    double *__restrict__ p = S.p + vo;
+    const double *__restrict__ r = S.r + vo;
+    const double *__restrict__ dinv = S.dinv + vo;
+    const double *__restrict__ z = S.z + vo;
+    GRID_LOOP_BEGIN(A.n)
+            double zv[4], pv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t e = i_ + j * S_;
+                zv[j] = PRE == PRE_JACOBI ? dinv[e] * r[e] : PRE == PRE_NONE ? r[e] : z[e];
+                pv[j] = p[e];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) p[i_ + j * S_] = zv[j] + beta * pv[j];
+            GRID_LOOP_TAIL
+            const double zi = PRE == PRE_JACOBI ? dinv[i_] * r[i_] : PRE == PRE_NONE ? r[i_] : z[i_];
+            p[i_] = zi + beta * p[i_];
+            GRID_LOOP_END
 }
 
 // FSAI apply, first half: w = G r (G lower, float32 values, FP64 products).
@@ -401,19 +446,50 @@ __global__ __launch_bounds__(kBlock) void k_bicg_dir(Pat A, Sys S) {
     if (stopped(st)) return;
     const double beta = st.beta, omega = st.omega;
     const int restart = st.restart_pending;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
-        const int64_t j = vo + i;
-        const double ri = S.r[j];
-        double pi;
-        if (restart) {
-            S.rh[j] = ri;
-            pi = ri;
-        } else {
-            pi = ri + beta * (S.p[j] - omega * S.v[j]);
-        }
-        S.p[j] = pi;
-        S.ph[j] = PRE == PRE_JACOBI ? S.dinv[j] * pi : pi;
+    const double *__restrict__ r = S.r + vo;
+    const double *__restrict__ v = S.v + vo;
+    const double *__restrict__ dinv = S.dinv + vo;
+    double *__restrict__ p = S.p + vo;
+    double *__restrict__ ph = S.ph + vo;
+    double *__restrict__ rh = S.rh + vo;
+    if (restart) {
+        GRID_LOOP_BEGIN(A.n)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t e = i_ + j * S_;
+                    const double ri = r[e];
+                    rh[e] = ri;
+                    p[e] = ri;
+                    ph[e] = PRE == PRE_JACOBI ? dinv[e] * ri : ri;
+                }
+                    GRID_LOOP_TAIL
+                const double ri = r[i_];
+                rh[i_] = ri;
+                p[i_] = ri;
+                ph[i_] = PRE == PRE_JACOBI ? dinv[i_] * ri : ri;
+                    GRID_LOOP_END
+        return;
     }
+    GRID_LOOP_BEGIN(A.n)
+            double rv[4], pv[4], vv[4], dv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t e = i_ + j * S_;
+                rv[j] = r[e]; pv[j] = p[e]; vv[j] = v[e];
+                dv[j] = PRE == PRE_JACOBI ? dinv[e] : 1.0;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t e = i_ + j * S_;
+                const double pi = rv[j] + beta * (pv[j] - omega * vv[j]);
+                p[e] = pi;
+                ph[e] = PRE == PRE_JACOBI ? dv[j] * pi : pi;
+            }
+            GRID_LOOP_TAIL
+            const double pi = r[i_] + beta * (p[i_] - omega * v[i_]);
+            p[i_] = pi;
+            ph[i_] = PRE == PRE_JACOBI ? dinv[i_] * pi : pi;
+            GRID_LOOP_END
 }
 
 // v = A p_hat and r_hat.v; alpha = rho' / (r_hat.v).
@@ -461,14 +537,34 @@ __global__ __launch_bounds__(kBlock) void k_bicg_s(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
     if (stopped(st) || st.restart_pending) return;
     const double alpha = st.alpha;
+    const double *__restrict__ r = S.r + vo;
+    const double *__restrict__ v = S.v + vo;
+    const double *__restrict__ dinv = S.dinv + vo;
+    double *__restrict__ s = S.s + vo;
+    double *__restrict__ sh = S.sh + vo;
     double acc[1] = {0.0};
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
-        const int64_t j = vo + i;
-        const double si = S.r[j] - alpha * S.v[j];
-        S.s[j] = si;
-        S.sh[j] = PRE == PRE_JACOBI ? S.dinv[j] * si : si;
-        acc[0] += si * si;
-    }
+    GRID_LOOP_BEGIN(A.n)
+            double rv[4], vv[4], dv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t e = i_ + j * S_;
+                rv[j] = r[e]; vv[j] = v[e];
+                dv[j] = PRE == PRE_JACOBI ? dinv[e] : 1.0;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t e = i_ + j * S_;
+                const double si = rv[j] - alpha * vv[j];
+                s[e] = si;
+                sh[e] = PRE == PRE_JACOBI ? dv[j] * si : si;
+                acc[0] += si * si;
+            }
+            GRID_LOOP_TAIL
+            const double si = r[i_] - alpha * v[i_];
+            s[i_] = si;
+            sh[i_] = PRE == PRE_JACOBI ? dinv[i_] * si : si;
+            acc[0] += si * si;
+            GRID_LOOP_END
     double tot[1];
     if (grid_sum<1>(acc, part, cnt, tot) && threadIdx.x == 0) {
         st.iters += 1;
@@ -527,20 +623,50 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(Pat A, Sys S) {
     if (stopped(st) || st.restart_pending) return;
     const double alpha = st.alpha, omega = st.omega;
     const int sx = st.s_exit;
+    double *__restrict__ x = S.x + vo;
+    double *__restrict__ r = S.r + vo;
+    const double *__restrict__ ph = S.ph + vo;
+    const double *__restrict__ sh = S.sh + vo;
+    const double *__restrict__ s = S.s + vo;
+    const double *__restrict__ t = S.t + vo;
+    const double *__restrict__ rh = S.rh + vo;
     double acc[2] = {0.0, 0.0};  // r.r, r_hat.r
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
-        const int64_t j = vo + i;
-        double ri;
-        if (sx) {
-            S.x[j] = S.x[j] + alpha * S.ph[j];
-            ri = S.s[j];
-        } else {
-            S.x[j] = S.x[j] + (alpha * S.ph[j] + omega * S.sh[j]);
-            ri = S.s[j] - omega * S.t[j];
-        }
-        S.r[j] = ri;
-        acc[0] += ri * ri;
-        acc[1] += S.rh[j] * ri;
+    if (sx) {
+        GRID_LOOP_BEGIN(A.n)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t e = i_ + j * S_;
+                    x[e] = x[e] + alpha * ph[e];
+                    r[e] = s[e];
+                }
+                    GRID_LOOP_TAIL
+                x[i_] = x[i_] + alpha * ph[i_];
+                r[i_] = s[i_];
+                    GRID_LOOP_END
+    } else {
+        GRID_LOOP_BEGIN(A.n)
+                double xv[4], pv[4], shv[4], sv[4], tv[4], rhv[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t e = i_ + j * S_;
+                    xv[j] = x[e]; pv[j] = ph[e]; shv[j] = sh[e]; sv[j] = s[e]; tv[j] = t[e]; rhv[j] = rh[e];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t e = i_ + j * S_;
+                    x[e] = xv[j] + (alpha * pv[j] + omega * shv[j]);
+                    const double ri = sv[j] - omega * tv[j];
+                    r[e] = ri;
+                    acc[0] += ri * ri;
+                    acc[1] += rhv[j] * ri;
+                }
+                    GRID_LOOP_TAIL
+                x[i_] = x[i_] + (alpha * ph[i_] + omega * sh[i_]);
+                const double ri = s[i_] - omega * t[i_];
+                r[i_] = ri;
+                acc[0] += ri * ri;
+                acc[1] += rh[i_] * ri;
+                    GRID_LOOP_END
     }
     double tot[2];
     if (grid_sum<2>(acc, part, cnt, tot) && threadIdx.x == 0) {

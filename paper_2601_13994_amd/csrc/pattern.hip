@@ -40,9 +40,11 @@ hsla_status ensure_workspace(hsla_handle *h, size_t bytes) {
         return set_error(h, HSLA_ERR_NO_MEMORY, "workspace of %zu bytes: %s", want, hipGetErrorString(e));
     }
     h->ws_bytes = want;
-    // counters at the start of each region must begin at zero; every user
-    // clears what it needs, but a clean start makes a faulty launch visible
-    HSLA_HIP(h, hipMemset(h->ws, 0, want));
+    // Zero-fill on the handle's own stream and wait for it: that stream does
+    // not wait on the legacy null stream, so a plain hipMemset could land in
+    // the middle of the solve that follows.
+    HSLA_HIP(h, hipMemsetAsync(h->ws, 0, want, h->stream));
+    HSLA_HIP(h, hipStreamSynchronize(h->stream));
     return HSLA_OK;
 }
 

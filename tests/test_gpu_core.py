@@ -309,3 +309,15 @@ def test_autograd_one_node_and_gradients(orc):
     gA_o, gb_o, _ = orc.adjoint(a, xo, xo - xs_np, precond="jacobi", rtol=1e-13)
     assert rel(vals.grad.cpu().numpy(), gA_o) <= 1e-6
     assert rel(b.grad.cpu().numpy(), gb_o) <= 1e-6
+
+
+def test_workspace_growth_between_solves(orc):
+    """Solves of increasing size on one handle grow its workspace each time;
+    every solve must match the oracle (regression: the zero-fill of a grown
+    workspace once ran unordered with the solve that followed)."""
+    for m in (6, 10, 14, 18, 22, 26):
+        a = W.diffusion3d(m, W.diffusion3d_kappa(m))
+        b = W.rng(2, 1, m).standard_normal(a.n)
+        x, info, st = solve(a, b, precond="jacobi", rtol=1e-12)
+        ref = orc.cg(a, b, precond="jacobi", rtol=1e-12)
+        assert st == 0 and rel(x, ref.x) <= 1e-8 and iters_close(info[0]["iters"], ref.iters)
