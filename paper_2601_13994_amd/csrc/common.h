@@ -168,45 +168,35 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *sh) {
     __syncthreads();
 }
 
-// Single-pass deterministic grid reduction.  Every block of the system's
-// grid (gridDim.x blocks) calls this with its thread-local partial values.
-// Block partials go to part[j * G + block]; a ticket counter elects the
-// last block to arrive, which sums the G partials in a fixed order
-// (independent of arrival order) and returns true with the totals in
-// thread 0's `tot`.  The counter is reset for the next use.
+// Block partial of NV values: the block sums of every reducing kernel go to
+// part[j * G + block] with plain stores (G = gridDim.x).  A separate
+// one-block finalize kernel per system (reduce_partials) adds the G partials
+// in a fixed order once the producing kernel has completed, so the result
+// does not depend on block scheduling, and no atomics or cross-XCD fences
+// sit on the hot path (contended ticket atomics from thousands of blocks
+// serialize at the memory side).
 template <int NV>
-__device__ __forceinline__ bool grid_sum(double (&v)[NV], double *part, unsigned *counter,
-                                         double (&tot)[NV]) {
+__device__ __forceinline__ void block_partial(double (&v)[NV], double *part) {
     __shared__ double sh[NV * kWavesPerBlock];
-    __shared__ int is_last;
-    const unsigned G = gridDim.x;
     block_sum<NV>(v, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int j = 0; j < NV; ++j)
-            __hip_atomic_store(&part[(size_t)j * G + blockIdx.x], v[j], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (t == G - 1);
+        for (int j = 0; j < NV; ++j) part[(size_t)j * gridDim.x + blockIdx.x] = v[j];
     }
-    __syncthreads();
-    if (!is_last) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    double acc[NV];
+}
+
+// Sum of the G partials of each of NV values (fixed order); valid in
+// thread 0.  Called by all threads of a finalize block.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double *part, int G, double (&tot)[NV]) {
+    __shared__ double sh[NV * kWavesPerBlock];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
-    for (unsigned i = threadIdx.x; i < G; i += blockDim.x) {
+    for (int j = 0; j < NV; ++j) tot[j] = 0.0;
+    for (int i = threadIdx.x; i < G; i += blockDim.x) {
 #pragma unroll
-        for (int j = 0; j < NV; ++j)
-            acc[j] += __hip_atomic_load(&part[(size_t)j * G + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int j = 0; j < NV; ++j) tot[j] += part[(size_t)j * G + i];
     }
-    block_sum<NV>(acc, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) tot[j] = acc[j];
-        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return true;
+    block_sum<NV>(tot, sh);
 }
 
 // XCD-aware tile walk.  Blocks are dispatched round-robin over the 8 XCDs,

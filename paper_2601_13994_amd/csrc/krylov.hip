@@ -41,31 +41,51 @@ struct Sys {
     double *r, *p, *q, *dinv, *z, *w;
     double *rh, *ph, *v, *s, *sh, *t;
     SysState *st;       // [B]
-    double *part;       // [B][3][G]
-    unsigned *cnt;      // [B] (64-byte stride)
-    int32_t G;          // blocks per system of the launch that uses `part`
+    double *part;       // [B][3][G] block partials
+    int32_t G;          // blocks per system of every producing kernel
 };
 
 #define SYS_OFFSETS(S, A)                                               \
     const int sidx = blockIdx.y;                                        \
     const int64_t vo = (int64_t)sidx * (A).n;                           \
     SysState &st = (S).st[sidx];                                        \
-    double *part = (S).part + (int64_t)sidx * 3 * gridDim.x;            \
-    unsigned *cnt = (S).cnt + (int64_t)sidx * 16;
+    double *part = (S).part + (int64_t)sidx * 3 * gridDim.x;
+
+// Finalize kernels run one block per system (grid = B).
+#define FIN_OFFSETS(S)                                                  \
+    const int sidx = blockIdx.x;                                        \
+    SysState &st = (S).st[sidx];                                        \
+    const double *part = (S).part + (int64_t)sidx * 3 * (S).G;
 
 __device__ __forceinline__ bool stopped(const SysState &st) { return st.done != 0; }
+
+// Grid-stride element loops: each thread takes 4 elements per trip
+// (i, i+S, i+2S, i+3S with S the grid's thread count) so that all their
+// loads are in flight together; the per-thread summation order is the
+// plain grid-stride order.
+#define GRID_LOOP_BEGIN(n)                                                           \
+    {                                                                                \
+        const int64_t n_ = (n);                                                      \
+        const int64_t S_ = (int64_t)gridDim.x * kBlock;                              \
+        int64_t i_ = (int64_t)blockIdx.x * kBlock + threadIdx.x;                     \
+        for (; i_ + 3 * S_ < n_; i_ += 4 * S_) {
+#define GRID_LOOP_TAIL \
+        }              \
+        for (; i_ < n_; i_ += S_) {
+#define GRID_LOOP_END \
+        }             \
+    }
 
 // ---------------------------------------------------------------------------
 // State reset
 // ---------------------------------------------------------------------------
-__global__ void k_reset(SysState *st, unsigned *cnt, int B, int64_t max_iter) {
+__global__ void k_reset(SysState *st, int B, int64_t max_iter) {
     for (int i = threadIdx.x; i < B; i += blockDim.x) {
         SysState z;
         memset(&z, 0, sizeof z);
         z.max_iter = max_iter;
         z.rho = z.alpha = z.omega = 1.0;
         st[i] = z;
-        cnt[(int64_t)i * 16] = 0u;
     }
 }
 
@@ -97,9 +117,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Pat A, const double *__restrict
 enum { PRE_NONE = 0, PRE_JACOBI = 1, PRE_FSAI = 2 };
 
 // x = 0 or x0, r = b - A x0 (q holds A x0), z = M^{-1} r (Jacobi / none),
-// p = z, rho = r.z; stop test against max(rtol ||b||, atol).
+// p = z; partials of b.b, r.r, r.z.
 template <int PRE>
-__global__ __launch_bounds__(kBlock) void k_cg_init(Pat A, Sys S, int use_x0, double rtol, double atol) {
+__global__ __launch_bounds__(kBlock) void k_cg_init(Pat A, Sys S, int use_x0) {
     SYS_OFFSETS(S, A)
     const double *val = S.val + sidx * A.nnz;
     double acc[3] = {0.0, 0.0, 0.0};  // b.b, r.r, r.z
@@ -118,46 +138,49 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Pat A, Sys S, int use_x0, do
             S.dinv[vo + i] = di;
             zi = di * ri;
         }
-        if (PRE == PRE_FSAI)
-            S.p[vo + i] = 0.0;
-        else
-            S.p[vo + i] = zi;
+        S.p[vo + i] = PRE == PRE_FSAI ? 0.0 : zi;
         acc[0] += bi * bi;
         acc[1] += ri * ri;
         acc[2] += ri * zi;
     }
-    if (bad) __hip_atomic_store(&st.bad_diag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (bad) st.bad_diag = 1;
+    block_partial<3>(acc, part);
+}
+
+// ||b||, tol = max(rtol ||b||, atol), initial stop test, rho = r.z.
+template <int PRE>
+__global__ __launch_bounds__(kBlock) void k_fin_cg_init(Sys S, double rtol, double atol) {
+    FIN_OFFSETS(S)
     double tot[3];
-    if (grid_sum<3>(acc, part, cnt, tot) && threadIdx.x == 0) {
-        const double bn = sqrt(tot[0]);
-        double tol = rtol * bn;
-        if (atol > tol) tol = atol;
-        st.bnorm = bn;
-        st.tol = tol;
-        st.rnorm2 = tot[1];
-        st.iters = 0;
-        const double rn = sqrt(tot[1]);
-        if (__hip_atomic_load(&st.bad_diag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            st.status = HSLA_ERR_ZERO_DIAGONAL;
-            st.done = 1;
-        } else if (!isfinite(rn) || !isfinite(bn)) {
-            st.status = HSLA_ERR_NONFINITE;
-            st.done = 1;
-        } else if (rn <= tol) {
-            st.status = HSLA_OK;
-            st.done = 1;
-        } else if (st.max_iter <= 0) {
-            st.status = HSLA_NOT_CONVERGED;
-            st.done = 1;
-        } else {
-            st.rho = (PRE == PRE_FSAI) ? 0.0 : tot[2];
-            st.beta = 0.0;
-        }
+    reduce_partials<3>(part, S.G, tot);
+    if (threadIdx.x != 0) return;
+    const double bn = sqrt(tot[0]);
+    double tol = rtol * bn;
+    if (atol > tol) tol = atol;
+    st.bnorm = bn;
+    st.tol = tol;
+    st.rnorm2 = tot[1];
+    st.iters = 0;
+    const double rn = sqrt(tot[1]);
+    if (st.bad_diag) {
+        st.status = HSLA_ERR_ZERO_DIAGONAL;
+        st.done = 1;
+    } else if (!isfinite(rn) || !isfinite(bn)) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+    } else if (rn <= tol) {
+        st.status = HSLA_OK;
+        st.done = 1;
+    } else if (st.max_iter <= 0) {
+        st.status = HSLA_NOT_CONVERGED;
+        st.done = 1;
+    } else {
+        st.rho = (PRE == PRE_FSAI) ? 0.0 : tot[2];
+        st.beta = 0.0;
     }
 }
 
-// q = A p and sigma = p.q; alpha = rho / sigma, or breakdown if sigma <= 0.
-template <int PRE>
+// q = A p and partials of sigma = p.q.
 __global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(Pat A, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
@@ -179,40 +202,29 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(Pat A, Sys S) {
             acc[0] += p[row] * yv;
         }
     }
+    block_partial<1>(acc, part);
+}
+
+// alpha = rho / sigma, or breakdown if sigma <= 0.
+__global__ __launch_bounds__(kBlock) void k_fin_alpha(Sys S) {
+    FIN_OFFSETS(S)
+    if (stopped(st)) return;
     double tot[1];
-    if (grid_sum<1>(acc, part, cnt, tot) && threadIdx.x == 0) {
-        const double sigma = tot[0];
-        if (!isfinite(sigma)) {
-            st.status = HSLA_ERR_NONFINITE;
-            st.done = 1;
-        } else if (!(sigma > 0.0)) {
-            st.status = HSLA_BREAKDOWN;
-            st.done = 1;
-        } else {
-            st.alpha = st.rho / sigma;
-        }
+    reduce_partials<1>(part, S.G, tot);
+    if (threadIdx.x != 0) return;
+    const double sigma = tot[0];
+    if (!isfinite(sigma)) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+    } else if (!(sigma > 0.0)) {
+        st.status = HSLA_BREAKDOWN;
+        st.done = 1;
+    } else {
+        st.alpha = st.rho / sigma;
     }
 }
 
-// Grid-stride element loops: each thread takes 4 elements per trip
-// (i, i+S, i+2S, i+3S with S the grid's thread count) so that all their
-// loads are in flight together; the per-thread summation order is the
-// plain grid-stride order.
-#define GRID_LOOP_BEGIN(n)                                                           \
-    {                                                                                \
-        const int64_t n_ = (n);                                                      \
-        const int64_t S_ = (int64_t)gridDim.x * kBlock;                              \
-        int64_t i_ = (int64_t)blockIdx.x * kBlock + threadIdx.x;                     \
-        for (; i_ + 3 * S_ < n_; i_ += 4 * S_) {
-#define GRID_LOOP_TAIL \
-        }              \
-        for (; i_ < n_; i_ += S_) {
-#define GRID_LOOP_END \
-        }             \
-    }
-
-// x += alpha p, r -= alpha q, stop test on ||r||, then (Jacobi / none)
-// rho' = r.M^{-1}r, beta = rho'/rho.
+// x += alpha p, r -= alpha q; partials of r.r and (Jacobi) r.D^{-1}r.
 template <int PRE>
 __global__ __launch_bounds__(kBlock) void k_cg_update(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
@@ -241,32 +253,40 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Pat A, Sys S) {
                 acc[0] += ri * ri;
                 if (PRE == PRE_JACOBI) acc[1] += ri * (dv[j] * ri);
             }
-            GRID_LOOP_TAIL
+    GRID_LOOP_TAIL
             x[i_] = x[i_] + alpha * p[i_];
             const double ri = r[i_] - alpha * q[i_];
             r[i_] = ri;
             acc[0] += ri * ri;
             if (PRE == PRE_JACOBI) acc[1] += ri * (dinv[i_] * ri);
-            GRID_LOOP_END
+    GRID_LOOP_END
     if (PRE == PRE_NONE) acc[1] = acc[0];
+    block_partial<2>(acc, part);
+}
+
+// Stop test on ||r||, then (Jacobi / none) rho' = r.z, beta = rho'/rho.
+template <int PRE>
+__global__ __launch_bounds__(kBlock) void k_fin_beta(Sys S) {
+    FIN_OFFSETS(S)
+    if (stopped(st)) return;
     double tot[2];
-    if (grid_sum<2>(acc, part, cnt, tot) && threadIdx.x == 0) {
-        st.iters += 1;
-        st.rnorm2 = tot[0];
-        const double rn = sqrt(tot[0]);
-        if (!isfinite(rn)) {
-            st.status = HSLA_ERR_NONFINITE;
-            st.done = 1;
-        } else if (rn <= st.tol) {
-            st.status = HSLA_OK;
-            st.done = 1;
-        } else if (st.iters >= st.max_iter) {
-            st.status = HSLA_NOT_CONVERGED;
-            st.done = 1;
-        } else if (PRE != PRE_FSAI) {
-            st.beta = tot[1] / st.rho;
-            st.rho = tot[1];
-        }
+    reduce_partials<2>(part, S.G, tot);
+    if (threadIdx.x != 0) return;
+    st.iters += 1;
+    st.rnorm2 = tot[0];
+    const double rn = sqrt(tot[0]);
+    if (!isfinite(rn)) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+    } else if (rn <= st.tol) {
+        st.status = HSLA_OK;
+        st.done = 1;
+    } else if (st.iters >= st.max_iter) {
+        st.status = HSLA_NOT_CONVERGED;
+        st.done = 1;
+    } else if (PRE != PRE_FSAI) {
+        st.beta = tot[1] / st.rho;
+        st.rho = tot[1];
     }
 }
 
@@ -274,9 +294,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Pat A, Sys S) {
 template <int PRE>
 __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
-    if (stopped(st)) return;
     (void)part;
-    (void)cnt;
+    if (stopped(st)) return;
     const double beta = st.beta;
     double *__restrict__ p = S.p + vo;
     const double *__restrict__ r = S.r + vo;
@@ -292,10 +311,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) p[i_ + j * S_] = zv[j] + beta * pv[j];
-            GRID_LOOP_TAIL
+    GRID_LOOP_TAIL
             const double zi = PRE == PRE_JACOBI ? dinv[i_] * r[i_] : PRE == PRE_NONE ? r[i_] : z[i_];
             p[i_] = zi + beta * p[i_];
-            GRID_LOOP_END
+    GRID_LOOP_END
 }
 
 // FSAI apply, first half: w = G r (G lower, float32 values, FP64 products).
@@ -303,7 +322,6 @@ __global__ __launch_bounds__(kBlock) void k_fsai_lower(Pat A, FPat L, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
     (void)part;
-    (void)cnt;
     if (stopped(st)) return;
     const float *g = L.val + sidx * L.nnz;
     const double *r = S.r + vo;
@@ -320,10 +338,8 @@ __global__ __launch_bounds__(kBlock) void k_fsai_lower(Pat A, FPat L, Sys S) {
     }
 }
 
-// FSAI apply, second half: z = G^T w and rho' = r.z; in the set-up phase
-// rho = rho' (p = z follows from beta = 0 and p = 0), in an iteration
-// beta = rho'/rho, rho = rho'.
-__global__ __launch_bounds__(kBlock) void k_fsai_upper_dot(Pat A, FPat U, Sys S, int setup) {
+// FSAI apply, second half: z = G^T w and partials of r.z.
+__global__ __launch_bounds__(kBlock) void k_fsai_upper_dot(Pat A, FPat U, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
     if (stopped(st)) return;
@@ -345,18 +361,26 @@ __global__ __launch_bounds__(kBlock) void k_fsai_upper_dot(Pat A, FPat U, Sys S,
             acc[0] += r[row] * yv;
         }
     }
+    block_partial<1>(acc, part);
+}
+
+// Set-up: rho = r.z (p = z follows from beta = 0 and p = 0); iteration:
+// beta = rho'/rho, rho = rho'.
+__global__ __launch_bounds__(kBlock) void k_fin_fsai(Sys S, int setup) {
+    FIN_OFFSETS(S)
+    if (stopped(st)) return;
     double tot[1];
-    if (grid_sum<1>(acc, part, cnt, tot) && threadIdx.x == 0) {
-        if (!isfinite(tot[0])) {
-            st.status = HSLA_ERR_NONFINITE;
-            st.done = 1;
-        } else if (setup) {
-            st.rho = tot[0];
-            st.beta = 0.0;
-        } else {
-            st.beta = tot[0] / st.rho;
-            st.rho = tot[0];
-        }
+    reduce_partials<1>(part, S.G, tot);
+    if (threadIdx.x != 0) return;
+    if (!isfinite(tot[0])) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+    } else if (setup) {
+        st.rho = tot[0];
+        st.beta = 0.0;
+    } else {
+        st.beta = tot[0] / st.rho;
+        st.rho = tot[0];
     }
 }
 
@@ -384,7 +408,7 @@ __device__ __forceinline__ void bicg_breakdown(SysState &st) {
 }
 
 template <int PRE>
-__global__ __launch_bounds__(kBlock) void k_bicg_init(Pat A, Sys S, int use_x0, double rtol, double atol) {
+__global__ __launch_bounds__(kBlock) void k_bicg_init(Pat A, Sys S, int use_x0) {
     SYS_OFFSETS(S, A)
     const double *val = S.val + sidx * A.nnz;
     double acc[2] = {0.0, 0.0};  // b.b, r.r
@@ -407,32 +431,37 @@ __global__ __launch_bounds__(kBlock) void k_bicg_init(Pat A, Sys S, int use_x0, 
         acc[0] += bi * bi;
         acc[1] += ri * ri;
     }
-    if (bad) __hip_atomic_store(&st.bad_diag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (bad) st.bad_diag = 1;
+    block_partial<2>(acc, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_bicg_init(Sys S, double rtol, double atol) {
+    FIN_OFFSETS(S)
     double tot[2];
-    if (grid_sum<2>(acc, part, cnt, tot) && threadIdx.x == 0) {
-        const double bn = sqrt(tot[0]);
-        double tol = rtol * bn;
-        if (atol > tol) tol = atol;
-        st.bnorm = bn;
-        st.tol = tol;
-        st.rnorm2 = tot[1];
-        const double rn = sqrt(tot[1]);
-        if (__hip_atomic_load(&st.bad_diag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            st.status = HSLA_ERR_ZERO_DIAGONAL;
-            st.done = 1;
-        } else if (!isfinite(rn) || !isfinite(bn)) {
-            st.status = HSLA_ERR_NONFINITE;
-            st.done = 1;
-        } else if (rn <= tol) {
-            st.status = HSLA_OK;
-            st.done = 1;
-        } else if (st.max_iter <= 0) {
-            st.status = HSLA_NOT_CONVERGED;
-            st.done = 1;
-        } else {
-            st.rho_new = tot[1];  // r_hat.r with r_hat = r
-            st.beta = (st.rho_new / st.rho) * (st.alpha / st.omega);
-        }
+    reduce_partials<2>(part, S.G, tot);
+    if (threadIdx.x != 0) return;
+    const double bn = sqrt(tot[0]);
+    double tol = rtol * bn;
+    if (atol > tol) tol = atol;
+    st.bnorm = bn;
+    st.tol = tol;
+    st.rnorm2 = tot[1];
+    const double rn = sqrt(tot[1]);
+    if (st.bad_diag) {
+        st.status = HSLA_ERR_ZERO_DIAGONAL;
+        st.done = 1;
+    } else if (!isfinite(rn) || !isfinite(bn)) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+    } else if (rn <= tol) {
+        st.status = HSLA_OK;
+        st.done = 1;
+    } else if (st.max_iter <= 0) {
+        st.status = HSLA_NOT_CONVERGED;
+        st.done = 1;
+    } else {
+        st.rho_new = tot[1];  // r_hat.r with r_hat = r
+        st.beta = (st.rho_new / st.rho) * (st.alpha / st.omega);
     }
 }
 
@@ -442,7 +471,6 @@ template <int PRE>
 __global__ __launch_bounds__(kBlock) void k_bicg_dir(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
     (void)part;
-    (void)cnt;
     if (stopped(st)) return;
     const double beta = st.beta, omega = st.omega;
     const int restart = st.restart_pending;
@@ -462,12 +490,12 @@ __global__ __launch_bounds__(kBlock) void k_bicg_dir(Pat A, Sys S) {
                     p[e] = ri;
                     ph[e] = PRE == PRE_JACOBI ? dinv[e] * ri : ri;
                 }
-                    GRID_LOOP_TAIL
+        GRID_LOOP_TAIL
                 const double ri = r[i_];
                 rh[i_] = ri;
                 p[i_] = ri;
                 ph[i_] = PRE == PRE_JACOBI ? dinv[i_] * ri : ri;
-                    GRID_LOOP_END
+        GRID_LOOP_END
         return;
     }
     GRID_LOOP_BEGIN(A.n)
@@ -485,14 +513,14 @@ __global__ __launch_bounds__(kBlock) void k_bicg_dir(Pat A, Sys S) {
                 p[e] = pi;
                 ph[e] = PRE == PRE_JACOBI ? dv[j] * pi : pi;
             }
-            GRID_LOOP_TAIL
+    GRID_LOOP_TAIL
             const double pi = r[i_] + beta * (p[i_] - omega * v[i_]);
             p[i_] = pi;
             ph[i_] = PRE == PRE_JACOBI ? dinv[i_] * pi : pi;
-            GRID_LOOP_END
+    GRID_LOOP_END
 }
 
-// v = A p_hat and r_hat.v; alpha = rho' / (r_hat.v).
+// v = A p_hat and partials of r_hat.v.
 __global__ __launch_bounds__(kBlock) void k_bicg_spmv_v(Pat A, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
@@ -515,23 +543,29 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_v(Pat A, Sys S) {
             acc[0] += rh[row] * yv;
         }
     }
+    block_partial<1>(acc, part);
+}
+
+// alpha = rho' / (r_hat.v); clears a pending restart (it ran in k_bicg_dir).
+__global__ __launch_bounds__(kBlock) void k_fin_bicg_v(Sys S) {
+    FIN_OFFSETS(S)
+    if (stopped(st)) return;
     double tot[1];
-    if (grid_sum<1>(acc, part, cnt, tot) && threadIdx.x == 0) {
-        st.restart_pending = 0;
-        const double rv = tot[0];
-        if (!isfinite(rv)) {
-            st.status = HSLA_ERR_NONFINITE;
-            st.done = 1;
-        } else if (rv == 0.0) {
-            bicg_breakdown(st);
-        } else {
-            st.alpha = st.rho_new / rv;
-        }
+    reduce_partials<1>(part, S.G, tot);
+    if (threadIdx.x != 0) return;
+    st.restart_pending = 0;
+    const double rv = tot[0];
+    if (!isfinite(rv)) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+    } else if (rv == 0.0) {
+        bicg_breakdown(st);
+    } else {
+        st.alpha = st.rho_new / rv;
     }
 }
 
-// s = r - alpha v, s_hat = M^{-1} s, ||s||; ||s|| <= tol finishes the
-// solve in the update kernel with x += alpha p_hat.
+// s = r - alpha v, s_hat = M^{-1} s and partials of s.s.
 template <int PRE>
 __global__ __launch_bounds__(kBlock) void k_bicg_s(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
@@ -559,27 +593,35 @@ __global__ __launch_bounds__(kBlock) void k_bicg_s(Pat A, Sys S) {
                 sh[e] = PRE == PRE_JACOBI ? dv[j] * si : si;
                 acc[0] += si * si;
             }
-            GRID_LOOP_TAIL
+    GRID_LOOP_TAIL
             const double si = r[i_] - alpha * v[i_];
             s[i_] = si;
             sh[i_] = PRE == PRE_JACOBI ? dinv[i_] * si : si;
             acc[0] += si * si;
-            GRID_LOOP_END
+    GRID_LOOP_END
+    block_partial<1>(acc, part);
+}
+
+// Counts the iteration; ||s|| <= tol finishes the solve in the update kernel
+// with x += alpha p_hat.
+__global__ __launch_bounds__(kBlock) void k_fin_bicg_s(Sys S) {
+    FIN_OFFSETS(S)
+    if (stopped(st) || st.restart_pending) return;
     double tot[1];
-    if (grid_sum<1>(acc, part, cnt, tot) && threadIdx.x == 0) {
-        st.iters += 1;
-        st.snorm2 = tot[0];
-        const double sn = sqrt(tot[0]);
-        if (!isfinite(sn)) {
-            st.status = HSLA_ERR_NONFINITE;
-            st.done = 1;
-        } else if (sn <= st.tol) {
-            st.s_exit = 1;
-        }
+    reduce_partials<1>(part, S.G, tot);
+    if (threadIdx.x != 0) return;
+    st.iters += 1;
+    st.snorm2 = tot[0];
+    const double sn = sqrt(tot[0]);
+    if (!isfinite(sn)) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+    } else if (sn <= st.tol) {
+        st.s_exit = 1;
     }
 }
 
-// t = A s_hat, t.s and t.t; omega = t.s / t.t.
+// t = A s_hat and partials of t.s, t.t.
 __global__ __launch_bounds__(kBlock) void k_bicg_spmv_t(Pat A, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
@@ -603,21 +645,28 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_t(Pat A, Sys S) {
             acc[1] += yv * yv;
         }
     }
+    block_partial<2>(acc, part);
+}
+
+// omega = t.s / t.t.
+__global__ __launch_bounds__(kBlock) void k_fin_bicg_t(Sys S) {
+    FIN_OFFSETS(S)
+    if (stopped(st) || st.restart_pending || st.s_exit) return;
     double tot[2];
-    if (grid_sum<2>(acc, part, cnt, tot) && threadIdx.x == 0) {
-        if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-            st.status = HSLA_ERR_NONFINITE;
-            st.done = 1;
-        } else if (tot[1] == 0.0) {
-            bicg_breakdown(st);
-        } else {
-            st.omega = tot[0] / tot[1];
-        }
+    reduce_partials<2>(part, S.G, tot);
+    if (threadIdx.x != 0) return;
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+    } else if (tot[1] == 0.0) {
+        bicg_breakdown(st);
+    } else {
+        st.omega = tot[0] / tot[1];
     }
 }
 
-// x += alpha p_hat + omega s_hat, r = s - omega t, stop test on ||r||, then
-// rho' = r_hat.r and beta = (rho'/rho)(alpha/omega) for the next step.
+// x += alpha p_hat + omega s_hat, r = s - omega t (or, after the s test,
+// x += alpha p_hat, r = s); partials of r.r and r_hat.r.
 __global__ __launch_bounds__(kBlock) void k_bicg_update(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
     if (stopped(st) || st.restart_pending) return;
@@ -639,10 +688,10 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(Pat A, Sys S) {
                     x[e] = x[e] + alpha * ph[e];
                     r[e] = s[e];
                 }
-                    GRID_LOOP_TAIL
+        GRID_LOOP_TAIL
                 x[i_] = x[i_] + alpha * ph[i_];
                 r[i_] = s[i_];
-                    GRID_LOOP_END
+        GRID_LOOP_END
     } else {
         GRID_LOOP_BEGIN(A.n)
                 double xv[4], pv[4], shv[4], sv[4], tv[4], rhv[4];
@@ -660,44 +709,52 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(Pat A, Sys S) {
                     acc[0] += ri * ri;
                     acc[1] += rhv[j] * ri;
                 }
-                    GRID_LOOP_TAIL
+        GRID_LOOP_TAIL
                 x[i_] = x[i_] + (alpha * ph[i_] + omega * sh[i_]);
                 const double ri = s[i_] - omega * t[i_];
                 r[i_] = ri;
                 acc[0] += ri * ri;
                 acc[1] += rh[i_] * ri;
-                    GRID_LOOP_END
+        GRID_LOOP_END
     }
+    block_partial<2>(acc, part);
+}
+
+// Stop test on ||r||, then rho' = r_hat.r and beta = (rho'/rho)(alpha/omega).
+__global__ __launch_bounds__(kBlock) void k_fin_bicg_update(Sys S) {
+    FIN_OFFSETS(S)
+    if (stopped(st) || st.restart_pending) return;
     double tot[2];
-    if (grid_sum<2>(acc, part, cnt, tot) && threadIdx.x == 0) {
-        st.rnorm2 = tot[0];
-        const double rn = sqrt(tot[0]);
-        if (sx) {
-            st.status = HSLA_OK;
-            st.done = 1;
-            st.rnorm2 = st.snorm2;
-        } else if (!isfinite(rn)) {
+    reduce_partials<2>(part, S.G, tot);
+    if (threadIdx.x != 0) return;
+    const double omega = st.omega;
+    st.rnorm2 = tot[0];
+    const double rn = sqrt(tot[0]);
+    if (st.s_exit) {
+        st.status = HSLA_OK;
+        st.done = 1;
+        st.rnorm2 = st.snorm2;
+    } else if (!isfinite(rn)) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+    } else if (rn <= st.tol) {
+        st.status = HSLA_OK;
+        st.done = 1;
+    } else if (omega == 0.0) {
+        bicg_breakdown(st);
+    } else if (st.iters >= st.max_iter) {
+        st.status = HSLA_NOT_CONVERGED;
+        st.done = 1;
+    } else {
+        st.rho = st.rho_new;
+        st.rho_new = tot[1];
+        if (!isfinite(st.rho_new)) {
             st.status = HSLA_ERR_NONFINITE;
             st.done = 1;
-        } else if (rn <= st.tol) {
-            st.status = HSLA_OK;
-            st.done = 1;
-        } else if (omega == 0.0) {
+        } else if (st.rho_new == 0.0) {
             bicg_breakdown(st);
-        } else if (st.iters >= st.max_iter) {
-            st.status = HSLA_NOT_CONVERGED;
-            st.done = 1;
         } else {
-            st.rho = st.rho_new;
-            st.rho_new = tot[1];
-            if (!isfinite(st.rho_new)) {
-                st.status = HSLA_ERR_NONFINITE;
-                st.done = 1;
-            } else if (st.rho_new == 0.0) {
-                bicg_breakdown(st);
-            } else {
-                st.beta = (st.rho_new / st.rho) * (st.alpha / st.omega);
-            }
+            st.beta = (st.rho_new / st.rho) * (st.alpha / st.omega);
         }
     }
 }
@@ -706,8 +763,8 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(Pat A, Sys S) {
 // Residual, symmetry and adjoint helpers
 // ---------------------------------------------------------------------------
 
-// ||b - A x||^2 and ||b||^2 per system into out[2*s], out[2*s+1].
-__global__ __launch_bounds__(kBlock) void k_residual(Pat A, Sys S, double *out) {
+// Partials of ||b - A x||^2 and ||b||^2 per system.
+__global__ __launch_bounds__(kBlock) void k_residual(Pat A, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
     (void)st;
@@ -729,11 +786,17 @@ __global__ __launch_bounds__(kBlock) void k_residual(Pat A, Sys S, double *out) 
             acc[1] += b[row] * b[row];
         }
     }
+    block_partial<2>(acc, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_residual(Sys S, double *out) {
+    FIN_OFFSETS(S)
+    (void)st;
     double tot[2];
-    if (grid_sum<2>(acc, part, cnt, tot) && threadIdx.x == 0) {
-        out[2 * sidx] = tot[0];
-        out[2 * sidx + 1] = tot[1];
-    }
+    reduce_partials<2>(part, S.G, tot);
+    if (threadIdx.x != 0) return;
+    out[2 * sidx] = tot[0];
+    out[2 * sidx + 1] = tot[1];
 }
 
 // flag = 1 if val[s][src[k]] != val[s][k] for some system and entry.
@@ -777,7 +840,7 @@ __global__ __launch_bounds__(kBlock) void k_outer(int32_t n, int64_t nnz, const 
 // ---------------------------------------------------------------------------
 
 struct Layout {
-    size_t off_state, off_cnt, off_part, off_vec, off_res, total;
+    size_t off_state, off_part, off_vec, off_res, total;
 };
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -787,8 +850,6 @@ static Layout make_layout(int B, int64_t n, int nvec, int G) {
     size_t o = 0;
     L.off_state = o;
     o = align_up(o + sizeof(SysState) * B, 256);
-    L.off_cnt = o;
-    o = align_up(o + 64 * (size_t)B, 256);
     L.off_part = o;
     o = align_up(o + sizeof(double) * 3 * (size_t)G * B, 256);
     L.off_res = o;
@@ -820,31 +881,33 @@ struct SolveCall {
 };
 
 // Enqueues `iters` iterations.  With `ev` (profile mode) the SpMV(+dot)
-// launch of iteration k is bracketed by ev[2k], ev[2k+1].
+// launch of iteration k is bracketed by ev[2k], ev[2k+1].  Every reducing
+// kernel is followed by its one-block-per-system finalize kernel.
 static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hipEvent_t *ev) {
-    const dim3 g(c.G, c.B);
+    const dim3 g(c.G, c.B), gf(c.B);
     for (int k = 0; k < iters; ++k) {
         if (c.method == HSLA_METHOD_CG) {
             if (ev) (void)hipEventRecord(ev[2 * k], s);
-            switch (c.precond) {
-                case PRE_NONE: k_cg_spmv_dot<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S); break;
-                case PRE_JACOBI: k_cg_spmv_dot<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S); break;
-                default: k_cg_spmv_dot<PRE_FSAI><<<g, kBlock, 0, s>>>(c.A, c.S); break;
-            }
+            k_cg_spmv_dot<<<g, kBlock, 0, s>>>(c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
+            k_fin_alpha<<<gf, kBlock, 0, s>>>(c.S);
             switch (c.precond) {
                 case PRE_NONE:
                     k_cg_update<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S);
+                    k_fin_beta<PRE_NONE><<<gf, kBlock, 0, s>>>(c.S);
                     k_cg_direction<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S);
                     break;
                 case PRE_JACOBI:
                     k_cg_update<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S);
+                    k_fin_beta<PRE_JACOBI><<<gf, kBlock, 0, s>>>(c.S);
                     k_cg_direction<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S);
                     break;
                 default:
                     k_cg_update<PRE_FSAI><<<g, kBlock, 0, s>>>(c.A, c.S);
+                    k_fin_beta<PRE_FSAI><<<gf, kBlock, 0, s>>>(c.S);
                     k_fsai_lower<<<g, kBlock, 0, s>>>(c.A, c.L, c.S);
-                    k_fsai_upper_dot<<<g, kBlock, 0, s>>>(c.A, c.U, c.S, 0);
+                    k_fsai_upper_dot<<<g, kBlock, 0, s>>>(c.A, c.U, c.S);
+                    k_fin_fsai<<<gf, kBlock, 0, s>>>(c.S, 0);
                     k_cg_direction<PRE_FSAI><<<g, kBlock, 0, s>>>(c.A, c.S);
                     break;
             }
@@ -856,12 +919,16 @@ static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hip
             if (ev) (void)hipEventRecord(ev[2 * k], s);
             k_bicg_spmv_v<<<g, kBlock, 0, s>>>(c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
+            k_fin_bicg_v<<<gf, kBlock, 0, s>>>(c.S);
             if (c.precond == PRE_JACOBI)
                 k_bicg_s<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S);
             else
                 k_bicg_s<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S);
+            k_fin_bicg_s<<<gf, kBlock, 0, s>>>(c.S);
             k_bicg_spmv_t<<<g, kBlock, 0, s>>>(c.A, c.S);
+            k_fin_bicg_t<<<gf, kBlock, 0, s>>>(c.S);
             k_bicg_update<<<g, kBlock, 0, s>>>(c.A, c.S);
+            k_fin_bicg_update<<<gf, kBlock, 0, s>>>(c.S);
         }
     }
 }
@@ -968,7 +1035,6 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
     S.b = b;
     S.x = x;
     S.st = (SysState *)(ws + lay.off_state);
-    S.cnt = (unsigned *)(ws + lay.off_cnt);
     S.part = (double *)(ws + lay.off_part);
     S.G = G;
     double *vec = (double *)(ws + lay.off_vec);
@@ -980,25 +1046,34 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
         S.t = S.w;
     }
     const int64_t max_iter = o.max_iter > 0 ? o.max_iter : (10 * n < 100000 ? 10 * n : 100000);
-    const dim3 g(G, B);
-    k_reset<<<1, kBlock, 0, s>>>(S.st, S.cnt, B, max_iter);
+    const dim3 g(G, B), gf(B);
+    k_reset<<<1, kBlock, 0, s>>>(S.st, B, max_iter);
     if (o.use_x0) k_spmv<<<g, kBlock, 0, s>>>(A, values, x, S.q);
     if (method == HSLA_METHOD_CG) {
         switch (pre) {
-            case PRE_NONE: k_cg_init<PRE_NONE><<<g, kBlock, 0, s>>>(A, S, o.use_x0, o.rtol, o.atol); break;
-            case PRE_JACOBI: k_cg_init<PRE_JACOBI><<<g, kBlock, 0, s>>>(A, S, o.use_x0, o.rtol, o.atol); break;
+            case PRE_NONE:
+                k_cg_init<PRE_NONE><<<g, kBlock, 0, s>>>(A, S, o.use_x0);
+                k_fin_cg_init<PRE_NONE><<<gf, kBlock, 0, s>>>(S, o.rtol, o.atol);
+                break;
+            case PRE_JACOBI:
+                k_cg_init<PRE_JACOBI><<<g, kBlock, 0, s>>>(A, S, o.use_x0);
+                k_fin_cg_init<PRE_JACOBI><<<gf, kBlock, 0, s>>>(S, o.rtol, o.atol);
+                break;
             default:
-                k_cg_init<PRE_FSAI><<<g, kBlock, 0, s>>>(A, S, o.use_x0, o.rtol, o.atol);
+                k_cg_init<PRE_FSAI><<<g, kBlock, 0, s>>>(A, S, o.use_x0);
+                k_fin_cg_init<PRE_FSAI><<<gf, kBlock, 0, s>>>(S, o.rtol, o.atol);
                 k_fsai_lower<<<g, kBlock, 0, s>>>(A, c.L, S);
-                k_fsai_upper_dot<<<g, kBlock, 0, s>>>(A, c.U, S, 1);
+                k_fsai_upper_dot<<<g, kBlock, 0, s>>>(A, c.U, S);
+                k_fin_fsai<<<gf, kBlock, 0, s>>>(S, 1);
                 k_cg_direction<PRE_FSAI><<<g, kBlock, 0, s>>>(A, S);
                 break;
         }
     } else {
         if (pre == PRE_JACOBI)
-            k_bicg_init<PRE_JACOBI><<<g, kBlock, 0, s>>>(A, S, o.use_x0, o.rtol, o.atol);
+            k_bicg_init<PRE_JACOBI><<<g, kBlock, 0, s>>>(A, S, o.use_x0);
         else
-            k_bicg_init<PRE_NONE><<<g, kBlock, 0, s>>>(A, S, o.use_x0, o.rtol, o.atol);
+            k_bicg_init<PRE_NONE><<<g, kBlock, 0, s>>>(A, S, o.use_x0);
+        k_fin_bicg_init<<<gf, kBlock, 0, s>>>(S, o.rtol, o.atol);
     }
     HSLA_HIP(h, hipGetLastError());
 
@@ -1049,7 +1124,8 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
     }
     // true residual ||b - A x|| / ||b||
     double *res = (double *)(ws + lay.off_res);
-    k_residual<<<g, kBlock, 0, s>>>(A, S, res);
+    k_residual<<<g, kBlock, 0, s>>>(A, S);
+    k_fin_residual<<<gf, kBlock, 0, s>>>(S, res);
     HSLA_HIP(h, hipGetLastError());
     std::vector<double> hres(2 * (size_t)B);
     HSLA_HIP(h, hipMemcpyAsync(hres.data(), res, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s));
@@ -1290,14 +1366,15 @@ hsla_status hsla_residual_norms(hsla_handle *h, const hsla_pattern *p, int32_t B
     S.b = d_b;
     S.x = const_cast<double *>(d_x);
     S.st = (hsla::SysState *)(ws + lay.off_state);
-    S.cnt = (unsigned *)(ws + lay.off_cnt);
     S.part = (double *)(ws + lay.off_part);
-    hsla::k_reset<<<1, hsla::kBlock, 0, s>>>(S.st, S.cnt, B, 1);
+    S.G = G;
+    hsla::k_reset<<<1, hsla::kBlock, 0, s>>>(S.st, B, 1);
     const hsla::Pat A{p->row_ptr, p->col, p->diag, p->tiles, p->ntiles, p->n, p->nnz};
     double *res = (double *)(ws + lay.off_res);
     std::vector<double> hr(2 * (size_t)B, 0.0);
     if (p->n > 0) {
-        hsla::k_residual<<<dim3(G, B), hsla::kBlock, 0, s>>>(A, S, res);
+        hsla::k_residual<<<dim3(G, B), hsla::kBlock, 0, s>>>(A, S);
+        hsla::k_fin_residual<<<dim3(B), hsla::kBlock, 0, s>>>(S, res);
         HSLA_HIP(h, hipGetLastError());
         HSLA_HIP(h, hipMemcpyAsync(hr.data(), res, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s));
     }
