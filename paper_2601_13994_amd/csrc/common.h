@@ -51,20 +51,20 @@ struct hsla_pattern {
     int32_t *row_ptr = nullptr;  // [n+1]
     int32_t *col = nullptr;      // [nnz]
     int32_t *diag = nullptr;     // [n] position of the diagonal entry, -1 if absent
-    int32_t *tiles = nullptr;    // [ntiles+1] first row of each SpMV tile
+    int2 *meta = nullptr;         // [ntiles+1] (first row, first entry) of each SpMV tile
     int32_t ntiles = 0;
     int32_t *rpT = nullptr, *colT = nullptr, *srcT = nullptr;  // transpose
-    int32_t *tilesT = nullptr;
+    int2 *metaT = nullptr;
     int32_t ntilesT = 0;
     int32_t *diagT = nullptr;
     int32_t pattern_symmetric = 0;
     int64_t nnz_lower = 0;
     // lower triangle (incl. diagonal) for factorized approximate inverses
     int32_t *rpL = nullptr, *colL = nullptr, *posL = nullptr;   // posL: position in A
-    int32_t *tilesL = nullptr;
+    int2 *metaL = nullptr;
     int32_t ntilesL = 0;
     int32_t *rpU = nullptr, *colU = nullptr, *srcU = nullptr;   // L^T (upper) + perm into L order
-    int32_t *tilesU = nullptr;
+    int2 *metaU = nullptr;
     int32_t ntilesU = 0;
 };
 
@@ -113,10 +113,11 @@ hsla_status enter(hsla_handle *h, hipStream_t user);
 hsla_status ensure_workspace(hsla_handle *h, size_t bytes);
 hsla_status ensure_host_state(hsla_handle *h, size_t nsys);
 
-// Blocks per system for grid-stride kernels: a multiple of kXcds.
-inline int grid_blocks(const hsla_handle *h, int64_t work_items_per_block_unit, int64_t units, int nsys) {
-    int64_t want = (units + work_items_per_block_unit - 1) / work_items_per_block_unit;
-    int64_t cap = (int64_t)h->dev.num_cu * 8 / (nsys > 0 ? nsys : 1);
+// Blocks per system for grid-stride kernels: enough for `units` work items
+// at `per_block` each, at most `per_cu` blocks per CU, a multiple of kXcds.
+inline int grid_blocks(const hsla_handle *h, int64_t per_block, int64_t units, int nsys, int per_cu = 8) {
+    int64_t want = (units + per_block - 1) / per_block;
+    int64_t cap = (int64_t)h->dev.num_cu * per_cu / (nsys > 0 ? nsys : 1);
     if (cap < kXcds) cap = kXcds;
     if (want > cap) want = cap;
     if (want < 1) want = 1;
@@ -235,68 +236,109 @@ struct TileWalk {
     }
 };
 
-// y_row = sum_k val[k] * x[col[k]] for the rows of one tile, one lane per
-// row.  All value/column loads of the tile are issued first (clamped
-// indices, no branches), then all x gathers, so a wave keeps ~2 KB of loads
-// in flight.  Products are staged in LDS (`lds`: kTileCap doubles owned by
-// this wave) and each row adds its products in ascending k, so the row sum
-// associates exactly like the sequential definition.  A tile with more than
-// kTileCap entries holds a single row; the wave then splits it lane-strided
-// and combines with a butterfly.  Returns true on the lane that owns a row.
-template <typename VT>
-__device__ __forceinline__ bool tile_spmv(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                          const VT *__restrict__ val, const double *__restrict__ x,
-                                          int32_t r0, int32_t r1, double *lds, int32_t &row, double &y) {
+// Tiled CSR SpMV over the rows of a pattern: y_row = sum_k val[k] x[col[k]].
+//
+// A tile is a run of consecutive rows, at most kTileRows rows and kTileCap
+// stored entries (one lane per row); a row longer than kTileCap is a tile by
+// itself.  meta[t] = (first row, first entry) of tile t, meta[T] = (n, nnz).
+// Per tile, every lane loads kTileCap/64 values and column indices (clamped
+// inside the tile, nontemporal: the matrix stream is read once per sweep),
+// gathers x, and stages the products in LDS; each row then adds its own
+// products in ascending k, which associates exactly like the sequential
+// definition.  The walk is software-pipelined: the next tile's value and
+// column loads are in flight while the current tile gathers and sums.
+// epi(row, y) is called on the lane owning each row.
+template <typename VT, class Epi>
+__device__ __forceinline__ void spmv_tiles(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                           const VT *__restrict__ val, const double *__restrict__ x,
+                                           const int2 *__restrict__ meta, int32_t ntiles, double *lds, Epi &&epi) {
+    constexpr int U = kTileCap / kWave;
     const int lane = threadIdx.x & (kWave - 1);
-    const int32_t k0 = rp[r0];
-    const int32_t cnt = rp[r1] - k0;
-    row = r0 + lane;
-    const bool own = row < r1;
-    if (cnt <= kTileCap) {
-        const int32_t rr = own ? row : r0;
-        const int32_t ra = rp[rr] - k0, rb = rp[rr + 1] - k0;
-        if (cnt > 0) {
-            constexpr int U = kTileCap / kWave;
-            VT v[U];
-            int32_t c[U];
+    const TileWalk tw(ntiles);
+    const int R = tw.rounds();
+    int32_t t = tw.tile(0);
+    if (R == 0 || t < 0) return;
+    int2 m0 = meta[t], m1 = meta[t + 1];
+    VT v[U];
+    int32_t c[U];
+    int32_t ra = 0, rb = 0;
+    auto issue = [&](int2 a, int2 b, VT *vv, int32_t *cc, int32_t &qa, int32_t &qb) {
+        const int32_t k0 = a.y, cnt = b.y - a.y;
+        const int32_t row = a.x + lane;
+        const int32_t rr = row < b.x ? row : a.x;
+        qa = rp[rr] - k0;
+        qb = rp[rr + 1] - k0;
+        if (cnt > 0 && cnt <= kTileCap) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int32_t e = u * kWave + lane;
                 const int32_t k = k0 + (e < cnt ? e : cnt - 1);
-                v[u] = val[k];
-                c[u] = col[k];
+                vv[u] = __builtin_nontemporal_load(&val[k]);
+                cc[u] = __builtin_nontemporal_load(&col[k]);
             }
+        }
+    };
+    issue(m0, m1, v, c, ra, rb);
+    for (int r = 0; r < R; ++r) {
+        const int32_t tn = tw.tile(r + 1);
+        int2 n0 = m1, n1 = m1;
+        if (tn >= 0) {
+            n0 = meta[tn];
+            n1 = meta[tn + 1];
+        }
+        const int32_t cnt = m1.y - m0.y;
+        if (cnt > kTileCap) {
+            // one long row: lane-strided partial sums and a butterfly
+            double s = 0.0;
+            for (int32_t e = lane; e < cnt; e += kWave) {
+                const int32_t k = m0.y + e;
+                s += (double)val[k] * x[col[k]];
+            }
+            s = wave_sum(s);
+            if (lane == 0) epi(m0.x, s);
+        } else {
             double xv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+            for (int u = 0; u < U; ++u) xv[u] = cnt > 0 ? x[c[u]] : 0.0;
+            VT vn[U];
+            int32_t cn[U];
+            int32_t ran = 0, rbn = 0;
+            if (tn >= 0) issue(n0, n1, vn, cn, ran, rbn);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int32_t e = u * kWave + lane;
                 if (e < cnt) lds[e] = (double)v[u] * xv[u];
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int32_t row = m0.x + lane;
+            const bool own = row < m1.x;
+            double s = 0.0;
+            if (own)
+                for (int32_t k = ra; k < rb; ++k) s += lds[k];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (own) epi(row, s);
+            if (tn >= 0) {
+                ra = ran;
+                rb = rbn;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    v[u] = vn[u];
+                    c[u] = cn[u];
+                }
+            }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double s = 0.0;
-        if (own)
-            for (int32_t k = ra; k < rb; ++k) s += lds[k];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        y = s;
-        return own;
+        if (tn < 0) break;
+        if (m1.y - m0.y > kTileCap || n1.y - n0.y > kTileCap) {
+            // a long row breaks the pipeline: (re)issue the next tile now
+            issue(n0, n1, v, c, ra, rb);
+        }
+        m0 = n0;
+        m1 = n1;
     }
-    // one long row
-    double s = 0.0;
-    for (int32_t e = lane; e < cnt; e += kWave) {
-        const int32_t k = k0 + e;
-        s += (double)val[k] * x[col[k]];
-    }
-    s = wave_sum(s);
-    row = r0;
-    y = s;
-    return lane == 0;
 }
 
 }  // namespace hsla

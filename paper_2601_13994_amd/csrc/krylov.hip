@@ -21,13 +21,15 @@ namespace hsla {
 // Kernel argument bundles
 // ---------------------------------------------------------------------------
 struct Pat {
-    const int32_t *rp, *col, *diag, *tiles;
+    const int32_t *rp, *col, *diag;
+    const int2 *meta;
     int32_t ntiles, n;
     int64_t nnz;
 };
 
 struct FPat {  // pattern + values of one FSAI factor (float32 values)
-    const int32_t *rp, *col, *tiles;
+    const int32_t *rp, *col;
+    const int2 *meta;
     int32_t ntiles;
     int64_t nnz;
     const float *val;
@@ -41,8 +43,7 @@ struct Sys {
     double *r, *p, *q, *dinv, *z, *w;
     double *rh, *ph, *v, *s, *sh, *t;
     SysState *st;       // [B]
-    double *part;       // [B][3][G] block partials
-    int32_t G;          // blocks per system of every producing kernel
+    double *part;       // [B][3][G] block partials of the last producing kernel
 };
 
 #define SYS_OFFSETS(S, A)                                               \
@@ -52,10 +53,10 @@ struct Sys {
     double *part = (S).part + (int64_t)sidx * 3 * gridDim.x;
 
 // Finalize kernels run one block per system (grid = B).
-#define FIN_OFFSETS(S)                                                  \
+#define FIN_OFFSETS(S, G)                                               \
     const int sidx = blockIdx.x;                                        \
     SysState &st = (S).st[sidx];                                        \
-    const double *part = (S).part + (int64_t)sidx * 3 * (S).G;
+    const double *part = (S).part + (int64_t)sidx * 3 * (G);
 
 __device__ __forceinline__ bool stopped(const SysState &st) { return st.done != 0; }
 
@@ -99,16 +100,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Pat A, const double *__restrict
     val += sidx * A.nnz;
     x += sidx * A.n;
     y += sidx * A.n;
-    const TileWalk tw(A.ntiles);
-    const int R = tw.rounds();
-    double *my = lds[threadIdx.x / kWave];
-    for (int r = 0; r < R; ++r) {
-        const int32_t t = tw.tile(r);
-        if (t < 0) break;
-        int32_t row;
-        double yv;
-        if (tile_spmv(A.rp, A.col, val, x, A.tiles[t], A.tiles[t + 1], my, row, yv)) y[row] = yv;
-    }
+    spmv_tiles(A.rp, A.col, val, x, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+               [&](int32_t row, double yv) {
+                   y[row] = yv;
+               });
 }
 
 // ---------------------------------------------------------------------------
@@ -149,10 +144,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Pat A, Sys S, int use_x0) {
 
 // ||b||, tol = max(rtol ||b||, atol), initial stop test, rho = r.z.
 template <int PRE>
-__global__ __launch_bounds__(kBlock) void k_fin_cg_init(Sys S, double rtol, double atol) {
-    FIN_OFFSETS(S)
+__global__ __launch_bounds__(kBlock) void k_fin_cg_init(Sys S, int G, double rtol, double atol) {
+    FIN_OFFSETS(S, G)
     double tot[3];
-    reduce_partials<3>(part, S.G, tot);
+    reduce_partials<3>(part, G, tot);
     if (threadIdx.x != 0) return;
     const double bn = sqrt(tot[0]);
     double tol = rtol * bn;
@@ -188,29 +183,21 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(Pat A, Sys S) {
     const double *val = S.val + sidx * A.nnz;
     const double *p = S.p + vo;
     double *q = S.q + vo;
-    const TileWalk tw(A.ntiles);
-    const int R = tw.rounds();
-    double *my = lds[threadIdx.x / kWave];
     double acc[1] = {0.0};
-    for (int r = 0; r < R; ++r) {
-        const int32_t t = tw.tile(r);
-        if (t < 0) break;
-        int32_t row;
-        double yv;
-        if (tile_spmv(A.rp, A.col, val, p, A.tiles[t], A.tiles[t + 1], my, row, yv)) {
-            q[row] = yv;
-            acc[0] += p[row] * yv;
-        }
-    }
+    spmv_tiles(A.rp, A.col, val, p, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+               [&](int32_t row, double yv) {
+                   q[row] = yv;
+                   acc[0] += p[row] * yv;
+               });
     block_partial<1>(acc, part);
 }
 
 // alpha = rho / sigma, or breakdown if sigma <= 0.
-__global__ __launch_bounds__(kBlock) void k_fin_alpha(Sys S) {
-    FIN_OFFSETS(S)
+__global__ __launch_bounds__(kBlock) void k_fin_alpha(Sys S, int G) {
+    FIN_OFFSETS(S, G)
     if (stopped(st)) return;
     double tot[1];
-    reduce_partials<1>(part, S.G, tot);
+    reduce_partials<1>(part, G, tot);
     if (threadIdx.x != 0) return;
     const double sigma = tot[0];
     if (!isfinite(sigma)) {
@@ -266,11 +253,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Pat A, Sys S) {
 
 // Stop test on ||r||, then (Jacobi / none) rho' = r.z, beta = rho'/rho.
 template <int PRE>
-__global__ __launch_bounds__(kBlock) void k_fin_beta(Sys S) {
-    FIN_OFFSETS(S)
+__global__ __launch_bounds__(kBlock) void k_fin_beta(Sys S, int G) {
+    FIN_OFFSETS(S, G)
     if (stopped(st)) return;
     double tot[2];
-    reduce_partials<2>(part, S.G, tot);
+    reduce_partials<2>(part, G, tot);
     if (threadIdx.x != 0) return;
     st.iters += 1;
     st.rnorm2 = tot[0];
@@ -326,16 +313,10 @@ __global__ __launch_bounds__(kBlock) void k_fsai_lower(Pat A, FPat L, Sys S) {
     const float *g = L.val + sidx * L.nnz;
     const double *r = S.r + vo;
     double *w = S.w + vo;
-    const TileWalk tw(L.ntiles);
-    const int R = tw.rounds();
-    double *my = lds[threadIdx.x / kWave];
-    for (int rr = 0; rr < R; ++rr) {
-        const int32_t t = tw.tile(rr);
-        if (t < 0) break;
-        int32_t row;
-        double yv;
-        if (tile_spmv(L.rp, L.col, g, r, L.tiles[t], L.tiles[t + 1], my, row, yv)) w[row] = yv;
-    }
+    spmv_tiles(L.rp, L.col, g, r, L.meta, L.ntiles, lds[threadIdx.x / kWave],
+               [&](int32_t row, double yv) {
+                   w[row] = yv;
+               });
 }
 
 // FSAI apply, second half: z = G^T w and partials of r.z.
@@ -347,30 +328,22 @@ __global__ __launch_bounds__(kBlock) void k_fsai_upper_dot(Pat A, FPat U, Sys S)
     const double *w = S.w + vo;
     const double *r = S.r + vo;
     double *z = S.z + vo;
-    const TileWalk tw(U.ntiles);
-    const int R = tw.rounds();
-    double *my = lds[threadIdx.x / kWave];
     double acc[1] = {0.0};
-    for (int rr = 0; rr < R; ++rr) {
-        const int32_t t = tw.tile(rr);
-        if (t < 0) break;
-        int32_t row;
-        double yv;
-        if (tile_spmv(U.rp, U.col, g, w, U.tiles[t], U.tiles[t + 1], my, row, yv)) {
-            z[row] = yv;
-            acc[0] += r[row] * yv;
-        }
-    }
+    spmv_tiles(U.rp, U.col, g, w, U.meta, U.ntiles, lds[threadIdx.x / kWave],
+               [&](int32_t row, double yv) {
+                   z[row] = yv;
+                   acc[0] += r[row] * yv;
+               });
     block_partial<1>(acc, part);
 }
 
 // Set-up: rho = r.z (p = z follows from beta = 0 and p = 0); iteration:
 // beta = rho'/rho, rho = rho'.
-__global__ __launch_bounds__(kBlock) void k_fin_fsai(Sys S, int setup) {
-    FIN_OFFSETS(S)
+__global__ __launch_bounds__(kBlock) void k_fin_fsai(Sys S, int G, int setup) {
+    FIN_OFFSETS(S, G)
     if (stopped(st)) return;
     double tot[1];
-    reduce_partials<1>(part, S.G, tot);
+    reduce_partials<1>(part, G, tot);
     if (threadIdx.x != 0) return;
     if (!isfinite(tot[0])) {
         st.status = HSLA_ERR_NONFINITE;
@@ -435,10 +408,10 @@ __global__ __launch_bounds__(kBlock) void k_bicg_init(Pat A, Sys S, int use_x0) 
     block_partial<2>(acc, part);
 }
 
-__global__ __launch_bounds__(kBlock) void k_fin_bicg_init(Sys S, double rtol, double atol) {
-    FIN_OFFSETS(S)
+__global__ __launch_bounds__(kBlock) void k_fin_bicg_init(Sys S, int G, double rtol, double atol) {
+    FIN_OFFSETS(S, G)
     double tot[2];
-    reduce_partials<2>(part, S.G, tot);
+    reduce_partials<2>(part, G, tot);
     if (threadIdx.x != 0) return;
     const double bn = sqrt(tot[0]);
     double tol = rtol * bn;
@@ -529,29 +502,21 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_v(Pat A, Sys S) {
     const double *ph = S.ph + vo;
     const double *rh = S.rh + vo;
     double *v = S.v + vo;
-    const TileWalk tw(A.ntiles);
-    const int R = tw.rounds();
-    double *my = lds[threadIdx.x / kWave];
     double acc[1] = {0.0};
-    for (int r = 0; r < R; ++r) {
-        const int32_t t = tw.tile(r);
-        if (t < 0) break;
-        int32_t row;
-        double yv;
-        if (tile_spmv(A.rp, A.col, val, ph, A.tiles[t], A.tiles[t + 1], my, row, yv)) {
-            v[row] = yv;
-            acc[0] += rh[row] * yv;
-        }
-    }
+    spmv_tiles(A.rp, A.col, val, ph, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+               [&](int32_t row, double yv) {
+                   v[row] = yv;
+                   acc[0] += rh[row] * yv;
+               });
     block_partial<1>(acc, part);
 }
 
 // alpha = rho' / (r_hat.v); clears a pending restart (it ran in k_bicg_dir).
-__global__ __launch_bounds__(kBlock) void k_fin_bicg_v(Sys S) {
-    FIN_OFFSETS(S)
+__global__ __launch_bounds__(kBlock) void k_fin_bicg_v(Sys S, int G) {
+    FIN_OFFSETS(S, G)
     if (stopped(st)) return;
     double tot[1];
-    reduce_partials<1>(part, S.G, tot);
+    reduce_partials<1>(part, G, tot);
     if (threadIdx.x != 0) return;
     st.restart_pending = 0;
     const double rv = tot[0];
@@ -604,11 +569,11 @@ __global__ __launch_bounds__(kBlock) void k_bicg_s(Pat A, Sys S) {
 
 // Counts the iteration; ||s|| <= tol finishes the solve in the update kernel
 // with x += alpha p_hat.
-__global__ __launch_bounds__(kBlock) void k_fin_bicg_s(Sys S) {
-    FIN_OFFSETS(S)
+__global__ __launch_bounds__(kBlock) void k_fin_bicg_s(Sys S, int G) {
+    FIN_OFFSETS(S, G)
     if (stopped(st) || st.restart_pending) return;
     double tot[1];
-    reduce_partials<1>(part, S.G, tot);
+    reduce_partials<1>(part, G, tot);
     if (threadIdx.x != 0) return;
     st.iters += 1;
     st.snorm2 = tot[0];
@@ -630,30 +595,22 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_t(Pat A, Sys S) {
     const double *sh = S.sh + vo;
     const double *s = S.s + vo;
     double *t = S.t + vo;
-    const TileWalk tw(A.ntiles);
-    const int R = tw.rounds();
-    double *my = lds[threadIdx.x / kWave];
     double acc[2] = {0.0, 0.0};
-    for (int r = 0; r < R; ++r) {
-        const int32_t tl = tw.tile(r);
-        if (tl < 0) break;
-        int32_t row;
-        double yv;
-        if (tile_spmv(A.rp, A.col, val, sh, A.tiles[tl], A.tiles[tl + 1], my, row, yv)) {
-            t[row] = yv;
-            acc[0] += yv * s[row];
-            acc[1] += yv * yv;
-        }
-    }
+    spmv_tiles(A.rp, A.col, val, sh, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+               [&](int32_t row, double yv) {
+                   t[row] = yv;
+                   acc[0] += yv * s[row];
+                   acc[1] += yv * yv;
+               });
     block_partial<2>(acc, part);
 }
 
 // omega = t.s / t.t.
-__global__ __launch_bounds__(kBlock) void k_fin_bicg_t(Sys S) {
-    FIN_OFFSETS(S)
+__global__ __launch_bounds__(kBlock) void k_fin_bicg_t(Sys S, int G) {
+    FIN_OFFSETS(S, G)
     if (stopped(st) || st.restart_pending || st.s_exit) return;
     double tot[2];
-    reduce_partials<2>(part, S.G, tot);
+    reduce_partials<2>(part, G, tot);
     if (threadIdx.x != 0) return;
     if (!isfinite(tot[0]) || !isfinite(tot[1])) {
         st.status = HSLA_ERR_NONFINITE;
@@ -721,11 +678,11 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(Pat A, Sys S) {
 }
 
 // Stop test on ||r||, then rho' = r_hat.r and beta = (rho'/rho)(alpha/omega).
-__global__ __launch_bounds__(kBlock) void k_fin_bicg_update(Sys S) {
-    FIN_OFFSETS(S)
+__global__ __launch_bounds__(kBlock) void k_fin_bicg_update(Sys S, int G) {
+    FIN_OFFSETS(S, G)
     if (stopped(st) || st.restart_pending) return;
     double tot[2];
-    reduce_partials<2>(part, S.G, tot);
+    reduce_partials<2>(part, G, tot);
     if (threadIdx.x != 0) return;
     const double omega = st.omega;
     st.rnorm2 = tot[0];
@@ -771,29 +728,21 @@ __global__ __launch_bounds__(kBlock) void k_residual(Pat A, Sys S) {
     const double *val = S.val + sidx * A.nnz;
     const double *x = S.x + vo;
     const double *b = S.b + vo;
-    const TileWalk tw(A.ntiles);
-    const int R = tw.rounds();
-    double *my = lds[threadIdx.x / kWave];
     double acc[2] = {0.0, 0.0};
-    for (int r = 0; r < R; ++r) {
-        const int32_t t = tw.tile(r);
-        if (t < 0) break;
-        int32_t row;
-        double yv;
-        if (tile_spmv(A.rp, A.col, val, x, A.tiles[t], A.tiles[t + 1], my, row, yv)) {
-            const double e = b[row] - yv;
-            acc[0] += e * e;
-            acc[1] += b[row] * b[row];
-        }
-    }
+    spmv_tiles(A.rp, A.col, val, x, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+               [&](int32_t row, double yv) {
+                   const double e = b[row] - yv;
+                   acc[0] += e * e;
+                   acc[1] += b[row] * b[row];
+               });
     block_partial<2>(acc, part);
 }
 
-__global__ __launch_bounds__(kBlock) void k_fin_residual(Sys S, double *out) {
-    FIN_OFFSETS(S)
+__global__ __launch_bounds__(kBlock) void k_fin_residual(Sys S, int G, double *out) {
+    FIN_OFFSETS(S, G)
     (void)st;
     double tot[2];
-    reduce_partials<2>(part, S.G, tot);
+    reduce_partials<2>(part, G, tot);
     if (threadIdx.x != 0) return;
     out[2 * sidx] = tot[0];
     out[2 * sidx + 1] = tot[1];
@@ -863,8 +812,8 @@ static Layout make_layout(int B, int64_t n, int nvec, int G) {
 hsla_status launch_spmv(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *x,
                         double *y, hipStream_t s) {
     if (p->n == 0 || B == 0) return HSLA_OK;
-    Pat A{p->row_ptr, p->col, p->diag, p->tiles, p->ntiles, p->n, p->nnz};
-    const int G = grid_blocks(h, kWavesPerBlock, p->ntiles, 1);
+    Pat A{p->row_ptr, p->col, p->diag, p->meta, p->ntiles, p->n, p->nnz};
+    const int G = grid_blocks(h, kWavesPerBlock, p->ntiles, 1, 16);
     k_spmv<<<dim3(G, B), kBlock, 0, s>>>(A, values, x, y);
     HSLA_HIP(h, hipGetLastError());
     return HSLA_OK;
@@ -877,58 +826,59 @@ struct SolveCall {
     int B;
     int method;   // HSLA_METHOD_CG / BICGSTAB
     int precond;  // PRE_*
-    int G;        // blocks per system, shared by every kernel (partial stride)
+    int Gt, Gv;   // blocks per system: SpMV-based kernels, vector kernels
 };
 
 // Enqueues `iters` iterations.  With `ev` (profile mode) the SpMV(+dot)
 // launch of iteration k is bracketed by ev[2k], ev[2k+1].  Every reducing
 // kernel is followed by its one-block-per-system finalize kernel.
 static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hipEvent_t *ev) {
-    const dim3 g(c.G, c.B), gf(c.B);
+    const dim3 gt(c.Gt, c.B), gv(c.Gv, c.B), gf(c.B);
+    const int Gt = c.Gt, Gv = c.Gv;
     for (int k = 0; k < iters; ++k) {
         if (c.method == HSLA_METHOD_CG) {
             if (ev) (void)hipEventRecord(ev[2 * k], s);
-            k_cg_spmv_dot<<<g, kBlock, 0, s>>>(c.A, c.S);
+            k_cg_spmv_dot<<<gt, kBlock, 0, s>>>(c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
-            k_fin_alpha<<<gf, kBlock, 0, s>>>(c.S);
+            k_fin_alpha<<<gf, kBlock, 0, s>>>(c.S, Gt);
             switch (c.precond) {
                 case PRE_NONE:
-                    k_cg_update<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S);
-                    k_fin_beta<PRE_NONE><<<gf, kBlock, 0, s>>>(c.S);
-                    k_cg_direction<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S);
+                    k_cg_update<PRE_NONE><<<gv, kBlock, 0, s>>>(c.A, c.S);
+                    k_fin_beta<PRE_NONE><<<gf, kBlock, 0, s>>>(c.S, Gv);
+                    k_cg_direction<PRE_NONE><<<gv, kBlock, 0, s>>>(c.A, c.S);
                     break;
                 case PRE_JACOBI:
-                    k_cg_update<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S);
-                    k_fin_beta<PRE_JACOBI><<<gf, kBlock, 0, s>>>(c.S);
-                    k_cg_direction<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S);
+                    k_cg_update<PRE_JACOBI><<<gv, kBlock, 0, s>>>(c.A, c.S);
+                    k_fin_beta<PRE_JACOBI><<<gf, kBlock, 0, s>>>(c.S, Gv);
+                    k_cg_direction<PRE_JACOBI><<<gv, kBlock, 0, s>>>(c.A, c.S);
                     break;
                 default:
-                    k_cg_update<PRE_FSAI><<<g, kBlock, 0, s>>>(c.A, c.S);
-                    k_fin_beta<PRE_FSAI><<<gf, kBlock, 0, s>>>(c.S);
-                    k_fsai_lower<<<g, kBlock, 0, s>>>(c.A, c.L, c.S);
-                    k_fsai_upper_dot<<<g, kBlock, 0, s>>>(c.A, c.U, c.S);
-                    k_fin_fsai<<<gf, kBlock, 0, s>>>(c.S, 0);
-                    k_cg_direction<PRE_FSAI><<<g, kBlock, 0, s>>>(c.A, c.S);
+                    k_cg_update<PRE_FSAI><<<gv, kBlock, 0, s>>>(c.A, c.S);
+                    k_fin_beta<PRE_FSAI><<<gf, kBlock, 0, s>>>(c.S, Gv);
+                    k_fsai_lower<<<gt, kBlock, 0, s>>>(c.A, c.L, c.S);
+                    k_fsai_upper_dot<<<gt, kBlock, 0, s>>>(c.A, c.U, c.S);
+                    k_fin_fsai<<<gf, kBlock, 0, s>>>(c.S, Gt, 0);
+                    k_cg_direction<PRE_FSAI><<<gv, kBlock, 0, s>>>(c.A, c.S);
                     break;
             }
         } else {
             if (c.precond == PRE_JACOBI)
-                k_bicg_dir<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S);
+                k_bicg_dir<PRE_JACOBI><<<gv, kBlock, 0, s>>>(c.A, c.S);
             else
-                k_bicg_dir<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S);
+                k_bicg_dir<PRE_NONE><<<gv, kBlock, 0, s>>>(c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k], s);
-            k_bicg_spmv_v<<<g, kBlock, 0, s>>>(c.A, c.S);
+            k_bicg_spmv_v<<<gt, kBlock, 0, s>>>(c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
-            k_fin_bicg_v<<<gf, kBlock, 0, s>>>(c.S);
+            k_fin_bicg_v<<<gf, kBlock, 0, s>>>(c.S, Gt);
             if (c.precond == PRE_JACOBI)
-                k_bicg_s<PRE_JACOBI><<<g, kBlock, 0, s>>>(c.A, c.S);
+                k_bicg_s<PRE_JACOBI><<<gv, kBlock, 0, s>>>(c.A, c.S);
             else
-                k_bicg_s<PRE_NONE><<<g, kBlock, 0, s>>>(c.A, c.S);
-            k_fin_bicg_s<<<gf, kBlock, 0, s>>>(c.S);
-            k_bicg_spmv_t<<<g, kBlock, 0, s>>>(c.A, c.S);
-            k_fin_bicg_t<<<gf, kBlock, 0, s>>>(c.S);
-            k_bicg_update<<<g, kBlock, 0, s>>>(c.A, c.S);
-            k_fin_bicg_update<<<gf, kBlock, 0, s>>>(c.S);
+                k_bicg_s<PRE_NONE><<<gv, kBlock, 0, s>>>(c.A, c.S);
+            k_fin_bicg_s<<<gf, kBlock, 0, s>>>(c.S, Gv);
+            k_bicg_spmv_t<<<gt, kBlock, 0, s>>>(c.A, c.S);
+            k_fin_bicg_t<<<gf, kBlock, 0, s>>>(c.S, Gt);
+            k_bicg_update<<<gv, kBlock, 0, s>>>(c.A, c.S);
+            k_fin_bicg_update<<<gf, kBlock, 0, s>>>(c.S, Gv);
         }
     }
 }
@@ -1015,8 +965,11 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
     if (method == HSLA_METHOD_BICGSTAB && pre == PRE_FSAI)
         return set_error(h, HSLA_ERR_INVALID_ARG, "FSAI preconditioning is for CG only");
     const int nvec = method == HSLA_METHOD_CG ? 6 : 10;
-    const int G = grid_blocks(h, kWavesPerBlock, A.ntiles, 1);
-    const Layout lay = make_layout(B, n, nvec, G);
+    // SpMV-based kernels: up to 16 blocks per CU; vector kernels: up to 8
+    const int Gt = grid_blocks(h, kWavesPerBlock, A.ntiles, 1, 16);
+    const int Gv = grid_blocks(h, kBlock * 4, n, 1, 8);
+    const int Gmax = Gt > Gv ? Gt : Gv;
+    const Layout lay = make_layout(B, n, nvec, Gmax);
     hsla_status st = ensure_workspace(h, lay.total);
     if (st != HSLA_OK) return st;
     st = ensure_host_state(h, B);
@@ -1029,14 +982,14 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
     c.B = B;
     c.method = method;
     c.precond = pre;
-    c.G = G;
+    c.Gt = Gt;
+    c.Gv = Gv;
     Sys &S = c.S;
     S.val = values;
     S.b = b;
     S.x = x;
     S.st = (SysState *)(ws + lay.off_state);
     S.part = (double *)(ws + lay.off_part);
-    S.G = G;
     double *vec = (double *)(ws + lay.off_vec);
     const size_t vs = (size_t)B * n;
     double **slots[] = {&S.r, &S.p, &S.q, &S.dinv, &S.z, &S.w, &S.rh, &S.ph, &S.v, &S.s};
@@ -1046,34 +999,34 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
         S.t = S.w;
     }
     const int64_t max_iter = o.max_iter > 0 ? o.max_iter : (10 * n < 100000 ? 10 * n : 100000);
-    const dim3 g(G, B), gf(B);
+    const dim3 gt(Gt, B), gv(Gv, B), gf(B);
     k_reset<<<1, kBlock, 0, s>>>(S.st, B, max_iter);
-    if (o.use_x0) k_spmv<<<g, kBlock, 0, s>>>(A, values, x, S.q);
+    if (o.use_x0) k_spmv<<<gt, kBlock, 0, s>>>(A, values, x, S.q);
     if (method == HSLA_METHOD_CG) {
         switch (pre) {
             case PRE_NONE:
-                k_cg_init<PRE_NONE><<<g, kBlock, 0, s>>>(A, S, o.use_x0);
-                k_fin_cg_init<PRE_NONE><<<gf, kBlock, 0, s>>>(S, o.rtol, o.atol);
+                k_cg_init<PRE_NONE><<<gv, kBlock, 0, s>>>(A, S, o.use_x0);
+                k_fin_cg_init<PRE_NONE><<<gf, kBlock, 0, s>>>(S, Gv, o.rtol, o.atol);
                 break;
             case PRE_JACOBI:
-                k_cg_init<PRE_JACOBI><<<g, kBlock, 0, s>>>(A, S, o.use_x0);
-                k_fin_cg_init<PRE_JACOBI><<<gf, kBlock, 0, s>>>(S, o.rtol, o.atol);
+                k_cg_init<PRE_JACOBI><<<gv, kBlock, 0, s>>>(A, S, o.use_x0);
+                k_fin_cg_init<PRE_JACOBI><<<gf, kBlock, 0, s>>>(S, Gv, o.rtol, o.atol);
                 break;
             default:
-                k_cg_init<PRE_FSAI><<<g, kBlock, 0, s>>>(A, S, o.use_x0);
-                k_fin_cg_init<PRE_FSAI><<<gf, kBlock, 0, s>>>(S, o.rtol, o.atol);
-                k_fsai_lower<<<g, kBlock, 0, s>>>(A, c.L, S);
-                k_fsai_upper_dot<<<g, kBlock, 0, s>>>(A, c.U, S);
-                k_fin_fsai<<<gf, kBlock, 0, s>>>(S, 1);
-                k_cg_direction<PRE_FSAI><<<g, kBlock, 0, s>>>(A, S);
+                k_cg_init<PRE_FSAI><<<gv, kBlock, 0, s>>>(A, S, o.use_x0);
+                k_fin_cg_init<PRE_FSAI><<<gf, kBlock, 0, s>>>(S, Gv, o.rtol, o.atol);
+                k_fsai_lower<<<gt, kBlock, 0, s>>>(A, c.L, S);
+                k_fsai_upper_dot<<<gt, kBlock, 0, s>>>(A, c.U, S);
+                k_fin_fsai<<<gf, kBlock, 0, s>>>(S, Gt, 1);
+                k_cg_direction<PRE_FSAI><<<gv, kBlock, 0, s>>>(A, S);
                 break;
         }
     } else {
         if (pre == PRE_JACOBI)
-            k_bicg_init<PRE_JACOBI><<<g, kBlock, 0, s>>>(A, S, o.use_x0);
+            k_bicg_init<PRE_JACOBI><<<gv, kBlock, 0, s>>>(A, S, o.use_x0);
         else
-            k_bicg_init<PRE_NONE><<<g, kBlock, 0, s>>>(A, S, o.use_x0);
-        k_fin_bicg_init<<<gf, kBlock, 0, s>>>(S, o.rtol, o.atol);
+            k_bicg_init<PRE_NONE><<<gv, kBlock, 0, s>>>(A, S, o.use_x0);
+        k_fin_bicg_init<<<gf, kBlock, 0, s>>>(S, Gv, o.rtol, o.atol);
     }
     HSLA_HIP(h, hipGetLastError());
 
@@ -1124,8 +1077,8 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
     }
     // true residual ||b - A x|| / ||b||
     double *res = (double *)(ws + lay.off_res);
-    k_residual<<<g, kBlock, 0, s>>>(A, S);
-    k_fin_residual<<<gf, kBlock, 0, s>>>(S, res);
+    k_residual<<<gt, kBlock, 0, s>>>(A, S);
+    k_fin_residual<<<gf, kBlock, 0, s>>>(S, Gt, res);
     HSLA_HIP(h, hipGetLastError());
     std::vector<double> hres(2 * (size_t)B);
     HSLA_HIP(h, hipMemcpyAsync(hres.data(), res, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s));
@@ -1223,12 +1176,12 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
         if (st != HSLA_OK) return st;
         method = sym ? HSLA_METHOD_CG : HSLA_METHOD_BICGSTAB;
     }
-    Pat A{p->row_ptr, p->col, p->diag, p->tiles, p->ntiles, p->n, p->nnz};
+    Pat A{p->row_ptr, p->col, p->diag, p->meta, p->ntiles, p->n, p->nnz};
     FPat L{}, U{};
     if (o.precond == HSLA_PRECOND_FSAI) {
         if (!o.d_G || !o.d_GT) return set_error(h, HSLA_ERR_INVALID_ARG, "FSAI needs d_G and d_GT");
-        L = FPat{p->rpL, p->colL, p->tilesL, p->ntilesL, p->nnz_lower, o.d_G};
-        U = FPat{p->rpU, p->colU, p->tilesU, p->ntilesU, p->nnz_lower, o.d_GT};
+        L = FPat{p->rpL, p->colL, p->metaL, p->ntilesL, p->nnz_lower, o.d_G};
+        U = FPat{p->rpU, p->colU, p->metaU, p->ntilesU, p->nnz_lower, o.d_GT};
     }
     return solve_core(h, A, &L, &U, B, values, b, x, o, method, infos, s);
 }
@@ -1266,7 +1219,7 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
     }
     hsla_status res;
     if (sym) {
-        Pat A{p->row_ptr, p->col, p->diag, p->tiles, p->ntiles, p->n, p->nnz};
+        Pat A{p->row_ptr, p->col, p->diag, p->meta, p->ntiles, p->n, p->nnz};
         res = solve_core(h, A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s);
     } else {
         if (hipMalloc((void **)&valT, sizeof(double) * (size_t)B * (p->nnz > 0 ? p->nnz : 1)) != hipSuccess) {
@@ -1277,7 +1230,7 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
         int blocks = (int)((tot + kBlock - 1) / kBlock);
         if (blocks > 8192) blocks = 8192;
         if (tot > 0) k_gather_values<<<blocks, kBlock, 0, s>>>(p->nnz, B, values, p->srcT, valT);
-        Pat AT{p->rpT, p->colT, p->diagT, p->tilesT, p->ntilesT, p->n, p->nnz};
+        Pat AT{p->rpT, p->colT, p->diagT, p->metaT, p->ntilesT, p->n, p->nnz};
         res = solve_core(h, AT, nullptr, nullptr, B, valT, gx, lam, o, method, infos, s);
     }
     if (res >= 0 && gA) {
@@ -1356,7 +1309,7 @@ hsla_status hsla_residual_norms(hsla_handle *h, const hsla_pattern *p, int32_t B
     if (B == 0) return HSLA_OK;
     if (p->n > 0 && (!d_values || !d_b || !d_x)) return hsla::set_error(h, HSLA_ERR_INVALID_ARG, "null pointer");
     hipStream_t s = h->stream;
-    const int G = hsla::grid_blocks(h, hsla::kWavesPerBlock, p->ntiles, 1);
+    const int G = hsla::grid_blocks(h, hsla::kWavesPerBlock, p->ntiles, 1, 16);
     const hsla::Layout lay = hsla::make_layout(B, p->n, 0, G);
     st = hsla::ensure_workspace(h, lay.total);
     if (st != HSLA_OK) return st;
@@ -1367,14 +1320,13 @@ hsla_status hsla_residual_norms(hsla_handle *h, const hsla_pattern *p, int32_t B
     S.x = const_cast<double *>(d_x);
     S.st = (hsla::SysState *)(ws + lay.off_state);
     S.part = (double *)(ws + lay.off_part);
-    S.G = G;
     hsla::k_reset<<<1, hsla::kBlock, 0, s>>>(S.st, B, 1);
-    const hsla::Pat A{p->row_ptr, p->col, p->diag, p->tiles, p->ntiles, p->n, p->nnz};
+    const hsla::Pat A{p->row_ptr, p->col, p->diag, p->meta, p->ntiles, p->n, p->nnz};
     double *res = (double *)(ws + lay.off_res);
     std::vector<double> hr(2 * (size_t)B, 0.0);
     if (p->n > 0) {
         hsla::k_residual<<<dim3(G, B), hsla::kBlock, 0, s>>>(A, S);
-        hsla::k_fin_residual<<<dim3(B), hsla::kBlock, 0, s>>>(S, res);
+        hsla::k_fin_residual<<<dim3(B), hsla::kBlock, 0, s>>>(S, G, res);
         HSLA_HIP(h, hipGetLastError());
         HSLA_HIP(h, hipMemcpyAsync(hr.data(), res, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s));
     }

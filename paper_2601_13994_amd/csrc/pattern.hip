@@ -293,45 +293,45 @@ static hsla_status device_transpose(hsla_handle *h, int32_t n, int64_t nnz, cons
 
 // Tile schedule: consecutive rows packed while a tile holds at most
 // kTileRows rows and kTileCap entries; a row longer than kTileCap forms a
-// tile by itself.  Built on the host from a copy of row_ptr.
-static hsla_status build_tiles(hsla_handle *h, int32_t n, const int32_t *d_rp, hipStream_t s, int32_t **d_tiles,
+// tile by itself.  Built on the host from a copy of row_ptr; meta[t] =
+// (first row, first entry) of tile t and meta[T] = (n, nnz).
+static hsla_status build_tiles(hsla_handle *h, int32_t n, const int32_t *d_rp, hipStream_t s, int2 **d_meta,
                                int32_t *ntiles) {
     std::vector<int32_t> rp(n + 1);
     HSLA_HIP(h, hipMemcpyAsync(rp.data(), d_rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
     HSLA_HIP(h, hipStreamSynchronize(s));
-    std::vector<int32_t> t;
+    std::vector<int2> t;
     t.reserve(n / kTileRows + 2);
-    t.push_back(0);
+    t.push_back(make_int2(0, rp[0]));
     int32_t r = 0;
     while (r < n) {
         const int32_t len = rp[r + 1] - rp[r];
         if (len > kTileCap) {
             ++r;
-            t.push_back(r);
-            continue;
+        } else {
+            int32_t e = r, acc = 0;
+            while (e < n && e - r < kTileRows) {
+                const int32_t l = rp[e + 1] - rp[e];
+                if (l > kTileCap || acc + l > kTileCap) break;
+                acc += l;
+                ++e;
+            }
+            r = e;
         }
-        int32_t e = r, acc = 0;
-        while (e < n && e - r < kTileRows) {
-            const int32_t l = rp[e + 1] - rp[e];
-            if (l > kTileCap || acc + l > kTileCap) break;
-            acc += l;
-            ++e;
-        }
-        r = e;
-        t.push_back(r);
+        t.push_back(make_int2(r, rp[r]));
     }
     *ntiles = (int32_t)t.size() - 1;
-    HSLA_HIP(h, hipMalloc((void **)d_tiles, sizeof(int32_t) * t.size()));
-    HSLA_HIP(h, hipMemcpyAsync(*d_tiles, t.data(), sizeof(int32_t) * t.size(), hipMemcpyHostToDevice, s));
+    HSLA_HIP(h, hipMalloc((void **)d_meta, sizeof(int2) * t.size()));
+    HSLA_HIP(h, hipMemcpyAsync(*d_meta, t.data(), sizeof(int2) * t.size(), hipMemcpyHostToDevice, s));
     HSLA_HIP(h, hipStreamSynchronize(s));
     return HSLA_OK;
 }
 
 static void free_pattern(hsla_pattern *p) {
     if (!p) return;
-    int32_t *bufs[] = {p->row_ptr, p->col, p->diag, p->tiles, p->rpT, p->colT, p->srcT, p->tilesT, p->diagT,
-                       p->rpL, p->colL, p->posL, p->tilesL, p->rpU, p->colU, p->srcU, p->tilesU};
-    for (int32_t *b : bufs)
+    void *bufs[] = {p->row_ptr, p->col, p->diag, p->meta, p->rpT, p->colT, p->srcT, p->metaT, p->diagT,
+                    p->rpL, p->colL, p->posL, p->metaL, p->rpU, p->colU, p->srcU, p->metaU};
+    for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
 }
@@ -389,7 +389,7 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
     }
     p->nnz_lower = hf.nnz_lower;
 
-    hsla_status st = build_tiles(h, n, p->row_ptr, s, &p->tiles, &p->ntiles);
+    hsla_status st = build_tiles(h, n, p->row_ptr, s, &p->meta, &p->ntiles);
     if (st != HSLA_OK) { (void)hipFree(df); return fail(st); }
 
     // transpose and pattern symmetry
@@ -405,7 +405,7 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
     PCHK(hipStreamSynchronize(s));
     p->pattern_symmetric = hf.differ ? 0 : 1;
     (void)hipFree(df);
-    st = build_tiles(h, n, p->rpT, s, &p->tilesT, &p->ntilesT);
+    st = build_tiles(h, n, p->rpT, s, &p->metaT, &p->ntilesT);
     if (st != HSLA_OK) return fail(st);
     PCHK(hipMalloc((void **)&p->diagT, sizeof(int32_t) * (nn > 0 ? nn : 1)));
     if (n > 0) k_find_diag<<<blocks_for(n), kBlock, 0, s>>>(n, p->rpT, p->colT, p->diagT);
@@ -424,14 +424,14 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
         k_fill_lower<<<blocks_for(n), kBlock, 0, s>>>(n, p->row_ptr, p->col, p->rpL, p->colL, p->posL);
         PCHK(hipGetLastError());
     }
-    st = build_tiles(h, n, p->rpL, s, &p->tilesL, &p->ntilesL);
+    st = build_tiles(h, n, p->rpL, s, &p->metaL, &p->ntilesL);
     if (st != HSLA_OK) return fail(st);
     PCHK(hipMalloc((void **)&p->rpU, sizeof(int32_t) * (nn + 1)));
     PCHK(hipMalloc((void **)&p->colU, sizeof(int32_t) * (nL > 0 ? nL : 1)));
     PCHK(hipMalloc((void **)&p->srcU, sizeof(int32_t) * (nL > 0 ? nL : 1)));
     st = device_transpose(h, n, nL, p->rpL, p->colL, p->rpU, p->colU, p->srcU, s);
     if (st != HSLA_OK) return fail(st);
-    st = build_tiles(h, n, p->rpU, s, &p->tilesU, &p->ntilesU);
+    st = build_tiles(h, n, p->rpU, s, &p->metaU, &p->ntilesU);
     if (st != HSLA_OK) return fail(st);
     PCHK(hipStreamSynchronize(s));
 #undef PCHK
