@@ -167,6 +167,52 @@ hsla_status hsla_residual_norms(hsla_handle *h, const hsla_pattern *p, int32_t B
                                 const double *d_values, const double *d_b, const double *d_x,
                                 double *res_norm, double *b_norm, void *stream);
 
+/* ------------------------------------------------------------ learned FSAI */
+/* A factorized sparse approximate inverse M^{-1} = G^T G with G lower
+ * triangular on A's lower pattern (diagonal included) and a positive
+ * diagonal, so preconditioned CG stays valid.  The values come from a small
+ * message-passing network over A's graph (this project's design; the paper
+ * names learned preconditioners as future work).  The network maps the
+ * Jacobi-scaled matrix A^ = D^{-1/2} A D^{-1/2} to G^, and G = G^ D^{-1/2}.
+ * Parameters are float32, packed as W0[4][64] b0[64], then per layer l = 1..3
+ * C_l[4][64] W_l[128][64] b_l[64], then H1[132][32] c1[32] H2[32] c2. */
+
+/* Number of float32 parameters in the packed layout. */
+int32_t hsla_mpnn_num_params(void);
+
+/* G^ (float32 [B][nnz_L], lower entries in the pattern's row order) for B
+ * systems sharing pattern p, from their values (float64 [B][nnz]) and the
+ * packed parameters (float32, device).  Weights and activations are rounded
+ * to bfloat16, products accumulate in float32 on the matrix cores.  With
+ * keep != 0 the activations stay in the handle for the next
+ * hsla_mpnn_backward (one kept forward per handle).  A missing or
+ * non-positive diagonal returns HSLA_ERR_ZERO_DIAGONAL. */
+hsla_status hsla_mpnn_forward(hsla_handle *h, const hsla_pattern *p, int32_t B, const double *d_values,
+                              const float *d_params, float *d_Ghat, int32_t keep, void *stream);
+
+/* Parameter gradients (float32 [num_params], overwritten) of sum(dGhat * G^)
+ * for the most recent kept forward of the same pattern and batch. */
+hsla_status hsla_mpnn_backward(hsla_handle *h, const hsla_pattern *p, int32_t B, const float *d_dGhat,
+                               float *d_grads, void *stream);
+
+/* Probe loss of the factor: loss[s] = scale * sum_p ||G^ A^ G^^T z_p - z_p||^2
+ * for each system s (host output, B doubles) with probes Z (float64
+ * [B][P][n], device), FP64 arithmetic on float32 factor values; d_dGhat
+ * (float32 [B][nnz_L], nullable) receives the gradient of loss[s] with
+ * respect to G^ of system s.  B * P must not exceed 65535. */
+hsla_status hsla_probe_loss(hsla_handle *h, const hsla_pattern *p, int32_t B, const double *d_values,
+                            const float *d_Ghat, int32_t P, const double *d_Z, double scale, double *loss,
+                            float *d_dGhat, void *stream);
+
+/* One Adam step on n float32 parameters (bias-corrected, step >= 1). */
+hsla_status hsla_adam_step(hsla_handle *h, int64_t n, float *d_params, const float *d_grads, float *d_m,
+                           float *d_v, float lr, float beta1, float beta2, float eps, int64_t step, void *stream);
+
+/* The factors hsla_solve applies with HSLA_PRECOND_FSAI: G = G^ D^{-1/2}
+ * (float32 [B][nnz_L]) and the same values in G^T's CSR order (d_GT). */
+hsla_status hsla_fsai_factors(hsla_handle *h, const hsla_pattern *p, int32_t B, const double *d_values,
+                              const float *d_Ghat, float *d_G, float *d_GT, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

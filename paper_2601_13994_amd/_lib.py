@@ -30,6 +30,8 @@ EXPORTS = [
     "hsla_pattern_create", "hsla_pattern_destroy", "hsla_pattern_info", "hsla_pattern_transpose",
     "hsla_spmv", "hsla_solve", "hsla_solve_batched", "hsla_adjoint", "hsla_adjoint_batched",
     "hsla_outer_on_pattern", "hsla_residual_norms",
+    "hsla_mpnn_num_params", "hsla_mpnn_forward", "hsla_mpnn_backward", "hsla_probe_loss", "hsla_adam_step",
+    "hsla_fsai_factors",
 ]
 
 
@@ -101,6 +103,14 @@ def load() -> ctypes.CDLL:
         L.hsla_adjoint_batched.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, P(Opts), P(Info), vp]
         L.hsla_outer_on_pattern.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.hsla_residual_norms.argtypes = [vp, vp, i32, vp, vp, vp, P(f64), P(f64), vp]
+        L.hsla_mpnn_num_params.argtypes = []
+        L.hsla_mpnn_num_params.restype = i32
+        L.hsla_mpnn_forward.argtypes = [vp, vp, i32, vp, vp, vp, i32, vp]
+        L.hsla_mpnn_backward.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.hsla_probe_loss.argtypes = [vp, vp, i32, vp, vp, i32, vp, f64, P(f64), vp, vp]
+        L.hsla_adam_step.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, i64, vp]
+        L.hsla_fsai_factors.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -287,3 +297,65 @@ def residual_norms(pat: Pattern, values: torch.Tensor, b: torch.Tensor, x: torch
         st = load().hsla_residual_norms(pat.h, pat.p, B, ptr(values), ptr(b), ptr(x), rn, bn, stream_ptr(pat.device))
         check(st, pat.h, "hsla_residual_norms")
     return list(rn), list(bn)
+
+
+# ---------------------------------------------------------------- learned FSAI
+
+def mpnn_forward(pat: Pattern, values: torch.Tensor, params: torch.Tensor, keep: bool = False) -> torch.Tensor:
+    values = need(values, torch.float64, "values", pat.device)
+    params = need(params, torch.float32, "params", pat.device)
+    B = _batch(values, pat.nnz)
+    g = torch.empty((B, pat.nnz_lower) if values.dim() == 2 else (pat.nnz_lower,), dtype=torch.float32,
+                    device=pat.device)
+    with torch.cuda.device(pat.device):
+        st = load().hsla_mpnn_forward(pat.h, pat.p, B, ptr(values), ptr(params), ptr(g), int(keep),
+                                      stream_ptr(pat.device))
+        check(st, pat.h, "hsla_mpnn_forward")
+    return g
+
+
+def mpnn_backward(pat: Pattern, B: int, dG: torch.Tensor) -> torch.Tensor:
+    dG = need(dG, torch.float32, "dG", pat.device)
+    grads = torch.empty(load().hsla_mpnn_num_params(), dtype=torch.float32, device=pat.device)
+    with torch.cuda.device(pat.device):
+        st = load().hsla_mpnn_backward(pat.h, pat.p, B, ptr(dG), ptr(grads), stream_ptr(pat.device))
+        check(st, pat.h, "hsla_mpnn_backward")
+    return grads
+
+
+def probe_loss(pat: Pattern, values: torch.Tensor, G: torch.Tensor, Z: torch.Tensor, scale: float = 1.0,
+               grad: bool = True):
+    """(loss per system [B] (host list), dG or None)."""
+    values = need(values, torch.float64, "values", pat.device)
+    G = need(G, torch.float32, "G", pat.device)
+    Z = need(Z, torch.float64, "Z", pat.device)
+    B = _batch(values, pat.nnz)
+    P = Z.numel() // (B * pat.n)
+    loss = (ctypes.c_double * B)()
+    dG = torch.empty_like(G) if grad else None
+    with torch.cuda.device(pat.device):
+        st = load().hsla_probe_loss(pat.h, pat.p, B, ptr(values), ptr(G), P, ptr(Z), float(scale), loss, ptr(dG),
+                                    stream_ptr(pat.device))
+        check(st, pat.h, "hsla_probe_loss")
+    return list(loss), dG
+
+
+def adam_step(params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    h = handle(params.device.index)
+    with torch.cuda.device(params.device):
+        st = load().hsla_adam_step(h, params.numel(), ptr(params), ptr(grads), ptr(m), ptr(v), float(lr),
+                                   float(beta1), float(beta2), float(eps), int(step), stream_ptr(params.device))
+        check(st, h, "hsla_adam_step")
+
+
+def fsai_factors(pat: Pattern, values: torch.Tensor, Ghat: torch.Tensor):
+    values = need(values, torch.float64, "values", pat.device)
+    Ghat = need(Ghat, torch.float32, "Ghat", pat.device)
+    B = _batch(values, pat.nnz)
+    G = torch.empty_like(Ghat)
+    GT = torch.empty_like(Ghat)
+    with torch.cuda.device(pat.device):
+        st = load().hsla_fsai_factors(pat.h, pat.p, B, ptr(values), ptr(Ghat), ptr(G), ptr(GT),
+                                      stream_ptr(pat.device))
+        check(st, pat.h, "hsla_fsai_factors")
+    return G, GT

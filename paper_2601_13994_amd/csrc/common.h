@@ -66,6 +66,8 @@ struct hsla_pattern {
     int32_t *rpU = nullptr, *colU = nullptr, *srcU = nullptr;   // L^T (upper) + perm into L order
     int2 *metaU = nullptr;
     int32_t ntilesU = 0;
+    int32_t *rowL = nullptr;     // row of each lower entry
+    uint8_t *isdiagL = nullptr;  // lower entry on the diagonal
 };
 
 struct hsla_handle {
@@ -89,6 +91,13 @@ struct hsla_handle {
     // profile mode: event pairs around the timed kernel
     hipEvent_t *prof_ev = nullptr;
     int prof_cap = 0;
+    // preconditioner network: activations of the last kept forward, probe buffers
+    void *mp_ws = nullptr;
+    size_t mp_ws_bytes = 0;
+    int mp_keep_B = 0;
+    const hsla_pattern *mp_keep_pattern = nullptr;
+    void *pr_ws = nullptr;
+    size_t pr_ws_bytes = 0;
 };
 
 // ---------------------------------------------------------------------------

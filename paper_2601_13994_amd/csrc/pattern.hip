@@ -245,6 +245,17 @@ __global__ __launch_bounds__(kBlock) void k_fill_lower(int32_t n, const int32_t 
     }
 }
 
+// Row index and diagonal flag of every entry of a CSR pattern.
+__global__ __launch_bounds__(kBlock) void k_row_flags(int32_t n, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ col, int32_t *__restrict__ row,
+                                                      uint8_t *__restrict__ isdiag) {
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            row[k] = i;
+            isdiag[k] = col[k] == i;
+        }
+}
+
 // ---------------------------------------------------------------------------
 // Host-side helpers
 // ---------------------------------------------------------------------------
@@ -330,7 +341,7 @@ static hsla_status build_tiles(hsla_handle *h, int32_t n, const int32_t *d_rp, h
 static void free_pattern(hsla_pattern *p) {
     if (!p) return;
     void *bufs[] = {p->row_ptr, p->col, p->diag, p->meta, p->rpT, p->colT, p->srcT, p->metaT, p->diagT,
-                    p->rpL, p->colL, p->posL, p->metaL, p->rpU, p->colU, p->srcU, p->metaU};
+                    p->rpL, p->colL, p->posL, p->metaL, p->rpU, p->colU, p->srcU, p->metaU, p->rowL, p->isdiagL};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -433,6 +444,10 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
     if (st != HSLA_OK) return fail(st);
     st = build_tiles(h, n, p->rpU, s, &p->metaU, &p->ntilesU);
     if (st != HSLA_OK) return fail(st);
+    PCHK(hipMalloc((void **)&p->rowL, sizeof(int32_t) * (nL > 0 ? nL : 1)));
+    PCHK(hipMalloc((void **)&p->isdiagL, (nL > 0 ? nL : 1)));
+    if (n > 0) k_row_flags<<<blocks_for(n), kBlock, 0, s>>>(n, p->rpL, p->colL, p->rowL, p->isdiagL);
+    PCHK(hipGetLastError());
     PCHK(hipStreamSynchronize(s));
 #undef PCHK
     *out = p;
@@ -509,6 +524,8 @@ void hsla_destroy(hsla_handle *h) {
     if (h->ws) (void)hipFree(h->ws);
     if (h->h_state) (void)hipHostFree(h->h_state);
     if (h->d_flags) (void)hipFree(h->d_flags);
+    if (h->mp_ws) (void)hipFree(h->mp_ws);
+    if (h->pr_ws) (void)hipFree(h->pr_ws);
     for (int i = 0; i < h->prof_cap; ++i) (void)hipEventDestroy(h->prof_ev[i]);
     delete[] h->prof_ev;
     if (h->entry_event) (void)hipEventDestroy(h->entry_event);

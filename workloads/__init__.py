@@ -167,23 +167,41 @@ def aniso_tensor(ratio: float, angle: float) -> tuple[float, float, float]:
     return c * c + s * s * inv, s * s + c * c * inv, (1.0 - inv) * s * c
 
 
-def aniso2d(m: int, ratio: float, angle: float) -> Csr:
-    """2D anisotropic diffusion -div(K grad u), 9-point stencil, unit spacing,
-    homogeneous Dirichlet; the full 9-point pattern is always stored (explicit
-    zeros kept).  Centre 2(k11+k22), E/W -k11, N/S -k22, NE/SW -k12/2,
-    NW/SE +k12/2.  Unknown (x, y) has index y*m + x."""
+ANISO_OFFSETS = [(-1, -1), (0, -1), (1, -1), (-1, 0), (0, 0), (1, 0), (-1, 1), (0, 1), (1, 1)]  # (dx, dy)
+
+
+def aniso_stencil(ratio: float, angle: float) -> np.ndarray:
+    """The 9 stencil coefficients in slot order (ascending column offset):
+    centre 2(k11+k22), E/W -k11, N/S -k22, NE/SW -k12/2, NW/SE +k12/2."""
     k11, k22, k12 = aniso_tensor(ratio, angle)
+    coef = {(-1, -1): -k12 / 2, (0, -1): -k22, (1, -1): k12 / 2, (-1, 0): -k11, (0, 0): 2 * (k11 + k22),
+            (1, 0): -k11, (-1, 1): k12 / 2, (0, 1): -k22, (1, 1): -k12 / 2}
+    return np.array([coef[o] for o in ANISO_OFFSETS])
+
+
+def aniso_pattern(m: int) -> tuple[Csr, np.ndarray]:
+    """Full 9-point Dirichlet pattern on an m x m grid (values zero) and the
+    stencil slot (0..8) of every stored entry."""
     n = m * m
     idx = np.arange(n, dtype=np.int64)
     x = idx % m
     y = idx // m
-    offs = [(-1, -1), (0, -1), (1, -1), (-1, 0), (0, 0), (1, 0), (-1, 1), (0, 1), (1, 1)]  # (dx, dy)
-    coef = {(-1, -1): -k12 / 2, (0, -1): -k22, (1, -1): k12 / 2, (-1, 0): -k11, (0, 0): 2 * (k11 + k22),
-            (1, 0): -k11, (-1, 1): k12 / 2, (0, 1): -k22, (1, 1): -k12 / 2}
-    cols = np.stack([idx + dy * m + dx for dx, dy in offs], axis=1)
-    mask = np.stack([(x + dx >= 0) & (x + dx < m) & (y + dy >= 0) & (y + dy < m) for dx, dy in offs], axis=1)
-    vals = np.broadcast_to(np.array([coef[o] for o in offs]), (n, 9)).copy()
-    return _compress(n, np.where(mask, cols, 0), vals, mask)
+    cols = np.stack([idx + dy * m + dx for dx, dy in ANISO_OFFSETS], axis=1)
+    mask = np.stack([(x + dx >= 0) & (x + dx < m) & (y + dy >= 0) & (y + dy < m) for dx, dy in ANISO_OFFSETS],
+                    axis=1)
+    slots = np.broadcast_to(np.arange(9), (n, 9))
+    a = _compress(n, np.where(mask, cols, 0), np.zeros((n, 9)), mask)
+    return a, np.ascontiguousarray(slots[mask], dtype=np.int64)
+
+
+def aniso2d(m: int, ratio: float, angle: float) -> Csr:
+    """2D anisotropic diffusion -div(K grad u), 9-point stencil, unit spacing,
+    homogeneous Dirichlet; the full 9-point pattern is always stored (explicit
+    zeros kept).  Unknown (x, y) has index y*m + x.  The values are
+    aniso_stencil(ratio, angle)[slot] of each entry."""
+    a, slots = aniso_pattern(m)
+    a.val = aniso_stencil(ratio, angle)[slots]
+    return a
 
 
 # ----------------------------------------------------------------------------
