@@ -156,6 +156,22 @@ hsla_status hsla_adjoint_batched(hsla_handle *h, const hsla_pattern *p, int32_t 
                                  double *d_gA, double *d_gb, const hsla_opts *opts,
                                  hsla_info *infos, void *stream);
 
+/* B systems with distinct patterns and sizes (the paper's matrix list with
+ * distinct patterns) solved with CG (Jacobi or no preconditioner, x0 = 0)
+ * in one persistent launch: workgroups take systems from a queue, largest
+ * first, and iterate each to its own stop test.  System s owns rows
+ * [row_off[s], row_off[s+1]) of b and x (float64) and entries
+ * [nnz_off[s], nnz_off[s+1]) of col (int32, local column indices) and values
+ * (float64); its local row pointer (n_s + 1 int32 entries starting at 0)
+ * starts at row_ptr[row_off[s] + s].  Offsets are int64[B+1] device arrays
+ * starting at 0.  Every local pattern is validated as canonical CSR
+ * (HSLA_ERR_INVALID_CSR names the first bad system).  `infos` (host, may be
+ * NULL) receives B records; the return value is the worst status. */
+hsla_status hsla_solve_ragged(hsla_handle *h, int32_t B, const int64_t *d_row_off, const int64_t *d_nnz_off,
+                              const int32_t *d_row_ptr, const int32_t *d_col, const double *d_values,
+                              const double *d_b, double *d_x, const hsla_opts *opts, hsla_info *infos,
+                              void *stream);
+
 /* The gradient assembly alone: gA[k] = -lambda[row(k)] * x[col(k)] for B
  * systems ([B][n] inputs, [B][nnz] output). */
 hsla_status hsla_outer_on_pattern(hsla_handle *h, const hsla_pattern *p, int32_t B,

@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import HslaError, Pattern
 
-__all__ = ["SparseCSR", "SolveFn", "HslaError", "Pattern", "from_coo"]
+__all__ = ["SparseCSR", "SparseCSRList", "SolveFn", "HslaError", "Pattern", "from_coo"]
 
 
 class SolveFn(torch.autograd.Function):
@@ -124,3 +124,40 @@ def from_coo(values: torch.Tensor, row: torch.Tensor, col: torch.Tensor, n: int)
     row_ptr[1:] = torch.cumsum(counts, 0)
     vals = values[..., order]
     return SparseCSR(vals, row_ptr.to(torch.int32), col.to(torch.int32)[order].contiguous(), shape=(n, n))
+
+
+class SparseCSRList:
+    """Matrices with distinct sparsity patterns and sizes (the paper's matrix
+    list); solved together in one persistent launch.  Each element is given
+    as (values float64 (nnz_s,), row_ptr int32 (n_s+1,), col int32 (nnz_s,))
+    tensors on one GPU; they are concatenated once here."""
+
+    def __init__(self, mats):
+        self.n = [int(rp.numel()) - 1 for _, rp, _ in mats]
+        self.nnz = [int(c.numel()) for _, _, c in mats]
+        dev = mats[0][1].device
+        self.device = dev
+        ro = [0]
+        no = [0]
+        for n, z in zip(self.n, self.nnz):
+            ro.append(ro[-1] + n)
+            no.append(no[-1] + z)
+        self.row_off = torch.tensor(ro, dtype=torch.int64, device=dev)
+        self.nnz_off = torch.tensor(no, dtype=torch.int64, device=dev)
+        self.row_ptr = torch.cat([rp.to(torch.int32) for _, rp, _ in mats]).contiguous()
+        self.col = torch.cat([c.to(torch.int32) for _, _, c in mats]).contiguous()
+        self.values = torch.cat([v.to(torch.float64) for v, _, _ in mats]).contiguous()
+
+    def __len__(self):
+        return len(self.n)
+
+    def split(self, v: torch.Tensor):
+        return list(torch.split(v, self.n))
+
+    def solve(self, bs, rtol: float = 1e-8, atol: float = 0.0, precond: str = "jacobi", max_iter: int = 0):
+        """Solves every system; `bs` is a list of right-hand sides or their
+        concatenation.  Returns (list of x, infos, status)."""
+        b = torch.cat(list(bs)) if isinstance(bs, (list, tuple)) else bs
+        opts = _lib.make_opts(method="cg", precond=precond, rtol=rtol, atol=atol, max_iter=max_iter)
+        x, infos, st = _lib.solve_ragged(self.row_off, self.nnz_off, self.row_ptr, self.col, self.values, b, opts)
+        return self.split(x), infos, st

@@ -31,7 +31,7 @@ EXPORTS = [
     "hsla_spmv", "hsla_solve", "hsla_solve_batched", "hsla_adjoint", "hsla_adjoint_batched",
     "hsla_outer_on_pattern", "hsla_residual_norms",
     "hsla_mpnn_num_params", "hsla_mpnn_forward", "hsla_mpnn_backward", "hsla_probe_loss", "hsla_adam_step",
-    "hsla_fsai_factors",
+    "hsla_fsai_factors", "hsla_solve_ragged",
 ]
 
 
@@ -111,6 +111,7 @@ def load() -> ctypes.CDLL:
         L.hsla_adam_step.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, i64, vp]
         L.hsla_fsai_factors.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
+        L.hsla_solve_ragged.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, P(Opts), P(Info), vp]
         _lib = L
     return _lib
 
@@ -359,3 +360,24 @@ def fsai_factors(pat: Pattern, values: torch.Tensor, Ghat: torch.Tensor):
                                       stream_ptr(pat.device))
         check(st, pat.h, "hsla_fsai_factors")
     return G, GT
+
+
+def solve_ragged(row_off: torch.Tensor, nnz_off: torch.Tensor, row_ptr: torch.Tensor, col: torch.Tensor,
+                 values: torch.Tensor, b: torch.Tensor, opts: Opts):
+    """Concatenated ragged batch (see hsla_solve_ragged).  Returns (x, infos, status)."""
+    device = b.device
+    row_off = need(row_off, torch.int64, "row_off", device)
+    nnz_off = need(nnz_off, torch.int64, "nnz_off", device)
+    row_ptr = need(row_ptr, torch.int32, "row_ptr", device)
+    col = need(col, torch.int32, "col", device)
+    values = need(values, torch.float64, "values", device)
+    b = need(b, torch.float64, "b", device)
+    B = row_off.numel() - 1
+    x = torch.empty_like(b)
+    infos = (Info * max(B, 1))()
+    with torch.cuda.device(device):
+        h = handle(device.index)
+        st = load().hsla_solve_ragged(h, B, ptr(row_off), ptr(nnz_off), ptr(row_ptr), ptr(col), ptr(values),
+                                      ptr(b), ptr(x), ctypes.byref(opts), infos, stream_ptr(device))
+        check(st, h, "hsla_solve_ragged")
+    return x, [infos[i].as_dict() for i in range(B)], st

@@ -1,0 +1,336 @@
+// Ragged batches: B systems with distinct sparsity patterns and sizes
+// (the paper's list of matrices with distinct patterns, Sec. "Typed
+// sparse-tensor hierarchy"), solved with Jacobi-preconditioned CG in one
+// persistent launch.
+//
+// Layout (all device memory, caller-owned): system s owns rows
+// [row_off[s], row_off[s+1]) of the concatenated vectors b and x and entries
+// [nnz_off[s], nnz_off[s+1]) of the concatenated col/values; its local
+// row pointer (n_s + 1 entries, starting at 0) starts at row_ptr[row_off[s]
+// + s]; column indices are local (0 <= col < n_s).
+//
+// Each workgroup pops systems from an atomic queue in longest-first order
+// (by stored entries) and runs the whole recurrence of one system with
+// workgroup-level reductions; the queue gives every workgroup an exit once
+// B systems have been handed out, and max_iter bounds every solve.  A
+// system's reductions use a fixed thread count and order, so its result does
+// not depend on which workgroup solved it.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "common.h"
+
+namespace hsla {
+namespace rg {
+
+constexpr int kRB = 1024;  // threads per workgroup
+constexpr int kRW = kRB / kWave;
+
+struct RInfo {  // per-system result record (device)
+    int64_t iters;
+    int32_t status;
+    int32_t pad;
+    double rel_residual, true_residual;
+};
+
+struct Args {
+    int32_t B;
+    const int64_t *row_off, *nnz_off;
+    const int32_t *rp, *col;
+    const double *val, *b;
+    double *x;
+    double *r, *p, *q, *dinv;  // work vectors, concatenated like b
+    const int32_t *order;      // systems in queue order
+    int32_t *queue;            // next queue slot
+    int32_t *bad;              // first invalid system (validation)
+    RInfo *info;
+    double rtol, atol;
+    int64_t max_iter;
+    int jacobi;
+};
+
+// Workgroup sum of NV values in a fixed order; result in every thread.
+template <int NV>
+__device__ __forceinline__ void wg_sum(double (&v)[NV], double *sh) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) sh[j * kRW + w] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double s = 0.0;
+        for (int q = 0; q < kRW; ++q) s += sh[j * kRW + q];
+        v[j] = s;
+    }
+    __syncthreads();
+}
+
+// Canonical-CSR check of every system's local pattern; reads a row only
+// after its bounds are known to lie inside the system's entries.
+__global__ __launch_bounds__(256) void k_ragged_validate(Args a) {
+    for (int64_t s = blockIdx.x; s < a.B; s += gridDim.x) {
+        const int64_t r0 = a.row_off[s], r1 = a.row_off[s + 1];
+        const int64_t k0 = a.nnz_off[s], k1 = a.nnz_off[s + 1];
+        const int64_t n = r1 - r0, nnz = k1 - k0;
+        if (n < 0 || nnz < 0 || n >= INT32_MAX) {
+            if (threadIdx.x == 0) atomicMin(a.bad, (int32_t)s);
+            continue;
+        }
+        const int32_t *rp = a.rp + r0 + s;
+        const int32_t *col = a.col + k0;
+        bool ok = true;
+        if (threadIdx.x == 0) ok = rp[0] == 0 && (int64_t)rp[n] == nnz;
+        for (int64_t i = threadIdx.x; i < n && ok; i += blockDim.x) {
+            const int32_t lo = rp[i], hi = rp[i + 1];
+            if (lo < 0 || lo > hi || (int64_t)hi > nnz) {
+                ok = false;
+                break;
+            }
+            int32_t prev = -1;
+            for (int32_t k = lo; k < hi; ++k) {
+                const int32_t c = col[k];
+                if (c < 0 || (int64_t)c >= n || c <= prev) {
+                    ok = false;
+                    break;
+                }
+                prev = c;
+            }
+        }
+        if (!ok) atomicMin(a.bad, (int32_t)s);
+    }
+}
+
+__global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
+    __shared__ double sh[3 * kRW];
+    __shared__ int32_t slot;
+    for (;;) {
+        if (threadIdx.x == 0) slot = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int32_t qs = slot;
+        __syncthreads();
+        if (qs >= a.B) return;
+        const int32_t s = a.order[qs];
+        const int64_t r0 = a.row_off[s];
+        const int32_t n = (int32_t)(a.row_off[s + 1] - r0);
+        const int64_t k0 = a.nnz_off[s];
+        const int32_t *rp = a.rp + r0 + s;
+        const int32_t *col = a.col + k0;
+        const double *val = a.val + k0;
+        const double *b = a.b + r0;
+        double *x = a.x + r0, *r = a.r + r0, *p = a.p + r0, *q = a.q + r0, *dinv = a.dinv + r0;
+        // set-up: x = 0, r = b, z = D^{-1} r, p = z
+        double acc3[3] = {0.0, 0.0, 0.0};
+        int bad_diag = 0;
+        for (int32_t i = threadIdx.x; i < n; i += kRB) {
+            double d = 0.0;
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+                if (col[k] == i) d = val[k];
+            if (a.jacobi && d == 0.0) bad_diag = 1;
+            const double di = a.jacobi ? 1.0 / d : 1.0;
+            const double bi = b[i];
+            dinv[i] = di;
+            x[i] = 0.0;
+            r[i] = bi;
+            p[i] = di * bi;
+            acc3[0] += bi * bi;
+            acc3[1] += bi * bi;
+            acc3[2] += bi * (di * bi);
+        }
+        double bd[1] = {(double)bad_diag};
+        wg_sum<1>(bd, sh);
+        wg_sum<3>(acc3, sh);
+        const double bn = sqrt(acc3[0]);
+        double tol = a.rtol * bn;
+        if (a.atol > tol) tol = a.atol;
+        double rho = acc3[2], rr = acc3[1];
+        int32_t status = HSLA_NOT_CONVERGED;
+        int64_t it = 0;
+        if (bd[0] > 0.0) {
+            status = HSLA_ERR_ZERO_DIAGONAL;
+        } else if (!isfinite(bn)) {
+            status = HSLA_ERR_NONFINITE;
+        } else if (sqrt(rr) <= tol) {
+            status = HSLA_OK;
+        } else {
+            while (it < a.max_iter) {
+                // q = A p, sigma = p.q (each row summed in ascending order)
+                double acc1[1] = {0.0};
+                for (int32_t i = threadIdx.x; i < n; i += kRB) {
+                    double sum = 0.0;
+                    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) sum += val[k] * p[col[k]];
+                    q[i] = sum;
+                    acc1[0] += p[i] * sum;
+                }
+                wg_sum<1>(acc1, sh);
+                const double sigma = acc1[0];
+                if (!isfinite(sigma)) { status = HSLA_ERR_NONFINITE; break; }
+                if (!(sigma > 0.0)) { status = HSLA_BREAKDOWN; break; }
+                const double alpha = rho / sigma;
+                double acc2[2] = {0.0, 0.0};
+                for (int32_t i = threadIdx.x; i < n; i += kRB) {
+                    x[i] = x[i] + alpha * p[i];
+                    const double ri = r[i] - alpha * q[i];
+                    r[i] = ri;
+                    acc2[0] += ri * ri;
+                    acc2[1] += ri * (dinv[i] * ri);
+                }
+                wg_sum<2>(acc2, sh);
+                ++it;
+                rr = acc2[0];
+                const double rn = sqrt(rr);
+                if (!isfinite(rn)) { status = HSLA_ERR_NONFINITE; break; }
+                if (rn <= tol) { status = HSLA_OK; break; }
+                const double beta = acc2[1] / rho;
+                rho = acc2[1];
+                for (int32_t i = threadIdx.x; i < n; i += kRB) p[i] = dinv[i] * r[i] + beta * p[i];
+                __syncthreads();
+            }
+        }
+        // true residual ||b - A x||
+        double accr[2] = {0.0, 0.0};
+        for (int32_t i = threadIdx.x; i < n; i += kRB) {
+            double sum = 0.0;
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k) sum += val[k] * x[col[k]];
+            const double e = b[i] - sum;
+            accr[0] += e * e;
+            accr[1] += b[i] * b[i];
+        }
+        wg_sum<2>(accr, sh);
+        if (threadIdx.x == 0) {
+            RInfo f;
+            f.iters = it;
+            f.status = n == 0 ? HSLA_OK : status;
+            f.pad = 0;
+            f.rel_residual = bn > 0 ? sqrt(rr) / bn : sqrt(rr);
+            f.true_residual = accr[1] > 0 ? sqrt(accr[0]) / sqrt(accr[1]) : sqrt(accr[0]);
+            a.info[s] = f;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace rg
+}  // namespace hsla
+
+extern "C" hsla_status hsla_solve_ragged(hsla_handle *h, int32_t B, const int64_t *d_row_off,
+                                         const int64_t *d_nnz_off, const int32_t *d_row_ptr, const int32_t *d_col,
+                                         const double *d_values, const double *d_b, double *d_x,
+                                         const hsla_opts *opts, hsla_info *infos, void *stream) {
+    using namespace hsla;
+    using namespace hsla::rg;
+    if (!h) return HSLA_ERR_INVALID_ARG;
+    if (B < 0) return set_error(h, HSLA_ERR_INVALID_ARG, "negative batch");
+    hsla_opts o;
+    if (opts)
+        o = *opts;
+    else
+        hsla_opts_default(&o);
+    if (o.method == HSLA_METHOD_BICGSTAB || o.precond == HSLA_PRECOND_FSAI || o.use_x0)
+        return set_error(h, HSLA_ERR_INVALID_ARG, "ragged batches run CG with Jacobi or no preconditioner from x0 = 0");
+    if (!(o.rtol >= 0) || !(o.atol >= 0)) return set_error(h, HSLA_ERR_INVALID_ARG, "negative or NaN tolerance");
+    hsla_status st = enter(h, (hipStream_t)stream);
+    if (st != HSLA_OK) return st;
+    if (B == 0) return HSLA_OK;
+    if (!d_row_off || !d_nnz_off || !d_row_ptr) return set_error(h, HSLA_ERR_INVALID_ARG, "null pointer");
+    hipStream_t s = h->stream;
+    std::vector<int64_t> ro(B + 1), no(B + 1);
+    HSLA_HIP(h, hipMemcpyAsync(ro.data(), d_row_off, sizeof(int64_t) * (B + 1), hipMemcpyDeviceToHost, s));
+    HSLA_HIP(h, hipMemcpyAsync(no.data(), d_nnz_off, sizeof(int64_t) * (B + 1), hipMemcpyDeviceToHost, s));
+    HSLA_HIP(h, hipStreamSynchronize(s));
+    if (ro[0] != 0 || no[0] != 0) return set_error(h, HSLA_ERR_INVALID_CSR, "offsets must start at 0");
+    int64_t max_n = 0;
+    for (int i = 0; i < B; ++i) {
+        if (ro[i + 1] < ro[i] || no[i + 1] < no[i])
+            return set_error(h, HSLA_ERR_INVALID_CSR, "offsets of system %d decrease", i);
+        max_n = std::max(max_n, ro[i + 1] - ro[i]);
+    }
+    const int64_t rows = ro[B];
+    if (rows > 0 && (!d_b || !d_x)) return set_error(h, HSLA_ERR_INVALID_ARG, "null b or x");
+    if (no[B] > 0 && (!d_col || !d_values)) return set_error(h, HSLA_ERR_INVALID_ARG, "null col or values");
+    // longest (most entries) first
+    std::vector<int32_t> order(B);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return no[a + 1] - no[a] > no[b + 1] - no[b]; });
+    size_t bytes = 0;
+    auto add = [&](size_t v) { bytes += (v + 255) / 256 * 256; };
+    add(sizeof(double) * 4 * (rows > 0 ? rows : 1));
+    add(sizeof(int32_t) * B);
+    add(sizeof(RInfo) * B);
+    add(256);
+    st = ensure_workspace(h, bytes);
+    if (st != HSLA_OK) return st;
+    char *ws = (char *)h->ws;
+    size_t off = 0;
+    auto take = [&](size_t v) {
+        char *p = ws + off;
+        off += (v + 255) / 256 * 256;
+        return p;
+    };
+    Args a{};
+    a.B = B;
+    a.row_off = d_row_off;
+    a.nnz_off = d_nnz_off;
+    a.rp = d_row_ptr;
+    a.col = d_col;
+    a.val = d_values;
+    a.b = d_b;
+    a.x = d_x;
+    double *vec = (double *)take(sizeof(double) * 4 * (rows > 0 ? rows : 1));
+    a.r = vec;
+    a.p = vec + rows;
+    a.q = vec + 2 * rows;
+    a.dinv = vec + 3 * rows;
+    int32_t *dorder = (int32_t *)take(sizeof(int32_t) * B);
+    a.order = dorder;
+    a.info = (RInfo *)take(sizeof(RInfo) * B);
+    int32_t *flags = (int32_t *)take(256);
+    a.queue = flags;
+    a.bad = flags + 1;
+    a.rtol = o.rtol;
+    a.atol = o.atol;
+    a.max_iter = o.max_iter > 0 ? o.max_iter : std::min<int64_t>(10 * std::max<int64_t>(max_n, 1), 100000);
+    a.jacobi = o.precond == HSLA_PRECOND_JACOBI;
+    const int32_t init_flags[2] = {0, INT32_MAX};
+    HSLA_HIP(h, hipMemcpyAsync(flags, init_flags, sizeof init_flags, hipMemcpyHostToDevice, s));
+    HSLA_HIP(h, hipMemcpyAsync(dorder, order.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
+    // every pointer the kernels dereference must be set (rows/entries > 0)
+    if (!a.row_off || !a.nnz_off || !a.rp || !a.order || !a.queue || !a.bad || !a.info ||
+        (rows > 0 && (!a.b || !a.x || !a.r || !a.p || !a.q || !a.dinv)) || (no[B] > 0 && (!a.col || !a.val)))
+        return set_error(h, HSLA_ERR_INTERNAL, "ragged solve: unset kernel argument");
+    k_ragged_validate<<<std::min(B, 4096), 256, 0, s>>>(a);
+    int32_t bad = INT32_MAX;
+    HSLA_HIP(h, hipMemcpyAsync(&bad, a.bad, sizeof bad, hipMemcpyDeviceToHost, s));
+    HSLA_HIP(h, hipStreamSynchronize(s));
+    if (bad != INT32_MAX) return set_error(h, HSLA_ERR_INVALID_CSR, "system %d is not canonical CSR", bad);
+    const int grid = std::min<int64_t>(B, 2 * (int64_t)h->dev.num_cu);
+    k_ragged_pcg<<<grid, kRB, 0, s>>>(a);
+    HSLA_HIP(h, hipGetLastError());
+    std::vector<RInfo> hi(B);
+    HSLA_HIP(h, hipMemcpyAsync(hi.data(), a.info, sizeof(RInfo) * B, hipMemcpyDeviceToHost, s));
+    HSLA_HIP(h, hipStreamSynchronize(s));
+    int worst = HSLA_OK;
+    for (int i = 0; i < B; ++i) {
+        const int sst = hi[i].status;
+        if (sst < 0 || worst < 0)
+            worst = std::min(worst, sst);
+        else
+            worst = std::max(worst, sst);
+        if (infos) {
+            infos[i].iters = hi[i].iters;
+            infos[i].status = sst;
+            infos[i].method = HSLA_METHOD_CG;
+            infos[i].rel_residual = hi[i].rel_residual;
+            infos[i].true_residual = hi[i].true_residual;
+            infos[i].spmv_ms = 0.0;
+            infos[i].spmv_launches = 0;
+        }
+    }
+    return (hsla_status)worst;
+}
