@@ -122,64 +122,92 @@ def cpu_baseline(a, b, gpu_iters: int, k1: int = 1, k2: int = 31):
     }
 
 
-def run(args):
+ALL_WORKLOADS = ("diffusion3d", "bicgstab", "poisson2d", "knn", "adjoint", "learned")
+
+
+def generate(sel, args):
+    """Host-side inputs of every selected workload.  Runs before the process
+    touches the GPU, so the k-NN and shared-pattern generators may fork."""
     import numpy as np
-    import torch
 
     import workloads as W
+
+    ctx = {}
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t = time.time()
+    if "diffusion3d" in sel or "bicgstab" in sel:
+        log(f"[bench] generating 3D diffusion m={args.m} ...")
+        ctx["d3"] = W.diffusion3d_workload(args.m)
+        if "bicgstab" in sel:
+            ctx["d3_conv_val"] = W.diffusion3d_values(args.m, W.diffusion3d_kappa(args.m), velocity=10.0)
+    if "poisson2d" in sel:
+        ctx["p2"] = W.poisson2d_workload(64)
+        ctx["p2_bs"] = np.stack([W.rng(1, 1, s).standard_normal(64 * 64) for s in range(args.poisson_copies)])
+    if "knn" in sel:
+        log(f"[bench] generating {args.knn_systems} k-NN systems on {workers} processes ...")
+        ctx["knn"] = W.knn_systems(args.knn_systems, workers=workers)
+    if "adjoint" in sel:
+        log(f"[bench] generating {args.adj_batch} shared-pattern systems m={args.adj_m} ...")
+        ctx["adj"] = W.shared_pattern_batch(args.adj_m, args.adj_batch, workers=workers)
+    if "learned" in sel:
+        ctx["aniso_pat"] = W.aniso_pattern(args.aniso_m)
+        ctx["aniso_train"] = np.stack([W.aniso_stencil(*W.aniso_params(s)) for s in range(args.train_systems)])
+        ctx["aniso_eval"] = np.stack([W.aniso_stencil(*W.aniso_params(s, heldout=True))
+                                      for s in range(args.eval_systems)])
+        n = args.aniso_m ** 2
+        bs = np.empty((args.eval_systems, n))
+        for s in range(args.eval_systems):
+            bs[s] = W.rng(5, 5, s).standard_normal(n)
+        ctx["aniso_b"] = bs
+    log(f"[bench] inputs generated in {time.time() - t:.1f}s")
+    return ctx
+
+
+def _sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
+def _pattern(dev, a):
+    import torch
+
     from paper_2601_13994_amd import _lib
 
-    if not torch.cuda.is_available():
-        raise SystemExit("bench.py needs a GPU")
-    dev = torch.device("cuda:0")
-    m = args.m
-    log(f"[bench] generating 3D diffusion m={m} ...")
-    t = time.time()
-    a, b = W.diffusion3d_workload(m)
+    return _lib.Pattern(torch.as_tensor(a.row_ptr).to(dev), torch.as_tensor(a.col).to(dev))
+
+
+def run_diffusion(ctx, args, dev, pat, vals, bt):
+    """Workload 2: Jacobi-PCG on the 256^3 log-normal diffusion system (the
+    headline line: value, roofline, CPU baseline)."""
+    from paper_2601_13994_amd import _lib
+
+    a, b = ctx["d3"]
     n, nnz = a.n, a.nnz
-    log(f"[bench] n={n} nnz={nnz} generated in {time.time() - t:.1f}s")
-    vals = torch.as_tensor(a.val).to(dev)
-    bt = torch.as_tensor(b).to(dev)
-    pat = _lib.Pattern(torch.as_tensor(a.row_ptr).to(dev), torch.as_tensor(a.col).to(dev))
-    torch.cuda.synchronize()
-    log("[bench] pattern ready")
-
-    if args.calibrate_copy:
-        # plain copy kernel of known size for counter calibration (1 GiB read + 1 GiB write)
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log("[bench] calibration copy done (1 GiB -> 1 GiB)")
-
     opts_w = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-8, max_iter=args.max_iter)
     for i in range(args.warmup):
         x, infos, st = _lib.solve(pat, vals, bt, opts_w)
-        log(f"[bench] warmup {i}: status={st} iters={infos[0]['iters']} true_res={infos[0]['true_residual']:.2e}")
-
+        log(f"[bench] diffusion3d warmup {i}: status={st} iters={infos[0]['iters']} "
+            f"true_res={infos[0]['true_residual']:.2e}")
     opts = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-8, max_iter=args.max_iter, profile=True)
-    torch.cuda.synchronize()
+    _sync()
     t0 = time.perf_counter()
     recs = []
     for i in range(args.steps):
         x, infos, st = _lib.solve(pat, vals, bt, opts)
         recs.append(infos[0])
-        log(f"[bench] step {i}: status={st} iters={infos[0]['iters']}")
-    torch.cuda.synchronize()
+        log(f"[bench] diffusion3d step {i}: status={st} iters={infos[0]['iters']}")
+    _sync()
     elapsed = time.perf_counter() - t0
-
     iters = recs[-1]["iters"]
     spmv_ms = sum(r["spmv_ms"] for r in recs)
     launches = sum(r["spmv_launches"] for r in recs)
     avg_ms = spmv_ms / max(launches, 1)
     bytes_launch = spmv_bytes(n, nnz)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(n, nnz)
     ms_step = elapsed / args.steps * 1e3
     it_bytes = pcg_iteration_bytes(n, nnz)
-    out = {
+    top = {
         "metric": METRIC,
         "value": args.steps / elapsed,
         "unit": "solves/s",
@@ -193,7 +221,7 @@ def run(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"diffusion3d-{m}^3 log-normal kappa, Jacobi-PCG to rtol 1e-8, x0=0",
+            "workload": f"diffusion3d-{args.m}^3 log-normal kappa, Jacobi-PCG to rtol 1e-8, x0=0",
             "n": n, "nnz": nnz, "method": "cg", "precond": "jacobi", "rtol": 1e-8,
             "index_dtype": "int32", "value_dtype": "float64",
         },
@@ -204,7 +232,7 @@ def run(args):
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": traffic,
+            "traffic": load_traffic(n, nnz),
             "algorithmic_bytes_per_launch": bytes_launch,
             "mean_launch_ms": avg_ms,
             "launches_timed": launches,
@@ -221,6 +249,320 @@ def run(args):
             "spmv_share_of_step": spmv_ms / args.steps / ms_step,
         },
     }
+    return top, iters
+
+
+def run_bicgstab(ctx, args, dev, pat):
+    """Workload 2b: Jacobi-BiCGStab on the same grid with upwind convection
+    at cell Peclet 10 along (1,1,1)/sqrt(3)."""
+    import torch
+
+    from paper_2601_13994_amd import _lib
+
+    a, b = ctx["d3"]
+    n, nnz = a.n, a.nnz
+    vals = torch.as_tensor(ctx["d3_conv_val"]).to(dev)
+    bt = torch.as_tensor(b).to(dev)
+    opts = _lib.make_opts(method="bicgstab", precond="jacobi", rtol=1e-8, max_iter=args.max_iter)
+    x, infos, st = _lib.solve(pat, vals, bt, opts)
+    log(f"[bench] bicgstab warmup: status={st} iters={infos[0]['iters']} true_res={infos[0]['true_residual']:.2e}")
+    _sync()
+    t0 = time.perf_counter()
+    for i in range(args.sub_steps):
+        x, infos, st = _lib.solve(pat, vals, bt, opts)
+    _sync()
+    dt = (time.perf_counter() - t0) / args.sub_steps
+    it = infos[0]["iters"]
+    it_bytes = 2 * (12 * nnz + 4 * (n + 1)) + 176 * n
+    return {
+        "workload": f"diffusion3d-{args.m}^3 + upwind convection (cell Peclet 10), Jacobi-BiCGStab to rtol 1e-8",
+        "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iterations": it, "status": st,
+        "true_relative_residual": infos[0]["true_residual"],
+        "ms_per_iteration": dt * 1e3 / max(it, 1),
+        "iteration_model_GBps": it_bytes * it / dt / 1e9,
+        "iteration_frac_of_peak": it_bytes * it / dt / 1e9 / HBM_PEAK_GBPS,
+        "GFLOPs": (4 * nnz + 26 * n) * it / dt / 1e9,
+        "algorithmic_bytes_per_iteration": it_bytes, "reps": args.sub_steps,
+    }
+
+
+def run_poisson(ctx, args, dev):
+    """Workload 1: 2D Poisson 64^2, plain CG to rtol 1e-10 -- latency of one
+    solve, and throughput of many independent right-hand sides on copies of
+    the matrix solved as one shared-pattern batch."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2601_13994_amd import _lib
+
+    a, b = ctx["p2"]
+    pat = _pattern(dev, a)
+    vals = torch.as_tensor(a.val).to(dev)
+    bt = torch.as_tensor(b).to(dev)
+    opts = _lib.make_opts(method="cg", precond="none", rtol=1e-10)
+    for _ in range(3):
+        x, infos, st = _lib.solve(pat, vals, bt, opts)
+    reps = 50
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        x, infos, st = _lib.solve(pat, vals, bt, opts)
+    _sync()
+    lat = (time.perf_counter() - t0) / reps
+    B = args.poisson_copies
+    vb = vals.repeat(B, 1).contiguous()
+    bb = torch.as_tensor(ctx["p2_bs"]).to(dev)
+    xb, ib, stb = _lib.solve(pat, vb, bb, opts)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.sub_steps):
+        xb, ib, stb = _lib.solve(pat, vb, bb, opts)
+    _sync()
+    tb = (time.perf_counter() - t0) / args.sub_steps
+    it = infos[0]["iters"]
+    itb = np.array([f["iters"] for f in ib])
+    it_bytes = 12 * a.nnz + 4 * (a.n + 1) + 88 * a.n
+    res = {
+        "workload": "poisson2d-64^2 (n=4096, nnz=20224), plain CG to rtol 1e-10, x0=0",
+        "latency_us_per_solve": lat * 1e6, "iterations": it, "status": st,
+        "true_relative_residual": infos[0]["true_residual"],
+        "us_per_iteration": lat * 1e6 / max(it, 1),
+        "batched_copies": B, "batched_solves_per_s": B / tb, "batched_status": stb,
+        "batched_max_iterations": int(itb.max()),
+        "batched_model_GBps": float(it_bytes * itb.sum() / tb / 1e9),
+    }
+    if not args.no_cpu_baseline:
+        oracle.lib()
+        t0 = time.perf_counter()
+        k = 20
+        for _ in range(k):
+            oracle.cg(a, b, precond="none", rtol=1e-10)
+        res["oracle_ms_per_solve"] = (time.perf_counter() - t0) / k * 1e3
+        res["oracle_cores"] = 1
+    return res
+
+
+def run_knn(ctx, args, dev):
+    """Workload 3: ragged k-NN Laplacian systems with distinct patterns, all
+    solved by one persistent launch (Jacobi-PCG to rtol 1e-8)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2601_13994_amd as hs
+
+    systems = ctx["knn"]
+    mats = [(torch.as_tensor(a.val).to(dev), torch.as_tensor(a.row_ptr).to(dev), torch.as_tensor(a.col).to(dev))
+            for a, _ in systems]
+    L = hs.SparseCSRList(mats)
+    del mats
+    bcat = torch.as_tensor(np.concatenate([b for _, b in systems])).to(dev)
+    xs, infos, st = L.solve(bcat, rtol=1e-8)
+    log(f"[bench] knn warmup: status={st}")
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.sub_steps):
+        xs, infos, st = L.solve(bcat, rtol=1e-8)
+    _sync()
+    dt = (time.perf_counter() - t0) / args.sub_steps
+    its = np.array([f["iters"] for f in infos])
+    ns = np.array([a.n for a, _ in systems])
+    nnzs = np.array([a.nnz for a, _ in systems])
+    work = float(((12 * nnzs + 4 * (ns + 1) + 104 * ns) * its).sum())
+    res = {
+        "workload": (f"{len(systems)} k-NN (k=8) Laplacians + 0.01 I, n ~ U[1000, 50000], distinct patterns, "
+                     "one persistent launch, Jacobi-PCG to rtol 1e-8"),
+        "solves_per_s": len(systems) / dt, "ms_per_batch": dt * 1e3, "status": st,
+        "total_rows": int(ns.sum()), "total_nnz": int(nnzs.sum()),
+        "iterations_mean": float(its.mean()), "iterations_max": int(its.max()),
+        "true_relative_residual_max": max(f["true_residual"] for f in infos),
+        "model_GBps": work / dt / 1e9, "model_frac_of_peak": work / dt / 1e9 / HBM_PEAK_GBPS,
+        "reps": args.sub_steps,
+    }
+    if not args.no_cpu_baseline:
+        oracle.lib()
+        k = 8
+        t0 = time.perf_counter()
+        for a, b in systems[:k]:
+            oracle.cg(a, b, precond="jacobi", rtol=1e-8)
+        dto = time.perf_counter() - t0
+        w_all = float((nnzs * its).sum())
+        w_k = float((nnzs[:k] * its[:k]).sum())
+        res["oracle_solves_per_s"] = len(systems) * w_k / (dto * w_all)
+        res["oracle_sample"] = (f"first {k} systems solved one after another on 1 core ({dto:.2f} s); the batch "
+                                "rate assumes time proportional to nnz x iterations per system")
+        res["oracle_cores"] = 1
+    return res
+
+
+def run_adjoint(ctx, args, dev):
+    """Workload 4: shared-pattern batch, forward Jacobi-PCG plus adjoint
+    backward (loss 1/2 ||x - x*||^2) giving dL/db and dL/dA on the pattern."""
+    import numpy as np
+    import torch
+
+    from paper_2601_13994_amd import _lib
+
+    a0, V, Bs, Xs = ctx["adj"]
+    B, n, nnz = V.shape[0], a0.n, a0.nnz
+    pat = _pattern(dev, a0)
+    vals = torch.as_tensor(V).to(dev)
+    bt = torch.as_tensor(Bs).to(dev)
+    xst = torch.as_tensor(Xs).to(dev)
+    opts = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-8)
+
+    def pair():
+        x, fi, st = _lib.solve(pat, vals, bt, opts)
+        gx = x - xst
+        gA, gb, bi, st2 = _lib.adjoint(pat, vals, x, gx, opts)
+        return x, gA, gb, fi, bi, st, st2
+
+    pair()
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.sub_steps):
+        x, gA, gb, fi, bi, st, st2 = pair()
+    _sync()
+    dt = (time.perf_counter() - t0) / args.sub_steps
+    itf = np.array([f["iters"] for f in fi])
+    itb = np.array([f["iters"] for f in bi])
+    per_it = 8 * nnz + 104 * n + (4 * nnz + 4 * (n + 1)) / B
+    work = float(per_it * (itf.sum() + itb.sum()) + B * (12 * nnz + 28 * n))
+    return {
+        "workload": (f"{B} systems on one 3D 7-point pattern, {args.adj_m}^3 (n={n}, nnz={nnz}), log-normal kappa "
+                     "per sample; forward Jacobi-PCG + adjoint, rtol 1e-8, loss 1/2||x - x*||^2"),
+        "pairs_per_s": B / dt, "ms_per_batch": dt * 1e3, "status_forward": st, "status_adjoint": st2,
+        "iterations_forward_mean": float(itf.mean()), "iterations_adjoint_mean": float(itb.mean()),
+        "true_relative_residual_max": max(max(f["true_residual"] for f in fi), max(f["true_residual"] for f in bi)),
+        "model_GBps": work / dt / 1e9, "model_frac_of_peak": work / dt / 1e9 / HBM_PEAK_GBPS,
+        "reps": args.sub_steps,
+    }
+
+
+def run_learned(ctx, args, dev):
+    """Workload 5: train the preconditioner network on the GPU on generated
+    anisotropic systems, then solve the held-out systems batched with
+    learned-FSAI PCG and with Jacobi-PCG; wall-clock time to rtol 1e-8."""
+    import numpy as np
+    import torch
+
+    from paper_2601_13994_amd import _lib, learned
+
+    pa, slots = ctx["aniso_pat"]
+    pat = _pattern(dev, pa)
+    sl = torch.as_tensor(slots).to(dev)
+    st_train = torch.as_tensor(ctx["aniso_train"]).to(dev)
+    st_eval = torch.as_tensor(ctx["aniso_eval"]).to(dev)
+    gen = np.random.default_rng(0)
+    model = learned.LearnedFSAI(seed=0, device=dev)
+    ntr = st_train.shape[0]
+
+    def sample(step):
+        idx = torch.as_tensor(gen.integers(0, ntr, args.train_batch)).to(dev)
+        return learned.aniso_batch_values(sl, st_train[idx])
+
+    _sync()
+    t0 = time.perf_counter()
+    hist = model.train(pat, sample, steps=args.train_steps, probes=args.train_probes, lr=args.train_lr,
+                       lr_final=args.train_lr / 10)
+    _sync()
+    t_train = time.perf_counter() - t0
+    log(f"[bench] learned: trained {args.train_steps} steps in {t_train:.1f}s, loss {np.mean(hist[:5]):.4f} -> "
+        f"{np.mean(hist[-20:]):.4f}")
+    V = learned.aniso_batch_values(sl, st_eval)
+    bt = torch.as_tensor(ctx["aniso_b"]).to(dev)
+    E = V.shape[0]
+    jopts = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-8)
+    w = min(E, 16)  # warm up both paths (graphs, workspaces) on a slice
+    _lib.solve(pat, V[:w].contiguous(), bt[:w].contiguous(), jopts)
+    model.solve(pat, V[:w].contiguous(), bt[:w].contiguous(), rtol=1e-8)
+    _sync()
+    t0 = time.perf_counter()
+    xj, ij, stj = _lib.solve(pat, V, bt, jopts)
+    _sync()
+    tj = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    G, GT = model.factors(pat, V)
+    _sync()
+    tf = time.perf_counter() - t0
+    xl, il, stl = model.solve(pat, V, bt, rtol=1e-8, factors=(G, GT))
+    _sync()
+    tl = time.perf_counter() - t0
+    # independent FP64 residual check of every returned solution
+    rl, bn = _lib.residual_norms(pat, V, bt, xl)
+    rj, _ = _lib.residual_norms(pat, V, bt, xj)
+    rel_l = max(r / max(c, 1e-300) for r, c in zip(rl, bn))
+    rel_j = max(r / max(c, 1e-300) for r, c in zip(rj, bn))
+    itj = np.array([f["iters"] for f in ij])
+    itl = np.array([f["iters"] for f in il])
+    fell = sum(f["status"] == _lib.FELL_BACK for f in il)
+    return {
+        "workload": (f"2D anisotropic diffusion {args.aniso_m}^2 9-point (n={pa.n}, nnz={pa.nnz}), ratio ~ "
+                     f"logU[1,1000], angle ~ U[0,pi); network trained on {ntr} generated systems, evaluated on "
+                     f"{E} held-out systems batched, PCG to rtol 1e-8"),
+        "learned_solves_per_s": E / tl, "jacobi_solves_per_s": E / tj, "speedup_wall_clock": tj / tl,
+        "learned_seconds": tl, "learned_factor_seconds": tf, "jacobi_seconds": tj,
+        "iterations_mean_learned": float(itl.mean()), "iterations_mean_jacobi": float(itj.mean()),
+        "iterations_max_learned": int(itl.max()), "iterations_max_jacobi": int(itj.max()),
+        "iteration_ratio_mean": float((itl / np.maximum(itj, 1)).mean()),
+        "fell_back": int(fell), "status_learned": stl, "status_jacobi": stj,
+        "true_relative_residual_max_learned": rel_l, "true_relative_residual_max_jacobi": rel_j,
+        "train_seconds": t_train, "train_steps": args.train_steps, "train_batch": args.train_batch,
+        "train_probes": args.train_probes, "train_loss_first": float(np.mean(hist[:5])),
+        "train_loss_last": float(np.mean(hist[-20:])),
+    }
+
+
+def run(args):
+    sel = ALL_WORKLOADS if args.workloads == "all" else tuple(w.strip() for w in args.workloads.split(","))
+    bad = [w for w in sel if w not in ALL_WORKLOADS]
+    if bad:
+        raise SystemExit(f"unknown workload(s) {bad}; choose from {ALL_WORKLOADS}")
+    if "diffusion3d" not in sel:
+        raise SystemExit("the diffusion3d workload carries the headline line and cannot be left out")
+    ctx = generate(sel, args)
+
+    import torch
+
+    from paper_2601_13994_amd import _lib
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    a, b = ctx["d3"]
+    log(f"[bench] n={a.n} nnz={a.nnz}")
+    vals = torch.as_tensor(a.val).to(dev)
+    bt = torch.as_tensor(b).to(dev)
+    pat = _pattern(dev, a)
+    _sync()
+    log("[bench] pattern ready")
+    if args.calibrate_copy:
+        # plain copy kernel of known size for counter calibration (1 GiB read + 1 GiB write)
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        _sync()
+        dst.copy_(src)
+        _sync()
+        del src, dst
+        log("[bench] calibration copy done (1 GiB -> 1 GiB)")
+
+    out, iters = run_diffusion(ctx, args, dev, pat, vals, bt)
+    del vals
+    sub = {}
+    runners = {"bicgstab": lambda: run_bicgstab(ctx, args, dev, pat), "poisson2d": lambda: run_poisson(ctx, args, dev),
+               "knn": lambda: run_knn(ctx, args, dev), "adjoint": lambda: run_adjoint(ctx, args, dev),
+               "learned": lambda: run_learned(ctx, args, dev)}
+    for name in sel:
+        if name == "diffusion3d":
+            continue
+        log(f"[bench] workload {name} ...")
+        t = time.time()
+        sub[name] = runners[name]()
+        torch.cuda.empty_cache()
+        log(f"[bench] workload {name} done in {time.time() - t:.1f}s: "
+            + json.dumps({k: v for k, v in sub[name].items() if k != "workload"})[:400])
+    out["workloads"] = sub
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(a, b, iters)
@@ -290,6 +632,19 @@ def main():
     ap.add_argument("--m", type=int, default=256, help="grid edge (256 is the benchmark size)")
     ap.add_argument("--max-iter", type=int, default=0, help="cap iterations (profiling runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workloads", default="all", help="comma list from " + ",".join(ALL_WORKLOADS))
+    ap.add_argument("--sub-steps", type=int, default=2, help="timed repetitions of the other workloads")
+    ap.add_argument("--poisson-copies", type=int, default=1024)
+    ap.add_argument("--knn-systems", type=int, default=512)
+    ap.add_argument("--adj-m", type=int, default=96)
+    ap.add_argument("--adj-batch", type=int, default=128)
+    ap.add_argument("--aniso-m", type=int, default=256)
+    ap.add_argument("--train-systems", type=int, default=4096)
+    ap.add_argument("--eval-systems", type=int, default=1024)
+    ap.add_argument("--train-steps", type=int, default=600)
+    ap.add_argument("--train-batch", type=int, default=4)
+    ap.add_argument("--train-probes", type=int, default=4)
+    ap.add_argument("--train-lr", type=float, default=3e-3)
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a 1 GiB copy for counter calibration")
     ap.add_argument("--summarize-rocprof", metavar="DIR")
     ap.add_argument("--label", default="summary")

@@ -95,23 +95,34 @@ class LearnedFSAI:
         return torch.cat(Gs), torch.cat(GTs)
 
     def solve(self, pat: Pattern, values: torch.Tensor, b: torch.Tensor, rtol=1e-8, max_iter=0, factors=None):
-        """FSAI-PCG with the learned factor; systems whose factor is invalid
-        (non-finite, non-positive diagonal) or whose solve fails are solved
-        again with Jacobi-PCG and reported with status FELL_BACK.
+        """FSAI-PCG with the learned factor.  Systems whose FSAI solve does not
+        end with status OK (a non-finite or non-positive factor diagonal ends
+        it early, so does a breakdown or the iteration cap) are solved again
+        with Jacobi-PCG and reported with status FELL_BACK.
         Returns (x, infos, status)."""
         G, GT = factors if factors is not None else self.factors(pat, values)
-        ok = bool(torch.isfinite(G).all())
-        if ok:
-            opts = _lib.make_opts(method="cg", precond="fsai", rtol=rtol, max_iter=max_iter, G=G, GT=GT)
-            x, infos, st = _lib.solve(pat, values, b, opts)
-            if st == _lib.OK:
-                return x, infos, st
-        opts = _lib.make_opts(method="cg", precond="jacobi", rtol=rtol, max_iter=max_iter)
+        opts = _lib.make_opts(method="cg", precond="fsai", rtol=rtol, max_iter=max_iter, G=G, GT=GT)
         x, infos, st = _lib.solve(pat, values, b, opts)
+        if st == _lib.OK:
+            return x, infos, st
+        bad = [i for i, f in enumerate(infos) if f["status"] != _lib.OK]
+        jopts = _lib.make_opts(method="cg", precond="jacobi", rtol=rtol, max_iter=max_iter)
+        if values.dim() == 1:
+            x, infos, st = _lib.solve(pat, values, b, jopts)
+            fixed = list(zip([0], infos))
+        else:
+            idx = torch.as_tensor(bad, device=values.device)
+            xb, fb, _ = _lib.solve(pat, values[idx].contiguous(), b.view(values.shape[0], -1)[idx].contiguous(), jopts)
+            x.view(values.shape[0], -1)[idx] = xb.view(len(bad), -1)
+            fixed = list(zip(bad, fb))
+        worst = _lib.OK
+        for i, f in fixed:
+            f["status"] = _lib.FELL_BACK if f["status"] == _lib.OK else f["status"]
+            infos[i] = f
         for f in infos:
-            if f["status"] == _lib.OK:
-                f["status"] = _lib.FELL_BACK
-        return x, infos, (_lib.FELL_BACK if st == _lib.OK else st)
+            if f["status"] not in (_lib.OK, _lib.FELL_BACK):
+                worst = f["status"]
+        return x, infos, (worst if worst != _lib.OK else _lib.FELL_BACK)
 
     def train(self, pat: Pattern, sample_values, steps: int, probes: int = 4, lr: float = 3e-3,
               log_every: int = 0, seed: int = 0, lr_final: float | None = None):

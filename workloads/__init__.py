@@ -106,6 +106,59 @@ def poisson2d(m: int) -> Csr:
     return _compress(n, np.where(mask, cols, 0), vals, mask)
 
 
+_D3_CACHE: dict = {}
+
+
+def _d3_pattern(m: int):
+    """Cached 7-point pattern pieces of an m^3 grid: (Csr with zero values,
+    boolean mask (m, m, m, 7) of the stored slots)."""
+    if m not in _D3_CACHE:
+        n = m ** 3
+        idx = np.arange(n, dtype=np.int64).reshape(m, m, m)
+        z, y, x = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+        cols = np.stack([idx - m * m, idx - m, idx - 1, idx, idx + 1, idx + m, idx + m * m], axis=-1)
+        mask = np.stack([z > 0, y > 0, x > 0, np.ones_like(x, bool), x < m - 1, y < m - 1, z < m - 1], axis=-1)
+        a = _compress(n, np.where(mask, cols, 0).reshape(n, 7), np.zeros((n, 7)), mask.reshape(n, 7))
+        _D3_CACHE.clear()
+        _D3_CACHE[m] = (a, mask)
+    return _D3_CACHE[m]
+
+
+def diffusion3d_values(m: int, kappa: np.ndarray | None = None, velocity: float = 0.0,
+                       diffusion: bool = True) -> np.ndarray:
+    """Values (CSR order of the cached 7-point pattern) of diffusion3d."""
+    _, mask = _d3_pattern(m)
+    if kappa is None:
+        kappa = np.ones(m ** 3)
+    k = np.asarray(kappa, dtype=np.float64).reshape(m, m, m)  # [z, y, x]
+
+    def face(axis: int, side: int) -> np.ndarray:
+        """Face coefficient on the side (-1/+1) of each cell along axis."""
+        nb = np.roll(k, -side, axis=axis)
+        hm = 2.0 * k * nb / (k + nb)
+        edge = [slice(None)] * 3
+        edge[axis] = 0 if side < 0 else m - 1
+        hm[tuple(edge)] = k[tuple(edge)]
+        return hm
+
+    if diffusion:
+        # axis 0 = z, 1 = y, 2 = x
+        a_zm, a_ym, a_xm = face(0, -1), face(1, -1), face(2, -1)
+        a_xp, a_yp, a_zp = face(2, +1), face(1, +1), face(0, +1)
+        diag = a_zm + a_ym + a_xm + a_xp + a_yp + a_zp
+        vals = np.stack([-a_zm, -a_ym, -a_xm, diag, -a_xp, -a_yp, -a_zp], axis=-1)
+        del a_zm, a_ym, a_xm, a_xp, a_yp, a_zp
+    else:
+        vals = np.zeros((m, m, m, 7))
+    if velocity:
+        vd = velocity / math.sqrt(3.0)
+        vals[..., 3] += vd + vd + vd
+        vals[..., 0] -= vd
+        vals[..., 1] -= vd
+        vals[..., 2] -= vd
+    return np.ascontiguousarray(vals[mask], dtype=np.float64)
+
+
 def diffusion3d(m: int, kappa: np.ndarray | None = None, velocity: float = 0.0,
                 diffusion: bool = True) -> Csr:
     """3D 7-point cell-centred operator on an m^3 grid, unit spacing, no 1/h^2.
@@ -123,41 +176,8 @@ def diffusion3d(m: int, kappa: np.ndarray | None = None, velocity: float = 0.0,
     * ``diffusion=False`` keeps the 7-point pattern but stores only the
       convection part (upper entries become explicit zeros).
     """
-    n = m ** 3
-    if kappa is None:
-        kappa = np.ones(n)
-    k = np.asarray(kappa, dtype=np.float64).reshape(m, m, m)  # [z, y, x]
-
-    def face(axis: int, side: int) -> np.ndarray:
-        """Face coefficient on the side (-1/+1) of each cell along axis."""
-        nb = np.roll(k, -side, axis=axis)
-        hm = 2.0 * k * nb / (k + nb)
-        edge = [slice(None)] * 3
-        edge[axis] = 0 if side < 0 else m - 1
-        hm[tuple(edge)] = k[tuple(edge)]
-        return hm
-
-    # axis 0 = z, 1 = y, 2 = x
-    a_zm, a_ym, a_xm = face(0, -1), face(1, -1), face(2, -1)
-    a_xp, a_yp, a_zp = face(2, +1), face(1, +1), face(0, +1)
-    idx = np.arange(n, dtype=np.int64).reshape(m, m, m)
-    z, y, x = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
-    cols = np.stack([idx - m * m, idx - m, idx - 1, idx, idx + 1, idx + m, idx + m * m], axis=-1)
-    mask = np.stack([z > 0, y > 0, x > 0, np.ones_like(x, bool), x < m - 1, y < m - 1, z < m - 1], axis=-1)
-    del z, y, x
-    if diffusion:
-        diag = a_zm + a_ym + a_xm + a_xp + a_yp + a_zp
-        vals = np.stack([-a_zm, -a_ym, -a_xm, diag, -a_xp, -a_yp, -a_zp], axis=-1)
-    else:
-        vals = np.zeros(cols.shape)
-    del a_zm, a_ym, a_xm, a_xp, a_yp, a_zp
-    if velocity:
-        vd = velocity / math.sqrt(3.0)
-        vals[..., 3] += vd + vd + vd
-        vals[..., 0] -= vd
-        vals[..., 1] -= vd
-        vals[..., 2] -= vd
-    return _compress(n, np.where(mask, cols, 0).reshape(n, 7), vals.reshape(n, 7), mask.reshape(n, 7))
+    a, _ = _d3_pattern(m)
+    return Csr(a.n, a.row_ptr, a.col, diffusion3d_values(m, kappa, velocity, diffusion))
 
 
 def aniso_tensor(ratio: float, angle: float) -> tuple[float, float, float]:
@@ -361,20 +381,35 @@ def knn_system(sample: int, n_lo: int = 1000, n_hi: int = 50000, morton: bool = 
     return a, b
 
 
-def shared_pattern_batch(m: int = 96, batch: int = 128):
+def shared_pattern_batch(m: int = 96, batch: int = 128, workers: int = 1):
     """Workload 4: ``batch`` samples of 3D log-normal diffusion on one m^3
     pattern.  Returns (pattern Csr of sample 0, values[B, nnz], b[B, n],
-    xstar[B, n])."""
-    vals, bs, xs = [], [], []
-    a0 = None
+    xstar[B, n]).  ``workers`` > 1 builds the samples in forked processes
+    (call it before the process touches a GPU)."""
+    a0, _ = _d3_pattern(m)
+    n = a0.n
+    vals = np.empty((batch, a0.nnz))
+    bs = np.empty((batch, n))
+    xs = np.empty((batch, n))
+    if workers > 1 and batch > 1:
+        import concurrent.futures as cf
+        import functools
+        import multiprocessing as mp
+
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+            for s, v in enumerate(ex.map(functools.partial(_d4_values, m), range(batch))):
+                vals[s] = v
+    else:
+        for s in range(batch):
+            vals[s] = _d4_values(m, s)
     for s in range(batch):
-        a = diffusion3d(m, diffusion3d_kappa(m, cfg=4, sample=s))
-        if a0 is None:
-            a0 = a
-        vals.append(a.val)
-        bs.append(rng(4, 1, s).standard_normal(a.n))
-        xs.append(rng(4, 2, s).standard_normal(a.n))
-    return a0, np.stack(vals), np.stack(bs), np.stack(xs)
+        bs[s] = rng(4, 1, s).standard_normal(n)
+        xs[s] = rng(4, 2, s).standard_normal(n)
+    return Csr(n, a0.row_ptr, a0.col, vals[0]), vals, bs, xs
+
+
+def _d4_values(m: int, s: int) -> np.ndarray:
+    return diffusion3d_values(m, diffusion3d_kappa(m, cfg=4, sample=s))
 
 
 def aniso_params(sample: int, heldout: bool = False) -> tuple[float, float]:
@@ -390,6 +425,23 @@ def aniso_system(sample: int, m: int = 256, heldout: bool = False):
     a = aniso2d(m, ratio, angle)
     b = rng(5, 5 if heldout else 1, sample).standard_normal(a.n)
     return a, b
+
+
+def knn_systems(count: int, workers: int = 8, **kw):
+    """The first ``count`` ragged k-NN systems (workload 3), built in forked
+    processes (call it before the process touches a GPU)."""
+    if workers <= 1 or count <= 1:
+        return [knn_system(s, **kw) for s in range(count)]
+    import concurrent.futures as cf
+    import functools
+    import multiprocessing as mp
+
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(functools.partial(_knn_one, kw=kw), range(count), chunksize=4))
+
+
+def _knn_one(s, kw):
+    return knn_system(s, **kw)
 
 
 def rademacher(r: np.random.Generator, shape) -> np.ndarray:
