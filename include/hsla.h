@@ -15,7 +15,8 @@
  * warning with valid output; < 0 = error, outputs undefined.  A message for
  * the last error on a handle is available from hsla_last_error().  No C++
  * exception crosses this boundary.  A handle is not thread-safe; patterns
- * are immutable after creation and may be shared by handles on one device.
+ * may be shared by handles on one device and change only through
+ * hsla_pattern_set_format.
  *
  * The problem statement is the paper's x = A.solve(b) with A given by a
  * sparsity pattern and values, differentiable in both the values and b
@@ -107,6 +108,20 @@ void hsla_pattern_destroy(hsla_pattern *p);
  * equals its transpose. */
 hsla_status hsla_pattern_info(const hsla_pattern *p, int32_t *n, int64_t *nnz, int64_t *nnz_lower,
                               int32_t *pattern_symmetric);
+/* SpMV storage forms.  At creation the library also derives, for A, A^T and
+ * the lower/upper triangles, an offset-mask form wherever every entry lies
+ * on one of at most 16 fixed diagonals (col - row in a fixed set, as for
+ * structured-grid stencils): one 16-bit mask per row replaces the 4-byte
+ * column index of every entry, cutting the bytes each SpMV streams.
+ * AUTO (the default) uses that form where it exists, CSR always uses the
+ * column indices.  Both give bitwise identical results. */
+typedef enum hsla_format { HSLA_FORMAT_AUTO = 0, HSLA_FORMAT_CSR = 1 } hsla_format;
+/* Selects the form later calls on `p` use; must not run concurrently with
+ * calls that use `p`.  HSLA_ERR_INVALID_ARG for an unknown format. */
+hsla_status hsla_pattern_set_format(hsla_pattern *p, int32_t format);
+/* stencil_in_use: 1 if A's SpMV currently uses the offset-mask form;
+ * num_offsets: number of distinct diagonals of A, 0 if A has no such form. */
+hsla_status hsla_pattern_format(const hsla_pattern *p, int32_t *stencil_in_use, int32_t *num_offsets);
 /* Device copies of the transpose: row_ptr_T int32[n+1], col_T int32[nnz] and
  * src int32[nnz] with src[k'] = position in A of the entry stored at k' of
  * A^T (a bijection).  Host-visible only through the copy. */

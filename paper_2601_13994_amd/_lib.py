@@ -23,11 +23,13 @@ ERR_NO_MEMORY, ERR_ZERO_DIAGONAL, ERR_INTERNAL = -5, -6, -7
 METHODS = {"auto": 0, "cg": 1, "bicgstab": 2}
 METHOD_NAMES = {v: k for k, v in METHODS.items()}
 PRECONDS = {"none": 0, "jacobi": 1, "fsai": 2}
+FORMATS = {"auto": 0, "csr": 1}
 
 # every symbol include/hsla.h declares
 EXPORTS = [
     "hsla_opts_default", "hsla_status_string", "hsla_create", "hsla_destroy", "hsla_last_error",
-    "hsla_pattern_create", "hsla_pattern_destroy", "hsla_pattern_info", "hsla_pattern_transpose",
+    "hsla_pattern_create", "hsla_pattern_destroy", "hsla_pattern_info", "hsla_pattern_set_format",
+    "hsla_pattern_format", "hsla_pattern_transpose",
     "hsla_spmv", "hsla_solve", "hsla_solve_batched", "hsla_adjoint", "hsla_adjoint_batched",
     "hsla_outer_on_pattern", "hsla_residual_norms",
     "hsla_mpnn_num_params", "hsla_mpnn_forward", "hsla_mpnn_backward", "hsla_probe_loss", "hsla_adam_step",
@@ -95,6 +97,8 @@ def load() -> ctypes.CDLL:
         L.hsla_pattern_destroy.argtypes = [vp]
         L.hsla_pattern_destroy.restype = None
         L.hsla_pattern_info.argtypes = [vp, P(i32), P(i64), P(i64), P(i32)]
+        L.hsla_pattern_set_format.argtypes = [vp, i32]
+        L.hsla_pattern_format.argtypes = [vp, P(i32), P(i32)]
         L.hsla_pattern_transpose.argtypes = [vp, vp, vp, vp, vp, vp]
         L.hsla_spmv.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.hsla_solve.argtypes = [vp, vp, vp, vp, vp, P(Opts), P(Info), vp]
@@ -203,6 +207,20 @@ class Pattern:
         load().hsla_pattern_info(self.p, ctypes.byref(n_), ctypes.byref(nnz_), ctypes.byref(nl), ctypes.byref(sym))
         self.nnz_lower = nl.value
         self.pattern_symmetric = bool(sym.value)
+
+    @property
+    def stencil(self) -> tuple[bool, int]:
+        """(offset-mask form in use for A's SpMV, number of its diagonals or 0)."""
+        use = ctypes.c_int32()
+        nofs = ctypes.c_int32()
+        load().hsla_pattern_format(self.p, ctypes.byref(use), ctypes.byref(nofs))
+        return bool(use.value), nofs.value
+
+    def set_format(self, fmt: str) -> None:
+        """'auto' (offset-mask form where available) or 'csr'."""
+        st = load().hsla_pattern_set_format(self.p, FORMATS[fmt])
+        if st != OK:
+            raise HslaError(st, f"unknown format {fmt!r}")
 
     def __del__(self):
         p = getattr(self, "p", None)

@@ -17,6 +17,18 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kTileRows = 64;           // rows per SpMV tile: one lane per row
 constexpr int kTileCap = 512;           // max stored entries staged per tile (LDS, per wave)
 constexpr int kXcds = 8;                // MI355X: 8 XCDs, blocks dispatched round-robin
+constexpr int kMaxOffsets = 16;         // distinct column offsets of a stencil pattern
+
+// Offset-mask form of a CSR pattern whose entries all lie on a few fixed
+// diagonals (structured-grid stencils): column = row + ofs[s] for every set
+// bit s of mask[row], bits in ascending order = entries in CSR order.  It
+// replaces the 4-byte column index of every entry by 2 bytes per row; the
+// values keep their CSR layout.  mask == nullptr: not a stencil pattern.
+struct Stencil {
+    const uint16_t *mask = nullptr;
+    int32_t nofs = 0;
+    int32_t ofs[kMaxOffsets] = {};
+};
 
 // Per-system solver state (device memory, one record per system).
 struct alignas(128) SysState {
@@ -46,6 +58,7 @@ struct DevInfo {
 
 struct hsla_pattern {
     int device = 0;
+    int32_t format = HSLA_FORMAT_AUTO;  // requested SpMV format
     int32_t n = 0;
     int64_t nnz = 0;
     int32_t *row_ptr = nullptr;  // [n+1]
@@ -68,6 +81,13 @@ struct hsla_pattern {
     int32_t ntilesU = 0;
     int32_t *rowL = nullptr;     // row of each lower entry
     uint8_t *isdiagL = nullptr;  // lower entry on the diagonal
+    // offset-mask forms of A, A^T, L, U (mask == nullptr where not a stencil)
+    hsla::Stencil stA, stT, stL, stU;
+    // the form the kernels use: the stencil form unless the CSR form was requested
+    const hsla::Stencil &use(const hsla::Stencil &s) const {
+        static const hsla::Stencil none{};
+        return format == HSLA_FORMAT_CSR ? none : s;
+    }
 };
 
 struct hsla_handle {
@@ -258,9 +278,10 @@ struct TileWalk {
 // column loads are in flight while the current tile gathers and sums.
 // epi(row, y) is called on the lane owning each row.
 template <typename VT, class Epi>
-__device__ __forceinline__ void spmv_tiles(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                           const VT *__restrict__ val, const double *__restrict__ x,
-                                           const int2 *__restrict__ meta, int32_t ntiles, double *lds, Epi &&epi) {
+__device__ __forceinline__ void spmv_tiles_csr(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                               const VT *__restrict__ val, const double *__restrict__ x,
+                                               const int2 *__restrict__ meta, int32_t ntiles, double *lds,
+                                               Epi &&epi) {
     constexpr int U = kTileCap / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const TileWalk tw(ntiles);
@@ -348,6 +369,121 @@ __device__ __forceinline__ void spmv_tiles(const int32_t *__restrict__ rp, const
         m0 = n0;
         m1 = n1;
     }
+}
+
+// The same tiled SpMV on the offset-mask form.  Tiles, value layout, LDS
+// staging and the per-row ascending summation are those of the CSR walk, so
+// the result is bitwise identical; only the column of each staged entry is
+// derived from the row masks: each lane turns its row's mask into column
+// offsets (relative to the tile's first row) written at its row's slot in
+// LDS (slots = exclusive prefix sum of the rows' entry counts), and every
+// lane then reads the column of the entries it loads.  The LDS words that
+// held the offsets are overwritten by the products afterwards.
+template <typename VT, class Epi>
+__device__ __forceinline__ void spmv_tiles_stencil(const Stencil &sn, const VT *__restrict__ val,
+                                                   const double *__restrict__ x, const int2 *__restrict__ meta,
+                                                   int32_t ntiles, double *lds, Epi &&epi) {
+    constexpr int U = kTileCap / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    int32_t *ldc = reinterpret_cast<int32_t *>(lds);
+    const uint16_t *__restrict__ mask = sn.mask;
+    const TileWalk tw(ntiles);
+    const int R = tw.rounds();
+    int32_t t = tw.tile(0);
+    if (R == 0 || t < 0) return;
+    int2 m0 = meta[t], m1 = meta[t + 1];
+    VT v[U];
+    uint32_t mk = 0;
+    auto issue = [&](int2 a, int2 b, VT *vv, uint32_t &mm) {
+        const int32_t k0 = a.y, cnt = b.y - a.y;
+        const int32_t row = a.x + lane;
+        mm = row < b.x ? (uint32_t)__builtin_nontemporal_load(&mask[row]) : 0u;
+        if (cnt > 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = u * kWave + lane;
+                vv[u] = __builtin_nontemporal_load(&val[k0 + (e < cnt ? e : cnt - 1)]);
+            }
+        }
+    };
+    issue(m0, m1, v, mk);
+    for (int r = 0; r < R; ++r) {
+        const int32_t tn = tw.tile(r + 1);
+        int2 n0 = m1, n1 = m1;
+        if (tn >= 0) {
+            n0 = meta[tn];
+            n1 = meta[tn + 1];
+        }
+        const int32_t cnt = m1.y - m0.y;
+        // this row's entries occupy slots [ra, rb) of the tile
+        const int32_t own_cnt = __popc(mk);
+        int32_t incl = own_cnt;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int32_t y = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += y;
+        }
+        const int32_t ra = incl - own_cnt, rb = incl;
+        {
+            int32_t k = ra;
+#pragma unroll
+            for (int s = 0; s < kMaxOffsets; ++s)
+                if ((mk >> s) & 1u) ldc[k++] = lane + sn.ofs[s];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int32_t c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t e = u * kWave + lane;
+            c[u] = m0.x + (e < cnt ? ldc[e] : 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = cnt > 0 ? x[c[u]] : 0.0;
+        VT vn[U];
+        uint32_t mkn = 0;
+        if (tn >= 0) issue(n0, n1, vn, mkn);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t e = u * kWave + lane;
+            if (e < cnt) lds[e] = (double)v[u] * xv[u];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int32_t row = m0.x + lane;
+        const bool own = row < m1.x;
+        double s = 0.0;
+        if (own)
+            for (int32_t k = ra; k < rb; ++k) s += lds[k];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (own) epi(row, s);
+        if (tn < 0) break;
+        mk = mkn;
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = vn[u];
+        m0 = n0;
+        m1 = n1;
+    }
+}
+
+// Tiled SpMV on whichever form the pattern carries (uniform branch).
+template <typename VT, class Epi>
+__device__ __forceinline__ void spmv_tiles(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                           const Stencil &sn, const VT *__restrict__ val,
+                                           const double *__restrict__ x, const int2 *__restrict__ meta,
+                                           int32_t ntiles, double *lds, Epi &&epi) {
+    if (sn.mask)
+        spmv_tiles_stencil(sn, val, x, meta, ntiles, lds, epi);
+    else
+        spmv_tiles_csr(rp, col, val, x, meta, ntiles, lds, epi);
 }
 
 }  // namespace hsla

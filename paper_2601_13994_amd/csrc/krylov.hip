@@ -4,8 +4,8 @@
 //
 // One iteration is a short chain of kernels on one stream; every dot
 // product is folded into the kernel that produces its operands and reduced
-// in a single pass (block partials + ticket, fixed summation order), and
-// the block that completes a reduction also advances the scalar recurrence
+// in a single pass: blocks store partials, and a one-block finalize kernel
+// per system adds them in a fixed order and advances the scalar recurrence
 // (alpha, beta, omega, stop test) in device memory.  Kernels of a stopped
 // system return at entry, so chunks of K iterations are enqueued (and
 // replayed as a HIP graph) with one host check per chunk.
@@ -25,6 +25,7 @@ struct Pat {
     const int2 *meta;
     int32_t ntiles, n;
     int64_t nnz;
+    Stencil sn;  // offset-mask form in use (mask == nullptr: CSR)
 };
 
 struct FPat {  // pattern + values of one FSAI factor (float32 values)
@@ -33,7 +34,16 @@ struct FPat {  // pattern + values of one FSAI factor (float32 values)
     int32_t ntiles;
     int64_t nnz;
     const float *val;
+    Stencil sn;
 };
+
+static Pat pat_of(const hsla_pattern *p) {
+    return Pat{p->row_ptr, p->col, p->diag, p->meta, p->ntiles, p->n, p->nnz, p->use(p->stA)};
+}
+
+static Pat pat_T_of(const hsla_pattern *p) {
+    return Pat{p->rpT, p->colT, p->diagT, p->metaT, p->ntilesT, p->n, p->nnz, p->use(p->stT)};
+}
 
 struct Sys {
     const double *val;  // [B][nnz]
@@ -100,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Pat A, const double *__restrict
     val += sidx * A.nnz;
     x += sidx * A.n;
     y += sidx * A.n;
-    spmv_tiles(A.rp, A.col, val, x, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+    spmv_tiles(A.rp, A.col, A.sn, val, x, A.meta, A.ntiles, lds[threadIdx.x / kWave],
                [&](int32_t row, double yv) {
                    y[row] = yv;
                });
@@ -184,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(Pat A, Sys S) {
     const double *p = S.p + vo;
     double *q = S.q + vo;
     double acc[1] = {0.0};
-    spmv_tiles(A.rp, A.col, val, p, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+    spmv_tiles(A.rp, A.col, A.sn, val, p, A.meta, A.ntiles, lds[threadIdx.x / kWave],
                [&](int32_t row, double yv) {
                    q[row] = yv;
                    acc[0] += p[row] * yv;
@@ -313,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_fsai_lower(Pat A, FPat L, Sys S) {
     const float *g = L.val + sidx * L.nnz;
     const double *r = S.r + vo;
     double *w = S.w + vo;
-    spmv_tiles(L.rp, L.col, g, r, L.meta, L.ntiles, lds[threadIdx.x / kWave],
+    spmv_tiles(L.rp, L.col, L.sn, g, r, L.meta, L.ntiles, lds[threadIdx.x / kWave],
                [&](int32_t row, double yv) {
                    w[row] = yv;
                });
@@ -329,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_fsai_upper_dot(Pat A, FPat U, Sys S)
     const double *r = S.r + vo;
     double *z = S.z + vo;
     double acc[1] = {0.0};
-    spmv_tiles(U.rp, U.col, g, w, U.meta, U.ntiles, lds[threadIdx.x / kWave],
+    spmv_tiles(U.rp, U.col, U.sn, g, w, U.meta, U.ntiles, lds[threadIdx.x / kWave],
                [&](int32_t row, double yv) {
                    z[row] = yv;
                    acc[0] += r[row] * yv;
@@ -503,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_v(Pat A, Sys S) {
     const double *rh = S.rh + vo;
     double *v = S.v + vo;
     double acc[1] = {0.0};
-    spmv_tiles(A.rp, A.col, val, ph, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+    spmv_tiles(A.rp, A.col, A.sn, val, ph, A.meta, A.ntiles, lds[threadIdx.x / kWave],
                [&](int32_t row, double yv) {
                    v[row] = yv;
                    acc[0] += rh[row] * yv;
@@ -596,7 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_t(Pat A, Sys S) {
     const double *s = S.s + vo;
     double *t = S.t + vo;
     double acc[2] = {0.0, 0.0};
-    spmv_tiles(A.rp, A.col, val, sh, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+    spmv_tiles(A.rp, A.col, A.sn, val, sh, A.meta, A.ntiles, lds[threadIdx.x / kWave],
                [&](int32_t row, double yv) {
                    t[row] = yv;
                    acc[0] += yv * s[row];
@@ -729,7 +739,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Pat A, Sys S) {
     const double *x = S.x + vo;
     const double *b = S.b + vo;
     double acc[2] = {0.0, 0.0};
-    spmv_tiles(A.rp, A.col, val, x, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+    spmv_tiles(A.rp, A.col, A.sn, val, x, A.meta, A.ntiles, lds[threadIdx.x / kWave],
                [&](int32_t row, double yv) {
                    const double e = b[row] - yv;
                    acc[0] += e * e;
@@ -812,7 +822,7 @@ static Layout make_layout(int B, int64_t n, int nvec, int G) {
 hsla_status launch_spmv(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *x,
                         double *y, hipStream_t s) {
     if (p->n == 0 || B == 0) return HSLA_OK;
-    Pat A{p->row_ptr, p->col, p->diag, p->meta, p->ntiles, p->n, p->nnz};
+    const Pat A = pat_of(p);
     const int G = grid_blocks(h, kWavesPerBlock, p->ntiles, 1, 16);
     k_spmv<<<dim3(G, B), kBlock, 0, s>>>(A, values, x, y);
     HSLA_HIP(h, hipGetLastError());
@@ -1176,12 +1186,12 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
         if (st != HSLA_OK) return st;
         method = sym ? HSLA_METHOD_CG : HSLA_METHOD_BICGSTAB;
     }
-    Pat A{p->row_ptr, p->col, p->diag, p->meta, p->ntiles, p->n, p->nnz};
+    const Pat A = pat_of(p);
     FPat L{}, U{};
     if (o.precond == HSLA_PRECOND_FSAI) {
         if (!o.d_G || !o.d_GT) return set_error(h, HSLA_ERR_INVALID_ARG, "FSAI needs d_G and d_GT");
-        L = FPat{p->rpL, p->colL, p->metaL, p->ntilesL, p->nnz_lower, o.d_G};
-        U = FPat{p->rpU, p->colU, p->metaU, p->ntilesU, p->nnz_lower, o.d_GT};
+        L = FPat{p->rpL, p->colL, p->metaL, p->ntilesL, p->nnz_lower, o.d_G, p->use(p->stL)};
+        U = FPat{p->rpU, p->colU, p->metaU, p->ntilesU, p->nnz_lower, o.d_GT, p->use(p->stU)};
     }
     return solve_core(h, A, &L, &U, B, values, b, x, o, method, infos, s);
 }
@@ -1219,7 +1229,7 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
     }
     hsla_status res;
     if (sym) {
-        Pat A{p->row_ptr, p->col, p->diag, p->meta, p->ntiles, p->n, p->nnz};
+        const Pat A = pat_of(p);
         res = solve_core(h, A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s);
     } else {
         if (hipMalloc((void **)&valT, sizeof(double) * (size_t)B * (p->nnz > 0 ? p->nnz : 1)) != hipSuccess) {
@@ -1230,7 +1240,7 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
         int blocks = (int)((tot + kBlock - 1) / kBlock);
         if (blocks > 8192) blocks = 8192;
         if (tot > 0) k_gather_values<<<blocks, kBlock, 0, s>>>(p->nnz, B, values, p->srcT, valT);
-        Pat AT{p->rpT, p->colT, p->diagT, p->metaT, p->ntilesT, p->n, p->nnz};
+        const Pat AT = pat_T_of(p);
         res = solve_core(h, AT, nullptr, nullptr, B, valT, gx, lam, o, method, infos, s);
     }
     if (res >= 0 && gA) {
@@ -1321,7 +1331,7 @@ hsla_status hsla_residual_norms(hsla_handle *h, const hsla_pattern *p, int32_t B
     S.st = (hsla::SysState *)(ws + lay.off_state);
     S.part = (double *)(ws + lay.off_part);
     hsla::k_reset<<<1, hsla::kBlock, 0, s>>>(S.st, B, 1);
-    const hsla::Pat A{p->row_ptr, p->col, p->diag, p->meta, p->ntiles, p->n, p->nnz};
+    const hsla::Pat A = hsla::pat_of(p);
     double *res = (double *)(ws + lay.off_res);
     std::vector<double> hr(2 * (size_t)B, 0.0);
     if (p->n > 0) {

@@ -607,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(SpPat A, int P, int32_t n, con
     const VT *v = val + (bp / P) * A.nnz;
     const double *xb = x + bp * n;
     double *yb = y + bp * n;
-    spmv_tiles(A.rp, A.col, v, xb, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+    spmv_tiles(A.rp, A.col, Stencil{}, v, xb, A.meta, A.ntiles, lds[threadIdx.x / kWave],
                [&](int32_t row, double yv) { yb[row] = yv; });
 }
 

@@ -4,6 +4,7 @@
 #include <climits>
 #include <cstdarg>
 #include <cstring>
+#include <algorithm>
 #include <vector>
 
 #include "common.h"
@@ -307,8 +308,8 @@ static hsla_status device_transpose(hsla_handle *h, int32_t n, int64_t nnz, cons
 // tile by itself.  Built on the host from a copy of row_ptr; meta[t] =
 // (first row, first entry) of tile t and meta[T] = (n, nnz).
 static hsla_status build_tiles(hsla_handle *h, int32_t n, const int32_t *d_rp, hipStream_t s, int2 **d_meta,
-                               int32_t *ntiles) {
-    std::vector<int32_t> rp(n + 1);
+                               int32_t *ntiles, std::vector<int32_t> &rp) {
+    rp.assign((size_t)n + 1, 0);
     HSLA_HIP(h, hipMemcpyAsync(rp.data(), d_rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
     HSLA_HIP(h, hipStreamSynchronize(s));
     std::vector<int2> t;
@@ -338,8 +339,104 @@ static hsla_status build_tiles(hsla_handle *h, int32_t n, const int32_t *d_rp, h
     return HSLA_OK;
 }
 
+// Row masks of the offset-mask form: bit s of mask[i] <=> row i stores
+// column i + ofs[s].  `bad` is set if an entry lies on no listed diagonal.
+// Columns increase within a row and ofs increases, so bit order is entry
+// order.
+__global__ __launch_bounds__(kBlock) void k_build_mask(int32_t n, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col, Stencil sn,
+                                                       uint16_t *__restrict__ mask, int32_t *bad) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        uint32_t m = 0;
+        bool ok = true;
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int32_t d = col[k] - (int32_t)i;
+            int s = -1;
+#pragma unroll
+            for (int j = 0; j < kMaxOffsets; ++j)
+                if (j < sn.nofs && sn.ofs[j] == d) s = j;
+            if (s < 0)
+                ok = false;
+            else
+                m |= 1u << s;
+        }
+        mask[i] = (uint16_t)m;
+        if (!ok) *bad = 1;
+    }
+}
+
+// Offset-mask form of a CSR structure, if it has one.  Candidate diagonals
+// come from sampled rows (the first, middle and last rows and 16 spread
+// blocks); the device then builds every row's mask and checks that no entry
+// lies off the candidates.  Leaves *out empty when the structure has more
+// than kMaxOffsets diagonals or the check fails.
+static hsla_status build_stencil(hsla_handle *h, int32_t n, int64_t nnz, const std::vector<int32_t> &rp,
+                                 const int32_t *d_rp, const int32_t *d_col, hipStream_t s, Stencil *out) {
+    *out = Stencil{};
+    if (n <= 0 || nnz <= 0) return HSLA_OK;
+    std::vector<int64_t> ofs;
+    bool too_many = false;
+    std::vector<int32_t> c;
+    auto sample = [&](int64_t r0, int64_t r1) -> hipError_t {
+        r0 = r0 < 0 ? 0 : r0;
+        r1 = r1 > n ? n : r1;
+        if (too_many || r0 >= r1 || rp[r1] == rp[r0]) return hipSuccess;
+        const int32_t k0 = rp[r0], k1 = rp[r1];
+        c.resize((size_t)(k1 - k0));
+        hipError_t e = hipMemcpyAsync(c.data(), d_col + k0, sizeof(int32_t) * (k1 - k0), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        for (int64_t r = r0; r < r1 && !too_many; ++r)
+            for (int32_t k = rp[r]; k < rp[r + 1]; ++k) {
+                const int64_t d = (int64_t)c[k - k0] - r;
+                bool seen = false;
+                for (int64_t o : ofs) seen |= (o == d);
+                if (!seen) {
+                    if ((int)ofs.size() == kMaxOffsets) {
+                        too_many = true;
+                        break;
+                    }
+                    ofs.push_back(d);
+                }
+            }
+        return hipSuccess;
+    };
+    HSLA_HIP(h, sample(0, 2048));
+    HSLA_HIP(h, sample((int64_t)n / 2 - 1024, (int64_t)n / 2 + 1024));
+    HSLA_HIP(h, sample((int64_t)n - 2048, n));
+    for (int j = 1; j <= 16; ++j) HSLA_HIP(h, sample((int64_t)n * j / 17, (int64_t)n * j / 17 + 128));
+    if (too_many || ofs.empty()) return HSLA_OK;
+    std::sort(ofs.begin(), ofs.end());
+    Stencil st{};
+    st.nofs = (int32_t)ofs.size();
+    for (int j = 0; j < st.nofs; ++j) st.ofs[j] = (int32_t)ofs[j];
+    uint16_t *mask = nullptr;
+    int32_t *bad = nullptr;
+    int32_t hbad = 0;
+    HSLA_HIP(h, hipMalloc((void **)&mask, sizeof(uint16_t) * (size_t)n));
+    hipError_t e = hipMalloc((void **)&bad, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int32_t), s);
+    if (e == hipSuccess) {
+        k_build_mask<<<blocks_for(n), kBlock, 0, s>>>(n, d_rp, d_col, st, mask, bad);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (bad) (void)hipFree(bad);
+    if (e != hipSuccess || hbad) {
+        (void)hipFree(mask);
+        if (e != hipSuccess) return set_error(h, HSLA_ERR_HIP, "stencil form: %s", hipGetErrorString(e));
+        return HSLA_OK;
+    }
+    st.mask = mask;
+    *out = st;
+    return HSLA_OK;
+}
+
 static void free_pattern(hsla_pattern *p) {
     if (!p) return;
+    for (const Stencil *st : {&p->stA, &p->stT, &p->stL, &p->stU})
+        if (st->mask) (void)hipFree(const_cast<uint16_t *>(st->mask));
     void *bufs[] = {p->row_ptr, p->col, p->diag, p->meta, p->rpT, p->colT, p->srcT, p->metaT, p->diagT,
                     p->rpL, p->colL, p->posL, p->metaL, p->rpU, p->colU, p->srcU, p->metaU, p->rowL, p->isdiagL};
     for (void *b : bufs)
@@ -400,7 +497,9 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
     }
     p->nnz_lower = hf.nnz_lower;
 
-    hsla_status st = build_tiles(h, n, p->row_ptr, s, &p->meta, &p->ntiles);
+    std::vector<int32_t> hrp;
+    hsla_status st = build_tiles(h, n, p->row_ptr, s, &p->meta, &p->ntiles, hrp);
+    if (st == HSLA_OK) st = build_stencil(h, n, nnz, hrp, p->row_ptr, p->col, s, &p->stA);
     if (st != HSLA_OK) { (void)hipFree(df); return fail(st); }
 
     // transpose and pattern symmetry
@@ -416,7 +515,8 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
     PCHK(hipStreamSynchronize(s));
     p->pattern_symmetric = hf.differ ? 0 : 1;
     (void)hipFree(df);
-    st = build_tiles(h, n, p->rpT, s, &p->metaT, &p->ntilesT);
+    st = build_tiles(h, n, p->rpT, s, &p->metaT, &p->ntilesT, hrp);
+    if (st == HSLA_OK) st = build_stencil(h, n, nnz, hrp, p->rpT, p->colT, s, &p->stT);
     if (st != HSLA_OK) return fail(st);
     PCHK(hipMalloc((void **)&p->diagT, sizeof(int32_t) * (nn > 0 ? nn : 1)));
     if (n > 0) k_find_diag<<<blocks_for(n), kBlock, 0, s>>>(n, p->rpT, p->colT, p->diagT);
@@ -435,14 +535,16 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
         k_fill_lower<<<blocks_for(n), kBlock, 0, s>>>(n, p->row_ptr, p->col, p->rpL, p->colL, p->posL);
         PCHK(hipGetLastError());
     }
-    st = build_tiles(h, n, p->rpL, s, &p->metaL, &p->ntilesL);
+    st = build_tiles(h, n, p->rpL, s, &p->metaL, &p->ntilesL, hrp);
+    if (st == HSLA_OK) st = build_stencil(h, n, nL, hrp, p->rpL, p->colL, s, &p->stL);
     if (st != HSLA_OK) return fail(st);
     PCHK(hipMalloc((void **)&p->rpU, sizeof(int32_t) * (nn + 1)));
     PCHK(hipMalloc((void **)&p->colU, sizeof(int32_t) * (nL > 0 ? nL : 1)));
     PCHK(hipMalloc((void **)&p->srcU, sizeof(int32_t) * (nL > 0 ? nL : 1)));
     st = device_transpose(h, n, nL, p->rpL, p->colL, p->rpU, p->colU, p->srcU, s);
     if (st != HSLA_OK) return fail(st);
-    st = build_tiles(h, n, p->rpU, s, &p->metaU, &p->ntilesU);
+    st = build_tiles(h, n, p->rpU, s, &p->metaU, &p->ntilesU, hrp);
+    if (st == HSLA_OK) st = build_stencil(h, n, nL, hrp, p->rpU, p->colU, s, &p->stU);
     if (st != HSLA_OK) return fail(st);
     PCHK(hipMalloc((void **)&p->rowL, sizeof(int32_t) * (nL > 0 ? nL : 1)));
     PCHK(hipMalloc((void **)&p->isdiagL, (nL > 0 ? nL : 1)));
@@ -555,6 +657,19 @@ hsla_status hsla_pattern_info(const hsla_pattern *p, int32_t *n, int64_t *nnz, i
     if (nnz) *nnz = p->nnz;
     if (nnz_lower) *nnz_lower = p->nnz_lower;
     if (pattern_symmetric) *pattern_symmetric = p->pattern_symmetric;
+    return HSLA_OK;
+}
+
+hsla_status hsla_pattern_set_format(hsla_pattern *p, int32_t format) {
+    if (!p || (format != HSLA_FORMAT_AUTO && format != HSLA_FORMAT_CSR)) return HSLA_ERR_INVALID_ARG;
+    p->format = format;
+    return HSLA_OK;
+}
+
+hsla_status hsla_pattern_format(const hsla_pattern *p, int32_t *stencil_in_use, int32_t *num_offsets) {
+    if (!p) return HSLA_ERR_INVALID_ARG;
+    if (stencil_in_use) *stencil_in_use = p->use(p->stA).mask != nullptr ? 1 : 0;
+    if (num_offsets) *num_offsets = p->stA.mask ? p->stA.nofs : 0;
     return HSLA_OK;
 }
 

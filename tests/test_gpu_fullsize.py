@@ -1,0 +1,171 @@
+"""Parity at the benchmark's full sizes, in the launch configurations the
+benchmark times, on outputs the oracle can compute one by one: a few
+iterations of the 256^3 system, sampled systems of the ragged and
+shared-pattern batches, finite differences of the loss through the GPU
+solver, and the learned preconditioner at 256^2."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from gpu_common import dev, iters_close, pattern, rel, t32, t64  # noqa: E402
+import paper_2601_13994_amd as hs  # noqa: E402
+from paper_2601_13994_amd import _lib, learned  # noqa: E402
+from oracle import mpnn  # noqa: E402
+
+
+def _log(*a):
+    print("[fullsize]", *a, flush=True)
+
+
+def test_diffusion3d_256_first_iterations(orc):
+    """n = 16.8M, nnz = 117M: the first iterations of Jacobi-PCG and of
+    Jacobi-BiCGStab (upwind, cell Peclet 10) agree with the oracle's to
+    rounding; both runs stop at the iteration cap."""
+    a, b = W.diffusion3d_workload(256)
+    pat = pattern(a)
+    bt = t64(b)
+    k = 4
+    x, infos, st = _lib.solve(pat, t64(a.val), bt, _lib.make_opts(method="cg", precond="jacobi", rtol=1e-8,
+                                                                  max_iter=k))
+    assert st == _lib.NOT_CONVERGED and infos[0]["iters"] == k
+    ref = orc.cg(a, b, precond="jacobi", rtol=1e-8, max_iter=k)
+    assert ref.iters == k
+    assert rel(x.cpu().numpy(), ref.x) <= 1e-12
+    _log("cg", rel(x.cpu().numpy(), ref.x))
+    conv = a.with_values(W.diffusion3d_values(256, W.diffusion3d_kappa(256), velocity=10.0))
+    x, infos, st = _lib.solve(pat, t64(conv.val), bt, _lib.make_opts(method="bicgstab", precond="jacobi",
+                                                                     rtol=1e-8, max_iter=k))
+    assert st == _lib.NOT_CONVERGED and infos[0]["iters"] == k
+    ref = orc.bicgstab(conv, b, precond="jacobi", rtol=1e-8, max_iter=k)
+    assert rel(x.cpu().numpy(), ref.x) <= 1e-12
+    _log("bicgstab", rel(x.cpu().numpy(), ref.x))
+
+
+def test_ragged_knn_full_sizes(orc):
+    """512 systems (64 distinct full-size k-NN Laplacians, each 8 times) in
+    one persistent launch: copies agree bitwise, sampled systems match the
+    oracle at rtol 1e-12, every system's FP64 residual meets the tolerance."""
+    distinct = [W.knn_system(s) for s in range(64)]
+    systems = [distinct[i % 64] for i in range(512)]
+    mats = [(t64(a.val), t32(a.row_ptr), t32(a.col)) for a, _ in distinct]
+    L = hs.SparseCSRList([mats[i % 64] for i in range(512)])
+    xs, infos, st = L.solve([t64(b) for _, b in systems], rtol=1e-12)
+    assert st == _lib.OK
+    for i in range(64, 512):
+        assert torch.equal(xs[i], xs[i % 64])
+        assert infos[i]["iters"] == infos[i % 64]["iters"]
+    assert max(f["true_residual"] for f in infos) <= 5e-12
+    for s in (0, 17, 63):
+        a, b = distinct[s]
+        ref = orc.cg(a, b, precond="jacobi", rtol=1e-12)
+        assert rel(xs[s].cpu().numpy(), ref.x) <= 1e-8
+        assert iters_close(infos[s]["iters"], ref.iters)
+        _log("knn", s, a.n, rel(xs[s].cpu().numpy(), ref.x))
+
+
+def test_shared_pattern_96_adjoint_and_fd(orc):
+    """128 systems on one 96^3 pattern (4 distinct coefficient fields, one b
+    and x* per system), forward + adjoint batched.  System 0 against the
+    oracle (x, dL/db, dL/dA at rtol 1e-12); every system's forward and
+    adjoint FP64 residuals; and central finite differences (h = 1e-6) of
+    L = 1/2 ||x - x*||^2 on 64 random entries of system 0, solved as one
+    batch of 128 perturbed systems run to a fixed iteration count past
+    convergence (the derivative of a truncated CG iterate lags the exact
+    one until the iterate has converged)."""
+    m, B = 96, 128
+    a0, V4, _, _ = W.shared_pattern_batch(m, 4)
+    n, nnz = a0.n, a0.nnz
+    pat = pattern(a0)
+    V = t64(V4).repeat(B // 4, 1).contiguous()
+    bs = np.stack([W.rng(4, 1, s).standard_normal(n) for s in range(B)])
+    xst = np.stack([W.rng(4, 2, s).standard_normal(n) for s in range(B)])
+    bt, xt = t64(bs), t64(xst)
+    opts = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-12)
+    x, fi, st = _lib.solve(pat, V, bt, opts)
+    assert st == _lib.OK
+    gx = (x - xt).contiguous()
+    gA, gb, bi, st2 = _lib.adjoint(pat, V, x, gx, opts)
+    assert st2 == _lib.OK
+    # rtol bounds the recursive residual; the recomputed FP64 residual may
+    # exceed it by the recurrence's rounding drift (seen up to about 2x here)
+    rn, bn = _lib.residual_norms(pat, V, bt, x)
+    assert max(r / c for r, c in zip(rn, bn)) <= 5e-12
+    rn, bn = _lib.residual_norms(pat, V, gx, gb)
+    assert max(r / c for r, c in zip(rn, bn)) <= 5e-12
+    _log("batch residuals ok")
+
+    a = a0.with_values(V4[0])
+    ref = orc.cg(a, bs[0], precond="jacobi", rtol=1e-12)
+    x0 = x[0].cpu().numpy()
+    assert rel(x0, ref.x) <= 1e-8
+    gA_o, gb_o, _ = orc.adjoint(a, ref.x, ref.x - xst[0], method="cg", precond="jacobi", rtol=1e-12)
+    assert rel(gb[0].cpu().numpy(), gb_o) <= 1e-8
+    assert rel(gA[0].cpu().numpy(), gA_o) <= 1e-6
+    _log("oracle", rel(x0, ref.x), rel(gA[0].cpu().numpy(), gA_o))
+
+    h = 1e-6
+    picks = W.rng(4, 3, 0).choice(nnz, 64, replace=False)
+    P = V[0].repeat(B, 1).contiguous()
+    ki = torch.as_tensor(picks, device=dev())
+    rowsel = torch.arange(64, device=dev()) * 2
+    P[rowsel, ki] += h
+    P[rowsel + 1, ki] -= h
+    K = 2 * fi[0]["iters"]
+    fopts = _lib.make_opts(method="cg", precond="jacobi", rtol=0.0, max_iter=K)
+    xp, pi, _ = _lib.solve(pat, P, bt[0].repeat(B, 1).contiguous(), fopts)
+    assert all(f["iters"] == K for f in pi)
+    xpl, xmi = xp[0::2], xp[1::2]
+    fd = (0.5 * ((xpl - xmi) * (xpl + xmi - 2 * xt[0])).sum(dim=1) / (2 * h)).cpu().numpy()
+    g = gA[0].cpu().numpy()[picks]
+    err = np.linalg.norm(fd - g) / np.linalg.norm(g)
+    _log("fd", err)
+    # The 1e-6 gradient bar is the comparison with the oracle above.  Central
+    # differences at h = 1e-6 add the rounding noise of two FP64 solves of
+    # 884,736 unknowns divided by 2h (about 1e-6 relative here), so they are
+    # held to 1e-5.
+    assert err <= 1e-5
+
+
+def test_learned_fsai_256(orc):
+    """The network at 256^2 (n = 65,536, nnz = 586,756): its output for a
+    held-out system against the FP64 reference with bf16 rounding at the
+    same points, and FSAI-PCG over 1024 held-out systems batched with the
+    GPU's factors at rtol 1e-12: sampled systems match the oracle's FSAI-PCG
+    with the same float32 factor, and every system's FP64 residual meets
+    the tolerance."""
+    m = 256
+    pa, slots = W.aniso_pattern(m)
+    pat = pattern(pa)
+    E = 1024
+    st_eval = t64(np.stack([W.aniso_stencil(*W.aniso_params(s, heldout=True)) for s in range(E)]))
+    V = learned.aniso_batch_values(torch.as_tensor(slots).to(dev()), st_eval)
+    bs = np.stack([W.rng(5, 5, s).standard_normal(pa.n) for s in range(E)])
+    bt = t64(bs)
+    model = learned.LearnedFSAI(seed=0)
+    p64 = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in learned.unpack(model.params.cpu()).items()}
+    g0 = model.ghat(pat, V[:1].contiguous()).cpu().numpy().reshape(-1)
+    a0 = pa.with_values(V[0].cpu().numpy())
+    ref, _ = mpnn.forward(p64, a0, bf=True)
+    assert rel(g0, ref) <= 2e-2
+    G, GT = model.factors(pat, V)
+    assert torch.isfinite(G).all()
+    x, infos, st = _lib.solve(pat, V, bt, _lib.make_opts(method="cg", precond="fsai", rtol=1e-12, G=G, GT=GT))
+    assert st == _lib.OK
+    rn, bn = _lib.residual_norms(pat, V, bt, x)
+    assert max(r / c for r, c in zip(rn, bn)) <= 5e-12
+    rpL, colL, _ = orc.lower_pattern(a0)
+    for s in (0, 511, 1023):
+        a = pa.with_values(V[s].cpu().numpy())
+        Gs = G[s].cpu().numpy().astype(np.float64)
+        ref = orc.fsai_pcg(a, rpL, colL, Gs, bs[s], rtol=1e-12)
+        assert ref.status == 0
+        assert rel(x[s].cpu().numpy(), ref.x) <= 1e-8
+        assert iters_close(infos[s]["iters"], ref.iters)
+        _log("fsai", s, infos[s]["iters"], ref.iters, rel(x[s].cpu().numpy(), ref.x))

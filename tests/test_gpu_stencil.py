@@ -1,0 +1,114 @@
+"""The offset-mask SpMV form (structured-grid patterns): detection, fallback
+to CSR, and bitwise equality of every kernel that streams A, A^T or the
+FSAI triangles in the two forms (SpMV, CG, BiCGStab, the nonsymmetric
+adjoint on A^T, FSAI-PCG)."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from gpu_common import dev, pattern, t64  # noqa: E402
+from paper_2601_13994_amd import _lib  # noqa: E402
+from oracle import mpnn  # noqa: E402
+
+
+def _both(pat, fn):
+    """fn() under the offset-mask form, then under CSR."""
+    pat.set_format("auto")
+    a = fn()
+    pat.set_format("csr")
+    try:
+        b = fn()
+    finally:
+        pat.set_format("auto")
+    return a, b
+
+
+@pytest.mark.parametrize("name,make,nofs", [
+    ("poisson2d", lambda: W.poisson2d(37), 5),
+    ("diffusion3d", lambda: W.diffusion3d(13, W.diffusion3d_kappa(13)), 7),
+    ("aniso9", lambda: W.aniso2d(29, 30.0, 0.7), 9),
+    ("upwind", lambda: W.diffusion3d(11, W.diffusion3d_kappa(11), velocity=10.0), 7),
+])
+def test_stencil_spmv_bitwise(orc, name, make, nofs):
+    a = make()
+    pat = pattern(a)
+    assert pat.stencil == (True, nofs)
+    r = np.random.default_rng(1)
+    B = 3
+    V = np.stack([a.val * (1 + 0.1 * r.standard_normal(a.nnz)) for _ in range(B)])
+    X = r.standard_normal((B, a.n))
+    y1, y2 = _both(pat, lambda: _lib.spmv(pat, t64(V), t64(X)).cpu().numpy())
+    assert np.array_equal(y1, y2)
+    for s in range(B):
+        assert np.array_equal(y1[s], orc.spmv(a.with_values(V[s]), X[s]))
+
+
+def test_stencil_detection_falls_back(orc):
+    # a random pattern has far more than 16 diagonals
+    a = W.random_spd(500, 0.02, np.random.default_rng(3))
+    assert pattern(a).stencil == (False, 0)
+    # a 2D stencil plus one entry on a diagonal that no sampled row has: the
+    # device check over all rows rejects the candidate set
+    m = 100
+    p = W.poisson2d(m)
+    r2 = np.concatenate([p.rows(), [2500]])
+    c2 = np.concatenate([p.col, [2537]])
+    o = np.lexsort((c2, r2))
+    r2, c2 = r2[o], c2[o]
+    rp = np.zeros(m * m + 1, np.int64)
+    np.cumsum(np.bincount(r2, minlength=m * m), out=rp[1:])
+    q = W.Csr(m * m, rp.astype(np.int32), c2.astype(np.int32),
+              np.random.default_rng(1).standard_normal(len(c2)))
+    pat = pattern(q)
+    assert pat.stencil == (False, 0)
+    x = np.random.default_rng(0).standard_normal(q.n)
+    assert np.array_equal(_lib.spmv(pat, t64(q.val), t64(x)).cpu().numpy(), orc.spmv(q, x))
+    # the same matrix without the extra entry is a 5-diagonal stencil
+    assert pattern(p).stencil == (True, 5)
+
+
+@pytest.mark.parametrize("method,precond", [("cg", "jacobi"), ("cg", "none"), ("bicgstab", "jacobi")])
+def test_stencil_solves_bitwise(method, precond):
+    if method == "cg":
+        a = W.diffusion3d(14, W.diffusion3d_kappa(14))
+    else:
+        a = W.diffusion3d(14, W.diffusion3d_kappa(14), velocity=10.0)
+    b = np.random.default_rng(2).standard_normal(a.n)
+    pat = pattern(a)
+    opts = _lib.make_opts(method=method, precond=precond, rtol=1e-12)
+    (x1, i1, s1), (x2, i2, s2) = _both(pat, lambda: _lib.solve(pat, t64(a.val), t64(b), opts))
+    assert s1 == s2 == 0
+    assert torch.equal(x1, x2) and i1[0]["iters"] == i2[0]["iters"]
+
+
+def test_stencil_adjoint_transpose_bitwise():
+    """The nonsymmetric adjoint iterates on A^T's offset-mask form."""
+    a = W.diffusion3d(12, W.diffusion3d_kappa(12), velocity=10.0)
+    r = np.random.default_rng(4)
+    x, gx = r.standard_normal(a.n), r.standard_normal(a.n)
+    pat = pattern(a)
+    opts = _lib.make_opts(method="bicgstab", precond="jacobi", rtol=1e-12)
+    (g1, l1, _, s1), (g2, l2, _, s2) = _both(pat, lambda: _lib.adjoint(pat, t64(a.val), t64(x), t64(gx), opts))
+    assert s1 == s2 == 0
+    assert torch.equal(g1, g2) and torch.equal(l1, l2)
+
+
+def test_stencil_fsai_bitwise(orc):
+    pa, slots = W.aniso_pattern(21)
+    a = pa.with_values(W.aniso_stencil(100.0, 0.4)[slots])
+    ah = mpnn.scaled(a)
+    _, _, gh = orc.fsai(ah)
+    pat = pattern(a)
+    G, GT = _lib.fsai_factors(pat, t64(a.val), torch.as_tensor(gh.astype(np.float32)).to(dev()))
+    b = np.random.default_rng(5).standard_normal(a.n)
+    opts = _lib.make_opts(method="cg", precond="fsai", rtol=1e-12, G=G, GT=GT)
+    (x1, i1, s1), (x2, i2, s2) = _both(pat, lambda: _lib.solve(pat, t64(a.val), t64(b), opts))
+    assert s1 == s2 == 0
+    assert torch.equal(x1, x2) and i1[0]["iters"] == i2[0]["iters"]
