@@ -59,18 +59,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def spmv_bytes(n: int, nnz: int) -> int:
-    """Algorithmic HBM bytes of one q = A p (+ p.q) launch: values and
-    column indices once (12 nnz), row pointers once (4(n+1)), p gathered
-    once with cache reuse (8n), q written once (8n)."""
-    return 12 * nnz + 4 * (n + 1) + 16 * n
+def spmv_bytes(n: int, nnz: int, stencil: bool) -> int:
+    """Algorithmic HBM bytes of one q = A p (+ p.q) launch: the values once
+    (8 nnz), the index structure once -- CSR: column indices and row
+    pointers (4 nnz + 4(n+1)); offset-mask form: one 16-bit mask per row
+    (2n) -- p gathered once with cache reuse (8n), q written once (8n).
+    The tile schedule (8 bytes per tile of <= 64 rows) is not counted."""
+    index = 2 * n if stencil else 4 * nnz + 4 * (n + 1)
+    return 8 * nnz + index + 16 * n
 
 
-def pcg_iteration_bytes(n: int, nnz: int) -> int:
+def pcg_iteration_bytes(n: int, nnz: int, stencil: bool) -> int:
     """Algorithmic bytes of one Jacobi-PCG iteration as scheduled here:
-    SpMV+dot (12nnz + 4(n+1) + 16n), update (reads x p r q D^-1, writes x r:
-    56n), direction (reads D^-1 r p, writes p: 32n)."""
-    return 12 * nnz + 4 * (n + 1) + 104 * n
+    SpMV+dot, update (reads x p r q D^-1, writes x r: 56n), direction
+    (reads D^-1 r p, writes p: 32n)."""
+    return spmv_bytes(n, nnz, stencil) + 88 * n
 
 
 def cpu_info() -> str:
@@ -203,10 +206,12 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
     spmv_ms = sum(r["spmv_ms"] for r in recs)
     launches = sum(r["spmv_launches"] for r in recs)
     avg_ms = spmv_ms / max(launches, 1)
-    bytes_launch = spmv_bytes(n, nnz)
+    stencil, nofs = pat.stencil
+    bytes_launch = spmv_bytes(n, nnz, stencil)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     ms_step = elapsed / args.steps * 1e3
-    it_bytes = pcg_iteration_bytes(n, nnz)
+    it_bytes = pcg_iteration_bytes(n, nnz, stencil)
+    csr_it_bytes = pcg_iteration_bytes(n, nnz, False)
     top = {
         "metric": METRIC,
         "value": args.steps / elapsed,
@@ -236,6 +241,7 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "algorithmic_bytes_per_launch": bytes_launch,
             "mean_launch_ms": avg_ms,
             "launches_timed": launches,
+            "format": f"offset-mask, {nofs} diagonals" if stencil else "csr",
         },
         "detail": {
             "iterations": iters,
@@ -247,6 +253,8 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "GFLOPs": (2 * nnz + 13 * n) * iters / (ms_step * 1e-3) / 1e9,
             "algorithmic_bytes_per_iteration": it_bytes,
             "spmv_share_of_step": spmv_ms / args.steps / ms_step,
+            "csr_bytes_per_iteration": csr_it_bytes,
+            "csr_equivalent_iteration_GBps": csr_it_bytes * iters / (ms_step * 1e-3) / 1e9,
         },
     }
     return top, iters
@@ -273,7 +281,7 @@ def run_bicgstab(ctx, args, dev, pat):
     _sync()
     dt = (time.perf_counter() - t0) / args.sub_steps
     it = infos[0]["iters"]
-    it_bytes = 2 * (12 * nnz + 4 * (n + 1)) + 176 * n
+    it_bytes = 2 * spmv_bytes(n, nnz, pat.stencil[0]) + 144 * n
     return {
         "workload": f"diffusion3d-{args.m}^3 + upwind convection (cell Peclet 10), Jacobi-BiCGStab to rtol 1e-8",
         "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iterations": it, "status": st,
@@ -322,7 +330,7 @@ def run_poisson(ctx, args, dev):
     tb = (time.perf_counter() - t0) / args.sub_steps
     it = infos[0]["iters"]
     itb = np.array([f["iters"] for f in ib])
-    it_bytes = 12 * a.nnz + 4 * (a.n + 1) + 88 * a.n
+    it_bytes = spmv_bytes(a.n, a.nnz, pat.stencil[0]) + 72 * a.n
     res = {
         "workload": "poisson2d-64^2 (n=4096, nnz=20224), plain CG to rtol 1e-10, x0=0",
         "latency_us_per_solve": lat * 1e6, "iterations": it, "status": st,
@@ -427,7 +435,8 @@ def run_adjoint(ctx, args, dev):
     dt = (time.perf_counter() - t0) / args.sub_steps
     itf = np.array([f["iters"] for f in fi])
     itb = np.array([f["iters"] for f in bi])
-    per_it = 8 * nnz + 104 * n + (4 * nnz + 4 * (n + 1)) / B
+    index = 2 * n if pat.stencil[0] else 4 * nnz + 4 * (n + 1)
+    per_it = 8 * nnz + 104 * n + index / B
     work = float(per_it * (itf.sum() + itb.sum()) + B * (12 * nnz + 28 * n))
     return {
         "workload": (f"{B} systems on one 3D 7-point pattern, {args.adj_m}^3 (n={n}, nnz={nnz}), log-normal kappa "

@@ -49,7 +49,7 @@ class Opts(ctypes.Structure):
         ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
         ("max_iter", ctypes.c_int64), ("check_every", ctypes.c_int32),
         ("use_x0", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32),
-        ("d_G", ctypes.c_void_p), ("d_GT", ctypes.c_void_p),
+        ("d_G", ctypes.c_void_p), ("d_GT", ctypes.c_void_p), ("persistent", ctypes.c_int32),
     ]
 
 
@@ -165,7 +165,7 @@ def need(t: torch.Tensor, dtype: torch.dtype, name: str, device: torch.device) -
 
 
 def make_opts(method="auto", precond="jacobi", rtol=1e-8, atol=0.0, max_iter=0, check_every=0,
-              x0=False, graph=True, profile=False, G=None, GT=None) -> Opts:
+              x0=False, graph=True, profile=False, G=None, GT=None, persistent=True) -> Opts:
     o = Opts()
     load().hsla_opts_default(ctypes.byref(o))
     o.method = METHODS[method]
@@ -179,6 +179,7 @@ def make_opts(method="auto", precond="jacobi", rtol=1e-8, atol=0.0, max_iter=0, 
     o.profile = int(bool(profile))
     o.d_G = G.data_ptr() if G is not None else None
     o.d_GT = GT.data_ptr() if GT is not None else None
+    o.persistent = int(bool(persistent))
     return o
 
 

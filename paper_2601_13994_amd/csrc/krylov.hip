@@ -823,7 +823,7 @@ hsla_status launch_spmv(hsla_handle *h, const hsla_pattern *p, int B, const doub
                         double *y, hipStream_t s) {
     if (p->n == 0 || B == 0) return HSLA_OK;
     const Pat A = pat_of(p);
-    const int G = grid_blocks(h, kWavesPerBlock, p->ntiles, 1, 16);
+    const int G = grid_blocks(h, kWavesPerBlock, p->ntiles, B, 16);
     k_spmv<<<dim3(G, B), kBlock, 0, s>>>(A, values, x, y);
     HSLA_HIP(h, hipGetLastError());
     return HSLA_OK;
@@ -975,9 +975,10 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
     if (method == HSLA_METHOD_BICGSTAB && pre == PRE_FSAI)
         return set_error(h, HSLA_ERR_INVALID_ARG, "FSAI preconditioning is for CG only");
     const int nvec = method == HSLA_METHOD_CG ? 6 : 10;
-    // SpMV-based kernels: up to 16 blocks per CU; vector kernels: up to 8
-    const int Gt = grid_blocks(h, kWavesPerBlock, A.ntiles, 1, 16);
-    const int Gv = grid_blocks(h, kBlock * 4, n, 1, 8);
+    // SpMV-based kernels: up to 16 blocks per CU; vector kernels: up to 8,
+    // shared by the systems of a batch (fewer, longer-running blocks each)
+    const int Gt = grid_blocks(h, kWavesPerBlock, A.ntiles, B, 16);
+    const int Gv = grid_blocks(h, kBlock * 4, n, B, 8);
     const int Gmax = Gt > Gv ? Gt : Gv;
     const Layout lay = make_layout(B, n, nvec, Gmax);
     hsla_status st = ensure_workspace(h, lay.total);
@@ -1186,6 +1187,8 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
         if (st != HSLA_OK) return st;
         method = sym ? HSLA_METHOD_CG : HSLA_METHOD_BICGSTAB;
     }
+    if (o.persistent && persistent_eligible(p, B, method, o))
+        return persistent_solve(h, p, B, values, b, x, o, infos, s);
     const Pat A = pat_of(p);
     FPat L{}, U{};
     if (o.precond == HSLA_PRECOND_FSAI) {
@@ -1230,7 +1233,10 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
     hsla_status res;
     if (sym) {
         const Pat A = pat_of(p);
-        res = solve_core(h, A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s);
+        if (o.persistent && persistent_eligible(p, B, method, o))
+            res = persistent_solve(h, p, B, values, gx, lam, o, infos, s);
+        else
+            res = solve_core(h, A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s);
     } else {
         if (hipMalloc((void **)&valT, sizeof(double) * (size_t)B * (p->nnz > 0 ? p->nnz : 1)) != hipSuccess) {
             if (lam_own) (void)hipFree(lam_own);
@@ -1319,7 +1325,7 @@ hsla_status hsla_residual_norms(hsla_handle *h, const hsla_pattern *p, int32_t B
     if (B == 0) return HSLA_OK;
     if (p->n > 0 && (!d_values || !d_b || !d_x)) return hsla::set_error(h, HSLA_ERR_INVALID_ARG, "null pointer");
     hipStream_t s = h->stream;
-    const int G = hsla::grid_blocks(h, hsla::kWavesPerBlock, p->ntiles, 1, 16);
+    const int G = hsla::grid_blocks(h, hsla::kWavesPerBlock, p->ntiles, B, 16);
     const hsla::Layout lay = hsla::make_layout(B, p->n, 0, G);
     st = hsla::ensure_workspace(h, lay.total);
     if (st != HSLA_OK) return st;

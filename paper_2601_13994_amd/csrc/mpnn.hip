@@ -916,8 +916,8 @@ static hsla_status probe_loss(hsla_handle *h, const hsla_pattern *p, int B, cons
     const int64_t n = p->n, nnz = p->nnz, nL = p->nnz_lower;
     const int64_t BP = (int64_t)B * P;
     if (BP > 65535) return set_error(h, HSLA_ERR_INVALID_ARG, "systems x probes must be <= 65535");
-    const int Gt = grid_blocks(h, kWavesPerBlock, p->ntiles, 1, 16);
-    const int Gp = grid_blocks(h, kBlock * 4, n, 1, 4);
+    const int Gt = grid_blocks(h, kWavesPerBlock, p->ntiles, (int)BP, 16);
+    const int Gp = grid_blocks(h, kBlock * 4, n, (int)BP, 4);
     size_t need = 0;
     auto add = [&](size_t bytes) { need += (bytes + 255) / 256 * 256 + 256; };
     add(8 * B * nnz); add(4 * B * nnz); add(8 * B * nnz); add(4 * B * nL);

@@ -574,6 +574,7 @@ void hsla_opts_default(hsla_opts *o) {
     o->check_every = 0;
     o->use_x0 = 0;
     o->use_graph = 1;
+    o->persistent = 1;
 }
 
 const char *hsla_status_string(int st) {

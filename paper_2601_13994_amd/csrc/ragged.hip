@@ -1,20 +1,23 @@
-// Ragged batches: B systems with distinct sparsity patterns and sizes
-// (the paper's list of matrices with distinct patterns, Sec. "Typed
-// sparse-tensor hierarchy"), solved with Jacobi-preconditioned CG in one
-// persistent launch.
+// Persistent one-workgroup-per-system Jacobi-PCG: ragged batches (B systems
+// with distinct sparsity patterns and sizes, the paper's list of matrices
+// with distinct patterns, Sec. "Typed sparse-tensor hierarchy") and small
+// systems that share one pattern, solved in a single launch.
 //
-// Layout (all device memory, caller-owned): system s owns rows
+// Ragged layout (all device memory, caller-owned): system s owns rows
 // [row_off[s], row_off[s+1]) of the concatenated vectors b and x and entries
 // [nnz_off[s], nnz_off[s+1]) of the concatenated col/values; its local
 // row pointer (n_s + 1 entries, starting at 0) starts at row_ptr[row_off[s]
-// + s]; column indices are local (0 <= col < n_s).
+// + s]; column indices are local (0 <= col < n_s).  Shared layout: one
+// pattern, values [B][nnz], vectors [B][n].
 //
-// Each workgroup pops systems from an atomic queue in longest-first order
-// (by stored entries) and runs the whole recurrence of one system with
+// Each workgroup pops systems from an atomic queue (ragged: longest first by
+// stored entries) and runs the whole recurrence of one system with
 // workgroup-level reductions; the queue gives every workgroup an exit once
-// B systems have been handed out, and max_iter bounds every solve.  A
-// system's reductions use a fixed thread count and order, so its result does
-// not depend on which workgroup solved it.
+// B systems have been handed out, and max_iter bounds every solve.  The
+// SpMV streams each 64-row block's entries in coalesced chunks staged in LDS
+// and adds each row's products in ascending column order, as the sequential
+// definition does.  A system's reductions use a fixed thread count and
+// order, so its result does not depend on which workgroup solved it.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -27,6 +30,7 @@ namespace rg {
 
 constexpr int kRB = 1024;  // threads per workgroup
 constexpr int kRW = kRB / kWave;
+constexpr int kChunk = 256;  // entries staged per wave and step
 
 struct RInfo {  // per-system result record (device)
     int64_t iters;
@@ -37,12 +41,13 @@ struct RInfo {  // per-system result record (device)
 
 struct Args {
     int32_t B;
+    int64_t shared_n, shared_nnz;  // >= 0: one shared pattern (row_off/nnz_off unused)
     const int64_t *row_off, *nnz_off;
     const int32_t *rp, *col;
     const double *val, *b;
     double *x;
     double *r, *p, *q, *dinv;  // work vectors, concatenated like b
-    const int32_t *order;      // systems in queue order
+    const int32_t *order;      // systems in queue order (nullptr: 0..B-1)
     int32_t *queue;            // next queue slot
     int32_t *bad;              // first invalid system (validation)
     RInfo *info;
@@ -69,6 +74,45 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV], double *sh) {
         v[j] = s;
     }
     __syncthreads();
+}
+
+// y = A v for one system, by the whole workgroup: wave w takes the 64-row
+// blocks w, w + kRW, ...; a block's entries are loaded in coalesced chunks of
+// kChunk, their products staged in the wave's LDS slice, and each lane adds
+// the products of its row in ascending order.  epi(i, y_i) runs on the lane
+// that owns row i.
+template <class Epi>
+__device__ __forceinline__ void wg_spmv(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                        const double *__restrict__ val, const double *__restrict__ v, double *lds,
+                                        Epi &&epi) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    double *L = lds + w * kChunk;
+    for (int32_t r0 = w * kWave; r0 < n; r0 += kRW * kWave) {
+        const int32_t row = r0 + lane;
+        const bool own = row < n;
+        const int32_t rend = r0 + kWave < n ? r0 + kWave : n;
+        const int32_t e0 = rp[r0], e1 = rp[rend];
+        const int32_t ka = own ? rp[row] : e1, kb = own ? rp[row + 1] : e1;
+        double acc = 0.0;
+        for (int32_t c0 = e0; c0 < e1; c0 += kChunk) {
+            const int32_t cnt = e1 - c0 < kChunk ? e1 - c0 : kChunk;
+#pragma unroll
+            for (int u = 0; u < kChunk / kWave; ++u) {
+                const int32_t e = u * kWave + lane;
+                if (e < cnt) L[e] = val[c0 + e] * v[col[c0 + e]];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int32_t lo = ka > c0 ? ka : c0;
+            const int32_t hi = kb < c0 + cnt ? kb : c0 + cnt;
+            for (int32_t k = lo; k < hi; ++k) acc += L[k - c0];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (own) epi(row, acc);
+    }
 }
 
 // Canonical-CSR check of every system's local pattern; reads a row only
@@ -108,6 +152,7 @@ __global__ __launch_bounds__(256) void k_ragged_validate(Args a) {
 
 __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
     __shared__ double sh[3 * kRW];
+    __shared__ double lds[kRW * kChunk];
     __shared__ int32_t slot;
     for (;;) {
         if (threadIdx.x == 0) slot = atomicAdd(a.queue, 1);
@@ -115,12 +160,13 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
         const int32_t qs = slot;
         __syncthreads();
         if (qs >= a.B) return;
-        const int32_t s = a.order[qs];
-        const int64_t r0 = a.row_off[s];
-        const int32_t n = (int32_t)(a.row_off[s + 1] - r0);
-        const int64_t k0 = a.nnz_off[s];
-        const int32_t *rp = a.rp + r0 + s;
-        const int32_t *col = a.col + k0;
+        const int32_t s = a.order ? a.order[qs] : qs;
+        const bool shared = a.shared_n >= 0;
+        const int64_t r0 = shared ? (int64_t)s * a.shared_n : a.row_off[s];
+        const int32_t n = (int32_t)(shared ? a.shared_n : a.row_off[s + 1] - r0);
+        const int64_t k0 = shared ? (int64_t)s * a.shared_nnz : a.nnz_off[s];
+        const int32_t *rp = shared ? a.rp : a.rp + r0 + s;
+        const int32_t *col = shared ? a.col : a.col + k0;
         const double *val = a.val + k0;
         const double *b = a.b + r0;
         double *x = a.x + r0, *r = a.r + r0, *p = a.p + r0, *q = a.q + r0, *dinv = a.dinv + r0;
@@ -161,12 +207,10 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
             while (it < a.max_iter) {
                 // q = A p, sigma = p.q (each row summed in ascending order)
                 double acc1[1] = {0.0};
-                for (int32_t i = threadIdx.x; i < n; i += kRB) {
-                    double sum = 0.0;
-                    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) sum += val[k] * p[col[k]];
+                wg_spmv(n, rp, col, val, p, lds, [&](int32_t i, double sum) {
                     q[i] = sum;
                     acc1[0] += p[i] * sum;
-                }
+                });
                 wg_sum<1>(acc1, sh);
                 const double sigma = acc1[0];
                 if (!isfinite(sigma)) { status = HSLA_ERR_NONFINITE; break; }
@@ -194,13 +238,12 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
         }
         // true residual ||b - A x||
         double accr[2] = {0.0, 0.0};
-        for (int32_t i = threadIdx.x; i < n; i += kRB) {
-            double sum = 0.0;
-            for (int32_t k = rp[i]; k < rp[i + 1]; ++k) sum += val[k] * x[col[k]];
+        __syncthreads();
+        wg_spmv(n, rp, col, val, x, lds, [&](int32_t i, double sum) {
             const double e = b[i] - sum;
             accr[0] += e * e;
             accr[1] += b[i] * b[i];
-        }
+        });
         wg_sum<2>(accr, sh);
         if (threadIdx.x == 0) {
             RInfo f;
@@ -215,7 +258,106 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
     }
 }
 
+// Carves the work vectors, launches the persistent kernel and returns the
+// per-system records.  `a` arrives with the system description set; `order`
+// (host, may be empty = identity) is the queue order.
+static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, int64_t rows, int64_t entries,
+                                  int64_t max_n, const std::vector<int32_t> &order, hsla_info *infos,
+                                  hipStream_t s) {
+    const int32_t B = a.B;
+    size_t bytes = 0;
+    auto add = [&](size_t v) { bytes += (v + 255) / 256 * 256; };
+    add(sizeof(double) * 4 * (rows > 0 ? rows : 1));
+    add(sizeof(int32_t) * B);
+    add(sizeof(RInfo) * B);
+    add(256);
+    hsla_status st = ensure_workspace(h, bytes);
+    if (st != HSLA_OK) return st;
+    char *ws = (char *)h->ws;
+    size_t off = 0;
+    auto take = [&](size_t v) {
+        char *p = ws + off;
+        off += (v + 255) / 256 * 256;
+        return p;
+    };
+    double *vec = (double *)take(sizeof(double) * 4 * (rows > 0 ? rows : 1));
+    a.r = vec;
+    a.p = vec + rows;
+    a.q = vec + 2 * rows;
+    a.dinv = vec + 3 * rows;
+    int32_t *dorder = (int32_t *)take(sizeof(int32_t) * B);
+    a.order = order.empty() ? nullptr : dorder;
+    a.info = (RInfo *)take(sizeof(RInfo) * B);
+    int32_t *flags = (int32_t *)take(256);
+    a.queue = flags;
+    a.bad = flags + 1;
+    a.rtol = o.rtol;
+    a.atol = o.atol;
+    a.max_iter = o.max_iter > 0 ? o.max_iter : std::min<int64_t>(10 * std::max<int64_t>(max_n, 1), 100000);
+    a.jacobi = o.precond == HSLA_PRECOND_JACOBI;
+    const int32_t init_flags[2] = {0, INT32_MAX};
+    HSLA_HIP(h, hipMemcpyAsync(flags, init_flags, sizeof init_flags, hipMemcpyHostToDevice, s));
+    if (!order.empty())
+        HSLA_HIP(h, hipMemcpyAsync(dorder, order.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
+    // every pointer the kernels dereference must be set (rows/entries > 0)
+    const bool shared = a.shared_n >= 0;
+    if (!a.rp || !a.queue || !a.bad || !a.info || (!shared && (!a.row_off || !a.nnz_off || !a.order)) ||
+        (rows > 0 && (!a.b || !a.x || !a.r || !a.p || !a.q || !a.dinv)) || (entries > 0 && (!a.col || !a.val)))
+        return set_error(h, HSLA_ERR_INTERNAL, "persistent solve: unset kernel argument");
+    if (!shared) {
+        k_ragged_validate<<<std::min(B, 4096), 256, 0, s>>>(a);
+        int32_t bad = INT32_MAX;
+        HSLA_HIP(h, hipMemcpyAsync(&bad, a.bad, sizeof bad, hipMemcpyDeviceToHost, s));
+        HSLA_HIP(h, hipStreamSynchronize(s));
+        if (bad != INT32_MAX) return set_error(h, HSLA_ERR_INVALID_CSR, "system %d is not canonical CSR", bad);
+    }
+    const int grid = (int)std::min<int64_t>(B, 2 * (int64_t)h->dev.num_cu);
+    k_ragged_pcg<<<grid, kRB, 0, s>>>(a);
+    HSLA_HIP(h, hipGetLastError());
+    std::vector<RInfo> hi(B);
+    HSLA_HIP(h, hipMemcpyAsync(hi.data(), a.info, sizeof(RInfo) * B, hipMemcpyDeviceToHost, s));
+    HSLA_HIP(h, hipStreamSynchronize(s));
+    int worst = HSLA_OK;
+    for (int i = 0; i < B; ++i) {
+        const int sst = hi[i].status;
+        if (sst < 0 || worst < 0)
+            worst = std::min(worst, sst);
+        else
+            worst = std::max(worst, sst);
+        if (infos) {
+            infos[i].iters = hi[i].iters;
+            infos[i].status = sst;
+            infos[i].method = HSLA_METHOD_CG;
+            infos[i].rel_residual = hi[i].rel_residual;
+            infos[i].true_residual = hi[i].true_residual;
+            infos[i].spmv_ms = 0.0;
+            infos[i].spmv_launches = 0;
+        }
+    }
+    return (hsla_status)worst;
+}
+
 }  // namespace rg
+
+bool persistent_eligible(const hsla_pattern *p, int B, int method, const hsla_opts &o) {
+    return method == HSLA_METHOD_CG && (o.precond == HSLA_PRECOND_JACOBI || o.precond == HSLA_PRECOND_NONE) &&
+           !o.use_x0 && !o.profile && B >= 1 && p->n >= 1 && p->nnz <= kPersistentMaxNnz;
+}
+
+hsla_status persistent_solve(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *b,
+                             double *x, const hsla_opts &o, hsla_info *infos, hipStream_t s) {
+    rg::Args a{};
+    a.B = B;
+    a.shared_n = p->n;
+    a.shared_nnz = p->nnz;
+    a.rp = p->row_ptr;
+    a.col = p->col;
+    a.val = values;
+    a.b = b;
+    a.x = x;
+    return rg::run_persistent(h, a, o, (int64_t)B * p->n, p->nnz, p->n, {}, infos, s);
+}
+
 }  // namespace hsla
 
 extern "C" hsla_status hsla_solve_ragged(hsla_handle *h, int32_t B, const int64_t *d_row_off,
@@ -258,23 +400,10 @@ extern "C" hsla_status hsla_solve_ragged(hsla_handle *h, int32_t B, const int64_
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return no[a + 1] - no[a] > no[b + 1] - no[b]; });
-    size_t bytes = 0;
-    auto add = [&](size_t v) { bytes += (v + 255) / 256 * 256; };
-    add(sizeof(double) * 4 * (rows > 0 ? rows : 1));
-    add(sizeof(int32_t) * B);
-    add(sizeof(RInfo) * B);
-    add(256);
-    st = ensure_workspace(h, bytes);
-    if (st != HSLA_OK) return st;
-    char *ws = (char *)h->ws;
-    size_t off = 0;
-    auto take = [&](size_t v) {
-        char *p = ws + off;
-        off += (v + 255) / 256 * 256;
-        return p;
-    };
     Args a{};
     a.B = B;
+    a.shared_n = -1;
+    a.shared_nnz = -1;
     a.row_off = d_row_off;
     a.nnz_off = d_nnz_off;
     a.rp = d_row_ptr;
@@ -282,55 +411,5 @@ extern "C" hsla_status hsla_solve_ragged(hsla_handle *h, int32_t B, const int64_
     a.val = d_values;
     a.b = d_b;
     a.x = d_x;
-    double *vec = (double *)take(sizeof(double) * 4 * (rows > 0 ? rows : 1));
-    a.r = vec;
-    a.p = vec + rows;
-    a.q = vec + 2 * rows;
-    a.dinv = vec + 3 * rows;
-    int32_t *dorder = (int32_t *)take(sizeof(int32_t) * B);
-    a.order = dorder;
-    a.info = (RInfo *)take(sizeof(RInfo) * B);
-    int32_t *flags = (int32_t *)take(256);
-    a.queue = flags;
-    a.bad = flags + 1;
-    a.rtol = o.rtol;
-    a.atol = o.atol;
-    a.max_iter = o.max_iter > 0 ? o.max_iter : std::min<int64_t>(10 * std::max<int64_t>(max_n, 1), 100000);
-    a.jacobi = o.precond == HSLA_PRECOND_JACOBI;
-    const int32_t init_flags[2] = {0, INT32_MAX};
-    HSLA_HIP(h, hipMemcpyAsync(flags, init_flags, sizeof init_flags, hipMemcpyHostToDevice, s));
-    HSLA_HIP(h, hipMemcpyAsync(dorder, order.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
-    // every pointer the kernels dereference must be set (rows/entries > 0)
-    if (!a.row_off || !a.nnz_off || !a.rp || !a.order || !a.queue || !a.bad || !a.info ||
-        (rows > 0 && (!a.b || !a.x || !a.r || !a.p || !a.q || !a.dinv)) || (no[B] > 0 && (!a.col || !a.val)))
-        return set_error(h, HSLA_ERR_INTERNAL, "ragged solve: unset kernel argument");
-    k_ragged_validate<<<std::min(B, 4096), 256, 0, s>>>(a);
-    int32_t bad = INT32_MAX;
-    HSLA_HIP(h, hipMemcpyAsync(&bad, a.bad, sizeof bad, hipMemcpyDeviceToHost, s));
-    HSLA_HIP(h, hipStreamSynchronize(s));
-    if (bad != INT32_MAX) return set_error(h, HSLA_ERR_INVALID_CSR, "system %d is not canonical CSR", bad);
-    const int grid = std::min<int64_t>(B, 2 * (int64_t)h->dev.num_cu);
-    k_ragged_pcg<<<grid, kRB, 0, s>>>(a);
-    HSLA_HIP(h, hipGetLastError());
-    std::vector<RInfo> hi(B);
-    HSLA_HIP(h, hipMemcpyAsync(hi.data(), a.info, sizeof(RInfo) * B, hipMemcpyDeviceToHost, s));
-    HSLA_HIP(h, hipStreamSynchronize(s));
-    int worst = HSLA_OK;
-    for (int i = 0; i < B; ++i) {
-        const int sst = hi[i].status;
-        if (sst < 0 || worst < 0)
-            worst = std::min(worst, sst);
-        else
-            worst = std::max(worst, sst);
-        if (infos) {
-            infos[i].iters = hi[i].iters;
-            infos[i].status = sst;
-            infos[i].method = HSLA_METHOD_CG;
-            infos[i].rel_residual = hi[i].rel_residual;
-            infos[i].true_residual = hi[i].true_residual;
-            infos[i].spmv_ms = 0.0;
-            infos[i].spmv_launches = 0;
-        }
-    }
-    return (hsla_status)worst;
+    return run_persistent(h, a, o, rows, no[B], max_n, order, infos, s);
 }

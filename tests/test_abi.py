@@ -56,12 +56,32 @@ def test_host_only_entry_points(lib):
     assert ctypes.sizeof(_lib.Info) == 48
 
 
-def test_struct_layout_matches_header():
-    """ctypes mirrors of hsla_opts / hsla_info have the C layout."""
+def test_struct_layout_matches_header(tmp_path):
+    """ctypes mirrors of hsla_opts / hsla_info have the layout a C compiler
+    gives the header's structs (every field's offset, and the sizes)."""
+    import subprocess
+
     from paper_2601_13994_amd import _lib
 
-    assert ctypes.sizeof(_lib.Opts) == 64
-    assert _lib.Opts.d_G.offset == 48
+    lines = []
+    for cname, mirror in (("hsla_opts", _lib.Opts), ("hsla_info", _lib.Info)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in mirror._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"hsla.h\"\nint main(void) {\n"
+                   + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in filter(None, out):
+        parts = line.split()
+        got[tuple(parts[:-1])] = int(parts[-1])
+    for cname, mirror in (("hsla_opts", _lib.Opts), ("hsla_info", _lib.Info)):
+        assert got[(cname, "size")] == ctypes.sizeof(mirror)
+        for f, _ in mirror._fields_:
+            assert got[(cname, f)] == getattr(mirror, f).offset, (cname, f)
 
 
 def test_product_path_has_no_cpu_fallback():

@@ -96,12 +96,13 @@ def test_spmv_batched(orc):
 
 # ---------------------------------------------------------------- CG / PCG
 
+@pytest.mark.parametrize("persistent", [True, False])
 @pytest.mark.parametrize("precond", ["none", "jacobi"])
-def test_cg_poisson2d_parity(orc, precond):
+def test_cg_poisson2d_parity(orc, precond, persistent):
     """2D 5-point Poisson 64 x 64 (n = 4096), the small adjoint-check problem
     of the paper: ||x_gpu - x_oracle|| / ||x_oracle|| <= 1e-8 at rtol 1e-12."""
     a, b = W.poisson2d_workload(64)
-    x, info, st = solve(a, b, method="cg", precond=precond, rtol=1e-12)
+    x, info, st = solve(a, b, method="cg", precond=precond, rtol=1e-12, persistent=persistent)
     ref = orc.cg(a, b, precond=precond, rtol=1e-12)
     assert st == 0 and info[0]["status"] == 0
     assert rel(x, ref.x) <= 1e-8
@@ -109,24 +110,26 @@ def test_cg_poisson2d_parity(orc, precond):
     assert info[0]["true_residual"] <= 2e-12
 
 
-def test_pcg_diffusion3d_parity(orc):
+@pytest.mark.parametrize("persistent", [True, False])
+def test_pcg_diffusion3d_parity(orc, persistent):
     """3D log-normal diffusion (the large workload's operator) at m = 24."""
     m = 24
     a = W.diffusion3d(m, W.diffusion3d_kappa(m))
     b = W.rng(2, 1).standard_normal(a.n)
-    x, info, st = solve(a, b, precond="jacobi", rtol=1e-12)
+    x, info, st = solve(a, b, precond="jacobi", rtol=1e-12, persistent=persistent)
     ref = orc.cg(a, b, precond="jacobi", rtol=1e-12)
     assert st == 0 and info[0]["method"] == "cg"
     assert rel(x, ref.x) <= 1e-8
     assert iters_close(info[0]["iters"], ref.iters)
 
 
+@pytest.mark.parametrize("persistent", [True, False])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_cg_random_spd_parity(orc, seed):
+def test_cg_random_spd_parity(orc, seed, persistent):
     r = np.random.default_rng(seed)
     a = W.random_spd(300, 0.02, r)
     b = r.standard_normal(a.n)
-    x, info, st = solve(a, b, precond="jacobi", rtol=1e-12)
+    x, info, st = solve(a, b, precond="jacobi", rtol=1e-12, persistent=persistent)
     ref = orc.cg(a, b, precond="jacobi", rtol=1e-12)
     assert st == 0 and rel(x, ref.x) <= 1e-8
 
@@ -183,23 +186,25 @@ def test_bicgstab_breakdown_reported():
 
 # ---------------------------------------------------------------- status codes
 
-def test_status_codes():
+@pytest.mark.parametrize("persistent", [True, False])
+def test_status_codes(persistent):
+    kw = dict(persistent=persistent)
     a, b = W.poisson2d_workload(16)
     pat = pattern(a)
-    x, info, st = solve(a, b, pat=pat, max_iter=1)
+    x, info, st = solve(a, b, pat=pat, max_iter=1, **kw)
     assert st == _lib.NOT_CONVERGED and info[0]["iters"] == 1
-    x, info, st = solve(a, np.zeros(a.n), pat=pat)
+    x, info, st = solve(a, np.zeros(a.n), pat=pat, **kw)
     assert st == 0 and info[0]["iters"] == 0 and not x.any()
     bad = b.copy()
     bad[3] = np.nan
     with pytest.raises(_lib.HslaError) as e:
-        solve(a, bad, pat=pat)
+        solve(a, bad, pat=pat, **kw)
     assert e.value.status == _lib.ERR_NONFINITE
-    x, info, st = solve(a, b, pat=pat, values=t64(-a.val), method="cg")
+    x, info, st = solve(a, b, pat=pat, values=t64(-a.val), method="cg", **kw)
     assert st == _lib.BREAKDOWN
     nodiag = W.Csr(2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0, 1.0]))
     with pytest.raises(_lib.HslaError) as e:
-        solve(nodiag, np.ones(2), precond="jacobi")
+        solve(nodiag, np.ones(2), precond="jacobi", **kw)
     assert e.value.status == _lib.ERR_ZERO_DIAGONAL
 
 
@@ -216,15 +221,22 @@ def test_deterministic_and_graph_equal():
     a = W.diffusion3d(m, W.diffusion3d_kappa(m))
     b = W.rng(2, 1).standard_normal(a.n)
     pat = pattern(a)
-    x1, i1, _ = solve(a, b, pat=pat, rtol=1e-10, graph=True)
-    x2, i2, _ = solve(a, b, pat=pat, rtol=1e-10, graph=True)
-    x3, i3, _ = solve(a, b, pat=pat, rtol=1e-10, graph=False)
-    x4, i4, _ = solve(a, b, pat=pat, rtol=1e-10, graph=False, check_every=5)
+    kw = dict(pat=pat, rtol=1e-10, persistent=False)
+    x1, i1, _ = solve(a, b, graph=True, **kw)
+    x2, i2, _ = solve(a, b, graph=True, **kw)
+    x3, i3, _ = solve(a, b, graph=False, **kw)
+    x4, i4, _ = solve(a, b, graph=False, check_every=5, **kw)
     assert np.array_equal(x1, x2) and np.array_equal(x1, x3) and np.array_equal(x1, x4)
     assert i1[0]["iters"] == i3[0]["iters"] == i4[0]["iters"]
+    # the persistent launch: run to run identical, same iterations to within rounding
+    x5, i5, _ = solve(a, b, pat=pat, rtol=1e-10)
+    x6, i6, _ = solve(a, b, pat=pat, rtol=1e-10)
+    assert np.array_equal(x5, x6) and i5[0]["iters"] == i6[0]["iters"]
+    assert iters_close(i5[0]["iters"], i1[0]["iters"]) and rel(x5, x1) <= 1e-9
 
 
-def test_batched_masks_and_independence(orc):
+@pytest.mark.parametrize("persistent", [True, False])
+def test_batched_masks_and_independence(orc, persistent):
     """Systems with very different iteration counts, a zero right-hand side
     and an easy one, iterated in lock step: each equals its own solve bit for
     bit and matches the oracle."""
@@ -240,7 +252,7 @@ def test_batched_masks_and_independence(orc):
         bs.append(np.zeros(base.n) if s == 2 else r.standard_normal(base.n))
     V, Bm = np.stack(vals), np.stack(bs)
     pat = pattern(base)
-    opts = _lib.make_opts(precond="jacobi", rtol=1e-11)
+    opts = _lib.make_opts(precond="jacobi", rtol=1e-11, persistent=persistent)
     X, infos, st = _lib.solve(pat, t64(V), t64(Bm), opts)
     X = X.cpu().numpy()
     assert st == 0
@@ -267,8 +279,9 @@ def test_outer_on_pattern_bitwise(orc):
     assert np.array_equal(g, orc.adjoint_grad(a, lam, x))
 
 
+@pytest.mark.parametrize("persistent", [True, False])
 @pytest.mark.parametrize("kind", ["spd", "nonsym"])
-def test_adjoint_parity(orc, kind):
+def test_adjoint_parity(orc, kind, persistent):
     m = 10
     if kind == "spd":
         a = W.diffusion3d(m, W.diffusion3d_kappa(m, cfg=4))
@@ -279,7 +292,7 @@ def test_adjoint_parity(orc, kind):
     x = orc.solve(a, b, precond="jacobi", rtol=1e-13).x
     gx = x - xs
     pat = pattern(a)
-    opts = _lib.make_opts(precond="jacobi", rtol=1e-13)
+    opts = _lib.make_opts(precond="jacobi", rtol=1e-13, persistent=persistent)
     gA, gb, infos, st = _lib.adjoint(pat, t64(a.val), t64(x), t64(gx), opts)
     gA_o, gb_o, _ = orc.adjoint(a, x, gx, precond="jacobi", rtol=1e-13)
     assert st == 0
