@@ -59,21 +59,22 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def spmv_bytes(n: int, nnz: int, stencil: bool) -> int:
-    """Algorithmic HBM bytes of one q = A p (+ p.q) launch: the values once
-    (8 nnz), the index structure once -- CSR: column indices and row
-    pointers (4 nnz + 4(n+1)); offset-mask form: one 16-bit mask per row
-    (2n) -- p gathered once with cache reuse (8n), q written once (8n).
-    The tile schedule (8 bytes per tile of <= 64 rows) is not counted."""
-    index = 2 * n if stencil else 4 * nnz + 4 * (n + 1)
-    return 8 * nnz + index + 16 * n
+def spmv_bytes(n: int, nnz: int, nofs: int) -> int:
+    """Algorithmic HBM bytes of one q = A p (+ p.q) launch: p gathered once
+    with cache reuse (8n), q written once (8n), and the matrix once -- CSR
+    (nofs = 0): values, column indices and row pointers (12 nnz + 4(n+1));
+    offset-mask patterns (nofs diagonals): the per-solve diagonal-major copy
+    of the values (8 nofs n, zeros where a row has no entry) and one 16-bit
+    row mask (2n)."""
+    matrix = 8 * nofs * n + 2 * n if nofs else 12 * nnz + 4 * (n + 1)
+    return matrix + 16 * n
 
 
-def pcg_iteration_bytes(n: int, nnz: int, stencil: bool) -> int:
+def pcg_iteration_bytes(n: int, nnz: int, nofs: int) -> int:
     """Algorithmic bytes of one Jacobi-PCG iteration as scheduled here:
     SpMV+dot, update (reads x p r q D^-1, writes x r: 56n), direction
     (reads D^-1 r p, writes p: 32n)."""
-    return spmv_bytes(n, nnz, stencil) + 88 * n
+    return spmv_bytes(n, nnz, nofs) + 88 * n
 
 
 def cpu_info() -> str:
@@ -207,11 +208,12 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
     launches = sum(r["spmv_launches"] for r in recs)
     avg_ms = spmv_ms / max(launches, 1)
     stencil, nofs = pat.stencil
-    bytes_launch = spmv_bytes(n, nnz, stencil)
+    nofs = nofs if stencil else 0
+    bytes_launch = spmv_bytes(n, nnz, nofs)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     ms_step = elapsed / args.steps * 1e3
-    it_bytes = pcg_iteration_bytes(n, nnz, stencil)
-    csr_it_bytes = pcg_iteration_bytes(n, nnz, False)
+    it_bytes = pcg_iteration_bytes(n, nnz, nofs)
+    csr_it_bytes = pcg_iteration_bytes(n, nnz, 0)
     top = {
         "metric": METRIC,
         "value": args.steps / elapsed,
@@ -241,7 +243,7 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "algorithmic_bytes_per_launch": bytes_launch,
             "mean_launch_ms": avg_ms,
             "launches_timed": launches,
-            "format": f"offset-mask, {nofs} diagonals" if stencil else "csr",
+            "format": f"diagonal-major values + row masks, {nofs} diagonals" if nofs else "csr",
         },
         "detail": {
             "iterations": iters,
@@ -281,7 +283,7 @@ def run_bicgstab(ctx, args, dev, pat):
     _sync()
     dt = (time.perf_counter() - t0) / args.sub_steps
     it = infos[0]["iters"]
-    it_bytes = 2 * spmv_bytes(n, nnz, pat.stencil[0]) + 144 * n
+    it_bytes = 2 * spmv_bytes(n, nnz, pat.stencil[1] if pat.stencil[0] else 0) + 144 * n
     return {
         "workload": f"diffusion3d-{args.m}^3 + upwind convection (cell Peclet 10), Jacobi-BiCGStab to rtol 1e-8",
         "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iterations": it, "status": st,
@@ -330,7 +332,7 @@ def run_poisson(ctx, args, dev):
     tb = (time.perf_counter() - t0) / args.sub_steps
     it = infos[0]["iters"]
     itb = np.array([f["iters"] for f in ib])
-    it_bytes = spmv_bytes(a.n, a.nnz, pat.stencil[0]) + 72 * a.n
+    it_bytes = spmv_bytes(a.n, a.nnz, 0) + 72 * a.n  # the persistent kernel reads CSR
     res = {
         "workload": "poisson2d-64^2 (n=4096, nnz=20224), plain CG to rtol 1e-10, x0=0",
         "latency_us_per_solve": lat * 1e6, "iterations": it, "status": st,
@@ -435,8 +437,8 @@ def run_adjoint(ctx, args, dev):
     dt = (time.perf_counter() - t0) / args.sub_steps
     itf = np.array([f["iters"] for f in fi])
     itb = np.array([f["iters"] for f in bi])
-    index = 2 * n if pat.stencil[0] else 4 * nnz + 4 * (n + 1)
-    per_it = 8 * nnz + 104 * n + index / B
+    nofs = pat.stencil[1] if pat.stencil[0] else 0
+    per_it = (8 * nofs * n + 104 * n + 2 * n / B) if nofs else (8 * nnz + 104 * n + (4 * nnz + 4 * (n + 1)) / B)
     work = float(per_it * (itf.sum() + itb.sum()) + B * (12 * nnz + 28 * n))
     return {
         "workload": (f"{B} systems on one 3D 7-point pattern, {args.adj_m}^3 (n={n}, nnz={nnz}), log-normal kappa "

@@ -116,9 +116,18 @@ hsla_status hsla_pattern_info(const hsla_pattern *p, int32_t *n, int64_t *nnz, i
  * on one of at most 16 fixed diagonals (col - row in a fixed set, as for
  * structured-grid stencils): one 16-bit mask per row replaces the 4-byte
  * column index of every entry, cutting the bytes each SpMV streams.
- * AUTO (the default) uses that form where it exists, CSR always uses the
- * column indices.  Both give bitwise identical results. */
-typedef enum hsla_format { HSLA_FORMAT_AUTO = 0, HSLA_FORMAT_CSR = 1 } hsla_format;
+ *   AUTO (default): hsla_spmv walks row tiles with the masks; the solvers
+ *     copy the values once per solve into a diagonal-major layout (entry of
+ *     row i on diagonal s at [s][i], zeros where a row has none) and run
+ *     every SpMV of the iteration as a row-per-thread stream over it.
+ *   CSR: column indices and row tiles everywhere.
+ *   DIAGONAL: as AUTO, and hsla_spmv also goes through the diagonal-major
+ *     copy (one extra pass over the values per call).
+ * Every form adds each row's products in ascending column order, so SpMV
+ * results are bitwise identical in all of them; a solve's dot products are
+ * reduced in an order that depends on the form's grid, so solves agree to
+ * rounding. */
+typedef enum hsla_format { HSLA_FORMAT_AUTO = 0, HSLA_FORMAT_CSR = 1, HSLA_FORMAT_DIAGONAL = 2 } hsla_format;
 /* Selects the form later calls on `p` use; must not run concurrently with
  * calls that use `p`.  HSLA_ERR_INVALID_ARG for an unknown format. */
 hsla_status hsla_pattern_set_format(hsla_pattern *p, int32_t format);

@@ -23,7 +23,7 @@ ERR_NO_MEMORY, ERR_ZERO_DIAGONAL, ERR_INTERNAL = -5, -6, -7
 METHODS = {"auto": 0, "cg": 1, "bicgstab": 2}
 METHOD_NAMES = {v: k for k, v in METHODS.items()}
 PRECONDS = {"none": 0, "jacobi": 1, "fsai": 2}
-FORMATS = {"auto": 0, "csr": 1}
+FORMATS = {"auto": 0, "csr": 1, "diagonal": 2}
 
 # every symbol include/hsla.h declares
 EXPORTS = [
@@ -218,7 +218,8 @@ class Pattern:
         return bool(use.value), nofs.value
 
     def set_format(self, fmt: str) -> None:
-        """'auto' (offset-mask form where available) or 'csr'."""
+        """'auto' (offset-mask form where available), 'csr', or 'diagonal'
+        (as 'auto', and SpMV calls also use the diagonal-major copy)."""
         st = load().hsla_pattern_set_format(self.p, FORMATS[fmt])
         if st != OK:
             raise HslaError(st, f"unknown format {fmt!r}")

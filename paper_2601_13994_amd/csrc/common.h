@@ -494,4 +494,90 @@ __device__ __forceinline__ void spmv_tiles(const int32_t *__restrict__ rp, const
         spmv_tiles_csr(rp, col, val, x, meta, ntiles, lds, epi);
 }
 
+// Diagonal-major values of an offset-mask pattern are stored in chunks of
+// kDiaChunk rows: the entries of chunk c on diagonal s are contiguous at
+// [(c * nofs + s) * kDiaChunk, + kDiaChunk), so one chunk's values for all
+// diagonals form a single contiguous run (zeros where a row has no entry
+// and past the last row).
+constexpr int kDiaChunk = 2 * kBlock;
+
+__host__ __device__ inline int64_t dia_chunks(int64_t n) { return (n + kDiaChunk - 1) / kDiaChunk; }
+__host__ __device__ inline int64_t dia_index(int64_t i, int s, int nofs) {
+    return ((i / kDiaChunk) * nofs + s) * kDiaChunk + (i % kDiaChunk);
+}
+
+// XCD-aware walk over row chunks: XCD k (blocks b with b % 8 == k) owns
+// chunks [C k / 8, C (k+1) / 8) and its blocks sweep that range, so the
+// rows being processed on one XCD at a time stay within a window whose
+// stencil neighbours are in that XCD's L2.
+struct ChunkWalk {
+    int64_t first, stride, hi;
+    __device__ __forceinline__ explicit ChunkWalk(int64_t nchunks) {
+        const int G = gridDim.x;
+        if (G % kXcds == 0) {
+            const int xcd = blockIdx.x % kXcds;
+            const int per = G / kXcds;
+            first = nchunks * xcd / kXcds + blockIdx.x / kXcds;
+            hi = nchunks * (xcd + 1) / kXcds;
+            stride = per;
+        } else {
+            first = blockIdx.x;
+            hi = nchunks;
+            stride = G;
+        }
+    }
+};
+
+// SpMV on the chunked diagonal-major copy of the values (see kDiaChunk).
+// A block takes one chunk of 512 rows per step, each thread two rows 256
+// apart; each row adds its present products in ascending diagonal order,
+// which is ascending column order, with products rounded before the add (no
+// contraction), so the result equals the CSR and tile forms bit for bit.
+// NS (a multiple of 4, >= nofs) is the unrolled slot count: slots past nofs
+// reload the last diagonal and are masked out.  epi(row, y) per row.
+template <int NS, typename VT, class Epi>
+__device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
+                                         const double *__restrict__ x, Epi &&epi) {
+#pragma clang fp contract(off)
+    const ChunkWalk cw(dia_chunks(n));
+    const uint16_t *__restrict__ mask = sn.mask;
+    const int nofs = sn.nofs;
+    for (int64_t c = cw.first; c < cw.hi; c += cw.stride) {
+        const int64_t i = c * kDiaChunk + threadIdx.x;
+        const int64_t i2 = i + kBlock;
+        const bool one = i < n, two = i2 < n;
+        const int64_t j1 = one ? i : 0, j2 = two ? i2 : 0;
+        const uint32_t m1 = one ? (uint32_t)mask[i] : 0u;
+        const uint32_t m2 = two ? (uint32_t)mask[i2] : 0u;
+        const VT *__restrict__ base = dv + c * nofs * kDiaChunk + threadIdx.x;
+        double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int g = 0; g < NS; g += 4) {
+            if (g < nofs) {
+                VT v1[4], v2[4];
+                double x1[4], x2[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int s = g + u < nofs ? g + u : nofs - 1;
+                    const int64_t d = sn.ofs[s];
+                    const bool o1 = (m1 >> (g + u)) & 1u, o2 = (m2 >> (g + u)) & 1u;
+                    v1[u] = __builtin_nontemporal_load(&base[s * kDiaChunk]);
+                    v2[u] = __builtin_nontemporal_load(&base[s * kDiaChunk + kBlock]);
+                    x1[u] = x[o1 ? i + d : j1];
+                    x2[u] = x[o2 ? i2 + d : j2];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double p1 = (double)v1[u] * x1[u];
+                    const double p2 = (double)v2[u] * x2[u];
+                    if ((m1 >> (g + u)) & 1u) a1 = a1 + p1;
+                    if ((m2 >> (g + u)) & 1u) a2 = a2 + p2;
+                }
+            }
+        }
+        if (one) epi(i, a1);
+        if (two) epi(i2, a2);
+    }
+}
+
 }  // namespace hsla

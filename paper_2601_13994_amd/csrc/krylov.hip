@@ -9,6 +9,7 @@
 // (alpha, beta, omega, stop test) in device memory.  Kernels of a stopped
 // system return at entry, so chunks of K iterations are enqueued (and
 // replayed as a HIP graph) with one host check per chunk.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -35,6 +36,7 @@ struct FPat {  // pattern + values of one FSAI factor (float32 values)
     int64_t nnz;
     const float *val;
     Stencil sn;
+    const float *dia;  // diagonal-major copy of val ([B][nofs][n]) when sn is used
 };
 
 static Pat pat_of(const hsla_pattern *p) {
@@ -47,6 +49,7 @@ static Pat pat_T_of(const hsla_pattern *p) {
 
 struct Sys {
     const double *val;  // [B][nnz]
+    const double *dia;  // [B][nofs][n] diagonal-major copy of val (offset-mask patterns)
     const double *b;    // [B][n]
     double *x;          // [B][n]
     // work vectors, [B][n] each
@@ -61,6 +64,49 @@ struct Sys {
     const int64_t vo = (int64_t)sidx * (A).n;                           \
     SysState &st = (S).st[sidx];                                        \
     double *part = (S).part + (int64_t)sidx * 3 * gridDim.x;
+
+// y = A v for system sidx through the form the solve uses: the
+// diagonal-major copy of the values (NS > 0, offset-mask patterns) or the
+// tile walk over CSR / row masks.
+template <int NS, class Epi>
+__device__ __forceinline__ void spmv_A(const Pat &A, const Sys &S, int sidx, const double *v, double *lds,
+                                       Epi &&epi) {
+    if constexpr (NS > 0)
+        spmv_dia<NS>(A.sn, S.dia + (int64_t)sidx * A.sn.nofs * dia_chunks(A.n) * kDiaChunk, (int64_t)A.n, v, epi);
+    else
+        spmv_tiles(A.rp, A.col, A.sn, S.val + (int64_t)sidx * A.nnz, v, A.meta, A.ntiles, lds, epi);
+}
+
+// y = F v for an FSAI factor (float32 values), same two forms.
+template <int NS, class Epi>
+__device__ __forceinline__ void spmv_F(const FPat &F, int64_t n, int sidx, const double *v, double *lds,
+                                       Epi &&epi) {
+    if constexpr (NS > 0)
+        spmv_dia<NS>(F.sn, F.dia + (int64_t)sidx * F.sn.nofs * dia_chunks(n) * kDiaChunk, n, v, epi);
+    else
+        spmv_tiles(F.rp, F.col, F.sn, F.val + (int64_t)sidx * F.nnz, v, F.meta, F.ntiles, lds, epi);
+}
+
+// Chunked diagonal-major copy of the values of an offset-mask pattern (see
+// kDiaChunk): the entry of row i on diagonal s at dia_index(i, s), 0 where
+// the row has none and for the padding rows of the last chunk.
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_to_dia(int32_t n, const int32_t *__restrict__ rp, Stencil sn,
+                                                   int64_t nnz, const VT *__restrict__ vals, VT *__restrict__ dia) {
+    const int sidx = blockIdx.y;
+    const int64_t rows = dia_chunks(n) * kDiaChunk;
+    const VT *v = vals + (int64_t)sidx * nnz;
+    VT *d = dia + (int64_t)sidx * sn.nofs * rows;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < rows; i += (int64_t)gridDim.x * kBlock) {
+        const uint32_t m = i < n ? (uint32_t)sn.mask[i] : 0u;
+        int32_t k = i < n ? rp[i] : 0;
+        for (int s = 0; s < sn.nofs; ++s) {
+            VT val = VT(0);
+            if ((m >> s) & 1u) val = v[k++];
+            d[dia_index(i, s, sn.nofs)] = val;
+        }
+    }
+}
 
 // Finalize kernels run one block per system (grid = B).
 #define FIN_OFFSETS(S, G)                                               \
@@ -114,6 +160,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Pat A, const double *__restrict
                [&](int32_t row, double yv) {
                    y[row] = yv;
                });
+}
+
+// y = A x on a diagonal-major copy of the values (offset-mask patterns).
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_spmv_dia(Pat A, const double *__restrict__ dia,
+                                                     const double *__restrict__ x, double *__restrict__ y) {
+    const int64_t sidx = blockIdx.y;
+    x += sidx * A.n;
+    y += sidx * A.n;
+    spmv_dia<NS>(A.sn, dia + sidx * A.sn.nofs * dia_chunks(A.n) * kDiaChunk, (int64_t)A.n, x,
+                 [&](int64_t row, double yv) { y[row] = yv; });
 }
 
 // ---------------------------------------------------------------------------
@@ -186,16 +243,16 @@ __global__ __launch_bounds__(kBlock) void k_fin_cg_init(Sys S, int G, double rto
 }
 
 // q = A p and partials of sigma = p.q.
+template <int NS>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(Pat A, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
     if (stopped(st)) return;
-    const double *val = S.val + sidx * A.nnz;
     const double *p = S.p + vo;
     double *q = S.q + vo;
     double acc[1] = {0.0};
-    spmv_tiles(A.rp, A.col, A.sn, val, p, A.meta, A.ntiles, lds[threadIdx.x / kWave],
-               [&](int32_t row, double yv) {
+    spmv_A<NS>(A, S, sidx, p, lds[threadIdx.x / kWave],
+               [&](int64_t row, double yv) {
                    q[row] = yv;
                    acc[0] += p[row] * yv;
                });
@@ -315,32 +372,32 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
 }
 
 // FSAI apply, first half: w = G r (G lower, float32 values, FP64 products).
+template <int NS>
 __global__ __launch_bounds__(kBlock) void k_fsai_lower(Pat A, FPat L, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
     (void)part;
     if (stopped(st)) return;
-    const float *g = L.val + sidx * L.nnz;
     const double *r = S.r + vo;
     double *w = S.w + vo;
-    spmv_tiles(L.rp, L.col, L.sn, g, r, L.meta, L.ntiles, lds[threadIdx.x / kWave],
-               [&](int32_t row, double yv) {
+    spmv_F<NS>(L, A.n, sidx, r, lds[threadIdx.x / kWave],
+               [&](int64_t row, double yv) {
                    w[row] = yv;
                });
 }
 
 // FSAI apply, second half: z = G^T w and partials of r.z.
+template <int NS>
 __global__ __launch_bounds__(kBlock) void k_fsai_upper_dot(Pat A, FPat U, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
     if (stopped(st)) return;
-    const float *g = U.val + sidx * U.nnz;
     const double *w = S.w + vo;
     const double *r = S.r + vo;
     double *z = S.z + vo;
     double acc[1] = {0.0};
-    spmv_tiles(U.rp, U.col, U.sn, g, w, U.meta, U.ntiles, lds[threadIdx.x / kWave],
-               [&](int32_t row, double yv) {
+    spmv_F<NS>(U, A.n, sidx, w, lds[threadIdx.x / kWave],
+               [&](int64_t row, double yv) {
                    z[row] = yv;
                    acc[0] += r[row] * yv;
                });
@@ -504,17 +561,17 @@ __global__ __launch_bounds__(kBlock) void k_bicg_dir(Pat A, Sys S) {
 }
 
 // v = A p_hat and partials of r_hat.v.
+template <int NS>
 __global__ __launch_bounds__(kBlock) void k_bicg_spmv_v(Pat A, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
     if (stopped(st)) return;
-    const double *val = S.val + sidx * A.nnz;
     const double *ph = S.ph + vo;
     const double *rh = S.rh + vo;
     double *v = S.v + vo;
     double acc[1] = {0.0};
-    spmv_tiles(A.rp, A.col, A.sn, val, ph, A.meta, A.ntiles, lds[threadIdx.x / kWave],
-               [&](int32_t row, double yv) {
+    spmv_A<NS>(A, S, sidx, ph, lds[threadIdx.x / kWave],
+               [&](int64_t row, double yv) {
                    v[row] = yv;
                    acc[0] += rh[row] * yv;
                });
@@ -597,17 +654,17 @@ __global__ __launch_bounds__(kBlock) void k_fin_bicg_s(Sys S, int G) {
 }
 
 // t = A s_hat and partials of t.s, t.t.
+template <int NS>
 __global__ __launch_bounds__(kBlock) void k_bicg_spmv_t(Pat A, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
     if (stopped(st) || st.restart_pending || st.s_exit) return;
-    const double *val = S.val + sidx * A.nnz;
     const double *sh = S.sh + vo;
     const double *s = S.s + vo;
     double *t = S.t + vo;
     double acc[2] = {0.0, 0.0};
-    spmv_tiles(A.rp, A.col, A.sn, val, sh, A.meta, A.ntiles, lds[threadIdx.x / kWave],
-               [&](int32_t row, double yv) {
+    spmv_A<NS>(A, S, sidx, sh, lds[threadIdx.x / kWave],
+               [&](int64_t row, double yv) {
                    t[row] = yv;
                    acc[0] += yv * s[row];
                    acc[1] += yv * yv;
@@ -799,12 +856,12 @@ __global__ __launch_bounds__(kBlock) void k_outer(int32_t n, int64_t nnz, const 
 // ---------------------------------------------------------------------------
 
 struct Layout {
-    size_t off_state, off_part, off_vec, off_res, total;
+    size_t off_state, off_part, off_vec, off_res, off_extra, total;
 };
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-static Layout make_layout(int B, int64_t n, int nvec, int G) {
+static Layout make_layout(int B, int64_t n, int nvec, int G, size_t extra = 0) {
     Layout L{};
     size_t o = 0;
     L.off_state = o;
@@ -815,14 +872,40 @@ static Layout make_layout(int B, int64_t n, int nvec, int G) {
     o = align_up(o + sizeof(double) * 2 * (size_t)B, 256);
     L.off_vec = o;
     o = align_up(o + sizeof(double) * (size_t)nvec * B * (size_t)n, 256);
+    L.off_extra = o;
+    o = align_up(o + extra, 256);
     L.total = o;
     return L;
 }
+
+// Launches K<NS> for the diagonal-major slot count `ns` (0 = tile walk).
+#define NS_LAUNCH(K, ns, grid, ...)                                       \
+    switch (ns) {                                                         \
+        case 0: K<0><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;         \
+        case 4: K<4><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;         \
+        case 8: K<8><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;         \
+        case 12: K<12><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;       \
+        default: K<16><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;       \
+    }
 
 hsla_status launch_spmv(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *x,
                         double *y, hipStream_t s) {
     if (p->n == 0 || B == 0) return HSLA_OK;
     const Pat A = pat_of(p);
+    if (p->format == HSLA_FORMAT_DIAGONAL && A.sn.mask) {
+        const int ns = (A.sn.nofs + 3) / 4 * 4;
+        const size_t rows = (size_t)dia_chunks(A.n) * kDiaChunk;
+        const hsla_status st = ensure_workspace(h, sizeof(double) * (size_t)B * A.sn.nofs * rows);
+        if (st != HSLA_OK) return st;
+        double *dia = (double *)h->ws;
+        const int Gv = grid_blocks(h, kBlock * 4, A.n, B, 8);
+        const int Gd = grid_blocks(h, kDiaChunk, A.n, B, 8);
+        k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>(A.n, A.rp, A.sn, A.nnz, values, dia);
+        const dim3 gd(Gd, B);
+        NS_LAUNCH(k_spmv_dia, ns, gd, A, dia, x, y);
+        HSLA_HIP(h, hipGetLastError());
+        return HSLA_OK;
+    }
     const int G = grid_blocks(h, kWavesPerBlock, p->ntiles, B, 16);
     k_spmv<<<dim3(G, B), kBlock, 0, s>>>(A, values, x, y);
     HSLA_HIP(h, hipGetLastError());
@@ -837,20 +920,24 @@ struct SolveCall {
     int method;   // HSLA_METHOD_CG / BICGSTAB
     int precond;  // PRE_*
     int Gt, Gv;   // blocks per system: SpMV-based kernels, vector kernels
+    int nsA, nsF; // slot counts of the diagonal-major SpMV of A and of the FSAI factors (0: tiles)
+    int Gs, Gf;   // blocks per system of the A-SpMV and FSAI kernels
 };
+
+
 
 // Enqueues `iters` iterations.  With `ev` (profile mode) the SpMV(+dot)
 // launch of iteration k is bracketed by ev[2k], ev[2k+1].  Every reducing
 // kernel is followed by its one-block-per-system finalize kernel.
 static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hipEvent_t *ev) {
-    const dim3 gt(c.Gt, c.B), gv(c.Gv, c.B), gf(c.B);
-    const int Gt = c.Gt, Gv = c.Gv;
+    const dim3 gs(c.Gs, c.B), gfs(c.Gf, c.B), gv(c.Gv, c.B), gf(c.B);
+    const int Gs = c.Gs, Gfs = c.Gf, Gv = c.Gv;
     for (int k = 0; k < iters; ++k) {
         if (c.method == HSLA_METHOD_CG) {
             if (ev) (void)hipEventRecord(ev[2 * k], s);
-            k_cg_spmv_dot<<<gt, kBlock, 0, s>>>(c.A, c.S);
+            NS_LAUNCH(k_cg_spmv_dot, c.nsA, gs, c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
-            k_fin_alpha<<<gf, kBlock, 0, s>>>(c.S, Gt);
+            k_fin_alpha<<<gf, kBlock, 0, s>>>(c.S, Gs);
             switch (c.precond) {
                 case PRE_NONE:
                     k_cg_update<PRE_NONE><<<gv, kBlock, 0, s>>>(c.A, c.S);
@@ -865,9 +952,9 @@ static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hip
                 default:
                     k_cg_update<PRE_FSAI><<<gv, kBlock, 0, s>>>(c.A, c.S);
                     k_fin_beta<PRE_FSAI><<<gf, kBlock, 0, s>>>(c.S, Gv);
-                    k_fsai_lower<<<gt, kBlock, 0, s>>>(c.A, c.L, c.S);
-                    k_fsai_upper_dot<<<gt, kBlock, 0, s>>>(c.A, c.U, c.S);
-                    k_fin_fsai<<<gf, kBlock, 0, s>>>(c.S, Gt, 0);
+                    NS_LAUNCH(k_fsai_lower, c.nsF, gfs, c.A, c.L, c.S);
+                    NS_LAUNCH(k_fsai_upper_dot, c.nsF, gfs, c.A, c.U, c.S);
+                    k_fin_fsai<<<gf, kBlock, 0, s>>>(c.S, Gfs, 0);
                     k_cg_direction<PRE_FSAI><<<gv, kBlock, 0, s>>>(c.A, c.S);
                     break;
             }
@@ -877,16 +964,16 @@ static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hip
             else
                 k_bicg_dir<PRE_NONE><<<gv, kBlock, 0, s>>>(c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k], s);
-            k_bicg_spmv_v<<<gt, kBlock, 0, s>>>(c.A, c.S);
+            NS_LAUNCH(k_bicg_spmv_v, c.nsA, gs, c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
-            k_fin_bicg_v<<<gf, kBlock, 0, s>>>(c.S, Gt);
+            k_fin_bicg_v<<<gf, kBlock, 0, s>>>(c.S, Gs);
             if (c.precond == PRE_JACOBI)
                 k_bicg_s<PRE_JACOBI><<<gv, kBlock, 0, s>>>(c.A, c.S);
             else
                 k_bicg_s<PRE_NONE><<<gv, kBlock, 0, s>>>(c.A, c.S);
             k_fin_bicg_s<<<gf, kBlock, 0, s>>>(c.S, Gv);
-            k_bicg_spmv_t<<<gt, kBlock, 0, s>>>(c.A, c.S);
-            k_fin_bicg_t<<<gf, kBlock, 0, s>>>(c.S, Gt);
+            NS_LAUNCH(k_bicg_spmv_t, c.nsA, gs, c.A, c.S);
+            k_fin_bicg_t<<<gf, kBlock, 0, s>>>(c.S, Gs);
             k_bicg_update<<<gv, kBlock, 0, s>>>(c.A, c.S);
             k_fin_bicg_update<<<gf, kBlock, 0, s>>>(c.S, Gv);
         }
@@ -979,8 +1066,21 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
     // shared by the systems of a batch (fewer, longer-running blocks each)
     const int Gt = grid_blocks(h, kWavesPerBlock, A.ntiles, B, 16);
     const int Gv = grid_blocks(h, kBlock * 4, n, B, 8);
-    const int Gmax = Gt > Gv ? Gt : Gv;
-    const Layout lay = make_layout(B, n, nvec, Gmax);
+    // offset-mask patterns run their SpMVs on diagonal-major copies of the
+    // values made once per solve (row per thread, two rows per step)
+    auto dia_slots = [](const Stencil &sn) { return sn.mask ? (sn.nofs + 3) / 4 * 4 : 0; };
+    const int nsA = dia_slots(A.sn);
+    const bool fsai = pre == PRE_FSAI && L && U;
+    const int nsF = fsai && L->sn.mask && U->sn.mask ? std::max(dia_slots(L->sn), dia_slots(U->sn)) : 0;
+    const int Gd = grid_blocks(h, kDiaChunk, n, B, 8);
+    const int Gs = nsA ? Gd : Gt, Gf = nsF ? Gd : Gt;
+    const size_t drows = (size_t)dia_chunks(n) * kDiaChunk;
+    const size_t diaA = nsA ? sizeof(double) * (size_t)B * A.sn.nofs * drows : 0;
+    const size_t diaL = nsF ? sizeof(float) * (size_t)B * L->sn.nofs * drows : 0;
+    const size_t diaU = nsF ? sizeof(float) * (size_t)B * U->sn.nofs * drows : 0;
+    const size_t extra = align_up(diaA, 256) + align_up(diaL, 256) + align_up(diaU, 256);
+    const int Gmax = std::max(std::max(Gt, Gv), Gd);
+    const Layout lay = make_layout(B, n, nvec, Gmax, extra);
     hsla_status st = ensure_workspace(h, lay.total);
     if (st != HSLA_OK) return st;
     st = ensure_host_state(h, B);
@@ -995,6 +1095,10 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
     c.precond = pre;
     c.Gt = Gt;
     c.Gv = Gv;
+    c.nsA = nsA;
+    c.nsF = nsF;
+    c.Gs = Gs;
+    c.Gf = Gf;
     Sys &S = c.S;
     S.val = values;
     S.b = b;
@@ -1010,7 +1114,24 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
         S.t = S.w;
     }
     const int64_t max_iter = o.max_iter > 0 ? o.max_iter : (10 * n < 100000 ? 10 * n : 100000);
-    const dim3 gt(Gt, B), gv(Gv, B), gf(B);
+    const dim3 gt(Gt, B), gv(Gv, B), gf(B), gfs(Gf, B);
+    {
+        char *ex = ws + lay.off_extra;
+        if (nsA) {
+            double *d = (double *)ex;
+            k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values, d);
+            S.dia = d;
+            ex += align_up(diaA, 256);
+        }
+        if (nsF) {
+            float *dl = (float *)ex;
+            float *du = (float *)(ex + align_up(diaL, 256));
+            k_to_dia<float><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, L->rp, L->sn, L->nnz, L->val, dl);
+            k_to_dia<float><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, U->rp, U->sn, U->nnz, U->val, du);
+            c.L.dia = dl;
+            c.U.dia = du;
+        }
+    }
     k_reset<<<1, kBlock, 0, s>>>(S.st, B, max_iter);
     if (o.use_x0) k_spmv<<<gt, kBlock, 0, s>>>(A, values, x, S.q);
     if (method == HSLA_METHOD_CG) {
@@ -1026,9 +1147,9 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
             default:
                 k_cg_init<PRE_FSAI><<<gv, kBlock, 0, s>>>(A, S, o.use_x0);
                 k_fin_cg_init<PRE_FSAI><<<gf, kBlock, 0, s>>>(S, Gv, o.rtol, o.atol);
-                k_fsai_lower<<<gt, kBlock, 0, s>>>(A, c.L, S);
-                k_fsai_upper_dot<<<gt, kBlock, 0, s>>>(A, c.U, S);
-                k_fin_fsai<<<gf, kBlock, 0, s>>>(S, Gt, 1);
+                NS_LAUNCH(k_fsai_lower, nsF, gfs, A, c.L, S);
+                NS_LAUNCH(k_fsai_upper_dot, nsF, gfs, A, c.U, S);
+                k_fin_fsai<<<gf, kBlock, 0, s>>>(S, Gf, 1);
                 k_cg_direction<PRE_FSAI><<<gv, kBlock, 0, s>>>(A, S);
                 break;
         }

@@ -662,7 +662,8 @@ hsla_status hsla_pattern_info(const hsla_pattern *p, int32_t *n, int64_t *nnz, i
 }
 
 hsla_status hsla_pattern_set_format(hsla_pattern *p, int32_t format) {
-    if (!p || (format != HSLA_FORMAT_AUTO && format != HSLA_FORMAT_CSR)) return HSLA_ERR_INVALID_ARG;
+    if (!p || (format != HSLA_FORMAT_AUTO && format != HSLA_FORMAT_CSR && format != HSLA_FORMAT_DIAGONAL))
+        return HSLA_ERR_INVALID_ARG;
     p->format = format;
     return HSLA_OK;
 }
