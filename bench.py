@@ -635,6 +635,41 @@ def summarize(args):
     print(out)
 
 
+def counters(args):
+    """Per-launch HBM traffic of the dominant kernel from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the
+    same counter read for the 1 GiB calibration copy of that run."""
+    fetch_dir, write_dir = args.counters_from
+    out = {}
+    for tag, d, cname in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        rows = [r for f in files for r in _read_csv(f) if r.get("Counter_Name") == cname]
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        calib = max(copies)  # the 1 GiB device-to-device copy is the largest one
+        scale = (1 << 20) / calib  # true KiB per counted KiB
+        vals = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"].split("(")[0].endswith(DOMINANT)
+                or (DOMINANT + "<") in r["Kernel_Name"]]
+        out[tag] = {"kib_per_dispatch": sum(vals) / len(vals), "dispatches": len(vals), "calibration_kib": calib,
+                    "scale": scale, "bytes_per_dispatch": sum(vals) / len(vals) * 1024 * scale}
+    total = out["fetch"]["bytes_per_dispatch"] + out["write"]["bytes_per_dispatch"]
+    rec = {"kernel": DOMINANT, "kernel_source_hash": kernel_source_hash(), "n": args.n, "nnz": args.nnz,
+           "bytes_per_launch": total, "fetch": out["fetch"], "write": out["write"], "command": args.command}
+    with open(COUNTER_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    md = COUNTER_FILE.replace(".json", ".md")
+    with open(md, "w") as f:
+        f.write(f"# HBM traffic of {DOMINANT}, diffusion3d 256^3 (rocprofv3 --pmc)\n\n")
+        f.write(f"Commands: `{args.command}`\n\n")
+        f.write("| counter | dispatches | KiB per dispatch | calibration copy KiB (1 GiB copied) | scale | bytes per dispatch |\n")
+        f.write("|---|---|---|---|---|---|\n")
+        for tag in ("fetch", "write"):
+            o = out[tag]
+            f.write(f"| {tag.upper()}_SIZE | {o['dispatches']} | {o['kib_per_dispatch']:.1f} | "
+                    f"{o['calibration_kib']:.1f} | {o['scale']:.3f} | {o['bytes_per_dispatch']:.4g} |\n")
+        f.write(f"\nTotal HBM traffic per launch: {total:.4g} bytes (kernel source hash {rec['kernel_source_hash']}).\n")
+    print(COUNTER_FILE)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -658,11 +693,18 @@ def main():
     ap.add_argument("--train-lr", type=float, default=3e-3)
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a 1 GiB copy for counter calibration")
     ap.add_argument("--summarize-rocprof", metavar="DIR")
+    ap.add_argument("--counters-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the dominant kernel's counter summary from two --pmc runs")
+    ap.add_argument("--n", type=int, default=256 ** 3)
+    ap.add_argument("--nnz", type=int, default=7 * 256 ** 3 - 6 * 256 ** 2)
     ap.add_argument("--label", default="summary")
     ap.add_argument("--command", default="")
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize(args)
+        return
+    if args.counters_from:
+        counters(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
