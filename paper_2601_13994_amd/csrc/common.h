@@ -59,6 +59,7 @@ struct DevInfo {
 struct hsla_pattern {
     int device = 0;
     int32_t format = HSLA_FORMAT_AUTO;  // requested SpMV format
+    int32_t max_row = 0;                // most entries in one row
     int32_t n = 0;
     int64_t nnz = 0;
     int32_t *row_ptr = nullptr;  // [n+1]

@@ -499,6 +499,7 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
 
     std::vector<int32_t> hrp;
     hsla_status st = build_tiles(h, n, p->row_ptr, s, &p->meta, &p->ntiles, hrp);
+    for (int32_t i = 0; st == HSLA_OK && i < n; ++i) p->max_row = std::max(p->max_row, hrp[i + 1] - hrp[i]);
     if (st == HSLA_OK) st = build_stencil(h, n, nnz, hrp, p->row_ptr, p->col, s, &p->stA);
     if (st != HSLA_OK) { (void)hipFree(df); return fail(st); }
 

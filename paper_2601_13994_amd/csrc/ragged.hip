@@ -70,6 +70,7 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV], double *sh) {
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
         double s = 0.0;
+#pragma unroll 4
         for (int q = 0; q < kRW; ++q) s += sh[j * kRW + q];
         v[j] = s;
     }
@@ -258,12 +259,188 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
     }
 }
 
+// Small systems (n <= kSmallMaxN rows of at most K entries, one shared
+// pattern): one workgroup per system keeps the whole recurrence on chip.
+// Thread t owns rows t, t + 1024, ... (R of them): their x, r, D^-1, q and p
+// live in registers, p is mirrored in LDS for the SpMV gathers, and the
+// matrix rows are re-read from L2 every iteration as R x K independent
+// loads.  Each row adds its products in ascending column order, products
+// rounded before the add.
+constexpr int kSmallMaxN = 4096;
+constexpr int kSmallMaxRow = 16;
+
+template <int K>
+__device__ __forceinline__ double small_row(int32_t lo, int32_t len, const int32_t *__restrict__ col,
+                                            const double *__restrict__ val, const double *v) {
+#pragma clang fp contract(off)
+    const double *__restrict__ vr = val + lo;
+    const int32_t *__restrict__ cr = col + lo;
+    double vv[K];
+    int32_t cc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        vv[k] = 0.0;
+        cc[k] = 0;
+        if (k < len) {
+            vv[k] = vr[k];
+            cc[k] = cr[k];
+        }
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (k < len) {
+            const double prd = vv[k] * v[cc[k]];
+            sum = sum + prd;
+        }
+    return sum;
+}
+
+template <int R, int K>
+__global__ __launch_bounds__(kRB) void k_small_pcg(Args a) {
+    __shared__ double ps[kSmallMaxN];
+    __shared__ double sh[3 * kRW];
+    __shared__ int32_t slot;
+    const int32_t n = (int32_t)a.shared_n;
+    const int32_t *rp = a.rp, *col = a.col;
+    for (;;) {
+        if (threadIdx.x == 0) slot = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int32_t s = slot;
+        __syncthreads();
+        if (s >= a.B) return;
+        const double *val = a.val + (int64_t)s * a.shared_nnz;
+        const double *b = a.b + (int64_t)s * n;
+        double *x = a.x + (int64_t)s * n;
+        int32_t lo[R], len[R];
+        double xr[R], rv[R], dv[R], pv[R], qv[R];
+        double acc3[3] = {0.0, 0.0, 0.0};
+        int bad_diag = 0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int32_t i = threadIdx.x + j * kRB;
+            lo[j] = 0;
+            len[j] = 0;
+            xr[j] = rv[j] = pv[j] = qv[j] = 0.0;
+            dv[j] = 1.0;
+            if (i < n) {
+                lo[j] = rp[i];
+                len[j] = rp[i + 1] - lo[j];
+                double d = 0.0;
+                for (int32_t k = 0; k < len[j]; ++k)
+                    if (col[lo[j] + k] == i) d = val[lo[j] + k];
+                if (a.jacobi && d == 0.0) bad_diag = 1;
+                const double di = a.jacobi ? 1.0 / d : 1.0;
+                const double bi = b[i];
+                dv[j] = di;
+                rv[j] = bi;
+                pv[j] = di * bi;
+                ps[i] = pv[j];
+                acc3[0] += bi * bi;
+                acc3[1] += bi * bi;
+                acc3[2] += bi * (di * bi);
+            }
+        }
+        double bd[1] = {(double)bad_diag};
+        wg_sum<1>(bd, sh);
+        wg_sum<3>(acc3, sh);
+        const double bn = sqrt(acc3[0]);
+        double tol = a.rtol * bn;
+        if (a.atol > tol) tol = a.atol;
+        double rho = acc3[2], rr = acc3[1];
+        int32_t status = HSLA_NOT_CONVERGED;
+        int64_t it = 0;
+        if (bd[0] > 0.0) {
+            status = HSLA_ERR_ZERO_DIAGONAL;
+        } else if (!isfinite(bn)) {
+            status = HSLA_ERR_NONFINITE;
+        } else if (sqrt(rr) <= tol) {
+            status = HSLA_OK;
+        } else {
+            while (it < a.max_iter) {
+                // q = A p from the LDS copy of p (visible after the barriers
+                // of the last reduction), sigma = p.q
+                // rows in pairs, so at most 2 K loads are in flight per thread
+                double acc1[1] = {0.0};
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    qv[j] = small_row<K>(lo[j], len[j], col, val, ps);
+                    acc1[0] += pv[j] * qv[j];
+                    if (j % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                }
+                wg_sum<1>(acc1, sh);
+                const double sigma = acc1[0];
+                if (!isfinite(sigma)) { status = HSLA_ERR_NONFINITE; break; }
+                if (!(sigma > 0.0)) { status = HSLA_BREAKDOWN; break; }
+                const double alpha = rho / sigma;
+                double acc2[2] = {0.0, 0.0};
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    xr[j] = xr[j] + alpha * pv[j];
+                    rv[j] = rv[j] - alpha * qv[j];
+                    acc2[0] += rv[j] * rv[j];
+                    acc2[1] += rv[j] * (dv[j] * rv[j]);
+                }
+                wg_sum<2>(acc2, sh);
+                ++it;
+                rr = acc2[0];
+                const double rn = sqrt(rr);
+                if (!isfinite(rn)) { status = HSLA_ERR_NONFINITE; break; }
+                if (rn <= tol) { status = HSLA_OK; break; }
+                const double beta = acc2[1] / rho;
+                rho = acc2[1];
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const int32_t i = threadIdx.x + j * kRB;
+                    pv[j] = dv[j] * rv[j] + beta * pv[j];
+                    if (i < n) ps[i] = pv[j];
+                }
+                __syncthreads();
+            }
+        }
+        // x out, and the true residual ||b - A x|| from an LDS copy of x
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int32_t i = threadIdx.x + j * kRB;
+            if (i < n) {
+                x[i] = xr[j];
+                ps[i] = xr[j];
+            }
+        }
+        __syncthreads();
+        double accr[2] = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int32_t i = threadIdx.x + j * kRB;
+            if (i < n) {
+                const double bi = b[i];
+                const double e = bi - small_row<K>(lo[j], len[j], col, val, ps);
+                accr[0] += e * e;
+                accr[1] += bi * bi;
+            }
+            if (j % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        wg_sum<2>(accr, sh);
+        if (threadIdx.x == 0) {
+            RInfo f;
+            f.iters = it;
+            f.status = status;
+            f.pad = 0;
+            f.rel_residual = bn > 0 ? sqrt(rr) / bn : sqrt(rr);
+            f.true_residual = accr[1] > 0 ? sqrt(accr[0]) / sqrt(accr[1]) : sqrt(accr[0]);
+            a.info[s] = f;
+        }
+        __syncthreads();
+    }
+}
+
 // Carves the work vectors, launches the persistent kernel and returns the
 // per-system records.  `a` arrives with the system description set; `order`
 // (host, may be empty = identity) is the queue order.
 static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, int64_t rows, int64_t entries,
                                   int64_t max_n, const std::vector<int32_t> &order, hsla_info *infos,
-                                  hipStream_t s) {
+                                  hipStream_t s, int small_rows = 0, int small_k = 0) {
     const int32_t B = a.B;
     size_t bytes = 0;
     auto add = [&](size_t v) { bytes += (v + 255) / 256 * 256; };
@@ -312,7 +489,20 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
         if (bad != INT32_MAX) return set_error(h, HSLA_ERR_INVALID_CSR, "system %d is not canonical CSR", bad);
     }
     const int grid = (int)std::min<int64_t>(B, 2 * (int64_t)h->dev.num_cu);
-    k_ragged_pcg<<<grid, kRB, 0, s>>>(a);
+    if (small_rows == 1 && small_k == 8)
+        k_small_pcg<1, 8><<<grid, kRB, 0, s>>>(a);
+    else if (small_rows == 1)
+        k_small_pcg<1, 16><<<grid, kRB, 0, s>>>(a);
+    else if (small_rows == 2 && small_k == 8)
+        k_small_pcg<2, 8><<<grid, kRB, 0, s>>>(a);
+    else if (small_rows == 2)
+        k_small_pcg<2, 16><<<grid, kRB, 0, s>>>(a);
+    else if (small_rows == 4 && small_k == 8)
+        k_small_pcg<4, 8><<<grid, kRB, 0, s>>>(a);
+    else if (small_rows == 4)
+        k_small_pcg<4, 16><<<grid, kRB, 0, s>>>(a);
+    else
+        k_ragged_pcg<<<grid, kRB, 0, s>>>(a);
     HSLA_HIP(h, hipGetLastError());
     std::vector<RInfo> hi(B);
     HSLA_HIP(h, hipMemcpyAsync(hi.data(), a.info, sizeof(RInfo) * B, hipMemcpyDeviceToHost, s));
@@ -355,7 +545,12 @@ hsla_status persistent_solve(hsla_handle *h, const hsla_pattern *p, int B, const
     a.val = values;
     a.b = b;
     a.x = x;
-    return rg::run_persistent(h, a, o, (int64_t)B * p->n, p->nnz, p->n, {}, infos, s);
+    int rows = 0, k = 0;
+    if (p->n <= rg::kSmallMaxN && p->max_row <= rg::kSmallMaxRow) {
+        rows = p->n <= rg::kRB ? 1 : p->n <= 2 * rg::kRB ? 2 : 4;
+        k = p->max_row <= 8 ? 8 : 16;
+    }
+    return rg::run_persistent(h, a, o, (int64_t)B * p->n, p->nnz, p->n, {}, infos, s, rows, k);
 }
 
 }  // namespace hsla
