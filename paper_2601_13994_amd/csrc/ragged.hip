@@ -28,8 +28,10 @@
 namespace hsla {
 namespace rg {
 
-constexpr int kRB = 1024;  // threads per workgroup
+constexpr int kRB = 1024;  // threads per workgroup of the general kernel
 constexpr int kRW = kRB / kWave;
+constexpr int kSB = 1024;  // threads per workgroup of the small-system kernel
+constexpr int kSW = kSB / kWave;
 constexpr int kChunk = 256;  // entries staged per wave and step
 
 struct RInfo {  // per-system result record (device)
@@ -56,44 +58,57 @@ struct Args {
     int jacobi;
 };
 
-// Workgroup sum of NV values in a fixed order; result in every thread.
-template <int NV>
+// Workgroup (NW waves) sum of NV values in a fixed order; result in every
+// thread.
+template <int NW, int NV>
 __device__ __forceinline__ void wg_sum(double (&v)[NV], double *sh) {
 #pragma unroll
     for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     if (lane == 0) {
 #pragma unroll
-        for (int j = 0; j < NV; ++j) sh[j * kRW + w] = v[j];
+        for (int j = 0; j < NV; ++j) sh[j * NW + w] = v[j];
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
         double s = 0.0;
 #pragma unroll 4
-        for (int q = 0; q < kRW; ++q) s += sh[j * kRW + q];
+        for (int q = 0; q < NW; ++q) s += sh[j * NW + q];
         v[j] = s;
     }
     __syncthreads();
 }
 
-// y = A v for one system, by the whole workgroup: wave w takes the 64-row
-// blocks w, w + kRW, ...; a block's entries are loaded in coalesced chunks of
-// kChunk, their products staged in the wave's LDS slice, and each lane adds
-// the products of its row in ascending order.  epi(i, y_i) runs on the lane
-// that owns row i.
-template <class Epi>
+// y = A v for one system, by the whole workgroup (NW waves): wave w takes
+// the 64-row blocks w, w + NW, ...; a block's entries are loaded in
+// coalesced chunks of kChunk, their products staged in the wave's LDS slice,
+// and each lane adds the products of its row in ascending order.  The next
+// block's row pointers are loaded while the current block is processed.
+// epi(i, y_i) runs on the lane that owns row i.
+template <int NW, class Epi>
 __device__ __forceinline__ void wg_spmv(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                         const double *__restrict__ val, const double *__restrict__ v, double *lds,
                                         Epi &&epi) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     double *L = lds + w * kChunk;
-    for (int32_t r0 = w * kWave; r0 < n; r0 += kRW * kWave) {
+    int32_t r0 = w * kWave;
+    int32_t e0 = 0, e1 = 0, ka = 0, kb = 0;
+    auto fetch = [&](int32_t b0, int32_t &f0, int32_t &f1, int32_t &fa, int32_t &fb) {
+        const int32_t row = b0 + lane;
+        const int32_t rend = b0 + kWave < n ? b0 + kWave : n;
+        f0 = rp[b0];
+        f1 = rp[rend];
+        fa = row < n ? rp[row] : 0;
+        fb = row < n ? rp[row + 1] : 0;
+        if (row >= n) fa = fb = f1;
+    };
+    if (r0 < n) fetch(r0, e0, e1, ka, kb);
+    for (; r0 < n; r0 += NW * kWave) {
+        const int32_t rn = r0 + NW * kWave;
+        int32_t n0 = 0, n1 = 0, na = 0, nb = 0;
+        if (rn < n) fetch(rn, n0, n1, na, nb);
         const int32_t row = r0 + lane;
-        const bool own = row < n;
-        const int32_t rend = r0 + kWave < n ? r0 + kWave : n;
-        const int32_t e0 = rp[r0], e1 = rp[rend];
-        const int32_t ka = own ? rp[row] : e1, kb = own ? rp[row + 1] : e1;
         double acc = 0.0;
         for (int32_t c0 = e0; c0 < e1; c0 += kChunk) {
             const int32_t cnt = e1 - c0 < kChunk ? e1 - c0 : kChunk;
@@ -112,7 +127,11 @@ __device__ __forceinline__ void wg_spmv(int32_t n, const int32_t *__restrict__ r
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        if (own) epi(row, acc);
+        if (row < n) epi(row, acc);
+        e0 = n0;
+        e1 = n1;
+        ka = na;
+        kb = nb;
     }
 }
 
@@ -168,9 +187,13 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
         const int64_t k0 = shared ? (int64_t)s * a.shared_nnz : a.nnz_off[s];
         const int32_t *rp = shared ? a.rp : a.rp + r0 + s;
         const int32_t *col = shared ? a.col : a.col + k0;
-        const double *val = a.val + k0;
-        const double *b = a.b + r0;
-        double *x = a.x + r0, *r = a.r + r0, *p = a.p + r0, *q = a.q + r0, *dinv = a.dinv + r0;
+        const double *__restrict__ val = a.val + k0;
+        const double *__restrict__ b = a.b + r0;
+        double *__restrict__ x = a.x + r0;
+        double *__restrict__ r = a.r + r0;
+        double *__restrict__ p = a.p + r0;
+        double *__restrict__ q = a.q + r0;
+        double *__restrict__ dinv = a.dinv + r0;
         // set-up: x = 0, r = b, z = D^{-1} r, p = z
         double acc3[3] = {0.0, 0.0, 0.0};
         int bad_diag = 0;
@@ -190,8 +213,8 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
             acc3[2] += bi * (di * bi);
         }
         double bd[1] = {(double)bad_diag};
-        wg_sum<1>(bd, sh);
-        wg_sum<3>(acc3, sh);
+        wg_sum<kRW, 1>(bd, sh);
+        wg_sum<kRW, 3>(acc3, sh);
         const double bn = sqrt(acc3[0]);
         double tol = a.rtol * bn;
         if (a.atol > tol) tol = a.atol;
@@ -208,24 +231,42 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
             while (it < a.max_iter) {
                 // q = A p, sigma = p.q (each row summed in ascending order)
                 double acc1[1] = {0.0};
-                wg_spmv(n, rp, col, val, p, lds, [&](int32_t i, double sum) {
+                wg_spmv<kRW>(n, rp, col, val, p, lds, [&](int32_t i, double sum) {
                     q[i] = sum;
                     acc1[0] += p[i] * sum;
                 });
-                wg_sum<1>(acc1, sh);
+                wg_sum<kRW, 1>(acc1, sh);
                 const double sigma = acc1[0];
                 if (!isfinite(sigma)) { status = HSLA_ERR_NONFINITE; break; }
                 if (!(sigma > 0.0)) { status = HSLA_BREAKDOWN; break; }
                 const double alpha = rho / sigma;
                 double acc2[2] = {0.0, 0.0};
-                for (int32_t i = threadIdx.x; i < n; i += kRB) {
-                    x[i] = x[i] + alpha * p[i];
-                    const double ri = r[i] - alpha * q[i];
-                    r[i] = ri;
-                    acc2[0] += ri * ri;
-                    acc2[1] += ri * (dinv[i] * ri);
+                for (int32_t i0 = threadIdx.x; i0 < n; i0 += 2 * kRB) {
+                    double xv[2], pv[2], rv[2], qv[2], dv[2];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int32_t i = i0 + u * kRB;
+                        if (i < n) {
+                            xv[u] = x[i];
+                            pv[u] = p[i];
+                            rv[u] = r[i];
+                            qv[u] = q[i];
+                            dv[u] = dinv[i];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int32_t i = i0 + u * kRB;
+                        if (i < n) {
+                            x[i] = xv[u] + alpha * pv[u];
+                            const double ri = rv[u] - alpha * qv[u];
+                            r[i] = ri;
+                            acc2[0] += ri * ri;
+                            acc2[1] += ri * (dv[u] * ri);
+                        }
+                    }
                 }
-                wg_sum<2>(acc2, sh);
+                wg_sum<kRW, 2>(acc2, sh);
                 ++it;
                 rr = acc2[0];
                 const double rn = sqrt(rr);
@@ -233,19 +274,35 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
                 if (rn <= tol) { status = HSLA_OK; break; }
                 const double beta = acc2[1] / rho;
                 rho = acc2[1];
-                for (int32_t i = threadIdx.x; i < n; i += kRB) p[i] = dinv[i] * r[i] + beta * p[i];
+                for (int32_t i0 = threadIdx.x; i0 < n; i0 += 4 * kRB) {
+                    double dv[4], rv[4], pv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int32_t i = i0 + u * kRB;
+                        if (i < n) {
+                            dv[u] = dinv[i];
+                            rv[u] = r[i];
+                            pv[u] = p[i];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int32_t i = i0 + u * kRB;
+                        if (i < n) p[i] = dv[u] * rv[u] + beta * pv[u];
+                    }
+                }
                 __syncthreads();
             }
         }
         // true residual ||b - A x||
         double accr[2] = {0.0, 0.0};
         __syncthreads();
-        wg_spmv(n, rp, col, val, x, lds, [&](int32_t i, double sum) {
+        wg_spmv<kRW>(n, rp, col, val, x, lds, [&](int32_t i, double sum) {
             const double e = b[i] - sum;
             accr[0] += e * e;
             accr[1] += b[i] * b[i];
         });
-        wg_sum<2>(accr, sh);
+        wg_sum<kRW, 2>(accr, sh);
         if (threadIdx.x == 0) {
             RInfo f;
             f.iters = it;
@@ -261,7 +318,7 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
 
 // Small systems (n <= kSmallMaxN rows of at most K entries, one shared
 // pattern): one workgroup per system keeps the whole recurrence on chip.
-// Thread t owns rows t, t + 1024, ... (R of them): their x, r, D^-1, q and p
+// Thread t owns rows t, t + kSB, ... (R of them): their x, r, D^-1, q and p
 // live in registers, p is mirrored in LDS for the SpMV gathers, and the
 // matrix rows are re-read from L2 every iteration as R x K independent
 // loads.  Each row adds its products in ascending column order, products
@@ -297,9 +354,9 @@ __device__ __forceinline__ double small_row(int32_t lo, int32_t len, const int32
 }
 
 template <int R, int K>
-__global__ __launch_bounds__(kRB) void k_small_pcg(Args a) {
+__global__ __launch_bounds__(kSB) void k_small_pcg(Args a) {
     __shared__ double ps[kSmallMaxN];
-    __shared__ double sh[3 * kRW];
+    __shared__ double sh[3 * kSW];
     __shared__ int32_t slot;
     const int32_t n = (int32_t)a.shared_n;
     const int32_t *rp = a.rp, *col = a.col;
@@ -318,7 +375,7 @@ __global__ __launch_bounds__(kRB) void k_small_pcg(Args a) {
         int bad_diag = 0;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            const int32_t i = threadIdx.x + j * kRB;
+            const int32_t i = threadIdx.x + j * kSB;
             lo[j] = 0;
             len[j] = 0;
             xr[j] = rv[j] = pv[j] = qv[j] = 0.0;
@@ -342,8 +399,8 @@ __global__ __launch_bounds__(kRB) void k_small_pcg(Args a) {
             }
         }
         double bd[1] = {(double)bad_diag};
-        wg_sum<1>(bd, sh);
-        wg_sum<3>(acc3, sh);
+        wg_sum<kSW, 1>(bd, sh);
+        wg_sum<kSW, 3>(acc3, sh);
         const double bn = sqrt(acc3[0]);
         double tol = a.rtol * bn;
         if (a.atol > tol) tol = a.atol;
@@ -368,7 +425,7 @@ __global__ __launch_bounds__(kRB) void k_small_pcg(Args a) {
                     acc1[0] += pv[j] * qv[j];
                     if (j % 2 == 1) __builtin_amdgcn_sched_barrier(0);
                 }
-                wg_sum<1>(acc1, sh);
+                wg_sum<kSW, 1>(acc1, sh);
                 const double sigma = acc1[0];
                 if (!isfinite(sigma)) { status = HSLA_ERR_NONFINITE; break; }
                 if (!(sigma > 0.0)) { status = HSLA_BREAKDOWN; break; }
@@ -381,7 +438,7 @@ __global__ __launch_bounds__(kRB) void k_small_pcg(Args a) {
                     acc2[0] += rv[j] * rv[j];
                     acc2[1] += rv[j] * (dv[j] * rv[j]);
                 }
-                wg_sum<2>(acc2, sh);
+                wg_sum<kSW, 2>(acc2, sh);
                 ++it;
                 rr = acc2[0];
                 const double rn = sqrt(rr);
@@ -391,7 +448,7 @@ __global__ __launch_bounds__(kRB) void k_small_pcg(Args a) {
                 rho = acc2[1];
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
-                    const int32_t i = threadIdx.x + j * kRB;
+                    const int32_t i = threadIdx.x + j * kSB;
                     pv[j] = dv[j] * rv[j] + beta * pv[j];
                     if (i < n) ps[i] = pv[j];
                 }
@@ -402,7 +459,7 @@ __global__ __launch_bounds__(kRB) void k_small_pcg(Args a) {
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            const int32_t i = threadIdx.x + j * kRB;
+            const int32_t i = threadIdx.x + j * kSB;
             if (i < n) {
                 x[i] = xr[j];
                 ps[i] = xr[j];
@@ -412,7 +469,7 @@ __global__ __launch_bounds__(kRB) void k_small_pcg(Args a) {
         double accr[2] = {0.0, 0.0};
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            const int32_t i = threadIdx.x + j * kRB;
+            const int32_t i = threadIdx.x + j * kSB;
             if (i < n) {
                 const double bi = b[i];
                 const double e = bi - small_row<K>(lo[j], len[j], col, val, ps);
@@ -421,7 +478,7 @@ __global__ __launch_bounds__(kRB) void k_small_pcg(Args a) {
             }
             if (j % 2 == 1) __builtin_amdgcn_sched_barrier(0);
         }
-        wg_sum<2>(accr, sh);
+        wg_sum<kSW, 2>(accr, sh);
         if (threadIdx.x == 0) {
             RInfo f;
             f.iters = it;
@@ -488,21 +545,23 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
         HSLA_HIP(h, hipStreamSynchronize(s));
         if (bad != INT32_MAX) return set_error(h, HSLA_ERR_INVALID_CSR, "system %d is not canonical CSR", bad);
     }
-    const int grid = (int)std::min<int64_t>(B, 2 * (int64_t)h->dev.num_cu);
+    // workgroups beyond the resident ones find the queue empty and exit
+    const int gs = (int)std::min<int64_t>(B, 2 * (int64_t)h->dev.num_cu);
+    const int gr = gs;
     if (small_rows == 1 && small_k == 8)
-        k_small_pcg<1, 8><<<grid, kRB, 0, s>>>(a);
+        k_small_pcg<1, 8><<<gs, kSB, 0, s>>>(a);
     else if (small_rows == 1)
-        k_small_pcg<1, 16><<<grid, kRB, 0, s>>>(a);
+        k_small_pcg<1, 16><<<gs, kSB, 0, s>>>(a);
     else if (small_rows == 2 && small_k == 8)
-        k_small_pcg<2, 8><<<grid, kRB, 0, s>>>(a);
+        k_small_pcg<2, 8><<<gs, kSB, 0, s>>>(a);
     else if (small_rows == 2)
-        k_small_pcg<2, 16><<<grid, kRB, 0, s>>>(a);
+        k_small_pcg<2, 16><<<gs, kSB, 0, s>>>(a);
     else if (small_rows == 4 && small_k == 8)
-        k_small_pcg<4, 8><<<grid, kRB, 0, s>>>(a);
+        k_small_pcg<4, 8><<<gs, kSB, 0, s>>>(a);
     else if (small_rows == 4)
-        k_small_pcg<4, 16><<<grid, kRB, 0, s>>>(a);
+        k_small_pcg<4, 16><<<gs, kSB, 0, s>>>(a);
     else
-        k_ragged_pcg<<<grid, kRB, 0, s>>>(a);
+        k_ragged_pcg<<<gr, kRB, 0, s>>>(a);
     HSLA_HIP(h, hipGetLastError());
     std::vector<RInfo> hi(B);
     HSLA_HIP(h, hipMemcpyAsync(hi.data(), a.info, sizeof(RInfo) * B, hipMemcpyDeviceToHost, s));
@@ -547,7 +606,7 @@ hsla_status persistent_solve(hsla_handle *h, const hsla_pattern *p, int B, const
     a.x = x;
     int rows = 0, k = 0;
     if (p->n <= rg::kSmallMaxN && p->max_row <= rg::kSmallMaxRow) {
-        rows = p->n <= rg::kRB ? 1 : p->n <= 2 * rg::kRB ? 2 : 4;
+        rows = p->n <= rg::kSB ? 1 : p->n <= 2 * rg::kSB ? 2 : 4;
         k = p->max_row <= 8 ? 8 : 16;
     }
     return rg::run_persistent(h, a, o, (int64_t)B * p->n, p->nnz, p->n, {}, infos, s, rows, k);
