@@ -188,6 +188,9 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
 
     a, b = ctx["d3"]
     n, nnz = a.n, a.nnz
+    tuning = pat.autotune(B=1, effort=5) if args.autotune else None
+    if tuning:
+        log(f"[bench] autotune: {tuning}")
     opts_w = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-8, max_iter=args.max_iter)
     for i in range(args.warmup):
         x, infos, st = _lib.solve(pat, vals, bt, opts_w)
@@ -208,11 +211,16 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
     launches = sum(r["spmv_launches"] for r in recs)
     avg_ms = spmv_ms / max(launches, 1)
     stencil, nofs = pat.stencil
-    nofs = nofs if stencil else 0
-    bytes_launch = spmv_bytes(n, nnz, nofs)
+    form = ("diagonal" if (tuning is None or tuning["form"] == "diagonal") else "mask-tiles") if stencil else "csr"
+    if form == "diagonal":
+        bytes_launch = spmv_bytes(n, nnz, nofs)
+    elif form == "mask-tiles":
+        bytes_launch = 8 * nnz + 2 * n + 16 * n  # values in CSR order + row masks
+    else:
+        bytes_launch = spmv_bytes(n, nnz, 0)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     ms_step = elapsed / args.steps * 1e3
-    it_bytes = pcg_iteration_bytes(n, nnz, nofs)
+    it_bytes = bytes_launch + 88 * n
     csr_it_bytes = pcg_iteration_bytes(n, nnz, 0)
     top = {
         "metric": METRIC,
@@ -243,7 +251,8 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "algorithmic_bytes_per_launch": bytes_launch,
             "mean_launch_ms": avg_ms,
             "launches_timed": launches,
-            "format": f"diagonal-major values + row masks, {nofs} diagonals" if nofs else "csr",
+            "format": {"diagonal": f"diagonal-major values + row masks, {nofs} diagonals",
+                       "mask-tiles": f"row tiles with row masks, {nofs} diagonals", "csr": "csr row tiles"}[form],
         },
         "detail": {
             "iterations": iters,
@@ -255,6 +264,7 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "GFLOPs": (2 * nnz + 13 * n) * iters / (ms_step * 1e-3) / 1e9,
             "algorithmic_bytes_per_iteration": it_bytes,
             "spmv_share_of_step": spmv_ms / args.steps / ms_step,
+            "autotune": tuning,
             "csr_bytes_per_iteration": csr_it_bytes,
             "csr_equivalent_iteration_GBps": csr_it_bytes * iters / (ms_step * 1e-3) / 1e9,
         },
@@ -420,6 +430,7 @@ def run_adjoint(ctx, args, dev):
     vals = torch.as_tensor(V).to(dev)
     bt = torch.as_tensor(Bs).to(dev)
     xst = torch.as_tensor(Xs).to(dev)
+    tuning = pat.autotune(B=B, effort=3) if args.autotune else None
     opts = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-8)
 
     def pair():
@@ -444,6 +455,7 @@ def run_adjoint(ctx, args, dev):
         "workload": (f"{B} systems on one 3D 7-point pattern, {args.adj_m}^3 (n={n}, nnz={nnz}), log-normal kappa "
                      "per sample; forward Jacobi-PCG + adjoint, rtol 1e-8, loss 1/2||x - x*||^2"),
         "pairs_per_s": B / dt, "ms_per_batch": dt * 1e3, "status_forward": st, "status_adjoint": st2,
+        "autotune": tuning,
         "iterations_forward_mean": float(itf.mean()), "iterations_adjoint_mean": float(itb.mean()),
         "true_relative_residual_max": max(max(f["true_residual"] for f in fi), max(f["true_residual"] for f in bi)),
         "model_GBps": work / dt / 1e9, "model_frac_of_peak": work / dt / 1e9 / HBM_PEAK_GBPS,
@@ -484,6 +496,7 @@ def run_learned(ctx, args, dev):
     V = learned.aniso_batch_values(sl, st_eval)
     bt = torch.as_tensor(ctx["aniso_b"]).to(dev)
     E = V.shape[0]
+    tuning = pat.autotune(B=E, effort=3) if args.autotune else None
     jopts = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-8)
     w = min(E, 16)  # warm up both paths (graphs, workspaces) on a slice
     _lib.solve(pat, V[:w].contiguous(), bt[:w].contiguous(), jopts)
@@ -517,7 +530,7 @@ def run_learned(ctx, args, dev):
         "iterations_mean_learned": float(itl.mean()), "iterations_mean_jacobi": float(itj.mean()),
         "iterations_max_learned": int(itl.max()), "iterations_max_jacobi": int(itj.max()),
         "iteration_ratio_mean": float((itl / np.maximum(itj, 1)).mean()),
-        "fell_back": int(fell), "status_learned": stl, "status_jacobi": stj,
+        "fell_back": int(fell), "status_learned": stl, "status_jacobi": stj, "autotune": tuning,
         "true_relative_residual_max_learned": rel_l, "true_relative_residual_max_jacobi": rel_j,
         "train_seconds": t_train, "train_steps": args.train_steps, "train_batch": args.train_batch,
         "train_probes": args.train_probes, "train_loss_first": float(np.mean(hist[:5])),
@@ -683,6 +696,8 @@ def main():
     ap.add_argument("--m", type=int, default=256, help="grid edge (256 is the benchmark size)")
     ap.add_argument("--max-iter", type=int, default=0, help="cap iterations (profiling runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="skip the SpMV autotuner (set-up, not timed)")
     ap.add_argument("--workloads", default="all", help="comma list from " + ",".join(ALL_WORKLOADS))
     ap.add_argument("--sub-steps", type=int, default=2, help="timed repetitions of the other workloads")
     ap.add_argument("--poisson-copies", type=int, default=1024)

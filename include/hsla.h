@@ -134,6 +134,23 @@ hsla_status hsla_pattern_set_format(hsla_pattern *p, int32_t format);
 /* stencil_in_use: 1 if A's SpMV currently uses the offset-mask form;
  * num_offsets: number of distinct diagonals of A, 0 if A has no such form. */
 hsla_status hsla_pattern_format(const hsla_pattern *p, int32_t *stencil_in_use, int32_t *num_offsets);
+/* Autotuner result: the SpMV configuration the solvers use on a pattern. */
+typedef struct hsla_tuning {
+    int32_t form;          /* 0: per-solve diagonal-major copy, 1: row tiles (CSR or row masks) */
+    int32_t blocks_per_cu; /* grid density of the chosen form's SpMV kernel                   */
+    double best_us;        /* mean SpMV time of the choice (B systems)                        */
+    double default_us;     /* mean SpMV time of the untuned default configuration             */
+} hsla_tuning;
+/* Times the solvers' SpMV on this pattern for a batch of B systems, on the
+ * device and with synthetic values: the diagonal-major form (offset-mask
+ * patterns, unless the CSR format was selected) at 2, 4, 8, 16 blocks per CU
+ * and the row-tile form at 4, 8, 16, 32 blocks per CU, `effort` launches each
+ * (1..100).  Stores the fastest in the pattern (later solves on it use it;
+ * results do not depend on the choice beyond rounding of dot products) and
+ * reports it in `out` (host, may be NULL).  Uses the handle's workspace;
+ * must not run concurrently with other calls that use `p`. */
+hsla_status hsla_autotune(hsla_handle *h, hsla_pattern *p, int32_t B, int32_t effort, hsla_tuning *out,
+                          void *stream);
 /* Device copies of the transpose: row_ptr_T int32[n+1], col_T int32[nnz] and
  * src int32[nnz] with src[k'] = position in A of the entry stored at k' of
  * A^T (a bijection).  Host-visible only through the copy. */

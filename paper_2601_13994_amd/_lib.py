@@ -29,7 +29,7 @@ FORMATS = {"auto": 0, "csr": 1, "diagonal": 2}
 EXPORTS = [
     "hsla_opts_default", "hsla_status_string", "hsla_create", "hsla_destroy", "hsla_last_error",
     "hsla_pattern_create", "hsla_pattern_destroy", "hsla_pattern_info", "hsla_pattern_set_format",
-    "hsla_pattern_format", "hsla_pattern_transpose",
+    "hsla_pattern_format", "hsla_autotune", "hsla_pattern_transpose",
     "hsla_spmv", "hsla_solve", "hsla_solve_batched", "hsla_adjoint", "hsla_adjoint_batched",
     "hsla_outer_on_pattern", "hsla_residual_norms",
     "hsla_mpnn_num_params", "hsla_mpnn_forward", "hsla_mpnn_backward", "hsla_probe_loss", "hsla_adam_step",
@@ -66,6 +66,11 @@ class Info(ctypes.Structure):
                 "spmv_ms": self.spmv_ms, "spmv_launches": self.spmv_launches}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("best_us", ctypes.c_double), ("default_us", ctypes.c_double)]
+
+
 _lib = None
 _lock = threading.Lock()
 _handles: dict[int, ctypes.c_void_p] = {}
@@ -99,6 +104,7 @@ def load() -> ctypes.CDLL:
         L.hsla_pattern_info.argtypes = [vp, P(i32), P(i64), P(i64), P(i32)]
         L.hsla_pattern_set_format.argtypes = [vp, i32]
         L.hsla_pattern_format.argtypes = [vp, P(i32), P(i32)]
+        L.hsla_autotune.argtypes = [vp, vp, i32, i32, P(Tuning), vp]
         L.hsla_pattern_transpose.argtypes = [vp, vp, vp, vp, vp, vp]
         L.hsla_spmv.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.hsla_solve.argtypes = [vp, vp, vp, vp, vp, P(Opts), P(Info), vp]
@@ -223,6 +229,16 @@ class Pattern:
         st = load().hsla_pattern_set_format(self.p, FORMATS[fmt])
         if st != OK:
             raise HslaError(st, f"unknown format {fmt!r}")
+
+    def autotune(self, B: int = 1, effort: int = 5) -> dict:
+        """Times the solvers' SpMV forms and grid densities for a batch of B
+        systems and keeps the fastest for later solves on this pattern."""
+        t = Tuning()
+        with torch.cuda.device(self.device):
+            st = load().hsla_autotune(self.h, self.p, int(B), int(effort), ctypes.byref(t), stream_ptr(self.device))
+            check(st, self.h, "hsla_autotune")
+        return {"form": ("diagonal" if t.form == 0 else "tiles"), "blocks_per_cu": t.blocks_per_cu,
+                "best_us": t.best_us, "default_us": t.default_us}
 
     def __del__(self):
         p = getattr(self, "p", None)

@@ -60,6 +60,9 @@ struct hsla_pattern {
     int device = 0;
     int32_t format = HSLA_FORMAT_AUTO;  // requested SpMV format
     int32_t max_row = 0;                // most entries in one row
+    // autotuned SpMV configuration of the solvers (hsla_autotune); defaults
+    // until tuned: diagonal-major form where available, 16 / 8 blocks per CU
+    int32_t tune_dia = 1, tune_tile_cu = 16, tune_dia_cu = 8, tuned = 0;
     int32_t n = 0;
     int64_t nnz = 0;
     int32_t *row_ptr = nullptr;  // [n+1]

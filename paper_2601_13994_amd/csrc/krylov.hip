@@ -878,6 +878,10 @@ static Layout make_layout(int B, int64_t n, int nvec, int G, size_t extra = 0) {
     return L;
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill_f64(double *__restrict__ a, int64_t m, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) a[i] = v;
+}
+
 // Launches K<NS> for the diagonal-major slot count `ns` (0 = tile walk).
 #define NS_LAUNCH(K, ns, grid, ...)                                       \
     switch (ns) {                                                         \
@@ -1054,7 +1058,15 @@ static int worst_status(int a, int b) {
 
 // Shared solve driver for the single, batched and transposed (adjoint)
 // paths.  `A` is the operator actually iterated on.
-static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const FPat *U, int B, const double *values,
+// SpMV configuration of a solve (the pattern's autotuned choice).
+struct Tune {
+    int dia, tile_cu, dia_cu;
+};
+
+static Tune tune_of(const hsla_pattern *p) { return Tune{p->tune_dia, p->tune_tile_cu, p->tune_dia_cu}; }
+
+static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, const FPat *L, const FPat *U, int B,
+                              const double *values,
                               const double *b, double *x, const hsla_opts &o, int method, hsla_info *infos,
                               hipStream_t s) {
     const int64_t n = A.n;
@@ -1064,22 +1076,25 @@ static hsla_status solve_core(hsla_handle *h, const Pat &A, const FPat *L, const
     const int nvec = method == HSLA_METHOD_CG ? 6 : 10;
     // SpMV-based kernels: up to 16 blocks per CU; vector kernels: up to 8,
     // shared by the systems of a batch (fewer, longer-running blocks each)
-    const int Gt = grid_blocks(h, kWavesPerBlock, A.ntiles, B, 16);
+    const int Gt = grid_blocks(h, kWavesPerBlock, A.ntiles, B, tn.tile_cu);
     const int Gv = grid_blocks(h, kBlock * 4, n, B, 8);
     // offset-mask patterns run their SpMVs on diagonal-major copies of the
-    // values made once per solve (row per thread, two rows per step)
+    // values made once per solve (row per thread, two rows per step) unless
+    // the autotuner found the row tiles faster
+    // (the tuning covers A's SpMV; the FSAI factors always use their
+    // diagonal-major copies where they have one)
     auto dia_slots = [](const Stencil &sn) { return sn.mask ? (sn.nofs + 3) / 4 * 4 : 0; };
-    const int nsA = dia_slots(A.sn);
+    const int nsA = tn.dia ? dia_slots(A.sn) : 0;
     const bool fsai = pre == PRE_FSAI && L && U;
     const int nsF = fsai && L->sn.mask && U->sn.mask ? std::max(dia_slots(L->sn), dia_slots(U->sn)) : 0;
-    const int Gd = grid_blocks(h, kDiaChunk, n, B, 8);
-    const int Gs = nsA ? Gd : Gt, Gf = nsF ? Gd : Gt;
+    const int Gd = grid_blocks(h, kDiaChunk, n, B, tn.dia_cu);
+    const int Gs = nsA ? Gd : Gt, Gf = nsF ? grid_blocks(h, kDiaChunk, n, B, 8) : Gt;
     const size_t drows = (size_t)dia_chunks(n) * kDiaChunk;
     const size_t diaA = nsA ? sizeof(double) * (size_t)B * A.sn.nofs * drows : 0;
     const size_t diaL = nsF ? sizeof(float) * (size_t)B * L->sn.nofs * drows : 0;
     const size_t diaU = nsF ? sizeof(float) * (size_t)B * U->sn.nofs * drows : 0;
     const size_t extra = align_up(diaA, 256) + align_up(diaL, 256) + align_up(diaU, 256);
-    const int Gmax = std::max(std::max(Gt, Gv), Gd);
+    const int Gmax = std::max(std::max(Gt, Gv), std::max(Gd, Gf));
     const Layout lay = make_layout(B, n, nvec, Gmax, extra);
     hsla_status st = ensure_workspace(h, lay.total);
     if (st != HSLA_OK) return st;
@@ -1317,7 +1332,7 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
         L = FPat{p->rpL, p->colL, p->metaL, p->ntilesL, p->nnz_lower, o.d_G, p->use(p->stL)};
         U = FPat{p->rpU, p->colU, p->metaU, p->ntilesU, p->nnz_lower, o.d_GT, p->use(p->stU)};
     }
-    return solve_core(h, A, &L, &U, B, values, b, x, o, method, infos, s);
+    return solve_core(h, tune_of(p), A, &L, &U, B, values, b, x, o, method, infos, s);
 }
 
 // Eq. adjoint_linear: A^T lambda = gx, gb = lambda, gA = -lambda x^T on the
@@ -1357,7 +1372,7 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
         if (o.persistent && persistent_eligible(p, B, method, o))
             res = persistent_solve(h, p, B, values, gx, lam, o, infos, s);
         else
-            res = solve_core(h, A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s);
+            res = solve_core(h, tune_of(p), A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s);
     } else {
         if (hipMalloc((void **)&valT, sizeof(double) * (size_t)B * (p->nnz > 0 ? p->nnz : 1)) != hipSuccess) {
             if (lam_own) (void)hipFree(lam_own);
@@ -1368,7 +1383,7 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
         if (blocks > 8192) blocks = 8192;
         if (tot > 0) k_gather_values<<<blocks, kBlock, 0, s>>>(p->nnz, B, values, p->srcT, valT);
         const Pat AT = pat_T_of(p);
-        res = solve_core(h, AT, nullptr, nullptr, B, valT, gx, lam, o, method, infos, s);
+        res = solve_core(h, tune_of(p), AT, nullptr, nullptr, B, valT, gx, lam, o, method, infos, s);
     }
     if (res >= 0 && gA) {
         int Gr = (int)((n + kBlock - 1) / kBlock);
@@ -1384,12 +1399,114 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
     return res;
 }
 
+// Autotuner: times the solvers' SpMV forms and grid densities on the device
+// (synthetic values 1, x = 1) and keeps the fastest in the pattern.
+hsla_status autotune(hsla_handle *h, hsla_pattern *p, int B, int effort, hsla_tuning *out, hipStream_t s) {
+    const Pat A = pat_of(p);
+    const int64_t n = p->n, nnz = p->nnz;
+    const bool dia_ok = A.sn.mask != nullptr;
+    const size_t rows = dia_ok ? (size_t)dia_chunks(n) * kDiaChunk : 0;
+    const size_t nv = align_up(sizeof(double) * (size_t)B * (nnz > 0 ? nnz : 1), 256);
+    const size_t nx = align_up(sizeof(double) * (size_t)B * n, 256);
+    const size_t nd = dia_ok ? align_up(sizeof(double) * (size_t)B * A.sn.nofs * rows, 256) : 0;
+    hsla_status st = ensure_workspace(h, nv + 2 * nx + nd);
+    if (st != HSLA_OK) return st;
+    char *ws = (char *)h->ws;
+    double *val = (double *)ws, *x = (double *)(ws + nv), *y = (double *)(ws + nv + nx);
+    double *dia = dia_ok ? (double *)(ws + nv + 2 * nx) : nullptr;
+    k_fill_f64<<<4096, kBlock, 0, s>>>(val, (int64_t)B * nnz, 1.0);
+    k_fill_f64<<<4096, kBlock, 0, s>>>(x, (int64_t)B * n, 1.0);
+    if (dia_ok) {
+        const int Gv = grid_blocks(h, kBlock * 4, n, B, 8);
+        k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, nnz, val, dia);
+    }
+    HSLA_HIP(h, hipGetLastError());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HSLA_HIP(h, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_error(h, HSLA_ERR_HIP, "autotune: event creation failed");
+    }
+    auto time = [&](bool use_dia, int cu, double *us) -> hipError_t {
+        const int ns = (A.sn.nofs + 3) / 4 * 4;
+        const dim3 g(use_dia ? grid_blocks(h, kDiaChunk, n, B, cu) : grid_blocks(h, kWavesPerBlock, p->ntiles, B, cu),
+                     B);
+        for (int r = -1; r < effort; ++r) {
+            if (r == 0) {
+                const hipError_t e = hipEventRecord(e0, s);
+                if (e != hipSuccess) return e;
+            }
+            if (use_dia) {
+                NS_LAUNCH(k_spmv_dia, ns, g, A, dia, x, y);
+            } else {
+                k_spmv<<<g, kBlock, 0, s>>>(A, val, x, y);
+            }
+        }
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        *us = 1e3 * ms / effort;
+        return e;
+    };
+    struct Cand {
+        bool dia;
+        int cu;
+        double us;
+    };
+    std::vector<Cand> cands;
+    if (dia_ok)
+        for (int cu : {2, 4, 8, 16}) cands.push_back({true, cu, 0.0});
+    for (int cu : {4, 8, 16, 32}) cands.push_back({false, cu, 0.0});
+    hipError_t err = hipSuccess;
+    for (Cand &c : cands)
+        if (err == hipSuccess) err = time(c.dia, c.cu, &c.us);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return set_error(h, HSLA_ERR_HIP, "autotune: %s", hipGetErrorString(err));
+    const Cand *best = &cands[0], *best_tiles = nullptr, *dflt = nullptr;
+    for (const Cand &c : cands) {
+        if (c.us < best->us) best = &c;
+        if (!c.dia && (!best_tiles || c.us < best_tiles->us)) best_tiles = &c;
+        if (c.dia == dia_ok && c.cu == (dia_ok ? 8 : 16)) dflt = &c;
+    }
+    p->tune_dia = best->dia ? 1 : 0;
+    if (best->dia) p->tune_dia_cu = best->cu;
+    p->tune_tile_cu = best_tiles->cu;
+    p->tuned = 1;
+    if (out) {
+        out->form = best->dia ? 0 : 1;
+        out->blocks_per_cu = best->cu;
+        out->best_us = best->us;
+        out->default_us = dflt ? dflt->us : best->us;
+    }
+    return HSLA_OK;
+}
+
 }  // namespace hsla
 
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
+
+hsla_status hsla_autotune(hsla_handle *h, hsla_pattern *p, int32_t B, int32_t effort, hsla_tuning *out,
+                          void *stream) {
+    hsla_status st = hsla::check_common(h, p, B, (hipStream_t)stream);
+    if (st != HSLA_OK) return st;
+    if (B < 1 || B > 65535 || effort < 1 || effort > 100)
+        return hsla::set_error(h, HSLA_ERR_INVALID_ARG, "autotune needs 1 <= B <= 65535 and 1 <= effort <= 100");
+    if (p->n == 0) {
+        if (out) *out = hsla_tuning{p->stA.mask ? 0 : 1, 0, 0.0, 0.0};
+        return HSLA_OK;
+    }
+    st = hsla::autotune(h, p, B, effort, out, h->stream);
+    if (st != HSLA_OK) return st;
+    HSLA_HIP(h, hipStreamSynchronize(h->stream));
+    return HSLA_OK;
+}
+
 
 hsla_status hsla_spmv(hsla_handle *h, const hsla_pattern *p, int32_t B, const double *d_values, const double *d_x,
                       double *d_y, void *stream) {

@@ -64,7 +64,8 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_2601_13994_amd import _lib
 
     lines = []
-    for cname, mirror in (("hsla_opts", _lib.Opts), ("hsla_info", _lib.Info)):
+    structs = (("hsla_opts", _lib.Opts), ("hsla_info", _lib.Info), ("hsla_tuning", _lib.Tuning))
+    for cname, mirror in structs:
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
         for f, _ in mirror._fields_:
             lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
@@ -78,7 +79,7 @@ def test_struct_layout_matches_header(tmp_path):
     for line in filter(None, out):
         parts = line.split()
         got[tuple(parts[:-1])] = int(parts[-1])
-    for cname, mirror in (("hsla_opts", _lib.Opts), ("hsla_info", _lib.Info)):
+    for cname, mirror in structs:
         assert got[(cname, "size")] == ctypes.sizeof(mirror)
         for f, _ in mirror._fields_:
             assert got[(cname, f)] == getattr(mirror, f).offset, (cname, f)

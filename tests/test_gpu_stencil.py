@@ -135,3 +135,22 @@ def test_stencil_fsai(orc):
     _close(*res)
     ref = orc.fsai_pcg(a, rpL, colL, G.cpu().numpy().astype(np.float64), b, rtol=1e-12)
     assert rel(res[0][0].cpu().numpy(), ref.x) <= 1e-8
+
+
+def test_autotune_choice_applies(orc):
+    """The autotuner picks a measured configuration, and solves on the tuned
+    pattern still match the oracle."""
+    m = 24
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m))
+    pat = pattern(a)
+    t = pat.autotune(B=2, effort=3)
+    assert t["form"] in ("diagonal", "tiles") and t["blocks_per_cu"] in (2, 4, 8, 16, 32)
+    assert 0 < t["best_us"] <= t["default_us"]
+    b = np.random.default_rng(6).standard_normal(a.n)
+    x, infos, st = _lib.solve(pat, t64(a.val), t64(b),
+                              _lib.make_opts(method="cg", precond="jacobi", rtol=1e-12, persistent=False))
+    ref = orc.cg(a, b, precond="jacobi", rtol=1e-12)
+    assert st == 0 and rel(x.cpu().numpy(), ref.x) <= 1e-8
+    # a pattern without a stencil form is tuned among the row tiles only
+    q = W.random_spd(400, 0.03, np.random.default_rng(7))
+    assert pattern(q).autotune(B=1, effort=2)["form"] == "tiles"
