@@ -193,7 +193,7 @@ struct EpiHead {
             for (int nt = 0; nt < 2; ++nt) {
                 const int c = nt * 16 + i;
                 const float zz = rbf(fmaxf(acc[nt][tt] + c1[c], 0.f));
-                if (r < M) z[r * HEAD + c] = f2bf(zz);
+                if (z && r < M) z[r * HEAD + c] = f2bf(zz);
                 part += zz * H2[c];
             }
             // sum over the 16 lanes of this q (fixed butterfly)
@@ -203,7 +203,7 @@ struct EpiHead {
             part += __shfl_xor(part, 8, 16);
             if (i == 0 && r < M) {
                 const float tv = part + c2;
-                t[r] = tv;
+                if (t) t[r] = tv;
                 const bool d = isdiag[r % nL] != 0;
                 g[r] = d ? (tv > 20.f ? tv : log1pf(expf(tv))) : tv;
             }
@@ -272,15 +272,27 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(int64_t M, const uint16_t *_
     }
 }
 
-// dst[e] (+)= sum_b part[b][e] in block order; rows >= rows_valid of a
+// dst[e] (+)= sum_b part[b][e]: four running sums over b mod 4 (sixteen
+// loads in flight per step), combined as (s0 + s1) + (s2 + s3) -- a fixed
+// order, so the result is deterministic; rows >= rows_valid of a
 // [rows x cols] partial are dropped (padding of the head's K).
 __global__ void k_sum_partials(const float *__restrict__ part, int nb, int rows, int cols, int rows_valid,
                                float *__restrict__ dst, int accumulate) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= rows_valid * cols) return;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(size_t)b * rows * cols + e];
-    dst[e] = accumulate ? dst[e] + (float)s : (float)s;
+    const size_t stride = (size_t)rows * cols;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = 0;
+    for (; b + 16 <= nb; b += 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = part[(size_t)(b + u) * stride + e];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s[u & 3] += v[u];
+    }
+    for (; b < nb; ++b) s[b & 3] += part[(size_t)b * stride + e];
+    const double t = (s[0] + s[1]) + (s[2] + s[3]);
+    dst[e] = accumulate ? dst[e] + (float)t : (float)t;
 }
 
 // ---------------------------------------------------------------------------
@@ -354,50 +366,130 @@ __global__ __launch_bounds__(kBlock) void k_mp_init(Graph g, int B, const float 
     }
 }
 
-// m_i = sum_{k in row i} (f_k C_l) * h_{col k}.  One wave per node.
+// m_i = sum_{k in row i} (f_k C_l) * h_{col k}.  Four nodes per wave: 16
+// lanes per node, 4 channels per lane (one 8-byte load of h per neighbour);
+// a row's column indices, features and neighbour rows are loaded 8 entries
+// at a time, then summed in ascending entry order.
 __global__ __launch_bounds__(kBlock) void k_mp_aggregate(Graph g, int B, const float *__restrict__ C,
                                                          const float *__restrict__ ah, const uint16_t *__restrict__ h,
                                                          uint16_t *__restrict__ m) {
-    const int c = threadIdx.x & 63;
-    float Cc[4];
+    const int lane = threadIdx.x & 63;
+    const int c0 = (lane & 15) * 4;
+    float Cc[4][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) Cc[t] = C[t * HID + c];
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) Cc[t][u] = C[t * HID + c0 + u];
     const int64_t total = (int64_t)B * g.n;
-    for (int64_t node = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; node < total;
-         node += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t node = wave * 4 + (lane >> 4); node < total; node += nwaves * 4) {
         const int64_t s = node / g.n;
         const int32_t i = (int32_t)(node - s * g.n);
         const float *a = ah + s * g.nnz;
-        const uint16_t *hs = h + s * (int64_t)g.n * HID;
-        float acc = 0.f;
-        for (int32_t k = g.rp[i]; k < g.rp[i + 1]; ++k) {
-            float f[4];
-            feats(g, a, k, i, f);
-            const float gate = f[0] * Cc[0] + f[1] * Cc[1] + f[2] * Cc[2] + f[3] * Cc[3];
-            acc += gate * bf2f(hs[(int64_t)g.col[k] * HID + c]);
+        const uint16_t *hs = h + s * (int64_t)g.n * HID + c0;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        const int32_t lo = g.rp[i], hi = g.rp[i + 1];
+        for (int32_t k0 = lo; k0 < hi; k0 += 8) {
+            int32_t cj[8];
+            float av[8];
+            uint2 hv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                cj[u] = i;
+                av[u] = 0.f;
+                if (k0 + u < hi) {
+                    cj[u] = g.col[k0 + u];
+                    av[u] = a[k0 + u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < hi) hv[u] = *reinterpret_cast<const uint2 *>(hs + (int64_t)cj[u] * HID);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (k0 + u < hi) {
+                    const float f[4] = {av[u], cj[u] < i ? 1.f : 0.f, cj[u] > i ? 1.f : 0.f, cj[u] == i ? 1.f : 0.f};
+                    const uint16_t hb[4] = {(uint16_t)(hv[u].x & 0xffffu), (uint16_t)(hv[u].x >> 16),
+                                            (uint16_t)(hv[u].y & 0xffffu), (uint16_t)(hv[u].y >> 16)};
+#pragma unroll
+                    for (int ch = 0; ch < 4; ++ch) {
+                        const float gate = f[0] * Cc[0][ch] + f[1] * Cc[1][ch] + f[2] * Cc[2][ch] + f[3] * Cc[3][ch];
+                        acc[ch] += gate * bf2f(hb[ch]);
+                    }
+                }
+            }
         }
-        m[node * HID + c] = f2bf(acc);
+        uint2 out;
+        out.x = (uint32_t)f2bf(acc[0]) | ((uint32_t)f2bf(acc[1]) << 16);
+        out.y = (uint32_t)f2bf(acc[2]) | ((uint32_t)f2bf(acc[3]) << 16);
+        *reinterpret_cast<uint2 *>(m + node * HID + c0) = out;
     }
 }
 
-// Head inputs x_k = [h3_i, h3_j, f_k, 0...] (bf16, 144 wide) for lower entries.
+// Head inputs x_k = [h3_i, h3_j, f_k, 0...] (bf16, 144 wide) for lower
+// entries.  Four entries per wave, 16 lanes per entry, 8-byte copies.
 __global__ __launch_bounds__(kBlock) void k_mp_head_gather(Graph g, int B, const float *__restrict__ ah,
                                                            const uint16_t *__restrict__ h3, uint16_t *__restrict__ X) {
-    const int c = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
+    const int l16 = lane & 15;
     const int64_t total = (int64_t)B * g.nL;
-    for (int64_t e = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; e < total;
-         e += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t e = wave * 4 + (lane >> 4); e < total; e += nwaves * 4) {
         const int64_t s = e / g.nL, kl = e - s * g.nL;
         const int32_t i = g.rowL[kl], j = g.colL[kl];
-        const uint16_t *hs = h3 + s * (int64_t)g.n * HID;
+        const uint16_t *hs = h3 + s * (int64_t)g.n * HID + l16 * 4;
         uint16_t *x = X + e * KHP;
-        x[c] = hs[(int64_t)i * HID + c];
-        x[HID + c] = hs[(int64_t)j * HID + c];
-        if (c < KHP - 2 * HID) {
+        const uint2 vi = *reinterpret_cast<const uint2 *>(hs + (int64_t)i * HID);
+        const uint2 vj = *reinterpret_cast<const uint2 *>(hs + (int64_t)j * HID);
+        *reinterpret_cast<uint2 *>(x + l16 * 4) = vi;
+        *reinterpret_cast<uint2 *>(x + HID + l16 * 4) = vj;
+        float f[4];
+        feats(g, ah + s * g.nnz, g.posL[kl], i, f);
+        x[2 * HID + l16] = l16 < NF ? f2bf(f[l16 < NF ? l16 : 0]) : (uint16_t)0;
+    }
+}
+
+// Inference head without the x_k buffer: the GEMM's A operand is fetched
+// straight from h3 (rows i and j of the entry) and the features, giving the
+// same bf16 operand values as k_mp_head_gather + k_gemm<9, 2>.
+__global__ __launch_bounds__(kBlock) void k_mp_head_fused(Graph g, int64_t M, const float *__restrict__ ah,
+                                                          const uint16_t *__restrict__ h3,
+                                                          const uint16_t *__restrict__ Bf, EpiHead epi) {
+    const int lane = threadIdx.x & 63, i = lane & 15, q = lane >> 4;
+    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; tile * 16 < M; tile += waves) {
+        const int64_t row0 = tile * 16;
+        int64_t ra = row0 + i;
+        if (ra >= M) ra = M - 1;
+        const int64_t s = ra / g.nL, kl = ra - s * g.nL;
+        const int32_t ni = g.rowL[kl], nj = g.colL[kl];
+        const uint16_t *hs = h3 + s * (int64_t)g.n * HID + 4 * q;
+        short4_t fa = short4_t{0, 0, 0, 0};
+        if (q == 0) {
             float f[4];
-            feats(g, ah + s * g.nnz, g.posL[kl], i, f);
-            x[2 * HID + c] = c < NF ? f2bf(f[c]) : (uint16_t)0;
+            feats(g, ah + s * g.nnz, g.posL[kl], ni, f);
+            fa = short4_t{(short)f2bf(f[0]), (short)f2bf(f[1]), (short)f2bf(f[2]), (short)f2bf(f[3])};
         }
+        float4_t acc[2];
+        acc[0] = acc[1] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 9; ++ks) {
+            short4_t a;
+            if (ks < 4)
+                a = *reinterpret_cast<const short4_t *>(hs + (int64_t)ni * HID + ks * 16);
+            else if (ks < 8)
+                a = *reinterpret_cast<const short4_t *>(hs + (int64_t)nj * HID + (ks - 4) * 16);
+            else
+                a = fa;
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const short4_t b = *reinterpret_cast<const short4_t *>(Bf + ((size_t)(ks * 2 + nt) * 64 + lane) * 4);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+            }
+        }
+        epi(row0, q, i, acc);
     }
 }
 
@@ -817,20 +909,28 @@ static hsla_status forward(hsla_handle *h, const hsla_pattern *p, int B, const d
     k_mp_weights<<<64, kBlock, 0, s>>>(params, f.w);
     k_mp_scale<<<nblocks(B * n, kBlock, 8192), kBlock, 0, s>>>(g, B, values, f.ah64, f.ah32, f.bad);
     const int gw = nblocks(B * n, kWavesPerBlock, 16384);
+    const int ga = nblocks(B * n, 4 * kWavesPerBlock, 16384);
     k_mp_init<<<gw, kBlock, 0, s>>>(g, B, f.w.wq, f.ah32, f.h[0]);
     for (int l = 1; l <= LAYERS; ++l) {
-        k_mp_aggregate<<<gw, kBlock, 0, s>>>(g, B, f.w.wq + off_layer(l) + L_C, f.ah32, f.h[l - 1], f.m[l - 1]);
+        k_mp_aggregate<<<ga, kBlock, 0, s>>>(g, B, f.w.wq + off_layer(l) + L_C, f.ah32, f.h[l - 1], f.m[l - 1]);
         const int64_t M = B * n;
         EpiBiasReluBf16<4> epi{f.w.wq + off_layer(l) + L_B, f.h[l], M};
         k_gemm<8, 4><<<nblocks((M + 15) / 16, kWavesPerBlock, 8192), kBlock, 0, s>>>(
             M, f.h[l - 1], HID, f.m[l - 1], HID, HID, f.w.Wf[l - 1], epi);
     }
-    k_mp_head_gather<<<nblocks(B * nL, kWavesPerBlock, 16384), kBlock, 0, s>>>(g, B, f.ah32, f.h[LAYERS], f.X);
-    {
+    if (keep) {
+        // training: keep x_k, z and t for the backward
+        k_mp_head_gather<<<nblocks(B * nL, 4 * kWavesPerBlock, 16384), kBlock, 0, s>>>(g, B, f.ah32, f.h[LAYERS],
+                                                                                        f.X);
         const int64_t M = B * nL;
         EpiHead epi{f.w.wq, f.z, f.t, Ghat, p->isdiagL, nL, M};
         k_gemm<9, 2><<<nblocks((M + 15) / 16, kWavesPerBlock, 8192), kBlock, 0, s>>>(M, f.X, KHP, f.X, KHP, KHP,
                                                                                    f.w.H1f, epi);
+    } else {
+        const int64_t M = B * nL;
+        EpiHead epi{f.w.wq, nullptr, nullptr, Ghat, p->isdiagL, nL, M};
+        k_mp_head_fused<<<nblocks((M + 15) / 16, kWavesPerBlock, 8192), kBlock, 0, s>>>(g, M, f.ah32, f.h[LAYERS],
+                                                                                        f.w.H1f, epi);
     }
     HSLA_HIP(h, hipGetLastError());
     int32_t bad = 0;
