@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 
 #include "hsla.h"
 
@@ -28,6 +29,7 @@ struct Stencil {
     const uint16_t *mask = nullptr;
     int32_t nofs = 0;
     int32_t ofs[kMaxOffsets] = {};
+    int32_t diag_slot = -1;  // s with ofs[s] == 0, -1 if none
 };
 
 // Per-system solver state (device memory, one record per system).
@@ -532,20 +534,32 @@ struct ChunkWalk {
     }
 };
 
+// Slot count of the diagonal-major SpMV for a pattern with nofs diagonals:
+// the common stencil widths 5, 7 and 9 get exact instantiations (every
+// diagonal's loads issued together), others round up to a multiple of 4.
+__host__ __device__ inline int dia_slots_for(int nofs) {
+    return (nofs == 5 || nofs == 7 || nofs == 9) ? nofs : (nofs + 3) / 4 * 4;
+}
+
 // SpMV on the chunked diagonal-major copy of the values (see kDiaChunk).
 // A block takes one chunk of 512 rows per step, each thread two rows 256
 // apart; each row adds its present products in ascending diagonal order,
 // which is ascending column order, with products rounded before the add (no
 // contraction), so the result equals the CSR and tile forms bit for bit.
-// NS (a multiple of 4, >= nofs) is the unrolled slot count: slots past nofs
-// reload the last diagonal and are masked out.  epi(row, y) per row.
+// NS is the slot count: exactly nofs for 5, 7 and 9 diagonals, otherwise a
+// multiple of 4 >= nofs whose slots past nofs reload the last diagonal and
+// are masked out.  epi(row, y) per row, or epi(row, y, x_row) when the
+// epilogue takes x of its own row too (it is the diagonal slot's gathered
+// value: absent entries gather the row's own x).
 template <int NS, typename VT, class Epi>
 __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                          const double *__restrict__ x, Epi &&epi) {
 #pragma clang fp contract(off)
+    constexpr bool kExact = NS == 5 || NS == 7 || NS == 9;
+    constexpr int kGroup = kExact ? NS : 4;
     const ChunkWalk cw(dia_chunks(n));
     const uint16_t *__restrict__ mask = sn.mask;
-    const int nofs = sn.nofs;
+    const int nofs = kExact ? NS : sn.nofs;
     for (int64_t c = cw.first; c < cw.hi; c += cw.stride) {
         const int64_t i = c * kDiaChunk + threadIdx.x;
         const int64_t i2 = i + kBlock;
@@ -555,14 +569,16 @@ __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict
         const uint32_t m2 = two ? (uint32_t)mask[i2] : 0u;
         const VT *__restrict__ base = dv + c * nofs * kDiaChunk + threadIdx.x;
         double a1 = 0.0, a2 = 0.0;
+        double c1 = 0.0, c2 = 0.0;  // x of the rows themselves
+        const int ds = sn.diag_slot;
 #pragma unroll
-        for (int g = 0; g < NS; g += 4) {
-            if (g < nofs) {
-                VT v1[4], v2[4];
-                double x1[4], x2[4];
+        for (int g = 0; g < NS; g += kGroup) {
+            if (kExact || g < nofs) {
+                VT v1[kGroup], v2[kGroup];
+                double x1[kGroup], x2[kGroup];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int s = g + u < nofs ? g + u : nofs - 1;
+                for (int u = 0; u < kGroup; ++u) {
+                    const int s = kExact ? g + u : (g + u < nofs ? g + u : nofs - 1);
                     const int64_t d = sn.ofs[s];
                     const bool o1 = (m1 >> (g + u)) & 1u, o2 = (m2 >> (g + u)) & 1u;
                     v1[u] = __builtin_nontemporal_load(&base[s * kDiaChunk]);
@@ -571,16 +587,29 @@ __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict
                     x2[u] = x[o2 ? i2 + d : j2];
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < kGroup; ++u) {
                     const double p1 = (double)v1[u] * x1[u];
                     const double p2 = (double)v2[u] * x2[u];
                     if ((m1 >> (g + u)) & 1u) a1 = a1 + p1;
                     if ((m2 >> (g + u)) & 1u) a2 = a2 + p2;
+                    if (g + u == ds) {
+                        c1 = x1[u];
+                        c2 = x2[u];
+                    }
                 }
             }
         }
-        if (one) epi(i, a1);
-        if (two) epi(i2, a2);
+        if constexpr (std::is_invocable_v<Epi, int64_t, double, double>) {
+            if (ds < 0) {
+                c1 = x[j1];
+                c2 = x[j2];
+            }
+            if (one) epi(i, a1, c1);
+            if (two) epi(i2, a2, c2);
+        } else {
+            if (one) epi(i, a1);
+            if (two) epi(i2, a2);
+        }
     }
 }
 

@@ -251,11 +251,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(Pat A, Sys S) {
     const double *p = S.p + vo;
     double *q = S.q + vo;
     double acc[1] = {0.0};
-    spmv_A<NS>(A, S, sidx, p, lds[threadIdx.x / kWave],
-               [&](int64_t row, double yv) {
-                   q[row] = yv;
-                   acc[0] += p[row] * yv;
-               });
+    if constexpr (NS > 0) {
+        // p of the row itself comes with the SpMV's gathers
+        spmv_dia<NS>(A.sn, S.dia + (int64_t)sidx * A.sn.nofs * dia_chunks(A.n) * kDiaChunk, (int64_t)A.n, p,
+                     [&](int64_t row, double yv, double prow) {
+                         q[row] = yv;
+                         acc[0] += prow * yv;
+                     });
+    } else {
+        spmv_tiles(A.rp, A.col, A.sn, S.val + (int64_t)sidx * A.nnz, p, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+                   [&](int64_t row, double yv) {
+                       q[row] = yv;
+                       acc[0] += p[row] * yv;
+                   });
+    }
     block_partial<1>(acc, part);
 }
 
@@ -887,7 +896,10 @@ __global__ __launch_bounds__(kBlock) void k_fill_f64(double *__restrict__ a, int
     switch (ns) {                                                         \
         case 0: K<0><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;         \
         case 4: K<4><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;         \
+        case 5: K<5><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;         \
+        case 7: K<7><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;         \
         case 8: K<8><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;         \
+        case 9: K<9><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;         \
         case 12: K<12><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;       \
         default: K<16><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;       \
     }
@@ -897,7 +909,7 @@ hsla_status launch_spmv(hsla_handle *h, const hsla_pattern *p, int B, const doub
     if (p->n == 0 || B == 0) return HSLA_OK;
     const Pat A = pat_of(p);
     if (p->format == HSLA_FORMAT_DIAGONAL && A.sn.mask) {
-        const int ns = (A.sn.nofs + 3) / 4 * 4;
+        const int ns = dia_slots_for(A.sn.nofs);
         const size_t rows = (size_t)dia_chunks(A.n) * kDiaChunk;
         const hsla_status st = ensure_workspace(h, sizeof(double) * (size_t)B * A.sn.nofs * rows);
         if (st != HSLA_OK) return st;
@@ -1083,7 +1095,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
     // the autotuner found the row tiles faster
     // (the tuning covers A's SpMV; the FSAI factors always use their
     // diagonal-major copies where they have one)
-    auto dia_slots = [](const Stencil &sn) { return sn.mask ? (sn.nofs + 3) / 4 * 4 : 0; };
+    auto dia_slots = [](const Stencil &sn) { return sn.mask ? dia_slots_for(sn.nofs) : 0; };
     const int nsA = tn.dia ? dia_slots(A.sn) : 0;
     const bool fsai = pre == PRE_FSAI && L && U;
     const int nsF = fsai && L->sn.mask && U->sn.mask ? std::max(dia_slots(L->sn), dia_slots(U->sn)) : 0;
@@ -1428,7 +1440,7 @@ hsla_status autotune(hsla_handle *h, hsla_pattern *p, int B, int effort, hsla_tu
         return set_error(h, HSLA_ERR_HIP, "autotune: event creation failed");
     }
     auto time = [&](bool use_dia, int cu, double *us) -> hipError_t {
-        const int ns = (A.sn.nofs + 3) / 4 * 4;
+        const int ns = dia_slots_for(A.sn.nofs);
         const dim3 g(use_dia ? grid_blocks(h, kDiaChunk, n, B, cu) : grid_blocks(h, kWavesPerBlock, p->ntiles, B, cu),
                      B);
         for (int r = -1; r < effort; ++r) {

@@ -409,7 +409,10 @@ static hsla_status build_stencil(hsla_handle *h, int32_t n, int64_t nnz, const s
     std::sort(ofs.begin(), ofs.end());
     Stencil st{};
     st.nofs = (int32_t)ofs.size();
-    for (int j = 0; j < st.nofs; ++j) st.ofs[j] = (int32_t)ofs[j];
+    for (int j = 0; j < st.nofs; ++j) {
+        st.ofs[j] = (int32_t)ofs[j];
+        if (ofs[j] == 0) st.diag_slot = j;
+    }
     uint16_t *mask = nullptr;
     int32_t *bad = nullptr;
     int32_t hbad = 0;
