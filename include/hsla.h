@@ -94,6 +94,26 @@ hsla_status hsla_create(hsla_handle **out, int device);
 void hsla_destroy(hsla_handle *h);
 const char *hsla_last_error(const hsla_handle *h);
 
+/* Device memory of the handle's workspaces (solver vectors and partials,
+ * per-solve diagonal-major copies, network activations, adjoint
+ * temporaries).  By default the library calls hipMalloc/hipFree; with an
+ * allocator set, it calls alloc(bytes, ctx) (which must return device memory
+ * on the handle's device aligned to 256 bytes, or NULL) and free(ptr, ctx),
+ * e.g. a framework's caching allocator.  Setting it releases the handle's
+ * current workspaces first (after waiting for the device).  alloc and free
+ * are both NULL (back to hipMalloc) or both set.  Pattern buffers are
+ * allocated with hipMalloc at pattern creation. */
+typedef void *(*hsla_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*hsla_free_fn)(void *ptr, void *ctx);
+hsla_status hsla_set_allocator(hsla_handle *h, hsla_alloc_fn alloc, hsla_free_fn free, void *ctx);
+/* Workspace bytes a solve of B systems on `p` with `opts` (NULL: defaults)
+ * takes from the handle (AUTO method: the larger of CG and BiCGStab), and
+ * hsla_reserve grows the workspace to at least `bytes` now, so that later
+ * calls needing no more than that allocate nothing for it. */
+hsla_status hsla_workspace_size(hsla_handle *h, const hsla_pattern *p, int32_t B, const hsla_opts *opts,
+                                size_t *bytes);
+hsla_status hsla_reserve(hsla_handle *h, size_t bytes);
+
 /* --------------------------------------------------------------- pattern */
 /* Validates and copies a CSR sparsity pattern (row_ptr int32[n+1], col
  * int32[nnz], device memory) and derives the per-pattern data every solve

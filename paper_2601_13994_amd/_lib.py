@@ -28,6 +28,7 @@ FORMATS = {"auto": 0, "csr": 1, "diagonal": 2}
 # every symbol include/hsla.h declares
 EXPORTS = [
     "hsla_opts_default", "hsla_status_string", "hsla_create", "hsla_destroy", "hsla_last_error",
+    "hsla_set_allocator", "hsla_workspace_size", "hsla_reserve",
     "hsla_pattern_create", "hsla_pattern_destroy", "hsla_pattern_info", "hsla_pattern_set_format",
     "hsla_pattern_format", "hsla_autotune", "hsla_pattern_transpose",
     "hsla_spmv", "hsla_solve", "hsla_solve_batched", "hsla_adjoint", "hsla_adjoint_batched",
@@ -66,6 +67,11 @@ class Info(ctypes.Structure):
                 "spmv_ms": self.spmv_ms, "spmv_launches": self.spmv_launches}
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocators = {}  # device index -> (alloc, free) callbacks kept alive
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("best_us", ctypes.c_double), ("default_us", ctypes.c_double)]
@@ -98,6 +104,9 @@ def load() -> ctypes.CDLL:
         L.hsla_destroy.restype = None
         L.hsla_last_error.argtypes = [vp]
         L.hsla_last_error.restype = ctypes.c_char_p
+        L.hsla_set_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp]
+        L.hsla_workspace_size.argtypes = [vp, vp, i32, P(Opts), P(ctypes.c_size_t)]
+        L.hsla_reserve.argtypes = [vp, ctypes.c_size_t]
         L.hsla_pattern_create.argtypes = [vp, i32, i64, vp, vp, vp, P(vp)]
         L.hsla_pattern_destroy.argtypes = [vp]
         L.hsla_pattern_destroy.restype = None
@@ -154,6 +163,52 @@ def check(st: int, h, what: str, warn_ok: bool = True) -> int:
 
 def stream_ptr(device=None) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def use_torch_allocator(device=None, enable: bool = True, counter: dict | None = None) -> None:
+    """Route the handle's workspaces on `device` through torch's caching
+    allocator (enable=False restores hipMalloc).  `counter`, if given, counts
+    the allocator calls (keys 'alloc', 'free')."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    if not enable:
+        st = load().hsla_set_allocator(handle(idx), ALLOC_FN(), FREE_FN(), None)
+        check(st, handle(idx), "hsla_set_allocator")
+        _allocators.pop(idx, None)
+        return
+
+    def _alloc(nbytes, ctx):
+        if counter is not None:
+            counter["alloc"] = counter.get("alloc", 0) + 1
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=idx)
+        except RuntimeError:
+            return None
+
+    def _free(p, ctx):
+        if counter is not None:
+            counter["free"] = counter.get("free", 0) + 1
+        torch.cuda.caching_allocator_delete(p)
+
+    cbs = (ALLOC_FN(_alloc), FREE_FN(_free))
+    st = load().hsla_set_allocator(handle(idx), cbs[0], cbs[1], None)
+    check(st, handle(idx), "hsla_set_allocator")
+    _allocators[idx] = cbs
+
+
+def workspace_size(pat: "Pattern", B: int = 1, opts: "Opts | None" = None) -> int:
+    n = ctypes.c_size_t()
+    st = load().hsla_workspace_size(pat.h, pat.p, int(B), ctypes.byref(opts) if opts is not None else None,
+                                    ctypes.byref(n))
+    check(st, pat.h, "hsla_workspace_size")
+    return n.value
+
+
+def reserve(nbytes: int, device=None) -> None:
+    idx = torch.device(device).index if device is not None else torch.cuda.current_device()
+    with torch.cuda.device(idx):
+        st = load().hsla_reserve(handle(idx), int(nbytes))
+        check(st, handle(idx), "hsla_reserve")
 
 
 def ptr(t: torch.Tensor | None) -> ctypes.c_void_p:

@@ -124,6 +124,10 @@ struct hsla_handle {
     const hsla_pattern *mp_keep_pattern = nullptr;
     void *pr_ws = nullptr;
     size_t pr_ws_bytes = 0;
+    // workspace allocator (hsla_set_allocator); hipMalloc/hipFree when unset
+    hsla_alloc_fn alloc_fn = nullptr;
+    hsla_free_fn free_fn = nullptr;
+    void *alloc_ctx = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -146,6 +150,9 @@ hsla_status enter(hsla_handle *h, hipStream_t user);
 
 // Grows the handle's workspace to at least `bytes` (contents not preserved).
 hsla_status ensure_workspace(hsla_handle *h, size_t bytes);
+// Workspace memory through the handle's allocator (hipMalloc when unset).
+hipError_t dev_alloc(hsla_handle *h, void **p, size_t bytes);
+void dev_free(hsla_handle *h, void *p);
 hsla_status ensure_host_state(hsla_handle *h, size_t nsys);
 
 // Blocks per system for grid-stride kernels: enough for `units` work items

@@ -1077,6 +1077,44 @@ struct Tune {
 
 static Tune tune_of(const hsla_pattern *p) { return Tune{p->tune_dia, p->tune_tile_cu, p->tune_dia_cu}; }
 
+// Grid sizes, SpMV forms and workspace layout of one solve.
+struct Plan {
+    int nvec, Gt, Gv, nsA, nsF, Gd, Gs, Gf;
+    size_t diaA, diaL, diaU;
+    Layout lay;
+};
+
+static Plan plan_solve(hsla_handle *h, const Tune &tn, const Pat &A, const FPat *L, const FPat *U, int B, int method,
+                       int pre) {
+    Plan pl{};
+    const int64_t n = A.n;
+    pl.nvec = method == HSLA_METHOD_CG ? 6 : 10;
+    // SpMV-based kernels: up to 16 blocks per CU; vector kernels: up to 8,
+    // shared by the systems of a batch (fewer, longer-running blocks each)
+    pl.Gt = grid_blocks(h, kWavesPerBlock, A.ntiles, B, tn.tile_cu);
+    pl.Gv = grid_blocks(h, kBlock * 4, n, B, 8);
+    // offset-mask patterns run their SpMVs on diagonal-major copies of the
+    // values made once per solve (row per thread, two rows per step) unless
+    // the autotuner found the row tiles faster (the tuning covers A's SpMV;
+    // the FSAI factors always use their diagonal-major copies where they
+    // have one)
+    auto dia_slots = [](const Stencil &sn) { return sn.mask ? dia_slots_for(sn.nofs) : 0; };
+    pl.nsA = tn.dia ? dia_slots(A.sn) : 0;
+    const bool fsai = pre == PRE_FSAI && L && U;
+    pl.nsF = fsai && L->sn.mask && U->sn.mask ? std::max(dia_slots(L->sn), dia_slots(U->sn)) : 0;
+    pl.Gd = grid_blocks(h, kDiaChunk, n, B, tn.dia_cu);
+    pl.Gs = pl.nsA ? pl.Gd : pl.Gt;
+    pl.Gf = pl.nsF ? grid_blocks(h, kDiaChunk, n, B, 8) : pl.Gt;
+    const size_t drows = (size_t)dia_chunks(n) * kDiaChunk;
+    pl.diaA = pl.nsA ? sizeof(double) * (size_t)B * A.sn.nofs * drows : 0;
+    pl.diaL = pl.nsF ? sizeof(float) * (size_t)B * L->sn.nofs * drows : 0;
+    pl.diaU = pl.nsF ? sizeof(float) * (size_t)B * U->sn.nofs * drows : 0;
+    const size_t extra = align_up(pl.diaA, 256) + align_up(pl.diaL, 256) + align_up(pl.diaU, 256);
+    const int Gmax = std::max(std::max(pl.Gt, pl.Gv), std::max(pl.Gd, pl.Gf));
+    pl.lay = make_layout(B, n, pl.nvec, Gmax, extra);
+    return pl;
+}
+
 static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, const FPat *L, const FPat *U, int B,
                               const double *values,
                               const double *b, double *x, const hsla_opts &o, int method, hsla_info *infos,
@@ -1085,29 +1123,10 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
     const int pre = o.precond == HSLA_PRECOND_NONE ? PRE_NONE : o.precond == HSLA_PRECOND_FSAI ? PRE_FSAI : PRE_JACOBI;
     if (method == HSLA_METHOD_BICGSTAB && pre == PRE_FSAI)
         return set_error(h, HSLA_ERR_INVALID_ARG, "FSAI preconditioning is for CG only");
-    const int nvec = method == HSLA_METHOD_CG ? 6 : 10;
-    // SpMV-based kernels: up to 16 blocks per CU; vector kernels: up to 8,
-    // shared by the systems of a batch (fewer, longer-running blocks each)
-    const int Gt = grid_blocks(h, kWavesPerBlock, A.ntiles, B, tn.tile_cu);
-    const int Gv = grid_blocks(h, kBlock * 4, n, B, 8);
-    // offset-mask patterns run their SpMVs on diagonal-major copies of the
-    // values made once per solve (row per thread, two rows per step) unless
-    // the autotuner found the row tiles faster
-    // (the tuning covers A's SpMV; the FSAI factors always use their
-    // diagonal-major copies where they have one)
-    auto dia_slots = [](const Stencil &sn) { return sn.mask ? dia_slots_for(sn.nofs) : 0; };
-    const int nsA = tn.dia ? dia_slots(A.sn) : 0;
-    const bool fsai = pre == PRE_FSAI && L && U;
-    const int nsF = fsai && L->sn.mask && U->sn.mask ? std::max(dia_slots(L->sn), dia_slots(U->sn)) : 0;
-    const int Gd = grid_blocks(h, kDiaChunk, n, B, tn.dia_cu);
-    const int Gs = nsA ? Gd : Gt, Gf = nsF ? grid_blocks(h, kDiaChunk, n, B, 8) : Gt;
-    const size_t drows = (size_t)dia_chunks(n) * kDiaChunk;
-    const size_t diaA = nsA ? sizeof(double) * (size_t)B * A.sn.nofs * drows : 0;
-    const size_t diaL = nsF ? sizeof(float) * (size_t)B * L->sn.nofs * drows : 0;
-    const size_t diaU = nsF ? sizeof(float) * (size_t)B * U->sn.nofs * drows : 0;
-    const size_t extra = align_up(diaA, 256) + align_up(diaL, 256) + align_up(diaU, 256);
-    const int Gmax = std::max(std::max(Gt, Gv), std::max(Gd, Gf));
-    const Layout lay = make_layout(B, n, nvec, Gmax, extra);
+    const Plan pl = plan_solve(h, tn, A, L, U, B, method, pre);
+    const int nvec = pl.nvec, Gt = pl.Gt, Gv = pl.Gv, nsA = pl.nsA, nsF = pl.nsF, Gs = pl.Gs, Gf = pl.Gf;
+    const size_t diaA = pl.diaA, diaL = pl.diaL;
+    const Layout lay = pl.lay;
     hsla_status st = ensure_workspace(h, lay.total);
     if (st != HSLA_OK) return st;
     st = ensure_host_state(h, B);
@@ -1375,7 +1394,7 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
     const int64_t n = p->n;
     double *lam = gb, *lam_own = nullptr, *valT = nullptr;
     if (!lam) {
-        HSLA_HIP(h, hipMalloc((void **)&lam_own, sizeof(double) * (size_t)B * n));
+        HSLA_HIP(h, dev_alloc(h, (void **)&lam_own, sizeof(double) * (size_t)B * n));
         lam = lam_own;
     }
     hsla_status res;
@@ -1386,8 +1405,8 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
         else
             res = solve_core(h, tune_of(p), A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s);
     } else {
-        if (hipMalloc((void **)&valT, sizeof(double) * (size_t)B * (p->nnz > 0 ? p->nnz : 1)) != hipSuccess) {
-            if (lam_own) (void)hipFree(lam_own);
+        if (dev_alloc(h, (void **)&valT, sizeof(double) * (size_t)B * (p->nnz > 0 ? p->nnz : 1)) != hipSuccess) {
+            dev_free(h, lam_own);
             return set_error(h, HSLA_ERR_NO_MEMORY, "transposed values");
         }
         const int64_t tot = p->nnz * B;
@@ -1405,10 +1424,29 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
         if (e != hipSuccess) res = set_error(h, HSLA_ERR_HIP, "outer product: %s", hipGetErrorString(e));
     }
     const hipError_t se = hipStreamSynchronize(s);
-    if (valT) (void)hipFree(valT);
-    if (lam_own) (void)hipFree(lam_own);
+    dev_free(h, valT);
+    dev_free(h, lam_own);
     if (se != hipSuccess) return set_error(h, HSLA_ERR_HIP, "adjoint: %s", hipGetErrorString(se));
     return res;
+}
+
+// Workspace bytes of a solve (hsla_workspace_size).
+hsla_status workspace_size(hsla_handle *h, const hsla_pattern *p, int B, const hsla_opts &o, size_t *bytes) {
+    const Pat A = pat_of(p);
+    const int pre = o.precond == HSLA_PRECOND_NONE ? PRE_NONE : o.precond == HSLA_PRECOND_FSAI ? PRE_FSAI : PRE_JACOBI;
+    FPat L{p->rpL, p->colL, p->metaL, p->ntilesL, p->nnz_lower, nullptr, p->use(p->stL)};
+    FPat U{p->rpU, p->colU, p->metaU, p->ntilesU, p->nnz_lower, nullptr, p->use(p->stU)};
+    size_t need = 0;
+    for (int method : {HSLA_METHOD_CG, HSLA_METHOD_BICGSTAB}) {
+        if (o.method != HSLA_METHOD_AUTO && o.method != method) continue;
+        if (method == HSLA_METHOD_BICGSTAB && pre == PRE_FSAI) continue;
+        const Plan pl = plan_solve(h, tune_of(p), A, &L, &U, B, method, pre);
+        need = std::max(need, pl.lay.total);
+        if (o.persistent && persistent_eligible(p, B, method, o))
+            need = std::max(need, sizeof(double) * 4 * (size_t)B * p->n + 1024 + 40 * (size_t)B);
+    }
+    *bytes = need + need / 8 + 4096;  // the growth margin ensure_workspace adds
+    return HSLA_OK;
 }
 
 // Autotuner: times the solvers' SpMV forms and grid densities on the device
@@ -1502,6 +1540,18 @@ hsla_status autotune(hsla_handle *h, hsla_pattern *p, int B, int effort, hsla_tu
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
+
+hsla_status hsla_workspace_size(hsla_handle *h, const hsla_pattern *p, int32_t B, const hsla_opts *opts,
+                                size_t *bytes) {
+    if (!h || !p || !bytes) return HSLA_ERR_INVALID_ARG;
+    if (B < 0) return hsla::set_error(h, HSLA_ERR_INVALID_ARG, "negative batch");
+    hsla_opts o;
+    if (opts)
+        o = *opts;
+    else
+        hsla_opts_default(&o);
+    return hsla::workspace_size(h, p, B, o, bytes);
+}
 
 hsla_status hsla_autotune(hsla_handle *h, hsla_pattern *p, int32_t B, int32_t effort, hsla_tuning *out,
                           void *stream) {

@@ -840,14 +840,14 @@ static hsla_status ensure_mp_ws(hsla_handle *h, size_t bytes) {
     if (bytes <= h->mp_ws_bytes) return HSLA_OK;
     if (h->mp_ws) {
         HSLA_HIP(h, hipStreamSynchronize(h->stream));
-        HSLA_HIP(h, hipFree(h->mp_ws));
+        dev_free(h, h->mp_ws);
         h->mp_ws = nullptr;
         h->mp_ws_bytes = 0;
         h->mp_keep_B = 0;
         h->mp_keep_pattern = nullptr;
     }
     const size_t want = bytes + bytes / 8 + 4096;
-    if (hipMalloc(&h->mp_ws, want) != hipSuccess) {
+    if (dev_alloc(h, &h->mp_ws, want) != hipSuccess) {
         h->mp_ws = nullptr;
         return set_error(h, HSLA_ERR_NO_MEMORY, "network workspace of %zu bytes", want);
     }
@@ -998,12 +998,12 @@ static hsla_status ensure_pr_ws(hsla_handle *h, size_t bytes) {
     if (bytes <= h->pr_ws_bytes) return HSLA_OK;
     if (h->pr_ws) {
         HSLA_HIP(h, hipStreamSynchronize(h->stream));
-        HSLA_HIP(h, hipFree(h->pr_ws));
+        dev_free(h, h->pr_ws);
         h->pr_ws = nullptr;
         h->pr_ws_bytes = 0;
     }
     const size_t want = bytes + bytes / 8 + 4096;
-    if (hipMalloc(&h->pr_ws, want) != hipSuccess) {
+    if (dev_alloc(h, &h->pr_ws, want) != hipSuccess) {
         h->pr_ws = nullptr;
         return set_error(h, HSLA_ERR_NO_MEMORY, "probe workspace of %zu bytes", want);
     }

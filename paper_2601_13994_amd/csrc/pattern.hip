@@ -21,11 +21,27 @@ hsla_status set_error(hsla_handle *h, hsla_status st, const char *fmt, ...) {
     return st;
 }
 
+hipError_t dev_alloc(hsla_handle *h, void **p, size_t bytes) {
+    if (h->alloc_fn) {
+        *p = h->alloc_fn(bytes, h->alloc_ctx);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+void dev_free(hsla_handle *h, void *p) {
+    if (!p) return;
+    if (h->free_fn)
+        h->free_fn(p, h->alloc_ctx);
+    else
+        (void)hipFree(p);
+}
+
 hsla_status ensure_workspace(hsla_handle *h, size_t bytes) {
     if (bytes <= h->ws_bytes) return HSLA_OK;
     if (h->ws) {
         HSLA_HIP(h, hipDeviceSynchronize());
-        HSLA_HIP(h, hipFree(h->ws));
+        dev_free(h, h->ws);
         h->ws = nullptr;
         h->ws_bytes = 0;
         for (int i = 0; i < hsla_handle::kGraphCache; ++i) {
@@ -35,7 +51,7 @@ hsla_status ensure_workspace(hsla_handle *h, size_t bytes) {
         }
     }
     size_t want = bytes + bytes / 8 + 4096;
-    hipError_t e = hipMalloc(&h->ws, want);
+    hipError_t e = dev_alloc(h, &h->ws, want);
     if (e != hipSuccess) {
         h->ws = nullptr;
         return set_error(h, HSLA_ERR_NO_MEMORY, "workspace of %zu bytes: %s", want, hipGetErrorString(e));
@@ -628,11 +644,11 @@ void hsla_destroy(hsla_handle *h) {
     (void)hipDeviceSynchronize();
     for (int i = 0; i < hsla_handle::kGraphCache; ++i)
         if (h->graph_exec[i]) (void)hipGraphExecDestroy(h->graph_exec[i]);
-    if (h->ws) (void)hipFree(h->ws);
+    hsla::dev_free(h, h->ws);
     if (h->h_state) (void)hipHostFree(h->h_state);
     if (h->d_flags) (void)hipFree(h->d_flags);
-    if (h->mp_ws) (void)hipFree(h->mp_ws);
-    if (h->pr_ws) (void)hipFree(h->pr_ws);
+    hsla::dev_free(h, h->mp_ws);
+    hsla::dev_free(h, h->pr_ws);
     for (int i = 0; i < h->prof_cap; ++i) (void)hipEventDestroy(h->prof_ev[i]);
     delete[] h->prof_ev;
     if (h->entry_event) (void)hipEventDestroy(h->entry_event);
@@ -641,6 +657,36 @@ void hsla_destroy(hsla_handle *h) {
 }
 
 const char *hsla_last_error(const hsla_handle *h) { return h ? h->last_error.c_str() : "null handle"; }
+
+hsla_status hsla_set_allocator(hsla_handle *h, hsla_alloc_fn alloc, hsla_free_fn free_fn, void *ctx) {
+    if (!h) return HSLA_ERR_INVALID_ARG;
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return hsla::set_error(h, HSLA_ERR_INVALID_ARG, "alloc and free must both be set or both be NULL");
+    HSLA_HIP(h, hipSetDevice(h->device));
+    HSLA_HIP(h, hipDeviceSynchronize());
+    for (int i = 0; i < hsla_handle::kGraphCache; ++i) {
+        if (h->graph_exec[i]) (void)hipGraphExecDestroy(h->graph_exec[i]);
+        h->graph_exec[i] = nullptr;
+        h->graph_key[i] = 0;
+    }
+    hsla::dev_free(h, h->ws);
+    hsla::dev_free(h, h->mp_ws);
+    hsla::dev_free(h, h->pr_ws);
+    h->ws = h->mp_ws = h->pr_ws = nullptr;
+    h->ws_bytes = h->mp_ws_bytes = h->pr_ws_bytes = 0;
+    h->mp_keep_B = 0;
+    h->mp_keep_pattern = nullptr;
+    h->alloc_fn = alloc;
+    h->free_fn = free_fn;
+    h->alloc_ctx = ctx;
+    return HSLA_OK;
+}
+
+hsla_status hsla_reserve(hsla_handle *h, size_t bytes) {
+    if (!h) return HSLA_ERR_INVALID_ARG;
+    HSLA_HIP(h, hipSetDevice(h->device));
+    return hsla::ensure_workspace(h, bytes);
+}
 
 hsla_status hsla_pattern_create(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *d_row_ptr,
                                 const int32_t *d_col, void *stream, hsla_pattern **out) {

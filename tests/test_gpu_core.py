@@ -334,3 +334,29 @@ def test_workspace_growth_between_solves(orc):
         x, info, st = solve(a, b, precond="jacobi", rtol=1e-12)
         ref = orc.cg(a, b, precond="jacobi", rtol=1e-12)
         assert st == 0 and rel(x, ref.x) <= 1e-8 and iters_close(info[0]["iters"], ref.iters)
+
+
+def test_torch_allocator_and_workspace_size(orc):
+    """Workspaces come from torch's caching allocator once it is set, and a
+    reservation of hsla_workspace_size bytes covers the solve that follows
+    (no further allocation)."""
+    m = 20
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m))
+    b = W.rng(2, 1).standard_normal(a.n)
+    pat = pattern(a)
+    cnt = {}
+    _lib.use_torch_allocator(dev(), counter=cnt)
+    try:
+        for persistent in (False, True):
+            opts = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-12, persistent=persistent)
+            need = _lib.workspace_size(pat, 3, opts)
+            _lib.reserve(need, dev())
+            allocs = cnt.get("alloc", 0)
+            assert allocs >= 1
+            x, infos, st = _lib.solve(pat, t64(np.stack([a.val] * 3)), t64(np.stack([b] * 3)), opts)
+            assert st == 0 and cnt["alloc"] == allocs
+            ref = orc.cg(a, b, precond="jacobi", rtol=1e-12)
+            assert rel(x[0].cpu().numpy(), ref.x) <= 1e-8
+    finally:
+        _lib.use_torch_allocator(dev(), enable=False)
+    assert cnt.get("free", 0) >= 1
