@@ -360,3 +360,36 @@ def test_torch_allocator_and_workspace_size(orc):
     finally:
         _lib.use_torch_allocator(dev(), enable=False)
     assert cnt.get("free", 0) >= 1
+
+
+def test_backward_memory_flat_in_iterations():
+    """The autograd node keeps only (values, x): device memory of forward +
+    backward does not grow with the number of CG iterations.  2D Poisson
+    N = 640,000 (800^2), plain CG forced to k iterations, all workspaces
+    drawn from torch's allocator so that they are counted."""
+    import paper_2601_13994_amd as hs
+
+    a = W.poisson2d(800)
+    b = np.random.default_rng(3).standard_normal(a.n)
+    rp, col = t32(a.row_ptr), t32(a.col)
+    pat = hs.SparseCSR(t64(a.val), rp, col).pattern
+    _lib.use_torch_allocator(dev())
+    try:
+        peaks = []
+        for k in (10, 10, 100, 1000):  # the first run sizes the workspaces
+            vals = t64(a.val).requires_grad_()
+            bt = t64(b).requires_grad_()
+            A = hs.SparseCSR(vals, rp, col, pattern=pat)
+            torch.cuda.synchronize()
+            torch.cuda.reset_peak_memory_stats()
+            base = torch.cuda.memory_allocated()
+            with pytest.warns(RuntimeWarning):
+                x = A.solve(bt, rtol=0.0, max_iter=k, method="cg", precond="none", allow_unconverged=True)
+                (x * x).sum().backward()
+            torch.cuda.synchronize()
+            peaks.append(torch.cuda.max_memory_allocated() - base)
+            assert vals.grad is not None and bt.grad is not None
+        peaks = peaks[1:]
+        assert max(peaks) <= min(peaks) * 1.01 + (1 << 20), peaks
+    finally:
+        _lib.use_torch_allocator(dev(), enable=False)
