@@ -67,9 +67,11 @@ typedef struct hsla_opts {
                             (graphs off); results in hsla_info.spmv_ms / spmv_launches          */
     const float *d_G;    /* FSAI: G values on the lower pattern (float32, [B][nnz_L]); else NULL */
     const float *d_GT;   /* FSAI: the same values in G^T's CSR order ([B][nnz_L])               */
-    int32_t persistent;  /* 1 (default): CG with Jacobi or no preconditioner on systems of at most
-                            131072 stored entries (x0 = 0, profile off) runs as one persistent
-                            launch, one workgroup per system; 0: always per-iteration kernels   */
+    int32_t persistent;  /* 1 (default): CG with Jacobi or no preconditioner (x0 = 0, profile off)
+                            on systems of at most 4096 rows of <= 16 entries, or on batches of at
+                            least one system per compute unit with at most 131072 entries each,
+                            runs as one persistent launch, one workgroup per system;
+                            0: always per-iteration kernels                                     */
 } hsla_opts;
 
 /* Per-system result information. */

@@ -167,11 +167,11 @@ inline int grid_blocks(const hsla_handle *h, int64_t per_block, int64_t units, i
     return (int)want;
 }
 
-// Shared-pattern CG batches whose systems are small enough for one
-// workgroup each run as one persistent launch (ragged.hip): no per-iteration
-// launches, every system iterating independently.
+// Shared-pattern CG batches of small systems (or of mid-size systems when
+// the batch fills the chip) run as one persistent launch (ragged.hip): no
+// per-iteration launches, every system iterating independently.
 constexpr int64_t kPersistentMaxNnz = 131072;
-bool persistent_eligible(const hsla_pattern *p, int B, int method, const hsla_opts &o);
+bool persistent_eligible(const hsla_handle *h, const hsla_pattern *p, int B, int method, const hsla_opts &o);
 hsla_status persistent_solve(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *b,
                              double *x, const hsla_opts &o, hsla_info *infos, hipStream_t s);
 

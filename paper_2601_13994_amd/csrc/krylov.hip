@@ -1354,7 +1354,7 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
         if (st != HSLA_OK) return st;
         method = sym ? HSLA_METHOD_CG : HSLA_METHOD_BICGSTAB;
     }
-    if (o.persistent && persistent_eligible(p, B, method, o))
+    if (o.persistent && persistent_eligible(h, p, B, method, o))
         return persistent_solve(h, p, B, values, b, x, o, infos, s);
     const Pat A = pat_of(p);
     FPat L{}, U{};
@@ -1400,7 +1400,7 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
     hsla_status res;
     if (sym) {
         const Pat A = pat_of(p);
-        if (o.persistent && persistent_eligible(p, B, method, o))
+        if (o.persistent && persistent_eligible(h, p, B, method, o))
             res = persistent_solve(h, p, B, values, gx, lam, o, infos, s);
         else
             res = solve_core(h, tune_of(p), A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s);
@@ -1442,7 +1442,7 @@ hsla_status workspace_size(hsla_handle *h, const hsla_pattern *p, int B, const h
         if (method == HSLA_METHOD_BICGSTAB && pre == PRE_FSAI) continue;
         const Plan pl = plan_solve(h, tune_of(p), A, &L, &U, B, method, pre);
         need = std::max(need, pl.lay.total);
-        if (o.persistent && persistent_eligible(p, B, method, o))
+        if (o.persistent && persistent_eligible(h, p, B, method, o))
             need = std::max(need, sizeof(double) * 4 * (size_t)B * p->n + 1024 + 40 * (size_t)B);
     }
     *bytes = need + need / 8 + 4096;  // the growth margin ensure_workspace adds

@@ -588,9 +588,16 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
 
 }  // namespace rg
 
-bool persistent_eligible(const hsla_pattern *p, int B, int method, const hsla_opts &o) {
-    return method == HSLA_METHOD_CG && (o.precond == HSLA_PRECOND_JACOBI || o.precond == HSLA_PRECOND_NONE) &&
-           !o.use_x0 && !o.profile && B >= 1 && p->n >= 1 && p->nnz <= kPersistentMaxNnz;
+// The register-resident kernel wins for every small system; the general
+// shared-mode kernel only once the batch gives every CU a system (one
+// workgroup streams a mid-size system slower than the per-iteration kernels
+// stream it over the whole chip).
+bool persistent_eligible(const hsla_handle *h, const hsla_pattern *p, int B, int method, const hsla_opts &o) {
+    if (method != HSLA_METHOD_CG || (o.precond != HSLA_PRECOND_JACOBI && o.precond != HSLA_PRECOND_NONE) ||
+        o.use_x0 || o.profile || B < 1 || p->n < 1)
+        return false;
+    if (p->n <= rg::kSmallMaxN && p->max_row <= rg::kSmallMaxRow) return true;
+    return B >= h->dev.num_cu && p->nnz <= kPersistentMaxNnz;
 }
 
 hsla_status persistent_solve(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *b,

@@ -393,3 +393,26 @@ def test_backward_memory_flat_in_iterations():
         assert max(peaks) <= min(peaks) * 1.01 + (1 << 20), peaks
     finally:
         _lib.use_torch_allocator(dev(), enable=False)
+
+
+def test_persistent_shared_mode_batch(orc):
+    """A batch with one system per compute unit and more runs the general
+    persistent kernel in shared-pattern mode (n > 4096): sampled systems
+    match the oracle and the per-iteration kernels."""
+    m = 24
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m))
+    B = 320
+    r = np.random.default_rng(8)
+    V = np.stack([a.val] * B)
+    bs = r.standard_normal((B, a.n))
+    pat = pattern(a)
+    x1, i1, s1 = _lib.solve(pat, t64(V), t64(bs), _lib.make_opts(method="cg", precond="jacobi", rtol=1e-12))
+    x2, i2, s2 = _lib.solve(pat, t64(V), t64(bs),
+                            _lib.make_opts(method="cg", precond="jacobi", rtol=1e-12, persistent=False))
+    assert s1 == s2 == 0
+    assert all(f["spmv_launches"] == 0 for f in i1)
+    for s in (0, 157, 319):
+        ref = orc.cg(a, bs[s], precond="jacobi", rtol=1e-12)
+        assert rel(x1[s].cpu().numpy(), ref.x) <= 1e-8
+        assert rel(x2[s].cpu().numpy(), ref.x) <= 1e-8
+        assert iters_close(i1[s]["iters"], ref.iters)
