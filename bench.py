@@ -59,22 +59,40 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def spmv_bytes(n: int, nnz: int, nofs: int) -> int:
-    """Algorithmic HBM bytes of one q = A p (+ p.q) launch: p gathered once
-    with cache reuse (8n), q written once (8n), and the matrix once -- CSR
-    (nofs = 0): values, column indices and row pointers (12 nnz + 4(n+1));
-    offset-mask patterns (nofs diagonals): the per-solve diagonal-major copy
-    of the values (8 nofs n, zeros where a row has no entry) and one 16-bit
-    row mask (2n)."""
-    matrix = 8 * nofs * n + 2 * n if nofs else 12 * nnz + 4 * (n + 1)
-    return matrix + 16 * n
+def matrix_bytes(n: int, nnz: int, form: str, nofs: int = 0) -> int:
+    """Bytes of one pass over the operator in the SpMV form a solve used:
+    CSR (values, column indices, row pointers: 12 nnz + 4(n+1)); row tiles
+    with 16-bit row masks (8 nnz + 2n); the per-solve diagonal-major copy
+    (8 nofs n, zeros where a row has no entry, + masks); its symmetric half
+    form (main and upper diagonals only: 8 (nofs/2 + 1) n + masks)."""
+    return {"csr": 12 * nnz + 4 * (n + 1), "mask-tiles": 8 * nnz + 2 * n, "diagonal": 8 * nofs * n + 2 * n,
+            "diagonal-half": 8 * (nofs // 2 + 1) * n + 2 * n}[form]
+
+
+def spmv_bytes(n: int, nnz: int, form: str, nofs: int = 0) -> int:
+    """Algorithmic HBM bytes of one q = A p (+ p.q) launch: the operator once,
+    p gathered once with cache reuse (8n), q written once (8n)."""
+    return matrix_bytes(n, nnz, form, nofs) + 16 * n
+
+
+def form_of(info: dict, pat) -> str:
+    """The SpMV form a solve reports (hsla_info.spmv_form) as a byte-model key."""
+    f = info["spmv_form"]
+    if f in ("diagonal", "diagonal-half"):
+        return f
+    return "mask-tiles" if f == "tiles" and pat.stencil[0] else "csr"
+
+
+FORM_TEXT = {"diagonal": "diagonal-major values + row masks, {} diagonals",
+             "diagonal-half": "symmetric half diagonal-major values (main + upper) + row masks, {} diagonals",
+             "mask-tiles": "row tiles with row masks, {} diagonals", "csr": "csr row tiles"}
 
 
 def pcg_iteration_bytes(n: int, nnz: int, nofs: int) -> int:
     """Algorithmic bytes of one Jacobi-PCG iteration as scheduled here:
     SpMV+dot, update (reads x p r q D^-1, writes x r: 56n), direction
     (reads D^-1 r p, writes p: 32n)."""
-    return spmv_bytes(n, nnz, nofs) + 88 * n
+    return spmv_bytes(n, nnz, "diagonal" if nofs else "csr", nofs) + 88 * n
 
 
 def cpu_info() -> str:
@@ -220,13 +238,8 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
     launches = sum(r["spmv_launches"] for r in recs)
     avg_ms = spmv_ms / max(launches, 1)
     stencil, nofs = pat.stencil
-    form = ("diagonal" if (tuning is None or tuning["form"] == "diagonal") else "mask-tiles") if stencil else "csr"
-    if form == "diagonal":
-        bytes_launch = spmv_bytes(n, nnz, nofs)
-    elif form == "mask-tiles":
-        bytes_launch = 8 * nnz + 2 * n + 16 * n  # values in CSR order + row masks
-    else:
-        bytes_launch = spmv_bytes(n, nnz, 0)
+    form = form_of(recs[-1], pat)
+    bytes_launch = spmv_bytes(n, nnz, form, nofs)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     ms_step = elapsed / args.steps * 1e3
     it_bytes = bytes_launch + 88 * n
@@ -260,8 +273,9 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "algorithmic_bytes_per_launch": bytes_launch,
             "mean_launch_ms": avg_ms,
             "launches_timed": launches,
-            "format": {"diagonal": f"diagonal-major values + row masks, {nofs} diagonals",
-                       "mask-tiles": f"row tiles with row masks, {nofs} diagonals", "csr": "csr row tiles"}[form],
+            "format": FORM_TEXT[form].format(nofs),
+            "full_copy_equivalent_GBps": (spmv_bytes(n, nnz, "diagonal", nofs) / (avg_ms * 1e-3) / 1e9
+                                          if stencil else None),
         },
         "detail": {
             "iterations": iters,
@@ -273,6 +287,7 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "GFLOPs": (2 * nnz + 13 * n) * iters / (ms_step * 1e-3) / 1e9,
             "algorithmic_bytes_per_iteration": it_bytes,
             "spmv_share_of_step": spmv_ms / args.steps / ms_step,
+            "spmv_form": recs[-1]["spmv_form"],
             "autotune": tuning,
             "csr_bytes_per_iteration": csr_it_bytes,
             "csr_equivalent_iteration_GBps": csr_it_bytes * iters / (ms_step * 1e-3) / 1e9,
@@ -303,7 +318,7 @@ def run_bicgstab(ctx, args, dev, pat):
     _sync()
     dt = (time.perf_counter() - t0) / args.sub_steps
     it = infos[0]["iters"]
-    it_bytes = 2 * spmv_bytes(n, nnz, pat.stencil[1] if pat.stencil[0] else 0) + 144 * n
+    it_bytes = 2 * spmv_bytes(n, nnz, form_of(infos[0], pat), pat.stencil[1]) + 144 * n
     return {
         "workload": f"diffusion3d-{args.m}^3 + upwind convection (cell Peclet 10), Jacobi-BiCGStab to rtol 1e-8",
         "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iterations": it, "status": st,
@@ -312,7 +327,7 @@ def run_bicgstab(ctx, args, dev, pat):
         "iteration_model_GBps": it_bytes * it / dt / 1e9,
         "iteration_frac_of_peak": it_bytes * it / dt / 1e9 / HBM_PEAK_GBPS,
         "GFLOPs": (4 * nnz + 26 * n) * it / dt / 1e9,
-        "algorithmic_bytes_per_iteration": it_bytes, "reps": args.sub_steps,
+        "algorithmic_bytes_per_iteration": it_bytes, "spmv_form": infos[0]["spmv_form"], "reps": args.sub_steps,
     }
 
 
@@ -353,7 +368,7 @@ def run_poisson(ctx, args, dev):
     tb = (time.perf_counter() - t0) / args.sub_steps
     it = infos[0]["iters"]
     itb = np.array([f["iters"] for f in ib])
-    it_bytes = spmv_bytes(a.n, a.nnz, 0) + 72 * a.n  # the persistent kernel reads CSR
+    it_bytes = spmv_bytes(a.n, a.nnz, "csr") + 72 * a.n  # the persistent kernel reads CSR
     res = {
         "workload": "poisson2d-64^2 (n=4096, nnz=20224), plain CG to rtol 1e-10, x0=0",
         "latency_us_per_solve": lat * 1e6, "iterations": it, "status": st,
@@ -461,14 +476,19 @@ def run_adjoint(ctx, args, dev):
     dt = (time.perf_counter() - t0) / args.sub_steps
     itf = np.array([f["iters"] for f in fi])
     itb = np.array([f["iters"] for f in bi])
-    nofs = pat.stencil[1] if pat.stencil[0] else 0
-    per_it = (8 * nofs * n + 104 * n + 2 * n / B) if nofs else (8 * nnz + 104 * n + (4 * nnz + 4 * (n + 1)) / B)
+    # per system per iteration: the operator's values in the form used (the
+    # row masks or CSR indices, shared by the batch, amortised over B) + 104n
+    form = form_of(fi[0], pat)
+    nofs = pat.stencil[1]
+    per_it = {"diagonal-half": 8 * (nofs // 2 + 1) * n, "diagonal": 8 * nofs * n,
+              "mask-tiles": 8 * nnz, "csr": 8 * nnz}[form] + 104 * n
+    per_it += (2 * n if form != "csr" else 4 * nnz + 4 * (n + 1)) / B
     work = float(per_it * (itf.sum() + itb.sum()) + B * (12 * nnz + 28 * n))
     return {
         "workload": (f"{B} systems on one 3D 7-point pattern, {args.adj_m}^3 (n={n}, nnz={nnz}), log-normal kappa "
                      "per sample; forward Jacobi-PCG + adjoint, rtol 1e-8, loss 1/2||x - x*||^2"),
         "pairs_per_s": B / dt, "ms_per_batch": dt * 1e3, "status_forward": st, "status_adjoint": st2,
-        "autotune": tuning,
+        "autotune": tuning, "spmv_form": fi[0]["spmv_form"],
         "iterations_forward_mean": float(itf.mean()), "iterations_adjoint_mean": float(itb.mean()),
         "true_relative_residual_max": max(max(f["true_residual"] for f in fi), max(f["true_residual"] for f in bi)),
         "model_GBps": work / dt / 1e9, "model_frac_of_peak": work / dt / 1e9 / HBM_PEAK_GBPS,

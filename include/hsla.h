@@ -84,6 +84,10 @@ typedef struct hsla_info {
     double spmv_ms;       /* profile mode: summed duration of the SpMV(+dot) launches that
                              did work (all systems of a batch share one launch)            */
     int64_t spmv_launches;/* profile mode: number of those launches                        */
+    int32_t spmv_form;    /* SpMV form of the solve: 0 row tiles (CSR or row masks),
+                             1 per-solve diagonal-major copy, 2 its symmetric half form
+                             (main and upper diagonals stored), 3 one persistent launch   */
+    int32_t reserved;     /* 0                                                             */
 } hsla_info;
 
 void hsla_opts_default(hsla_opts *opts);
@@ -158,7 +162,8 @@ hsla_status hsla_pattern_set_format(hsla_pattern *p, int32_t format);
 hsla_status hsla_pattern_format(const hsla_pattern *p, int32_t *stencil_in_use, int32_t *num_offsets);
 /* Autotuner result: the SpMV configuration the solvers use on a pattern. */
 typedef struct hsla_tuning {
-    int32_t form;          /* 0: per-solve diagonal-major copy, 1: row tiles (CSR or row masks) */
+    int32_t form;          /* 0: per-solve diagonal-major copy, 1: row tiles (CSR or row masks),
+                              2: the copy's symmetric half form (used for symmetric values)    */
     int32_t blocks_per_cu; /* grid density of the chosen form's SpMV kernel                   */
     double best_us;        /* mean SpMV time of the choice (B systems)                        */
     double default_us;     /* mean SpMV time of the untuned default configuration             */

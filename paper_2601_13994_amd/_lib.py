@@ -54,17 +54,22 @@ class Opts(ctypes.Structure):
     ]
 
 
+SPMV_FORMS = {0: "tiles", 1: "diagonal", 2: "diagonal-half", 3: "persistent"}
+
+
 class Info(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int64), ("status", ctypes.c_int32), ("method", ctypes.c_int32),
         ("rel_residual", ctypes.c_double), ("true_residual", ctypes.c_double),
         ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int64),
+        ("spmv_form", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {"iters": self.iters, "status": self.status, "method": METHOD_NAMES.get(self.method, "?"),
                 "rel_residual": self.rel_residual, "true_residual": self.true_residual,
-                "spmv_ms": self.spmv_ms, "spmv_launches": self.spmv_launches}
+                "spmv_ms": self.spmv_ms, "spmv_launches": self.spmv_launches,
+                "spmv_form": SPMV_FORMS.get(self.spmv_form, "?")}
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -292,7 +297,7 @@ class Pattern:
         with torch.cuda.device(self.device):
             st = load().hsla_autotune(self.h, self.p, int(B), int(effort), ctypes.byref(t), stream_ptr(self.device))
             check(st, self.h, "hsla_autotune")
-        return {"form": ("diagonal" if t.form == 0 else "tiles"), "blocks_per_cu": t.blocks_per_cu,
+        return {"form": {0: "diagonal", 1: "tiles", 2: "diagonal-half"}[t.form], "blocks_per_cu": t.blocks_per_cu,
                 "best_us": t.best_us, "default_us": t.default_us}
 
     def __del__(self):

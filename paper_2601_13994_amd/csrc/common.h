@@ -63,8 +63,9 @@ struct hsla_pattern {
     int32_t format = HSLA_FORMAT_AUTO;  // requested SpMV format
     int32_t max_row = 0;                // most entries in one row
     // autotuned SpMV configuration of the solvers (hsla_autotune); defaults
-    // until tuned: diagonal-major form where available, 16 / 8 blocks per CU
-    int32_t tune_dia = 1, tune_tile_cu = 16, tune_dia_cu = 8, tuned = 0;
+    // until tuned: diagonal-major form where available (its symmetric half
+    // form for symmetric values), 16 / 8 / 8 blocks per CU
+    int32_t tune_dia = 1, tune_tile_cu = 16, tune_dia_cu = 8, tune_sym = 1, tune_sym_cu = 8, tuned = 0;
     int32_t n = 0;
     int64_t nnz = 0;
     int32_t *row_ptr = nullptr;  // [n+1]
@@ -548,6 +549,63 @@ __host__ __device__ inline int dia_slots_for(int nofs) {
     return (nofs == 5 || nofs == 7 || nofs == 9) ? nofs : (nofs + 3) / 4 * 4;
 }
 
+// Symmetric half form.  When the offsets come in pairs +-o around the main
+// diagonal, the pattern is symmetric and the values are symmetric bit for
+// bit, only the main and the upper diagonals are stored (stored slot
+// s - nofs/2 for diagonal s >= nofs/2, same chunked layout with nofs/2 + 1
+// slots): the entry (i, i - o) of a lower diagonal is the stored entry
+// (i - o, i).  The SpMV then walks pencils: a block takes one chunk position
+// inside an o_max-row plane (o_max = the largest offset, a multiple of
+// kDiaChunk) for kPencil consecutive planes, so the +o_max diagonal loaded
+// for one plane is, unchanged, the -o_max diagonal of the next plane's rows;
+// the other lower diagonals are re-read from entries that the block or its
+// XCD neighbours loaded moments before.  Slot counts above kSymNS select this
+// form for NS - kSymNS diagonals.
+constexpr int kSymNS = 100;
+constexpr int kPencil = 8;
+
+// Stored diagonals per system of a diagonal-major copy for slot count ns.
+__host__ __device__ inline int dia_stored(int ns, int nofs) { return ns > kSymNS ? nofs / 2 + 1 : nofs; }
+
+inline bool stencil_half_ok(const Stencil &sn) {
+    if (!sn.mask || (sn.nofs != 5 && sn.nofs != 7 && sn.nofs != 9)) return false;
+    const int ds = sn.nofs / 2;
+    if (sn.diag_slot != ds) return false;
+    for (int u = 1; u <= ds; ++u)
+        if (sn.ofs[ds - u] != -sn.ofs[ds + u]) return false;
+    const int64_t omax = sn.ofs[sn.nofs - 1];
+    return omax > 0 && omax % kDiaChunk == 0;
+}
+
+// Pencil items: column col (chunk position inside a plane of cols chunks)
+// and segment seg (planes [seg * kPencil, + kPencil)).  With a grid that is
+// a multiple of kXcds, XCD k owns columns [cols k / 8, cols (k+1) / 8), so
+// the neighbouring columns whose entries and x a row gathers are processed
+// on the same XCD at the same time.
+struct PencilWalk {
+    int64_t cols, nch, c0, ncx, items, first, stride;
+    __device__ __forceinline__ PencilWalk(int64_t n, int64_t omax) {
+        nch = dia_chunks(n);
+        cols = omax / kDiaChunk;
+        const int64_t planes = (nch + cols - 1) / cols;
+        const int64_t segs = (planes + kPencil - 1) / kPencil;
+        const int G = gridDim.x;
+        if (G % kXcds == 0 && cols >= kXcds) {
+            const int xcd = blockIdx.x % kXcds;
+            c0 = cols * xcd / kXcds;
+            ncx = cols * (xcd + 1) / kXcds - c0;
+            first = blockIdx.x / kXcds;
+            stride = G / kXcds;
+        } else {
+            c0 = 0;
+            ncx = cols;
+            first = blockIdx.x;
+            stride = G;
+        }
+        items = ncx * segs;
+    }
+};
+
 // SpMV on the chunked diagonal-major copy of the values (see kDiaChunk).
 // A block takes one chunk of 512 rows per step, each thread two rows 256
 // apart; each row adds its present products in ascending diagonal order,
@@ -559,9 +617,17 @@ __host__ __device__ inline int dia_slots_for(int nofs) {
 // epilogue takes x of its own row too (it is the diagonal slot's gathered
 // value: absent entries gather the row's own x).
 template <int NS, typename VT, class Epi>
+__device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
+                                             const double *__restrict__ x, Epi &&epi);
+
+template <int NS, typename VT, class Epi>
 __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                          const double *__restrict__ x, Epi &&epi) {
 #pragma clang fp contract(off)
+    if constexpr (NS > kSymNS) {
+        spmv_dia_sym<NS - kSymNS>(sn, dv, n, x, epi);
+        return;
+    }
     constexpr bool kExact = NS == 5 || NS == 7 || NS == 9;
     constexpr int kGroup = kExact ? NS : 4;
     const ChunkWalk cw(dia_chunks(n));
@@ -616,6 +682,73 @@ __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict
         } else {
             if (one) epi(i, a1);
             if (two) epi(i2, a2);
+        }
+    }
+}
+
+// The half form's SpMV (see kSymNS): the same products as spmv_dia, added
+// in the same ascending diagonal order, so the result is bitwise that of the
+// full copy, the tiles and CSR.  The upper and main diagonals stream
+// (nontemporal); the lower ones are cached re-reads or, for -o_max, the
+// previous plane's +o_max values kept in registers.
+template <int NS, typename VT, class Epi>
+__device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
+                                             const double *__restrict__ x, Epi &&epi) {
+#pragma clang fp contract(off)
+    static_assert(NS == 5 || NS == 7 || NS == 9, "half form for 5, 7 or 9 diagonals");
+    constexpr int DS = NS / 2, NH = DS + 1;
+    const PencilWalk pw(n, sn.ofs[NS - 1]);
+    const uint16_t *__restrict__ mask = sn.mask;
+    for (int64_t it = pw.first; it < pw.items; it += pw.stride) {
+        const int64_t col = pw.c0 + it % pw.ncx, seg = it / pw.ncx;
+        VT carry1 = VT(0), carry2 = VT(0);
+        for (int t = 0; t < kPencil; ++t) {
+            const int64_t c = (seg * kPencil + t) * pw.cols + col;
+            if (c >= pw.nch) break;
+            const int64_t i = c * kDiaChunk + threadIdx.x;
+            const int64_t i2 = i + kBlock;
+            const bool one = i < n, two = i2 < n;
+            const int64_t j1 = one ? i : 0, j2 = two ? i2 : 0;
+            const uint32_t m1 = one ? (uint32_t)mask[i] : 0u;
+            const uint32_t m2 = two ? (uint32_t)mask[i2] : 0u;
+            const VT *__restrict__ base = dv + c * NH * kDiaChunk + threadIdx.x;
+            VT v1[NS], v2[NS];
+            double x1[NS], x2[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int64_t d = sn.ofs[s];
+                const int64_t r1 = ((m1 >> s) & 1u) ? i + d : j1;
+                const int64_t r2 = ((m2 >> s) & 1u) ? i2 + d : j2;
+                if (s >= DS) {
+                    v1[s] = __builtin_nontemporal_load(&base[(s - DS) * kDiaChunk]);
+                    v2[s] = __builtin_nontemporal_load(&base[(s - DS) * kDiaChunk + kBlock]);
+                } else if (s == 0 && t > 0) {
+                    v1[s] = carry1;
+                    v2[s] = carry2;
+                } else {
+                    v1[s] = dv[dia_index(r1, DS - s, NH)];
+                    v2[s] = dv[dia_index(r2, DS - s, NH)];
+                }
+                x1[s] = x[r1];
+                x2[s] = x[r2];
+            }
+            double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const double p1 = (double)v1[s] * x1[s];
+                const double p2 = (double)v2[s] * x2[s];
+                if ((m1 >> s) & 1u) a1 = a1 + p1;
+                if ((m2 >> s) & 1u) a2 = a2 + p2;
+            }
+            carry1 = v1[NS - 1];
+            carry2 = v2[NS - 1];
+            if constexpr (std::is_invocable_v<Epi, int64_t, double, double>) {
+                if (one) epi(i, a1, x1[DS]);
+                if (two) epi(i2, a2, x2[DS]);
+            } else {
+                if (one) epi(i, a1);
+                if (two) epi(i2, a2);
+            }
         }
     }
 }

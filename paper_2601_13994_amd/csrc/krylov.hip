@@ -72,7 +72,8 @@ template <int NS, class Epi>
 __device__ __forceinline__ void spmv_A(const Pat &A, const Sys &S, int sidx, const double *v, double *lds,
                                        Epi &&epi) {
     if constexpr (NS > 0)
-        spmv_dia<NS>(A.sn, S.dia + (int64_t)sidx * A.sn.nofs * dia_chunks(A.n) * kDiaChunk, (int64_t)A.n, v, epi);
+        spmv_dia<NS>(A.sn, S.dia + (int64_t)sidx * dia_stored(NS, A.sn.nofs) * dia_chunks(A.n) * kDiaChunk,
+                     (int64_t)A.n, v, epi);
     else
         spmv_tiles(A.rp, A.col, A.sn, S.val + (int64_t)sidx * A.nnz, v, A.meta, A.ntiles, lds, epi);
 }
@@ -104,6 +105,28 @@ __global__ __launch_bounds__(kBlock) void k_to_dia(int32_t n, const int32_t *__r
             VT val = VT(0);
             if ((m >> s) & 1u) val = v[k++];
             d[dia_index(i, s, sn.nofs)] = val;
+        }
+    }
+}
+
+// The half form's copy (see kSymNS): the main and upper diagonals only, at
+// stored slot s - nofs/2.
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_to_dia_sym(int32_t n, const int32_t *__restrict__ rp, Stencil sn,
+                                                       int64_t nnz, const VT *__restrict__ vals,
+                                                       VT *__restrict__ dia) {
+    const int sidx = blockIdx.y;
+    const int ds = sn.nofs / 2, nh = ds + 1;
+    const int64_t rows = dia_chunks(n) * kDiaChunk;
+    const VT *v = vals + (int64_t)sidx * nnz;
+    VT *d = dia + (int64_t)sidx * nh * rows;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < rows; i += (int64_t)gridDim.x * kBlock) {
+        const uint32_t m = i < n ? (uint32_t)sn.mask[i] : 0u;
+        int32_t k = i < n ? rp[i] + __popc(m & ((1u << ds) - 1u)) : 0;
+        for (int s = ds; s < sn.nofs; ++s) {
+            VT val = VT(0);
+            if ((m >> s) & 1u) val = v[k++];
+            d[dia_index(i, s - ds, nh)] = val;
         }
     }
 }
@@ -169,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia(Pat A, const double *__rest
     const int64_t sidx = blockIdx.y;
     x += sidx * A.n;
     y += sidx * A.n;
-    spmv_dia<NS>(A.sn, dia + sidx * A.sn.nofs * dia_chunks(A.n) * kDiaChunk, (int64_t)A.n, x,
+    spmv_dia<NS>(A.sn, dia + sidx * dia_stored(NS, A.sn.nofs) * dia_chunks(A.n) * kDiaChunk, (int64_t)A.n, x,
                  [&](int64_t row, double yv) { y[row] = yv; });
 }
 
@@ -253,7 +276,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(Pat A, Sys S) {
     double acc[1] = {0.0};
     if constexpr (NS > 0) {
         // p of the row itself comes with the SpMV's gathers
-        spmv_dia<NS>(A.sn, S.dia + (int64_t)sidx * A.sn.nofs * dia_chunks(A.n) * kDiaChunk, (int64_t)A.n, p,
+        spmv_dia<NS>(A.sn, S.dia + (int64_t)sidx * dia_stored(NS, A.sn.nofs) * dia_chunks(A.n) * kDiaChunk,
+                     (int64_t)A.n, p,
                      [&](int64_t row, double yv, double prow) {
                          q[row] = yv;
                          acc[0] += prow * yv;
@@ -904,21 +928,42 @@ __global__ __launch_bounds__(kBlock) void k_fill_f64(double *__restrict__ a, int
         default: K<16><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break;       \
     }
 
+// NS_LAUNCH plus the half form's slot counts, for the SpMV kernels on A.
+#define NS_LAUNCH_A(K, ns, grid, ...)                                           \
+    switch (ns) {                                                               \
+        case kSymNS + 5: K<kSymNS + 5><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
+        case kSymNS + 7: K<kSymNS + 7><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
+        case kSymNS + 9: K<kSymNS + 9><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
+        default: NS_LAUNCH(K, ns, grid, __VA_ARGS__);                          \
+    }
+
+static hsla_status values_symmetric(hsla_handle *h, const hsla_pattern *p, int B, const double *values, hipStream_t s,
+                                    bool *sym);
+
 hsla_status launch_spmv(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *x,
                         double *y, hipStream_t s) {
     if (p->n == 0 || B == 0) return HSLA_OK;
     const Pat A = pat_of(p);
     if (p->format == HSLA_FORMAT_DIAGONAL && A.sn.mask) {
-        const int ns = dia_slots_for(A.sn.nofs);
+        // the half form where the values allow it, else the full copy
+        bool half = false;
+        if (stencil_half_ok(A.sn)) {
+            const hsla_status st = values_symmetric(h, p, B, values, s, &half);
+            if (st != HSLA_OK) return st;
+        }
+        const int ns = half ? kSymNS + A.sn.nofs : dia_slots_for(A.sn.nofs);
         const size_t rows = (size_t)dia_chunks(A.n) * kDiaChunk;
-        const hsla_status st = ensure_workspace(h, sizeof(double) * (size_t)B * A.sn.nofs * rows);
+        const hsla_status st = ensure_workspace(h, sizeof(double) * (size_t)B * dia_stored(ns, A.sn.nofs) * rows);
         if (st != HSLA_OK) return st;
         double *dia = (double *)h->ws;
         const int Gv = grid_blocks(h, kBlock * 4, A.n, B, 8);
-        const int Gd = grid_blocks(h, kDiaChunk, A.n, B, 8);
-        k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>(A.n, A.rp, A.sn, A.nnz, values, dia);
+        const int Gd = half ? grid_blocks(h, kDiaChunk * kPencil, A.n, B, 8) : grid_blocks(h, kDiaChunk, A.n, B, 8);
+        if (half)
+            k_to_dia_sym<double><<<dim3(Gv, B), kBlock, 0, s>>>(A.n, A.rp, A.sn, A.nnz, values, dia);
+        else
+            k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>(A.n, A.rp, A.sn, A.nnz, values, dia);
         const dim3 gd(Gd, B);
-        NS_LAUNCH(k_spmv_dia, ns, gd, A, dia, x, y);
+        NS_LAUNCH_A(k_spmv_dia, ns, gd, A, dia, x, y);
         HSLA_HIP(h, hipGetLastError());
         return HSLA_OK;
     }
@@ -951,7 +996,7 @@ static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hip
     for (int k = 0; k < iters; ++k) {
         if (c.method == HSLA_METHOD_CG) {
             if (ev) (void)hipEventRecord(ev[2 * k], s);
-            NS_LAUNCH(k_cg_spmv_dot, c.nsA, gs, c.A, c.S);
+            NS_LAUNCH_A(k_cg_spmv_dot, c.nsA, gs, c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
             k_fin_alpha<<<gf, kBlock, 0, s>>>(c.S, Gs);
             switch (c.precond) {
@@ -980,7 +1025,7 @@ static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hip
             else
                 k_bicg_dir<PRE_NONE><<<gv, kBlock, 0, s>>>(c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k], s);
-            NS_LAUNCH(k_bicg_spmv_v, c.nsA, gs, c.A, c.S);
+            NS_LAUNCH_A(k_bicg_spmv_v, c.nsA, gs, c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
             k_fin_bicg_v<<<gf, kBlock, 0, s>>>(c.S, Gs);
             if (c.precond == PRE_JACOBI)
@@ -988,7 +1033,7 @@ static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hip
             else
                 k_bicg_s<PRE_NONE><<<gv, kBlock, 0, s>>>(c.A, c.S);
             k_fin_bicg_s<<<gf, kBlock, 0, s>>>(c.S, Gv);
-            NS_LAUNCH(k_bicg_spmv_t, c.nsA, gs, c.A, c.S);
+            NS_LAUNCH_A(k_bicg_spmv_t, c.nsA, gs, c.A, c.S);
             k_fin_bicg_t<<<gf, kBlock, 0, s>>>(c.S, Gs);
             k_bicg_update<<<gv, kBlock, 0, s>>>(c.A, c.S);
             k_fin_bicg_update<<<gf, kBlock, 0, s>>>(c.S, Gv);
@@ -1071,11 +1116,32 @@ static int worst_status(int a, int b) {
 // Shared solve driver for the single, batched and transposed (adjoint)
 // paths.  `A` is the operator actually iterated on.
 // SpMV configuration of a solve (the pattern's autotuned choice).
+// `half`: this solve's values are symmetric and the half form applies.
 struct Tune {
-    int dia, tile_cu, dia_cu;
+    int dia, tile_cu, dia_cu, sym, sym_cu;
+    bool half;
 };
 
-static Tune tune_of(const hsla_pattern *p) { return Tune{p->tune_dia, p->tune_tile_cu, p->tune_dia_cu}; }
+static Tune tune_of(const hsla_pattern *p) {
+    return Tune{p->tune_dia, p->tune_tile_cu, p->tune_dia_cu, p->tune_sym, p->tune_sym_cu, false};
+}
+
+// Sets tn.half for a solve on p's own pattern: the half form is enabled for
+// p, applies to its stencil, and the values are symmetric (`sym` < 0:
+// unknown, checked here).
+static hsla_status decide_half(hsla_handle *h, const hsla_pattern *p, const Pat &A, int B, const double *values,
+                               int sym, hipStream_t s, Tune *tn) {
+    tn->half = false;
+    if (!tn->sym || !p->pattern_symmetric || !stencil_half_ok(A.sn)) return HSLA_OK;
+    if (sym < 0) {
+        bool v = false;
+        const hsla_status st = values_symmetric(h, p, B, values, s, &v);
+        if (st != HSLA_OK) return st;
+        sym = v ? 1 : 0;
+    }
+    tn->half = sym == 1;
+    return HSLA_OK;
+}
 
 // Grid sizes, SpMV forms and workspace layout of one solve.
 struct Plan {
@@ -1099,14 +1165,14 @@ static Plan plan_solve(hsla_handle *h, const Tune &tn, const Pat &A, const FPat 
     // the FSAI factors always use their diagonal-major copies where they
     // have one)
     auto dia_slots = [](const Stencil &sn) { return sn.mask ? dia_slots_for(sn.nofs) : 0; };
-    pl.nsA = tn.dia ? dia_slots(A.sn) : 0;
+    pl.nsA = tn.half ? kSymNS + A.sn.nofs : tn.dia ? dia_slots(A.sn) : 0;
     const bool fsai = pre == PRE_FSAI && L && U;
     pl.nsF = fsai && L->sn.mask && U->sn.mask ? std::max(dia_slots(L->sn), dia_slots(U->sn)) : 0;
-    pl.Gd = grid_blocks(h, kDiaChunk, n, B, tn.dia_cu);
+    pl.Gd = tn.half ? grid_blocks(h, kDiaChunk * kPencil, n, B, tn.sym_cu) : grid_blocks(h, kDiaChunk, n, B, tn.dia_cu);
     pl.Gs = pl.nsA ? pl.Gd : pl.Gt;
     pl.Gf = pl.nsF ? grid_blocks(h, kDiaChunk, n, B, 8) : pl.Gt;
     const size_t drows = (size_t)dia_chunks(n) * kDiaChunk;
-    pl.diaA = pl.nsA ? sizeof(double) * (size_t)B * A.sn.nofs * drows : 0;
+    pl.diaA = pl.nsA ? sizeof(double) * (size_t)B * dia_stored(pl.nsA, A.sn.nofs) * drows : 0;
     pl.diaL = pl.nsF ? sizeof(float) * (size_t)B * L->sn.nofs * drows : 0;
     pl.diaU = pl.nsF ? sizeof(float) * (size_t)B * U->sn.nofs * drows : 0;
     const size_t extra = align_up(pl.diaA, 256) + align_up(pl.diaL, 256) + align_up(pl.diaU, 256);
@@ -1165,7 +1231,10 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
         char *ex = ws + lay.off_extra;
         if (nsA) {
             double *d = (double *)ex;
-            k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values, d);
+            if (nsA > kSymNS)
+                k_to_dia_sym<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values, d);
+            else
+                k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values, d);
             S.dia = d;
             ex += align_up(diaA, 256);
         }
@@ -1277,6 +1346,8 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             f.true_residual = tb > 0 ? tr / tb : tr;
             f.spmv_ms = prof_ms;
             f.spmv_launches = prof_n;
+            f.spmv_form = nsA > kSymNS ? 2 : nsA > 0 ? 1 : 0;
+            f.reserved = 0;
         }
     }
     return (hsla_status)worst;
@@ -1348,11 +1419,13 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
     }
     if (!values || !b || !x) return set_error(h, HSLA_ERR_INVALID_ARG, "null values, b or x");
     int method = o.method;
+    int symv = -1;  // values symmetric: -1 not checked
     if (method == HSLA_METHOD_AUTO) {
         bool sym = false;
         st = values_symmetric(h, p, B, values, s, &sym);
         if (st != HSLA_OK) return st;
         method = sym ? HSLA_METHOD_CG : HSLA_METHOD_BICGSTAB;
+        symv = sym ? 1 : 0;
     }
     if (o.persistent && persistent_eligible(h, p, B, method, o))
         return persistent_solve(h, p, B, values, b, x, o, infos, s);
@@ -1363,7 +1436,10 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
         L = FPat{p->rpL, p->colL, p->metaL, p->ntilesL, p->nnz_lower, o.d_G, p->use(p->stL)};
         U = FPat{p->rpU, p->colU, p->metaU, p->ntilesU, p->nnz_lower, o.d_GT, p->use(p->stU)};
     }
-    return solve_core(h, tune_of(p), A, &L, &U, B, values, b, x, o, method, infos, s);
+    Tune tn = tune_of(p);
+    st = decide_half(h, p, A, B, values, symv, s, &tn);
+    if (st != HSLA_OK) return st;
+    return solve_core(h, tn, A, &L, &U, B, values, b, x, o, method, infos, s);
 }
 
 // Eq. adjoint_linear: A^T lambda = gx, gb = lambda, gA = -lambda x^T on the
@@ -1400,10 +1476,14 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
     hsla_status res;
     if (sym) {
         const Pat A = pat_of(p);
-        if (o.persistent && persistent_eligible(h, p, B, method, o))
+        if (o.persistent && persistent_eligible(h, p, B, method, o)) {
             res = persistent_solve(h, p, B, values, gx, lam, o, infos, s);
-        else
-            res = solve_core(h, tune_of(p), A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s);
+        } else {
+            Tune tn = tune_of(p);
+            res = decide_half(h, p, A, B, values, 1, s, &tn);
+            if (res == HSLA_OK)
+                res = solve_core(h, tn, A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s);
+        }
     } else {
         if (dev_alloc(h, (void **)&valT, sizeof(double) * (size_t)B * (p->nnz > 0 ? p->nnz : 1)) != hipSuccess) {
             dev_free(h, lam_own);
@@ -1450,25 +1530,32 @@ hsla_status workspace_size(hsla_handle *h, const hsla_pattern *p, int B, const h
 }
 
 // Autotuner: times the solvers' SpMV forms and grid densities on the device
-// (synthetic values 1, x = 1) and keeps the fastest in the pattern.
+// (synthetic values 1, x = 1) and keeps the fastest in the pattern.  The
+// half form is timed where the pattern allows it (the synthetic values are
+// symmetric); it is used only by solves whose values are symmetric, so the
+// full copy and the tiles are ranked among themselves for the others.
 hsla_status autotune(hsla_handle *h, hsla_pattern *p, int B, int effort, hsla_tuning *out, hipStream_t s) {
     const Pat A = pat_of(p);
     const int64_t n = p->n, nnz = p->nnz;
     const bool dia_ok = A.sn.mask != nullptr;
+    const bool half_ok = dia_ok && p->pattern_symmetric && stencil_half_ok(A.sn);
     const size_t rows = dia_ok ? (size_t)dia_chunks(n) * kDiaChunk : 0;
     const size_t nv = align_up(sizeof(double) * (size_t)B * (nnz > 0 ? nnz : 1), 256);
     const size_t nx = align_up(sizeof(double) * (size_t)B * n, 256);
     const size_t nd = dia_ok ? align_up(sizeof(double) * (size_t)B * A.sn.nofs * rows, 256) : 0;
-    hsla_status st = ensure_workspace(h, nv + 2 * nx + nd);
+    const size_t nh = half_ok ? align_up(sizeof(double) * (size_t)B * (A.sn.nofs / 2 + 1) * rows, 256) : 0;
+    hsla_status st = ensure_workspace(h, nv + 2 * nx + nd + nh);
     if (st != HSLA_OK) return st;
     char *ws = (char *)h->ws;
     double *val = (double *)ws, *x = (double *)(ws + nv), *y = (double *)(ws + nv + nx);
     double *dia = dia_ok ? (double *)(ws + nv + 2 * nx) : nullptr;
+    double *diah = half_ok ? (double *)(ws + nv + 2 * nx + nd) : nullptr;
     k_fill_f64<<<4096, kBlock, 0, s>>>(val, (int64_t)B * nnz, 1.0);
     k_fill_f64<<<4096, kBlock, 0, s>>>(x, (int64_t)B * n, 1.0);
     if (dia_ok) {
         const int Gv = grid_blocks(h, kBlock * 4, n, B, 8);
         k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, nnz, val, dia);
+        if (half_ok) k_to_dia_sym<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, nnz, val, diah);
     }
     HSLA_HIP(h, hipGetLastError());
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1477,19 +1564,22 @@ hsla_status autotune(hsla_handle *h, hsla_pattern *p, int B, int effort, hsla_tu
         (void)hipEventDestroy(e0);
         return set_error(h, HSLA_ERR_HIP, "autotune: event creation failed");
     }
-    auto time = [&](bool use_dia, int cu, double *us) -> hipError_t {
-        const int ns = dia_slots_for(A.sn.nofs);
-        const dim3 g(use_dia ? grid_blocks(h, kDiaChunk, n, B, cu) : grid_blocks(h, kWavesPerBlock, p->ntiles, B, cu),
-                     B);
+    enum { F_DIA = 0, F_TILES = 1, F_HALF = 2 };
+    auto time = [&](int form, int cu, double *us) -> hipError_t {
+        const int ns = form == F_HALF ? kSymNS + A.sn.nofs : dia_slots_for(A.sn.nofs);
+        const int gx = form == F_HALF  ? grid_blocks(h, kDiaChunk * kPencil, n, B, cu)
+                       : form == F_DIA ? grid_blocks(h, kDiaChunk, n, B, cu)
+                                       : grid_blocks(h, kWavesPerBlock, p->ntiles, B, cu);
+        const dim3 g(gx, B);
         for (int r = -1; r < effort; ++r) {
             if (r == 0) {
                 const hipError_t e = hipEventRecord(e0, s);
                 if (e != hipSuccess) return e;
             }
-            if (use_dia) {
-                NS_LAUNCH(k_spmv_dia, ns, g, A, dia, x, y);
-            } else {
+            if (form == F_TILES) {
                 k_spmv<<<g, kBlock, 0, s>>>(A, val, x, y);
+            } else {
+                NS_LAUNCH_A(k_spmv_dia, ns, g, A, form == F_HALF ? diah : dia, x, y);
             }
         }
         hipError_t e = hipGetLastError();
@@ -1501,32 +1591,39 @@ hsla_status autotune(hsla_handle *h, hsla_pattern *p, int B, int effort, hsla_tu
         return e;
     };
     struct Cand {
-        bool dia;
+        int form;
         int cu;
         double us;
     };
     std::vector<Cand> cands;
+    if (half_ok)
+        for (int cu : {2, 4, 8, 16}) cands.push_back({F_HALF, cu, 0.0});
     if (dia_ok)
-        for (int cu : {2, 4, 8, 16}) cands.push_back({true, cu, 0.0});
-    for (int cu : {4, 8, 16, 32}) cands.push_back({false, cu, 0.0});
+        for (int cu : {2, 4, 8, 16}) cands.push_back({F_DIA, cu, 0.0});
+    for (int cu : {4, 8, 16, 32}) cands.push_back({F_TILES, cu, 0.0});
     hipError_t err = hipSuccess;
     for (Cand &c : cands)
-        if (err == hipSuccess) err = time(c.dia, c.cu, &c.us);
+        if (err == hipSuccess) err = time(c.form, c.cu, &c.us);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return set_error(h, HSLA_ERR_HIP, "autotune: %s", hipGetErrorString(err));
-    const Cand *best = &cands[0], *best_tiles = nullptr, *dflt = nullptr;
+    const Cand *best = nullptr, *best_other = nullptr, *best_tiles = nullptr, *best_half = nullptr, *dflt = nullptr;
+    const int dflt_form = half_ok ? F_HALF : dia_ok ? F_DIA : F_TILES;
     for (const Cand &c : cands) {
-        if (c.us < best->us) best = &c;
-        if (!c.dia && (!best_tiles || c.us < best_tiles->us)) best_tiles = &c;
-        if (c.dia == dia_ok && c.cu == (dia_ok ? 8 : 16)) dflt = &c;
+        if (!best || c.us < best->us) best = &c;
+        if (c.form != F_HALF && (!best_other || c.us < best_other->us)) best_other = &c;
+        if (c.form == F_TILES && (!best_tiles || c.us < best_tiles->us)) best_tiles = &c;
+        if (c.form == F_HALF && (!best_half || c.us < best_half->us)) best_half = &c;
+        if (c.form == dflt_form && c.cu == (dflt_form == F_TILES ? 16 : 8)) dflt = &c;
     }
-    p->tune_dia = best->dia ? 1 : 0;
-    if (best->dia) p->tune_dia_cu = best->cu;
+    p->tune_dia = best_other->form == F_DIA ? 1 : 0;
+    if (best_other->form == F_DIA) p->tune_dia_cu = best_other->cu;
     p->tune_tile_cu = best_tiles->cu;
+    p->tune_sym = best_half && best_half->us < best_other->us ? 1 : 0;
+    if (best_half) p->tune_sym_cu = best_half->cu;
     p->tuned = 1;
     if (out) {
-        out->form = best->dia ? 0 : 1;
+        out->form = best->form;
         out->blocks_per_cu = best->cu;
         out->best_us = best->us;
         out->default_us = dflt ? dflt->us : best->us;

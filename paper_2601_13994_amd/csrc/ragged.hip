@@ -581,6 +581,8 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
             infos[i].true_residual = hi[i].true_residual;
             infos[i].spmv_ms = 0.0;
             infos[i].spmv_launches = 0;
+            infos[i].spmv_form = 3;
+            infos[i].reserved = 0;
         }
     }
     return (hsla_status)worst;
