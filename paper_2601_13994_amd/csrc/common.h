@@ -562,7 +562,7 @@ __host__ __device__ inline int dia_slots_for(int nofs) {
 // XCD neighbours loaded moments before.  Slot counts above kSymNS select this
 // form for NS - kSymNS diagonals.
 constexpr int kSymNS = 100;
-constexpr int kPencil = 8;
+constexpr int kPencil = 16;
 
 // Stored diagonals per system of a diagonal-major copy for slot count ns.
 __host__ __device__ inline int dia_stored(int ns, int nofs) { return ns > kSymNS ? nofs / 2 + 1 : nofs; }
@@ -690,7 +690,10 @@ __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict
 // in the same ascending diagonal order, so the result is bitwise that of the
 // full copy, the tiles and CSR.  The upper and main diagonals stream
 // (nontemporal); the lower ones are cached re-reads or, for -o_max, the
-// previous plane's +o_max values kept in registers.
+// previous plane's +o_max values kept in registers.  x moves along the
+// pencil the same way: the previous plane's own x is this plane's x at
+// -o_max, and its x at +o_max (gathered whenever that row exists) is this
+// plane's own x.
 template <int NS, typename VT, class Epi>
 __device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                              const double *__restrict__ x, Epi &&epi) {
@@ -702,6 +705,7 @@ __device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__rest
     for (int64_t it = pw.first; it < pw.items; it += pw.stride) {
         const int64_t col = pw.c0 + it % pw.ncx, seg = it / pw.ncx;
         VT carry1 = VT(0), carry2 = VT(0);
+        double xlo1 = 0.0, xlo2 = 0.0, xown1 = 0.0, xown2 = 0.0;
         for (int t = 0; t < kPencil; ++t) {
             const int64_t c = (seg * kPencil + t) * pw.cols + col;
             if (c >= pw.nch) break;
@@ -729,8 +733,19 @@ __device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__rest
                     v1[s] = dv[dia_index(r1, DS - s, NH)];
                     v2[s] = dv[dia_index(r2, DS - s, NH)];
                 }
-                x1[s] = x[r1];
-                x2[s] = x[r2];
+                if (t > 0 && s == 0) {
+                    x1[s] = xlo1;
+                    x2[s] = xlo2;
+                } else if (t > 0 && s == DS) {
+                    x1[s] = xown1;
+                    x2[s] = xown2;
+                } else if (s == NS - 1) {
+                    x1[s] = x[i + d < n ? i + d : j1];
+                    x2[s] = x[i2 + d < n ? i2 + d : j2];
+                } else {
+                    x1[s] = x[r1];
+                    x2[s] = x[r2];
+                }
             }
             double a1 = 0.0, a2 = 0.0;
 #pragma unroll
@@ -742,6 +757,10 @@ __device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__rest
             }
             carry1 = v1[NS - 1];
             carry2 = v2[NS - 1];
+            xlo1 = x1[DS];
+            xlo2 = x2[DS];
+            xown1 = x1[NS - 1];
+            xown2 = x2[NS - 1];
             if constexpr (std::is_invocable_v<Epi, int64_t, double, double>) {
                 if (one) epi(i, a1, x1[DS]);
                 if (two) epi(i2, a2, x2[DS]);
