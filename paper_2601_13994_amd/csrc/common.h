@@ -30,6 +30,7 @@ struct Stencil {
     int32_t nofs = 0;
     int32_t ofs[kMaxOffsets] = {};
     int32_t diag_slot = -1;  // s with ofs[s] == 0, -1 if none
+    int32_t pencil = 1;      // planes per pencil of the half form's SpMV (set per launch)
 };
 
 // Per-system solver state (device memory, one record per system).
@@ -554,15 +555,15 @@ __host__ __device__ inline int dia_slots_for(int nofs) {
 // bit, only the main and the upper diagonals are stored (stored slot
 // s - nofs/2 for diagonal s >= nofs/2, same chunked layout with nofs/2 + 1
 // slots): the entry (i, i - o) of a lower diagonal is the stored entry
-// (i - o, i).  The SpMV then walks pencils: a block takes one chunk position
-// inside an o_max-row plane (o_max = the largest offset, a multiple of
-// kDiaChunk) for kPencil consecutive planes, so the +o_max diagonal loaded
-// for one plane is, unchanged, the -o_max diagonal of the next plane's rows;
-// the other lower diagonals are re-read from entries that the block or its
-// XCD neighbours loaded moments before.  Slot counts above kSymNS select this
+// (i - o, i).  When the largest offset o_max is a multiple of kDiaChunk the
+// SpMV walks pencils: a block takes one chunk position inside an o_max-row
+// plane for kPencil consecutive planes, so the +o_max diagonal loaded for one
+// plane is, unchanged, the -o_max diagonal of the next plane's rows; the
+// other lower diagonals are re-read from entries that the block or its XCD
+// neighbours loaded moments before.  Slot counts above kSymNS select this
 // form for NS - kSymNS diagonals.
 constexpr int kSymNS = 100;
-constexpr int kPencil = 16;
+constexpr int kPencil = 16;  // longest pencil
 
 // Stored diagonals per system of a diagonal-major copy for slot count ns.
 __host__ __device__ inline int dia_stored(int ns, int nofs) { return ns > kSymNS ? nofs / 2 + 1 : nofs; }
@@ -573,22 +574,36 @@ inline bool stencil_half_ok(const Stencil &sn) {
     if (sn.diag_slot != ds) return false;
     for (int u = 1; u <= ds; ++u)
         if (sn.ofs[ds - u] != -sn.ofs[ds + u]) return false;
-    const int64_t omax = sn.ofs[sn.nofs - 1];
-    return omax > 0 && omax % kDiaChunk == 0;
+    return sn.ofs[sn.nofs - 1] > 0;
+}
+
+// The half form walks pencils when the largest offset is a whole number of
+// chunks, else chunks.
+inline bool half_pencil(const Stencil &sn) { return sn.ofs[sn.nofs - 1] % kDiaChunk == 0; }
+
+// Pencil length for a launch over B systems of n rows: the longest (up to
+// kPencil planes) that still gives the grid about 8 pencils per CU.
+inline int pencil_len(const Stencil &sn, int64_t n, int B, int num_cu) {
+    if (!half_pencil(sn)) return 1;
+    const int64_t cols = sn.ofs[sn.nofs - 1] / kDiaChunk;
+    const int64_t planes = (dia_chunks(n) + cols - 1) / cols;
+    int P = kPencil;
+    while (P > 1 && cols * ((planes + P - 1) / P) * (int64_t)B < 8 * (int64_t)num_cu) P /= 2;
+    return P;
 }
 
 // Pencil items: column col (chunk position inside a plane of cols chunks)
-// and segment seg (planes [seg * kPencil, + kPencil)).  With a grid that is
+// and segment seg (planes [seg * P, + P), P = sn.pencil).  With a grid that is
 // a multiple of kXcds, XCD k owns columns [cols k / 8, cols (k+1) / 8), so
 // the neighbouring columns whose entries and x a row gathers are processed
 // on the same XCD at the same time.
 struct PencilWalk {
     int64_t cols, nch, c0, ncx, items, first, stride;
-    __device__ __forceinline__ PencilWalk(int64_t n, int64_t omax) {
+    __device__ __forceinline__ PencilWalk(int64_t n, int64_t omax, int P) {
         nch = dia_chunks(n);
         cols = omax / kDiaChunk;
         const int64_t planes = (nch + cols - 1) / cols;
-        const int64_t segs = (planes + kPencil - 1) / kPencil;
+        const int64_t segs = (planes + P - 1) / P;
         const int G = gridDim.x;
         if (G % kXcds == 0 && cols >= kXcds) {
             const int xcd = blockIdx.x % kXcds;
@@ -689,85 +704,107 @@ __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict
 // The half form's SpMV (see kSymNS): the same products as spmv_dia, added
 // in the same ascending diagonal order, so the result is bitwise that of the
 // full copy, the tiles and CSR.  The upper and main diagonals stream
-// (nontemporal); the lower ones are cached re-reads or, for -o_max, the
-// previous plane's +o_max values kept in registers.  x moves along the
-// pencil the same way: the previous plane's own x is this plane's x at
-// -o_max, and its x at +o_max (gathered whenever that row exists) is this
-// plane's own x.
+// (nontemporal); the lower ones are cached re-reads.  Along a pencil the
+// previous plane's +o_max values are, in registers, this plane's -o_max
+// values, and x moves the same way: the previous plane's own x is this
+// plane's x at -o_max, and its x at +o_max (gathered whenever that row
+// exists) is this plane's own x.  When o_max is not a multiple of kDiaChunk
+// (small planes) the chunks are walked as in spmv_dia and every lower value
+// is a re-read from the chunk or the one before.
+template <typename VT>
+struct SymCarry {
+    VT v1 = VT(0), v2 = VT(0);
+    double xlo1 = 0.0, xlo2 = 0.0, xown1 = 0.0, xown2 = 0.0;
+};
+
+template <int NS, bool CONT, typename VT, class Epi>
+__device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
+                                          const double *__restrict__ x, int64_t c, SymCarry<VT> &cy, Epi &&epi) {
+#pragma clang fp contract(off)
+    constexpr int DS = NS / 2, NH = DS + 1;
+    const int64_t i = c * kDiaChunk + threadIdx.x;
+    const int64_t i2 = i + kBlock;
+    const bool one = i < n, two = i2 < n;
+    const int64_t j1 = one ? i : 0, j2 = two ? i2 : 0;
+    const uint32_t m1 = one ? (uint32_t)sn.mask[i] : 0u;
+    const uint32_t m2 = two ? (uint32_t)sn.mask[i2] : 0u;
+    const VT *__restrict__ base = dv + c * NH * kDiaChunk + threadIdx.x;
+    VT v1[NS], v2[NS];
+    double x1[NS], x2[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int64_t d = sn.ofs[s];
+        const int64_t r1 = ((m1 >> s) & 1u) ? i + d : j1;
+        const int64_t r2 = ((m2 >> s) & 1u) ? i2 + d : j2;
+        if (s >= DS) {
+            v1[s] = __builtin_nontemporal_load(&base[(s - DS) * kDiaChunk]);
+            v2[s] = __builtin_nontemporal_load(&base[(s - DS) * kDiaChunk + kBlock]);
+        } else if (CONT && s == 0) {
+            v1[s] = cy.v1;
+            v2[s] = cy.v2;
+        } else {
+            v1[s] = dv[dia_index(r1, DS - s, NH)];
+            v2[s] = dv[dia_index(r2, DS - s, NH)];
+        }
+        if (CONT && s == 0) {
+            x1[s] = cy.xlo1;
+            x2[s] = cy.xlo2;
+        } else if (CONT && s == DS) {
+            x1[s] = cy.xown1;
+            x2[s] = cy.xown2;
+        } else if (s == NS - 1) {
+            x1[s] = x[i + d < n ? i + d : j1];
+            x2[s] = x[i2 + d < n ? i2 + d : j2];
+        } else {
+            x1[s] = x[r1];
+            x2[s] = x[r2];
+        }
+    }
+    double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const double p1 = (double)v1[s] * x1[s];
+        const double p2 = (double)v2[s] * x2[s];
+        if ((m1 >> s) & 1u) a1 = a1 + p1;
+        if ((m2 >> s) & 1u) a2 = a2 + p2;
+    }
+    cy.v1 = v1[NS - 1];
+    cy.v2 = v2[NS - 1];
+    cy.xlo1 = x1[DS];
+    cy.xlo2 = x2[DS];
+    cy.xown1 = x1[NS - 1];
+    cy.xown2 = x2[NS - 1];
+    if constexpr (std::is_invocable_v<Epi, int64_t, double, double>) {
+        if (one) epi(i, a1, x1[DS]);
+        if (two) epi(i2, a2, x2[DS]);
+    } else {
+        if (one) epi(i, a1);
+        if (two) epi(i2, a2);
+    }
+}
+
 template <int NS, typename VT, class Epi>
 __device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                              const double *__restrict__ x, Epi &&epi) {
-#pragma clang fp contract(off)
     static_assert(NS == 5 || NS == 7 || NS == 9, "half form for 5, 7 or 9 diagonals");
-    constexpr int DS = NS / 2, NH = DS + 1;
-    const PencilWalk pw(n, sn.ofs[NS - 1]);
-    const uint16_t *__restrict__ mask = sn.mask;
+    const int64_t omax = sn.ofs[NS - 1];
+    SymCarry<VT> cy;
+    if (omax % kDiaChunk != 0) {
+        const ChunkWalk cw(dia_chunks(n));
+        for (int64_t c = cw.first; c < cw.hi; c += cw.stride) sym_chunk<NS, false>(sn, dv, n, x, c, cy, epi);
+        return;
+    }
+    const int P = sn.pencil;
+    const PencilWalk pw(n, omax, P);
     for (int64_t it = pw.first; it < pw.items; it += pw.stride) {
         const int64_t col = pw.c0 + it % pw.ncx, seg = it / pw.ncx;
-        VT carry1 = VT(0), carry2 = VT(0);
-        double xlo1 = 0.0, xlo2 = 0.0, xown1 = 0.0, xown2 = 0.0;
-        for (int t = 0; t < kPencil; ++t) {
-            const int64_t c = (seg * kPencil + t) * pw.cols + col;
+        int64_t c = seg * P * pw.cols + col;
+        if (c >= pw.nch) continue;
+        sym_chunk<NS, false>(sn, dv, n, x, c, cy, epi);
+        for (int t = 1; t < P; ++t) {
+            c += pw.cols;
             if (c >= pw.nch) break;
-            const int64_t i = c * kDiaChunk + threadIdx.x;
-            const int64_t i2 = i + kBlock;
-            const bool one = i < n, two = i2 < n;
-            const int64_t j1 = one ? i : 0, j2 = two ? i2 : 0;
-            const uint32_t m1 = one ? (uint32_t)mask[i] : 0u;
-            const uint32_t m2 = two ? (uint32_t)mask[i2] : 0u;
-            const VT *__restrict__ base = dv + c * NH * kDiaChunk + threadIdx.x;
-            VT v1[NS], v2[NS];
-            double x1[NS], x2[NS];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const int64_t d = sn.ofs[s];
-                const int64_t r1 = ((m1 >> s) & 1u) ? i + d : j1;
-                const int64_t r2 = ((m2 >> s) & 1u) ? i2 + d : j2;
-                if (s >= DS) {
-                    v1[s] = __builtin_nontemporal_load(&base[(s - DS) * kDiaChunk]);
-                    v2[s] = __builtin_nontemporal_load(&base[(s - DS) * kDiaChunk + kBlock]);
-                } else if (s == 0 && t > 0) {
-                    v1[s] = carry1;
-                    v2[s] = carry2;
-                } else {
-                    v1[s] = dv[dia_index(r1, DS - s, NH)];
-                    v2[s] = dv[dia_index(r2, DS - s, NH)];
-                }
-                if (t > 0 && s == 0) {
-                    x1[s] = xlo1;
-                    x2[s] = xlo2;
-                } else if (t > 0 && s == DS) {
-                    x1[s] = xown1;
-                    x2[s] = xown2;
-                } else if (s == NS - 1) {
-                    x1[s] = x[i + d < n ? i + d : j1];
-                    x2[s] = x[i2 + d < n ? i2 + d : j2];
-                } else {
-                    x1[s] = x[r1];
-                    x2[s] = x[r2];
-                }
-            }
-            double a1 = 0.0, a2 = 0.0;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const double p1 = (double)v1[s] * x1[s];
-                const double p2 = (double)v2[s] * x2[s];
-                if ((m1 >> s) & 1u) a1 = a1 + p1;
-                if ((m2 >> s) & 1u) a2 = a2 + p2;
-            }
-            carry1 = v1[NS - 1];
-            carry2 = v2[NS - 1];
-            xlo1 = x1[DS];
-            xlo2 = x2[DS];
-            xown1 = x1[NS - 1];
-            xown2 = x2[NS - 1];
-            if constexpr (std::is_invocable_v<Epi, int64_t, double, double>) {
-                if (one) epi(i, a1, x1[DS]);
-                if (two) epi(i2, a2, x2[DS]);
-            } else {
-                if (one) epi(i, a1);
-                if (two) epi(i2, a2);
-            }
+            sym_chunk<NS, true>(sn, dv, n, x, c, cy, epi);
         }
     }
 }

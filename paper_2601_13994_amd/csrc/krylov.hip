@@ -943,7 +943,7 @@ static hsla_status values_symmetric(hsla_handle *h, const hsla_pattern *p, int B
 hsla_status launch_spmv(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *x,
                         double *y, hipStream_t s) {
     if (p->n == 0 || B == 0) return HSLA_OK;
-    const Pat A = pat_of(p);
+    Pat A = pat_of(p);
     if (p->format == HSLA_FORMAT_DIAGONAL && A.sn.mask) {
         // the half form where the values allow it, else the full copy
         bool half = false;
@@ -957,7 +957,8 @@ hsla_status launch_spmv(hsla_handle *h, const hsla_pattern *p, int B, const doub
         if (st != HSLA_OK) return st;
         double *dia = (double *)h->ws;
         const int Gv = grid_blocks(h, kBlock * 4, A.n, B, 8);
-        const int Gd = half ? grid_blocks(h, kDiaChunk * kPencil, A.n, B, 8) : grid_blocks(h, kDiaChunk, A.n, B, 8);
+        A.sn.pencil = pencil_len(A.sn, A.n, B, h->dev.num_cu);
+        const int Gd = grid_blocks(h, half ? (int64_t)kDiaChunk * A.sn.pencil : kDiaChunk, A.n, B, 8);
         if (half)
             k_to_dia_sym<double><<<dim3(Gv, B), kBlock, 0, s>>>(A.n, A.rp, A.sn, A.nnz, values, dia);
         else
@@ -1145,7 +1146,7 @@ static hsla_status decide_half(hsla_handle *h, const hsla_pattern *p, const Pat 
 
 // Grid sizes, SpMV forms and workspace layout of one solve.
 struct Plan {
-    int nvec, Gt, Gv, nsA, nsF, Gd, Gs, Gf;
+    int nvec, Gt, Gv, nsA, nsF, Gd, Gs, Gf, pencil;
     size_t diaA, diaL, diaU;
     Layout lay;
 };
@@ -1168,7 +1169,9 @@ static Plan plan_solve(hsla_handle *h, const Tune &tn, const Pat &A, const FPat 
     pl.nsA = tn.half ? kSymNS + A.sn.nofs : tn.dia ? dia_slots(A.sn) : 0;
     const bool fsai = pre == PRE_FSAI && L && U;
     pl.nsF = fsai && L->sn.mask && U->sn.mask ? std::max(dia_slots(L->sn), dia_slots(U->sn)) : 0;
-    pl.Gd = tn.half ? grid_blocks(h, kDiaChunk * kPencil, n, B, tn.sym_cu) : grid_blocks(h, kDiaChunk, n, B, tn.dia_cu);
+    pl.pencil = tn.half ? pencil_len(A.sn, n, B, h->dev.num_cu) : 1;
+    pl.Gd = tn.half ? grid_blocks(h, (int64_t)kDiaChunk * pl.pencil, n, B, tn.sym_cu)
+                    : grid_blocks(h, kDiaChunk, n, B, tn.dia_cu);
     pl.Gs = pl.nsA ? pl.Gd : pl.Gt;
     pl.Gf = pl.nsF ? grid_blocks(h, kDiaChunk, n, B, 8) : pl.Gt;
     const size_t drows = (size_t)dia_chunks(n) * kDiaChunk;
@@ -1200,6 +1203,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
     char *ws = (char *)h->ws;
     SolveCall c{};
     c.A = A;
+    c.A.sn.pencil = pl.pencil;
     if (L) c.L = *L;
     if (U) c.U = *U;
     c.B = B;
@@ -1535,10 +1539,11 @@ hsla_status workspace_size(hsla_handle *h, const hsla_pattern *p, int B, const h
 // symmetric); it is used only by solves whose values are symmetric, so the
 // full copy and the tiles are ranked among themselves for the others.
 hsla_status autotune(hsla_handle *h, hsla_pattern *p, int B, int effort, hsla_tuning *out, hipStream_t s) {
-    const Pat A = pat_of(p);
+    Pat A = pat_of(p);
     const int64_t n = p->n, nnz = p->nnz;
     const bool dia_ok = A.sn.mask != nullptr;
     const bool half_ok = dia_ok && p->pattern_symmetric && stencil_half_ok(A.sn);
+    if (half_ok) A.sn.pencil = pencil_len(A.sn, n, B, h->dev.num_cu);
     const size_t rows = dia_ok ? (size_t)dia_chunks(n) * kDiaChunk : 0;
     const size_t nv = align_up(sizeof(double) * (size_t)B * (nnz > 0 ? nnz : 1), 256);
     const size_t nx = align_up(sizeof(double) * (size_t)B * n, 256);
@@ -1567,7 +1572,7 @@ hsla_status autotune(hsla_handle *h, hsla_pattern *p, int B, int effort, hsla_tu
     enum { F_DIA = 0, F_TILES = 1, F_HALF = 2 };
     auto time = [&](int form, int cu, double *us) -> hipError_t {
         const int ns = form == F_HALF ? kSymNS + A.sn.nofs : dia_slots_for(A.sn.nofs);
-        const int gx = form == F_HALF  ? grid_blocks(h, kDiaChunk * kPencil, n, B, cu)
+        const int gx = form == F_HALF  ? grid_blocks(h, (int64_t)kDiaChunk * A.sn.pencil, n, B, cu)
                        : form == F_DIA ? grid_blocks(h, kDiaChunk, n, B, cu)
                                        : grid_blocks(h, kWavesPerBlock, p->ntiles, B, cu);
         const dim3 g(gx, B);

@@ -193,11 +193,13 @@ def _grid7(nx, ny, nz, seed, keep=None):
 
 
 @pytest.mark.parametrize("shape,keep", [((32, 32, 37), None), ((32, 32, 37), 37788), ((512, 20, 1), None),
-                                        ((16, 32, 29), 14500), ((64, 64, 21), 85000)])
+                                        ((16, 32, 29), 14500), ((64, 64, 21), 85000), ((37, 41, 1), None),
+                                        ((100, 30, 7), 20000)])
 def test_half_form_spmv_bitwise(orc, shape, keep):
-    """The symmetric half form (main + upper diagonals stored, pencil walk)
-    equals the CSR SpMV bit for bit; nonsymmetric values on the same pattern
-    take the full copy, also bitwise."""
+    """The symmetric half form (main + upper diagonals stored; pencil walk
+    when the largest offset is a whole number of 512-row chunks, chunk walk
+    otherwise) equals the CSR SpMV bit for bit; nonsymmetric values on the
+    same pattern take the full copy, also bitwise."""
     a = _grid7(*shape, seed=11, keep=keep)
     pat = pattern(a)
     assert pat.stencil[0]
