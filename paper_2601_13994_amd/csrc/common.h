@@ -50,7 +50,8 @@ struct alignas(128) SysState {
     int32_t s_exit;  // BiCGStab: ||s|| <= tol, finish with x += alpha p_hat
     int32_t restart_pending;
     int32_t bad_diag;  // set when Jacobi finds a missing or zero diagonal
-    int32_t pad[2];
+    int32_t xpend;     // CG: the stopping iteration's x += alpha p is still to be applied
+    int32_t pad;
 };
 
 struct DevInfo {

@@ -311,37 +311,35 @@ __global__ __launch_bounds__(kBlock) void k_fin_alpha(Sys S, int G) {
     }
 }
 
-// x += alpha p, r -= alpha q; partials of r.r and (Jacobi) r.D^{-1}r.
+// r -= alpha q; partials of r.r and (Jacobi) r.D^{-1}r.  x += alpha p of
+// the same iteration is applied by the direction kernel, which reads p
+// anyway, so p is read once per iteration.
 template <int PRE>
 __global__ __launch_bounds__(kBlock) void k_cg_update(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
     if (stopped(st)) return;
     const double alpha = st.alpha;
-    double *__restrict__ x = S.x + vo;
     double *__restrict__ r = S.r + vo;
-    const double *__restrict__ p = S.p + vo;
     const double *__restrict__ q = S.q + vo;
     const double *__restrict__ dinv = S.dinv + vo;
     double acc[2] = {0.0, 0.0};  // r.r, r.z
     GRID_LOOP_BEGIN(A.n)
-            double xv[4], pv[4], rv[4], qv[4], dv[4];
+            double rv[4], qv[4], dv[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t e = i_ + j * S_;
-                xv[j] = x[e]; pv[j] = p[e]; rv[j] = r[e]; qv[j] = q[e];
+                rv[j] = r[e]; qv[j] = q[e];
                 dv[j] = PRE == PRE_JACOBI ? dinv[e] : 1.0;
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t e = i_ + j * S_;
-                x[e] = xv[j] + alpha * pv[j];
                 const double ri = rv[j] - alpha * qv[j];
                 r[e] = ri;
                 acc[0] += ri * ri;
                 if (PRE == PRE_JACOBI) acc[1] += ri * (dv[j] * ri);
             }
     GRID_LOOP_TAIL
-            x[i_] = x[i_] + alpha * p[i_];
             const double ri = r[i_] - alpha * q[i_];
             r[i_] = ri;
             acc[0] += ri * ri;
@@ -351,11 +349,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Pat A, Sys S) {
     block_partial<2>(acc, part);
 }
 
-// Stop test on ||r||, then (Jacobi / none) rho' = r.z, beta = rho'/rho.
+// Stop test on ||r||, then (Jacobi / none) rho' = r.z, beta = rho'/rho.  A
+// system that stops here still has this iteration's x += alpha p to apply
+// (xpend); one already stopped clears it.
 template <int PRE>
 __global__ __launch_bounds__(kBlock) void k_fin_beta(Sys S, int G) {
     FIN_OFFSETS(S, G)
-    if (stopped(st)) return;
+    if (stopped(st)) {
+        if (threadIdx.x == 0) st.xpend = 0;
+        return;
+    }
     double tot[2];
     reduce_partials<2>(part, G, tot);
     if (threadIdx.x != 0) return;
@@ -365,42 +368,72 @@ __global__ __launch_bounds__(kBlock) void k_fin_beta(Sys S, int G) {
     if (!isfinite(rn)) {
         st.status = HSLA_ERR_NONFINITE;
         st.done = 1;
+        st.xpend = 1;
     } else if (rn <= st.tol) {
         st.status = HSLA_OK;
         st.done = 1;
+        st.xpend = 1;
     } else if (st.iters >= st.max_iter) {
         st.status = HSLA_NOT_CONVERGED;
         st.done = 1;
+        st.xpend = 1;
     } else if (PRE != PRE_FSAI) {
         st.beta = tot[1] / st.rho;
         st.rho = tot[1];
     }
 }
 
-// p = z + beta p with z = D^{-1} r (Jacobi), r (none) or the stored z (FSAI).
-template <int PRE>
+// x += alpha p, then p = z + beta p with z = D^{-1} r (Jacobi), r (none) or
+// the stored z (FSAI); a system that stopped in this iteration takes only
+// the x update.  XUP = false (the FSAI start, p = z): no x update.
+template <int PRE, bool XUP = true>
 __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
     (void)part;
-    if (stopped(st)) return;
-    const double beta = st.beta;
+    const bool xonly = stopped(st);
+    if (xonly && (!XUP || !st.xpend)) return;
+    const double alpha = st.alpha, beta = st.beta;
+    double *__restrict__ x = S.x + vo;
     double *__restrict__ p = S.p + vo;
     const double *__restrict__ r = S.r + vo;
     const double *__restrict__ dinv = S.dinv + vo;
     const double *__restrict__ z = S.z + vo;
+    if (xonly) {
+        GRID_LOOP_BEGIN(A.n)
+                double xv[4], pv[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t e = i_ + j * S_;
+                    xv[j] = x[e];
+                    pv[j] = p[e];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) x[i_ + j * S_] = xv[j] + alpha * pv[j];
+        GRID_LOOP_TAIL
+                x[i_] = x[i_] + alpha * p[i_];
+        GRID_LOOP_END
+        return;
+    }
     GRID_LOOP_BEGIN(A.n)
-            double zv[4], pv[4];
+            double zv[4], pv[4], xv[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t e = i_ + j * S_;
                 zv[j] = PRE == PRE_JACOBI ? dinv[e] * r[e] : PRE == PRE_NONE ? r[e] : z[e];
                 pv[j] = p[e];
+                if (XUP) xv[j] = x[e];
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) p[i_ + j * S_] = zv[j] + beta * pv[j];
+            for (int j = 0; j < 4; ++j) {
+                const int64_t e = i_ + j * S_;
+                if (XUP) x[e] = xv[j] + alpha * pv[j];
+                p[e] = zv[j] + beta * pv[j];
+            }
     GRID_LOOP_TAIL
             const double zi = PRE == PRE_JACOBI ? dinv[i_] * r[i_] : PRE == PRE_NONE ? r[i_] : z[i_];
-            p[i_] = zi + beta * p[i_];
+            const double pi = p[i_];
+            if (XUP) x[i_] = x[i_] + alpha * pi;
+            p[i_] = zi + beta * pi;
     GRID_LOOP_END
 }
 
@@ -448,6 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_fsai(Sys S, int G, int setup) {
     if (!isfinite(tot[0])) {
         st.status = HSLA_ERR_NONFINITE;
         st.done = 1;
+        st.xpend = setup ? 0 : 1;
     } else if (setup) {
         st.rho = tot[0];
         st.beta = 0.0;
@@ -1269,7 +1303,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
                 NS_LAUNCH(k_fsai_lower, nsF, gfs, A, c.L, S);
                 NS_LAUNCH(k_fsai_upper_dot, nsF, gfs, A, c.U, S);
                 k_fin_fsai<<<gf, kBlock, 0, s>>>(S, Gf, 1);
-                k_cg_direction<PRE_FSAI><<<gv, kBlock, 0, s>>>(A, S);
+                k_cg_direction<PRE_FSAI, false><<<gv, kBlock, 0, s>>>(A, S);
                 break;
         }
     } else {
