@@ -248,3 +248,33 @@ def test_half_form_solves(orc, method):
                                     rtol=1e-12)
         assert rel(gb[0].cpu().numpy(), gb_o) <= 1e-8
         assert rel(gA[0].cpu().numpy(), gA_o) <= 1e-8
+
+
+@pytest.mark.parametrize("fmt", ["auto", "csr"])
+@pytest.mark.parametrize("precond", ["jacobi", "none", "fsai"])
+def test_truncated_iterates_match_oracle(orc, fmt, precond):
+    """Runs cut at k = 1, 2, 7 iterations (status NOT_CONVERGED) return the
+    k-th iterate, x included (the direction kernel applies the stopping
+    iteration's x += alpha p), in the half, full and tile forms."""
+    m = 14
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m))
+    b = np.random.default_rng(12).standard_normal(a.n)
+    pat = pattern(a)
+    pat.set_format(fmt)
+    kw = {}
+    if precond == "fsai":
+        rpL, colL, gh = orc.fsai(mpnn.scaled(a))
+        G, GT = _lib.fsai_factors(pat, t64(a.val), torch.as_tensor(gh.astype(np.float32)).to(dev()))
+        kw = dict(G=G, GT=GT)
+    try:
+        for k in (1, 2, 7):
+            opts = _lib.make_opts(method="cg", precond=precond, rtol=1e-14, max_iter=k, persistent=False, **kw)
+            x, infos, st = _lib.solve(pat, t64(a.val), t64(b), opts)
+            assert st == _lib.NOT_CONVERGED and infos[0]["iters"] == k
+            if precond == "fsai":
+                ref = orc.fsai_pcg(a, rpL, colL, G.cpu().numpy().astype(np.float64), b, rtol=1e-14, max_iter=k)
+            else:
+                ref = orc.cg(a, b, precond=precond, rtol=1e-14, max_iter=k)
+            assert rel(x.cpu().numpy(), ref.x) <= 1e-12, (k, rel(x.cpu().numpy(), ref.x))
+    finally:
+        pat.set_format("auto")
