@@ -71,7 +71,7 @@ typedef struct hsla_opts {
                             on systems of at most 4096 rows of <= 16 entries, or on batches of at
                             least one system per compute unit with at most 131072 entries each,
                             runs as one persistent launch, one workgroup per system;
-                            0: always per-iteration kernels                                     */
+                            0: always per-iteration kernels (ragged batches: the segmented path) */
 } hsla_opts;
 
 /* Per-system result information. */
@@ -228,9 +228,14 @@ hsla_status hsla_adjoint_batched(hsla_handle *h, const hsla_pattern *p, int32_t 
                                  hsla_info *infos, void *stream);
 
 /* B systems with distinct patterns and sizes (the paper's matrix list with
- * distinct patterns) solved with CG (Jacobi or no preconditioner, x0 = 0)
- * in one persistent launch: workgroups take systems from a queue, largest
- * first, and iterate each to its own stop test.  System s owns rows
+ * distinct patterns) solved with CG (Jacobi or no preconditioner, x0 = 0),
+ * each to its own stop test.  Batches of at least 2^20 rows with a system
+ * above 8192 rows, and every batch when opts->persistent is 0, run
+ * segmented: per-iteration kernels stream all systems as one block-diagonal
+ * operator in 512-row chunks (a chunk never spans two systems) with each
+ * system's sums and scalars kept apart.  Other batches run in one persistent
+ * launch: workgroups take systems from a queue, largest first.  A system's
+ * result does not depend on the rest of the batch.  System s owns rows
  * [row_off[s], row_off[s+1]) of b and x (float64) and entries
  * [nnz_off[s], nnz_off[s+1]) of col (int32, local column indices) and values
  * (float64); its local row pointer (n_s + 1 int32 entries starting at 0)

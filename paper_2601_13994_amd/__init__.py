@@ -128,7 +128,8 @@ def from_coo(values: torch.Tensor, row: torch.Tensor, col: torch.Tensor, n: int)
 
 class SparseCSRList:
     """Matrices with distinct sparsity patterns and sizes (the paper's matrix
-    list); solved together in one persistent launch.  Each element is given
+    list); solved together in one persistent launch, or, for large batches,
+    by per-iteration kernels over all systems at once.  Each element is given
     as (values float64 (nnz_s,), row_ptr int32 (n_s+1,), col int32 (nnz_s,))
     tensors on one GPU; they are concatenated once here."""
 
@@ -154,10 +155,14 @@ class SparseCSRList:
     def split(self, v: torch.Tensor):
         return list(torch.split(v, self.n))
 
-    def solve(self, bs, rtol: float = 1e-8, atol: float = 0.0, precond: str = "jacobi", max_iter: int = 0):
+    def solve(self, bs, rtol: float = 1e-8, atol: float = 0.0, precond: str = "jacobi", max_iter: int = 0,
+              persistent: bool = True):
         """Solves every system; `bs` is a list of right-hand sides or their
-        concatenation.  Returns (list of x, infos, status)."""
+        concatenation.  persistent=False always takes the segmented
+        per-iteration path (large batches take it anyway).  Returns (list of
+        x, infos, status)."""
         b = torch.cat(list(bs)) if isinstance(bs, (list, tuple)) else bs
-        opts = _lib.make_opts(method="cg", precond=precond, rtol=rtol, atol=atol, max_iter=max_iter)
+        opts = _lib.make_opts(method="cg", precond=precond, rtol=rtol, atol=atol, max_iter=max_iter,
+                              persistent=persistent)
         x, infos, st = _lib.solve_ragged(self.row_off, self.nnz_off, self.row_ptr, self.col, self.values, b, opts)
         return self.split(x), infos, st

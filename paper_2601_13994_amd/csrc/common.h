@@ -54,6 +54,76 @@ struct alignas(128) SysState {
     int32_t pad;
 };
 
+// Scalar steps of the CG recurrence (Alg. 1), run by thread 0 of a
+// finalize block once the system's sums are complete; shared by the batched
+// solver and the segmented ragged solver.
+// Start: ||b||, tol = max(rtol ||b||, atol), stop test on r0, rho = r.z.
+__device__ __forceinline__ void cg_step_init(SysState &st, double bb, double rr, double rz, double rtol,
+                                             double atol) {
+    const double bn = sqrt(bb);
+    double tol = rtol * bn;
+    if (atol > tol) tol = atol;
+    st.bnorm = bn;
+    st.tol = tol;
+    st.rnorm2 = rr;
+    st.iters = 0;
+    const double rn = sqrt(rr);
+    if (st.bad_diag) {
+        st.status = HSLA_ERR_ZERO_DIAGONAL;
+        st.done = 1;
+    } else if (!isfinite(rn) || !isfinite(bn)) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+    } else if (rn <= tol) {
+        st.status = HSLA_OK;
+        st.done = 1;
+    } else if (st.max_iter <= 0) {
+        st.status = HSLA_NOT_CONVERGED;
+        st.done = 1;
+    } else {
+        st.rho = rz;
+        st.beta = 0.0;
+    }
+}
+
+// alpha = rho / sigma with sigma = p.Ap, or breakdown when sigma <= 0.
+__device__ __forceinline__ void cg_step_alpha(SysState &st, double sigma) {
+    if (!isfinite(sigma)) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+    } else if (!(sigma > 0.0)) {
+        st.status = HSLA_BREAKDOWN;
+        st.done = 1;
+    } else {
+        st.alpha = st.rho / sigma;
+    }
+}
+
+// After r -= alpha q: stop test on ||r|| (a system stopping here still has
+// this iteration's x += alpha p to apply: xpend), else, when rz is the new
+// r.z (with_rho), beta = rz / rho and rho = rz.
+__device__ __forceinline__ void cg_step_beta(SysState &st, double rr, double rz, bool with_rho) {
+    st.iters += 1;
+    st.rnorm2 = rr;
+    const double rn = sqrt(rr);
+    if (!isfinite(rn)) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+        st.xpend = 1;
+    } else if (rn <= st.tol) {
+        st.status = HSLA_OK;
+        st.done = 1;
+        st.xpend = 1;
+    } else if (st.iters >= st.max_iter) {
+        st.status = HSLA_NOT_CONVERGED;
+        st.done = 1;
+        st.xpend = 1;
+    } else if (with_rho) {
+        st.beta = rz / st.rho;
+        st.rho = rz;
+    }
+}
+
 struct DevInfo {
     int num_cu = 256;
 };

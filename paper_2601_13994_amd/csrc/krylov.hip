@@ -239,30 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_cg_init(Sys S, int G, double rto
     double tot[3];
     reduce_partials<3>(part, G, tot);
     if (threadIdx.x != 0) return;
-    const double bn = sqrt(tot[0]);
-    double tol = rtol * bn;
-    if (atol > tol) tol = atol;
-    st.bnorm = bn;
-    st.tol = tol;
-    st.rnorm2 = tot[1];
-    st.iters = 0;
-    const double rn = sqrt(tot[1]);
-    if (st.bad_diag) {
-        st.status = HSLA_ERR_ZERO_DIAGONAL;
-        st.done = 1;
-    } else if (!isfinite(rn) || !isfinite(bn)) {
-        st.status = HSLA_ERR_NONFINITE;
-        st.done = 1;
-    } else if (rn <= tol) {
-        st.status = HSLA_OK;
-        st.done = 1;
-    } else if (st.max_iter <= 0) {
-        st.status = HSLA_NOT_CONVERGED;
-        st.done = 1;
-    } else {
-        st.rho = (PRE == PRE_FSAI) ? 0.0 : tot[2];
-        st.beta = 0.0;
-    }
+    cg_step_init(st, tot[0], tot[1], PRE == PRE_FSAI ? 0.0 : tot[2], rtol, atol);
 }
 
 // q = A p and partials of sigma = p.q.
@@ -299,16 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_alpha(Sys S, int G) {
     double tot[1];
     reduce_partials<1>(part, G, tot);
     if (threadIdx.x != 0) return;
-    const double sigma = tot[0];
-    if (!isfinite(sigma)) {
-        st.status = HSLA_ERR_NONFINITE;
-        st.done = 1;
-    } else if (!(sigma > 0.0)) {
-        st.status = HSLA_BREAKDOWN;
-        st.done = 1;
-    } else {
-        st.alpha = st.rho / sigma;
-    }
+    cg_step_alpha(st, tot[0]);
 }
 
 // r -= alpha q; partials of r.r and (Jacobi) r.D^{-1}r.  x += alpha p of
@@ -362,25 +330,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_beta(Sys S, int G) {
     double tot[2];
     reduce_partials<2>(part, G, tot);
     if (threadIdx.x != 0) return;
-    st.iters += 1;
-    st.rnorm2 = tot[0];
-    const double rn = sqrt(tot[0]);
-    if (!isfinite(rn)) {
-        st.status = HSLA_ERR_NONFINITE;
-        st.done = 1;
-        st.xpend = 1;
-    } else if (rn <= st.tol) {
-        st.status = HSLA_OK;
-        st.done = 1;
-        st.xpend = 1;
-    } else if (st.iters >= st.max_iter) {
-        st.status = HSLA_NOT_CONVERGED;
-        st.done = 1;
-        st.xpend = 1;
-    } else if (PRE != PRE_FSAI) {
-        st.beta = tot[1] / st.rho;
-        st.rho = tot[1];
-    }
+    cg_step_beta(st, tot[0], tot[1], PRE != PRE_FSAI);
 }
 
 // x += alpha p, then p = z + beta p with z = D^{-1} r (Jacobi), r (none) or

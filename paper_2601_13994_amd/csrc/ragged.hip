@@ -588,6 +588,389 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
     return (hsla_status)worst;
 }
 
+// ---------------------------------------------------------------------------
+// Segmented ragged solve: the systems of a large ragged batch are treated as
+// one block-diagonal operator streamed by per-iteration kernels over the
+// whole chip, with each system's reductions and CG scalars kept apart.  The
+// rows are cut into chunks of kSegRows that never span two systems; every
+// reducing kernel writes one partial per chunk, and a one-block-per-system
+// finalize adds a system's chunk partials in chunk order and advances its
+// recurrence (the same scalar steps as the batched solver).  Chunks follow
+// the system's own rows, so a system's result does not depend on the batch.
+// ---------------------------------------------------------------------------
+constexpr int kSegRows = 512;
+constexpr int kSegW = kBlock / kWave;
+// Batches of at least kSegMinRows rows with a system above kSegMinN rows run
+// segmented (one workgroup streams a large system slower than the chip
+// streams it); smaller ones run persistent.
+constexpr int64_t kSegMinRows = 1 << 20;
+constexpr int64_t kSegMinN = 8192;
+
+struct Seg {
+    Args a;
+    const int32_t *csys;    // chunk -> system
+    const int32_t *crow;    // chunk -> its first row, local to the system
+    const int32_t *cfirst;  // system -> its first chunk ([B + 1])
+    SysState *st;           // [B]
+    double *part;           // [chunks][4]
+};
+
+struct SegChunk {
+    int32_t s, lo, hi;  // system, local rows [lo, hi)
+    int64_t r0, k0;     // the system's first row and entry
+    const int32_t *rp;  // the system's local row pointer
+};
+
+__device__ __forceinline__ SegChunk seg_chunk(const Seg &g, int32_t c) {
+    SegChunk k;
+    k.s = g.csys[c];
+    k.r0 = g.a.row_off[k.s];
+    k.k0 = g.a.nnz_off[k.s];
+    const int32_t n = (int32_t)(g.a.row_off[k.s + 1] - k.r0);
+    k.lo = g.crow[c];
+    k.hi = k.lo + kSegRows < n ? k.lo + kSegRows : n;
+    k.rp = g.a.rp + k.r0 + k.s;
+    return k;
+}
+
+// Sum of a system's chunk partials (value j), fixed order; thread 0.
+template <int NV>
+__device__ __forceinline__ void seg_reduce(const Seg &g, int32_t s, double (&tot)[NV]) {
+    __shared__ double sh[NV * kWavesPerBlock];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) tot[j] = 0.0;
+    for (int32_t c = g.cfirst[s] + threadIdx.x; c < g.cfirst[s + 1]; c += blockDim.x) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) tot[j] += g.part[(int64_t)c * 4 + j];
+    }
+    block_sum<NV>(tot, sh);
+}
+
+template <int NV>
+__device__ __forceinline__ void seg_partial(const Seg &g, int32_t c, double (&v)[NV]) {
+    __shared__ double sh[NV * kWavesPerBlock];
+    block_sum<NV>(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) g.part[(int64_t)c * 4 + j] = v[j];
+    }
+}
+
+__global__ void k_seg_reset(SysState *st, int32_t B, int64_t max_iter) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x) {
+        SysState z;
+        memset(&z, 0, sizeof z);
+        z.max_iter = max_iter;
+        z.rho = z.alpha = z.omega = 1.0;
+        st[i] = z;
+    }
+}
+
+// x = 0, r = b, D^{-1} (1 without Jacobi), p = D^{-1} r; partials of b.b,
+// r.r, r.D^{-1}r and a missing-diagonal flag.
+__global__ __launch_bounds__(kBlock) void k_seg_init(Seg g) {
+    const int32_t c = blockIdx.x;
+    const SegChunk k = seg_chunk(g, c);
+    const Args &a = g.a;
+    const int32_t *col = a.col + k.k0;
+    const double *val = a.val + k.k0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t i = k.lo + threadIdx.x; i < k.hi; i += kBlock) {
+        double d = 0.0;
+        for (int32_t e = k.rp[i]; e < k.rp[i + 1]; ++e)
+            if (col[e] == i) d = val[e];
+        if (a.jacobi && d == 0.0) acc[3] = 1.0;
+        const double di = a.jacobi ? 1.0 / d : 1.0;
+        const int64_t gi = k.r0 + i;
+        const double bi = a.b[gi];
+        a.dinv[gi] = di;
+        a.x[gi] = 0.0;
+        a.r[gi] = bi;
+        a.p[gi] = di * bi;
+        acc[0] += bi * bi;
+        acc[1] += bi * bi;
+        acc[2] += bi * (di * bi);
+    }
+    seg_partial<4>(g, c, acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_fin_init(Seg g) {
+    const int32_t s = blockIdx.x;
+    double tot[4];
+    seg_reduce<4>(g, s, tot);
+    if (threadIdx.x != 0) return;
+    SysState &st = g.st[s];
+    if (tot[3] > 0.0) st.bad_diag = 1;
+    cg_step_init(st, tot[0], tot[1], tot[2], g.a.rtol, g.a.atol);
+}
+
+// q = A p for the chunk's rows (ascending per-row sums); partial of p.q.
+__global__ __launch_bounds__(kBlock) void k_seg_spmv_dot(Seg g) {
+    __shared__ double lds[kSegW * kChunk];
+    const int32_t c = blockIdx.x;
+    const SegChunk k = seg_chunk(g, c);
+    if (g.st[k.s].done) return;
+    const Args &a = g.a;
+    const double *p = a.p + k.r0;
+    double *q = a.q + k.r0;
+    double acc[1] = {0.0};
+    wg_spmv<kSegW>(k.hi - k.lo, k.rp + k.lo, a.col + k.k0, a.val + k.k0, p, lds, [&](int32_t i, double sum) {
+        const int32_t row = k.lo + i;
+        q[row] = sum;
+        acc[0] += p[row] * sum;
+    });
+    seg_partial<1>(g, c, acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_fin_alpha(Seg g) {
+    const int32_t s = blockIdx.x;
+    SysState &st = g.st[s];
+    if (st.done) return;
+    double tot[1];
+    seg_reduce<1>(g, s, tot);
+    if (threadIdx.x == 0) cg_step_alpha(st, tot[0]);
+}
+
+// r -= alpha q; partials of r.r and r.D^{-1}r.
+__global__ __launch_bounds__(kBlock) void k_seg_update(Seg g) {
+    const int32_t c = blockIdx.x;
+    const SegChunk k = seg_chunk(g, c);
+    const SysState &st = g.st[k.s];
+    if (st.done) return;
+    const double alpha = st.alpha;
+    const Args &a = g.a;
+    double acc[2] = {0.0, 0.0};
+    for (int32_t i = k.lo + threadIdx.x; i < k.hi; i += 2 * kBlock) {
+        double rv[2], qv[2], dv[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int32_t j = i + u * kBlock;
+            if (j < k.hi) {
+                rv[u] = a.r[k.r0 + j];
+                qv[u] = a.q[k.r0 + j];
+                dv[u] = a.dinv[k.r0 + j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int32_t j = i + u * kBlock;
+            if (j < k.hi) {
+                const double ri = rv[u] - alpha * qv[u];
+                a.r[k.r0 + j] = ri;
+                acc[0] += ri * ri;
+                acc[1] += ri * (dv[u] * ri);
+            }
+        }
+    }
+    seg_partial<2>(g, c, acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_fin_beta(Seg g) {
+    const int32_t s = blockIdx.x;
+    SysState &st = g.st[s];
+    if (st.done) {
+        if (threadIdx.x == 0) st.xpend = 0;
+        return;
+    }
+    double tot[2];
+    seg_reduce<2>(g, s, tot);
+    if (threadIdx.x == 0) cg_step_beta(st, tot[0], tot[1], true);
+}
+
+// x += alpha p, then p = D^{-1} r + beta p (only the x update for a system
+// that stopped in this iteration).
+__global__ __launch_bounds__(kBlock) void k_seg_direction(Seg g) {
+    const int32_t c = blockIdx.x;
+    const SegChunk k = seg_chunk(g, c);
+    const SysState &st = g.st[k.s];
+    const bool xonly = st.done != 0;
+    if (xonly && !st.xpend) return;
+    const double alpha = st.alpha, beta = st.beta;
+    const Args &a = g.a;
+    for (int32_t i = k.lo + threadIdx.x; i < k.hi; i += 2 * kBlock) {
+        double xv[2], pv[2], rv[2], dv[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int32_t j = i + u * kBlock;
+            if (j < k.hi) {
+                xv[u] = a.x[k.r0 + j];
+                pv[u] = a.p[k.r0 + j];
+                if (!xonly) {
+                    rv[u] = a.r[k.r0 + j];
+                    dv[u] = a.dinv[k.r0 + j];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int32_t j = i + u * kBlock;
+            if (j < k.hi) {
+                a.x[k.r0 + j] = xv[u] + alpha * pv[u];
+                if (!xonly) a.p[k.r0 + j] = dv[u] * rv[u] + beta * pv[u];
+            }
+        }
+    }
+}
+
+// Partials of ||b - A x||^2 and ||b||^2.
+__global__ __launch_bounds__(kBlock) void k_seg_residual(Seg g) {
+    __shared__ double lds[kSegW * kChunk];
+    const int32_t c = blockIdx.x;
+    const SegChunk k = seg_chunk(g, c);
+    const Args &a = g.a;
+    const double *b = a.b + k.r0;
+    double acc[2] = {0.0, 0.0};
+    wg_spmv<kSegW>(k.hi - k.lo, k.rp + k.lo, a.col + k.k0, a.val + k.k0, a.x + k.r0, lds,
+                   [&](int32_t i, double sum) {
+                       const double bi = b[k.lo + i];
+                       const double e = bi - sum;
+                       acc[0] += e * e;
+                       acc[1] += bi * bi;
+                   });
+    seg_partial<2>(g, c, acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_fin_residual(Seg g) {
+    const int32_t s = blockIdx.x;
+    double tot[2];
+    seg_reduce<2>(g, s, tot);
+    if (threadIdx.x != 0) return;
+    const SysState &st = g.st[s];
+    RInfo f;
+    f.iters = st.iters;
+    f.status = st.done ? st.status : HSLA_ERR_INTERNAL;
+    f.pad = 0;
+    const double rn = sqrt(st.rnorm2);
+    f.rel_residual = st.bnorm > 0 ? rn / st.bnorm : rn;
+    f.true_residual = tot[1] > 0 ? sqrt(tot[0]) / sqrt(tot[1]) : sqrt(tot[0]);
+    g.a.info[s] = f;
+}
+
+// Host side of the segmented solve; `a` has the ragged system description,
+// `ro` the host copy of its row offsets.
+static hsla_status run_segmented(hsla_handle *h, Args a, const hsla_opts &o, const std::vector<int64_t> &ro,
+                                 int64_t max_n, hsla_info *infos, hipStream_t s) {
+    const int32_t B = a.B;
+    const int64_t rows = ro[B];
+    std::vector<int32_t> cfirst(B + 1), csys, crow;
+    for (int32_t i = 0; i < B; ++i) {
+        cfirst[i] = (int32_t)csys.size();
+        const int64_t n = ro[i + 1] - ro[i];
+        for (int64_t r = 0; r < n; r += kSegRows) {
+            csys.push_back(i);
+            crow.push_back((int32_t)r);
+        }
+    }
+    const int32_t nch = (int32_t)csys.size();
+    cfirst[B] = nch;
+    size_t bytes = 0;
+    auto add = [&](size_t v) { bytes += (v + 255) / 256 * 256; };
+    add(sizeof(double) * 4 * (size_t)(rows > 0 ? rows : 1));
+    add(sizeof(int32_t) * (size_t)(nch > 0 ? nch : 1) * 2);
+    add(sizeof(int32_t) * (B + 1));
+    add(sizeof(SysState) * B);
+    add(sizeof(double) * 4 * (size_t)(nch > 0 ? nch : 1));
+    add(sizeof(RInfo) * B);
+    add(256);
+    hsla_status st = ensure_workspace(h, bytes);
+    if (st != HSLA_OK) return st;
+    st = ensure_host_state(h, B);
+    if (st != HSLA_OK) return st;
+    char *ws = (char *)h->ws;
+    size_t off = 0;
+    auto take = [&](size_t v) {
+        char *q = ws + off;
+        off += (v + 255) / 256 * 256;
+        return q;
+    };
+    double *vec = (double *)take(sizeof(double) * 4 * (size_t)(rows > 0 ? rows : 1));
+    a.r = vec;
+    a.p = vec + rows;
+    a.q = vec + 2 * rows;
+    a.dinv = vec + 3 * rows;
+    int32_t *tab = (int32_t *)take(sizeof(int32_t) * (size_t)(nch > 0 ? nch : 1) * 2);
+    int32_t *dfirst = (int32_t *)take(sizeof(int32_t) * (B + 1));
+    Seg g{};
+    g.st = (SysState *)take(sizeof(SysState) * B);
+    g.part = (double *)take(sizeof(double) * 4 * (size_t)(nch > 0 ? nch : 1));
+    a.info = (RInfo *)take(sizeof(RInfo) * B);
+    a.bad = (int32_t *)take(256);
+    a.queue = nullptr;
+    a.order = nullptr;
+    a.rtol = o.rtol;
+    a.atol = o.atol;
+    a.max_iter = o.max_iter > 0 ? o.max_iter : std::min<int64_t>(10 * std::max<int64_t>(max_n, 1), 100000);
+    a.jacobi = o.precond == HSLA_PRECOND_JACOBI;
+    // every pointer the kernels dereference must be set (rows/entries > 0)
+    if (!a.rp || !a.row_off || !a.nnz_off || !a.info || !a.bad ||
+        (rows > 0 && (!a.b || !a.x || !a.r || !a.p || !a.q || !a.dinv)))
+        return set_error(h, HSLA_ERR_INTERNAL, "segmented solve: unset kernel argument");
+    const int32_t no_bad = INT32_MAX;
+    HSLA_HIP(h, hipMemcpyAsync(a.bad, &no_bad, sizeof no_bad, hipMemcpyHostToDevice, s));
+    k_ragged_validate<<<std::min(B, 4096), 256, 0, s>>>(a);
+    int32_t bad = INT32_MAX;
+    HSLA_HIP(h, hipMemcpyAsync(&bad, a.bad, sizeof bad, hipMemcpyDeviceToHost, s));
+    HSLA_HIP(h, hipStreamSynchronize(s));
+    if (bad != INT32_MAX) return set_error(h, HSLA_ERR_INVALID_CSR, "system %d is not canonical CSR", bad);
+    g.a = a;
+    g.csys = tab;
+    g.crow = tab + nch;
+    g.cfirst = dfirst;
+    if (nch > 0) {
+        HSLA_HIP(h, hipMemcpyAsync(tab, csys.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, s));
+        HSLA_HIP(h, hipMemcpyAsync(tab + nch, crow.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, s));
+    }
+    HSLA_HIP(h, hipMemcpyAsync(dfirst, cfirst.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
+    k_seg_reset<<<(B + kBlock - 1) / kBlock, kBlock, 0, s>>>(g.st, B, a.max_iter);
+    if (nch > 0) k_seg_init<<<nch, kBlock, 0, s>>>(g);
+    k_seg_fin_init<<<B, kBlock, 0, s>>>(g);
+    HSLA_HIP(h, hipGetLastError());
+    // chunks of 8 iterations between host checks; every system stops by
+    // max_iter, so the loop ends
+    SysState *hs = h->h_state;
+    for (;;) {
+        HSLA_HIP(h, hipMemcpyAsync(hs, g.st, sizeof(SysState) * B, hipMemcpyDeviceToHost, s));
+        HSLA_HIP(h, hipStreamSynchronize(s));
+        bool all = true;
+        for (int32_t i = 0; i < B && all; ++i) all = hs[i].done != 0;
+        if (all || nch == 0) break;
+        for (int k = 0; k < 8; ++k) {
+            k_seg_spmv_dot<<<nch, kBlock, 0, s>>>(g);
+            k_seg_fin_alpha<<<B, kBlock, 0, s>>>(g);
+            k_seg_update<<<nch, kBlock, 0, s>>>(g);
+            k_seg_fin_beta<<<B, kBlock, 0, s>>>(g);
+            k_seg_direction<<<nch, kBlock, 0, s>>>(g);
+        }
+        HSLA_HIP(h, hipGetLastError());
+    }
+    if (nch > 0) k_seg_residual<<<nch, kBlock, 0, s>>>(g);
+    k_seg_fin_residual<<<B, kBlock, 0, s>>>(g);
+    HSLA_HIP(h, hipGetLastError());
+    std::vector<RInfo> hi(B);
+    HSLA_HIP(h, hipMemcpyAsync(hi.data(), a.info, sizeof(RInfo) * B, hipMemcpyDeviceToHost, s));
+    HSLA_HIP(h, hipStreamSynchronize(s));
+    int worst = HSLA_OK;
+    for (int i = 0; i < B; ++i) {
+        const int sst = hi[i].status;
+        if (sst < 0 || worst < 0)
+            worst = std::min(worst, sst);
+        else
+            worst = std::max(worst, sst);
+        if (infos) {
+            infos[i].iters = hi[i].iters;
+            infos[i].status = sst;
+            infos[i].method = HSLA_METHOD_CG;
+            infos[i].rel_residual = hi[i].rel_residual;
+            infos[i].true_residual = hi[i].true_residual;
+            infos[i].spmv_ms = 0.0;
+            infos[i].spmv_launches = 0;
+            infos[i].spmv_form = 0;
+            infos[i].reserved = 0;
+        }
+    }
+    return (hsla_status)worst;
+}
+
 }  // namespace rg
 
 // The register-resident kernel wins for every small system; the general
@@ -674,5 +1057,6 @@ extern "C" hsla_status hsla_solve_ragged(hsla_handle *h, int32_t B, const int64_
     a.val = d_values;
     a.b = d_b;
     a.x = d_x;
+    if (!o.persistent || (rows >= kSegMinRows && max_n > kSegMinN)) return run_segmented(h, a, o, ro, max_n, infos, s);
     return run_persistent(h, a, o, rows, no[B], max_n, order, infos, s);
 }

@@ -1,4 +1,5 @@
-"""GPU parity of the ragged persistent batch against the CPU oracle."""
+"""GPU parity of ragged batches against the CPU oracle, on the persistent
+one-workgroup-per-system kernel and on the segmented per-iteration path."""
 import numpy as np
 import pytest
 
@@ -19,7 +20,8 @@ def _knn(sample, lo, hi):
     return W.knn_system(sample, n_lo=lo, n_hi=hi)
 
 
-def test_ragged_knn_parity(orc):
+@pytest.mark.parametrize("persistent", [True, False])
+def test_ragged_knn_parity(orc, persistent):
     """k-NN Laplacians of different sizes, a zero right-hand side and an
     empty system: each result matches the oracle's CG and does not depend on
     the batch (bitwise equal when solved alone)."""
@@ -29,7 +31,7 @@ def test_ragged_knn_parity(orc):
     systems.insert(6, (empty, np.zeros(0)))
     mats = [(t64(a.val), t32(a.row_ptr), t32(a.col)) for a, _ in systems]
     L = hs.SparseCSRList(mats)
-    xs, infos, st = L.solve([t64(b) for _, b in systems], rtol=1e-12)
+    xs, infos, st = L.solve([t64(b) for _, b in systems], rtol=1e-12, persistent=persistent)
     assert st == 0
     for (a, b), x, f in zip(systems, xs, infos):
         if a.n == 0:
@@ -45,14 +47,15 @@ def test_ragged_knn_parity(orc):
     # alone vs in the batch: bitwise equal
     a, b = systems[2]
     alone = hs.SparseCSRList([(t64(a.val), t32(a.row_ptr), t32(a.col))])
-    x1, _, _ = alone.solve([t64(b)], rtol=1e-12)
+    x1, _, _ = alone.solve([t64(b)], rtol=1e-12, persistent=persistent)
     assert torch.equal(x1[0], xs[2])
     # run to run: bitwise equal
-    xs2, _, _ = L.solve([t64(b) for _, b in systems], rtol=1e-12)
+    xs2, _, _ = L.solve([t64(b) for _, b in systems], rtol=1e-12, persistent=persistent)
     assert all(torch.equal(u, v) for u, v in zip(xs, xs2))
 
 
-def test_ragged_rejects_invalid_system():
+@pytest.mark.parametrize("persistent", [True, False])
+def test_ragged_rejects_invalid_system(persistent):
     a, b = _knn(0, 100, 200)
     c = a.col.copy()
     c[3], c[4] = c[4], c[3]
@@ -60,15 +63,42 @@ def test_ragged_rejects_invalid_system():
     badm = (t64(a.val), t32(a.row_ptr), t32(c))
     L = hs.SparseCSRList([good, badm])
     with pytest.raises(_lib.HslaError) as e:
-        L.solve([t64(b), t64(b)])
+        L.solve([t64(b), t64(b)], persistent=persistent)
     assert e.value.status == _lib.ERR_INVALID_CSR and "system 1" in str(e.value)
 
 
-def test_ragged_status_codes():
+@pytest.mark.parametrize("persistent", [True, False])
+def test_ragged_status_codes(orc, persistent):
     a, b = _knn(1, 200, 300)
     L = hs.SparseCSRList([(t64(a.val), t32(a.row_ptr), t32(a.col))])
-    _, infos, st = L.solve([t64(b)], max_iter=2)
+    xs, infos, st = L.solve([t64(b)], max_iter=2, persistent=persistent)
     assert st == _lib.NOT_CONVERGED and infos[0]["iters"] == 2
+    ref = orc.cg(a, b, precond="jacobi", rtol=1e-8, max_iter=2)
+    assert rel(xs[0].cpu().numpy(), ref.x) <= 1e-13
     L2 = hs.SparseCSRList([(t64(-a.val), t32(a.row_ptr), t32(a.col))])
-    _, infos, st = L2.solve([t64(b)])
+    _, infos, st = L2.solve([t64(b)], persistent=persistent)
     assert st == _lib.BREAKDOWN
+    _, infos, st = L.solve([t64(b)], precond="none", rtol=1e-12, persistent=persistent)
+    ref = orc.cg(a, b, precond="none", rtol=1e-12)
+    assert st == _lib.OK and iters_close(infos[0]["iters"], ref.iters)
+
+
+def test_ragged_segmented_large_batch(orc):
+    """A batch past the segmented path's thresholds (more than 2^20 rows, a
+    system above 8192 rows) takes it by default; sampled systems match the
+    oracle and copies of one system agree bitwise."""
+    distinct = [_knn(s, 9000, 30000) for s in range(12)]
+    systems = [distinct[i % 12] for i in range(96)]
+    assert sum(a.n for a, _ in systems) > 2 ** 20
+    mats = [(t64(a.val), t32(a.row_ptr), t32(a.col)) for a, _ in distinct]
+    L = hs.SparseCSRList([mats[i % 12] for i in range(96)])
+    xs, infos, st = L.solve([t64(b) for _, b in systems], rtol=1e-12)
+    assert st == _lib.OK
+    for i in range(12, 96):
+        assert torch.equal(xs[i], xs[i % 12]) and infos[i]["iters"] == infos[i % 12]["iters"]
+    assert max(f["true_residual"] for f in infos) <= 5e-12
+    for s in (0, 5, 11):
+        a, b = distinct[s]
+        ref = orc.cg(a, b, precond="jacobi", rtol=1e-12)
+        assert rel(xs[s].cpu().numpy(), ref.x) <= 1e-8
+        assert iters_close(infos[s]["iters"], ref.iters)
