@@ -318,7 +318,9 @@ def run_bicgstab(ctx, args, dev, pat):
     _sync()
     dt = (time.perf_counter() - t0) / args.sub_steps
     it = infos[0]["iters"]
-    it_bytes = 2 * spmv_bytes(n, nnz, form_of(infos[0], pat), pat.stencil[1]) + 144 * n
+    # two SpMVs (p and s gathered, v and t written) + the vector sweeps on
+    # A D^{-1}: direction 32n, r_hat in the first SpMV 8n, s 24n, update 56n
+    it_bytes = 2 * spmv_bytes(n, nnz, form_of(infos[0], pat), pat.stencil[1]) + 120 * n
     return {
         "workload": f"diffusion3d-{args.m}^3 + upwind convection (cell Peclet 10), Jacobi-BiCGStab to rtol 1e-8",
         "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iterations": it, "status": st,

@@ -49,12 +49,14 @@ static Pat pat_T_of(const hsla_pattern *p) {
 
 struct Sys {
     const double *val;  // [B][nnz]
+    const double *aval; // [B][nnz] values of the operator iterated on: val, or for right-Jacobi
+                        // BiCGStab the column-scaled A D^{-1} (tile form)
     const double *dia;  // [B][nofs][n] diagonal-major copy of val (offset-mask patterns)
     const double *b;    // [B][n]
     double *x;          // [B][n]
     // work vectors, [B][n] each
     double *r, *p, *q, *dinv, *z, *w;
-    double *rh, *ph, *v, *s, *sh, *t;
+    double *rh, *y, *v, *s, *t;  // BiCGStab: y accumulates the iterate of A M^{-1} y = b - A x0
     SysState *st;       // [B]
     double *part;       // [B][3][G] block partials of the last producing kernel
 };
@@ -75,7 +77,7 @@ __device__ __forceinline__ void spmv_A(const Pat &A, const Sys &S, int sidx, con
         spmv_dia<NS>(A.sn, S.dia + (int64_t)sidx * dia_stored(NS, A.sn.nofs) * dia_chunks(A.n) * kDiaChunk,
                      (int64_t)A.n, v, epi);
     else
-        spmv_tiles(A.rp, A.col, A.sn, S.val + (int64_t)sidx * A.nnz, v, A.meta, A.ntiles, lds, epi);
+        spmv_tiles(A.rp, A.col, A.sn, S.aval + (int64_t)sidx * A.nnz, v, A.meta, A.ntiles, lds, epi);
 }
 
 // y = F v for an FSAI factor (float32 values), same two forms.
@@ -90,23 +92,42 @@ __device__ __forceinline__ void spmv_F(const FPat &F, int64_t n, int sidx, const
 
 // Chunked diagonal-major copy of the values of an offset-mask pattern (see
 // kDiaChunk): the entry of row i on diagonal s at dia_index(i, s), 0 where
-// the row has none and for the padding rows of the last chunk.
+// the row has none and for the padding rows of the last chunk.  With
+// `cscale` ([B][n]) the entry of column j is multiplied by cscale[j] (the
+// operator A D^{-1} of right-Jacobi BiCGStab).
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_to_dia(int32_t n, const int32_t *__restrict__ rp, Stencil sn,
-                                                   int64_t nnz, const VT *__restrict__ vals, VT *__restrict__ dia) {
+                                                   int64_t nnz, const VT *__restrict__ vals, VT *__restrict__ dia,
+                                                   const double *__restrict__ cscale = nullptr) {
     const int sidx = blockIdx.y;
     const int64_t rows = dia_chunks(n) * kDiaChunk;
     const VT *v = vals + (int64_t)sidx * nnz;
     VT *d = dia + (int64_t)sidx * sn.nofs * rows;
+    const double *cs = cscale ? cscale + (int64_t)sidx * n : nullptr;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < rows; i += (int64_t)gridDim.x * kBlock) {
         const uint32_t m = i < n ? (uint32_t)sn.mask[i] : 0u;
         int32_t k = i < n ? rp[i] : 0;
         for (int s = 0; s < sn.nofs; ++s) {
             VT val = VT(0);
-            if ((m >> s) & 1u) val = v[k++];
+            if ((m >> s) & 1u) {
+                val = v[k++];
+                if (cs) val = VT((double)val * cs[i + sn.ofs[s]]);
+            }
             d[dia_index(i, s, sn.nofs)] = val;
         }
     }
+}
+
+// The same column scaling on the CSR values (tile form): out = val D^{-1}.
+__global__ __launch_bounds__(kBlock) void k_scale_cols(int32_t n, int64_t nnz, const int32_t *__restrict__ col,
+                                                       const double *__restrict__ val,
+                                                       const double *__restrict__ cscale, double *__restrict__ out) {
+    const int sidx = blockIdx.y;
+    const double *v = val + (int64_t)sidx * nnz;
+    const double *cs = cscale + (int64_t)sidx * n;
+    double *o = out + (int64_t)sidx * nnz;
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kBlock)
+        o[k] = v[k] * cs[col[k]];
 }
 
 // The half form's copy (see kSymNS): the main and upper diagonals only, at
@@ -260,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(Pat A, Sys S) {
                          acc[0] += prow * yv;
                      });
     } else {
-        spmv_tiles(A.rp, A.col, A.sn, S.val + (int64_t)sidx * A.nnz, p, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+        spmv_tiles(A.rp, A.col, A.sn, S.aval + (int64_t)sidx * A.nnz, p, A.meta, A.ntiles, lds[threadIdx.x / kWave],
                    [&](int64_t row, double yv) {
                        q[row] = yv;
                        acc[0] += p[row] * yv;
@@ -479,6 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg_init(Pat A, Sys S, int use_x0) 
         S.rh[j] = ri;
         S.p[j] = 0.0;
         S.v[j] = 0.0;
+        S.y[j] = 0.0;
         if (PRE == PRE_JACOBI) {
             const int32_t d = A.diag[i];
             const double a = d >= 0 ? val[d] : 0.0;
@@ -522,9 +544,13 @@ __global__ __launch_bounds__(kBlock) void k_fin_bicg_init(Sys S, int G, double r
     }
 }
 
-// p = r + beta (p - omega v), p_hat = M^{-1} p (after a restart: r_hat = r,
-// p = r).
-template <int PRE>
+// Right preconditioning runs on the operator A M^{-1} (M = D for Jacobi, I
+// otherwise; its values are copied once per solve with the columns scaled
+// by D^{-1}): the recurrence iterates y for A M^{-1} y = b - A x0 with
+// v = (A M^{-1}) p and t = (A M^{-1}) s, so p_hat = M^{-1} p and s_hat =
+// M^{-1} s are never formed, and x = x0 + M^{-1} y once at the end.
+
+// p = r + beta (p - omega v) (after a restart: r_hat = r, p = r).
 __global__ __launch_bounds__(kBlock) void k_bicg_dir(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
     (void)part;
@@ -533,9 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg_dir(Pat A, Sys S) {
     const int restart = st.restart_pending;
     const double *__restrict__ r = S.r + vo;
     const double *__restrict__ v = S.v + vo;
-    const double *__restrict__ dinv = S.dinv + vo;
     double *__restrict__ p = S.p + vo;
-    double *__restrict__ ph = S.ph + vo;
     double *__restrict__ rh = S.rh + vo;
     if (restart) {
         GRID_LOOP_BEGIN(A.n)
@@ -545,49 +569,39 @@ __global__ __launch_bounds__(kBlock) void k_bicg_dir(Pat A, Sys S) {
                     const double ri = r[e];
                     rh[e] = ri;
                     p[e] = ri;
-                    ph[e] = PRE == PRE_JACOBI ? dinv[e] * ri : ri;
                 }
         GRID_LOOP_TAIL
                 const double ri = r[i_];
                 rh[i_] = ri;
                 p[i_] = ri;
-                ph[i_] = PRE == PRE_JACOBI ? dinv[i_] * ri : ri;
         GRID_LOOP_END
         return;
     }
     GRID_LOOP_BEGIN(A.n)
-            double rv[4], pv[4], vv[4], dv[4];
+            double rv[4], pv[4], vv[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t e = i_ + j * S_;
                 rv[j] = r[e]; pv[j] = p[e]; vv[j] = v[e];
-                dv[j] = PRE == PRE_JACOBI ? dinv[e] : 1.0;
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t e = i_ + j * S_;
-                const double pi = rv[j] + beta * (pv[j] - omega * vv[j]);
-                p[e] = pi;
-                ph[e] = PRE == PRE_JACOBI ? dv[j] * pi : pi;
-            }
+            for (int j = 0; j < 4; ++j) p[i_ + j * S_] = rv[j] + beta * (pv[j] - omega * vv[j]);
     GRID_LOOP_TAIL
-            const double pi = r[i_] + beta * (p[i_] - omega * v[i_]);
-            p[i_] = pi;
-            ph[i_] = PRE == PRE_JACOBI ? dinv[i_] * pi : pi;
+            p[i_] = r[i_] + beta * (p[i_] - omega * v[i_]);
     GRID_LOOP_END
 }
 
-// v = A p_hat and partials of r_hat.v.
+// v = (A M^{-1}) p and partials of r_hat.v.
 template <int NS>
 __global__ __launch_bounds__(kBlock) void k_bicg_spmv_v(Pat A, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
     if (stopped(st)) return;
-    const double *ph = S.ph + vo;
+    const double *p = S.p + vo;
     const double *rh = S.rh + vo;
     double *v = S.v + vo;
     double acc[1] = {0.0};
-    spmv_A<NS>(A, S, sidx, ph, lds[threadIdx.x / kWave],
+    spmv_A<NS>(A, S, sidx, p, lds[threadIdx.x / kWave],
                [&](int64_t row, double yv) {
                    v[row] = yv;
                    acc[0] += rh[row] * yv;
@@ -614,45 +628,38 @@ __global__ __launch_bounds__(kBlock) void k_fin_bicg_v(Sys S, int G) {
     }
 }
 
-// s = r - alpha v, s_hat = M^{-1} s and partials of s.s.
-template <int PRE>
+// s = r - alpha v and partials of s.s.
 __global__ __launch_bounds__(kBlock) void k_bicg_s(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
     if (stopped(st) || st.restart_pending) return;
     const double alpha = st.alpha;
     const double *__restrict__ r = S.r + vo;
     const double *__restrict__ v = S.v + vo;
-    const double *__restrict__ dinv = S.dinv + vo;
     double *__restrict__ s = S.s + vo;
-    double *__restrict__ sh = S.sh + vo;
     double acc[1] = {0.0};
     GRID_LOOP_BEGIN(A.n)
-            double rv[4], vv[4], dv[4];
+            double rv[4], vv[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t e = i_ + j * S_;
                 rv[j] = r[e]; vv[j] = v[e];
-                dv[j] = PRE == PRE_JACOBI ? dinv[e] : 1.0;
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int64_t e = i_ + j * S_;
                 const double si = rv[j] - alpha * vv[j];
-                s[e] = si;
-                sh[e] = PRE == PRE_JACOBI ? dv[j] * si : si;
+                s[i_ + j * S_] = si;
                 acc[0] += si * si;
             }
     GRID_LOOP_TAIL
             const double si = r[i_] - alpha * v[i_];
             s[i_] = si;
-            sh[i_] = PRE == PRE_JACOBI ? dinv[i_] * si : si;
             acc[0] += si * si;
     GRID_LOOP_END
     block_partial<1>(acc, part);
 }
 
 // Counts the iteration; ||s|| <= tol finishes the solve in the update kernel
-// with x += alpha p_hat.
+// with y += alpha p.
 __global__ __launch_bounds__(kBlock) void k_fin_bicg_s(Sys S, int G) {
     FIN_OFFSETS(S, G)
     if (stopped(st) || st.restart_pending) return;
@@ -670,22 +677,31 @@ __global__ __launch_bounds__(kBlock) void k_fin_bicg_s(Sys S, int G) {
     }
 }
 
-// t = A s_hat and partials of t.s, t.t.
+// t = (A M^{-1}) s and partials of t.s, t.t (the diagonal-major walk hands
+// over s of the row itself with its gathers).
 template <int NS>
 __global__ __launch_bounds__(kBlock) void k_bicg_spmv_t(Pat A, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
     if (stopped(st) || st.restart_pending || st.s_exit) return;
-    const double *sh = S.sh + vo;
     const double *s = S.s + vo;
     double *t = S.t + vo;
     double acc[2] = {0.0, 0.0};
-    spmv_A<NS>(A, S, sidx, sh, lds[threadIdx.x / kWave],
-               [&](int64_t row, double yv) {
-                   t[row] = yv;
-                   acc[0] += yv * s[row];
-                   acc[1] += yv * yv;
-               });
+    if constexpr (NS > 0) {
+        spmv_A<NS>(A, S, sidx, s, lds[threadIdx.x / kWave],
+                   [&](int64_t row, double yv, double srow) {
+                       t[row] = yv;
+                       acc[0] += yv * srow;
+                       acc[1] += yv * yv;
+                   });
+    } else {
+        spmv_A<NS>(A, S, sidx, s, lds[threadIdx.x / kWave],
+                   [&](int64_t row, double yv) {
+                       t[row] = yv;
+                       acc[0] += yv * s[row];
+                       acc[1] += yv * yv;
+                   });
+    }
     block_partial<2>(acc, part);
 }
 
@@ -706,17 +722,16 @@ __global__ __launch_bounds__(kBlock) void k_fin_bicg_t(Sys S, int G) {
     }
 }
 
-// x += alpha p_hat + omega s_hat, r = s - omega t (or, after the s test,
-// x += alpha p_hat, r = s); partials of r.r and r_hat.r.
+// y += alpha p + omega s, r = s - omega t (or, after the s test, y += alpha
+// p, r = s); partials of r.r and r_hat.r.
 __global__ __launch_bounds__(kBlock) void k_bicg_update(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
     if (stopped(st) || st.restart_pending) return;
     const double alpha = st.alpha, omega = st.omega;
     const int sx = st.s_exit;
-    double *__restrict__ x = S.x + vo;
+    double *__restrict__ y = S.y + vo;
     double *__restrict__ r = S.r + vo;
-    const double *__restrict__ ph = S.ph + vo;
-    const double *__restrict__ sh = S.sh + vo;
+    const double *__restrict__ p = S.p + vo;
     const double *__restrict__ s = S.s + vo;
     const double *__restrict__ t = S.t + vo;
     const double *__restrict__ rh = S.rh + vo;
@@ -726,32 +741,32 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(Pat A, Sys S) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int64_t e = i_ + j * S_;
-                    x[e] = x[e] + alpha * ph[e];
+                    y[e] = y[e] + alpha * p[e];
                     r[e] = s[e];
                 }
         GRID_LOOP_TAIL
-                x[i_] = x[i_] + alpha * ph[i_];
+                y[i_] = y[i_] + alpha * p[i_];
                 r[i_] = s[i_];
         GRID_LOOP_END
     } else {
         GRID_LOOP_BEGIN(A.n)
-                double xv[4], pv[4], shv[4], sv[4], tv[4], rhv[4];
+                double yv[4], pv[4], sv[4], tv[4], rhv[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int64_t e = i_ + j * S_;
-                    xv[j] = x[e]; pv[j] = ph[e]; shv[j] = sh[e]; sv[j] = s[e]; tv[j] = t[e]; rhv[j] = rh[e];
+                    yv[j] = y[e]; pv[j] = p[e]; sv[j] = s[e]; tv[j] = t[e]; rhv[j] = rh[e];
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int64_t e = i_ + j * S_;
-                    x[e] = xv[j] + (alpha * pv[j] + omega * shv[j]);
+                    y[e] = yv[j] + (alpha * pv[j] + omega * sv[j]);
                     const double ri = sv[j] - omega * tv[j];
                     r[e] = ri;
                     acc[0] += ri * ri;
                     acc[1] += rhv[j] * ri;
                 }
         GRID_LOOP_TAIL
-                x[i_] = x[i_] + (alpha * ph[i_] + omega * sh[i_]);
+                y[i_] = y[i_] + (alpha * p[i_] + omega * s[i_]);
                 const double ri = s[i_] - omega * t[i_];
                 r[i_] = ri;
                 acc[0] += ri * ri;
@@ -759,6 +774,19 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(Pat A, Sys S) {
         GRID_LOOP_END
     }
     block_partial<2>(acc, part);
+}
+
+// x = x0 + M^{-1} y after the last iteration.
+template <int PRE>
+__global__ __launch_bounds__(kBlock) void k_bicg_finish(Pat A, Sys S) {
+    SYS_OFFSETS(S, A)
+    (void)part;
+    (void)st;
+    double *__restrict__ x = S.x + vo;
+    const double *__restrict__ y = S.y + vo;
+    const double *__restrict__ dinv = S.dinv + vo;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock)
+        x[i] = x[i] + (PRE == PRE_JACOBI ? dinv[i] * y[i] : y[i]);
 }
 
 // Stop test on ||r||, then rho' = r_hat.r and beta = (rho'/rho)(alpha/omega).
@@ -1005,18 +1033,12 @@ static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hip
                     break;
             }
         } else {
-            if (c.precond == PRE_JACOBI)
-                k_bicg_dir<PRE_JACOBI><<<gv, kBlock, 0, s>>>(c.A, c.S);
-            else
-                k_bicg_dir<PRE_NONE><<<gv, kBlock, 0, s>>>(c.A, c.S);
+            k_bicg_dir<<<gv, kBlock, 0, s>>>(c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k], s);
             NS_LAUNCH_A(k_bicg_spmv_v, c.nsA, gs, c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
             k_fin_bicg_v<<<gf, kBlock, 0, s>>>(c.S, Gs);
-            if (c.precond == PRE_JACOBI)
-                k_bicg_s<PRE_JACOBI><<<gv, kBlock, 0, s>>>(c.A, c.S);
-            else
-                k_bicg_s<PRE_NONE><<<gv, kBlock, 0, s>>>(c.A, c.S);
+            k_bicg_s<<<gv, kBlock, 0, s>>>(c.A, c.S);
             k_fin_bicg_s<<<gf, kBlock, 0, s>>>(c.S, Gv);
             NS_LAUNCH_A(k_bicg_spmv_t, c.nsA, gs, c.A, c.S);
             k_fin_bicg_t<<<gf, kBlock, 0, s>>>(c.S, Gs);
@@ -1131,7 +1153,7 @@ static hsla_status decide_half(hsla_handle *h, const hsla_pattern *p, const Pat 
 // Grid sizes, SpMV forms and workspace layout of one solve.
 struct Plan {
     int nvec, Gt, Gv, nsA, nsF, Gd, Gs, Gf, pencil;
-    size_t diaA, diaL, diaU;
+    size_t diaA, diaL, diaU, sval;
     Layout lay;
 };
 
@@ -1139,7 +1161,7 @@ static Plan plan_solve(hsla_handle *h, const Tune &tn, const Pat &A, const FPat 
                        int pre) {
     Plan pl{};
     const int64_t n = A.n;
-    pl.nvec = method == HSLA_METHOD_CG ? 6 : 10;
+    pl.nvec = method == HSLA_METHOD_CG ? 6 : 8;
     // SpMV-based kernels: up to 16 blocks per CU; vector kernels: up to 8,
     // shared by the systems of a batch (fewer, longer-running blocks each)
     pl.Gt = grid_blocks(h, kWavesPerBlock, A.ntiles, B, tn.tile_cu);
@@ -1150,19 +1172,24 @@ static Plan plan_solve(hsla_handle *h, const Tune &tn, const Pat &A, const FPat 
     // the FSAI factors always use their diagonal-major copies where they
     // have one)
     auto dia_slots = [](const Stencil &sn) { return sn.mask ? dia_slots_for(sn.nofs) : 0; };
-    pl.nsA = tn.half ? kSymNS + A.sn.nofs : tn.dia ? dia_slots(A.sn) : 0;
+    // right-Jacobi BiCGStab iterates on A D^{-1}, which is not symmetric
+    const bool scaled = method == HSLA_METHOD_BICGSTAB && pre == PRE_JACOBI;
+    const bool half = tn.half && !scaled;
+    pl.nsA = half ? kSymNS + A.sn.nofs : tn.dia ? dia_slots(A.sn) : 0;
     const bool fsai = pre == PRE_FSAI && L && U;
     pl.nsF = fsai && L->sn.mask && U->sn.mask ? std::max(dia_slots(L->sn), dia_slots(U->sn)) : 0;
-    pl.pencil = tn.half ? pencil_len(A.sn, n, B, h->dev.num_cu) : 1;
-    pl.Gd = tn.half ? grid_blocks(h, (int64_t)kDiaChunk * pl.pencil, n, B, tn.sym_cu)
-                    : grid_blocks(h, kDiaChunk, n, B, tn.dia_cu);
+    pl.pencil = half ? pencil_len(A.sn, n, B, h->dev.num_cu) : 1;
+    pl.Gd = half ? grid_blocks(h, (int64_t)kDiaChunk * pl.pencil, n, B, tn.sym_cu)
+                 : grid_blocks(h, kDiaChunk, n, B, tn.dia_cu);
     pl.Gs = pl.nsA ? pl.Gd : pl.Gt;
     pl.Gf = pl.nsF ? grid_blocks(h, kDiaChunk, n, B, 8) : pl.Gt;
     const size_t drows = (size_t)dia_chunks(n) * kDiaChunk;
     pl.diaA = pl.nsA ? sizeof(double) * (size_t)B * dia_stored(pl.nsA, A.sn.nofs) * drows : 0;
     pl.diaL = pl.nsF ? sizeof(float) * (size_t)B * L->sn.nofs * drows : 0;
     pl.diaU = pl.nsF ? sizeof(float) * (size_t)B * U->sn.nofs * drows : 0;
-    const size_t extra = align_up(pl.diaA, 256) + align_up(pl.diaL, 256) + align_up(pl.diaU, 256);
+    pl.sval = scaled && !pl.nsA ? sizeof(double) * (size_t)B * (size_t)A.nnz : 0;
+    const size_t extra = align_up(pl.diaA, 256) + align_up(pl.diaL, 256) + align_up(pl.diaU, 256) +
+                         align_up(pl.sval, 256);
     const int Gmax = std::max(std::max(pl.Gt, pl.Gv), std::max(pl.Gd, pl.Gf));
     pl.lay = make_layout(B, n, pl.nvec, Gmax, extra);
     return pl;
@@ -1207,12 +1234,14 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
     S.part = (double *)(ws + lay.off_part);
     double *vec = (double *)(ws + lay.off_vec);
     const size_t vs = (size_t)B * n;
-    double **slots[] = {&S.r, &S.p, &S.q, &S.dinv, &S.z, &S.w, &S.rh, &S.ph, &S.v, &S.s};
+    double **cg_slots[] = {&S.r, &S.p, &S.q, &S.dinv, &S.z, &S.w};
+    double **bicg_slots[] = {&S.r, &S.p, &S.t, &S.dinv, &S.rh, &S.y, &S.v, &S.s};
+    double ***slots = method == HSLA_METHOD_CG ? cg_slots : bicg_slots;
     for (int k = 0; k < nvec; ++k) *slots[k] = vec + k * vs;
-    if (method == HSLA_METHOD_BICGSTAB) {
-        S.sh = S.z;  // s_hat
-        S.t = S.w;
-    }
+    S.aval = values;
+    // right-Jacobi BiCGStab iterates on A D^{-1}: its values are scaled
+    // below, once D^{-1} is known
+    const bool scaled = method == HSLA_METHOD_BICGSTAB && pre == PRE_JACOBI;
     const int64_t max_iter = o.max_iter > 0 ? o.max_iter : (10 * n < 100000 ? 10 * n : 100000);
     const dim3 gt(Gt, B), gv(Gv, B), gf(B), gfs(Gf, B);
     {
@@ -1221,10 +1250,13 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             double *d = (double *)ex;
             if (nsA > kSymNS)
                 k_to_dia_sym<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values, d);
-            else
+            else if (!scaled)
                 k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values, d);
             S.dia = d;
             ex += align_up(diaA, 256);
+        } else if (scaled) {
+            S.aval = (const double *)ex;
+            ex += align_up(pl.sval, 256);
         }
         if (nsF) {
             float *dl = (float *)ex;
@@ -1262,6 +1294,12 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
         else
             k_bicg_init<PRE_NONE><<<gv, kBlock, 0, s>>>(A, S, o.use_x0);
         k_fin_bicg_init<<<gf, kBlock, 0, s>>>(S, Gv, o.rtol, o.atol);
+        if (scaled && nsA)
+            k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values,
+                                                            (double *)S.dia, S.dinv);
+        else if (scaled)
+            k_scale_cols<<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.nnz, A.col, values, S.dinv,
+                                                        (double *)S.aval);
     }
     HSLA_HIP(h, hipGetLastError());
 
@@ -1309,6 +1347,12 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
         run += chunk;
         pending = chunk;
         if (chunk < chunk_cap) chunk *= 2;
+    }
+    if (method == HSLA_METHOD_BICGSTAB) {
+        if (pre == PRE_JACOBI)
+            k_bicg_finish<PRE_JACOBI><<<gv, kBlock, 0, s>>>(A, S);
+        else
+            k_bicg_finish<PRE_NONE><<<gv, kBlock, 0, s>>>(A, S);
     }
     // true residual ||b - A x|| / ||b||
     double *res = (double *)(ws + lay.off_res);
@@ -1718,6 +1762,7 @@ hsla_status hsla_residual_norms(hsla_handle *h, const hsla_pattern *p, int32_t B
     char *ws = (char *)h->ws;
     hsla::Sys S{};
     S.val = d_values;
+    S.aval = d_values;
     S.b = d_b;
     S.x = const_cast<double *>(d_x);
     S.st = (hsla::SysState *)(ws + lay.off_state);
