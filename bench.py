@@ -215,7 +215,9 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
 
     a, b = ctx["d3"]
     n, nnz = a.n, a.nnz
+    t0 = time.perf_counter()
     tuning = pat.autotune(B=1, effort=5) if args.autotune else None
+    tune_ms = (time.perf_counter() - t0) * 1e3
     if tuning:
         log(f"[bench] autotune: {tuning}")
     opts_w = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-8, max_iter=args.max_iter)
@@ -288,6 +290,7 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "algorithmic_bytes_per_iteration": it_bytes,
             "spmv_share_of_step": spmv_ms / args.steps / ms_step,
             "spmv_form": recs[-1]["spmv_form"],
+            "setup_excluded_ms": {"pattern": ctx.get("setup_ms"), "autotune": tune_ms if tuning else None},
             "autotune": tuning,
             "csr_bytes_per_iteration": csr_it_bytes,
             "csr_equivalent_iteration_GBps": csr_it_bytes * iters / (ms_step * 1e-3) / 1e9,
@@ -644,9 +647,12 @@ def run(args):
         log(f"[bench] n={a.n} nnz={a.nnz}")
         vals = torch.as_tensor(a.val).to(dev)
         bt = torch.as_tensor(b).to(dev)
+        _sync()
+        t0 = time.perf_counter()
         pat = _pattern(dev, a)
         _sync()
-        log("[bench] pattern ready")
+        ctx["setup_ms"] = (time.perf_counter() - t0) * 1e3
+        log(f"[bench] pattern ready ({ctx['setup_ms']:.1f} ms)")
     if args.calibrate_copy:
         # plain copy kernel of known size for counter calibration (1 GiB read + 1 GiB write)
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)

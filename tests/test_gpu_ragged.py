@@ -102,3 +102,23 @@ def test_ragged_segmented_large_batch(orc):
         ref = orc.cg(a, b, precond="jacobi", rtol=1e-12)
         assert rel(xs[s].cpu().numpy(), ref.x) <= 1e-8
         assert iters_close(infos[s]["iters"], ref.iters)
+
+
+@pytest.mark.parametrize("persistent", [True, False])
+def test_ragged_zero_diagonal_and_no_preconditioner(orc, persistent):
+    """A system with a zero diagonal entry fails the Jacobi solve with
+    ERR_ZERO_DIAGONAL on both paths; without a preconditioner the rest of
+    the batch still matches the oracle."""
+    a, b = _knn(2, 300, 600)
+    v = a.val.copy()
+    v[a.row_ptr[5]:a.row_ptr[6]][a.col[a.row_ptr[5]:a.row_ptr[6]] == 5] = 0.0
+    L = hs.SparseCSRList([(t64(a.val), t32(a.row_ptr), t32(a.col)), (t64(v), t32(a.row_ptr), t32(a.col))])
+    with pytest.raises(_lib.HslaError) as e:
+        L.solve([t64(b), t64(b)], persistent=persistent)
+    assert e.value.status == _lib.ERR_ZERO_DIAGONAL
+    L1 = hs.SparseCSRList([(t64(a.val), t32(a.row_ptr), t32(a.col))] * 3)
+    xs, infos, st = L1.solve([t64(b)] * 3, precond="none", rtol=1e-12, persistent=persistent)
+    ref = orc.cg(a, b, precond="none", rtol=1e-12)
+    assert st == _lib.OK
+    assert all(rel(x.cpu().numpy(), ref.x) <= 1e-8 for x in xs)
+    assert torch.equal(xs[0], xs[2])
