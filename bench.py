@@ -144,7 +144,7 @@ def cpu_baseline(a, b, gpu_iters: int, k1: int = 1, k2: int = 31):
     }
 
 
-ALL_WORKLOADS = ("diffusion3d", "bicgstab", "poisson2d", "knn", "adjoint", "learned", "paper")
+ALL_WORKLOADS = ("diffusion3d", "bicgstab", "poisson2d", "knn", "adjoint", "learned", "paper", "inverse")
 
 # The paper's own numbers for the same operator (context only: other hardware,
 # its own residual definitions): Table tab:benchmark, Jacobi-CG with the
@@ -152,6 +152,9 @@ ALL_WORKLOADS = ("diffusion3d", "bicgstab", "poisson2d", "knn", "adjoint", "lear
 # adjoint backward time by forced CG iterations on an RTX PRO 6000 Blackwell.
 PAPER_POISSON_MS = {100: 20.0, 316: 43.0, 1000: 190.0, 1414: 418.0, 4000: 7300.0}
 PAPER_ADJOINT_MS = {10: 35.0, 50: 9.0, 100: 13.0, 200: 25.0, 500: 60.0, 1000: 117.0, 2000: 230.0, 5000: 332.0}
+# Sec. "End-to-End: Inverse Coefficient Learning": 1500 Adam steps in 48.6 s on
+# one RTX PRO 6000 Blackwell; recovered kappa error 2.3e-3, solution misfit 3.0e-5.
+PAPER_INVERSE = {"steps": 1500, "seconds": 48.6, "kappa_rel_error": 2.3e-3, "u_rel_error": 3.0e-5}
 
 
 def generate(sel, args):
@@ -180,6 +183,8 @@ def generate(sel, args):
         ctx["adj"] = W.shared_pattern_batch(args.adj_m, args.adj_batch, workers=workers)
     if "paper" in sel:
         ctx["paper"] = {m: W.poisson2d(m) for m in list(PAPER_POISSON_MS) + [800]}
+    if "inverse" in sel:
+        ctx["inverse"] = W.inverse_truth(64)
     if "learned" in sel:
         ctx["aniso_pat"] = W.aniso_pattern(args.aniso_m)
         ctx["aniso_train"] = np.stack([W.aniso_stencil(*W.aniso_params(s)) for s in range(args.train_systems)])
@@ -627,6 +632,54 @@ def run_paper(ctx, args, dev):
             "jacobi_pcg_rtol_1e-6": rows, "adjoint_backward_forced_k_n640000": adj}
 
 
+def run_inverse(ctx, args, dev):
+    """Sec. "End-to-End: Inverse Coefficient Learning": recover kappa on the
+    64 x 64 grid with 1500 Adam steps (lr 5e-2) through the adjoint solve
+    (CG with Jacobi to rtol 1e-10, forward and backward)."""
+    import numpy as np
+
+    from paper_2601_13994_amd import inverse
+
+    kt, f = ctx["inverse"]
+    prob = inverse.InverseProblem(kt, f, m=64, device=dev, rtol=1e-10)
+    for _ in range(2):  # first-call set-up (graphs, workspace, allocator)
+        prob.loss()[0].backward()
+    prob.opt.zero_grad(set_to_none=True)
+    _sync()
+    steps = args.inverse_steps
+    hist = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        hist.append(prob.step())
+    _sync()
+    dt = time.perf_counter() - t0
+    ek, eu, kmin, kmax = prob.errors()
+    res = {
+        "workload": "inverse coefficient learning, 64x64 cells, kappa = softplus(theta), Adam lr 5e-2, "
+                    "loss ||u - u_obs||^2 + 1e-3 ||grad_h kappa||^2 / N, CG+Jacobi rtol 1e-10 forward and adjoint",
+        "steps": steps, "seconds": dt, "ms_per_step": dt / steps * 1e3,
+        "kappa_rel_error": ek, "u_rel_error": eu, "kappa_min": kmin, "kappa_max": kmax,
+        "loss_first": hist[0], "loss_last": hist[-1], "paper_rtx_pro_6000": PAPER_INVERSE,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import inverse as OI
+
+        oracle.lib()
+        u_obs = OI.observe(64, kt, f, rtol=1e-10)
+        theta = np.full(64 * 64, np.log(np.e - 1.0))
+        st = {"t": 0, "m": np.zeros_like(theta), "v": np.zeros_like(theta)}
+        k = 3
+        t0 = time.perf_counter()
+        for _ in range(k):
+            _, g, _ = OI.loss_and_grad(theta, 64, u_obs, f, rtol=1e-10)
+            theta = OI.adam(theta, g, st)
+        dto = (time.perf_counter() - t0) / k
+        res["oracle_ms_per_step"] = dto * 1e3
+        res["oracle_sample"] = f"first {k} steps of the same loop on the CPU oracle (numpy + sequential C), 1 core"
+    return res
+
+
 def run(args):
     sel = ALL_WORKLOADS if args.workloads == "all" else tuple(w.strip() for w in args.workloads.split(","))
     bad = [w for w in sel if w not in ALL_WORKLOADS]
@@ -673,7 +726,8 @@ def run(args):
     sub = {}
     runners = {"bicgstab": lambda: run_bicgstab(ctx, args, dev, pat), "poisson2d": lambda: run_poisson(ctx, args, dev),
                "knn": lambda: run_knn(ctx, args, dev), "adjoint": lambda: run_adjoint(ctx, args, dev),
-               "learned": lambda: run_learned(ctx, args, dev), "paper": lambda: run_paper(ctx, args, dev)}
+               "learned": lambda: run_learned(ctx, args, dev), "paper": lambda: run_paper(ctx, args, dev),
+               "inverse": lambda: run_inverse(ctx, args, dev)}
     for name in sel:
         if name == "diffusion3d":
             continue
@@ -793,6 +847,7 @@ def main():
     ap.add_argument("--workloads", default="all", help="comma list from " + ",".join(ALL_WORKLOADS))
     ap.add_argument("--sub-steps", type=int, default=2, help="timed repetitions of the other workloads")
     ap.add_argument("--poisson-copies", type=int, default=1024)
+    ap.add_argument("--inverse-steps", type=int, default=1500)
     ap.add_argument("--knn-systems", type=int, default=512)
     ap.add_argument("--adj-m", type=int, default=96)
     ap.add_argument("--adj-batch", type=int, default=128)

@@ -446,3 +446,15 @@ def _knn_one(s, kw):
 
 def rademacher(r: np.random.Generator, shape) -> np.ndarray:
     return np.where(r.random(shape) < 0.5, -1.0, 1.0)
+
+
+def inverse_truth(m: int = 64):
+    """Inputs of the inverse coefficient problem (Sec. "End-to-End: Inverse
+    Coefficient Learning"): the ground-truth conductivity
+    kappa*(x, y) = 1 + 0.5 sin(2 pi x) sin(2 pi y) at the centres of an m x m
+    grid of cells on (0, 1)^2 (cell (ix, iy) at index iy * m + ix) and the
+    source f = 1 per cell."""
+    c = (np.arange(m) + 0.5) / m
+    x, y = np.meshgrid(c, c)  # x varies along a row of the grid
+    kappa = 1.0 + 0.5 * np.sin(2.0 * np.pi * x) * np.sin(2.0 * np.pi * y)
+    return kappa.reshape(-1), np.ones(m * m)
