@@ -144,7 +144,8 @@ def cpu_baseline(a, b, gpu_iters: int, k1: int = 1, k2: int = 31):
     }
 
 
-ALL_WORKLOADS = ("diffusion3d", "bicgstab", "poisson2d", "knn", "adjoint", "learned", "paper", "inverse")
+ALL_WORKLOADS = ("diffusion3d", "bicgstab", "poisson2d", "knn", "adjoint", "learned", "paper", "inverse",
+                 "nonlinear")
 
 # The paper's own numbers for the same operator (context only: other hardware,
 # its own residual definitions): Table tab:benchmark, Jacobi-CG with the
@@ -185,6 +186,10 @@ def generate(sel, args):
         ctx["paper"] = {m: W.poisson2d(m) for m in list(PAPER_POISSON_MS) + [800]}
     if "inverse" in sel:
         ctx["inverse"] = W.inverse_truth(64)
+    if "nonlinear" in sel:
+        m = args.nonlinear_m
+        a = W.diffusion3d(m, W.diffusion3d_kappa(m))
+        ctx["nonlinear"] = (a.with_values(a.val * m * m), 1.0 + 0.5 * W.rng(2, 1, 7).standard_normal(a.n))
     if "learned" in sel:
         ctx["aniso_pat"] = W.aniso_pattern(args.aniso_m)
         ctx["aniso_train"] = np.stack([W.aniso_stencil(*W.aniso_params(s)) for s in range(args.train_systems)])
@@ -680,6 +685,45 @@ def run_inverse(ctx, args, dev):
     return res
 
 
+def run_nonlinear(ctx, args, dev):
+    """Sec. "Adjoint Differentiation", nonlinear systems: F(u) = A u + u^2 - f
+    (the paper's listing example) on the 3D log-normal diffusion operator
+    scaled to unit-cube spacing, Newton from u = 0 (each step a Jacobi-PCG
+    solve on A + 2 diag(u) to rtol 1e-10), then one adjoint solve for
+    dL/dA and dL/df of L = 1/2 ||u||^2."""
+    import torch
+
+    import paper_2601_13994_amd as hs
+    from paper_2601_13994_amd import nonlinear
+
+    a, f = ctx["nonlinear"]
+    rp, col = torch.as_tensor(a.row_ptr).to(dev), torch.as_tensor(a.col).to(dev)
+    pat = _pattern(dev, a)
+    ft0 = torch.as_tensor(f).to(dev)
+
+    def run_once():
+        vals = torch.as_tensor(a.val).to(dev).requires_grad_(True)
+        ft = ft0.clone().requires_grad_(True)
+        A = hs.SparseCSR(vals, rp, col, pattern=pat)
+        info = {}
+        _sync()
+        t0 = time.perf_counter()
+        u = nonlinear.newton_solve(A, ft, tol=1e-10, lin_rtol=1e-10, info=info)
+        _sync()
+        t1 = time.perf_counter()
+        (0.5 * (u * u).sum()).backward()
+        _sync()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, info["newton_steps"]
+
+    run_once()
+    fw, bw, steps = run_once()
+    return {"workload": (f"A u + u^2 = f on the {args.nonlinear_m}^3 log-normal diffusion operator (h^-2 scaled, "
+                         f"n={a.n}), Newton from 0 to ||F|| <= 1e-10 ||f||, Jacobi-PCG steps to rtol 1e-10"),
+            "newton_steps": steps, "forward_ms": fw * 1e3, "backward_ms": bw * 1e3,
+            "backward_over_forward": bw / fw}
+
+
 def run(args):
     sel = ALL_WORKLOADS if args.workloads == "all" else tuple(w.strip() for w in args.workloads.split(","))
     bad = [w for w in sel if w not in ALL_WORKLOADS]
@@ -727,7 +771,7 @@ def run(args):
     runners = {"bicgstab": lambda: run_bicgstab(ctx, args, dev, pat), "poisson2d": lambda: run_poisson(ctx, args, dev),
                "knn": lambda: run_knn(ctx, args, dev), "adjoint": lambda: run_adjoint(ctx, args, dev),
                "learned": lambda: run_learned(ctx, args, dev), "paper": lambda: run_paper(ctx, args, dev),
-               "inverse": lambda: run_inverse(ctx, args, dev)}
+               "inverse": lambda: run_inverse(ctx, args, dev), "nonlinear": lambda: run_nonlinear(ctx, args, dev)}
     for name in sel:
         if name == "diffusion3d":
             continue
@@ -848,6 +892,7 @@ def main():
     ap.add_argument("--sub-steps", type=int, default=2, help="timed repetitions of the other workloads")
     ap.add_argument("--poisson-copies", type=int, default=1024)
     ap.add_argument("--inverse-steps", type=int, default=1500)
+    ap.add_argument("--nonlinear-m", type=int, default=128)
     ap.add_argument("--knn-systems", type=int, default=512)
     ap.add_argument("--adj-m", type=int, default=96)
     ap.add_argument("--adj-batch", type=int, default=128)
