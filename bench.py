@@ -145,7 +145,7 @@ def cpu_baseline(a, b, gpu_iters: int, k1: int = 1, k2: int = 31):
 
 
 ALL_WORKLOADS = ("diffusion3d", "bicgstab", "poisson2d", "knn", "adjoint", "learned", "paper", "inverse",
-                 "nonlinear")
+                 "nonlinear", "eigen")
 
 # The paper's own numbers for the same operator (context only: other hardware,
 # its own residual definitions): Table tab:benchmark, Jacobi-CG with the
@@ -186,6 +186,8 @@ def generate(sel, args):
         ctx["paper"] = {m: W.poisson2d(m) for m in list(PAPER_POISSON_MS) + [800]}
     if "inverse" in sel:
         ctx["inverse"] = W.inverse_truth(64)
+    if "eigen" in sel:
+        ctx["eigen"] = W.diffusion3d(64, W.diffusion3d_kappa(64))
     if "nonlinear" in sel:
         m = args.nonlinear_m
         a = W.diffusion3d(m, W.diffusion3d_kappa(m))
@@ -724,6 +726,42 @@ def run_nonlinear(ctx, args, dev):
             "backward_over_forward": bw / fw}
 
 
+def run_eigen(ctx, args, dev):
+    """Sec. "Adjoint Differentiation", eigenvalue problems: the 6 smallest
+    eigenpairs of the 64^3 log-normal diffusion operator by shift-invert
+    Lanczos (library CG solves to rtol 1e-14 per step), then the
+    Hellmann-Feynman gradient of their sum (one on-pattern outer product)."""
+    import torch
+
+    import paper_2601_13994_amd as hs
+    from paper_2601_13994_amd import eigen
+
+    a = ctx["eigen"]
+    rp, col = torch.as_tensor(a.row_ptr).to(dev), torch.as_tensor(a.col).to(dev)
+    pat = _pattern(dev, a)
+
+    def run_once():
+        vals = torch.as_tensor(a.val).to(dev).requires_grad_(True)
+        A = hs.SparseCSR(vals, rp, col, pattern=pat)
+        info = {}
+        _sync()
+        t0 = time.perf_counter()
+        lam, _ = eigen.eigsh(A, k=6, which="SA", info=info)
+        _sync()
+        t1 = time.perf_counter()
+        lam.sum().backward()
+        _sync()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, info, lam.detach().cpu().tolist()
+
+    run_once()
+    fw, bw, info, lam = run_once()
+    return {"workload": f"6 smallest eigenpairs of the 64^3 log-normal diffusion operator (n={a.n}), shift-invert "
+                        "Lanczos with full reorthogonalisation, CG solves to rtol 1e-14",
+            "eigenvalues": lam, "lanczos_steps": info["lanczos_steps"],
+            "max_rel_residual": info["max_rel_residual"], "forward_ms": fw * 1e3, "backward_ms": bw * 1e3}
+
+
 def run(args):
     sel = ALL_WORKLOADS if args.workloads == "all" else tuple(w.strip() for w in args.workloads.split(","))
     bad = [w for w in sel if w not in ALL_WORKLOADS]
@@ -771,7 +809,8 @@ def run(args):
     runners = {"bicgstab": lambda: run_bicgstab(ctx, args, dev, pat), "poisson2d": lambda: run_poisson(ctx, args, dev),
                "knn": lambda: run_knn(ctx, args, dev), "adjoint": lambda: run_adjoint(ctx, args, dev),
                "learned": lambda: run_learned(ctx, args, dev), "paper": lambda: run_paper(ctx, args, dev),
-               "inverse": lambda: run_inverse(ctx, args, dev), "nonlinear": lambda: run_nonlinear(ctx, args, dev)}
+               "inverse": lambda: run_inverse(ctx, args, dev), "nonlinear": lambda: run_nonlinear(ctx, args, dev),
+               "eigen": lambda: run_eigen(ctx, args, dev)}
     for name in sel:
         if name == "diffusion3d":
             continue

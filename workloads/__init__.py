@@ -106,6 +106,20 @@ def poisson2d(m: int) -> Csr:
     return _compress(n, np.where(mask, cols, 0), vals, mask)
 
 
+def poisson2d_rect(mx: int, my: int) -> Csr:
+    """2D 5-point Dirichlet Laplacian on an mx x my interior grid (unknown
+    (x, y) at y*mx + x; diagonal 4, neighbours -1): with mx != my its small
+    eigenvalues are simple."""
+    n = mx * my
+    idx = np.arange(n, dtype=np.int64)
+    x = idx % mx
+    y = idx // mx
+    cols = np.stack([idx - mx, idx - 1, idx, idx + 1, idx + mx], axis=1)
+    mask = np.stack([y > 0, x > 0, np.ones(n, bool), x < mx - 1, y < my - 1], axis=1)
+    vals = np.broadcast_to(np.array([-1.0, -1.0, 4.0, -1.0, -1.0]), (n, 5)).copy()
+    return _compress(n, np.where(mask, cols, 0), vals, mask)
+
+
 _D3_CACHE: dict = {}
 
 
