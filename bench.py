@@ -372,6 +372,16 @@ def run_poisson(ctx, args, dev):
         x, infos, st = _lib.solve(pat, vals, bt, opts)
     _sync()
     lat = (time.perf_counter() - t0) / reps
+    # the single-reduction recurrence (CG_SR) in the same kernel
+    opts_sr = _lib.make_opts(method="cg_sr", precond="none", rtol=1e-10)
+    for _ in range(3):
+        _lib.solve(pat, vals, bt, opts_sr)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        xs, infos_sr, st_sr = _lib.solve(pat, vals, bt, opts_sr)
+    _sync()
+    lat_sr = (time.perf_counter() - t0) / reps
     B = args.poisson_copies
     vb = vals.repeat(B, 1).contiguous()
     bb = torch.as_tensor(ctx["p2_bs"]).to(dev)
@@ -383,6 +393,14 @@ def run_poisson(ctx, args, dev):
         xb, ib, stb = _lib.solve(pat, vb, bb, opts)
     _sync()
     tb = (time.perf_counter() - t0) / args.sub_steps
+    for _ in range(2):
+        _lib.solve(pat, vb, bb, opts_sr)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.sub_steps):
+        _, ib_sr, stb_sr = _lib.solve(pat, vb, bb, opts_sr)
+    _sync()
+    tb_sr = (time.perf_counter() - t0) / args.sub_steps
     it = infos[0]["iters"]
     itb = np.array([f["iters"] for f in ib])
     it_bytes = spmv_bytes(a.n, a.nnz, "csr") + 72 * a.n  # the persistent kernel reads CSR
@@ -394,6 +412,9 @@ def run_poisson(ctx, args, dev):
         "batched_copies": B, "batched_solves_per_s": B / tb, "batched_status": stb,
         "batched_max_iterations": int(itb.max()),
         "batched_model_GBps": float(it_bytes * itb.sum() / tb / 1e9),
+        "single_reduction": {"latency_us_per_solve": lat_sr * 1e6, "iterations": infos_sr[0]["iters"],
+                             "status": st_sr, "true_relative_residual": infos_sr[0]["true_residual"],
+                             "batched_solves_per_s": B / tb_sr, "batched_status": stb_sr},
     }
     if not args.no_cpu_baseline:
         oracle.lib()

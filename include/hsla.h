@@ -47,7 +47,17 @@ typedef enum hsla_status {
     HSLA_ERR_INTERNAL = -7
 } hsla_status;
 
-typedef enum hsla_method { HSLA_METHOD_AUTO = 0, HSLA_METHOD_CG = 1, HSLA_METHOD_BICGSTAB = 2 } hsla_method;
+/* CG_SR: CG with the single-reduction recurrence of Chronopoulos and Gear
+ * (the same iterates in exact arithmetic, different rounding; one
+ * workgroup reduction per iteration instead of two) where it pays: the
+ * persistent small-system kernel (n <= 4096 rows of <= 16 entries); every
+ * other path runs it as CG.  hsla_info.method reports which ran. */
+typedef enum hsla_method {
+    HSLA_METHOD_AUTO = 0,
+    HSLA_METHOD_CG = 1,
+    HSLA_METHOD_BICGSTAB = 2,
+    HSLA_METHOD_CG_SR = 3
+} hsla_method;
 typedef enum hsla_precond { HSLA_PRECOND_NONE = 0, HSLA_PRECOND_JACOBI = 1, HSLA_PRECOND_FSAI = 2 } hsla_precond;
 
 typedef struct hsla_handle hsla_handle;

@@ -20,7 +20,7 @@ OK, NOT_CONVERGED, BREAKDOWN, FELL_BACK = 0, 1, 2, 3
 ERR_INVALID_ARG, ERR_INVALID_CSR, ERR_NONFINITE, ERR_HIP = -1, -2, -3, -4
 ERR_NO_MEMORY, ERR_ZERO_DIAGONAL, ERR_INTERNAL = -5, -6, -7
 
-METHODS = {"auto": 0, "cg": 1, "bicgstab": 2}
+METHODS = {"auto": 0, "cg": 1, "bicgstab": 2, "cg_sr": 3}
 METHOD_NAMES = {v: k for k, v in METHODS.items()}
 PRECONDS = {"none": 0, "jacobi": 1, "fsai": 2}
 FORMATS = {"auto": 0, "csr": 1, "diagonal": 2}

@@ -245,8 +245,11 @@ inline int grid_blocks(const hsla_handle *h, int64_t per_block, int64_t units, i
 // per-iteration launches, every system iterating independently.
 constexpr int64_t kPersistentMaxNnz = 131072;
 bool persistent_eligible(const hsla_handle *h, const hsla_pattern *p, int B, int method, const hsla_opts &o);
+// single_reduction: the Chronopoulos-Gear recurrence in the small-system
+// kernel (HSLA_METHOD_CG_SR); other persistent solves run Algorithm 1.
 hsla_status persistent_solve(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *b,
-                             double *x, const hsla_opts &o, hsla_info *infos, hipStream_t s);
+                             double *x, const hsla_opts &o, hsla_info *infos, hipStream_t s,
+                             bool single_reduction = false);
 
 // Kernel launch helpers implemented in the .hip files.
 hsla_status launch_spmv(hsla_handle *h, const hsla_pattern *p, int B, const double *values,

@@ -1422,7 +1422,7 @@ static hsla_status read_opts(hsla_handle *h, const hsla_opts *opts, hsla_opts *o
     else
         hsla_opts_default(o);
     if (!(o->rtol >= 0) || !(o->atol >= 0)) return set_error(h, HSLA_ERR_INVALID_ARG, "negative or NaN tolerance");
-    if (o->method < HSLA_METHOD_AUTO || o->method > HSLA_METHOD_BICGSTAB)
+    if (o->method < HSLA_METHOD_AUTO || o->method > HSLA_METHOD_CG_SR)
         return set_error(h, HSLA_ERR_INVALID_ARG, "unknown method %d", o->method);
     if (o->precond < HSLA_PRECOND_NONE || o->precond > HSLA_PRECOND_FSAI)
         return set_error(h, HSLA_ERR_INVALID_ARG, "unknown preconditioner %d", o->precond);
@@ -1451,6 +1451,8 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
     }
     if (!values || !b || !x) return set_error(h, HSLA_ERR_INVALID_ARG, "null values, b or x");
     int method = o.method;
+    const bool sr = method == HSLA_METHOD_CG_SR;  // single-reduction CG where it applies
+    if (sr) method = HSLA_METHOD_CG;
     int symv = -1;  // values symmetric: -1 not checked
     if (method == HSLA_METHOD_AUTO) {
         bool sym = false;
@@ -1460,7 +1462,7 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
         symv = sym ? 1 : 0;
     }
     if (o.persistent && persistent_eligible(h, p, B, method, o))
-        return persistent_solve(h, p, B, values, b, x, o, infos, s);
+        return persistent_solve(h, p, B, values, b, x, o, infos, s, sr);
     const Pat A = pat_of(p);
     FPat L{}, U{};
     if (o.precond == HSLA_PRECOND_FSAI) {
@@ -1498,7 +1500,10 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
     bool sym = false;
     st = values_symmetric(h, p, B, values, s, &sym);
     if (st != HSLA_OK) return st;
-    const int method = o.method != HSLA_METHOD_AUTO ? o.method : (sym ? HSLA_METHOD_CG : HSLA_METHOD_BICGSTAB);
+    const bool sr = o.method == HSLA_METHOD_CG_SR;
+    const int method = o.method == HSLA_METHOD_AUTO ? (sym ? HSLA_METHOD_CG : HSLA_METHOD_BICGSTAB)
+                       : sr                         ? HSLA_METHOD_CG
+                                                    : o.method;
     const int64_t n = p->n;
     double *lam = gb, *lam_own = nullptr, *valT = nullptr;
     if (!lam) {
@@ -1509,7 +1514,7 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
     if (sym) {
         const Pat A = pat_of(p);
         if (o.persistent && persistent_eligible(h, p, B, method, o)) {
-            res = persistent_solve(h, p, B, values, gx, lam, o, infos, s);
+            res = persistent_solve(h, p, B, values, gx, lam, o, infos, s, sr);
         } else {
             Tune tn = tune_of(p);
             res = decide_half(h, p, A, B, values, 1, s, &tn);

@@ -353,7 +353,13 @@ __device__ __forceinline__ double small_row(int32_t lo, int32_t len, const int32
     return sum;
 }
 
-template <int R, int K>
+// SR: the single-reduction recurrence of Chronopoulos and Gear (1989) --
+// the same iterates as Algorithm "Distributed CG" in exact arithmetic, with
+// s = A p carried as a vector so that r.u, (A u).u and r.r of an iteration
+// are one workgroup reduction (three barriers per iteration instead of
+// five).  Breakdown when the step's curvature delta - beta gamma / alpha is
+// not positive.
+template <int R, int K, bool SR>
 __global__ __launch_bounds__(kSB) void k_small_pcg(Args a) {
     __shared__ double ps[kSmallMaxN];
     __shared__ double sh[3 * kSW];
@@ -413,6 +419,65 @@ __global__ __launch_bounds__(kSB) void k_small_pcg(Args a) {
             status = HSLA_ERR_NONFINITE;
         } else if (sqrt(rr) <= tol) {
             status = HSLA_OK;
+        } else if (SR) {
+            // u = D^{-1} r is p at the start (in LDS); w = A u, s = w
+            double gamma = rho, alpha = 0.0;
+            {
+                double d1[1] = {0.0};
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    qv[j] = small_row<K>(lo[j], len[j], col, val, ps);  // s = w = A u
+                    d1[0] += qv[j] * pv[j];
+                    if (j % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                }
+                wg_sum<kSW, 1>(d1, sh);
+                if (!isfinite(d1[0])) {
+                    status = HSLA_ERR_NONFINITE;
+                } else if (!(d1[0] > 0.0)) {
+                    status = HSLA_BREAKDOWN;
+                } else {
+                    alpha = gamma / d1[0];
+                }
+            }
+            while (status == HSLA_NOT_CONVERGED && it < a.max_iter) {
+                // x += alpha p, r -= alpha s, u = D^{-1} r (to LDS)
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const int32_t i = threadIdx.x + j * kSB;
+                    xr[j] = xr[j] + alpha * pv[j];
+                    rv[j] = rv[j] - alpha * qv[j];
+                    if (i < n) ps[i] = dv[j] * rv[j];
+                }
+                ++it;
+                __syncthreads();
+                // w = A u; r.u, w.u, r.r in one reduction
+                double w[R];
+                double d3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    w[j] = small_row<K>(lo[j], len[j], col, val, ps);
+                    const double u = dv[j] * rv[j];
+                    d3[0] += rv[j] * u;
+                    d3[1] += w[j] * u;
+                    d3[2] += rv[j] * rv[j];
+                    if (j % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                }
+                wg_sum<kSW, 3>(d3, sh);
+                rr = d3[2];
+                const double rn = sqrt(rr);
+                if (!isfinite(rn) || !isfinite(d3[0]) || !isfinite(d3[1])) { status = HSLA_ERR_NONFINITE; break; }
+                if (rn <= tol) { status = HSLA_OK; break; }
+                const double beta = d3[0] / gamma;
+                const double curv = d3[1] - beta * d3[0] / alpha;
+                if (!(curv > 0.0)) { status = HSLA_BREAKDOWN; break; }
+                alpha = d3[0] / curv;
+                gamma = d3[0];
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    pv[j] = dv[j] * rv[j] + beta * pv[j];
+                    qv[j] = w[j] + beta * qv[j];
+                }
+            }
         } else {
             while (it < a.max_iter) {
                 // q = A p from the LDS copy of p (visible after the barriers
@@ -497,7 +562,8 @@ __global__ __launch_bounds__(kSB) void k_small_pcg(Args a) {
 // (host, may be empty = identity) is the queue order.
 static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, int64_t rows, int64_t entries,
                                   int64_t max_n, const std::vector<int32_t> &order, hsla_info *infos,
-                                  hipStream_t s, int small_rows = 0, int small_k = 0) {
+                                  hipStream_t s, int small_rows = 0, int small_k = 0,
+                                  bool single_reduction = false) {
     const int32_t B = a.B;
     size_t bytes = 0;
     auto add = [&](size_t v) { bytes += (v + 255) / 256 * 256; };
@@ -548,20 +614,27 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
     // workgroups beyond the resident ones find the queue empty and exit
     const int gs = (int)std::min<int64_t>(B, 2 * (int64_t)h->dev.num_cu);
     const int gr = gs;
-    if (small_rows == 1 && small_k == 8)
-        k_small_pcg<1, 8><<<gs, kSB, 0, s>>>(a);
-    else if (small_rows == 1)
-        k_small_pcg<1, 16><<<gs, kSB, 0, s>>>(a);
-    else if (small_rows == 2 && small_k == 8)
-        k_small_pcg<2, 8><<<gs, kSB, 0, s>>>(a);
-    else if (small_rows == 2)
-        k_small_pcg<2, 16><<<gs, kSB, 0, s>>>(a);
-    else if (small_rows == 4 && small_k == 8)
-        k_small_pcg<4, 8><<<gs, kSB, 0, s>>>(a);
-    else if (small_rows == 4)
-        k_small_pcg<4, 16><<<gs, kSB, 0, s>>>(a);
-    else
+#define SMALL_LAUNCH(SRV)                                                    \
+    if (small_rows == 1 && small_k == 8)                                     \
+        k_small_pcg<1, 8, SRV><<<gs, kSB, 0, s>>>(a);                        \
+    else if (small_rows == 1)                                                \
+        k_small_pcg<1, 16, SRV><<<gs, kSB, 0, s>>>(a);                       \
+    else if (small_rows == 2 && small_k == 8)                                \
+        k_small_pcg<2, 8, SRV><<<gs, kSB, 0, s>>>(a);                        \
+    else if (small_rows == 2)                                                \
+        k_small_pcg<2, 16, SRV><<<gs, kSB, 0, s>>>(a);                       \
+    else if (small_rows == 4 && small_k == 8)                                \
+        k_small_pcg<4, 8, SRV><<<gs, kSB, 0, s>>>(a);                        \
+    else if (small_rows == 4)                                                \
+        k_small_pcg<4, 16, SRV><<<gs, kSB, 0, s>>>(a);
+    if (small_rows > 0 && single_reduction) {
+        SMALL_LAUNCH(true)
+    } else if (small_rows > 0) {
+        SMALL_LAUNCH(false)
+    } else {
         k_ragged_pcg<<<gr, kRB, 0, s>>>(a);
+    }
+#undef SMALL_LAUNCH
     HSLA_HIP(h, hipGetLastError());
     std::vector<RInfo> hi(B);
     HSLA_HIP(h, hipMemcpyAsync(hi.data(), a.info, sizeof(RInfo) * B, hipMemcpyDeviceToHost, s));
@@ -576,7 +649,7 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
         if (infos) {
             infos[i].iters = hi[i].iters;
             infos[i].status = sst;
-            infos[i].method = HSLA_METHOD_CG;
+            infos[i].method = single_reduction && small_rows > 0 ? HSLA_METHOD_CG_SR : HSLA_METHOD_CG;
             infos[i].rel_residual = hi[i].rel_residual;
             infos[i].true_residual = hi[i].true_residual;
             infos[i].spmv_ms = 0.0;
@@ -986,7 +1059,7 @@ bool persistent_eligible(const hsla_handle *h, const hsla_pattern *p, int B, int
 }
 
 hsla_status persistent_solve(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *b,
-                             double *x, const hsla_opts &o, hsla_info *infos, hipStream_t s) {
+                             double *x, const hsla_opts &o, hsla_info *infos, hipStream_t s, bool single_reduction) {
     rg::Args a{};
     a.B = B;
     a.shared_n = p->n;
@@ -1001,7 +1074,7 @@ hsla_status persistent_solve(hsla_handle *h, const hsla_pattern *p, int B, const
         rows = p->n <= rg::kSB ? 1 : p->n <= 2 * rg::kSB ? 2 : 4;
         k = p->max_row <= 8 ? 8 : 16;
     }
-    return rg::run_persistent(h, a, o, (int64_t)B * p->n, p->nnz, p->n, {}, infos, s, rows, k);
+    return rg::run_persistent(h, a, o, (int64_t)B * p->n, p->nnz, p->n, {}, infos, s, rows, k, single_reduction);
 }
 
 }  // namespace hsla

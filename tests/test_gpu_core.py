@@ -416,3 +416,41 @@ def test_persistent_shared_mode_batch(orc):
         assert rel(x1[s].cpu().numpy(), ref.x) <= 1e-8
         assert rel(x2[s].cpu().numpy(), ref.x) <= 1e-8
         assert iters_close(i1[s]["iters"], ref.iters)
+
+
+@pytest.mark.parametrize("name,make", [
+    ("poisson64", lambda: W.poisson2d(64)),                 # 4 rows per thread, 5 entries
+    ("poisson30", lambda: W.poisson2d(30)),                 # 1 row per thread
+    ("poisson40", lambda: W.poisson2d(40)),                 # 2 rows per thread
+    ("aniso9", lambda: W.aniso2d(60, 50.0, 0.6)),           # 9 entries per row
+])
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_cg_single_reduction_parity(orc, name, make, precond):
+    """CG_SR (the Chronopoulos-Gear recurrence in the small-system kernel)
+    against the oracle's Algorithm-1 CG: same solution, iteration counts
+    within max(2, 2%), reported as CG_SR; capped and singular cases."""
+    a = make()
+    b = np.random.default_rng(13).standard_normal(a.n)
+    x, info, st = solve(a, b, method="cg_sr", precond=precond, rtol=1e-12)
+    ref = orc.cg(a, b, precond=precond, rtol=1e-12)
+    assert st == 0 and info[0]["method"] == "cg_sr"
+    assert rel(x, ref.x) <= 1e-8
+    assert iters_close(info[0]["iters"], ref.iters), (info[0]["iters"], ref.iters)
+    assert info[0]["true_residual"] <= 5e-12
+    pat = pattern(a)
+    x, info, st = solve(a, b, pat=pat, method="cg_sr", precond=precond, rtol=1e-12, max_iter=3)
+    ref3 = orc.cg(a, b, precond=precond, rtol=1e-12, max_iter=3)
+    assert st == _lib.NOT_CONVERGED and info[0]["iters"] == 3 and rel(x, ref3.x) <= 1e-12
+    x, info, st = solve(a, b, pat=pat, values=t64(-a.val), method="cg_sr", precond=precond)
+    assert st == _lib.BREAKDOWN
+    x, info, st = solve(a, np.zeros(a.n), pat=pat, method="cg_sr", precond=precond)
+    assert st == 0 and info[0]["iters"] == 0 and not x.any()
+
+
+def test_cg_single_reduction_elsewhere_runs_cg(orc):
+    """Outside the small-system kernel CG_SR runs Algorithm 1 and says so."""
+    a = W.diffusion3d(20, W.diffusion3d_kappa(20))
+    b = np.random.default_rng(14).standard_normal(a.n)
+    x, info, st = solve(a, b, method="cg_sr", precond="jacobi", rtol=1e-12)
+    assert st == 0 and info[0]["method"] == "cg"
+    assert rel(x, orc.cg(a, b, precond="jacobi", rtol=1e-12).x) <= 1e-8
