@@ -90,9 +90,10 @@ FORM_TEXT = {"diagonal": "diagonal-major values + row masks, {} diagonals",
 
 def pcg_iteration_bytes(n: int, nnz: int, nofs: int) -> int:
     """Algorithmic bytes of one Jacobi-PCG iteration as scheduled here:
-    SpMV+dot, update (reads r q D^-1, writes r: 32n), direction with the
-    iteration's x update (reads D^-1 r p x, writes p x: 48n)."""
-    return spmv_bytes(n, nnz, "diagonal" if nofs else "csr", nofs) + 80 * n
+    SpMV+dot on the scaled operator S A S, update (reads r q S, writes r:
+    32n), direction with the iteration's x update (reads r p x, writes p x:
+    40n)."""
+    return spmv_bytes(n, nnz, "diagonal" if nofs else "csr", nofs) + 72 * n
 
 
 def cpu_info() -> str:
@@ -256,7 +257,7 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
     bytes_launch = spmv_bytes(n, nnz, form, nofs)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     ms_step = elapsed / args.steps * 1e3
-    it_bytes = bytes_launch + 80 * n
+    it_bytes = bytes_launch + 72 * n
     csr_it_bytes = pcg_iteration_bytes(n, nnz, 0)
     top = {
         "metric": METRIC,
@@ -521,12 +522,12 @@ def run_adjoint(ctx, args, dev):
     itf = np.array([f["iters"] for f in fi])
     itb = np.array([f["iters"] for f in bi])
     # per system per iteration: the operator's values in the form used (the
-    # row masks or CSR indices, shared by the batch, amortised over B) + 96n
-    # (p gathered, q written: 16n; update and direction: 80n)
+    # row masks or CSR indices, shared by the batch, amortised over B) + 88n
+    # (p gathered, q written: 16n; update and direction: 72n)
     form = form_of(fi[0], pat)
     nofs = pat.stencil[1]
     per_it = {"diagonal-half": 8 * (nofs // 2 + 1) * n, "diagonal": 8 * nofs * n,
-              "mask-tiles": 8 * nnz, "csr": 8 * nnz}[form] + 96 * n
+              "mask-tiles": 8 * nnz, "csr": 8 * nnz}[form] + 88 * n
     per_it += (2 * n if form != "csr" else 4 * nnz + 4 * (n + 1)) / B
     work = float(per_it * (itf.sum() + itb.sum()) + B * (12 * nnz + 28 * n))
     return {

@@ -93,12 +93,13 @@ __device__ __forceinline__ void spmv_F(const FPat &F, int64_t n, int sidx, const
 // Chunked diagonal-major copy of the values of an offset-mask pattern (see
 // kDiaChunk): the entry of row i on diagonal s at dia_index(i, s), 0 where
 // the row has none and for the padding rows of the last chunk.  With
-// `cscale` ([B][n]) the entry of column j is multiplied by cscale[j] (the
-// operator A D^{-1} of right-Jacobi BiCGStab).
+// `cscale` ([B][n]) the entry (i, j) is multiplied by cscale[j] (the
+// operator A D^{-1} of right-Jacobi BiCGStab) or, with `sym`, by
+// cscale[i] cscale[j] (S A S of Jacobi CG).
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_to_dia(int32_t n, const int32_t *__restrict__ rp, Stencil sn,
                                                    int64_t nnz, const VT *__restrict__ vals, VT *__restrict__ dia,
-                                                   const double *__restrict__ cscale = nullptr) {
+                                                   const double *__restrict__ cscale = nullptr, int sym = 0) {
     const int sidx = blockIdx.y;
     const int64_t rows = dia_chunks(n) * kDiaChunk;
     const VT *v = vals + (int64_t)sidx * nnz;
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_to_dia(int32_t n, const int32_t *__r
             VT val = VT(0);
             if ((m >> s) & 1u) {
                 val = v[k++];
-                if (cs) val = VT((double)val * cs[i + sn.ofs[s]]);
+                if (cs) val = VT((double)val * (sym ? cs[i] * cs[i + sn.ofs[s]] : cs[i + sn.ofs[s]]));
             }
             d[dia_index(i, s, sn.nofs)] = val;
         }
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_scale_cols(int32_t n, int64_t nnz, c
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_to_dia_sym(int32_t n, const int32_t *__restrict__ rp, Stencil sn,
                                                        int64_t nnz, const VT *__restrict__ vals,
-                                                       VT *__restrict__ dia) {
+                                                       VT *__restrict__ dia, const double *__restrict__ sc = nullptr) {
     const int sidx = blockIdx.y;
     const int ds = sn.nofs / 2, nh = ds + 1;
     const int64_t rows = dia_chunks(n) * kDiaChunk;
@@ -144,9 +145,13 @@ __global__ __launch_bounds__(kBlock) void k_to_dia_sym(int32_t n, const int32_t 
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < rows; i += (int64_t)gridDim.x * kBlock) {
         const uint32_t m = i < n ? (uint32_t)sn.mask[i] : 0u;
         int32_t k = i < n ? rp[i] + __popc(m & ((1u << ds) - 1u)) : 0;
+        const double *cs = sc ? sc + (int64_t)sidx * n : nullptr;
         for (int s = ds; s < sn.nofs; ++s) {
             VT val = VT(0);
-            if ((m >> s) & 1u) val = v[k++];
+            if ((m >> s) & 1u) {
+                val = v[k++];
+                if (cs) val = VT((double)val * (cs[i] * cs[i + sn.ofs[s]]));
+            }
             d[dia_index(i, s - ds, nh)] = val;
         }
     }
@@ -222,34 +227,51 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia(Pat A, const double *__rest
 // ---------------------------------------------------------------------------
 enum { PRE_NONE = 0, PRE_JACOBI = 1, PRE_FSAI = 2 };
 
-// x = 0 or x0, r = b - A x0 (q holds A x0), z = M^{-1} r (Jacobi / none),
+// x = 0 or x0, r = b - A x0 (q holds A x0), z = M^{-1} r (none / FSAI),
 // p = z; partials of b.b, r.r, r.z.
+// Jacobi runs as CG on the scaled system S A S y = S r0 with S = D^{-1/2}
+// (the same iterates as Jacobi-PCG in exact arithmetic: x = x0 + S y, the
+// scaled residual is S r and its inner product the PCG's r.D^{-1}r): the
+// work vectors hold S r, S^{-1} x and the scaled p, the dinv slot holds
+// S, and the operator's values are scaled once per solve.  The stop test
+// stays on the unscaled ||r||.  A negative diagonal (no real S; Jacobi is
+// then not a valid CG preconditioner) stops the solve with BREAKDOWN before
+// the first iteration.
 template <int PRE>
 __global__ __launch_bounds__(kBlock) void k_cg_init(Pat A, Sys S, int use_x0) {
     SYS_OFFSETS(S, A)
     const double *val = S.val + sidx * A.nnz;
     double acc[3] = {0.0, 0.0, 0.0};  // b.b, r.r, r.z
-    bool bad = false;
+    bool bad = false, neg = false;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock) {
         const double bi = S.b[vo + i];
         const double ri = use_x0 ? bi - S.q[vo + i] : bi;
-        if (!use_x0) S.x[vo + i] = 0.0;
-        S.r[vo + i] = ri;
         double zi = ri;
         if (PRE == PRE_JACOBI) {
             const int32_t d = A.diag[i];
             const double a = d >= 0 ? val[d] : 0.0;
             if (a == 0.0) bad = true;
-            const double di = 1.0 / a;
-            S.dinv[vo + i] = di;
-            zi = di * ri;
+            if (a < 0.0) neg = true;
+            const double si = a > 0.0 ? 1.0 / sqrt(a) : 1.0;
+            S.dinv[vo + i] = si;
+            zi = si * ri;  // the scaled residual S r
+            S.r[vo + i] = zi;
+            S.x[vo + i] = use_x0 ? S.x[vo + i] / si : 0.0;
+            acc[2] += zi * zi;
+        } else {
+            if (!use_x0) S.x[vo + i] = 0.0;
+            S.r[vo + i] = ri;
+            acc[2] += ri * zi;
         }
         S.p[vo + i] = PRE == PRE_FSAI ? 0.0 : zi;
         acc[0] += bi * bi;
         acc[1] += ri * ri;
-        acc[2] += ri * zi;
     }
-    if (bad) st.bad_diag = 1;
+    // bit 0: a missing or zero diagonal, bit 1: a negative one
+    const int any_bad = __syncthreads_or(bad ? 1 : 0);
+    const int any_neg = __syncthreads_or(neg ? 1 : 0);
+    const int flags = (any_bad ? 1 : 0) | (any_neg ? 2 : 0);
+    if (threadIdx.x == 0 && flags) atomicOr(&st.bad_diag, flags);
     block_partial<3>(acc, part);
 }
 
@@ -260,7 +282,13 @@ __global__ __launch_bounds__(kBlock) void k_fin_cg_init(Sys S, int G, double rto
     double tot[3];
     reduce_partials<3>(part, G, tot);
     if (threadIdx.x != 0) return;
+    const bool neg = st.bad_diag == 2;
+    st.bad_diag &= 1;
     cg_step_init(st, tot[0], tot[1], PRE == PRE_FSAI ? 0.0 : tot[2], rtol, atol);
+    if (neg && !st.done) {
+        st.status = HSLA_BREAKDOWN;
+        st.done = 1;
+    }
 }
 
 // q = A p and partials of sigma = p.q.
@@ -300,9 +328,10 @@ __global__ __launch_bounds__(kBlock) void k_fin_alpha(Sys S, int G) {
     cg_step_alpha(st, tot[0]);
 }
 
-// r -= alpha q; partials of r.r and (Jacobi) r.D^{-1}r.  x += alpha p of
-// the same iteration is applied by the direction kernel, which reads p
-// anyway, so p is read once per iteration.
+// r -= alpha q; partials of r.r and r.z (Jacobi, scaled system: r holds
+// S r, so the unscaled r.r is the sum of (r_i / S_i)^2 and r.z = r.r of the
+// scaled vector).  x += alpha p of the same iteration is applied by the
+// direction kernel, which reads p anyway, so p is read once per iteration.
 template <int PRE>
 __global__ __launch_bounds__(kBlock) void k_cg_update(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
@@ -325,14 +354,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Pat A, Sys S) {
                 const int64_t e = i_ + j * S_;
                 const double ri = rv[j] - alpha * qv[j];
                 r[e] = ri;
-                acc[0] += ri * ri;
-                if (PRE == PRE_JACOBI) acc[1] += ri * (dv[j] * ri);
+                if (PRE == PRE_JACOBI) {
+                    const double u = ri / dv[j];
+                    acc[0] += u * u;
+                    acc[1] += ri * ri;
+                } else {
+                    acc[0] += ri * ri;
+                }
             }
     GRID_LOOP_TAIL
             const double ri = r[i_] - alpha * q[i_];
             r[i_] = ri;
-            acc[0] += ri * ri;
-            if (PRE == PRE_JACOBI) acc[1] += ri * (dinv[i_] * ri);
+            if (PRE == PRE_JACOBI) {
+                const double u = ri / dinv[i_];
+                acc[0] += u * u;
+                acc[1] += ri * ri;
+            } else {
+                acc[0] += ri * ri;
+            }
     GRID_LOOP_END
     if (PRE == PRE_NONE) acc[1] = acc[0];
     block_partial<2>(acc, part);
@@ -354,9 +393,10 @@ __global__ __launch_bounds__(kBlock) void k_fin_beta(Sys S, int G) {
     cg_step_beta(st, tot[0], tot[1], PRE != PRE_FSAI);
 }
 
-// x += alpha p, then p = z + beta p with z = D^{-1} r (Jacobi), r (none) or
-// the stored z (FSAI); a system that stopped in this iteration takes only
-// the x update.  XUP = false (the FSAI start, p = z): no x update.
+// x += alpha p, then p = z + beta p with z = r (none, and Jacobi on the
+// scaled system) or the stored z (FSAI); a system that stopped in this
+// iteration takes only the x update.  XUP = false (the FSAI start, p = z):
+// no x update.
 template <int PRE, bool XUP = true>
 __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
@@ -367,7 +407,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
     double *__restrict__ x = S.x + vo;
     double *__restrict__ p = S.p + vo;
     const double *__restrict__ r = S.r + vo;
-    const double *__restrict__ dinv = S.dinv + vo;
     const double *__restrict__ z = S.z + vo;
     if (xonly) {
         GRID_LOOP_BEGIN(A.n)
@@ -390,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t e = i_ + j * S_;
-                zv[j] = PRE == PRE_JACOBI ? dinv[e] * r[e] : PRE == PRE_NONE ? r[e] : z[e];
+                zv[j] = PRE == PRE_FSAI ? z[e] : r[e];
                 pv[j] = p[e];
                 if (XUP) xv[j] = x[e];
             }
@@ -401,11 +440,33 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
                 p[e] = zv[j] + beta * pv[j];
             }
     GRID_LOOP_TAIL
-            const double zi = PRE == PRE_JACOBI ? dinv[i_] * r[i_] : PRE == PRE_NONE ? r[i_] : z[i_];
+            const double zi = PRE == PRE_FSAI ? z[i_] : r[i_];
             const double pi = p[i_];
             if (XUP) x[i_] = x[i_] + alpha * pi;
             p[i_] = zi + beta * pi;
     GRID_LOOP_END
+}
+
+// Jacobi on the scaled system: x = S x_scaled after the last iteration.
+__global__ __launch_bounds__(kBlock) void k_cg_unscale(Pat A, Sys S) {
+    SYS_OFFSETS(S, A)
+    (void)part;
+    (void)st;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock)
+        S.x[vo + i] = S.dinv[vo + i] * S.x[vo + i];
+}
+
+// The operator S A S of the scaled system on CSR values (tile form): each
+// entry times S_row S_col.
+__global__ __launch_bounds__(kBlock) void k_scale_sym(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                      const double *__restrict__ sc, double *__restrict__ out) {
+    const int sidx = blockIdx.y;
+    const double *v = val + (int64_t)sidx * nnz;
+    const double *sv = sc + (int64_t)sidx * n;
+    double *o = out + (int64_t)sidx * nnz;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) o[k] = v[k] * (sv[i] * sv[col[k]]);
 }
 
 // FSAI apply, first half: w = G r (G lower, float32 values, FP64 products).
@@ -1172,9 +1233,11 @@ static Plan plan_solve(hsla_handle *h, const Tune &tn, const Pat &A, const FPat 
     // the FSAI factors always use their diagonal-major copies where they
     // have one)
     auto dia_slots = [](const Stencil &sn) { return sn.mask ? dia_slots_for(sn.nofs) : 0; };
-    // right-Jacobi BiCGStab iterates on A D^{-1}, which is not symmetric
-    const bool scaled = method == HSLA_METHOD_BICGSTAB && pre == PRE_JACOBI;
-    const bool half = tn.half && !scaled;
+    // right-Jacobi BiCGStab iterates on A D^{-1}, which is not symmetric;
+    // Jacobi CG on S A S, which is
+    const bool cscaled = method == HSLA_METHOD_BICGSTAB && pre == PRE_JACOBI;
+    const bool scaled = cscaled || (method == HSLA_METHOD_CG && pre == PRE_JACOBI);
+    const bool half = tn.half && !cscaled;
     pl.nsA = half ? kSymNS + A.sn.nofs : tn.dia ? dia_slots(A.sn) : 0;
     const bool fsai = pre == PRE_FSAI && L && U;
     pl.nsF = fsai && L->sn.mask && U->sn.mask ? std::max(dia_slots(L->sn), dia_slots(U->sn)) : 0;
@@ -1241,14 +1304,16 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
     S.aval = values;
     // right-Jacobi BiCGStab iterates on A D^{-1}: its values are scaled
     // below, once D^{-1} is known
-    const bool scaled = method == HSLA_METHOD_BICGSTAB && pre == PRE_JACOBI;
+    const bool cscaled = method == HSLA_METHOD_BICGSTAB && pre == PRE_JACOBI;
+    const bool sscaled = method == HSLA_METHOD_CG && pre == PRE_JACOBI;
+    const bool scaled = cscaled || sscaled;
     const int64_t max_iter = o.max_iter > 0 ? o.max_iter : (10 * n < 100000 ? 10 * n : 100000);
     const dim3 gt(Gt, B), gv(Gv, B), gf(B), gfs(Gf, B);
     {
         char *ex = ws + lay.off_extra;
         if (nsA) {
             double *d = (double *)ex;
-            if (nsA > kSymNS)
+            if (!scaled && nsA > kSymNS)
                 k_to_dia_sym<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values, d);
             else if (!scaled)
                 k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values, d);
@@ -1278,6 +1343,16 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             case PRE_JACOBI:
                 k_cg_init<PRE_JACOBI><<<gv, kBlock, 0, s>>>(A, S, o.use_x0);
                 k_fin_cg_init<PRE_JACOBI><<<gf, kBlock, 0, s>>>(S, Gv, o.rtol, o.atol);
+                // S A S, once S is known
+                if (nsA > kSymNS)
+                    k_to_dia_sym<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values,
+                                                                        (double *)S.dia, S.dinv);
+                else if (nsA)
+                    k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values,
+                                                                    (double *)S.dia, S.dinv, 1);
+                else
+                    k_scale_sym<<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.nnz, A.rp, A.col, values, S.dinv,
+                                                               (double *)S.aval);
                 break;
             default:
                 k_cg_init<PRE_FSAI><<<gv, kBlock, 0, s>>>(A, S, o.use_x0);
@@ -1353,6 +1428,8 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             k_bicg_finish<PRE_JACOBI><<<gv, kBlock, 0, s>>>(A, S);
         else
             k_bicg_finish<PRE_NONE><<<gv, kBlock, 0, s>>>(A, S);
+    } else if (sscaled) {
+        k_cg_unscale<<<gv, kBlock, 0, s>>>(A, S);
     }
     // true residual ||b - A x|| / ||b||
     double *res = (double *)(ws + lay.off_res);
