@@ -64,9 +64,12 @@ def matrix_bytes(n: int, nnz: int, form: str, nofs: int = 0) -> int:
     CSR (values, column indices, row pointers: 12 nnz + 4(n+1)); row tiles
     with 16-bit row masks (8 nnz + 2n); the per-solve diagonal-major copy
     (8 nofs n, zeros where a row has no entry, + masks); its symmetric half
-    form (main and upper diagonals only: 8 (nofs/2 + 1) n + masks)."""
+    form (main and upper diagonals only: 8 (nofs/2 + 1) n + masks), and
+    that of Jacobi CG's scaled operator S A S, whose unit diagonal is not
+    stored (8 (nofs/2) n + masks)."""
     return {"csr": 12 * nnz + 4 * (n + 1), "mask-tiles": 8 * nnz + 2 * n, "diagonal": 8 * nofs * n + 2 * n,
-            "diagonal-half": 8 * (nofs // 2 + 1) * n + 2 * n}[form]
+            "diagonal-half": 8 * (nofs // 2 + 1) * n + 2 * n,
+            "diagonal-half-unit": 8 * (nofs // 2) * n + 2 * n}[form]
 
 
 def spmv_bytes(n: int, nnz: int, form: str, nofs: int = 0) -> int:
@@ -78,13 +81,15 @@ def spmv_bytes(n: int, nnz: int, form: str, nofs: int = 0) -> int:
 def form_of(info: dict, pat) -> str:
     """The SpMV form a solve reports (hsla_info.spmv_form) as a byte-model key."""
     f = info["spmv_form"]
-    if f in ("diagonal", "diagonal-half"):
+    if f in ("diagonal", "diagonal-half", "diagonal-half-unit"):
         return f
     return "mask-tiles" if f == "tiles" and pat.stencil[0] else "csr"
 
 
 FORM_TEXT = {"diagonal": "diagonal-major values + row masks, {} diagonals",
              "diagonal-half": "symmetric half diagonal-major values (main + upper) + row masks, {} diagonals",
+             "diagonal-half-unit": "symmetric half diagonal-major values of S A S (upper only, unit diagonal) + "
+                                   "row masks, {} diagonals",
              "mask-tiles": "row tiles with row masks, {} diagonals", "csr": "csr row tiles"}
 
 
@@ -526,7 +531,8 @@ def run_adjoint(ctx, args, dev):
     # (p gathered, q written: 16n; update and direction: 72n)
     form = form_of(fi[0], pat)
     nofs = pat.stencil[1]
-    per_it = {"diagonal-half": 8 * (nofs // 2 + 1) * n, "diagonal": 8 * nofs * n,
+    per_it = {"diagonal-half-unit": 8 * (nofs // 2) * n, "diagonal-half": 8 * (nofs // 2 + 1) * n,
+              "diagonal": 8 * nofs * n,
               "mask-tiles": 8 * nnz, "csr": 8 * nnz}[form] + 88 * n
     per_it += (2 * n if form != "csr" else 4 * nnz + 4 * (n + 1)) / B
     work = float(per_it * (itf.sum() + itb.sum()) + B * (12 * nnz + 28 * n))

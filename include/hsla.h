@@ -96,7 +96,9 @@ typedef struct hsla_info {
     int64_t spmv_launches;/* profile mode: number of those launches                        */
     int32_t spmv_form;    /* SpMV form of the solve: 0 row tiles (CSR or row masks),
                              1 per-solve diagonal-major copy, 2 its symmetric half form
-                             (main and upper diagonals stored), 3 one persistent launch   */
+                             (main and upper diagonals stored), 3 one persistent launch,
+                             4 the half form of Jacobi CG's scaled operator (upper
+                             diagonals only; its diagonal is 1)                           */
     int32_t reserved;     /* 0                                                             */
 } hsla_info;
 

@@ -54,7 +54,7 @@ class Opts(ctypes.Structure):
     ]
 
 
-SPMV_FORMS = {0: "tiles", 1: "diagonal", 2: "diagonal-half", 3: "persistent"}
+SPMV_FORMS = {0: "tiles", 1: "diagonal", 2: "diagonal-half", 3: "persistent", 4: "diagonal-half-unit"}
 
 
 class Info(ctypes.Structure):

@@ -637,10 +637,16 @@ __host__ __device__ inline int dia_slots_for(int nofs) {
 // neighbours loaded moments before.  Slot counts above kSymNS select this
 // form for NS - kSymNS diagonals.
 constexpr int kSymNS = 100;
+// Slot counts above kUnitNS select the half form of an operator whose
+// diagonal is 1 by construction (Jacobi CG's S A S): the main diagonal is not
+// stored either, and its product is p_i itself.
+constexpr int kUnitNS = 200;
 constexpr int kPencil = 16;  // longest pencil
 
 // Stored diagonals per system of a diagonal-major copy for slot count ns.
-__host__ __device__ inline int dia_stored(int ns, int nofs) { return ns > kSymNS ? nofs / 2 + 1 : nofs; }
+__host__ __device__ inline int dia_stored(int ns, int nofs) {
+    return ns > kUnitNS ? nofs / 2 : ns > kSymNS ? nofs / 2 + 1 : nofs;
+}
 
 inline bool stencil_half_ok(const Stencil &sn) {
     if (!sn.mask || (sn.nofs != 5 && sn.nofs != 7 && sn.nofs != 9)) return false;
@@ -705,7 +711,7 @@ struct PencilWalk {
 // are masked out.  epi(row, y) per row, or epi(row, y, x_row) when the
 // epilogue takes x of its own row too (it is the diagonal slot's gathered
 // value: absent entries gather the row's own x).
-template <int NS, typename VT, class Epi>
+template <int NS, bool UNIT, typename VT, class Epi>
 __device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                              const double *__restrict__ x, Epi &&epi);
 
@@ -713,8 +719,11 @@ template <int NS, typename VT, class Epi>
 __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                          const double *__restrict__ x, Epi &&epi) {
 #pragma clang fp contract(off)
-    if constexpr (NS > kSymNS) {
-        spmv_dia_sym<NS - kSymNS>(sn, dv, n, x, epi);
+    if constexpr (NS > kUnitNS) {
+        spmv_dia_sym<NS - kUnitNS, true>(sn, dv, n, x, epi);
+        return;
+    } else if constexpr (NS > kSymNS) {
+        spmv_dia_sym<NS - kSymNS, false>(sn, dv, n, x, epi);
         return;
     }
     constexpr bool kExact = NS == 5 || NS == 7 || NS == 9;
@@ -791,11 +800,11 @@ struct SymCarry {
     double xlo1 = 0.0, xlo2 = 0.0, xown1 = 0.0, xown2 = 0.0;
 };
 
-template <int NS, bool CONT, typename VT, class Epi>
+template <int NS, bool CONT, bool UNIT, typename VT, class Epi>
 __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                           const double *__restrict__ x, int64_t c, SymCarry<VT> &cy, Epi &&epi) {
 #pragma clang fp contract(off)
-    constexpr int DS = NS / 2, NH = DS + 1;
+    constexpr int DS = NS / 2, NH = UNIT ? DS : DS + 1, U0 = UNIT ? DS + 1 : DS;
     const int64_t i = c * kDiaChunk + threadIdx.x;
     const int64_t i2 = i + kBlock;
     const bool one = i < n, two = i2 < n;
@@ -810,15 +819,18 @@ __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restric
         const int64_t d = sn.ofs[s];
         const int64_t r1 = ((m1 >> s) & 1u) ? i + d : j1;
         const int64_t r2 = ((m2 >> s) & 1u) ? i2 + d : j2;
-        if (s >= DS) {
-            v1[s] = __builtin_nontemporal_load(&base[(s - DS) * kDiaChunk]);
-            v2[s] = __builtin_nontemporal_load(&base[(s - DS) * kDiaChunk + kBlock]);
+        if (UNIT && s == DS) {
+            v1[s] = VT(1);
+            v2[s] = VT(1);
+        } else if (s >= DS) {
+            v1[s] = __builtin_nontemporal_load(&base[(s - U0) * kDiaChunk]);
+            v2[s] = __builtin_nontemporal_load(&base[(s - U0) * kDiaChunk + kBlock]);
         } else if (CONT && s == 0) {
             v1[s] = cy.v1;
             v2[s] = cy.v2;
         } else {
-            v1[s] = dv[dia_index(r1, DS - s, NH)];
-            v2[s] = dv[dia_index(r2, DS - s, NH)];
+            v1[s] = dv[dia_index(r1, NS - 1 - s - U0, NH)];
+            v2[s] = dv[dia_index(r2, NS - 1 - s - U0, NH)];
         }
         if (CONT && s == 0) {
             x1[s] = cy.xlo1;
@@ -857,7 +869,7 @@ __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restric
     }
 }
 
-template <int NS, typename VT, class Epi>
+template <int NS, bool UNIT, typename VT, class Epi>
 __device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                              const double *__restrict__ x, Epi &&epi) {
     static_assert(NS == 5 || NS == 7 || NS == 9, "half form for 5, 7 or 9 diagonals");
@@ -865,7 +877,7 @@ __device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__rest
     SymCarry<VT> cy;
     if (omax % kDiaChunk != 0) {
         const ChunkWalk cw(dia_chunks(n));
-        for (int64_t c = cw.first; c < cw.hi; c += cw.stride) sym_chunk<NS, false>(sn, dv, n, x, c, cy, epi);
+        for (int64_t c = cw.first; c < cw.hi; c += cw.stride) sym_chunk<NS, false, UNIT>(sn, dv, n, x, c, cy, epi);
         return;
     }
     const int P = sn.pencil;
@@ -874,11 +886,11 @@ __device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__rest
         const int64_t col = pw.c0 + it % pw.ncx, seg = it / pw.ncx;
         int64_t c = seg * P * pw.cols + col;
         if (c >= pw.nch) continue;
-        sym_chunk<NS, false>(sn, dv, n, x, c, cy, epi);
+        sym_chunk<NS, false, UNIT>(sn, dv, n, x, c, cy, epi);
         for (int t = 1; t < P; ++t) {
             c += pw.cols;
             if (c >= pw.nch) break;
-            sym_chunk<NS, true>(sn, dv, n, x, c, cy, epi);
+            sym_chunk<NS, true, UNIT>(sn, dv, n, x, c, cy, epi);
         }
     }
 }

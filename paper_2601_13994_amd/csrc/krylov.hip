@@ -112,7 +112,10 @@ __global__ __launch_bounds__(kBlock) void k_to_dia(int32_t n, const int32_t *__r
             VT val = VT(0);
             if ((m >> s) & 1u) {
                 val = v[k++];
-                if (cs) val = VT((double)val * (sym ? cs[i] * cs[i + sn.ofs[s]] : cs[i + sn.ofs[s]]));
+                if (cs && sym && sn.ofs[s] == 0)
+                    val = VT(1);  // the diagonal of S A S is 1 by construction
+                else if (cs)
+                    val = VT((double)val * (sym ? cs[i] * cs[i + sn.ofs[s]] : cs[i + sn.ofs[s]]));
             }
             d[dia_index(i, s, sn.nofs)] = val;
         }
@@ -136,9 +139,10 @@ __global__ __launch_bounds__(kBlock) void k_scale_cols(int32_t n, int64_t nnz, c
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_to_dia_sym(int32_t n, const int32_t *__restrict__ rp, Stencil sn,
                                                        int64_t nnz, const VT *__restrict__ vals,
-                                                       VT *__restrict__ dia, const double *__restrict__ sc = nullptr) {
+                                                       VT *__restrict__ dia, const double *__restrict__ sc = nullptr,
+                                                       int unit = 0) {
     const int sidx = blockIdx.y;
-    const int ds = sn.nofs / 2, nh = ds + 1;
+    const int ds = sn.nofs / 2, nh = unit ? ds : ds + 1, u0 = unit ? ds + 1 : ds;
     const int64_t rows = dia_chunks(n) * kDiaChunk;
     const VT *v = vals + (int64_t)sidx * nnz;
     VT *d = dia + (int64_t)sidx * nh * rows;
@@ -152,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_to_dia_sym(int32_t n, const int32_t 
                 val = v[k++];
                 if (cs) val = VT((double)val * (cs[i] * cs[i + sn.ofs[s]]));
             }
-            d[dia_index(i, s - ds, nh)] = val;
+            if (s >= u0) d[dia_index(i, s - u0, nh)] = val;
         }
     }
 }
@@ -457,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_unscale(Pat A, Sys S) {
 }
 
 // The operator S A S of the scaled system on CSR values (tile form): each
-// entry times S_row S_col.
+// entry times S_row S_col, the diagonal 1 by construction.
 __global__ __launch_bounds__(kBlock) void k_scale_sym(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                       const int32_t *__restrict__ col, const double *__restrict__ val,
                                                       const double *__restrict__ sc, double *__restrict__ out) {
@@ -466,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_scale_sym(int32_t n, int64_t nnz, co
     const double *sv = sc + (int64_t)sidx * n;
     double *o = out + (int64_t)sidx * nnz;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) o[k] = v[k] * (sv[i] * sv[col[k]]);
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) o[k] = col[k] == i ? 1.0 : v[k] * (sv[i] * sv[col[k]]);
 }
 
 // FSAI apply, first half: w = G r (G lower, float32 values, FP64 products).
@@ -1007,6 +1011,9 @@ __global__ __launch_bounds__(kBlock) void k_fill_f64(double *__restrict__ a, int
         case kSymNS + 5: K<kSymNS + 5><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
         case kSymNS + 7: K<kSymNS + 7><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
         case kSymNS + 9: K<kSymNS + 9><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
+        case kUnitNS + 5: K<kUnitNS + 5><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
+        case kUnitNS + 7: K<kUnitNS + 7><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
+        case kUnitNS + 9: K<kUnitNS + 9><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
         default: NS_LAUNCH(K, ns, grid, __VA_ARGS__);                          \
     }
 
@@ -1238,7 +1245,8 @@ static Plan plan_solve(hsla_handle *h, const Tune &tn, const Pat &A, const FPat 
     const bool cscaled = method == HSLA_METHOD_BICGSTAB && pre == PRE_JACOBI;
     const bool scaled = cscaled || (method == HSLA_METHOD_CG && pre == PRE_JACOBI);
     const bool half = tn.half && !cscaled;
-    pl.nsA = half ? kSymNS + A.sn.nofs : tn.dia ? dia_slots(A.sn) : 0;
+    const bool unit = half && scaled;  // Jacobi CG: S A S has a unit diagonal
+    pl.nsA = half ? (unit ? kUnitNS : kSymNS) + A.sn.nofs : tn.dia ? dia_slots(A.sn) : 0;
     const bool fsai = pre == PRE_FSAI && L && U;
     pl.nsF = fsai && L->sn.mask && U->sn.mask ? std::max(dia_slots(L->sn), dia_slots(U->sn)) : 0;
     pl.pencil = half ? pencil_len(A.sn, n, B, h->dev.num_cu) : 1;
@@ -1346,7 +1354,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
                 // S A S, once S is known
                 if (nsA > kSymNS)
                     k_to_dia_sym<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values,
-                                                                        (double *)S.dia, S.dinv);
+                                                                        (double *)S.dia, S.dinv, nsA > kUnitNS);
                 else if (nsA)
                     k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values,
                                                                     (double *)S.dia, S.dinv, 1);
@@ -1455,7 +1463,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             f.true_residual = tb > 0 ? tr / tb : tr;
             f.spmv_ms = prof_ms;
             f.spmv_launches = prof_n;
-            f.spmv_form = nsA > kSymNS ? 2 : nsA > 0 ? 1 : 0;
+            f.spmv_form = nsA > kUnitNS ? 4 : nsA > kSymNS ? 2 : nsA > 0 ? 1 : 0;
             f.reserved = 0;
         }
     }

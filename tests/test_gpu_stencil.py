@@ -235,7 +235,7 @@ def test_half_form_solves(orc, method):
     pat = pattern(a)
     opts = _lib.make_opts(method=method, precond="jacobi", rtol=1e-12, persistent=False)
     res = _both(pat, lambda: _lib.solve(pat, t64(V), t64(b), opts))
-    form = "diagonal-half" if method == "cg" else "diagonal"
+    form = "diagonal-half-unit" if method == "cg" else "diagonal"
     assert all(f["spmv_form"] == form for f in res[0][1])
     assert all(f["spmv_form"] == "tiles" for f in res[1][1])
     _close(*res, cg=method == "cg")
@@ -245,7 +245,7 @@ def test_half_form_solves(orc, method):
         x = res[0][0]
         gx = t64(r.standard_normal((2, a.n)))
         gA, gb, bi, st = _lib.adjoint(pat, t64(V), x, gx, opts)
-        assert st == _lib.OK and all(f["spmv_form"] == "diagonal-half" for f in bi)
+        assert st == _lib.OK and all(f["spmv_form"] == "diagonal-half-unit" for f in bi)
         gA_o, gb_o, _ = orc.adjoint(a, x[0].cpu().numpy(), gx[0].cpu().numpy(), method="cg", precond="jacobi",
                                     rtol=1e-12)
         assert rel(gb[0].cpu().numpy(), gb_o) <= 1e-8
