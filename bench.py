@@ -69,7 +69,7 @@ def matrix_bytes(n: int, nnz: int, form: str, nofs: int = 0) -> int:
     stored (8 (nofs/2) n + masks)."""
     return {"csr": 12 * nnz + 4 * (n + 1), "mask-tiles": 8 * nnz + 2 * n, "diagonal": 8 * nofs * n + 2 * n,
             "diagonal-half": 8 * (nofs // 2 + 1) * n + 2 * n,
-            "diagonal-half-unit": 8 * (nofs // 2) * n + 2 * n}[form]
+            "diagonal-half-unit": 8 * (nofs // 2) * n + 2 * n, "diagonal-unit": 8 * (nofs - 1) * n + 2 * n}[form]
 
 
 def spmv_bytes(n: int, nnz: int, form: str, nofs: int = 0) -> int:
@@ -81,7 +81,7 @@ def spmv_bytes(n: int, nnz: int, form: str, nofs: int = 0) -> int:
 def form_of(info: dict, pat) -> str:
     """The SpMV form a solve reports (hsla_info.spmv_form) as a byte-model key."""
     f = info["spmv_form"]
-    if f in ("diagonal", "diagonal-half", "diagonal-half-unit"):
+    if f in ("diagonal", "diagonal-half", "diagonal-half-unit", "diagonal-unit"):
         return f
     return "mask-tiles" if f == "tiles" and pat.stencil[0] else "csr"
 
@@ -90,6 +90,7 @@ FORM_TEXT = {"diagonal": "diagonal-major values + row masks, {} diagonals",
              "diagonal-half": "symmetric half diagonal-major values (main + upper) + row masks, {} diagonals",
              "diagonal-half-unit": "symmetric half diagonal-major values of S A S (upper only, unit diagonal) + "
                                    "row masks, {} diagonals",
+             "diagonal-unit": "diagonal-major values of A D^-1 without its unit diagonal + row masks, {} diagonals",
              "mask-tiles": "row tiles with row masks, {} diagonals", "csr": "csr row tiles"}
 
 

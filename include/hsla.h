@@ -98,7 +98,8 @@ typedef struct hsla_info {
                              1 per-solve diagonal-major copy, 2 its symmetric half form
                              (main and upper diagonals stored), 3 one persistent launch,
                              4 the half form of Jacobi CG's scaled operator (upper
-                             diagonals only; its diagonal is 1)                           */
+                             diagonals only; its diagonal is 1), 5 the full copy of
+                             right-Jacobi BiCGStab's A D^{-1} without its unit diagonal    */
     int32_t reserved;     /* 0                                                             */
 } hsla_info;
 

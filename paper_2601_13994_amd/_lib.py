@@ -54,7 +54,8 @@ class Opts(ctypes.Structure):
     ]
 
 
-SPMV_FORMS = {0: "tiles", 1: "diagonal", 2: "diagonal-half", 3: "persistent", 4: "diagonal-half-unit"}
+SPMV_FORMS = {0: "tiles", 1: "diagonal", 2: "diagonal-half", 3: "persistent", 4: "diagonal-half-unit",
+              5: "diagonal-unit"}
 
 
 class Info(ctypes.Structure):

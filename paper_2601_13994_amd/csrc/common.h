@@ -641,11 +641,15 @@ constexpr int kSymNS = 100;
 // diagonal is 1 by construction (Jacobi CG's S A S): the main diagonal is not
 // stored either, and its product is p_i itself.
 constexpr int kUnitNS = 200;
+// Slot counts above kUnitFullNS select the full copy of an operator whose
+// diagonal is 1 by construction (right-Jacobi BiCGStab's A D^{-1}): every
+// diagonal but the main one is stored.
+constexpr int kUnitFullNS = 300;
 constexpr int kPencil = 16;  // longest pencil
 
 // Stored diagonals per system of a diagonal-major copy for slot count ns.
 __host__ __device__ inline int dia_stored(int ns, int nofs) {
-    return ns > kUnitNS ? nofs / 2 : ns > kSymNS ? nofs / 2 + 1 : nofs;
+    return ns > kUnitFullNS ? nofs - 1 : ns > kUnitNS ? nofs / 2 : ns > kSymNS ? nofs / 2 + 1 : nofs;
 }
 
 inline bool stencil_half_ok(const Stencil &sn) {
@@ -715,22 +719,36 @@ template <int NS, bool UNIT, typename VT, class Epi>
 __device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                              const double *__restrict__ x, Epi &&epi);
 
+template <int NS, bool UF, typename VT, class Epi>
+__device__ __forceinline__ void spmv_dia_full(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
+                                              const double *__restrict__ x, Epi &&epi);
+
 template <int NS, typename VT, class Epi>
 __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                          const double *__restrict__ x, Epi &&epi) {
-#pragma clang fp contract(off)
-    if constexpr (NS > kUnitNS) {
+    if constexpr (NS > kUnitFullNS)
+        spmv_dia_full<NS - kUnitFullNS, true>(sn, dv, n, x, epi);
+    else if constexpr (NS > kUnitNS)
         spmv_dia_sym<NS - kUnitNS, true>(sn, dv, n, x, epi);
-        return;
-    } else if constexpr (NS > kSymNS) {
+    else if constexpr (NS > kSymNS)
         spmv_dia_sym<NS - kSymNS, false>(sn, dv, n, x, epi);
-        return;
-    }
+    else
+        spmv_dia_full<NS, false>(sn, dv, n, x, epi);
+}
+
+// The full copy; UF: the main diagonal is 1 and not stored (slots past it
+// move down by one).
+template <int NS, bool UF, typename VT, class Epi>
+__device__ __forceinline__ void spmv_dia_full(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
+                                              const double *__restrict__ x, Epi &&epi) {
+#pragma clang fp contract(off)
     constexpr bool kExact = NS == 5 || NS == 7 || NS == 9;
+    static_assert(!UF || kExact, "the unit-diagonal copy has 5, 7 or 9 diagonals");
     constexpr int kGroup = kExact ? NS : 4;
     const ChunkWalk cw(dia_chunks(n));
     const uint16_t *__restrict__ mask = sn.mask;
     const int nofs = kExact ? NS : sn.nofs;
+    const int nst = UF ? nofs - 1 : nofs;  // stored diagonals
     for (int64_t c = cw.first; c < cw.hi; c += cw.stride) {
         const int64_t i = c * kDiaChunk + threadIdx.x;
         const int64_t i2 = i + kBlock;
@@ -738,7 +756,7 @@ __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict
         const int64_t j1 = one ? i : 0, j2 = two ? i2 : 0;
         const uint32_t m1 = one ? (uint32_t)mask[i] : 0u;
         const uint32_t m2 = two ? (uint32_t)mask[i2] : 0u;
-        const VT *__restrict__ base = dv + c * nofs * kDiaChunk + threadIdx.x;
+        const VT *__restrict__ base = dv + c * nst * kDiaChunk + threadIdx.x;
         double a1 = 0.0, a2 = 0.0;
         double c1 = 0.0, c2 = 0.0;  // x of the rows themselves
         const int ds = sn.diag_slot;
@@ -752,8 +770,14 @@ __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict
                     const int s = kExact ? g + u : (g + u < nofs ? g + u : nofs - 1);
                     const int64_t d = sn.ofs[s];
                     const bool o1 = (m1 >> (g + u)) & 1u, o2 = (m2 >> (g + u)) & 1u;
-                    v1[u] = __builtin_nontemporal_load(&base[s * kDiaChunk]);
-                    v2[u] = __builtin_nontemporal_load(&base[s * kDiaChunk + kBlock]);
+                    if (UF && s == sn.diag_slot) {
+                        v1[u] = VT(1);
+                        v2[u] = VT(1);
+                    } else {
+                        const int si = UF && s > sn.diag_slot ? s - 1 : s;
+                        v1[u] = __builtin_nontemporal_load(&base[si * kDiaChunk]);
+                        v2[u] = __builtin_nontemporal_load(&base[si * kDiaChunk + kBlock]);
+                    }
                     x1[u] = x[o1 ? i + d : j1];
                     x2[u] = x[o2 ? i2 + d : j2];
                 }

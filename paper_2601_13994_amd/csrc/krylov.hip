@@ -96,14 +96,18 @@ __device__ __forceinline__ void spmv_F(const FPat &F, int64_t n, int sidx, const
 // `cscale` ([B][n]) the entry (i, j) is multiplied by cscale[j] (the
 // operator A D^{-1} of right-Jacobi BiCGStab) or, with `sym`, by
 // cscale[i] cscale[j] (S A S of Jacobi CG).
+// `unit`: the diagonal of the scaled operator is 1 and is left out (slots
+// past it move down by one; needs a diagonal slot).
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_to_dia(int32_t n, const int32_t *__restrict__ rp, Stencil sn,
                                                    int64_t nnz, const VT *__restrict__ vals, VT *__restrict__ dia,
-                                                   const double *__restrict__ cscale = nullptr, int sym = 0) {
+                                                   const double *__restrict__ cscale = nullptr, int sym = 0,
+                                                   int unit = 0) {
     const int sidx = blockIdx.y;
     const int64_t rows = dia_chunks(n) * kDiaChunk;
+    const int nst = unit ? sn.nofs - 1 : sn.nofs;
     const VT *v = vals + (int64_t)sidx * nnz;
-    VT *d = dia + (int64_t)sidx * sn.nofs * rows;
+    VT *d = dia + (int64_t)sidx * nst * rows;
     const double *cs = cscale ? cscale + (int64_t)sidx * n : nullptr;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < rows; i += (int64_t)gridDim.x * kBlock) {
         const uint32_t m = i < n ? (uint32_t)sn.mask[i] : 0u;
@@ -117,21 +121,24 @@ __global__ __launch_bounds__(kBlock) void k_to_dia(int32_t n, const int32_t *__r
                 else if (cs)
                     val = VT((double)val * (sym ? cs[i] * cs[i + sn.ofs[s]] : cs[i + sn.ofs[s]]));
             }
-            d[dia_index(i, s, sn.nofs)] = val;
+            if (unit && s == sn.diag_slot) continue;
+            d[dia_index(i, unit && s > sn.diag_slot ? s - 1 : s, nst)] = val;
         }
     }
 }
 
-// The same column scaling on the CSR values (tile form): out = val D^{-1}.
-__global__ __launch_bounds__(kBlock) void k_scale_cols(int32_t n, int64_t nnz, const int32_t *__restrict__ col,
+// The same column scaling on the CSR values (tile form): out = val D^{-1},
+// the diagonal 1 by construction.
+__global__ __launch_bounds__(kBlock) void k_scale_cols(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col,
                                                        const double *__restrict__ val,
                                                        const double *__restrict__ cscale, double *__restrict__ out) {
     const int sidx = blockIdx.y;
     const double *v = val + (int64_t)sidx * nnz;
     const double *cs = cscale + (int64_t)sidx * n;
     double *o = out + (int64_t)sidx * nnz;
-    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kBlock)
-        o[k] = v[k] * cs[col[k]];
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) o[k] = col[k] == i ? 1.0 : v[k] * cs[col[k]];
 }
 
 // The half form's copy (see kSymNS): the main and upper diagonals only, at
@@ -1014,6 +1021,9 @@ __global__ __launch_bounds__(kBlock) void k_fill_f64(double *__restrict__ a, int
         case kUnitNS + 5: K<kUnitNS + 5><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
         case kUnitNS + 7: K<kUnitNS + 7><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
         case kUnitNS + 9: K<kUnitNS + 9><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
+        case kUnitFullNS + 5: K<kUnitFullNS + 5><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
+        case kUnitFullNS + 7: K<kUnitFullNS + 7><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
+        case kUnitFullNS + 9: K<kUnitFullNS + 9><<<grid, kBlock, 0, s>>>(__VA_ARGS__); break; \
         default: NS_LAUNCH(K, ns, grid, __VA_ARGS__);                          \
     }
 
@@ -1246,7 +1256,12 @@ static Plan plan_solve(hsla_handle *h, const Tune &tn, const Pat &A, const FPat 
     const bool scaled = cscaled || (method == HSLA_METHOD_CG && pre == PRE_JACOBI);
     const bool half = tn.half && !cscaled;
     const bool unit = half && scaled;  // Jacobi CG: S A S has a unit diagonal
-    pl.nsA = half ? (unit ? kUnitNS : kSymNS) + A.sn.nofs : tn.dia ? dia_slots(A.sn) : 0;
+    // right-Jacobi BiCGStab: A D^{-1} has a unit diagonal, left out of the full copy
+    const bool unit_full = cscaled && tn.dia && A.sn.mask && A.sn.diag_slot >= 0 &&
+                           (A.sn.nofs == 5 || A.sn.nofs == 7 || A.sn.nofs == 9);
+    pl.nsA = half ? (unit ? kUnitNS : kSymNS) + A.sn.nofs : unit_full ? kUnitFullNS + A.sn.nofs
+             : tn.dia                                  ? dia_slots(A.sn)
+                                                       : 0;
     const bool fsai = pre == PRE_FSAI && L && U;
     pl.nsF = fsai && L->sn.mask && U->sn.mask ? std::max(dia_slots(L->sn), dia_slots(U->sn)) : 0;
     pl.pencil = half ? pencil_len(A.sn, n, B, h->dev.num_cu) : 1;
@@ -1379,9 +1394,9 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
         k_fin_bicg_init<<<gf, kBlock, 0, s>>>(S, Gv, o.rtol, o.atol);
         if (scaled && nsA)
             k_to_dia<double><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.rp, A.sn, A.nnz, values,
-                                                            (double *)S.dia, S.dinv);
+                                                            (double *)S.dia, S.dinv, 0, nsA > kUnitFullNS);
         else if (scaled)
-            k_scale_cols<<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.nnz, A.col, values, S.dinv,
+            k_scale_cols<<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, A.nnz, A.rp, A.col, values, S.dinv,
                                                         (double *)S.aval);
     }
     HSLA_HIP(h, hipGetLastError());
@@ -1463,7 +1478,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             f.true_residual = tb > 0 ? tr / tb : tr;
             f.spmv_ms = prof_ms;
             f.spmv_launches = prof_n;
-            f.spmv_form = nsA > kUnitNS ? 4 : nsA > kSymNS ? 2 : nsA > 0 ? 1 : 0;
+            f.spmv_form = nsA > kUnitFullNS ? 5 : nsA > kUnitNS ? 4 : nsA > kSymNS ? 2 : nsA > 0 ? 1 : 0;
             f.reserved = 0;
         }
     }

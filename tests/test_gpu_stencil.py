@@ -235,7 +235,7 @@ def test_half_form_solves(orc, method):
     pat = pattern(a)
     opts = _lib.make_opts(method=method, precond="jacobi", rtol=1e-12, persistent=False)
     res = _both(pat, lambda: _lib.solve(pat, t64(V), t64(b), opts))
-    form = "diagonal-half-unit" if method == "cg" else "diagonal"
+    form = "diagonal-half-unit" if method == "cg" else "diagonal-unit"
     assert all(f["spmv_form"] == form for f in res[0][1])
     assert all(f["spmv_form"] == "tiles" for f in res[1][1])
     _close(*res, cg=method == "cg")
