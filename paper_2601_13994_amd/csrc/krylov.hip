@@ -480,37 +480,37 @@ __global__ __launch_bounds__(kBlock) void k_scale_sym(int32_t n, int64_t nnz, co
         for (int32_t k = rp[i]; k < rp[i + 1]; ++k) o[k] = col[k] == i ? 1.0 : v[k] * (sv[i] * sv[col[k]]);
 }
 
-// FSAI apply, first half: w = G r (G lower, float32 values, FP64 products).
+// FSAI apply, first half: w = G r (G lower, float32 values, FP64 products)
+// and partials of r.z = r^T G^T G r = w.w, so the second half needs no r.
 template <int NS>
-__global__ __launch_bounds__(kBlock) void k_fsai_lower(Pat A, FPat L, Sys S) {
+__global__ __launch_bounds__(kBlock) void k_fsai_lower_dot(Pat A, FPat L, Sys S) {
+    __shared__ double lds[kWavesPerBlock][kTileCap];
+    SYS_OFFSETS(S, A)
+    if (stopped(st)) return;
+    const double *r = S.r + vo;
+    double *w = S.w + vo;
+    double acc[1] = {0.0};
+    spmv_F<NS>(L, A.n, sidx, r, lds[threadIdx.x / kWave],
+               [&](int64_t row, double yv) {
+                   w[row] = yv;
+                   acc[0] += yv * yv;
+               });
+    block_partial<1>(acc, part);
+}
+
+// FSAI apply, second half: z = G^T w.
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_fsai_upper(Pat A, FPat U, Sys S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
     (void)part;
     if (stopped(st)) return;
-    const double *r = S.r + vo;
-    double *w = S.w + vo;
-    spmv_F<NS>(L, A.n, sidx, r, lds[threadIdx.x / kWave],
-               [&](int64_t row, double yv) {
-                   w[row] = yv;
-               });
-}
-
-// FSAI apply, second half: z = G^T w and partials of r.z.
-template <int NS>
-__global__ __launch_bounds__(kBlock) void k_fsai_upper_dot(Pat A, FPat U, Sys S) {
-    __shared__ double lds[kWavesPerBlock][kTileCap];
-    SYS_OFFSETS(S, A)
-    if (stopped(st)) return;
     const double *w = S.w + vo;
-    const double *r = S.r + vo;
     double *z = S.z + vo;
-    double acc[1] = {0.0};
     spmv_F<NS>(U, A.n, sidx, w, lds[threadIdx.x / kWave],
                [&](int64_t row, double yv) {
                    z[row] = yv;
-                   acc[0] += r[row] * yv;
                });
-    block_partial<1>(acc, part);
 }
 
 // Set-up: rho = r.z (p = z follows from beta = 0 and p = 0); iteration:
@@ -1104,8 +1104,8 @@ static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hip
                 default:
                     k_cg_update<PRE_FSAI><<<gv, kBlock, 0, s>>>(c.A, c.S);
                     k_fin_beta<PRE_FSAI><<<gf, kBlock, 0, s>>>(c.S, Gv);
-                    NS_LAUNCH(k_fsai_lower, c.nsF, gfs, c.A, c.L, c.S);
-                    NS_LAUNCH(k_fsai_upper_dot, c.nsF, gfs, c.A, c.U, c.S);
+                    NS_LAUNCH(k_fsai_lower_dot, c.nsF, gfs, c.A, c.L, c.S);
+                    NS_LAUNCH(k_fsai_upper, c.nsF, gfs, c.A, c.U, c.S);
                     k_fin_fsai<<<gf, kBlock, 0, s>>>(c.S, Gfs, 0);
                     k_cg_direction<PRE_FSAI><<<gv, kBlock, 0, s>>>(c.A, c.S);
                     break;
@@ -1380,8 +1380,8 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             default:
                 k_cg_init<PRE_FSAI><<<gv, kBlock, 0, s>>>(A, S, o.use_x0);
                 k_fin_cg_init<PRE_FSAI><<<gf, kBlock, 0, s>>>(S, Gv, o.rtol, o.atol);
-                NS_LAUNCH(k_fsai_lower, nsF, gfs, A, c.L, S);
-                NS_LAUNCH(k_fsai_upper_dot, nsF, gfs, A, c.U, S);
+                NS_LAUNCH(k_fsai_lower_dot, nsF, gfs, A, c.L, S);
+                NS_LAUNCH(k_fsai_upper, nsF, gfs, A, c.U, S);
                 k_fin_fsai<<<gf, kBlock, 0, s>>>(S, Gf, 1);
                 k_cg_direction<PRE_FSAI, false><<<gv, kBlock, 0, s>>>(A, S);
                 break;
