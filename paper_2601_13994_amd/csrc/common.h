@@ -810,19 +810,29 @@ __device__ __forceinline__ void spmv_dia_full(const Stencil &sn, const VT *__res
 
 // The half form's SpMV (see kSymNS): the same products as spmv_dia, added
 // in the same ascending diagonal order, so the result is bitwise that of the
-// full copy, the tiles and CSR.  The upper and main diagonals stream
-// (nontemporal); the lower ones are cached re-reads.  Along a pencil the
+// full copy, the tiles and CSR.  The upper and main diagonals stream; the
+// lower ones are re-reads of the mirrored upper entries.  Along a pencil the
 // previous plane's +o_max values are, in registers, this plane's -o_max
 // values, and x moves the same way: the previous plane's own x is this
-// plane's x at -o_max, and its x at +o_max (gathered whenever that row
-// exists) is this plane's own x.  When o_max is not a multiple of kDiaChunk
-// (small planes) the chunks are walked as in spmv_dia and every lower value
-// is a re-read from the chunk or the one before.
+// plane's x at -o_max, and its x at +o_max is this plane's own x.  When o_max
+// is not a multiple of kDiaChunk (small planes) the chunks are walked as in
+// spmv_dia and every lower value is a re-read.
+//
+// Two row layouts.  Paired (sym_pair): each thread takes two adjacent rows
+// r0 = 2t, r1 = 2t + 1 of the chunk, so that every stream and every gather
+// at an even offset is one 16-byte load for both rows, and the pair's own
+// entries and x are each other's -1 and +1 neighbours.  It needs the offsets
+// -1 and +1 beside the main diagonal, every other offset even, n even and x
+// 16-byte aligned: then a pair start clamped into [0, n - 2] reads exactly
+// the x of every row whose mask keeps the product.  Otherwise (sym_chunk)
+// each thread takes rows t and t + 256, one 8-byte load per row.
 template <typename VT>
 struct SymCarry {
-    VT v1 = VT(0), v2 = VT(0);
-    double xlo1 = 0.0, xlo2 = 0.0, xown1 = 0.0, xown2 = 0.0;
+    VT v0 = VT(0), v1 = VT(0);
+    double xlo0 = 0.0, xlo1 = 0.0, xown0 = 0.0, xown1 = 0.0;
 };
+
+__device__ __forceinline__ int64_t clamp_row(int64_t r, int64_t n) { return r < 0 ? 0 : r < n ? r : n - 1; }
 
 template <int NS, bool CONT, bool UNIT, typename VT, class Epi>
 __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
@@ -841,30 +851,29 @@ __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restric
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int64_t d = sn.ofs[s];
-        const int64_t r1 = ((m1 >> s) & 1u) ? i + d : j1;
-        const int64_t r2 = ((m2 >> s) & 1u) ? i2 + d : j2;
+        // gather rows clamped into [0, n) rather than chosen by the mask, so
+        // that no address waits for the mask load; the mask gates the adds
+        const int64_t r1 = clamp_row(j1 + d, n);
+        const int64_t r2 = clamp_row(j2 + d, n);
         if (UNIT && s == DS) {
             v1[s] = VT(1);
             v2[s] = VT(1);
         } else if (s >= DS) {
-            v1[s] = __builtin_nontemporal_load(&base[(s - U0) * kDiaChunk]);
-            v2[s] = __builtin_nontemporal_load(&base[(s - U0) * kDiaChunk + kBlock]);
+            v1[s] = base[(s - U0) * kDiaChunk];
+            v2[s] = base[(s - U0) * kDiaChunk + kBlock];
         } else if (CONT && s == 0) {
-            v1[s] = cy.v1;
-            v2[s] = cy.v2;
+            v1[s] = cy.v0;
+            v2[s] = cy.v1;
         } else {
             v1[s] = dv[dia_index(r1, NS - 1 - s - U0, NH)];
             v2[s] = dv[dia_index(r2, NS - 1 - s - U0, NH)];
         }
         if (CONT && s == 0) {
-            x1[s] = cy.xlo1;
-            x2[s] = cy.xlo2;
+            x1[s] = cy.xlo0;
+            x2[s] = cy.xlo1;
         } else if (CONT && s == DS) {
-            x1[s] = cy.xown1;
-            x2[s] = cy.xown2;
-        } else if (s == NS - 1) {
-            x1[s] = x[i + d < n ? i + d : j1];
-            x2[s] = x[i2 + d < n ? i2 + d : j2];
+            x1[s] = cy.xown0;
+            x2[s] = cy.xown1;
         } else {
             x1[s] = x[r1];
             x2[s] = x[r2];
@@ -878,12 +887,12 @@ __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restric
         if ((m1 >> s) & 1u) a1 = a1 + p1;
         if ((m2 >> s) & 1u) a2 = a2 + p2;
     }
-    cy.v1 = v1[NS - 1];
-    cy.v2 = v2[NS - 1];
-    cy.xlo1 = x1[DS];
-    cy.xlo2 = x2[DS];
-    cy.xown1 = x1[NS - 1];
-    cy.xown2 = x2[NS - 1];
+    cy.v0 = v1[NS - 1];
+    cy.v1 = v2[NS - 1];
+    cy.xlo0 = x1[DS];
+    cy.xlo1 = x2[DS];
+    cy.xown0 = x1[NS - 1];
+    cy.xown1 = x2[NS - 1];
     if constexpr (std::is_invocable_v<Epi, int64_t, double, double>) {
         if (one) epi(i, a1, x1[DS]);
         if (two) epi(i2, a2, x2[DS]);
@@ -893,15 +902,115 @@ __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restric
     }
 }
 
-template <int NS, bool UNIT, typename VT, class Epi>
-__device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
-                                             const double *__restrict__ x, Epi &&epi) {
-    static_assert(NS == 5 || NS == 7 || NS == 9, "half form for 5, 7 or 9 diagonals");
+typedef double dpair __attribute__((ext_vector_type(2)));
+
+template <int NS, bool CONT, bool UNIT, typename VT, class Epi>
+__device__ __forceinline__ void sym_pair(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
+                                         const double *__restrict__ x, int64_t c, SymCarry<VT> &cy, Epi &&epi) {
+#pragma clang fp contract(off)
+    static_assert(std::is_same_v<VT, double>, "the paired layout reads FP64 pairs");
+    constexpr int DS = NS / 2, NH = UNIT ? DS : DS + 1, U0 = UNIT ? DS + 1 : DS;
+    const int64_t r0 = c * kDiaChunk + 2 * (int64_t)threadIdx.x;
+    const int64_t npad = dia_chunks(n) * kDiaChunk;  // rows of the padded diagonal-major copy
+    const bool one = r0 < n;                         // n is even: r0 and r0 + 1 exist together
+    const uint32_t w = one ? *(const uint32_t *)(sn.mask + r0) : 0u;
+    const uint32_t m0 = w & 0xffffu, m1 = w >> 16;
+    const VT *__restrict__ base = dv + c * NH * kDiaChunk + 2 * (int64_t)threadIdx.x;
+    VT v0[NS], v1[NS];
+    double x0[NS], x1[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int64_t d = sn.ofs[s];
+        const int ms = NS - 1 - s - U0;  // stored slot of the mirrored upper entry
+        if (UNIT && s == DS) {
+            v0[s] = VT(1);
+            v1[s] = VT(1);
+        } else if (s >= DS) {
+            const dpair t = *(const dpair *)(base + (s - U0) * kDiaChunk);
+            v0[s] = t.x;
+            v1[s] = t.y;
+        } else if (CONT && s == 0) {
+            v0[s] = cy.v0;
+            v1[s] = cy.v1;
+        } else if (s == DS - 1) {  // d = -1: row r1's entry mirrors row r0's +1 entry
+            v0[s] = dv[dia_index(clamp_row(r0 - 1, n), ms, NH)];
+        } else {
+            const int64_t a = r0 + d, pa = a < 0 ? 0 : a > npad - 2 ? npad - 2 : a;
+            const dpair t = *(const dpair *)(dv + dia_index(pa, ms, NH));
+            v0[s] = t.x;
+            v1[s] = t.y;
+        }
+        if (CONT && s == 0) {
+            x0[s] = cy.xlo0;
+            x1[s] = cy.xlo1;
+        } else if (CONT && s == DS) {
+            x0[s] = cy.xown0;
+            x1[s] = cy.xown1;
+        } else if (s == DS - 1) {
+            x0[s] = x[clamp_row(r0 - 1, n)];
+        } else if (s == DS + 1) {
+            x1[s] = x[clamp_row(r0 + 2, n)];
+        } else {
+            const int64_t a = r0 + d, pa = a < 0 ? 0 : a > n - 2 ? n - 2 : a;
+            const dpair t = *(const dpair *)(x + pa);
+            x0[s] = t.x;
+            x1[s] = t.y;
+        }
+    }
+    v1[DS - 1] = v0[DS + 1];
+    x1[DS - 1] = x0[DS];
+    x0[DS + 1] = x1[DS];
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const double p0 = (double)v0[s] * x0[s];
+        const double p1 = (double)v1[s] * x1[s];
+        if ((m0 >> s) & 1u) a0 = a0 + p0;
+        if ((m1 >> s) & 1u) a1 = a1 + p1;
+    }
+    cy.v0 = v0[NS - 1];
+    cy.v1 = v1[NS - 1];
+    cy.xlo0 = x0[DS];
+    cy.xlo1 = x1[DS];
+    cy.xown0 = x0[NS - 1];
+    cy.xown1 = x1[NS - 1];
+    if (one) {
+        if constexpr (std::is_invocable_v<Epi, int64_t, double, double>) {
+            epi(r0, a0, x0[DS]);
+            epi(r0 + 1, a1, x1[DS]);
+        } else {
+            epi(r0, a0);
+            epi(r0 + 1, a1);
+        }
+    }
+}
+
+// Whether the paired layout applies (see sym_pair).
+template <int NS>
+__device__ __forceinline__ bool sym_pairable(const Stencil &sn, int64_t n, const double *x) {
+    constexpr int DS = NS / 2;
+    if ((n & 1) != 0 || ((uintptr_t)x & 15u) != 0) return false;
+    if (sn.ofs[DS - 1] != -1 || sn.ofs[DS + 1] != 1) return false;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+        if (s != DS - 1 && s != DS + 1 && (sn.ofs[s] & 1) != 0) return false;
+    return true;
+}
+
+template <int NS, bool UNIT, bool PAIR, typename VT, class Epi>
+__device__ __forceinline__ void sym_walk(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
+                                         const double *__restrict__ x, Epi &&epi) {
     const int64_t omax = sn.ofs[NS - 1];
     SymCarry<VT> cy;
+    auto step = [&](int64_t c, auto cont) {
+        if constexpr (PAIR)
+            sym_pair<NS, decltype(cont)::value, UNIT>(sn, dv, n, x, c, cy, epi);
+        else
+            sym_chunk<NS, decltype(cont)::value, UNIT>(sn, dv, n, x, c, cy, epi);
+    };
     if (omax % kDiaChunk != 0) {
         const ChunkWalk cw(dia_chunks(n));
-        for (int64_t c = cw.first; c < cw.hi; c += cw.stride) sym_chunk<NS, false, UNIT>(sn, dv, n, x, c, cy, epi);
+        for (int64_t c = cw.first; c < cw.hi; c += cw.stride) step(c, std::false_type{});
         return;
     }
     const int P = sn.pencil;
@@ -910,13 +1019,23 @@ __device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__rest
         const int64_t col = pw.c0 + it % pw.ncx, seg = it / pw.ncx;
         int64_t c = seg * P * pw.cols + col;
         if (c >= pw.nch) continue;
-        sym_chunk<NS, false, UNIT>(sn, dv, n, x, c, cy, epi);
+        step(c, std::false_type{});
         for (int t = 1; t < P; ++t) {
             c += pw.cols;
             if (c >= pw.nch) break;
-            sym_chunk<NS, true, UNIT>(sn, dv, n, x, c, cy, epi);
+            step(c, std::true_type{});
         }
     }
+}
+
+template <int NS, bool UNIT, typename VT, class Epi>
+__device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
+                                             const double *__restrict__ x, Epi &&epi) {
+    static_assert(NS == 5 || NS == 7 || NS == 9, "half form for 5, 7 or 9 diagonals");
+    if (sym_pairable<NS>(sn, n, x))
+        sym_walk<NS, UNIT, true>(sn, dv, n, x, epi);
+    else
+        sym_walk<NS, UNIT, false>(sn, dv, n, x, epi);
 }
 
 }  // namespace hsla
