@@ -193,6 +193,22 @@ __device__ __forceinline__ bool stopped(const SysState &st) { return st.done != 
         }             \
     }
 
+// The same over pairs of elements (2 i_, 2 i_ + 1), for vectors that are all
+// 16-byte aligned: each access is one 16-byte load or store for two
+// elements, two pairs per thread per step.
+#define PAIR_LOOP_BEGIN(np)                                                          \
+    {                                                                                \
+        const int64_t n_ = (np);                                                     \
+        const int64_t S_ = (int64_t)gridDim.x * kBlock;                              \
+        int64_t i_ = (int64_t)blockIdx.x * kBlock + threadIdx.x;                     \
+        for (; i_ + S_ < n_; i_ += 2 * S_) {
+#define PAIR_LOOP_TAIL GRID_LOOP_TAIL
+#define PAIR_LOOP_END GRID_LOOP_END
+
+__device__ __forceinline__ bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+__device__ __forceinline__ dpair ldp(const double *p) { return *(const dpair *)p; }
+__device__ __forceinline__ void stp(double *p, dpair v) { *(dpair *)p = v; }
+
 // ---------------------------------------------------------------------------
 // State reset
 // ---------------------------------------------------------------------------
@@ -352,38 +368,63 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Pat A, Sys S) {
     const double *__restrict__ q = S.q + vo;
     const double *__restrict__ dinv = S.dinv + vo;
     double acc[2] = {0.0, 0.0};  // r.r, r.z
-    GRID_LOOP_BEGIN(A.n)
-            double rv[4], qv[4], dv[4];
+    auto elem = [&](double rv, double qv, double dv) {
+        const double ri = rv - alpha * qv;
+        if (PRE == PRE_JACOBI) {
+            const double u = ri / dv;
+            acc[0] += u * u;
+            acc[1] += ri * ri;
+        } else {
+            acc[0] += ri * ri;
+        }
+        return ri;
+    };
+    if (al16(r) && al16(q) && (PRE != PRE_JACOBI || al16(dinv))) {
+        const dpair one = {1.0, 1.0};
+        PAIR_LOOP_BEGIN(A.n / 2)
+                dpair rv[2], qv[2], dv[2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t e = i_ + j * S_;
-                rv[j] = r[e]; qv[j] = q[e];
-                dv[j] = PRE == PRE_JACOBI ? dinv[e] : 1.0;
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t e = i_ + j * S_;
-                const double ri = rv[j] - alpha * qv[j];
-                r[e] = ri;
-                if (PRE == PRE_JACOBI) {
-                    const double u = ri / dv[j];
-                    acc[0] += u * u;
-                    acc[1] += ri * ri;
-                } else {
-                    acc[0] += ri * ri;
+                for (int j = 0; j < 2; ++j) {
+                    const int64_t e = 2 * (i_ + j * S_);
+                    rv[j] = ldp(r + e);
+                    qv[j] = ldp(q + e);
+                    dv[j] = PRE == PRE_JACOBI ? ldp(dinv + e) : one;
                 }
-            }
-    GRID_LOOP_TAIL
-            const double ri = r[i_] - alpha * q[i_];
-            r[i_] = ri;
-            if (PRE == PRE_JACOBI) {
-                const double u = ri / dinv[i_];
-                acc[0] += u * u;
-                acc[1] += ri * ri;
-            } else {
-                acc[0] += ri * ri;
-            }
-    GRID_LOOP_END
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    dpair o;
+                    o.x = elem(rv[j].x, qv[j].x, dv[j].x);
+                    o.y = elem(rv[j].y, qv[j].y, dv[j].y);
+                    stp(r + 2 * (i_ + j * S_), o);
+                }
+        PAIR_LOOP_TAIL
+                const int64_t e = 2 * i_;
+                const dpair rv = ldp(r + e), qv = ldp(q + e), dv = PRE == PRE_JACOBI ? ldp(dinv + e) : one;
+                dpair o;
+                o.x = elem(rv.x, qv.x, dv.x);
+                o.y = elem(rv.y, qv.y, dv.y);
+                stp(r + e, o);
+        PAIR_LOOP_END
+        if ((A.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+            const int64_t e = A.n - 1;
+            r[e] = elem(r[e], q[e], PRE == PRE_JACOBI ? dinv[e] : 1.0);
+        }
+    } else {
+        GRID_LOOP_BEGIN(A.n)
+                double rv[4], qv[4], dv[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t e = i_ + j * S_;
+                    rv[j] = r[e];
+                    qv[j] = q[e];
+                    dv[j] = PRE == PRE_JACOBI ? dinv[e] : 1.0;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) r[i_ + j * S_] = elem(rv[j], qv[j], dv[j]);
+        GRID_LOOP_TAIL
+                r[i_] = elem(r[i_], q[i_], PRE == PRE_JACOBI ? dinv[i_] : 1.0);
+        GRID_LOOP_END
+    }
     if (PRE == PRE_NONE) acc[1] = acc[0];
     block_partial<2>(acc, part);
 }
@@ -419,6 +460,37 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
     double *__restrict__ p = S.p + vo;
     const double *__restrict__ r = S.r + vo;
     const double *__restrict__ z = S.z + vo;
+    const double *__restrict__ zz = PRE == PRE_FSAI ? z : r;
+    if (al16(x) && al16(p) && al16(zz)) {
+        PAIR_LOOP_BEGIN(A.n / 2)
+                dpair zv[2], pv[2], xv[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int64_t e = 2 * (i_ + j * S_);
+                    pv[j] = ldp(p + e);
+                    if (XUP) xv[j] = ldp(x + e);
+                    if (!xonly) zv[j] = ldp(zz + e);
+                }
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int64_t e = 2 * (i_ + j * S_);
+                    if (XUP) stp(x + e, xv[j] + alpha * pv[j]);
+                    if (!xonly) stp(p + e, zv[j] + beta * pv[j]);
+                }
+        PAIR_LOOP_TAIL
+                const int64_t e = 2 * i_;
+                const dpair pv = ldp(p + e);
+                if (XUP) stp(x + e, ldp(x + e) + alpha * pv);
+                if (!xonly) stp(p + e, ldp(zz + e) + beta * pv);
+        PAIR_LOOP_END
+        if ((A.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+            const int64_t e = A.n - 1;
+            const double pi = p[e];
+            if (XUP) x[e] = x[e] + alpha * pi;
+            if (!xonly) p[e] = zz[e] + beta * pi;
+        }
+        return;
+    }
     if (xonly) {
         GRID_LOOP_BEGIN(A.n)
                 double xv[4], pv[4];
@@ -440,7 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t e = i_ + j * S_;
-                zv[j] = PRE == PRE_FSAI ? z[e] : r[e];
+                zv[j] = zz[e];
                 pv[j] = p[e];
                 if (XUP) xv[j] = x[e];
             }
@@ -451,10 +523,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
                 p[e] = zv[j] + beta * pv[j];
             }
     GRID_LOOP_TAIL
-            const double zi = PRE == PRE_FSAI ? z[i_] : r[i_];
             const double pi = p[i_];
             if (XUP) x[i_] = x[i_] + alpha * pi;
-            p[i_] = zi + beta * pi;
+            p[i_] = zz[i_] + beta * pi;
     GRID_LOOP_END
 }
 
