@@ -736,6 +736,81 @@ __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict
         spmv_dia_full<NS, false>(sn, dv, n, x, epi);
 }
 
+typedef double dpair __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int64_t clamp_row(int64_t r, int64_t n) { return r < 0 ? 0 : r < n ? r : n - 1; }
+
+// Whether the paired row layout applies to a stencil of NS diagonals (see
+// sym_pair): the main diagonal in the middle with -1 and +1 beside it, every
+// other offset even, n even and x 16-byte aligned.
+template <int NS>
+__device__ __forceinline__ bool pairable(const Stencil &sn, int64_t n, const double *x) {
+    constexpr int DS = NS / 2;
+    if ((n & 1) != 0 || ((uintptr_t)x & 15u) != 0 || sn.diag_slot != DS) return false;
+    if (sn.ofs[DS - 1] != -1 || sn.ofs[DS + 1] != 1) return false;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+        if (s != DS - 1 && s != DS + 1 && (sn.ofs[s] & 1) != 0) return false;
+    return true;
+}
+
+// One chunk of the full copy in the paired layout: rows r0 = 2t and r1 =
+// 2t + 1 of the chunk, one 16-byte load per stored diagonal and per x gather
+// at an even offset for both rows, the pair's own x as each other's -1 and
+// +1 neighbour.  Same products in the same order as spmv_dia_full.
+template <int NS, bool UF, class Epi>
+__device__ __forceinline__ void full_pair(const Stencil &sn, const double *__restrict__ dv, int64_t n,
+                                          const double *__restrict__ x, int64_t c, Epi &&epi) {
+#pragma clang fp contract(off)
+    constexpr int DS = NS / 2, NST = UF ? NS - 1 : NS;
+    const int64_t r0 = c * kDiaChunk + 2 * (int64_t)threadIdx.x;
+    const bool one = r0 < n;  // n is even: r0 and r0 + 1 exist together
+    const uint32_t w = one ? *(const uint32_t *)(sn.mask + r0) : 0u;
+    const uint32_t m0 = w & 0xffffu, m1 = w >> 16;
+    const double *__restrict__ base = dv + c * NST * kDiaChunk + 2 * (int64_t)threadIdx.x;
+    double v0[NS], v1[NS], x0[NS], x1[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (UF && s == DS) {
+            v0[s] = 1.0;
+            v1[s] = 1.0;
+        } else {
+            const dpair t = *(const dpair *)(base + (UF && s > DS ? s - 1 : s) * kDiaChunk);
+            v0[s] = t.x;
+            v1[s] = t.y;
+        }
+        if (s == DS - 1) {
+            x0[s] = x[clamp_row(r0 - 1, n)];
+        } else if (s == DS + 1) {
+            x1[s] = x[clamp_row(r0 + 2, n)];
+        } else {
+            const int64_t a = r0 + sn.ofs[s], pa = a < 0 ? 0 : a > n - 2 ? n - 2 : a;
+            const dpair t = *(const dpair *)(x + pa);
+            x0[s] = t.x;
+            x1[s] = t.y;
+        }
+    }
+    x1[DS - 1] = x0[DS];
+    x0[DS + 1] = x1[DS];
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const double p0 = v0[s] * x0[s];
+        const double p1 = v1[s] * x1[s];
+        if ((m0 >> s) & 1u) a0 = a0 + p0;
+        if ((m1 >> s) & 1u) a1 = a1 + p1;
+    }
+    if (one) {
+        if constexpr (std::is_invocable_v<Epi, int64_t, double, double>) {
+            epi(r0, a0, x0[DS]);
+            epi(r0 + 1, a1, x1[DS]);
+        } else {
+            epi(r0, a0);
+            epi(r0 + 1, a1);
+        }
+    }
+}
+
 // The full copy; UF: the main diagonal is 1 and not stored (slots past it
 // move down by one).
 template <int NS, bool UF, typename VT, class Epi>
@@ -746,6 +821,12 @@ __device__ __forceinline__ void spmv_dia_full(const Stencil &sn, const VT *__res
     static_assert(!UF || kExact, "the unit-diagonal copy has 5, 7 or 9 diagonals");
     constexpr int kGroup = kExact ? NS : 4;
     const ChunkWalk cw(dia_chunks(n));
+    if constexpr (kExact && std::is_same_v<VT, double>) {
+        if (pairable<NS>(sn, n, x)) {
+            for (int64_t c = cw.first; c < cw.hi; c += cw.stride) full_pair<NS, UF>(sn, dv, n, x, c, epi);
+            return;
+        }
+    }
     const uint16_t *__restrict__ mask = sn.mask;
     const int nofs = kExact ? NS : sn.nofs;
     const int nst = UF ? nofs - 1 : nofs;  // stored diagonals
@@ -832,8 +913,6 @@ struct SymCarry {
     double xlo0 = 0.0, xlo1 = 0.0, xown0 = 0.0, xown1 = 0.0;
 };
 
-__device__ __forceinline__ int64_t clamp_row(int64_t r, int64_t n) { return r < 0 ? 0 : r < n ? r : n - 1; }
-
 template <int NS, bool CONT, bool UNIT, typename VT, class Epi>
 __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                           const double *__restrict__ x, int64_t c, SymCarry<VT> &cy, Epi &&epi) {
@@ -901,8 +980,6 @@ __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restric
         if (two) epi(i2, a2);
     }
 }
-
-typedef double dpair __attribute__((ext_vector_type(2)));
 
 template <int NS, bool CONT, bool UNIT, typename VT, class Epi>
 __device__ __forceinline__ void sym_pair(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
@@ -985,18 +1062,6 @@ __device__ __forceinline__ void sym_pair(const Stencil &sn, const VT *__restrict
     }
 }
 
-// Whether the paired layout applies (see sym_pair).
-template <int NS>
-__device__ __forceinline__ bool sym_pairable(const Stencil &sn, int64_t n, const double *x) {
-    constexpr int DS = NS / 2;
-    if ((n & 1) != 0 || ((uintptr_t)x & 15u) != 0) return false;
-    if (sn.ofs[DS - 1] != -1 || sn.ofs[DS + 1] != 1) return false;
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-        if (s != DS - 1 && s != DS + 1 && (sn.ofs[s] & 1) != 0) return false;
-    return true;
-}
-
 template <int NS, bool UNIT, bool PAIR, typename VT, class Epi>
 __device__ __forceinline__ void sym_walk(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                          const double *__restrict__ x, Epi &&epi) {
@@ -1032,7 +1097,7 @@ template <int NS, bool UNIT, typename VT, class Epi>
 __device__ __forceinline__ void spmv_dia_sym(const Stencil &sn, const VT *__restrict__ dv, int64_t n,
                                              const double *__restrict__ x, Epi &&epi) {
     static_assert(NS == 5 || NS == 7 || NS == 9, "half form for 5, 7 or 9 diagonals");
-    if (sym_pairable<NS>(sn, n, x))
+    if (pairable<NS>(sn, n, x))
         sym_walk<NS, UNIT, true>(sn, dv, n, x, epi);
     else
         sym_walk<NS, UNIT, false>(sn, dv, n, x, epi);

@@ -1806,9 +1806,9 @@ hsla_status autotune(hsla_handle *h, hsla_pattern *p, int B, int effort, hsla_tu
     };
     std::vector<Cand> cands;
     if (half_ok)
-        for (int cu : {2, 4, 8, 16}) cands.push_back({F_HALF, cu, 0.0});
+        for (int cu : {1, 2, 3, 4, 8, 16}) cands.push_back({F_HALF, cu, 0.0});
     if (dia_ok)
-        for (int cu : {2, 4, 8, 16}) cands.push_back({F_DIA, cu, 0.0});
+        for (int cu : {1, 2, 4, 8, 16}) cands.push_back({F_DIA, cu, 0.0});
     for (int cu : {4, 8, 16, 32}) cands.push_back({F_TILES, cu, 0.0});
     hipError_t err = hipSuccess;
     for (Cand &c : cands)
