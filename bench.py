@@ -66,10 +66,13 @@ def matrix_bytes(n: int, nnz: int, form: str, nofs: int = 0) -> int:
     (8 nofs n, zeros where a row has no entry, + masks); its symmetric half
     form (main and upper diagonals only: 8 (nofs/2 + 1) n + masks), and
     that of Jacobi CG's scaled operator S A S, whose unit diagonal is not
-    stored (8 (nofs/2) n + masks)."""
-    return {"csr": 12 * nnz + 4 * (n + 1), "mask-tiles": 8 * nnz + 2 * n, "diagonal": 8 * nofs * n + 2 * n,
-            "diagonal-half": 8 * (nofs // 2 + 1) * n + 2 * n,
-            "diagonal-half-unit": 8 * (nofs // 2) * n + 2 * n, "diagonal-unit": 8 * (nofs - 1) * n + 2 * n}[form]
+    stored (8 (nofs/2) n + masks).  A "-paired" form (two adjacent rows per
+    thread) reads no row masks."""
+    base = form.removesuffix("-paired")
+    b = {"csr": 12 * nnz + 4 * (n + 1), "mask-tiles": 8 * nnz + 2 * n, "diagonal": 8 * nofs * n + 2 * n,
+         "diagonal-half": 8 * (nofs // 2 + 1) * n + 2 * n,
+         "diagonal-half-unit": 8 * (nofs // 2) * n + 2 * n, "diagonal-unit": 8 * (nofs - 1) * n + 2 * n}[base]
+    return b - 2 * n if form.endswith("-paired") else b
 
 
 def spmv_bytes(n: int, nnz: int, form: str, nofs: int = 0) -> int:
@@ -79,10 +82,11 @@ def spmv_bytes(n: int, nnz: int, form: str, nofs: int = 0) -> int:
 
 
 def form_of(info: dict, pat) -> str:
-    """The SpMV form a solve reports (hsla_info.spmv_form) as a byte-model key."""
+    """The SpMV form a solve reports (hsla_info.spmv_form, spmv_paired) as a
+    byte-model key."""
     f = info["spmv_form"]
     if f in ("diagonal", "diagonal-half", "diagonal-half-unit", "diagonal-unit"):
-        return f
+        return f + "-paired" if info.get("spmv_paired") else f
     return "mask-tiles" if f == "tiles" and pat.stencil[0] else "csr"
 
 
@@ -92,6 +96,12 @@ FORM_TEXT = {"diagonal": "diagonal-major values + row masks, {} diagonals",
                                    "row masks, {} diagonals",
              "diagonal-unit": "diagonal-major values of A D^-1 without its unit diagonal + row masks, {} diagonals",
              "mask-tiles": "row tiles with row masks, {} diagonals", "csr": "csr row tiles"}
+
+
+def form_text(form: str, nofs: int) -> str:
+    base = form.removesuffix("-paired")
+    t = FORM_TEXT[base].format(nofs)
+    return t.replace(" + row masks", "") + ", two adjacent rows per thread" if form.endswith("-paired") else t
 
 
 def pcg_iteration_bytes(n: int, nnz: int, nofs: int) -> int:
@@ -294,7 +304,7 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "algorithmic_bytes_per_launch": bytes_launch,
             "mean_launch_ms": avg_ms,
             "launches_timed": launches,
-            "format": FORM_TEXT[form].format(nofs),
+            "format": form_text(form, nofs),
             "full_copy_equivalent_GBps": (spmv_bytes(n, nnz, "diagonal", nofs) / (avg_ms * 1e-3) / 1e9
                                           if stencil else None),
         },
@@ -532,10 +542,12 @@ def run_adjoint(ctx, args, dev):
     # (p gathered, q written: 16n; update and direction: 72n)
     form = form_of(fi[0], pat)
     nofs = pat.stencil[1]
+    base = form.removesuffix("-paired")
     per_it = {"diagonal-half-unit": 8 * (nofs // 2) * n, "diagonal-half": 8 * (nofs // 2 + 1) * n,
               "diagonal": 8 * nofs * n,
-              "mask-tiles": 8 * nnz, "csr": 8 * nnz}[form] + 88 * n
-    per_it += (2 * n if form != "csr" else 4 * nnz + 4 * (n + 1)) / B
+              "mask-tiles": 8 * nnz, "csr": 8 * nnz}[base] + 88 * n
+    if not form.endswith("-paired"):
+        per_it += (2 * n if form != "csr" else 4 * nnz + 4 * (n + 1)) / B
     work = float(per_it * (itf.sum() + itb.sum()) + B * (12 * nnz + 28 * n))
     return {
         "workload": (f"{B} systems on one 3D 7-point pattern, {args.adj_m}^3 (n={n}, nnz={nnz}), log-normal kappa "

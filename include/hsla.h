@@ -100,7 +100,10 @@ typedef struct hsla_info {
                              4 the half form of Jacobi CG's scaled operator (upper
                              diagonals only; its diagonal is 1), 5 the full copy of
                              right-Jacobi BiCGStab's A D^{-1} without its unit diagonal    */
-    int32_t reserved;     /* 0                                                             */
+    int32_t spmv_paired;  /* 1 if the diagonal forms ran two adjacent rows per thread: 5, 7
+                             or 9 diagonals with offsets -1, 0, +1 in the middle, every
+                             other offset even and n even; that layout reads no row masks
+                             (absent entries are stored as 0).  0 otherwise              */
 } hsla_info;
 
 void hsla_opts_default(hsla_opts *opts);

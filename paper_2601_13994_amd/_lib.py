@@ -63,14 +63,14 @@ class Info(ctypes.Structure):
         ("iters", ctypes.c_int64), ("status", ctypes.c_int32), ("method", ctypes.c_int32),
         ("rel_residual", ctypes.c_double), ("true_residual", ctypes.c_double),
         ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int64),
-        ("spmv_form", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("spmv_form", ctypes.c_int32), ("spmv_paired", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {"iters": self.iters, "status": self.status, "method": METHOD_NAMES.get(self.method, "?"),
                 "rel_residual": self.rel_residual, "true_residual": self.true_residual,
                 "spmv_ms": self.spmv_ms, "spmv_launches": self.spmv_launches,
-                "spmv_form": SPMV_FORMS.get(self.spmv_form, "?")}
+                "spmv_form": SPMV_FORMS.get(self.spmv_form, "?"), "spmv_paired": bool(self.spmv_paired)}
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

@@ -740,24 +740,31 @@ typedef double dpair __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int64_t clamp_row(int64_t r, int64_t n) { return r < 0 ? 0 : r < n ? r : n - 1; }
 
-// Whether the paired row layout applies to a stencil of NS diagonals (see
-// sym_pair): the main diagonal in the middle with -1 and +1 beside it, every
-// other offset even, n even and x 16-byte aligned.
+// Whether the paired row layout applies (see full_pair and sym_pair): 5, 7
+// or 9 diagonals with the main one in the middle and -1 and +1 beside it,
+// every other offset even, n even and x 16-byte aligned.  The host makes the
+// same test to report the layout a solve ran.
+__host__ __device__ inline bool pairable_stencil(const Stencil &sn, int64_t n) {
+    const int ns = sn.nofs, ds = ns / 2;
+    if ((ns != 5 && ns != 7 && ns != 9) || (n & 1) != 0 || sn.diag_slot != ds) return false;
+    if (sn.ofs[ds - 1] != -1 || sn.ofs[ds + 1] != 1) return false;
+    for (int s = 0; s < ns; ++s)
+        if (s != ds - 1 && s != ds + 1 && (sn.ofs[s] & 1) != 0) return false;
+    return true;
+}
+
 template <int NS>
 __device__ __forceinline__ bool pairable(const Stencil &sn, int64_t n, const double *x) {
-    constexpr int DS = NS / 2;
-    if ((n & 1) != 0 || ((uintptr_t)x & 15u) != 0 || sn.diag_slot != DS) return false;
-    if (sn.ofs[DS - 1] != -1 || sn.ofs[DS + 1] != 1) return false;
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-        if (s != DS - 1 && s != DS + 1 && (sn.ofs[s] & 1) != 0) return false;
-    return true;
+    return sn.nofs == NS && ((uintptr_t)x & 15u) == 0 && pairable_stencil(sn, n);
 }
 
 // One chunk of the full copy in the paired layout: rows r0 = 2t and r1 =
 // 2t + 1 of the chunk, one 16-byte load per stored diagonal and per x gather
 // at an even offset for both rows, the pair's own x as each other's -1 and
-// +1 neighbour.  Same products in the same order as spmv_dia_full.
+// +1 neighbour.  Same products in the same order as spmv_dia_full, without
+// the row masks: an absent entry is stored as 0 and every gather row is
+// clamped into [0, n), so its product is 0 * (a finite x) and the add leaves
+// the sum as it was (up to the sign of a zero sum).
 template <int NS, bool UF, class Epi>
 __device__ __forceinline__ void full_pair(const Stencil &sn, const double *__restrict__ dv, int64_t n,
                                           const double *__restrict__ x, int64_t c, Epi &&epi) {
@@ -765,8 +772,6 @@ __device__ __forceinline__ void full_pair(const Stencil &sn, const double *__res
     constexpr int DS = NS / 2, NST = UF ? NS - 1 : NS;
     const int64_t r0 = c * kDiaChunk + 2 * (int64_t)threadIdx.x;
     const bool one = r0 < n;  // n is even: r0 and r0 + 1 exist together
-    const uint32_t w = one ? *(const uint32_t *)(sn.mask + r0) : 0u;
-    const uint32_t m0 = w & 0xffffu, m1 = w >> 16;
     const double *__restrict__ base = dv + c * NST * kDiaChunk + 2 * (int64_t)threadIdx.x;
     double v0[NS], v1[NS], x0[NS], x1[NS];
 #pragma unroll
@@ -797,8 +802,8 @@ __device__ __forceinline__ void full_pair(const Stencil &sn, const double *__res
     for (int s = 0; s < NS; ++s) {
         const double p0 = v0[s] * x0[s];
         const double p1 = v1[s] * x1[s];
-        if ((m0 >> s) & 1u) a0 = a0 + p0;
-        if ((m1 >> s) & 1u) a1 = a1 + p1;
+        a0 = a0 + p0;
+        a1 = a1 + p1;
     }
     if (one) {
         if constexpr (std::is_invocable_v<Epi, int64_t, double, double>) {
@@ -905,8 +910,10 @@ __device__ __forceinline__ void spmv_dia_full(const Stencil &sn, const VT *__res
 // entries and x are each other's -1 and +1 neighbours.  It needs the offsets
 // -1 and +1 beside the main diagonal, every other offset even, n even and x
 // 16-byte aligned: then a pair start clamped into [0, n - 2] reads exactly
-// the x of every row whose mask keeps the product.  Otherwise (sym_chunk)
-// each thread takes rows t and t + 256, one 8-byte load per row.
+// the x of every row that has the entry.  It reads no row masks: an absent
+// entry is stored as 0 (a mirror row above the first row is taken as 0), so
+// its product adds 0 to the sum.  Otherwise (sym_chunk) each thread takes
+// rows t and t + 256, one 8-byte load per row, and the masks gate the adds.
 template <typename VT>
 struct SymCarry {
     VT v0 = VT(0), v1 = VT(0);
@@ -990,8 +997,6 @@ __device__ __forceinline__ void sym_pair(const Stencil &sn, const VT *__restrict
     const int64_t r0 = c * kDiaChunk + 2 * (int64_t)threadIdx.x;
     const int64_t npad = dia_chunks(n) * kDiaChunk;  // rows of the padded diagonal-major copy
     const bool one = r0 < n;                         // n is even: r0 and r0 + 1 exist together
-    const uint32_t w = one ? *(const uint32_t *)(sn.mask + r0) : 0u;
-    const uint32_t m0 = w & 0xffffu, m1 = w >> 16;
     const VT *__restrict__ base = dv + c * NH * kDiaChunk + 2 * (int64_t)threadIdx.x;
     VT v0[NS], v1[NS];
     double x0[NS], x1[NS];
@@ -1010,12 +1015,12 @@ __device__ __forceinline__ void sym_pair(const Stencil &sn, const VT *__restrict
             v0[s] = cy.v0;
             v1[s] = cy.v1;
         } else if (s == DS - 1) {  // d = -1: row r1's entry mirrors row r0's +1 entry
-            v0[s] = dv[dia_index(clamp_row(r0 - 1, n), ms, NH)];
-        } else {
+            v0[s] = r0 >= 1 ? dv[dia_index(r0 - 1, ms, NH)] : VT(0);
+        } else {  // a mirror row above the first row holds no entry: 0
             const int64_t a = r0 + d, pa = a < 0 ? 0 : a > npad - 2 ? npad - 2 : a;
             const dpair t = *(const dpair *)(dv + dia_index(pa, ms, NH));
-            v0[s] = t.x;
-            v1[s] = t.y;
+            v0[s] = a >= 0 ? t.x : VT(0);
+            v1[s] = a >= 0 ? t.y : VT(0);
         }
         if (CONT && s == 0) {
             x0[s] = cy.xlo0;
@@ -1042,8 +1047,8 @@ __device__ __forceinline__ void sym_pair(const Stencil &sn, const VT *__restrict
     for (int s = 0; s < NS; ++s) {
         const double p0 = (double)v0[s] * x0[s];
         const double p1 = (double)v1[s] * x1[s];
-        if ((m0 >> s) & 1u) a0 = a0 + p0;
-        if ((m1 >> s) & 1u) a1 = a1 + p1;
+        a0 = a0 + p0;
+        a1 = a1 + p1;
     }
     cy.v0 = v0[NS - 1];
     cy.v1 = v1[NS - 1];

@@ -1550,7 +1550,9 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             f.spmv_ms = prof_ms;
             f.spmv_launches = prof_n;
             f.spmv_form = nsA > kUnitFullNS ? 5 : nsA > kUnitNS ? 4 : nsA > kSymNS ? 2 : nsA > 0 ? 1 : 0;
-            f.reserved = 0;
+            // the diagonal forms' SpMV operands (p, and BiCGStab's s) share
+            // p's alignment: every work vector is B n doubles past the last
+            f.spmv_paired = nsA > 0 && pairable_stencil(A.sn, n) && ((uintptr_t)S.p & 15u) == 0 ? 1 : 0;
         }
     }
     return (hsla_status)worst;

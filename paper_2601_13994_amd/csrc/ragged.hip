@@ -655,7 +655,7 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
             infos[i].spmv_ms = 0.0;
             infos[i].spmv_launches = 0;
             infos[i].spmv_form = 3;
-            infos[i].reserved = 0;
+            infos[i].spmv_paired = 0;
         }
     }
     return (hsla_status)worst;
@@ -1038,7 +1038,7 @@ static hsla_status run_segmented(hsla_handle *h, Args a, const hsla_opts &o, con
             infos[i].spmv_ms = 0.0;
             infos[i].spmv_launches = 0;
             infos[i].spmv_form = 0;
-            infos[i].reserved = 0;
+            infos[i].spmv_paired = 0;
         }
     }
     return (hsla_status)worst;
