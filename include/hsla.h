@@ -185,9 +185,10 @@ typedef struct hsla_tuning {
     double default_us;     /* mean SpMV time of the untuned default configuration             */
 } hsla_tuning;
 /* Times the solvers' SpMV on this pattern for a batch of B systems, on the
- * device and with synthetic values: the diagonal-major form (offset-mask
- * patterns, unless the CSR format was selected) at 2, 4, 8, 16 blocks per CU
- * and the row-tile form at 4, 8, 16, 32 blocks per CU, `effort` launches each
+ * device and with synthetic values: the diagonal-major forms (offset-mask
+ * patterns, unless the CSR format was selected) at 1, 2, 4, 8, 16 blocks per
+ * CU (the symmetric half form also at 3) and the row-tile form at 4, 8, 16,
+ * 32 blocks per CU, `effort` launches each
  * (1..100).  Stores the fastest in the pattern (later solves on it use it;
  * results do not depend on the choice beyond rounding of dot products) and
  * reports it in `out` (host, may be NULL).  Uses the handle's workspace;

@@ -37,6 +37,10 @@ def _both(pat, fn):
     ("diffusion3d", lambda: W.diffusion3d(13, W.diffusion3d_kappa(13)), 7),
     ("aniso9", lambda: W.aniso2d(29, 30.0, 0.7), 9),
     ("upwind", lambda: W.diffusion3d(11, W.diffusion3d_kappa(11), velocity=10.0), 7),
+    # even n: the diagonal-major copy runs two adjacent rows per thread
+    ("poisson2d_even", lambda: W.poisson2d(38), 5),
+    ("diffusion3d_even", lambda: W.diffusion3d(14, W.diffusion3d_kappa(14)), 7),
+    ("upwind_even", lambda: W.diffusion3d(12, W.diffusion3d_kappa(12), velocity=10.0), 7),
 ])
 def test_stencil_spmv_bitwise(orc, name, make, nofs):
     a = make()
@@ -150,7 +154,7 @@ def test_autotune_choice_applies(orc):
     a = W.diffusion3d(m, W.diffusion3d_kappa(m))
     pat = pattern(a)
     t = pat.autotune(B=2, effort=3)
-    assert t["form"] in ("diagonal", "diagonal-half", "tiles") and t["blocks_per_cu"] in (2, 4, 8, 16, 32)
+    assert t["form"] in ("diagonal", "diagonal-half", "tiles") and t["blocks_per_cu"] in (1, 2, 3, 4, 8, 16, 32)
     assert 0 < t["best_us"] <= t["default_us"]
     b = np.random.default_rng(6).standard_normal(a.n)
     x, infos, st = _lib.solve(pat, t64(a.val), t64(b),
@@ -280,3 +284,29 @@ def test_truncated_iterates_match_oracle(orc, fmt, precond):
             assert rel(x.cpu().numpy(), ref.x) <= 1e-12, (k, rel(x.cpu().numpy(), ref.x))
     finally:
         pat.set_format("auto")
+
+
+@pytest.mark.parametrize("m,paired", [(14, True), (13, False)])
+@pytest.mark.parametrize("method", ["cg", "bicgstab"])
+def test_paired_layout(orc, m, paired, method):
+    """A 7-point grid with even n runs the diagonal forms two adjacent rows
+    per thread without row masks (hsla_info.spmv_paired), odd n two rows
+    256 apart with masks; both match the oracle, and CG's truncated iterate
+    too."""
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m), velocity=10.0 if method == "bicgstab" else 0.0)
+    b = np.random.default_rng(m).standard_normal(a.n)
+    pat = pattern(a)
+    opts = _lib.make_opts(method=method, precond="jacobi", rtol=1e-12, persistent=False)
+    x, infos, st = _lib.solve(pat, t64(a.val), t64(b), opts)
+    assert st == _lib.OK and infos[0]["spmv_paired"] is paired
+    assert infos[0]["spmv_form"] == ("diagonal-half-unit" if method == "cg" else "diagonal-unit")
+    ref = orc.solve(a, b, method=method, precond="jacobi", rtol=1e-12)
+    assert rel(x.cpu().numpy(), ref.x) <= 1e-8
+    if method == "cg":
+        assert iters_close(infos[0]["iters"], ref.iters)
+        k = 7
+        opts = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-14, max_iter=k, persistent=False)
+        xk, fk, st = _lib.solve(pat, t64(a.val), t64(b), opts)
+        refk = orc.cg(a, b, precond="jacobi", rtol=1e-14, max_iter=k)
+        assert st == _lib.NOT_CONVERGED and fk[0]["iters"] == k
+        assert rel(xk.cpu().numpy(), refk.x) <= 1e-12
