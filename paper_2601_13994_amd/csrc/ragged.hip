@@ -84,7 +84,8 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV], double *sh) {
 // the 64-row blocks w, w + NW, ...; a block's entries are loaded in
 // coalesced chunks of kChunk, their products staged in the wave's LDS slice,
 // and each lane adds the products of its row in ascending order.  The next
-// block's row pointers are loaded while the current block is processed.
+// block's row pointers, and the next chunk's values and column indices, are
+// loaded while the current block or chunk is processed.
 // epi(i, y_i) runs on the lane that owns row i.
 template <int NW, class Epi>
 __device__ __forceinline__ void wg_spmv(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
@@ -110,12 +111,36 @@ __device__ __forceinline__ void wg_spmv(int32_t n, const int32_t *__restrict__ r
         if (rn < n) fetch(rn, n0, n1, na, nb);
         const int32_t row = r0 + lane;
         double acc = 0.0;
+        constexpr int U = kChunk / kWave;
+        // entries of the first chunk; each step loads the next chunk's
+        // values and column indices before it gathers and stages this one
+        double vv[U];
+        int32_t cv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t e = e0 + u * kWave + lane;
+            vv[u] = e < e1 ? val[e] : 0.0;
+            cv[u] = e < e1 ? col[e] : 0;
+        }
         for (int32_t c0 = e0; c0 < e1; c0 += kChunk) {
             const int32_t cnt = e1 - c0 < kChunk ? e1 - c0 : kChunk;
+            double xv[U];
 #pragma unroll
-            for (int u = 0; u < kChunk / kWave; ++u) {
+            for (int u = 0; u < U; ++u) xv[u] = u * kWave + lane < cnt ? v[cv[u]] : 0.0;
+            double nv[U];
+            int32_t nc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = c0 + kChunk + u * kWave + lane;
+                nv[u] = e < e1 ? val[e] : 0.0;
+                nc[u] = e < e1 ? col[e] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
                 const int32_t e = u * kWave + lane;
-                if (e < cnt) L[e] = val[c0 + e] * v[col[c0 + e]];
+                if (e < cnt) L[e] = vv[u] * xv[u];
+                vv[u] = nv[u];
+                cv[u] = nc[u];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
