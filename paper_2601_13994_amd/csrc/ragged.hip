@@ -105,35 +105,43 @@ __device__ __forceinline__ void wg_spmv(int32_t n, const int32_t *__restrict__ r
         if (row >= n) fa = fb = f1;
     };
     if (r0 < n) fetch(r0, e0, e1, ka, kb);
+    constexpr int U = kChunk / kWave;
+    // entries of the chunk to process next; each step loads the following
+    // chunk's values and column indices (the next block's first chunk after
+    // a block's last) before it gathers and stages this one
+    double vv[U];
+    int32_t cv[U];
+    bool have = false;  // vv, cv hold the current block's first chunk
     for (; r0 < n; r0 += NW * kWave) {
         const int32_t rn = r0 + NW * kWave;
         int32_t n0 = 0, n1 = 0, na = 0, nb = 0;
         if (rn < n) fetch(rn, n0, n1, na, nb);
         const int32_t row = r0 + lane;
         double acc = 0.0;
-        constexpr int U = kChunk / kWave;
-        // entries of the first chunk; each step loads the next chunk's
-        // values and column indices before it gathers and stages this one
-        double vv[U];
-        int32_t cv[U];
+        if (!have) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t e = e0 + u * kWave + lane;
-            vv[u] = e < e1 ? val[e] : 0.0;
-            cv[u] = e < e1 ? col[e] : 0;
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = e0 + u * kWave + lane;
+                vv[u] = e < e1 ? val[e] : 0.0;
+                cv[u] = e < e1 ? col[e] : 0;
+            }
         }
+        have = false;
         for (int32_t c0 = e0; c0 < e1; c0 += kChunk) {
             const int32_t cnt = e1 - c0 < kChunk ? e1 - c0 : kChunk;
             double xv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) xv[u] = u * kWave + lane < cnt ? v[cv[u]] : 0.0;
+            const bool last = c0 + kChunk >= e1;
+            const int32_t ns = last ? n0 : c0 + kChunk, ne = last ? n1 : e1;
+            have = last;
             double nv[U];
             int32_t nc[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int32_t e = c0 + kChunk + u * kWave + lane;
-                nv[u] = e < e1 ? val[e] : 0.0;
-                nc[u] = e < e1 ? col[e] : 0;
+                const int32_t e = ns + u * kWave + lane;
+                nv[u] = e < ne ? val[e] : 0.0;
+                nc[u] = e < ne ? col[e] : 0;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
