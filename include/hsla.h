@@ -166,9 +166,12 @@ hsla_status hsla_pattern_info(const hsla_pattern *p, int32_t *n, int64_t *nnz, i
  *   DIAGONAL: as AUTO, and hsla_spmv also goes through the diagonal-major
  *     copy (one extra pass over the values per call).
  * Every form adds each row's products in ascending column order, so SpMV
- * results are bitwise identical in all of them; a solve's dot products are
- * reduced in an order that depends on the form's grid, so solves agree to
- * rounding. */
+ * results are bitwise identical in all of them (for finite x, up to the sign
+ * of a zero sum: the diagonal-major copy's paired layout, hsla_info.spmv_paired,
+ * reads no row masks and adds an absent entry's stored 0 times a finite x; a
+ * non-finite x there can also reach rows that have no entry at its column);
+ * a solve's dot products are reduced in an order that depends on the form's
+ * grid, so solves agree to rounding. */
 typedef enum hsla_format { HSLA_FORMAT_AUTO = 0, HSLA_FORMAT_CSR = 1, HSLA_FORMAT_DIAGONAL = 2 } hsla_format;
 /* Selects the form later calls on `p` use; must not run concurrently with
  * calls that use `p`.  HSLA_ERR_INVALID_ARG for an unknown format. */
