@@ -36,8 +36,15 @@ typedef enum hsla_status {
     HSLA_OK = 0,
     HSLA_NOT_CONVERGED = 1, /* max_iter reached; x holds the last iterate       */
     HSLA_BREAKDOWN = 2,     /* p^T A p <= 0 (CG) or a BiCGStab breakdown after
-                               its one restart; x holds the last iterate        */
+                               its one restart; x holds the last iterate.  Also
+                               before the first iteration (x = x0) when Jacobi
+                               meets a negative diagonal under CG, or an FSAI
+                               factor holds a non-finite value or a row whose
+                               last entry is not a positive diagonal          */
     HSLA_FELL_BACK = 3,     /* learned preconditioner rejected, Jacobi used     */
+    HSLA_STAGNATED = 4,     /* stall_window set and ||r_k|| fell less than 10x
+                               over the last stall_window iterations; x holds
+                               the last iterate                                */
     HSLA_ERR_INVALID_ARG = -1,
     HSLA_ERR_INVALID_CSR = -2, /* pattern not canonical CSR (see hsla_pattern_create) */
     HSLA_ERR_NONFINITE = -3,   /* NaN/Inf met in b, values or a recurrence      */
@@ -82,6 +89,11 @@ typedef struct hsla_opts {
                             least one system per compute unit with at most 131072 entries each,
                             runs as one persistent launch, one workgroup per system;
                             0: always per-iteration kernels (ragged batches: the segmented path) */
+    int32_t stall_window;/* > 0: a system whose recursive ||r_k|| has not fallen by 10x within
+                            stall_window iterations (counted from the start or from the last
+                            iteration where it had) stops with HSLA_STAGNATED, e.g. so that a
+                            poor learned preconditioner gives way to Jacobi early.  Runs on the
+                            per-iteration kernels (no persistent launch).  Default 0: off     */
 } hsla_opts;
 
 /* Per-system result information. */

@@ -16,7 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhsla.so")
 
-OK, NOT_CONVERGED, BREAKDOWN, FELL_BACK = 0, 1, 2, 3
+OK, NOT_CONVERGED, BREAKDOWN, FELL_BACK, STAGNATED = 0, 1, 2, 3, 4
 ERR_INVALID_ARG, ERR_INVALID_CSR, ERR_NONFINITE, ERR_HIP = -1, -2, -3, -4
 ERR_NO_MEMORY, ERR_ZERO_DIAGONAL, ERR_INTERNAL = -5, -6, -7
 
@@ -51,6 +51,7 @@ class Opts(ctypes.Structure):
         ("max_iter", ctypes.c_int64), ("check_every", ctypes.c_int32),
         ("use_x0", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32),
         ("d_G", ctypes.c_void_p), ("d_GT", ctypes.c_void_p), ("persistent", ctypes.c_int32),
+        ("stall_window", ctypes.c_int32),
     ]
 
 
@@ -232,7 +233,7 @@ def need(t: torch.Tensor, dtype: torch.dtype, name: str, device: torch.device) -
 
 
 def make_opts(method="auto", precond="jacobi", rtol=1e-8, atol=0.0, max_iter=0, check_every=0,
-              x0=False, graph=True, profile=False, G=None, GT=None, persistent=True) -> Opts:
+              x0=False, graph=True, profile=False, G=None, GT=None, persistent=True, stall_window=0) -> Opts:
     o = Opts()
     load().hsla_opts_default(ctypes.byref(o))
     o.method = METHODS[method]
@@ -247,6 +248,7 @@ def make_opts(method="auto", precond="jacobi", rtol=1e-8, atol=0.0, max_iter=0, 
     o.d_G = G.data_ptr() if G is not None else None
     o.d_GT = GT.data_ptr() if GT is not None else None
     o.persistent = int(bool(persistent))
+    o.stall_window = int(stall_window or 0)
     return o
 
 

@@ -51,8 +51,23 @@ struct alignas(128) SysState {
     int32_t restart_pending;
     int32_t bad_diag;  // set when Jacobi finds a missing or zero diagonal
     int32_t xpend;     // CG: the stopping iteration's x += alpha p is still to be applied
-    int32_t pad;
+    int32_t stall;     // stall window (iterations; 0 = off)
+    double win_rr;     // ||r||^2 at the start of the current stall window
+    int64_t win_it;    // iteration at the start of the current stall window
 };
+
+// Stall test after an iteration with ||r||^2 = rr: once st.stall iterations
+// have passed since the window began, the window either shows a 10x fall of
+// ||r|| (100x of rr) and a new window begins, or the system has stagnated.
+__device__ __forceinline__ bool stall_step(SysState &st, double rr) {
+    if (st.stall <= 0 || st.iters - st.win_it < st.stall) return false;
+    if (rr <= 0.01 * st.win_rr) {
+        st.win_rr = rr;
+        st.win_it = st.iters;
+        return false;
+    }
+    return true;
+}
 
 // Scalar steps of the CG recurrence (Alg. 1), run by thread 0 of a
 // finalize block once the system's sums are complete; shared by the batched
@@ -67,6 +82,8 @@ __device__ __forceinline__ void cg_step_init(SysState &st, double bb, double rr,
     st.tol = tol;
     st.rnorm2 = rr;
     st.iters = 0;
+    st.win_rr = rr;
+    st.win_it = 0;
     const double rn = sqrt(rr);
     if (st.bad_diag) {
         st.status = HSLA_ERR_ZERO_DIAGONAL;
@@ -116,6 +133,10 @@ __device__ __forceinline__ void cg_step_beta(SysState &st, double rr, double rz,
         st.xpend = 1;
     } else if (st.iters >= st.max_iter) {
         st.status = HSLA_NOT_CONVERGED;
+        st.done = 1;
+        st.xpend = 1;
+    } else if (stall_step(st, rr)) {
+        st.status = HSLA_STAGNATED;
         st.done = 1;
         st.xpend = 1;
     } else if (with_rho) {
@@ -366,7 +387,7 @@ struct TileWalk {
 //
 // A tile is a run of consecutive rows, at most kTileRows rows and kTileCap
 // stored entries (one lane per row); a row longer than kTileCap is a tile by
-// itself.  meta[t] = (first row, first entry) of tile t, meta[T] = (n, nnz).
+// itself and is summed in kTileCap-entry pieces, still in ascending k.  meta[t] = (first row, first entry) of tile t, meta[T] = (n, nnz).
 // Per tile, every lane loads kTileCap/64 values and column indices (clamped
 // inside the tile, nontemporal: the matrix stream is read once per sweep),
 // gathers x, and stages the products in LDS; each row then adds its own
@@ -415,13 +436,26 @@ __device__ __forceinline__ void spmv_tiles_csr(const int32_t *__restrict__ rp, c
         }
         const int32_t cnt = m1.y - m0.y;
         if (cnt > kTileCap) {
-            // one long row: lane-strided partial sums and a butterfly
+            // one long row, summed like every other row in ascending k: the
+            // wave stages kTileCap rounded products at a time in LDS and
+            // lane 0 adds them in order (the store rounds each product, so
+            // no product is fused into the running sum)
             double s = 0.0;
-            for (int32_t e = lane; e < cnt; e += kWave) {
-                const int32_t k = m0.y + e;
-                s += (double)val[k] * x[col[k]];
+            for (int32_t e0 = 0; e0 < cnt; e0 += kTileCap) {
+                const int32_t m = cnt - e0 < kTileCap ? cnt - e0 : kTileCap;
+                for (int32_t e = lane; e < m; e += kWave) {
+                    const int32_t k = m0.y + e0 + e;
+                    lds[e] = (double)val[k] * x[col[k]];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane == 0)
+                    for (int32_t e = 0; e < m; ++e) s += lds[e];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            s = wave_sum(s);
             if (lane == 0) epi(m0.x, s);
         } else {
             double xv[U];

@@ -212,11 +212,12 @@ __device__ __forceinline__ void stp(double *p, dpair v) { *(dpair *)p = v; }
 // ---------------------------------------------------------------------------
 // State reset
 // ---------------------------------------------------------------------------
-__global__ void k_reset(SysState *st, int B, int64_t max_iter) {
+__global__ void k_reset(SysState *st, int B, int64_t max_iter, int32_t stall) {
     for (int i = threadIdx.x; i < B; i += blockDim.x) {
         SysState z;
         memset(&z, 0, sizeof z);
         z.max_iter = max_iter;
+        z.stall = stall;
         z.rho = z.alpha = z.omega = 1.0;
         st[i] = z;
     }
@@ -309,7 +310,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_cg_init(Sys S, int G, double rto
     double tot[3];
     reduce_partials<3>(part, G, tot);
     if (threadIdx.x != 0) return;
-    const bool neg = st.bad_diag == 2;
+    // bit 0: missing or zero Jacobi diagonal, bit 1: negative one, bit 2:
+    // invalid FSAI factor
+    const bool neg = (st.bad_diag & 6) != 0;
     st.bad_diag &= 1;
     cg_step_init(st, tot[0], tot[1], PRE == PRE_FSAI ? 0.0 : tot[2], rtol, atol);
     if (neg && !st.done) {
@@ -569,6 +572,23 @@ __global__ __launch_bounds__(kBlock) void k_fsai_lower_dot(Pat A, FPat L, Sys S)
     block_partial<1>(acc, part);
 }
 
+// The FSAI factor of each system must have finite values and end every
+// row of its lower pattern with a positive diagonal entry (G nonsingular, so
+// M^{-1} = G^T G is SPD); a system whose factor fails is flagged (bit 2 of
+// bad_diag) and stops with BREAKDOWN before its first iteration.
+__global__ __launch_bounds__(kBlock) void k_fsai_check(FPat L, Sys S, int32_t n) {
+    const int sidx = blockIdx.y;
+    const float *__restrict__ g = L.val + (int64_t)sidx * L.nnz;
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const int32_t lo = L.rp[i], hi = L.rp[i + 1];
+        if (hi <= lo || L.col[hi - 1] != i || !(g[hi - 1] > 0.0f)) bad = true;
+        for (int32_t k = lo; k < hi; ++k)
+            if (!isfinite(g[k])) bad = true;
+    }
+    if (__syncthreads_or(bad ? 1 : 0) && threadIdx.x == 0) atomicOr(&S.st[sidx].bad_diag, 4);
+}
+
 // FSAI apply, second half: z = G^T w.
 template <int NS>
 __global__ __launch_bounds__(kBlock) void k_fsai_upper(Pat A, FPat U, Sys S) {
@@ -668,6 +688,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_bicg_init(Sys S, int G, double r
     st.bnorm = bn;
     st.tol = tol;
     st.rnorm2 = tot[1];
+    st.win_rr = tot[1];
+    st.win_it = 0;
     const double rn = sqrt(tot[1]);
     if (st.bad_diag) {
         st.status = HSLA_ERR_ZERO_DIAGONAL;
@@ -956,6 +978,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_bicg_update(Sys S, int G) {
         bicg_breakdown(st);
     } else if (st.iters >= st.max_iter) {
         st.status = HSLA_NOT_CONVERGED;
+        st.done = 1;
+    } else if (stall_step(st, tot[0])) {
+        st.status = HSLA_STAGNATED;
         st.done = 1;
     } else {
         st.rho = st.rho_new;
@@ -1426,7 +1451,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             c.U.dia = du;
         }
     }
-    k_reset<<<1, kBlock, 0, s>>>(S.st, B, max_iter);
+    k_reset<<<1, kBlock, 0, s>>>(S.st, B, max_iter, o.stall_window > 0 ? o.stall_window : 0);
     if (o.use_x0) k_spmv<<<gt, kBlock, 0, s>>>(A, values, x, S.q);
     if (method == HSLA_METHOD_CG) {
         switch (pre) {
@@ -1450,6 +1475,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
                 break;
             default:
                 k_cg_init<PRE_FSAI><<<gv, kBlock, 0, s>>>(A, S, o.use_x0);
+                k_fsai_check<<<gv, kBlock, 0, s>>>(c.L, S, (int32_t)n);
                 k_fin_cg_init<PRE_FSAI><<<gf, kBlock, 0, s>>>(S, Gv, o.rtol, o.atol);
                 NS_LAUNCH(k_fsai_lower_dot, nsF, gfs, A, c.L, S);
                 NS_LAUNCH(k_fsai_upper, nsF, gfs, A, c.U, S);
@@ -1945,7 +1971,7 @@ hsla_status hsla_residual_norms(hsla_handle *h, const hsla_pattern *p, int32_t B
     S.x = const_cast<double *>(d_x);
     S.st = (hsla::SysState *)(ws + lay.off_state);
     S.part = (double *)(ws + lay.off_part);
-    hsla::k_reset<<<1, hsla::kBlock, 0, s>>>(S.st, B, 1);
+    hsla::k_reset<<<1, hsla::kBlock, 0, s>>>(S.st, B, 1, 0);
     const hsla::Pat A = hsla::pat_of(p);
     double *res = (double *)(ws + lay.off_res);
     std::vector<double> hr(2 * (size_t)B, 0.0);

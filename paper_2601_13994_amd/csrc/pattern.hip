@@ -595,6 +595,7 @@ void hsla_opts_default(hsla_opts *o) {
     o->use_x0 = 0;
     o->use_graph = 1;
     o->persistent = 1;
+    o->stall_window = 0;
 }
 
 const char *hsla_status_string(int st) {
@@ -603,6 +604,7 @@ const char *hsla_status_string(int st) {
         case HSLA_NOT_CONVERGED: return "not converged";
         case HSLA_BREAKDOWN: return "breakdown";
         case HSLA_FELL_BACK: return "fell back to Jacobi";
+        case HSLA_STAGNATED: return "stagnated";
         case HSLA_ERR_INVALID_ARG: return "invalid argument";
         case HSLA_ERR_INVALID_CSR: return "invalid CSR pattern";
         case HSLA_ERR_NONFINITE: return "non-finite value";

@@ -229,12 +229,13 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
         double *__restrict__ dinv = a.dinv + r0;
         // set-up: x = 0, r = b, z = D^{-1} r, p = z
         double acc3[3] = {0.0, 0.0, 0.0};
-        int bad_diag = 0;
+        int bad_diag = 0, neg_diag = 0;
         for (int32_t i = threadIdx.x; i < n; i += kRB) {
             double d = 0.0;
             for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
                 if (col[k] == i) d = val[k];
             if (a.jacobi && d == 0.0) bad_diag = 1;
+            if (a.jacobi && d < 0.0) neg_diag = 1;
             const double di = a.jacobi ? 1.0 / d : 1.0;
             const double bi = b[i];
             dinv[i] = di;
@@ -245,8 +246,8 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
             acc3[1] += bi * bi;
             acc3[2] += bi * (di * bi);
         }
-        double bd[1] = {(double)bad_diag};
-        wg_sum<kRW, 1>(bd, sh);
+        double bd[2] = {(double)bad_diag, (double)neg_diag};
+        wg_sum<kRW, 2>(bd, sh);
         wg_sum<kRW, 3>(acc3, sh);
         const double bn = sqrt(acc3[0]);
         double tol = a.rtol * bn;
@@ -260,6 +261,8 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
             status = HSLA_ERR_NONFINITE;
         } else if (sqrt(rr) <= tol) {
             status = HSLA_OK;
+        } else if (bd[1] > 0.0) {
+            status = HSLA_BREAKDOWN;  // negative Jacobi diagonal: x stays 0
         } else {
             while (it < a.max_iter) {
                 // q = A p, sigma = p.q (each row summed in ascending order)
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(kSB) void k_small_pcg(Args a) {
         int32_t lo[R], len[R];
         double xr[R], rv[R], dv[R], pv[R], qv[R];
         double acc3[3] = {0.0, 0.0, 0.0};
-        int bad_diag = 0;
+        int bad_diag = 0, neg_diag = 0;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int32_t i = threadIdx.x + j * kSB;
@@ -426,6 +429,7 @@ __global__ __launch_bounds__(kSB) void k_small_pcg(Args a) {
                 for (int32_t k = 0; k < len[j]; ++k)
                     if (col[lo[j] + k] == i) d = val[lo[j] + k];
                 if (a.jacobi && d == 0.0) bad_diag = 1;
+                if (a.jacobi && d < 0.0) neg_diag = 1;
                 const double di = a.jacobi ? 1.0 / d : 1.0;
                 const double bi = b[i];
                 dv[j] = di;
@@ -437,8 +441,8 @@ __global__ __launch_bounds__(kSB) void k_small_pcg(Args a) {
                 acc3[2] += bi * (di * bi);
             }
         }
-        double bd[1] = {(double)bad_diag};
-        wg_sum<kSW, 1>(bd, sh);
+        double bd[2] = {(double)bad_diag, (double)neg_diag};
+        wg_sum<kSW, 2>(bd, sh);
         wg_sum<kSW, 3>(acc3, sh);
         const double bn = sqrt(acc3[0]);
         double tol = a.rtol * bn;
@@ -452,6 +456,8 @@ __global__ __launch_bounds__(kSB) void k_small_pcg(Args a) {
             status = HSLA_ERR_NONFINITE;
         } else if (sqrt(rr) <= tol) {
             status = HSLA_OK;
+        } else if (bd[1] > 0.0) {
+            status = HSLA_BREAKDOWN;  // negative Jacobi diagonal: x stays 0
         } else if (SR) {
             // u = D^{-1} r is p at the start (in LDS); w = A u, s = w
             double gamma = rho, alpha = 0.0;
@@ -706,6 +712,7 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
 // ---------------------------------------------------------------------------
 constexpr int kSegRows = 512;
 constexpr int kSegW = kBlock / kWave;
+constexpr int kSegSlots = 5;  // partials per chunk (the set-up kernel writes five)
 // Batches of at least kSegMinRows rows with a system above kSegMinN rows run
 // segmented (one workgroup streams a large system slower than the chip
 // streams it); smaller ones run persistent.
@@ -718,7 +725,7 @@ struct Seg {
     const int32_t *crow;    // chunk -> its first row, local to the system
     const int32_t *cfirst;  // system -> its first chunk ([B + 1])
     SysState *st;           // [B]
-    double *part;           // [chunks][4]
+    double *part;           // [chunks][kSegSlots]
 };
 
 struct SegChunk {
@@ -747,7 +754,7 @@ __device__ __forceinline__ void seg_reduce(const Seg &g, int32_t s, double (&tot
     for (int j = 0; j < NV; ++j) tot[j] = 0.0;
     for (int32_t c = g.cfirst[s] + threadIdx.x; c < g.cfirst[s + 1]; c += blockDim.x) {
 #pragma unroll
-        for (int j = 0; j < NV; ++j) tot[j] += g.part[(int64_t)c * 4 + j];
+        for (int j = 0; j < NV; ++j) tot[j] += g.part[(int64_t)c * kSegSlots + j];
     }
     block_sum<NV>(tot, sh);
 }
@@ -758,34 +765,37 @@ __device__ __forceinline__ void seg_partial(const Seg &g, int32_t c, double (&v)
     block_sum<NV>(v, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int j = 0; j < NV; ++j) g.part[(int64_t)c * 4 + j] = v[j];
+        for (int j = 0; j < NV; ++j) g.part[(int64_t)c * kSegSlots + j] = v[j];
     }
 }
 
-__global__ void k_seg_reset(SysState *st, int32_t B, int64_t max_iter) {
+__global__ void k_seg_reset(SysState *st, int32_t B, int64_t max_iter, int32_t stall) {
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x) {
         SysState z;
         memset(&z, 0, sizeof z);
         z.max_iter = max_iter;
+        z.stall = stall;
         z.rho = z.alpha = z.omega = 1.0;
         st[i] = z;
     }
 }
 
 // x = 0, r = b, D^{-1} (1 without Jacobi), p = D^{-1} r; partials of b.b,
-// r.r, r.D^{-1}r and a missing-diagonal flag.
+// r.r, r.D^{-1}r, a missing-or-zero-diagonal flag and a negative-diagonal
+// flag (Jacobi).
 __global__ __launch_bounds__(kBlock) void k_seg_init(Seg g) {
     const int32_t c = blockIdx.x;
     const SegChunk k = seg_chunk(g, c);
     const Args &a = g.a;
     const int32_t *col = a.col + k.k0;
     const double *val = a.val + k.k0;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int32_t i = k.lo + threadIdx.x; i < k.hi; i += kBlock) {
         double d = 0.0;
         for (int32_t e = k.rp[i]; e < k.rp[i + 1]; ++e)
             if (col[e] == i) d = val[e];
         if (a.jacobi && d == 0.0) acc[3] = 1.0;
+        if (a.jacobi && d < 0.0) acc[4] = 1.0;
         const double di = a.jacobi ? 1.0 / d : 1.0;
         const int64_t gi = k.r0 + i;
         const double bi = a.b[gi];
@@ -797,17 +807,24 @@ __global__ __launch_bounds__(kBlock) void k_seg_init(Seg g) {
         acc[1] += bi * bi;
         acc[2] += bi * (di * bi);
     }
-    seg_partial<4>(g, c, acc);
+    seg_partial<5>(g, c, acc);
 }
 
+// A negative Jacobi diagonal (D^{-1} is then no SPD preconditioner) ends the
+// solve with BREAKDOWN before the first iteration, x = 0, as on the batched
+// path; a zero or missing one is an error and takes precedence.
 __global__ __launch_bounds__(kBlock) void k_seg_fin_init(Seg g) {
     const int32_t s = blockIdx.x;
-    double tot[4];
-    seg_reduce<4>(g, s, tot);
+    double tot[5];
+    seg_reduce<5>(g, s, tot);
     if (threadIdx.x != 0) return;
     SysState &st = g.st[s];
     if (tot[3] > 0.0) st.bad_diag = 1;
     cg_step_init(st, tot[0], tot[1], tot[2], g.a.rtol, g.a.atol);
+    if (tot[4] > 0.0 && !st.done) {
+        st.status = HSLA_BREAKDOWN;
+        st.done = 1;
+    }
 }
 
 // q = A p for the chunk's rows (ascending per-row sums); partial of p.q.
@@ -975,7 +992,7 @@ static hsla_status run_segmented(hsla_handle *h, Args a, const hsla_opts &o, con
     add(sizeof(int32_t) * (size_t)(nch > 0 ? nch : 1) * 2);
     add(sizeof(int32_t) * (B + 1));
     add(sizeof(SysState) * B);
-    add(sizeof(double) * 4 * (size_t)(nch > 0 ? nch : 1));
+    add(sizeof(double) * kSegSlots * (size_t)(nch > 0 ? nch : 1));
     add(sizeof(RInfo) * B);
     add(256);
     hsla_status st = ensure_workspace(h, bytes);
@@ -998,7 +1015,7 @@ static hsla_status run_segmented(hsla_handle *h, Args a, const hsla_opts &o, con
     int32_t *dfirst = (int32_t *)take(sizeof(int32_t) * (B + 1));
     Seg g{};
     g.st = (SysState *)take(sizeof(SysState) * B);
-    g.part = (double *)take(sizeof(double) * 4 * (size_t)(nch > 0 ? nch : 1));
+    g.part = (double *)take(sizeof(double) * kSegSlots * (size_t)(nch > 0 ? nch : 1));
     a.info = (RInfo *)take(sizeof(RInfo) * B);
     a.bad = (int32_t *)take(256);
     a.queue = nullptr;
@@ -1027,7 +1044,8 @@ static hsla_status run_segmented(hsla_handle *h, Args a, const hsla_opts &o, con
         HSLA_HIP(h, hipMemcpyAsync(tab + nch, crow.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, s));
     }
     HSLA_HIP(h, hipMemcpyAsync(dfirst, cfirst.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
-    k_seg_reset<<<(B + kBlock - 1) / kBlock, kBlock, 0, s>>>(g.st, B, a.max_iter);
+    k_seg_reset<<<(B + kBlock - 1) / kBlock, kBlock, 0, s>>>(g.st, B, a.max_iter,
+                                                             o.stall_window > 0 ? o.stall_window : 0);
     if (nch > 0) k_seg_init<<<nch, kBlock, 0, s>>>(g);
     k_seg_fin_init<<<B, kBlock, 0, s>>>(g);
     HSLA_HIP(h, hipGetLastError());
@@ -1085,7 +1103,7 @@ static hsla_status run_segmented(hsla_handle *h, Args a, const hsla_opts &o, con
 // stream it over the whole chip).
 bool persistent_eligible(const hsla_handle *h, const hsla_pattern *p, int B, int method, const hsla_opts &o) {
     if (method != HSLA_METHOD_CG || (o.precond != HSLA_PRECOND_JACOBI && o.precond != HSLA_PRECOND_NONE) ||
-        o.use_x0 || o.profile || B < 1 || p->n < 1)
+        o.use_x0 || o.profile || o.stall_window > 0 || B < 1 || p->n < 1)
         return false;
     if (p->n <= rg::kSmallMaxN && p->max_row <= rg::kSmallMaxRow) return true;
     return B >= h->dev.num_cu && p->nnz <= kPersistentMaxNnz;
@@ -1163,6 +1181,7 @@ extern "C" hsla_status hsla_solve_ragged(hsla_handle *h, int32_t B, const int64_
     a.val = d_values;
     a.b = d_b;
     a.x = d_x;
-    if (!o.persistent || (rows >= kSegMinRows && max_n > kSegMinN)) return run_segmented(h, a, o, ro, max_n, infos, s);
+    if (!o.persistent || o.stall_window > 0 || (rows >= kSegMinRows && max_n > kSegMinN))
+        return run_segmented(h, a, o, ro, max_n, infos, s);
     return run_persistent(h, a, o, rows, no[B], max_n, order, infos, s);
 }

@@ -94,29 +94,58 @@ class LearnedFSAI:
             GTs.append(GT)
         return torch.cat(Gs), torch.cat(GTs)
 
-    def solve(self, pat: Pattern, values: torch.Tensor, b: torch.Tensor, rtol=1e-8, max_iter=0, factors=None):
-        """FSAI-PCG with the learned factor.  Systems whose FSAI solve does not
-        end with status OK (a non-finite or non-positive factor diagonal ends
-        it early, so does a breakdown or the iteration cap) are solved again
-        with Jacobi-PCG and reported with status FELL_BACK.
+    def calibrate(self, pat: Pattern, values: torch.Tensor, b: torch.Tensor, rtol=1e-8) -> int:
+        """Runs Jacobi-PCG on a sample of systems (values [B][nnz], b [B][n])
+        and records its largest iteration count; solve() then caps every
+        FSAI attempt at twice that count."""
+        _, infos, _ = _lib.solve(pat, values, b, _lib.make_opts(method="cg", precond="jacobi", rtol=rtol))
+        self.jacobi_iters = max(f["iters"] for f in infos)
+        return self.jacobi_iters
+
+    @staticmethod
+    def default_stall_window(n: int) -> int:
+        """Iterations within which FSAI-PCG must cut ||r|| tenfold: 2 sqrt(n),
+        at least 50 (Jacobi-PCG on the 2D anisotropic operators needs about
+        sqrt(n) iterations per decade at the largest anisotropy)."""
+        return max(50, 2 * math.isqrt(max(n - 1, 0)) + 2)
+
+    def solve(self, pat: Pattern, values: torch.Tensor, b: torch.Tensor, rtol=1e-8, max_iter=0, factors=None,
+              stall_window: int | None = None):
+        """FSAI-PCG with the learned factor, Jacobi-PCG as the fallback.
+
+        A system's FSAI attempt is abandoned, and the system solved again with
+        Jacobi-PCG and reported with status FELL_BACK, when its factor is
+        invalid (a non-finite value or a non-positive diagonal: the library
+        stops it before the first iteration), when ||r|| falls less than
+        tenfold within `stall_window` iterations (default
+        default_stall_window(n); 0 turns the test off), when it reaches the
+        attempt's cap (twice the Jacobi count recorded by calibrate(), else
+        max_iter or the library default), or on a breakdown.  The info of a
+        fallen-back system is its Jacobi solve's, plus the FSAI attempt's
+        status and iterations ('fsai_status', 'fsai_iters').
         Returns (x, infos, status)."""
         G, GT = factors if factors is not None else self.factors(pat, values)
-        opts = _lib.make_opts(method="cg", precond="fsai", rtol=rtol, max_iter=max_iter, G=G, GT=GT)
+        if stall_window is None:
+            stall_window = self.default_stall_window(pat.n)
+        cap = max_iter
+        if not cap and getattr(self, "jacobi_iters", 0):
+            cap = 2 * self.jacobi_iters
+        opts = _lib.make_opts(method="cg", precond="fsai", rtol=rtol, max_iter=cap, G=G, GT=GT,
+                              stall_window=stall_window)
         x, infos, st = _lib.solve(pat, values, b, opts)
         if st == _lib.OK:
             return x, infos, st
         bad = [i for i, f in enumerate(infos) if f["status"] != _lib.OK]
         jopts = _lib.make_opts(method="cg", precond="jacobi", rtol=rtol, max_iter=max_iter)
         if values.dim() == 1:
-            x, infos, st = _lib.solve(pat, values, b, jopts)
-            fixed = list(zip([0], infos))
+            x, fb, _ = _lib.solve(pat, values, b, jopts)
         else:
             idx = torch.as_tensor(bad, device=values.device)
             xb, fb, _ = _lib.solve(pat, values[idx].contiguous(), b.view(values.shape[0], -1)[idx].contiguous(), jopts)
             x.view(values.shape[0], -1)[idx] = xb.view(len(bad), -1)
-            fixed = list(zip(bad, fb))
         worst = _lib.OK
-        for i, f in fixed:
+        for i, f in zip(bad, fb):
+            f["fsai_status"], f["fsai_iters"] = infos[i]["status"], infos[i]["iters"]
             f["status"] = _lib.FELL_BACK if f["status"] == _lib.OK else f["status"]
             infos[i] = f
         for f in infos:

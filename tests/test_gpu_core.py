@@ -84,6 +84,22 @@ def test_spmv_long_rows_and_empty_rows(orc):
     assert np.array_equal(y, np.array([0.0, 14.0, 0.0, 10.0]))
 
 
+def test_spmv_long_rows_random_values(orc):
+    """Rows of 513 to 1500 entries (longer than one LDS tile, summed in
+    pieces) with random FP64 values: still ascending per-row sums, bitwise
+    equal to the oracle; also through the solvers' SpMV+dot on the CSR form."""
+    a = _rand_csr(1500, 0.002, 6, long_rows=(3, 700, 1499))
+    lens = np.diff(a.row_ptr)
+    assert lens.max() > 512
+    x = np.random.default_rng(2).standard_normal(a.n)
+    pat = pattern(a)
+    y = _lib.spmv(pat, t64(a.val), t64(x)).cpu().numpy()
+    assert np.array_equal(y, orc.spmv(a, x))
+    pat.set_format("csr")
+    y = _lib.spmv(pat, t64(a.val), t64(x)).cpu().numpy()
+    assert np.array_equal(y, orc.spmv(a, x))
+
+
 def test_spmv_batched(orc):
     a = W.diffusion3d(7, W.diffusion3d_kappa(7))
     r = np.random.default_rng(3)
@@ -202,6 +218,11 @@ def test_status_codes(persistent):
     assert e.value.status == _lib.ERR_NONFINITE
     x, info, st = solve(a, b, pat=pat, values=t64(-a.val), method="cg", **kw)
     assert st == _lib.BREAKDOWN
+    # one negative Jacobi diagonal: BREAKDOWN before the first iteration, x = 0
+    v = a.val.copy()
+    v[(a.rows() == 7) & (a.col == 7)] *= -1.0
+    x, info, st = solve(a, b, pat=pat, values=t64(v), method="cg", precond="jacobi", **kw)
+    assert st == _lib.BREAKDOWN and info[0]["iters"] == 0 and not x.any()
     nodiag = W.Csr(2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0, 1.0]))
     with pytest.raises(_lib.HslaError) as e:
         solve(nodiag, np.ones(2), precond="jacobi", **kw)

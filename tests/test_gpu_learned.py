@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
-from gpu_common import dev, pattern, rel, t32, t64  # noqa: E402
+from gpu_common import dev, iters_close, pattern, rel, t32, t64  # noqa: E402
 from paper_2601_13994_amd import _lib, learned  # noqa: E402
 from oracle import mpnn  # noqa: E402
 
@@ -170,3 +170,70 @@ def test_training_reduces_probe_loss_and_iterations(orc):
         its_l.append(infos[0]["iters"])
         its_j.append(orc.cg(a, b, precond="jacobi", rtol=1e-8).iters)
     assert sum(its_l) < sum(its_j)
+
+
+def _forged_batch(orc, m=24, B=4):
+    """B systems on one 9-point pattern with classical-FSAI factors G^ of
+    their scaled matrices (float32), as the learned path would hold them."""
+    a, V = _systems(m, B, seed=3)
+    bs = np.stack([np.random.default_rng(40 + s).standard_normal(a.n) for s in range(B)])
+    gh = []
+    for s in range(B):
+        rpL, colL, g = orc.fsai(mpnn.scaled(a.with_values(V[s])))
+        gh.append(g.astype(np.float32))
+    return a, V, bs, rpL, colL, np.stack(gh)
+
+
+def test_learned_fallback_on_forged_factors(orc):
+    """System 1 gets a NaN in G^, system 2 a zero diagonal entry, system 3 a
+    valid but useless diagonal factor (half its rows scaled by 1e-8: ||r||
+    stalls); each must come back FELL_BACK with x equal to the oracle's
+    Jacobi-PCG, after an FSAI attempt that stopped early (BREAKDOWN before the
+    first iteration for the invalid factors, STAGNATED at the stall window for
+    the useless one); system 0 keeps its factor and matches the oracle's
+    FSAI-PCG with the same float32 factor."""
+    a, V, bs, rpL, colL, gh = _forged_batch(orc)
+    lrow = np.repeat(np.arange(a.n), np.diff(rpL))
+    diagL = colL == lrow
+    gh[1][17] = np.nan
+    gh[2][np.nonzero(diagL)[0][5]] = 0.0
+    r = np.random.default_rng(1)
+    gh[3] = np.where(diagL, np.where(r.random(len(colL)) < 0.5, 1e-8, 1.0), 0.0).astype(np.float32)
+    pat = pattern(a)
+    Vt, bt = t64(V), t64(bs)
+    G, GT = _lib.fsai_factors(pat, Vt, torch.as_tensor(gh).to(dev()))
+    model = learned.LearnedFSAI(seed=0)
+    window = model.default_stall_window(a.n)
+    x, infos, st = model.solve(pat, Vt, bt, rtol=1e-12, factors=(G, GT))
+    assert st == _lib.FELL_BACK
+    x = x.cpu().numpy().reshape(4, -1)
+    assert infos[0]["status"] == _lib.OK
+    ref = orc.fsai_pcg(a.with_values(V[0]), rpL, colL, G[0].cpu().numpy().astype(np.float64), bs[0], rtol=1e-12)
+    assert rel(x[0], ref.x) <= 1e-8
+    for s, why, its in ((1, _lib.BREAKDOWN, 0), (2, _lib.BREAKDOWN, 0), (3, _lib.STAGNATED, window)):
+        f = infos[s]
+        assert f["status"] == _lib.FELL_BACK and f["fsai_status"] == why and f["fsai_iters"] == its, (s, f)
+        jac = orc.cg(a.with_values(V[s]), bs[s], precond="jacobi", rtol=1e-12)
+        assert rel(x[s], jac.x) <= 1e-8
+        assert iters_close(f["iters"], jac.iters)
+
+
+def test_learned_fallback_single_system_and_budget(orc):
+    """A single system (values of one dimension) takes the same path; with
+    the stall test off, the Jacobi-calibrated cap (twice Jacobi's iterations)
+    ends the useless factor's attempt instead."""
+    a, V, bs, rpL, colL, gh = _forged_batch(orc, B=1)
+    lrow = np.repeat(np.arange(a.n), np.diff(rpL))
+    r = np.random.default_rng(1)
+    gh[0] = np.where(colL == lrow, np.where(r.random(len(colL)) < 0.5, 1e-8, 1.0), 0.0).astype(np.float32)
+    pat = pattern(a)
+    v1, b1 = t64(V[0]), t64(bs[0])
+    G, GT = _lib.fsai_factors(pat, v1, torch.as_tensor(gh[0]).to(dev()))
+    model = learned.LearnedFSAI(seed=0)
+    jac_its = model.calibrate(pat, t64(V), t64(bs), rtol=1e-12)
+    jac = orc.cg(a.with_values(V[0]), bs[0], precond="jacobi", rtol=1e-12)
+    assert iters_close(jac_its, jac.iters)
+    x, infos, st = model.solve(pat, v1, b1, rtol=1e-12, factors=(G, GT), stall_window=0)
+    f = infos[0]
+    assert st == _lib.FELL_BACK and f["fsai_status"] == _lib.NOT_CONVERGED and f["fsai_iters"] == 2 * jac_its
+    assert rel(x.cpu().numpy(), jac.x) <= 1e-8

@@ -78,6 +78,16 @@ def test_ragged_status_codes(orc, persistent):
     L2 = hs.SparseCSRList([(t64(-a.val), t32(a.row_ptr), t32(a.col))])
     _, infos, st = L2.solve([t64(b)], persistent=persistent)
     assert st == _lib.BREAKDOWN
+    # one negative Jacobi diagonal: that system stops with BREAKDOWN before
+    # its first iteration (x = 0); its batch companion is unaffected
+    v = a.val.copy()
+    v[(a.rows() == 11) & (a.col == 11)] *= -1.0
+    L3 = hs.SparseCSRList([(t64(v), t32(a.row_ptr), t32(a.col)), (t64(a.val), t32(a.row_ptr), t32(a.col))])
+    xs, infos, st = L3.solve([t64(b), t64(b)], rtol=1e-12, persistent=persistent)
+    assert st == _lib.BREAKDOWN
+    assert infos[0]["status"] == _lib.BREAKDOWN and infos[0]["iters"] == 0 and not xs[0].any()
+    ref = orc.cg(a, b, precond="jacobi", rtol=1e-12)
+    assert infos[1]["status"] == _lib.OK and rel(xs[1].cpu().numpy(), ref.x) <= 1e-8
     _, infos, st = L.solve([t64(b)], precond="none", rtol=1e-12, persistent=persistent)
     ref = orc.cg(a, b, precond="none", rtol=1e-12)
     assert st == _lib.OK and iters_close(infos[0]["iters"], ref.iters)

@@ -426,3 +426,17 @@ def test_probe_loss_gradient_fd(orc):
         dense += 2 * (np.outer(e, u) + np.outer(z, y))
     rowsL = np.repeat(np.arange(ns.n), np.diff(rpL2))
     assert _rel(grad2, dense[rowsL, colL2]) < 1e-13
+
+
+def test_residual_norm_integer_exact(orc):
+    """||b - A x||_2 with integer data: every product, row sum and square is
+    exact, so the oracle equals the sum of squares numpy forms from the dense
+    product, up to the final square root (correctly rounded both ways)."""
+    r = np.random.default_rng(21)
+    rp, col = W.random_pattern(300, 0.03, r)
+    a = W.Csr(300, rp, col, r.integers(-50, 50, len(col)).astype(np.float64))
+    x = r.integers(-100, 100, a.n).astype(np.float64)
+    b = r.integers(-10000, 10000, a.n).astype(np.float64)
+    e = b - a.to_dense() @ x
+    assert orc.residual_norm(a, b, x) == np.sqrt(float(np.sum(e * e)))
+    assert orc.residual_norm(a, a.to_dense() @ x, x) == 0.0
