@@ -149,17 +149,29 @@ hsla_status hsla_workspace_size(hsla_handle *h, const hsla_pattern *p, int32_t B
 hsla_status hsla_reserve(hsla_handle *h, size_t bytes);
 
 /* --------------------------------------------------------------- pattern */
-/* Validates and copies a CSR sparsity pattern (row_ptr int32[n+1], col
+/* A sparsity pattern shared by one matrix or by a batch of value sets: the
+ * paper's single-matrix sparse tensor, which holds one matrix or a batch
+ * sharing one pattern so that the per-pattern work is done once (Sec.
+ * "Unified Backend Abstraction", paragraph "Typed sparse-tensor hierarchy").
+ * The paper stores COO with 64-bit indices; this library takes canonical CSR
+ * with 32-bit indices.
+ *
+ * Validates and copies a CSR sparsity pattern (row_ptr int32[n+1], col
  * int32[nnz], device memory) and derives the per-pattern data every solve
  * reuses: diagonal positions, the transpose permutation, symmetry of the
- * pattern, and the SpMV tile schedule.  Canonical CSR means: 0-based,
- * row_ptr[0] = 0, row_ptr nondecreasing, row_ptr[n] = nnz, 0 <= col < n,
- * columns strictly increasing within a row, nnz < 2^31.  Explicit zeros are
- * legal; empty rows are legal for SpMV but a solve rejects a missing
- * diagonal under Jacobi.  Returns HSLA_ERR_INVALID_CSR (with the first bad
- * row in hsla_last_error) otherwise.  The caller's buffers are not retained. */
+ * pattern, the lower triangle, and the SpMV tile schedule.  Canonical CSR
+ * means: 0-based, row_ptr[0] = 0, row_ptr nondecreasing, row_ptr[n] = nnz,
+ * 0 <= col < n, columns strictly increasing within a row, nnz < 2^31.
+ * Explicit zeros are legal; empty rows are legal for SpMV but a solve
+ * rejects a missing diagonal under Jacobi.  Returns HSLA_ERR_INVALID_CSR
+ * (with the first bad row in hsla_last_error) otherwise.  The caller's
+ * buffers are not retained.  `flags` is 0 or HSLA_PATTERN_CSR (no
+ * offset-mask forms are derived: the pattern behaves as after
+ * hsla_pattern_set_format(p, HSLA_FORMAT_CSR) for good, and creation skips
+ * their detection); other bits give HSLA_ERR_INVALID_ARG. */
+enum { HSLA_PATTERN_CSR = 1u };
 hsla_status hsla_pattern_create(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *d_row_ptr,
-                                const int32_t *d_col, void *stream, hsla_pattern **out);
+                                const int32_t *d_col, uint32_t flags, void *stream, hsla_pattern **out);
 void hsla_pattern_destroy(hsla_pattern *p);
 /* n, nnz, nnz of the lower triangle (incl. diagonal), and 1 if the pattern
  * equals its transpose. */
@@ -210,6 +222,34 @@ typedef struct hsla_tuning {
  * must not run concurrently with other calls that use `p`. */
 hsla_status hsla_autotune(hsla_handle *h, hsla_pattern *p, int32_t B, int32_t effort, hsla_tuning *out,
                           void *stream);
+/* Device copies of the lower triangle, diagonal included, on which FSAI
+ * factors and the network's output live ([B][nnz_lower] value arrays follow
+ * its entry order): row_ptr_L int32[n+1], col_L int32[nnz_lower] and
+ * pos int32[nnz_lower] with pos[k'] = position in A of the entry stored at
+ * k' of the lower triangle.  Any output may be NULL. */
+hsla_status hsla_pattern_lower(hsla_handle *h, const hsla_pattern *p, int32_t *d_row_ptr_L, int32_t *d_col_L,
+                               int32_t *d_pos, void *stream);
+/* A 64-bit signature of the pattern (a hash of n, nnz, row_ptr and col taken
+ * at creation): equal patterns have equal signatures in any process. */
+hsla_status hsla_pattern_signature(const hsla_pattern *p, uint64_t *signature);
+/* The SpMV configuration a pattern holds (its defaults, or the autotuner's
+ * choice) as a plain record, so that a tuning can be stored (keyed by the
+ * signature, batch size and device) and applied to an equal pattern later,
+ * e.g. in another process, without timing again.  hsla_pattern_set_tuning
+ * returns HSLA_ERR_INVALID_ARG if the signature differs from the pattern's
+ * or a field is out of range; it must not run concurrently with calls that
+ * use the pattern. */
+typedef struct hsla_tune_state {
+    uint64_t signature; /* of the pattern the record was taken from                       */
+    int32_t tuned;      /* 1 if set by hsla_autotune (or from such a record)              */
+    int32_t dia;        /* 1: the diagonal-major copy, 0: row tiles (offset-mask patterns) */
+    int32_t dia_cu;     /* blocks per CU of the diagonal-major SpMV (1..64)               */
+    int32_t tile_cu;    /* blocks per CU of the row-tile SpMV (1..64)                     */
+    int32_t sym;        /* 1: symmetric half form for symmetric values                    */
+    int32_t sym_cu;     /* blocks per CU of the half form's SpMV (1..64)                  */
+} hsla_tune_state;
+hsla_status hsla_pattern_get_tuning(const hsla_pattern *p, hsla_tune_state *out);
+hsla_status hsla_pattern_set_tuning(hsla_pattern *p, const hsla_tune_state *in);
 /* Device copies of the transpose: row_ptr_T int32[n+1], col_T int32[nnz] and
  * src int32[nnz] with src[k'] = position in A of the entry stored at k' of
  * A^T (a bijection).  Host-visible only through the copy. */
@@ -233,8 +273,12 @@ hsla_status hsla_solve(hsla_handle *h, const hsla_pattern *p, const double *d_va
                        const double *d_b, double *d_x, const hsla_opts *opts, hsla_info *info,
                        void *stream);
 
-/* B independent systems on one pattern (values [B][nnz], b and x [B][n]),
- * iterated in lock step with a per-system convergence mask: a system stops
+/* B independent systems on one pattern (values [B][nnz], b and x [B][n]):
+ * the paper's batched solve with a shared sparsity pattern (Sec. "Unified
+ * Backend Abstraction", paragraph "Typed sparse-tensor hierarchy", and item
+ * 3 of the API listing in Sec. "API Examples"), where the per-pattern data
+ * is reused across the batch.  The systems are iterated in lock step with a
+ * per-system convergence mask: a system stops
  * when its own test passes, and its result does not depend on the others.
  * `infos` (host, may be NULL) receives B records.  Returns the worst status
  * (an error < 0 if any system errs, else the largest warning). */
@@ -252,8 +296,10 @@ hsla_status hsla_adjoint(hsla_handle *h, const hsla_pattern *p, const double *d_
                          const double *d_x, const double *d_gx, double *d_gA, double *d_gb,
                          const hsla_opts *opts, hsla_info *info, void *stream);
 
-/* Batched adjoint over a shared pattern: values [B][nnz], x, gx, gb [B][n],
- * gA [B][nnz]. */
+/* Batched adjoint over a shared pattern (Eq. adjoint_linear per system;
+ * the paper's batched solves keep gradients flowing through the same
+ * adjoint path, Sec. "API Examples"): values [B][nnz], x, gx, gb [B][n],
+ * gA [B][nnz].  Each system's adjoint solve stops on its own test. */
 hsla_status hsla_adjoint_batched(hsla_handle *h, const hsla_pattern *p, int32_t B,
                                  const double *d_values, const double *d_x, const double *d_gx,
                                  double *d_gA, double *d_gb, const hsla_opts *opts,

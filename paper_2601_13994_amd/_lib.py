@@ -24,13 +24,15 @@ METHODS = {"auto": 0, "cg": 1, "bicgstab": 2, "cg_sr": 3}
 METHOD_NAMES = {v: k for k, v in METHODS.items()}
 PRECONDS = {"none": 0, "jacobi": 1, "fsai": 2}
 FORMATS = {"auto": 0, "csr": 1, "diagonal": 2}
+PATTERN_CSR = 1  # hsla_pattern_create flag
 
 # every symbol include/hsla.h declares
 EXPORTS = [
     "hsla_opts_default", "hsla_status_string", "hsla_create", "hsla_destroy", "hsla_last_error",
     "hsla_set_allocator", "hsla_workspace_size", "hsla_reserve",
     "hsla_pattern_create", "hsla_pattern_destroy", "hsla_pattern_info", "hsla_pattern_set_format",
-    "hsla_pattern_format", "hsla_autotune", "hsla_pattern_transpose",
+    "hsla_pattern_format", "hsla_autotune", "hsla_pattern_transpose", "hsla_pattern_lower",
+    "hsla_pattern_signature", "hsla_pattern_get_tuning", "hsla_pattern_set_tuning",
     "hsla_spmv", "hsla_solve", "hsla_solve_batched", "hsla_adjoint", "hsla_adjoint_batched",
     "hsla_outer_on_pattern", "hsla_residual_norms",
     "hsla_mpnn_num_params", "hsla_mpnn_forward", "hsla_mpnn_backward", "hsla_probe_loss", "hsla_adam_step",
@@ -57,6 +59,15 @@ class Opts(ctypes.Structure):
 
 SPMV_FORMS = {0: "tiles", 1: "diagonal", 2: "diagonal-half", 3: "persistent", 4: "diagonal-half-unit",
               5: "diagonal-unit"}
+
+
+class TuneState(ctypes.Structure):
+    _fields_ = [("signature", ctypes.c_uint64), ("tuned", ctypes.c_int32), ("dia", ctypes.c_int32),
+                ("dia_cu", ctypes.c_int32), ("tile_cu", ctypes.c_int32), ("sym", ctypes.c_int32),
+                ("sym_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class Info(ctypes.Structure):
@@ -114,7 +125,7 @@ def load() -> ctypes.CDLL:
         L.hsla_set_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp]
         L.hsla_workspace_size.argtypes = [vp, vp, i32, P(Opts), P(ctypes.c_size_t)]
         L.hsla_reserve.argtypes = [vp, ctypes.c_size_t]
-        L.hsla_pattern_create.argtypes = [vp, i32, i64, vp, vp, vp, P(vp)]
+        L.hsla_pattern_create.argtypes = [vp, i32, i64, vp, vp, ctypes.c_uint32, vp, P(vp)]
         L.hsla_pattern_destroy.argtypes = [vp]
         L.hsla_pattern_destroy.restype = None
         L.hsla_pattern_info.argtypes = [vp, P(i32), P(i64), P(i64), P(i32)]
@@ -122,6 +133,10 @@ def load() -> ctypes.CDLL:
         L.hsla_pattern_format.argtypes = [vp, P(i32), P(i32)]
         L.hsla_autotune.argtypes = [vp, vp, i32, i32, P(Tuning), vp]
         L.hsla_pattern_transpose.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.hsla_pattern_lower.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.hsla_pattern_signature.argtypes = [vp, P(ctypes.c_uint64)]
+        L.hsla_pattern_get_tuning.argtypes = [vp, P(TuneState)]
+        L.hsla_pattern_set_tuning.argtypes = [vp, P(TuneState)]
         L.hsla_spmv.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.hsla_solve.argtypes = [vp, vp, vp, vp, vp, P(Opts), P(Info), vp]
         L.hsla_solve_batched.argtypes = [vp, vp, i32, vp, vp, vp, P(Opts), P(Info), vp]
@@ -255,7 +270,8 @@ def make_opts(method="auto", precond="jacobi", rtol=1e-8, atol=0.0, max_iter=0, 
 class Pattern:
     """A validated CSR pattern resident on one device (hsla_pattern)."""
 
-    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor):
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, csr_only: bool = False):
+        """csr_only=True creates it with HSLA_PATTERN_CSR (no offset-mask forms)."""
         if not row_ptr.is_cuda:
             raise ValueError("row_ptr must be on a GPU")
         self.device = row_ptr.device
@@ -267,7 +283,8 @@ class Pattern:
             self.h = handle(self.device.index)
             p = ctypes.c_void_p()
             st = load().hsla_pattern_create(self.h, self.n, self.nnz, ptr(self.row_ptr), ptr(self.col),
-                                            stream_ptr(self.device), ctypes.byref(p))
+                                            PATTERN_CSR if csr_only else 0, stream_ptr(self.device),
+                                            ctypes.byref(p))
             check(st, self.h, "hsla_pattern_create")
         self.p = p
         n_ = ctypes.c_int32()
@@ -293,15 +310,49 @@ class Pattern:
         if st != OK:
             raise HslaError(st, f"unknown format {fmt!r}")
 
-    def autotune(self, B: int = 1, effort: int = 5) -> dict:
+    @property
+    def signature(self) -> int:
+        """64-bit hash of (n, nnz, row_ptr, col); equal patterns agree across processes."""
+        v = ctypes.c_uint64()
+        check(load().hsla_pattern_signature(self.p, ctypes.byref(v)), self.h, "hsla_pattern_signature")
+        return v.value
+
+    def get_tuning(self) -> dict:
+        t = TuneState()
+        check(load().hsla_pattern_get_tuning(self.p, ctypes.byref(t)), self.h, "hsla_pattern_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, state: dict) -> None:
+        t = TuneState(**{k: int(state[k]) for k, _ in TuneState._fields_})
+        st = load().hsla_pattern_set_tuning(self.p, ctypes.byref(t))
+        if st != OK:
+            raise HslaError(st, "tuning record does not fit this pattern")
+
+    def autotune(self, B: int = 1, effort: int = 5, cache: str | None = None) -> dict:
         """Times the solvers' SpMV forms and grid densities for a batch of B
-        systems and keeps the fastest for later solves on this pattern."""
+        systems and keeps the fastest for later solves on this pattern.
+
+        cache: a JSON file of tunings keyed by pattern signature, batch size and
+        device architecture.  A stored record is applied without timing
+        ({'cached': True, ...}); otherwise the timed choice is added to the
+        file (written to a temporary file and renamed into place)."""
+        key = None
+        if cache is not None:
+            arch = torch.cuda.get_device_properties(self.device).gcnArchName
+            key = f"{self.signature:016x}/B{int(B)}/{arch}"
+            stored = _read_tune_cache(cache).get(key)
+            if stored is not None:
+                self.set_tuning(stored)
+                return {"cached": True, **stored}
         t = Tuning()
         with torch.cuda.device(self.device):
             st = load().hsla_autotune(self.h, self.p, int(B), int(effort), ctypes.byref(t), stream_ptr(self.device))
             check(st, self.h, "hsla_autotune")
-        return {"form": {0: "diagonal", 1: "tiles", 2: "diagonal-half"}[t.form], "blocks_per_cu": t.blocks_per_cu,
-                "best_us": t.best_us, "default_us": t.default_us}
+        out = {"form": {0: "diagonal", 1: "tiles", 2: "diagonal-half"}[t.form], "blocks_per_cu": t.blocks_per_cu,
+               "best_us": t.best_us, "default_us": t.default_us, "cached": False}
+        if key is not None:
+            _write_tune_cache(cache, key, self.get_tuning())
+        return out
 
     def __del__(self):
         p = getattr(self, "p", None)
@@ -321,6 +372,37 @@ class Pattern:
             st = load().hsla_pattern_transpose(self.h, self.p, ptr(rpT), ptr(colT), ptr(src), stream_ptr(self.device))
             check(st, self.h, "hsla_pattern_transpose")
         return rpT, colT[:self.nnz], src[:self.nnz]
+
+    def lower(self):
+        """(row_ptr_L, col_L, pos) of the lower triangle incl. the diagonal
+        (device int32 tensors; pos = position in A of each lower entry)."""
+        rpL = torch.empty(self.n + 1, dtype=torch.int32, device=self.device)
+        colL = torch.empty(max(self.nnz_lower, 1), dtype=torch.int32, device=self.device)
+        pos = torch.empty(max(self.nnz_lower, 1), dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            st = load().hsla_pattern_lower(self.h, self.p, ptr(rpL), ptr(colL), ptr(pos), stream_ptr(self.device))
+            check(st, self.h, "hsla_pattern_lower")
+        return rpL, colL[:self.nnz_lower], pos[:self.nnz_lower]
+
+
+def _read_tune_cache(path: str) -> dict:
+    import json
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _write_tune_cache(path: str, key: str, state: dict) -> None:
+    import json
+    d = _read_tune_cache(path)
+    d[key] = state
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
 
 
 def _batch(values: torch.Tensor, nnz: int) -> int:

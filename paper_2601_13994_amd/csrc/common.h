@@ -159,6 +159,7 @@ struct hsla_pattern {
     // until tuned: diagonal-major form where available (its symmetric half
     // form for symmetric values), 16 / 8 / 8 blocks per CU
     int32_t tune_dia = 1, tune_tile_cu = 16, tune_dia_cu = 8, tune_sym = 1, tune_sym_cu = 8, tuned = 0;
+    uint64_t signature = 0;  // hash of (n, nnz, row_ptr, col): key of stored tunings
     int32_t n = 0;
     int64_t nnz = 0;
     int32_t *row_ptr = nullptr;  // [n+1]

@@ -240,6 +240,31 @@ __global__ __launch_bounds__(kBlock) void k_compare_i32(const int32_t *__restric
         if (a[i] != b[i]) *differ = 1;
 }
 
+// Pattern signature: sum over elements of splitmix64(salt ^ (i << 32 | a[i]))
+// (position-bound, so any change of an index or its place changes it with
+// overwhelming probability); one 64-bit atomic add per block.
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kBlock) void k_hash_i32(const int32_t *__restrict__ a, int64_t m, uint64_t salt,
+                                                     unsigned long long *acc) {
+    __shared__ uint64_t sh[kBlock];
+    uint64_t s = 0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock)
+        s += mix64(salt ^ (((uint64_t)i << 32) | (uint32_t)a[i]));
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(acc, (unsigned long long)sh[0]);
+}
+
 // Lower triangle (col <= row) of a canonical CSR: a prefix of every row.
 __global__ __launch_bounds__(kBlock) void k_count_lower(int32_t n, const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col, int32_t *__restrict__ cnt1) {
@@ -464,9 +489,11 @@ static void free_pattern(hsla_pattern *p) {
 }
 
 hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col,
-                         hipStream_t s, hsla_pattern **out) {
+                         uint32_t flags, hipStream_t s, hsla_pattern **out) {
     if (!h || !out) return set_error(h, HSLA_ERR_INVALID_ARG, "null handle or output");
     *out = nullptr;
+    if (flags & ~(uint32_t)HSLA_PATTERN_CSR) return set_error(h, HSLA_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const bool stencils = !(flags & HSLA_PATTERN_CSR);
     if (n < 0 || nnz < 0 || nnz >= INT32_MAX)
         return set_error(h, HSLA_ERR_INVALID_ARG, "n=%d nnz=%lld out of range", n, (long long)nnz);
     if (!d_row_ptr || (nnz > 0 && !d_col)) return set_error(h, HSLA_ERR_INVALID_ARG, "null pattern pointer");
@@ -475,6 +502,7 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
     p->device = h->device;
     p->n = n;
     p->nnz = nnz;
+    if (!stencils) p->format = HSLA_FORMAT_CSR;
     auto fail = [&](hsla_status st) {
         free_pattern(p);
         return st;
@@ -502,10 +530,13 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
         int32_t bad_row;
         int32_t differ;
         int64_t nnz_lower;
-    } hf{INT32_MAX, 0, 0}, *df = nullptr;
+        unsigned long long hash_rp, hash_col;
+    } hf{INT32_MAX, 0, 0, 0, 0}, *df = nullptr;
     PCHK(hipMalloc((void **)&df, sizeof(Flags)));
     PCHK(hipMemcpyAsync(df, &hf, sizeof(Flags), hipMemcpyHostToDevice, s));
     if (n > 0) k_validate<<<blocks_for(n), kBlock, 0, s>>>(n, nnz, p->row_ptr, p->col, p->diag, &df->bad_row, &df->nnz_lower);
+    k_hash_i32<<<blocks_for(n + 1), kBlock, 0, s>>>(p->row_ptr, (int64_t)n + 1, 0x5241u, &df->hash_rp);
+    if (nnz > 0) k_hash_i32<<<blocks_for(nnz), kBlock, 0, s>>>(p->col, nnz, 0x434Fu, &df->hash_col);
     PCHK(hipGetLastError());
     PCHK(hipMemcpyAsync(&hf, df, sizeof(Flags), hipMemcpyDeviceToHost, s));
     PCHK(hipStreamSynchronize(s));
@@ -515,11 +546,12 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
                               hf.bad_row));
     }
     p->nnz_lower = hf.nnz_lower;
+    p->signature = mix64(mix64((uint64_t)n) ^ (uint64_t)nnz) + 3ull * hf.hash_rp + hf.hash_col;
 
     std::vector<int32_t> hrp;
     hsla_status st = build_tiles(h, n, p->row_ptr, s, &p->meta, &p->ntiles, hrp);
     for (int32_t i = 0; st == HSLA_OK && i < n; ++i) p->max_row = std::max(p->max_row, hrp[i + 1] - hrp[i]);
-    if (st == HSLA_OK) st = build_stencil(h, n, nnz, hrp, p->row_ptr, p->col, s, &p->stA);
+    if (st == HSLA_OK && stencils) st = build_stencil(h, n, nnz, hrp, p->row_ptr, p->col, s, &p->stA);
     if (st != HSLA_OK) { (void)hipFree(df); return fail(st); }
 
     // transpose and pattern symmetry
@@ -536,7 +568,7 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
     p->pattern_symmetric = hf.differ ? 0 : 1;
     (void)hipFree(df);
     st = build_tiles(h, n, p->rpT, s, &p->metaT, &p->ntilesT, hrp);
-    if (st == HSLA_OK) st = build_stencil(h, n, nnz, hrp, p->rpT, p->colT, s, &p->stT);
+    if (st == HSLA_OK && stencils) st = build_stencil(h, n, nnz, hrp, p->rpT, p->colT, s, &p->stT);
     if (st != HSLA_OK) return fail(st);
     PCHK(hipMalloc((void **)&p->diagT, sizeof(int32_t) * (nn > 0 ? nn : 1)));
     if (n > 0) k_find_diag<<<blocks_for(n), kBlock, 0, s>>>(n, p->rpT, p->colT, p->diagT);
@@ -556,7 +588,7 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
         PCHK(hipGetLastError());
     }
     st = build_tiles(h, n, p->rpL, s, &p->metaL, &p->ntilesL, hrp);
-    if (st == HSLA_OK) st = build_stencil(h, n, nL, hrp, p->rpL, p->colL, s, &p->stL);
+    if (st == HSLA_OK && stencils) st = build_stencil(h, n, nL, hrp, p->rpL, p->colL, s, &p->stL);
     if (st != HSLA_OK) return fail(st);
     PCHK(hipMalloc((void **)&p->rpU, sizeof(int32_t) * (nn + 1)));
     PCHK(hipMalloc((void **)&p->colU, sizeof(int32_t) * (nL > 0 ? nL : 1)));
@@ -564,7 +596,7 @@ hsla_status make_pattern(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *
     st = device_transpose(h, n, nL, p->rpL, p->colL, p->rpU, p->colU, p->srcU, s);
     if (st != HSLA_OK) return fail(st);
     st = build_tiles(h, n, p->rpU, s, &p->metaU, &p->ntilesU, hrp);
-    if (st == HSLA_OK) st = build_stencil(h, n, nL, hrp, p->rpU, p->colU, s, &p->stU);
+    if (st == HSLA_OK && stencils) st = build_stencil(h, n, nL, hrp, p->rpU, p->colU, s, &p->stU);
     if (st != HSLA_OK) return fail(st);
     PCHK(hipMalloc((void **)&p->rowL, sizeof(int32_t) * (nL > 0 ? nL : 1)));
     PCHK(hipMalloc((void **)&p->isdiagL, (nL > 0 ? nL : 1)));
@@ -691,11 +723,11 @@ hsla_status hsla_reserve(hsla_handle *h, size_t bytes) {
 }
 
 hsla_status hsla_pattern_create(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *d_row_ptr,
-                                const int32_t *d_col, void *stream, hsla_pattern **out) {
+                                const int32_t *d_col, uint32_t flags, void *stream, hsla_pattern **out) {
     if (!h) return HSLA_ERR_INVALID_ARG;
     hsla_status st = hsla::enter(h, (hipStream_t)stream);
     if (st != HSLA_OK) return st;
-    return hsla::make_pattern(h, n, nnz, d_row_ptr, d_col, h->stream, out);
+    return hsla::make_pattern(h, n, nnz, d_row_ptr, d_col, flags, h->stream, out);
 }
 
 void hsla_pattern_destroy(hsla_pattern *p) {
@@ -724,6 +756,51 @@ hsla_status hsla_pattern_format(const hsla_pattern *p, int32_t *stencil_in_use, 
     if (!p) return HSLA_ERR_INVALID_ARG;
     if (stencil_in_use) *stencil_in_use = p->use(p->stA).mask != nullptr ? 1 : 0;
     if (num_offsets) *num_offsets = p->stA.mask ? p->stA.nofs : 0;
+    return HSLA_OK;
+}
+
+hsla_status hsla_pattern_signature(const hsla_pattern *p, uint64_t *signature) {
+    if (!p || !signature) return HSLA_ERR_INVALID_ARG;
+    *signature = p->signature;
+    return HSLA_OK;
+}
+
+hsla_status hsla_pattern_get_tuning(const hsla_pattern *p, hsla_tune_state *out) {
+    if (!p || !out) return HSLA_ERR_INVALID_ARG;
+    *out = hsla_tune_state{p->signature, p->tuned, p->tune_dia, p->tune_dia_cu, p->tune_tile_cu, p->tune_sym,
+                           p->tune_sym_cu};
+    return HSLA_OK;
+}
+
+hsla_status hsla_pattern_set_tuning(hsla_pattern *p, const hsla_tune_state *in) {
+    if (!p || !in || in->signature != p->signature) return HSLA_ERR_INVALID_ARG;
+    auto cu_ok = [](int32_t v) { return v >= 1 && v <= 64; };
+    if ((in->dia != 0 && in->dia != 1) || (in->sym != 0 && in->sym != 1) || !cu_ok(in->dia_cu) ||
+        !cu_ok(in->tile_cu) || !cu_ok(in->sym_cu) || (in->tuned != 0 && in->tuned != 1))
+        return HSLA_ERR_INVALID_ARG;
+    p->tune_dia = in->dia;
+    p->tune_dia_cu = in->dia_cu;
+    p->tune_tile_cu = in->tile_cu;
+    p->tune_sym = in->sym;
+    p->tune_sym_cu = in->sym_cu;
+    p->tuned = in->tuned;
+    return HSLA_OK;
+}
+
+hsla_status hsla_pattern_lower(hsla_handle *h, const hsla_pattern *p, int32_t *d_row_ptr_L, int32_t *d_col_L,
+                               int32_t *d_pos, void *stream) {
+    if (!h || !p) return hsla::set_error(h, HSLA_ERR_INVALID_ARG, "null handle or pattern");
+    hsla_status st = hsla::enter(h, (hipStream_t)stream);
+    if (st != HSLA_OK) return st;
+    hipStream_t s = h->stream;
+    if (d_row_ptr_L)
+        HSLA_HIP(h, hipMemcpyAsync(d_row_ptr_L, p->rpL, sizeof(int32_t) * (p->n + 1), hipMemcpyDeviceToDevice, s));
+    if (p->nnz_lower > 0) {
+        if (d_col_L)
+            HSLA_HIP(h, hipMemcpyAsync(d_col_L, p->colL, sizeof(int32_t) * p->nnz_lower, hipMemcpyDeviceToDevice, s));
+        if (d_pos) HSLA_HIP(h, hipMemcpyAsync(d_pos, p->posL, sizeof(int32_t) * p->nnz_lower, hipMemcpyDeviceToDevice, s));
+    }
+    HSLA_HIP(h, hipStreamSynchronize(s));
     return HSLA_OK;
 }
 

@@ -64,7 +64,8 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_2601_13994_amd import _lib
 
     lines = []
-    structs = (("hsla_opts", _lib.Opts), ("hsla_info", _lib.Info), ("hsla_tuning", _lib.Tuning))
+    structs = (("hsla_opts", _lib.Opts), ("hsla_info", _lib.Info), ("hsla_tuning", _lib.Tuning),
+               ("hsla_tune_state", _lib.TuneState))
     for cname, mirror in structs:
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
         for f, _ in mirror._fields_:

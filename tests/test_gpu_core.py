@@ -59,6 +59,38 @@ def test_pattern_transpose_exact(orc):
     assert not pattern(_rand_csr(40, 0.1, 9)).pattern_symmetric
 
 
+def test_pattern_lower_exact(orc):
+    """The lower triangle (the layout of FSAI factors and the network's
+    output) equals the oracle's bit for bit, with each entry's position in A."""
+    for seed, (n, d) in enumerate([(1, 1.0), (57, 0.08), (700, 0.01)]):
+        a = _rand_csr(n, d, seed)
+        rpL, colL, pos = pattern(a).lower()
+        ro, co, po = orc.lower_pattern(a)
+        assert np.array_equal(rpL.cpu().numpy(), ro)
+        assert np.array_equal(colL.cpu().numpy(), co)
+        assert np.array_equal(pos.cpu().numpy(), po)
+
+
+def test_pattern_csr_only_flag(orc):
+    """HSLA_PATTERN_CSR: no offset-mask form is derived (a stencil pattern
+    reports none), SpMV and solves still match the oracle; unknown flag bits
+    are rejected."""
+    import ctypes
+    a, b = W.poisson2d_workload(20)
+    assert pattern(a).stencil == (True, 5)
+    pat = _lib.Pattern(t32(a.row_ptr), t32(a.col), csr_only=True)
+    assert pat.stencil == (False, 0)
+    x = np.random.default_rng(3).standard_normal(a.n)
+    assert np.array_equal(_lib.spmv(pat, t64(a.val), t64(x)).cpu().numpy(), orc.spmv(a, x))
+    xs, info, st = solve(a, b, pat=pat, rtol=1e-12, persistent=False)
+    assert st == 0 and info[0]["spmv_form"] == "tiles"
+    assert rel(xs, orc.cg(a, b, precond="jacobi", rtol=1e-12).x) <= 1e-8
+    p = ctypes.c_void_p()
+    rp, col = t32(a.row_ptr), t32(a.col)
+    st = _lib.load().hsla_pattern_create(pat.h, a.n, a.nnz, rp.data_ptr(), col.data_ptr(), 6, None, ctypes.byref(p))
+    assert st == _lib.ERR_INVALID_ARG and not p.value
+
+
 # ---------------------------------------------------------------- SpMV
 
 @pytest.mark.parametrize("n,density,seed", [(1, 1.0, 0), (63, 0.1, 1), (64, 0.1, 2), (1000, 0.005, 3),

@@ -166,6 +166,39 @@ def test_autotune_choice_applies(orc):
     assert pattern(q).autotune(B=1, effort=2)["form"] == "tiles"
 
 
+def test_tuning_cache_across_patterns(tmp_path):
+    """Signatures: equal patterns agree, a one-index change differs.  The
+    autotuner's choice is stored in a JSON cache keyed by signature, batch
+    size and device, and a second pattern object with the same indices (as
+    in a later process) takes it from the file without timing; a record
+    from another pattern is refused."""
+    m = 16
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m))
+    p1, p2 = pattern(a), pattern(a)
+    assert p1.signature == p2.signature != 0
+    # the same n and nnz, one column index moved by one within its row
+    c = a.col.copy()
+    k = int(a.row_ptr[100])
+    assert c[k] + 1 < c[k + 1]
+    c[k] += 1
+    assert pattern(W.Csr(a.n, a.row_ptr, c, a.val)).signature != p1.signature
+    other = W.poisson2d(64)
+    assert pattern(other).signature != p1.signature
+    cache = str(tmp_path / "tune.json")
+    t1 = p1.autotune(B=2, effort=2, cache=cache)
+    assert t1["cached"] is False
+    t2 = p2.autotune(B=2, effort=2, cache=cache)
+    assert t2["cached"] is True
+    assert p2.get_tuning() == p1.get_tuning() and p2.get_tuning()["tuned"] == 1
+    assert p2.autotune(B=3, effort=2, cache=cache)["cached"] is False  # another batch size: timed
+    q = pattern(other)
+    with pytest.raises(_lib.HslaError):
+        q.set_tuning(p1.get_tuning())
+    bad = dict(p1.get_tuning(), dia_cu=0)
+    with pytest.raises(_lib.HslaError):
+        p1.set_tuning(bad)
+
+
 def _grid7(nx, ny, nz, seed, keep=None):
     """7-point SPD operator on an nx x ny x nz grid with random face
     coefficients (bitwise symmetric values), optionally cut to its first
