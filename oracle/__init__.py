@@ -49,8 +49,9 @@ _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 
 
 def build() -> str:
-    """Compile oracle.c into liboracle.so (gcc, -O2, no FP contraction)."""
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared",
+    """Compile oracle.c into liboracle.so (gcc, -O2, no FP contraction,
+    OpenMP for the optional threaded mode)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fopenmp", "-fPIC", "-shared",
            "-o", LIB_PATH, SRC_PATH, "-lm"]
     subprocess.run(cmd, check=True)
     return LIB_PATH
@@ -65,6 +66,8 @@ def lib():
         i32, i64, f64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
         i64p = ctypes.POINTER(ctypes.c_int64)
         f64p_ = ctypes.POINTER(ctypes.c_double)
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         L.orc_spmv.argtypes = [i32, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.orc_dot.argtypes = [i64, _f64p, _f64p]
         L.orc_dot.restype = f64
@@ -105,6 +108,35 @@ def default_max_iter(n: int) -> int:
 
 
 # ---------------------------------------------------------------------------
+
+_threads = 1
+
+
+def set_threads(threads: int) -> None:
+    """Threads of the oracle's parallel mode (1 = the plain sequential code).
+    With more, SpMV rows and element-wise loops are split over the threads
+    and inner products are summed as per-thread partials in thread order
+    (deterministic for a given count)."""
+    global _threads
+    _threads = max(1, int(threads))
+    lib().orc_set_threads(_threads)
+
+
+class threads:
+    """Context manager: run the oracle with `n` threads inside the block."""
+
+    def __init__(self, n: int):
+        self.n = n
+
+    def __enter__(self):
+        self.prev = _threads
+        set_threads(self.n)
+        return self
+
+    def __exit__(self, *exc):
+        set_threads(self.prev)
+        return False
+
 
 def spmv(a, x):
     n, rp, col, val = _csr(a)

@@ -32,6 +32,15 @@
  *                     the paper, which names learned preconditioners only as
  *                     future work.
  *   orc_probe_loss    ||G A G^T z - z||^2 and its gradient w.r.t. G's values.
+ *
+ * Threads (orc_set_threads, default 1).  With one thread everything above
+ * holds as stated.  With T > 1 threads (OpenMP, for timing the oracle on all
+ * host cores and for solving grid-size systems in the tests) the SpMV rows
+ * and the element-wise vector loops of CG and BiCGStab are split over the
+ * threads, which changes no result, and every inner product and residual
+ * norm is the sum, in thread order, of T left-to-right partial sums over
+ * contiguous index ranges of equal size: deterministic for a given T, equal
+ * to the one-thread result up to the rounding of that summation order.
  */
 #include <math.h>
 #include <stdint.h>
@@ -42,6 +51,18 @@
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_BREAKDOWN = 2, ORC_NONFINITE = 3, ORC_BAD_INPUT = 4 };
 enum { ORC_PRECOND_NONE = 0, ORC_PRECOND_JACOBI = 1 };
 
+enum { ORC_MAX_THREADS = 256 };
+static int g_threads = 1;
+
+/* Number of threads of the parallel mode (1 = plain sequential code). */
+void orc_set_threads(int threads)
+{
+    g_threads = threads < 1 ? 1 : threads > ORC_MAX_THREADS ? ORC_MAX_THREADS : threads;
+}
+
+/* an element-wise loop split over the threads when more than one is set */
+#define PAR_FOR _Pragma("omp parallel for num_threads(g_threads) schedule(static) if(g_threads > 1)")
+
 /* ------------------------------------------------------------------------ */
 /* basic vector operations                                                   */
 /* ------------------------------------------------------------------------ */
@@ -49,6 +70,7 @@ enum { ORC_PRECOND_NONE = 0, ORC_PRECOND_JACOBI = 1 };
 void orc_spmv(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
               const double *x, double *y)
 {
+    PAR_FOR
     for (int32_t i = 0; i < n; ++i) {
         double s = 0.0;
         for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
@@ -59,6 +81,21 @@ void orc_spmv(int32_t n, const int32_t *rp, const int32_t *col, const double *va
 
 double orc_dot(int64_t n, const double *a, const double *b)
 {
+    if (g_threads > 1) {
+        /* T partial sums over [n t / T, n (t+1) / T), added in t order */
+        const int T = g_threads;
+        double part[ORC_MAX_THREADS];
+        #pragma omp parallel for num_threads(T) schedule(static, 1)
+        for (int t = 0; t < T; ++t) {
+            double s = 0.0;
+            for (int64_t i = n * t / T; i < n * (t + 1) / T; ++i)
+                s += a[i] * b[i];
+            part[t] = s;
+        }
+        double s = 0.0;
+        for (int t = 0; t < T; ++t) s += part[t];
+        return s;
+    }
     double s = 0.0;
     for (int64_t i = 0; i < n; ++i)
         s += a[i] * b[i];
@@ -84,18 +121,35 @@ int orc_jacobi_inverse(int32_t n, const int32_t *rp, const int32_t *col, const d
 }
 
 /* ||b - A x||_2 */
-double orc_residual_norm(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                         const double *b, const double *x)
+static double residual_sq(int32_t lo, int32_t hi, const int32_t *rp, const int32_t *col,
+                          const double *val, const double *b, const double *x)
 {
     double s = 0.0;
-    for (int32_t i = 0; i < n; ++i) {
+    for (int32_t i = lo; i < hi; ++i) {
         double ax = 0.0;
         for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
             ax += val[k] * x[col[k]];
         double r = b[i] - ax;
         s += r * r;
     }
-    return sqrt(s);
+    return s;
+}
+
+double orc_residual_norm(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                         const double *b, const double *x)
+{
+    if (g_threads > 1) {
+        const int T = g_threads;
+        double part[ORC_MAX_THREADS];
+        #pragma omp parallel for num_threads(T) schedule(static, 1)
+        for (int t = 0; t < T; ++t)
+            part[t] = residual_sq((int32_t)((int64_t)n * t / T), (int32_t)((int64_t)n * (t + 1) / T),
+                                  rp, col, val, b, x);
+        double s = 0.0;
+        for (int t = 0; t < T; ++t) s += part[t];
+        return sqrt(s);
+    }
+    return sqrt(residual_sq(0, n, rp, col, val, b, x));
 }
 
 /* ------------------------------------------------------------------------ */
@@ -130,16 +184,21 @@ int orc_cg(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
         status = ORC_BAD_INPUT;
         goto done;
     }
-    if (!use_x0)
+    if (!use_x0) {
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+    }
     orc_spmv(n, rp, col, val, x, q);
+    PAR_FOR
     for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
     double tol = rtol * bnorm;
     if (atol > tol) tol = atol;
     rnorm = nrm2(n, r);
     if (!isfinite(rnorm) || !isfinite(bnorm)) { status = ORC_NONFINITE; goto done; }
     if (rnorm <= tol) { status = ORC_OK; goto done; }
+    PAR_FOR
     for (int32_t i = 0; i < n; ++i) z[i] = precond == ORC_PRECOND_JACOBI ? dinv[i] * r[i] : r[i];
+    PAR_FOR
     for (int32_t i = 0; i < n; ++i) p[i] = z[i];
     double rho = orc_dot(n, r, z);
     while (it < max_iter) {
@@ -148,17 +207,21 @@ int orc_cg(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
         if (!isfinite(sigma)) { status = ORC_NONFINITE; break; }
         if (!(sigma > 0.0)) { status = ORC_BREAKDOWN; break; }
         double alpha = rho / sigma;
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) x[i] += alpha * p[i];
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) r[i] -= alpha * q[i];
         if (alphas) alphas[it] = alpha;
         ++it;
         rnorm = nrm2(n, r);
         if (!isfinite(rnorm)) { status = ORC_NONFINITE; break; }
         if (rnorm <= tol) { status = ORC_OK; break; }
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) z[i] = precond == ORC_PRECOND_JACOBI ? dinv[i] * r[i] : r[i];
         double rho_new = orc_dot(n, r, z);
         double beta = rho_new / rho;
         if (betas) betas[it - 1] = beta;
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
         rho = rho_new;
     }
@@ -202,11 +265,15 @@ int orc_bicgstab(int32_t n, const int32_t *rp, const int32_t *col, const double 
     if (precond == ORC_PRECOND_JACOBI) {
         if (orc_jacobi_inverse(n, rp, col, val, dinv) != 0) { status = ORC_BAD_INPUT; goto done; }
     } else {
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) dinv[i] = 1.0;
     }
-    if (!use_x0)
+    if (!use_x0) {
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+    }
     orc_spmv(n, rp, col, val, x, t);
+    PAR_FOR
     for (int32_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
     double tol = rtol * bnorm;
     if (atol > tol) tol = atol;
@@ -215,6 +282,7 @@ int orc_bicgstab(int32_t n, const int32_t *rp, const int32_t *col, const double 
     if (rnorm <= tol) { status = ORC_OK; goto done; }
 
 restart:
+    PAR_FOR
     for (int32_t i = 0; i < n; ++i) { rh[i] = r[i]; p[i] = 0.0; v[i] = 0.0; }
     double rho = 1.0, alpha = 1.0, omega = 1.0;
     while (it < max_iter) {
@@ -222,23 +290,29 @@ restart:
         if (!isfinite(rho_new)) { status = ORC_NONFINITE; break; }
         if (rho_new == 0.0) goto breakdown;
         double beta = (rho_new / rho) * (alpha / omega);
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) ph[i] = precond == ORC_PRECOND_JACOBI ? dinv[i] * p[i] : p[i];
         orc_spmv(n, rp, col, val, ph, v);
         double rv = orc_dot(n, rh, v);
         if (!isfinite(rv)) { status = ORC_NONFINITE; break; }
         if (rv == 0.0) goto breakdown;
         alpha = rho_new / rv;
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
         ++it;
         double snorm = nrm2(n, s);
         if (!isfinite(snorm)) { status = ORC_NONFINITE; break; }
         if (snorm <= tol) {
+            PAR_FOR
             for (int32_t i = 0; i < n; ++i) x[i] += alpha * ph[i];
+            PAR_FOR
             for (int32_t i = 0; i < n; ++i) r[i] = s[i];
             status = ORC_OK;
             break;
         }
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) sh[i] = precond == ORC_PRECOND_JACOBI ? dinv[i] * s[i] : s[i];
         orc_spmv(n, rp, col, val, sh, t);
         double tt = orc_dot(n, t, t);
@@ -246,7 +320,9 @@ restart:
         if (!isfinite(tt) || !isfinite(ts)) { status = ORC_NONFINITE; break; }
         if (tt == 0.0) goto breakdown;
         omega = ts / tt;
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) x[i] += alpha * ph[i] + omega * sh[i];
+        PAR_FOR
         for (int32_t i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
         rnorm = nrm2(n, r);
         if (!isfinite(rnorm)) { status = ORC_NONFINITE; break; }

@@ -440,3 +440,57 @@ def test_residual_norm_integer_exact(orc):
     e = b - a.to_dense() @ x
     assert orc.residual_norm(a, b, x) == np.sqrt(float(np.sum(e * e)))
     assert orc.residual_norm(a, a.to_dense() @ x, x) == 0.0
+
+
+# ------------------------------------------------------------------ threaded mode
+
+def test_threaded_mode_changes_only_summation_order(orc):
+    """With several threads the oracle splits rows and element-wise loops
+    (no result changes: SpMV bitwise equal to one thread, and integer data
+    stays exact) and sums inner products as per-thread partials: each
+    within n * eps * sum|a_i b_i| of the exactly rounded sum (math.fsum)."""
+    a = W.diffusion3d(12, W.diffusion3d_kappa(12))
+    r = np.random.default_rng(5)
+    x = r.standard_normal(a.n)
+    y1 = orc.spmv(a, x)
+    with orc.threads(7):
+        y7 = orc.spmv(a, x)
+        for n in (1, 6, 7, 1000, a.n):
+            u, v = r.standard_normal(n), r.standard_normal(n)
+            exact = math.fsum(u * v)
+            assert abs(orc.dot(u, v) - exact) <= n * 2.3e-16 * float(np.sum(np.abs(u * v)))
+        bi = r.integers(-1000, 1000, a.n).astype(np.float64)
+        xi = r.integers(-1000, 1000, a.n).astype(np.float64)
+        ai = a.with_values(r.integers(-1000, 1000, a.nnz).astype(np.float64))
+        res = bi - ai.to_dense() @ xi
+        assert orc.residual_norm(ai, bi, xi) == math.sqrt(math.fsum(res * res))
+    assert np.array_equal(y1, y7)
+
+
+@pytest.mark.parametrize("threads", [3, 8])
+def test_threaded_cg_and_bicgstab_match_closed_forms(orc, threads):
+    """The threaded solvers still meet the pins the sequential ones do: CG on
+    the 64^2 Poisson operator against the DST-I closed form within kappa *
+    rtol, BiCGStab on the pure-upwind (lower triangular) operator against
+    forward substitution, and both against the one-thread solve to rounding
+    with iteration counts within max(2, 2%)."""
+    m = 64
+    a = W.poisson2d(m)
+    b = W.rng(1, 1).standard_normal(a.n)
+    seq = orc.cg(a, b, precond="jacobi", rtol=1e-12)
+    with orc.threads(threads):
+        par = orc.cg(a, b, precond="jacobi", rtol=1e-12)
+    kappa = 1.0 / math.tan(math.pi / 130) ** 2
+    assert par.status == orc.OK
+    assert _rel(par.x, _dst_solve_2d(m, b)) <= kappa * 1e-12
+    assert _rel(par.x, seq.x) <= 1e-10
+    assert abs(par.iters - seq.iters) <= max(2, int(0.02 * seq.iters))
+    u = W.diffusion3d(10, velocity=10.0, diffusion=False)
+    keep = u.val != 0
+    d = np.zeros((u.n, u.n))
+    d[u.rows()[keep], u.col[keep]] = u.val[keep]
+    bu = W.rng(2, 1, 3).standard_normal(u.n)
+    with orc.threads(threads):
+        pu = orc.bicgstab(u, bu, precond="jacobi", rtol=1e-13)
+    assert pu.status == orc.OK
+    assert _rel(pu.x, scipy.linalg.solve_triangular(d, bu, lower=True)) <= 1e-10
