@@ -55,10 +55,15 @@ typedef enum hsla_status {
 } hsla_status;
 
 /* CG_SR: CG with the single-reduction recurrence of Chronopoulos and Gear
- * (the same iterates in exact arithmetic, different rounding; one
- * workgroup reduction per iteration instead of two) where it pays: the
- * persistent small-system kernel (n <= 4096 rows of <= 16 entries); every
- * other path runs it as CG.  hsla_info.method reports which ran. */
+ * (the same iterates in exact arithmetic, different rounding): w = A r, and
+ * r.r and w.r in one reduction per iteration instead of two (the roadmap
+ * after the paper's Algorithm "Distributed CG", appendix "Distributed
+ * Conjugate Gradient and Halo Exchange").  It runs with no or Jacobi
+ * preconditioning on the per-iteration kernels (three launches per
+ * iteration instead of five; one more vector, s = A p, is streamed) and in
+ * the persistent small-system kernel (n <= 4096 rows of <= 16 entries);
+ * FSAI and the other persistent kernels run it as CG.  hsla_info.method
+ * reports which ran. */
 typedef enum hsla_method {
     HSLA_METHOD_AUTO = 0,
     HSLA_METHOD_CG = 1,

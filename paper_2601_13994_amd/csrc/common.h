@@ -54,6 +54,7 @@ struct alignas(128) SysState {
     int32_t stall;     // stall window (iterations; 0 = off)
     double win_rr;     // ||r||^2 at the start of the current stall window
     int64_t win_it;    // iteration at the start of the current stall window
+    int32_t sr_swept;  // single-reduction CG: a vector sweep has run since the start
 };
 
 // Stall test after an iteration with ||r||^2 = rr: once st.stall iterations

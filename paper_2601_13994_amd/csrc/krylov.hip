@@ -59,6 +59,7 @@ struct Sys {
     double *rh, *y, *v, *s, *t;  // BiCGStab: y accumulates the iterate of A M^{-1} y = b - A x0
     SysState *st;       // [B]
     double *part;       // [B][3][G] block partials of the last producing kernel
+    double *part2;      // [B][G] block partials of the single-reduction sweep (kept past the next SpMV)
 };
 
 #define SYS_OFFSETS(S, A)                                               \
@@ -539,6 +540,196 @@ __global__ __launch_bounds__(kBlock) void k_cg_unscale(Pat A, Sys S) {
     (void)st;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock)
         S.x[vo + i] = S.dinv[vo + i] * S.x[vo + i];
+}
+
+// ---------------------------------------------------------------------------
+// Single-reduction CG (Chronopoulos and Gear), the roadmap the paper gives
+// after its Algorithm "Distributed CG" for cutting synchronisation points
+// (appendix "Distributed Conjugate Gradient and Halo Exchange").  With
+// w = A r, gamma = r.r and delta = w.r of the same residual:
+//   beta = gamma / gamma_old,  sigma = delta - beta gamma / alpha_old
+//   (= p.Ap of the new direction),  alpha = gamma / sigma,
+//   p = r + beta p,  s = w + beta s  (s = A p),  x += alpha p,  r -= alpha s.
+// The same iterates as CG in exact arithmetic.  One iteration is three
+// launches: the SpMV with both sums, one finalize, one vector sweep.  The
+// sweep's ||r||^2 partials go to part2 and are read by the next finalize,
+// which takes the stop test there (a stopped system's x is already final,
+// one SpMV later).  Jacobi runs on the scaled system S A S as in CG.
+// ---------------------------------------------------------------------------
+
+// w = A r and partials of gamma = r.r, delta = w.r.
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_sr_spmv_dot(Pat A, Sys S) {
+    __shared__ double lds[kWavesPerBlock][kTileCap];
+    SYS_OFFSETS(S, A)
+    if (stopped(st)) return;
+    const double *r = S.r + vo;
+    double *w = S.w + vo;
+    double acc[2] = {0.0, 0.0};
+    if constexpr (NS > 0) {
+        spmv_dia<NS>(A.sn, S.dia + (int64_t)sidx * dia_stored(NS, A.sn.nofs) * dia_chunks(A.n) * kDiaChunk,
+                     (int64_t)A.n, r,
+                     [&](int64_t row, double yv, double rrow) {
+                         w[row] = yv;
+                         acc[0] += rrow * rrow;
+                         acc[1] += rrow * yv;
+                     });
+    } else {
+        spmv_tiles(A.rp, A.col, A.sn, S.aval + (int64_t)sidx * A.nnz, r, A.meta, A.ntiles, lds[threadIdx.x / kWave],
+                   [&](int64_t row, double yv) {
+                       const double rv = r[row];
+                       w[row] = yv;
+                       acc[0] += rv * rv;
+                       acc[1] += rv * yv;
+                   });
+    }
+    block_partial<2>(acc, part);
+}
+
+// Stop test on the last sweep's ||r|| (from part2, Gv partials; none before
+// the first sweep), then beta, sigma and alpha from gamma and delta (Gs
+// partials); sigma <= 0 is BREAKDOWN, as p.Ap <= 0 in CG.
+__global__ __launch_bounds__(kBlock) void k_fin_sr(Sys S, int Gs, int Gv) {
+    FIN_OFFSETS(S, Gs)
+    if (stopped(st)) return;
+    double tot[2];
+    reduce_partials<2>(part, Gs, tot);
+    double rr[1] = {0.0};
+    const bool swept = st.sr_swept != 0;
+    if (swept) reduce_partials<1>(S.part2 + (int64_t)sidx * Gv, Gv, rr);
+    if (threadIdx.x != 0) return;
+    if (swept) {
+        cg_step_beta(st, rr[0], 0.0, false);
+        if (st.done) return;
+    }
+    const double gamma = tot[0], delta = tot[1];
+    double beta = 0.0, sigma = delta;
+    if (swept) {
+        beta = gamma / st.rho;
+        sigma = delta - beta * gamma / st.alpha;
+    }
+    if (!isfinite(sigma) || !isfinite(gamma)) {
+        st.status = HSLA_ERR_NONFINITE;
+        st.done = 1;
+    } else if (!(sigma > 0.0)) {
+        st.status = HSLA_BREAKDOWN;
+        st.done = 1;
+    } else {
+        st.beta = beta;
+        st.alpha = gamma / sigma;
+        st.rho = gamma;
+        st.sr_swept = 1;
+    }
+}
+
+// p = r + beta p; s = w + beta s; x += alpha p; r -= alpha s; partials of
+// the unscaled ||r||^2 into part2 (Jacobi: r holds S r).
+template <int PRE>
+__global__ __launch_bounds__(kBlock) void k_sr_sweep(Pat A, Sys S) {
+    SYS_OFFSETS(S, A)
+    (void)part;
+    if (stopped(st)) return;
+    const double alpha = st.alpha, beta = st.beta;
+    double *__restrict__ x = S.x + vo;
+    double *__restrict__ p = S.p + vo;
+    double *__restrict__ sv = S.q + vo;
+    double *__restrict__ r = S.r + vo;
+    const double *__restrict__ w = S.w + vo;
+    const double *__restrict__ dinv = S.dinv + vo;
+    double acc[1] = {0.0};
+    auto elem = [&](double &xv, double &pv, double &s_, double &rv, double wv, double dv) {
+        pv = rv + beta * pv;
+        s_ = wv + beta * s_;
+        xv = xv + alpha * pv;
+        rv = rv - alpha * s_;
+        const double u = PRE == PRE_JACOBI ? rv / dv : rv;
+        acc[0] += u * u;
+    };
+    auto pair_elem = [&](dpair &xv, dpair &pv, dpair &s_, dpair &rv, dpair wv, dpair dv) {
+        double x0 = xv.x, p0 = pv.x, s0 = s_.x, r0 = rv.x, x1 = xv.y, p1 = pv.y, s1 = s_.y, r1 = rv.y;
+        elem(x0, p0, s0, r0, wv.x, dv.x);
+        elem(x1, p1, s1, r1, wv.y, dv.y);
+        xv = dpair{x0, x1};
+        pv = dpair{p0, p1};
+        s_ = dpair{s0, s1};
+        rv = dpair{r0, r1};
+    };
+    if (al16(x) && al16(p) && al16(sv) && al16(r) && al16(w) && (PRE != PRE_JACOBI || al16(dinv))) {
+        const dpair one = {1.0, 1.0};
+        PAIR_LOOP_BEGIN(A.n / 2)
+                dpair xv[2], pv[2], sq[2], rv[2], wv[2], dv[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int64_t e = 2 * (i_ + j * S_);
+                    xv[j] = ldp(x + e);
+                    pv[j] = ldp(p + e);
+                    sq[j] = ldp(sv + e);
+                    rv[j] = ldp(r + e);
+                    wv[j] = ldp(w + e);
+                    dv[j] = PRE == PRE_JACOBI ? ldp(dinv + e) : one;
+                }
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int64_t e = 2 * (i_ + j * S_);
+                    pair_elem(xv[j], pv[j], sq[j], rv[j], wv[j], dv[j]);
+                    stp(x + e, xv[j]);
+                    stp(p + e, pv[j]);
+                    stp(sv + e, sq[j]);
+                    stp(r + e, rv[j]);
+                }
+        PAIR_LOOP_TAIL
+                const int64_t e = 2 * i_;
+                dpair xv = ldp(x + e), pv = ldp(p + e), sq = ldp(sv + e), rv = ldp(r + e);
+                const dpair wv = ldp(w + e), dv = PRE == PRE_JACOBI ? ldp(dinv + e) : one;
+                pair_elem(xv, pv, sq, rv, wv, dv);
+                stp(x + e, xv);
+                stp(p + e, pv);
+                stp(sv + e, sq);
+                stp(r + e, rv);
+        PAIR_LOOP_END
+        if ((A.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+            const int64_t e = A.n - 1;
+            double xv = x[e], pv = p[e], sq = sv[e], rv = r[e];
+            elem(xv, pv, sq, rv, w[e], PRE == PRE_JACOBI ? dinv[e] : 1.0);
+            x[e] = xv;
+            p[e] = pv;
+            sv[e] = sq;
+            r[e] = rv;
+        }
+    } else {
+        GRID_LOOP_BEGIN(A.n)
+                double xv[4], pv[4], sq[4], rv[4], wv[4], dv[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t e = i_ + j * S_;
+                    xv[j] = x[e];
+                    pv[j] = p[e];
+                    sq[j] = sv[e];
+                    rv[j] = r[e];
+                    wv[j] = w[e];
+                    dv[j] = PRE == PRE_JACOBI ? dinv[e] : 1.0;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t e = i_ + j * S_;
+                    elem(xv[j], pv[j], sq[j], rv[j], wv[j], dv[j]);
+                    x[e] = xv[j];
+                    p[e] = pv[j];
+                    sv[e] = sq[j];
+                    r[e] = rv[j];
+                }
+        GRID_LOOP_TAIL
+                double xv = x[i_], pv = p[i_], sq = sv[i_], rv = r[i_];
+                elem(xv, pv, sq, rv, w[i_], PRE == PRE_JACOBI ? dinv[i_] : 1.0);
+                x[i_] = xv;
+                p[i_] = pv;
+                sv[i_] = sq;
+                r[i_] = rv;
+        GRID_LOOP_END
+    }
+    __shared__ double sh[kWavesPerBlock];
+    block_sum<1>(acc, sh);
+    if (threadIdx.x == 0) S.part2[(int64_t)sidx * gridDim.x + blockIdx.x] = acc[0];
 }
 
 // The operator S A S of the scaled system on CSR values (tile form): each
@@ -1070,6 +1261,7 @@ __global__ __launch_bounds__(kBlock) void k_outer(int32_t n, int64_t nnz, const 
 
 struct Layout {
     size_t off_state, off_part, off_vec, off_res, off_extra, total;
+    int gmax;  // partials per value and system; part2 starts 3 gmax B doubles past off_part
 };
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -1080,7 +1272,8 @@ static Layout make_layout(int B, int64_t n, int nvec, int G, size_t extra = 0) {
     L.off_state = o;
     o = align_up(o + sizeof(SysState) * B, 256);
     L.off_part = o;
-    o = align_up(o + sizeof(double) * 3 * (size_t)G * B, 256);
+    L.gmax = G;
+    o = align_up(o + sizeof(double) * 4 * (size_t)G * B, 256);
     L.off_res = o;
     o = align_up(o + sizeof(double) * 2 * (size_t)B, 256);
     L.off_vec = o;
@@ -1170,6 +1363,7 @@ struct SolveCall {
     int Gt, Gv;   // blocks per system: SpMV-based kernels, vector kernels
     int nsA, nsF; // slot counts of the diagonal-major SpMV of A and of the FSAI factors (0: tiles)
     int Gs, Gf;   // blocks per system of the A-SpMV and FSAI kernels
+    int sr;       // CG with the single-reduction recurrence (no or Jacobi preconditioner)
 };
 
 
@@ -1181,7 +1375,16 @@ static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hip
     const dim3 gs(c.Gs, c.B), gfs(c.Gf, c.B), gv(c.Gv, c.B), gf(c.B);
     const int Gs = c.Gs, Gfs = c.Gf, Gv = c.Gv;
     for (int k = 0; k < iters; ++k) {
-        if (c.method == HSLA_METHOD_CG) {
+        if (c.method == HSLA_METHOD_CG && c.sr) {
+            if (ev) (void)hipEventRecord(ev[2 * k], s);
+            NS_LAUNCH_A(k_sr_spmv_dot, c.nsA, gs, c.A, c.S);
+            if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
+            k_fin_sr<<<gf, kBlock, 0, s>>>(c.S, Gs, Gv);
+            if (c.precond == PRE_JACOBI)
+                k_sr_sweep<PRE_JACOBI><<<gv, kBlock, 0, s>>>(c.A, c.S);
+            else
+                k_sr_sweep<PRE_NONE><<<gv, kBlock, 0, s>>>(c.A, c.S);
+        } else if (c.method == HSLA_METHOD_CG) {
             if (ev) (void)hipEventRecord(ev[2 * k], s);
             NS_LAUNCH_A(k_cg_spmv_dot, c.nsA, gs, c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
@@ -1380,7 +1583,7 @@ static Plan plan_solve(hsla_handle *h, const Tune &tn, const Pat &A, const FPat 
 static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, const FPat *L, const FPat *U, int B,
                               const double *values,
                               const double *b, double *x, const hsla_opts &o, int method, hsla_info *infos,
-                              hipStream_t s) {
+                              hipStream_t s, bool sr = false) {
     const int64_t n = A.n;
     const int pre = o.precond == HSLA_PRECOND_NONE ? PRE_NONE : o.precond == HSLA_PRECOND_FSAI ? PRE_FSAI : PRE_JACOBI;
     if (method == HSLA_METHOD_BICGSTAB && pre == PRE_FSAI)
@@ -1408,12 +1611,14 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
     c.nsF = nsF;
     c.Gs = Gs;
     c.Gf = Gf;
+    c.sr = sr && method == HSLA_METHOD_CG && (pre == PRE_NONE || pre == PRE_JACOBI);
     Sys &S = c.S;
     S.val = values;
     S.b = b;
     S.x = x;
     S.st = (SysState *)(ws + lay.off_state);
     S.part = (double *)(ws + lay.off_part);
+    S.part2 = S.part + 3 * (size_t)lay.gmax * B;
     double *vec = (double *)(ws + lay.off_vec);
     const size_t vs = (size_t)B * n;
     double **cg_slots[] = {&S.r, &S.p, &S.q, &S.dinv, &S.z, &S.w};
@@ -1567,7 +1772,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             hsla_info &f = infos[i];
             f.iters = hs[i].iters;
             f.status = sst;
-            f.method = method;
+            f.method = c.sr ? HSLA_METHOD_CG_SR : method;
             const double bn = hs[i].bnorm;
             const double rn = std::sqrt(hs[i].rnorm2);
             f.rel_residual = bn > 0 ? rn / bn : rn;
@@ -1672,7 +1877,7 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
     Tune tn = tune_of(p);
     st = decide_half(h, p, A, B, values, symv, s, &tn);
     if (st != HSLA_OK) return st;
-    return solve_core(h, tn, A, &L, &U, B, values, b, x, o, method, infos, s);
+    return solve_core(h, tn, A, &L, &U, B, values, b, x, o, method, infos, s, sr);
 }
 
 // Eq. adjoint_linear: A^T lambda = gx, gb = lambda, gA = -lambda x^T on the
@@ -1718,7 +1923,7 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
             Tune tn = tune_of(p);
             res = decide_half(h, p, A, B, values, 1, s, &tn);
             if (res == HSLA_OK)
-                res = solve_core(h, tn, A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s);
+                res = solve_core(h, tn, A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s, sr);
         }
     } else {
         if (dev_alloc(h, (void **)&valT, sizeof(double) * (size_t)B * (p->nnz > 0 ? p->nnz : 1)) != hipSuccess) {
@@ -1730,7 +1935,7 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
         if (blocks > 8192) blocks = 8192;
         if (tot > 0) k_gather_values<<<blocks, kBlock, 0, s>>>(p->nnz, B, values, p->srcT, valT);
         const Pat AT = pat_T_of(p);
-        res = solve_core(h, tune_of(p), AT, nullptr, nullptr, B, valT, gx, lam, o, method, infos, s);
+        res = solve_core(h, tune_of(p), AT, nullptr, nullptr, B, valT, gx, lam, o, method, infos, s, sr);
     }
     if (res >= 0 && gA) {
         int Gr = (int)((n + kBlock - 1) / kBlock);

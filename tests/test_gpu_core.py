@@ -500,10 +500,59 @@ def test_cg_single_reduction_parity(orc, name, make, precond):
     assert st == 0 and info[0]["iters"] == 0 and not x.any()
 
 
-def test_cg_single_reduction_elsewhere_runs_cg(orc):
-    """Outside the small-system kernel CG_SR runs Algorithm 1 and says so."""
-    a = W.diffusion3d(20, W.diffusion3d_kappa(20))
-    b = np.random.default_rng(14).standard_normal(a.n)
-    x, info, st = solve(a, b, method="cg_sr", precond="jacobi", rtol=1e-12)
+@pytest.mark.parametrize("fmt", ["auto", "csr"])
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_cg_single_reduction_per_iteration(orc, fmt, precond):
+    """CG_SR on the per-iteration kernels (w = A r with r.r and w.r in one
+    launch, one finalize, one vector sweep) in the diagonal-major and tile
+    forms: the oracle's CG solution, iteration counts within max(2, 2%),
+    graph replay bitwise equal to plain launches, a batch member bitwise
+    equal to its own solve, the k-th iterate at a cap, breakdown and b = 0."""
+    m = 20
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m))
+    r = np.random.default_rng(14)
+    b = r.standard_normal(a.n)
+    pat = pattern(a)
+    pat.set_format(fmt)
+    kw = dict(method="cg_sr", precond=precond, rtol=1e-12, persistent=False)
+    x, info, st = solve(a, b, pat=pat, **kw)
+    ref = orc.cg(a, b, precond=precond, rtol=1e-12)
+    assert st == 0 and info[0]["method"] == "cg_sr", info
+    assert info[0]["spmv_form"] != "persistent"
+    assert rel(x, ref.x) <= 1e-8
+    assert iters_close(info[0]["iters"], ref.iters), (info[0]["iters"], ref.iters)
+    assert info[0]["true_residual"] <= 5e-12
+    xg, _, _ = solve(a, b, pat=pat, graph=False, **kw)
+    assert np.array_equal(x, xg)
+    # a batch: each member is its own solve
+    V = np.stack([a.val, W.diffusion3d_values(m, W.diffusion3d_kappa(m, sample=1)), a.val])
+    bs = np.stack([r.standard_normal(a.n), b, b])
+    xb, ib, sb = _lib.solve(pat, t64(V), t64(bs), _lib.make_opts(**kw))
+    assert sb == 0 and np.array_equal(xb[2].cpu().numpy(), x)
+    ref1 = orc.cg(a.with_values(V[1]), b, precond=precond, rtol=1e-12)
+    assert rel(xb[1].cpu().numpy(), ref1.x) <= 1e-8 and iters_close(ib[1]["iters"], ref1.iters)
+    # the k-th iterate of a capped run is CG's k-th iterate
+    for k in (1, 2, 7):
+        xk, ik, sk = solve(a, b, pat=pat, **dict(kw, max_iter=k))
+        refk = orc.cg(a, b, precond=precond, rtol=1e-12, max_iter=k)
+        assert sk == _lib.NOT_CONVERGED and ik[0]["iters"] == k and rel(xk, refk.x) <= 1e-10, (k, rel(xk, refk.x))
+    _, _, st = solve(a, b, pat=pat, values=t64(-a.val), **dict(kw, precond="none"))
+    assert st == _lib.BREAKDOWN
+    x0, i0, st = solve(a, np.zeros(a.n), pat=pat, **kw)
+    assert st == 0 and i0[0]["iters"] == 0 and not x0.any()
+
+
+def test_cg_single_reduction_fsai_runs_cg(orc):
+    """FSAI preconditioning keeps the two-reduction recurrence and says so."""
+    from oracle import mpnn
+    pa, slots = W.aniso_pattern(21)
+    a = pa.with_values(W.aniso_stencil(100.0, 0.4)[slots])
+    rpL, colL, gh = orc.fsai(mpnn.scaled(a))
+    pat = pattern(a)
+    G, GT = _lib.fsai_factors(pat, t64(a.val), torch.as_tensor(gh.astype(np.float32)).to(dev()))
+    b = np.random.default_rng(15).standard_normal(a.n)
+    x, info, st = _lib.solve(pat, t64(a.val), t64(b),
+                             _lib.make_opts(method="cg_sr", precond="fsai", rtol=1e-12, G=G, GT=GT))
     assert st == 0 and info[0]["method"] == "cg"
-    assert rel(x, orc.cg(a, b, precond="jacobi", rtol=1e-12).x) <= 1e-8
+    ref = orc.fsai_pcg(a, rpL, colL, G.cpu().numpy().astype(np.float64), b, rtol=1e-12)
+    assert rel(x.cpu().numpy(), ref.x) <= 1e-8
