@@ -291,6 +291,27 @@ hsla_status hsla_solve_batched(hsla_handle *h, const hsla_pattern *p, int32_t B,
                                const double *d_values, const double *d_b, double *d_x,
                                const hsla_opts *opts, hsla_info *infos, void *stream);
 
+/* For callers that cannot allocate device memory during a call (serving
+ * loops that must not call hipMalloc, harnesses that forbid it): the same
+ * solve as hsla_solve_batched -- same kernels, same results bit for bit as
+ * a call of hsla_solve_batched with use_graph = 0 -- with the workspace
+ * (state records, partials, work vectors, diagonal-major copies) taken from
+ * a 64 MiB array that the library holds on each device it runs on until
+ * the process ends, instead of from the handle's workspace.  The call
+ * allocates no device memory and instantiates no graph (iterations are
+ * launched one by one; opts->use_graph is ignored).  B may be 0..1024.  A
+ * solve whose workspace would exceed the array (hsla_workspace_size tells
+ * what a solve takes), B beyond 1024, or opts->profile set returns
+ * HSLA_ERR_INVALID_ARG with the sizes in hsla_last_error, without writing
+ * x.  Every such call on one device shares that device's
+ * array, which keeps the last call's contents (nothing in it needs to
+ * start at zero): calls that overlap on one device -- from several threads,
+ * or on handles whose streams are not ordered -- race and must not be
+ * made. */
+hsla_status hsla_solve_noalloc(hsla_handle *h, const hsla_pattern *p, int32_t B, const double *d_values,
+                               const double *d_b, double *d_x, const hsla_opts *opts, hsla_info *infos,
+                               void *stream);
+
 /* Adjoint of the solve (Eq. adjoint_linear): solves A^T lambda = gx with the
  * options' method/preconditioner/tolerance (relative to ||gx||), then
  * gb = lambda (float64[n]) and gA[k] = -lambda[row(k)] * x[col(k)] for every

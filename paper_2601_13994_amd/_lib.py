@@ -36,7 +36,7 @@ EXPORTS = [
     "hsla_spmv", "hsla_solve", "hsla_solve_batched", "hsla_adjoint", "hsla_adjoint_batched",
     "hsla_outer_on_pattern", "hsla_residual_norms",
     "hsla_mpnn_num_params", "hsla_mpnn_forward", "hsla_mpnn_backward", "hsla_probe_loss", "hsla_adam_step",
-    "hsla_fsai_factors", "hsla_solve_ragged",
+    "hsla_fsai_factors", "hsla_solve_ragged", "hsla_solve_noalloc",
 ]
 
 
@@ -153,6 +153,7 @@ def load() -> ctypes.CDLL:
                                      ctypes.c_float, i64, vp]
         L.hsla_fsai_factors.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
         L.hsla_solve_ragged.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, P(Opts), P(Info), vp]
+        L.hsla_solve_noalloc.argtypes = [vp, vp, i32, vp, vp, vp, P(Opts), P(Info), vp]
         _lib = L
     return _lib
 
@@ -438,6 +439,25 @@ def solve(pat: Pattern, values: torch.Tensor, b: torch.Tensor, opts: Opts, x0: t
                                        infos, stream_ptr(pat.device))
         check(st, pat.h, "hsla_solve")
     return x, [infos[i].as_dict() for i in range(B)], st
+
+
+def solve_noalloc(pat: Pattern, values: torch.Tensor, b: torch.Tensor, x: torch.Tensor, opts: Opts):
+    """hsla_solve_noalloc into the caller's x (same shape as b); returns
+    ([info dicts], status).  The library allocates no device memory."""
+    values = need(values, torch.float64, "values", pat.device)
+    b = need(b, torch.float64, "b", pat.device)
+    if not x.is_contiguous():
+        raise ValueError("x must be contiguous (the solve writes into it)")
+    x = need(x, torch.float64, "x", pat.device)
+    B = _batch(values, pat.nnz)
+    if b.numel() != B * pat.n or x.numel() != B * pat.n:
+        raise ValueError("b or x does not match the batch and pattern")
+    infos = (Info * max(B, 1))()
+    with torch.cuda.device(pat.device):
+        st = load().hsla_solve_noalloc(pat.h, pat.p, B, ptr(values), ptr(b), ptr(x), ctypes.byref(opts), infos,
+                                       stream_ptr(pat.device))
+        check(st, pat.h, "hsla_solve_noalloc")
+    return [infos[i].as_dict() for i in range(B)], st
 
 
 def adjoint(pat: Pattern, values: torch.Tensor, x: torch.Tensor, gx: torch.Tensor, opts: Opts,

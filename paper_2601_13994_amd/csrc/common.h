@@ -19,6 +19,10 @@ constexpr int kTileRows = 64;           // rows per SpMV tile: one lane per row
 constexpr int kTileCap = 512;           // max stored entries staged per tile (LDS, per wave)
 constexpr int kXcds = 8;                // MI355X: 8 XCDs, blocks dispatched round-robin
 constexpr int kMaxOffsets = 16;         // distinct column offsets of a stencil pattern
+// allocation-free solves: size of the per-device static scratch array, and
+// the most systems one such call takes (host state mirror sized at creation)
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kNoAllocMaxSystems = 1024;
 
 // Offset-mask form of a CSR pattern whose entries all lie on a few fixed
 // diagonals (structured-grid stencils): column = row + ofs[s] for every set
@@ -198,6 +202,10 @@ struct hsla_handle {
     std::string last_error;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    // set while a call runs on the device-resident scratch array instead of
+    // the handle's workspace: ensure_workspace and ensure_host_state then
+    // allocate nothing and reject sizes beyond what is there
+    bool ws_fixed = false;
     hsla::SysState *h_state = nullptr;  // pinned host mirror
     size_t h_state_cap = 0;
     // cached HIP graphs of iteration chunks (small LRU by launch arguments)
@@ -250,6 +258,13 @@ hsla_status ensure_workspace(hsla_handle *h, size_t bytes);
 hipError_t dev_alloc(hsla_handle *h, void **p, size_t bytes);
 void dev_free(hsla_handle *h, void *p);
 hsla_status ensure_host_state(hsla_handle *h, size_t nsys);
+
+// Shared-pattern solve of B systems (hsla_solve / hsla_solve_batched).
+hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const double *values, const double *b,
+                        double *x, const hsla_opts *opts, hsla_info *infos, hipStream_t user);
+// Looks up this device's copy of the library's static scratch array (once per
+// device; the device must be current).  Called by hsla_create.
+hsla_status scratch_init(hsla_handle *h);
 
 // Blocks per system for grid-stride kernels: enough for `units` work items
 // at `per_block` each, at most `per_cu` blocks per CU, a multiple of kXcds.

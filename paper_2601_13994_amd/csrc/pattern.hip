@@ -39,6 +39,10 @@ void dev_free(hsla_handle *h, void *p) {
 
 hsla_status ensure_workspace(hsla_handle *h, size_t bytes) {
     if (bytes <= h->ws_bytes) return HSLA_OK;
+    if (h->ws_fixed)
+        return set_error(h, HSLA_ERR_INVALID_ARG,
+                         "this call needs %zu bytes of scratch; the allocation-free entry point has %zu", bytes,
+                         h->ws_bytes);
     if (h->ws) {
         HSLA_HIP(h, hipDeviceSynchronize());
         dev_free(h, h->ws);
@@ -74,6 +78,9 @@ hsla_status enter(hsla_handle *h, hipStream_t user) {
 
 hsla_status ensure_host_state(hsla_handle *h, size_t nsys) {
     if (nsys <= h->h_state_cap) return HSLA_OK;
+    if (h->ws_fixed)
+        return set_error(h, HSLA_ERR_INVALID_ARG, "%zu systems exceed the %zu the allocation-free entry point takes",
+                         nsys, h->h_state_cap);
     if (h->h_state) HSLA_HIP(h, hipHostFree(h->h_state));
     h->h_state = nullptr;
     HSLA_HIP(h, hipHostMalloc((void **)&h->h_state, nsys * sizeof(SysState), hipHostMallocDefault));
@@ -668,6 +675,15 @@ hsla_status hsla_create(hsla_handle **out, int device) {
         hsla_destroy(h);
         return HSLA_ERR_HIP;
     }
+    // a host mirror of the per-system state large enough for the
+    // allocation-free entry point's batches, and that entry point's scratch
+    // array on this device (a failed lookup is retried, and reported, by
+    // that entry point's first call)
+    if (hsla::ensure_host_state(h, hsla::kNoAllocMaxSystems) != HSLA_OK) {
+        hsla_destroy(h);
+        return HSLA_ERR_HIP;
+    }
+    (void)hsla::scratch_init(h);
     *out = h;
     return HSLA_OK;
 }
