@@ -11,14 +11,18 @@ before the timed region starts.
 Prints one JSON line on stdout (progress goes to stderr):
   value      solves/s (whole job, one GPU)
   roofline   the dominant kernel (SpMV fused with p.q) against HBM peak:
-             achieved = algorithmic bytes per launch / mean launch duration,
-             durations from HIP events around every launch of the timed
-             solves; traffic = FETCH_SIZE + WRITE_SIZE per launch from the
-             committed rocprofv3 counter summary (null if the kernel source
-             changed since the counters were taken)
-  cpu_baseline  the CPU oracle (single thread) timed on a bounded sample of
-             the same system: a few PCG iterations, scaled by the GPU solve's
-             iteration count
+             achieved = algorithmic bytes per launch of the stored form the
+             kernel streams / mean launch duration, durations from HIP events
+             around every SpMV launch of profiled solves run right after the
+             timed region (the timed solves replay graphs and carry no
+             events); survey_unit prices the same launches at the CSR SpMV
+             unit 12 nnz + 4(n+1) + 16n; traffic = FETCH_SIZE + WRITE_SIZE
+             per launch from the committed rocprofv3 counter summary (null if
+             the kernel source changed since the counters were taken)
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same system
+             on all host cores (threaded mode) and on one thread: the
+             difference of a short and a longer capped PCG run, scaled by the
+             GPU solve's iteration count
 
 Other modes:
   --summarize-rocprof DIR --label NAME   turn rocprofv3 output into a text
@@ -44,6 +48,7 @@ METRIC = "solves/s to rtol 1e-8, learned-FSAI vs Jacobi PCG; SpMV/CG HBM GB/s vs
 HBM_PEAK_GBPS = 8000.0
 DOMINANT = "k_cg_spmv_dot"
 COUNTER_FILE = os.path.join(ROOT, "profiles", "k_cg_spmv_dot_diffusion3d_256_counters.json")
+CSR_COUNTER_FILE = os.path.join(ROOT, "profiles", "k_cg_spmv_dot_csr_diffusion3d_256_counters.json")
 KERNEL_SOURCES = ["paper_2601_13994_amd/csrc/krylov.hip", "paper_2601_13994_amd/csrc/common.h"]
 
 
@@ -123,40 +128,71 @@ def cpu_info() -> str:
     return platform.processor() or "unknown"
 
 
-def load_traffic(n: int, nnz: int):
+def load_traffic(n: int, nnz: int, path: str = COUNTER_FILE):
     """Per-launch HBM bytes of the dominant kernel from the committed
     counter summary, scaled by the copy-kernel calibration; None if absent
     or taken on different kernel source."""
-    if not os.path.exists(COUNTER_FILE):
+    if not os.path.exists(path):
         return None
-    with open(COUNTER_FILE) as f:
+    with open(path) as f:
         d = json.load(f)
     if d.get("kernel_source_hash") != kernel_source_hash() or d.get("n") != n or d.get("nnz") != nnz:
         return None
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(a, b, gpu_iters: int, k1: int = 1, k2: int = 31):
+def host_threads() -> int:
+    """Host threads the CPU oracle may use: the CPUs this process may run on,
+    at most 16 (the host share of one GPU on the measurement machine)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_rate(run, k1: int, k2: int):
+    """Seconds per iteration and set-up seconds of an oracle solver from the
+    difference of a k1- and a k2-iteration capped run."""
+    t0 = time.perf_counter()
+    run(k1)
+    t1 = time.perf_counter()
+    run(k2)
+    t2 = time.perf_counter()
+    per_it = ((t2 - t1) - (t1 - t0)) / (k2 - k1)
+    return per_it, max(0.0, (t1 - t0) - k1 * per_it)
+
+
+def cpu_baseline(a, b, gpu_iters: int):
+    """The oracle's Jacobi-PCG on the headline system: all host cores
+    (value) and one thread, each from a capped-run difference scaled to the
+    GPU solve's iteration count."""
     import oracle
 
     oracle.lib()
-    t0 = time.perf_counter()
-    oracle.cg(a, b, precond="jacobi", rtol=1e-8, max_iter=k1)
-    t1 = time.perf_counter()
-    oracle.cg(a, b, precond="jacobi", rtol=1e-8, max_iter=k2)
-    t2 = time.perf_counter()
-    per_it = ((t2 - t1) - (t1 - t0)) / (k2 - k1)
-    setup = (t1 - t0) - k1 * per_it
-    solve_s = setup + gpu_iters * per_it
+    cores = host_threads()
+
+    def run(k):
+        oracle.cg(a, b, precond="jacobi", rtol=1e-8, max_iter=k)
+
+    with oracle.threads(cores):
+        per_all, setup_all = _oracle_rate(run, 1, 61)
+    with oracle.threads(1):
+        per_one, setup_one = _oracle_rate(run, 1, 11)
+    all_s = setup_all + gpu_iters * per_all
+    one_s = setup_one + gpu_iters * per_one
     return {
-        "value": 1.0 / solve_s,
+        "value": 1.0 / all_s,
         "unit": "solves/s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"{k2 - k1} Jacobi-PCG iterations of the same 256^3 system (difference of {k2}- and "
-                   f"{k1}-iteration runs: {per_it:.3f} s/iteration, {setup:.2f} s set-up), scaled to the "
-                   f"GPU solve's {gpu_iters} iterations; sequential FP64 C, {cpu_info()}"),
-        "seconds_per_iteration": per_it,
+        "sample": (f"60 Jacobi-PCG iterations of the same 256^3 system on {cores} threads (difference of 61- and "
+                   f"1-iteration runs: {per_all * 1e3:.1f} ms/iteration, {setup_all:.2f} s set-up), scaled to the "
+                   f"GPU solve's {gpu_iters} iterations; FP64 C with OpenMP over rows and per-thread partial sums, "
+                   f"{cpu_info()}"),
+        "seconds_per_iteration": per_all,
+        "one_thread": {"value": 1.0 / one_s, "unit": "solves/s", "cores": 1, "seconds_per_iteration": per_one,
+                       "sample": "10 iterations (difference of 11- and 1-iteration runs), same scaling"},
         "host_cpus": os.cpu_count(),
     }
 
@@ -237,9 +273,32 @@ def _pattern(dev, a):
     return _lib.Pattern(torch.as_tensor(a.row_ptr).to(dev), torch.as_tensor(a.col).to(dev))
 
 
+def _profiled_spmv(pat, vals, bt, opts_kw, solves: int):
+    """Mean duration of the SpMV(+dot) launches that did work, from HIP
+    events the library records around each of them on its stream (profile
+    mode: graphs off), over `solves` full solves."""
+    from paper_2601_13994_amd import _lib
+
+    opts = _lib.make_opts(profile=True, **opts_kw)
+    ms, launches, info = 0.0, 0, None
+    for _ in range(solves):
+        _, infos, _ = _lib.solve(pat, vals, bt, opts)
+        info = infos[0]
+        ms += info["spmv_ms"]
+        launches += info["spmv_launches"]
+    return ms / max(launches, 1), launches, info
+
+
+def survey_spmv_bytes(n: int, nnz: int) -> int:
+    """The scope table's SpMV unit: CSR values, int32 column indices and row
+    pointers, p gathered once and q written once."""
+    return 12 * nnz + 4 * (n + 1) + 16 * n
+
+
 def run_diffusion(ctx, args, dev, pat, vals, bt):
     """Workload 2: Jacobi-PCG on the 256^3 log-normal diffusion system (the
-    headline line: value, roofline, CPU baseline)."""
+    headline line: value, roofline, CPU baseline), plus the same solve on the
+    plain CSR form."""
     from paper_2601_13994_amd import _lib
 
     a, b = ctx["d3"]
@@ -249,12 +308,12 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
     tune_ms = (time.perf_counter() - t0) * 1e3
     if tuning:
         log(f"[bench] autotune: {tuning}")
-    opts_w = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-8, max_iter=args.max_iter)
+    kw = dict(method="cg", precond="jacobi", rtol=1e-8, max_iter=args.max_iter)
+    opts = _lib.make_opts(**kw)  # the production path: graph-replayed iteration chunks
     for i in range(args.warmup):
-        x, infos, st = _lib.solve(pat, vals, bt, opts_w)
+        x, infos, st = _lib.solve(pat, vals, bt, opts)
         log(f"[bench] diffusion3d warmup {i}: status={st} iters={infos[0]['iters']} "
             f"true_res={infos[0]['true_residual']:.2e}")
-    opts = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-8, max_iter=args.max_iter, profile=True)
     _sync()
     t0 = time.perf_counter()
     recs = []
@@ -265,14 +324,14 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
     _sync()
     elapsed = time.perf_counter() - t0
     iters = recs[-1]["iters"]
-    spmv_ms = sum(r["spmv_ms"] for r in recs)
-    launches = sum(r["spmv_launches"] for r in recs)
-    avg_ms = spmv_ms / max(launches, 1)
+    ms_step = elapsed / args.steps * 1e3
+    # the dominant kernel's launch time, from profiled solves of the same system
+    avg_ms, launches, pinfo = _profiled_spmv(pat, vals, bt, kw, args.profile_solves)
     stencil, nofs = pat.stencil
-    form = form_of(recs[-1], pat)
+    form = form_of(pinfo, pat)
     bytes_launch = spmv_bytes(n, nnz, form, nofs)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    ms_step = elapsed / args.steps * 1e3
+    unit_bytes = survey_spmv_bytes(n, nnz)
     it_bytes = bytes_launch + 72 * n
     csr_it_bytes = pcg_iteration_bytes(n, nnz, 0)
     top = {
@@ -301,10 +360,19 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": load_traffic(n, nnz),
+            "bytes_model": "stored form: " + form_text(form, nofs) + ", p gathered once, q written once",
             "algorithmic_bytes_per_launch": bytes_launch,
             "mean_launch_ms": avg_ms,
             "launches_timed": launches,
-            "format": form_text(form, nofs),
+            "launch_timing": (f"HIP events around every SpMV launch of {args.profile_solves} profiled solve(s) of "
+                              "the same system run after the timed region"),
+            "survey_unit": {
+                "bytes_per_launch": unit_bytes,
+                "achieved_GBps": unit_bytes / (avg_ms * 1e-3) / 1e9,
+                "frac": unit_bytes / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                "note": ("work-equivalent rate: the same launches priced at the CSR SpMV unit "
+                         "12 nnz + 4(n+1) + 16n; above the peak because the stored form streams fewer bytes"),
+            },
             "full_copy_equivalent_GBps": (spmv_bytes(n, nnz, "diagonal", nofs) / (avg_ms * 1e-3) / 1e9
                                           if stencil else None),
         },
@@ -317,15 +385,55 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "iteration_frac_of_peak": it_bytes * iters / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS,
             "GFLOPs": (2 * nnz + 13 * n) * iters / (ms_step * 1e-3) / 1e9,
             "algorithmic_bytes_per_iteration": it_bytes,
-            "spmv_share_of_step": spmv_ms / args.steps / ms_step,
+            "spmv_share_of_step": avg_ms * iters / ms_step,
             "spmv_form": recs[-1]["spmv_form"],
             "setup_excluded_ms": {"pattern": ctx.get("setup_ms"), "autotune": tune_ms if tuning else None},
             "autotune": tuning,
-            "csr_bytes_per_iteration": csr_it_bytes,
-            "csr_equivalent_iteration_GBps": csr_it_bytes * iters / (ms_step * 1e-3) / 1e9,
+            "survey_bytes_per_iteration": csr_it_bytes,
+            "survey_equivalent_iteration_GBps": csr_it_bytes * iters / (ms_step * 1e-3) / 1e9,
         },
     }
+    if args.csr_line:
+        top["csr_path"] = run_diffusion_csr(pat, vals, bt, kw, n, nnz, args)
     return top, iters
+
+
+def run_diffusion_csr(pat, vals, bt, kw, n, nnz, args):
+    """The same Jacobi-PCG solve with the pattern forced to plain CSR (row
+    tiles with int32 column indices; S A S values scaled once into a CSR
+    copy): the unstructured-SpMV path, whose SpMV moves exactly the scope
+    table's unit."""
+    from paper_2601_13994_amd import _lib
+
+    pat.set_format("csr")
+    try:
+        opts = _lib.make_opts(**kw)
+        _lib.solve(pat, vals, bt, opts)
+        _sync()
+        t0 = time.perf_counter()
+        reps = max(1, args.sub_steps)
+        for _ in range(reps):
+            _, infos, st = _lib.solve(pat, vals, bt, opts)
+        _sync()
+        dt = (time.perf_counter() - t0) / reps
+        avg_ms, launches, _ = _profiled_spmv(pat, vals, bt, kw, 1)
+    finally:
+        pat.set_format("auto")
+    it = infos[0]["iters"]
+    ub = survey_spmv_bytes(n, nnz)
+    it_bytes = ub + 72 * n
+    return {
+        "workload": "the headline system with the CSR form forced (k_cg_spmv_dot<0>)",
+        "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iterations": it, "status": st,
+        "true_relative_residual": infos[0]["true_residual"], "spmv_form": infos[0]["spmv_form"],
+        "spmv_mean_launch_ms": avg_ms, "spmv_launches_timed": launches, "spmv_bytes_per_launch": ub,
+        "spmv_GBps": ub / (avg_ms * 1e-3) / 1e9, "spmv_frac_of_peak": ub / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "ms_per_iteration": dt * 1e3 / max(it, 1),
+        "iteration_model_GBps": it_bytes * it / dt / 1e9,
+        "iteration_frac_of_peak": it_bytes * it / dt / 1e9 / HBM_PEAK_GBPS,
+        "algorithmic_bytes_per_iteration": it_bytes, "reps": reps,
+        "traffic": load_traffic(n, nnz, CSR_COUNTER_FILE),
+    }
 
 
 def run_bicgstab(ctx, args, dev, pat):
@@ -362,7 +470,28 @@ def run_bicgstab(ctx, args, dev, pat):
         "iteration_frac_of_peak": it_bytes * it / dt / 1e9 / HBM_PEAK_GBPS,
         "GFLOPs": (4 * nnz + 26 * n) * it / dt / 1e9,
         "algorithmic_bytes_per_iteration": it_bytes, "spmv_form": infos[0]["spmv_form"], "reps": args.sub_steps,
+        **(oracle_bicgstab(ctx, it) if not args.no_cpu_baseline else {}),
     }
+
+
+def oracle_bicgstab(ctx, gpu_iters):
+    """The oracle's Jacobi-BiCGStab on the same system, all host cores, from
+    a capped-run difference scaled to the GPU's iteration count."""
+    import oracle
+
+    a, b = ctx["d3"]
+    ac = a.with_values(ctx["d3_conv_val"])
+    cores = host_threads()
+
+    def run(k):
+        oracle.bicgstab(ac, b, precond="jacobi", rtol=1e-8, max_iter=k)
+
+    oracle.lib()
+    with oracle.threads(cores):
+        per, setup = _oracle_rate(run, 1, 21)
+    return {"oracle_solves_per_s": 1.0 / (setup + gpu_iters * per), "oracle_cores": cores,
+            "oracle_sample": (f"20 iterations on {cores} threads (difference of 21- and 1-iteration runs: "
+                              f"{per * 1e3:.1f} ms/iteration), scaled to the GPU's {gpu_iters} iterations")}
 
 
 def run_poisson(ctx, args, dev):
@@ -472,6 +601,29 @@ def run_knn(ctx, args, dev):
     its = np.array([f["iters"] for f in infos])
     ns = np.array([a.n for a, _ in systems])
     nnzs = np.array([a.nnz for a, _ in systems])
+    # the same batch in one persistent launch (workgroups take systems from a
+    # longest-first queue): time and load balance from the device clock
+    L.solve(bcat, rtol=1e-8, persistent="force")
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.sub_steps):
+        _, pinfos, pst = L.solve(bcat, rtol=1e-8, persistent="force")
+    _sync()
+    dtp = (time.perf_counter() - t0) / args.sub_steps
+    wg = pinfos[0]["workgroups"]
+    busy = sum(f["t_end_ms"] - f["t_start_ms"] for f in pinfos)
+    wall = max(f["t_end_ms"] for f in pinfos)
+    pits = np.array([f["iters"] for f in pinfos])
+    pwork = float(((12 * nnzs + 4 * (ns + 1) + 104 * ns) * pits).sum())
+    persistent = {
+        "solves_per_s": len(systems) / dtp, "ms_per_batch": dtp * 1e3, "status": pst, "workgroups": wg,
+        "kernel_wall_ms": wall, "load_balance_efficiency": busy / (wg * wall) if wall > 0 else None,
+        "load_balance_definition": ("sum over systems of (end - start) on the workgroup that ran it / "
+                                    "(workgroups x kernel wall), device wall clock"),
+        "model_GBps": pwork / dtp / 1e9, "model_frac_of_peak": pwork / dtp / 1e9 / HBM_PEAK_GBPS,
+        "iterations_mean": float(pits.mean()),
+        "true_relative_residual_max": max(f["true_residual"] for f in pinfos),
+    }
     # per system per iteration: CSR once, p gathered and q written (16n), and
     # the vector updates: 88n in the persistent kernel, 80n in the
     # segmented path (x += alpha p folded into the direction sweep)
@@ -486,21 +638,23 @@ def run_knn(ctx, args, dev):
         "iterations_mean": float(its.mean()), "iterations_max": int(its.max()),
         "true_relative_residual_max": max(f["true_residual"] for f in infos),
         "model_GBps": work / dt / 1e9, "model_frac_of_peak": work / dt / 1e9 / HBM_PEAK_GBPS,
-        "reps": args.sub_steps,
+        "reps": args.sub_steps, "persistent_launch": persistent,
     }
     if not args.no_cpu_baseline:
+        import concurrent.futures as cf
+
         oracle.lib()
-        k = 8
-        t0 = time.perf_counter()
-        for a, b in systems[:k]:
-            oracle.cg(a, b, precond="jacobi", rtol=1e-8)
-        dto = time.perf_counter() - t0
-        w_all = float((nnzs * its).sum())
-        w_k = float((nnzs[:k] * its[:k]).sum())
-        res["oracle_solves_per_s"] = len(systems) * w_k / (dto * w_all)
-        res["oracle_sample"] = (f"first {k} systems solved one after another on 1 core ({dto:.2f} s); the batch "
-                                "rate assumes time proportional to nnz x iterations per system")
-        res["oracle_cores"] = 1
+        cores = host_threads()
+        order = sorted(range(len(systems)), key=lambda i: -systems[i][0].nnz)  # longest first
+        with oracle.threads(1):
+            t0 = time.perf_counter()
+            with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+                list(ex.map(lambda i: oracle.cg(systems[i][0], systems[i][1], precond="jacobi", rtol=1e-8), order))
+            dto = time.perf_counter() - t0
+        res["oracle_solves_per_s"] = len(systems) / dto
+        res["oracle_sample"] = (f"all {len(systems)} systems, one system per thread on {cores} threads, longest "
+                                f"first ({dto:.2f} s)")
+        res["oracle_cores"] = cores
     return res
 
 
@@ -558,7 +712,28 @@ def run_adjoint(ctx, args, dev):
         "true_relative_residual_max": max(max(f["true_residual"] for f in fi), max(f["true_residual"] for f in bi)),
         "model_GBps": work / dt / 1e9, "model_frac_of_peak": work / dt / 1e9 / HBM_PEAK_GBPS,
         "reps": args.sub_steps,
+        **(oracle_adjoint(ctx, args.oracle_adj_systems) if not args.no_cpu_baseline else {}),
     }
+
+
+def oracle_adjoint(ctx, k):
+    """The oracle's forward Jacobi-PCG plus adjoint (gradients w.r.t. b and
+    every stored value) on the first k systems of the batch, all host
+    cores, one system after another."""
+    import oracle
+
+    a0, V, Bs, Xs = ctx["adj"]
+    cores = host_threads()
+    oracle.lib()
+    with oracle.threads(cores):
+        t0 = time.perf_counter()
+        for s in range(k):
+            a = a0.with_values(V[s])
+            x = oracle.cg(a, Bs[s], precond="jacobi", rtol=1e-8).x
+            oracle.adjoint(a, x, x - Xs[s], precond="jacobi", rtol=1e-8)
+        dto = time.perf_counter() - t0
+    return {"oracle_pairs_per_s": k / dto, "oracle_cores": cores,
+            "oracle_sample": f"forward + adjoint of the first {k} systems, one after another on {cores} threads"}
 
 
 def run_learned(ctx, args, dev):
@@ -585,12 +760,12 @@ def run_learned(ctx, args, dev):
 
     _sync()
     t0 = time.perf_counter()
-    hist = model.train(pat, sample, steps=args.train_steps, probes=args.train_probes, lr=args.train_lr,
-                       lr_final=args.train_lr / 10)
+    hist_loss = model.train(pat, sample, steps=args.train_steps, probes=args.train_probes, lr=args.train_lr,
+                            lr_final=args.train_lr / 10)
     _sync()
     t_train = time.perf_counter() - t0
-    log(f"[bench] learned: trained {args.train_steps} steps in {t_train:.1f}s, loss {np.mean(hist[:5]):.4f} -> "
-        f"{np.mean(hist[-20:]):.4f}")
+    log(f"[bench] learned: trained {args.train_steps} steps in {t_train:.1f}s, loss {np.mean(hist_loss[:5]):.4f} -> "
+        f"{np.mean(hist_loss[-20:]):.4f}")
     V = learned.aniso_batch_values(sl, st_eval)
     bt = torch.as_tensor(ctx["aniso_b"]).to(dev)
     E = V.shape[0]
@@ -619,6 +794,23 @@ def run_learned(ctx, args, dev):
     itj = np.array([f["iters"] for f in ij])
     itl = np.array([f["iters"] for f in il])
     fell = sum(f["status"] == _lib.FELL_BACK for f in il)
+    edges = np.linspace(min(itl.min(), itj.min()), max(itl.max(), itj.max()) + 1, 13).round().astype(int)
+    hist = {"bin_edges": edges.tolist(), "learned": np.histogram(itl, edges)[0].tolist(),
+            "jacobi": np.histogram(itj, edges)[0].tolist()}
+    # the network's forward alone (matrix-core GEMMs: three 128 -> 64 node
+    # layers and the 132 -> 32 edge head) on the held-out batch
+    params = model.params
+    _lib.mpnn_forward(pat, V, params)
+    _sync()
+    t0 = time.perf_counter()
+    _lib.mpnn_forward(pat, V, params)
+    _sync()
+    t_fwd = time.perf_counter() - t0
+    mfma_flops = E * (3 * 2 * pa.n * 128 * 64 + 2 * pat.nnz_lower * 132 * 32)
+    mfma = {"forward_seconds": t_fwd, "mfma_flops": mfma_flops, "TFLOPs": mfma_flops / t_fwd / 1e12,
+            "peak_TFLOPs_bf16_dense": 2500.0, "frac_of_peak": mfma_flops / t_fwd / 1e12 / 2500.0,
+            "note": ("dense-layer flops only; the forward also gathers neighbour activations and aggregates "
+                     "them on the vector units, which bounds it")}
     return {
         "workload": (f"2D anisotropic diffusion {args.aniso_m}^2 9-point (n={pa.n}, nnz={pa.nnz}), ratio ~ "
                      f"logU[1,1000], angle ~ U[0,pi); network trained on {ntr} generated systems, evaluated on "
@@ -631,9 +823,45 @@ def run_learned(ctx, args, dev):
         "fell_back": int(fell), "status_learned": stl, "status_jacobi": stj, "autotune": tuning,
         "true_relative_residual_max_learned": rel_l, "true_relative_residual_max_jacobi": rel_j,
         "train_seconds": t_train, "train_steps": args.train_steps, "train_batch": args.train_batch,
-        "train_probes": args.train_probes, "train_loss_first": float(np.mean(hist[:5])),
-        "train_loss_last": float(np.mean(hist[-20:])),
+        "train_probes": args.train_probes, "train_loss_first": float(np.mean(hist_loss[:5])),
+        "train_loss_last": float(np.mean(hist_loss[-20:])), "iteration_histogram": hist, "mpnn_forward": mfma,
+        **(oracle_learned(ctx, pa, args.oracle_aniso_systems) if not args.no_cpu_baseline else {}),
     }
+
+
+def oracle_learned(ctx, pa, k):
+    """The oracle on the first k held-out systems, one system per thread:
+    Jacobi-PCG, and classical FSAI-PCG (the textbook factor on A's lower
+    pattern) as a yardstick for the learned factor."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+
+    pat_a, slots = ctx["aniso_pat"]
+    cores = host_threads()
+    oracle.lib()
+    mats = [pat_a.with_values(ctx["aniso_eval"][s][slots]) for s in range(k)]
+    bs = ctx["aniso_b"][:k]
+
+    def jac(s):
+        return oracle.cg(mats[s], bs[s], precond="jacobi", rtol=1e-8).iters
+
+    def fsai(s):
+        rpL, colL, g = oracle.fsai(mats[s])
+        return oracle.fsai_pcg(mats[s], rpL, colL, g, bs[s], rtol=1e-8).iters
+
+    out = {}
+    with oracle.threads(1):
+        for name, fn in (("jacobi", jac), ("classical_fsai", fsai)):
+            t0 = time.perf_counter()
+            with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+                its = list(ex.map(fn, range(k)))
+            dt = time.perf_counter() - t0
+            out[name] = {"solves_per_s": k / dt, "iterations_mean": float(np.mean(its))}
+    return {"oracle": out, "oracle_cores": cores,
+            "oracle_sample": f"first {k} held-out systems, one system per thread on {cores} threads"}
 
 
 def run_paper(ctx, args, dev):
@@ -828,6 +1056,9 @@ def run(args):
         pat = _pattern(dev, a)
         _sync()
         ctx["setup_ms"] = (time.perf_counter() - t0) * 1e3
+        if args.format == "csr":
+            pat.set_format("csr")
+            args.csr_line = False
         log(f"[bench] pattern ready ({ctx['setup_ms']:.1f} ms)")
     if args.calibrate_copy:
         # plain copy kernel of known size for counter calibration (1 GiB read + 1 GiB write)
@@ -937,25 +1168,34 @@ def counters(args):
         scale = (1 << 20) / calib  # true KiB per counted KiB
         vals = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"].split("(")[0].endswith(DOMINANT)
                 or (DOMINANT + "<") in r["Kernel_Name"]]
-        out[tag] = {"kib_per_dispatch": sum(vals) / len(vals), "dispatches": len(vals), "calibration_kib": calib,
-                    "scale": scale, "bytes_per_dispatch": sum(vals) / len(vals) * 1024 * scale}
+        # launches of a graph chunk after the system stopped return at entry;
+        # the per-launch figure is over the launches that did work
+        worked = [v for v in vals if v > 0.1 * max(vals)]
+        out[tag] = {"kib_per_dispatch": sum(worked) / len(worked), "dispatches": len(worked),
+                    "dispatches_returned_at_entry": len(vals) - len(worked), "calibration_kib": calib,
+                    "scale": scale, "bytes_per_dispatch": sum(worked) / len(worked) * 1024 * scale}
     total = out["fetch"]["bytes_per_dispatch"] + out["write"]["bytes_per_dispatch"]
     rec = {"kernel": DOMINANT, "kernel_source_hash": kernel_source_hash(), "n": args.n, "nnz": args.nnz,
-           "bytes_per_launch": total, "fetch": out["fetch"], "write": out["write"], "command": args.command}
-    with open(COUNTER_FILE, "w") as f:
+           "bytes_per_launch": total, "fetch": out["fetch"], "write": out["write"], "command": args.command,
+           "format": args.format}
+    path = CSR_COUNTER_FILE if args.format == "csr" else COUNTER_FILE
+    with open(path, "w") as f:
         json.dump(rec, f, indent=1)
-    md = COUNTER_FILE.replace(".json", ".md")
+    md = path.replace(".json", ".md")
+    what = "CSR form" if args.format == "csr" else "the solve's stored form"
     with open(md, "w") as f:
-        f.write(f"# HBM traffic of {DOMINANT}, diffusion3d 256^3 (rocprofv3 --pmc)\n\n")
+        f.write(f"# HBM traffic of {DOMINANT}, diffusion3d 256^3, {what} (rocprofv3 --pmc)\n\n")
         f.write(f"Commands: `{args.command}`\n\n")
-        f.write("| counter | dispatches | KiB per dispatch | calibration copy KiB (1 GiB copied) | scale | bytes per dispatch |\n")
+        f.write("| counter | dispatches that did work (returned at entry) | KiB per dispatch | calibration copy KiB "
+                "(1 GiB copied) | scale | bytes per dispatch |\n")
         f.write("|---|---|---|---|---|---|\n")
         for tag in ("fetch", "write"):
             o = out[tag]
-            f.write(f"| {tag.upper()}_SIZE | {o['dispatches']} | {o['kib_per_dispatch']:.1f} | "
-                    f"{o['calibration_kib']:.1f} | {o['scale']:.3f} | {o['bytes_per_dispatch']:.4g} |\n")
+            f.write(f"| {tag.upper()}_SIZE | {o['dispatches']} ({o['dispatches_returned_at_entry']}) | "
+                    f"{o['kib_per_dispatch']:.1f} | {o['calibration_kib']:.1f} | {o['scale']:.3f} | "
+                    f"{o['bytes_per_dispatch']:.4g} |\n")
         f.write(f"\nTotal HBM traffic per launch: {total:.4g} bytes (kernel source hash {rec['kernel_source_hash']}).\n")
-    print(COUNTER_FILE)
+    print(path)
 
 
 def main():
@@ -965,6 +1205,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--m", type=int, default=256, help="grid edge (256 is the benchmark size)")
     ap.add_argument("--max-iter", type=int, default=0, help="cap iterations (profiling runs only)")
+    ap.add_argument("--profile-solves", type=int, default=1,
+                    help="profiled solves after the timed region that give the SpMV launch time")
+    ap.add_argument("--no-csr-line", dest="csr_line", action="store_false",
+                    help="skip the headline system's solve on the forced CSR form")
+    ap.add_argument("--format", default="auto", choices=["auto", "csr"],
+                    help="SpMV form of the headline pattern (csr: profiling runs of the CSR kernel)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="skip the SpMV autotuner (set-up, not timed)")
@@ -983,6 +1229,8 @@ def main():
     ap.add_argument("--train-batch", type=int, default=4)
     ap.add_argument("--train-probes", type=int, default=4)
     ap.add_argument("--train-lr", type=float, default=3e-3)
+    ap.add_argument("--oracle-adj-systems", type=int, default=2, help="systems of the oracle's adjoint timing")
+    ap.add_argument("--oracle-aniso-systems", type=int, default=32, help="held-out systems the oracle solves")
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a 1 GiB copy for counter calibration")
     ap.add_argument("--summarize-rocprof", metavar="DIR")
     ap.add_argument("--counters-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),

@@ -61,9 +61,10 @@ typedef enum hsla_status {
  * Conjugate Gradient and Halo Exchange").  It runs with no or Jacobi
  * preconditioning on the per-iteration kernels (three launches per
  * iteration instead of five; one more vector, s = A p, is streamed) and in
- * the persistent small-system kernel (n <= 4096 rows of <= 16 entries);
- * FSAI and the other persistent kernels run it as CG.  hsla_info.method
- * reports which ran. */
+ * the persistent kernels, shared-pattern and ragged (one workgroup
+ * reduction and two passes per iteration instead of two and three); FSAI
+ * and the segmented ragged path run it as CG.  hsla_info.method reports
+ * which ran. */
 typedef enum hsla_method {
     HSLA_METHOD_AUTO = 0,
     HSLA_METHOD_CG = 1,
@@ -93,7 +94,8 @@ typedef struct hsla_opts {
                             on systems of at most 4096 rows of <= 16 entries, or on batches of at
                             least one system per compute unit with at most 131072 entries each,
                             runs as one persistent launch, one workgroup per system;
-                            0: always per-iteration kernels (ragged batches: the segmented path) */
+                            0: always per-iteration kernels (ragged batches: the segmented path);
+                            2: as 1, and ragged batches always run in one persistent launch     */
     int32_t stall_window;/* > 0: a system whose recursive ||r_k|| has not fallen by 10x within
                             stall_window iterations (counted from the start or from the last
                             iteration where it had) stops with HSLA_STAGNATED, e.g. so that a
@@ -121,6 +123,12 @@ typedef struct hsla_info {
                              or 9 diagonals with offsets -1, 0, +1 in the middle, every
                              other offset even and n even; that layout reads no row masks
                              (absent entries are stored as 0).  0 otherwise              */
+    double t_start_ms;    /* persistent launches (spmv_form 3): when the workgroup that ran
+                             this system began it and ended it, on the device clock, in ms
+                             after the earliest start in the launch; 0 elsewhere          */
+    double t_end_ms;
+    int32_t workgroups;   /* persistent launches: workgroups the launch started; 0 elsewhere */
+    int32_t reserved;
 } hsla_info;
 
 void hsla_opts_default(hsla_opts *opts);
@@ -178,6 +186,15 @@ enum { HSLA_PATTERN_CSR = 1u };
 hsla_status hsla_pattern_create(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *d_row_ptr,
                                 const int32_t *d_col, uint32_t flags, void *stream, hsla_pattern **out);
 void hsla_pattern_destroy(hsla_pattern *p);
+/* The rule hsla_pattern_create applies, on host memory and without a
+ * device (e.g. to check a pattern before uploading it): row_ptr
+ * int32[n+1] and col int32[nnz] are host pointers.  HSLA_OK if canonical;
+ * HSLA_ERR_INVALID_CSR with *bad_row (nullable) = the first row that breaks
+ * it, or -1 when row_ptr[0] != 0 or row_ptr[n] != nnz (checked first, so
+ * every row's range is read only after its bounds are known to lie in
+ * [0, nnz]); HSLA_ERR_INVALID_ARG for n < 0, nnz out of [0, 2^31 - 1) or a
+ * null pointer. */
+hsla_status hsla_csr_check(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col, int32_t *bad_row);
 /* n, nnz, nnz of the lower triangle (incl. diagonal), and 1 if the pattern
  * equals its transpose. */
 hsla_status hsla_pattern_info(const hsla_pattern *p, int32_t *n, int64_t *nnz, int64_t *nnz_lower,

@@ -156,11 +156,11 @@ class SparseCSRList:
         return list(torch.split(v, self.n))
 
     def solve(self, bs, rtol: float = 1e-8, atol: float = 0.0, precond: str = "jacobi", max_iter: int = 0,
-              persistent: bool = True):
+              persistent: bool | str = True):
         """Solves every system; `bs` is a list of right-hand sides or their
         concatenation.  persistent=False always takes the segmented
-        per-iteration path (large batches take it anyway).  Returns (list of
-        x, infos, status)."""
+        per-iteration path (large batches take it anyway); "force" always the
+        persistent launch.  Returns (list of x, infos, status)."""
         b = torch.cat(list(bs)) if isinstance(bs, (list, tuple)) else bs
         opts = _lib.make_opts(method="cg", precond=precond, rtol=rtol, atol=atol, max_iter=max_iter,
                               persistent=persistent)

@@ -36,7 +36,7 @@ EXPORTS = [
     "hsla_spmv", "hsla_solve", "hsla_solve_batched", "hsla_adjoint", "hsla_adjoint_batched",
     "hsla_outer_on_pattern", "hsla_residual_norms",
     "hsla_mpnn_num_params", "hsla_mpnn_forward", "hsla_mpnn_backward", "hsla_probe_loss", "hsla_adam_step",
-    "hsla_fsai_factors", "hsla_solve_ragged", "hsla_solve_noalloc",
+    "hsla_fsai_factors", "hsla_solve_ragged", "hsla_solve_noalloc", "hsla_csr_check",
 ]
 
 
@@ -76,13 +76,16 @@ class Info(ctypes.Structure):
         ("rel_residual", ctypes.c_double), ("true_residual", ctypes.c_double),
         ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int64),
         ("spmv_form", ctypes.c_int32), ("spmv_paired", ctypes.c_int32),
+        ("t_start_ms", ctypes.c_double), ("t_end_ms", ctypes.c_double),
+        ("workgroups", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {"iters": self.iters, "status": self.status, "method": METHOD_NAMES.get(self.method, "?"),
                 "rel_residual": self.rel_residual, "true_residual": self.true_residual,
                 "spmv_ms": self.spmv_ms, "spmv_launches": self.spmv_launches,
-                "spmv_form": SPMV_FORMS.get(self.spmv_form, "?"), "spmv_paired": bool(self.spmv_paired)}
+                "spmv_form": SPMV_FORMS.get(self.spmv_form, "?"), "spmv_paired": bool(self.spmv_paired),
+                "t_start_ms": self.t_start_ms, "t_end_ms": self.t_end_ms, "workgroups": self.workgroups}
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -154,6 +157,7 @@ def load() -> ctypes.CDLL:
         L.hsla_fsai_factors.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
         L.hsla_solve_ragged.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, P(Opts), P(Info), vp]
         L.hsla_solve_noalloc.argtypes = [vp, vp, i32, vp, vp, vp, P(Opts), P(Info), vp]
+        L.hsla_csr_check.argtypes = [i32, i64, vp, vp, P(i32)]
         _lib = L
     return _lib
 
@@ -263,7 +267,7 @@ def make_opts(method="auto", precond="jacobi", rtol=1e-8, atol=0.0, max_iter=0, 
     o.profile = int(bool(profile))
     o.d_G = G.data_ptr() if G is not None else None
     o.d_GT = GT.data_ptr() if GT is not None else None
-    o.persistent = int(bool(persistent))
+    o.persistent = 2 if persistent == "force" else int(bool(persistent))
     o.stall_window = int(stall_window or 0)
     return o
 
@@ -439,6 +443,19 @@ def solve(pat: Pattern, values: torch.Tensor, b: torch.Tensor, opts: Opts, x0: t
                                        infos, stream_ptr(pat.device))
         check(st, pat.h, "hsla_solve")
     return x, [infos[i].as_dict() for i in range(B)], st
+
+
+def csr_check(row_ptr, col, n: int | None = None):
+    """hsla_csr_check on host arrays: (status, first bad row)."""
+    import numpy as np
+
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    n = len(rp) - 1 if n is None else int(n)
+    bad = ctypes.c_int32()
+    st = load().hsla_csr_check(n, int(cl.size), rp.ctypes.data_as(ctypes.c_void_p),
+                               cl.ctypes.data_as(ctypes.c_void_p) if cl.size else None, ctypes.byref(bad))
+    return st, bad.value
 
 
 def solve_noalloc(pat: Pattern, values: torch.Tensor, b: torch.Tensor, x: torch.Tensor, opts: Opts):

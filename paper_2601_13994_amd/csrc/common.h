@@ -152,6 +152,7 @@ __device__ __forceinline__ void cg_step_beta(SysState &st, double rr, double rz,
 
 struct DevInfo {
     int num_cu = 256;
+    int wall_khz = 100000;  // device wall clock (wall_clock64) rate
 };
 
 }  // namespace hsla

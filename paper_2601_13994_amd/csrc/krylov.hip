@@ -618,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_sr(Sys S, int Gs, int Gv) {
         st.beta = beta;
         st.alpha = gamma / sigma;
         st.rho = gamma;
-        st.sr_swept = 1;
+        st.sr_swept = swept ? 2 : 1;  // 1: the coming sweep is the first
     }
 }
 
@@ -630,6 +630,9 @@ __global__ __launch_bounds__(kBlock) void k_sr_sweep(Pat A, Sys S) {
     (void)part;
     if (stopped(st)) return;
     const double alpha = st.alpha, beta = st.beta;
+    // the first sweep sets p = r and s = w without reading them (the work
+    // vectors hold whatever an earlier call left there)
+    const bool first = st.sr_swept == 1;
     double *__restrict__ x = S.x + vo;
     double *__restrict__ p = S.p + vo;
     double *__restrict__ sv = S.q + vo;
@@ -638,8 +641,8 @@ __global__ __launch_bounds__(kBlock) void k_sr_sweep(Pat A, Sys S) {
     const double *__restrict__ dinv = S.dinv + vo;
     double acc[1] = {0.0};
     auto elem = [&](double &xv, double &pv, double &s_, double &rv, double wv, double dv) {
-        pv = rv + beta * pv;
-        s_ = wv + beta * s_;
+        pv = first ? rv : rv + beta * pv;
+        s_ = first ? wv : wv + beta * s_;
         xv = xv + alpha * pv;
         rv = rv - alpha * s_;
         const double u = PRE == PRE_JACOBI ? rv / dv : rv;
@@ -1784,6 +1787,9 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             // the diagonal forms' SpMV operands (p, and BiCGStab's s) share
             // p's alignment: every work vector is B n doubles past the last
             f.spmv_paired = nsA > 0 && pairable_stencil(A.sn, n) && ((uintptr_t)S.p & 15u) == 0 ? 1 : 0;
+            f.t_start_ms = f.t_end_ms = 0.0;
+            f.workgroups = 0;
+            f.reserved = 0;
         }
     }
     return (hsla_status)worst;

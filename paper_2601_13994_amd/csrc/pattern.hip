@@ -92,27 +92,36 @@ hsla_status ensure_host_state(hsla_handle *h, size_t nsys) {
 // Kernels
 // ---------------------------------------------------------------------------
 
-// Per-row canonical-CSR checks.  A row's entries are read only after its
-// bounds are known to lie in [0, nnz].  The first offending row wins via an
+// Canonical-CSR check of row i: its entry range [rp[i], rp[i+1]) lies in
+// [0, nnz] (checked before any entry is read) and its columns are in
+// [0, n) and strictly increasing.  *d receives the position of (i, i) (-1
+// if absent) and *lower is advanced by the row's entries with col <= i.
+// Shared by the device validation and hsla_csr_check.
+__host__ __device__ inline bool csr_row_ok(int32_t i, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
+                                           int32_t *d, int64_t *lower) {
+    const int32_t lo = rp[i], hi = rp[i + 1];
+    *d = -1;
+    if (!(lo >= 0 && lo <= hi && (int64_t)hi <= nnz)) return false;
+    int32_t prev = -1;
+    for (int32_t k = lo; k < hi; ++k) {
+        const int32_t c = col[k];
+        if (c < 0 || c >= n || c <= prev) return false;
+        if (c == i) *d = k;
+        if (c <= i) ++*lower;
+        prev = c;
+    }
+    return true;
+}
+
+// Per-row canonical-CSR checks.  The first offending row wins via an
 // integer atomic minimum (order-independent).  diag[i] = position of (i, i).
 __global__ __launch_bounds__(kBlock) void k_validate(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ col, int32_t *__restrict__ diag,
                                                      int32_t *__restrict__ bad_row, int64_t *__restrict__ nnz_lower) {
     int64_t lower = 0;
     for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const int32_t lo = rp[i], hi = rp[i + 1];
         int32_t d = -1;
-        bool ok = lo >= 0 && lo <= hi && (int64_t)hi <= nnz;
-        if (ok) {
-            int32_t prev = -1;
-            for (int32_t k = lo; k < hi; ++k) {
-                const int32_t c = col[k];
-                if (c < 0 || c >= n || c <= prev) { ok = false; break; }
-                if (c == i) d = k;
-                if (c <= i) ++lower;
-                prev = c;
-            }
-        }
+        const bool ok = csr_row_ok(i, n, nnz, rp, col, &d, &lower);
         diag[i] = d;
         if (!ok) atomicMin(bad_row, i);
     }
@@ -669,6 +678,9 @@ hsla_status hsla_create(hsla_handle **out, int device) {
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
         h->dev.num_cu = cu;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+        h->dev.wall_khz = khz;
     if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&h->entry_event, hipEventDisableTiming) != hipSuccess ||
         hipMalloc((void **)&h->d_flags, 256) != hipSuccess) {
@@ -736,6 +748,24 @@ hsla_status hsla_reserve(hsla_handle *h, size_t bytes) {
     if (!h) return HSLA_ERR_INVALID_ARG;
     HSLA_HIP(h, hipSetDevice(h->device));
     return hsla::ensure_workspace(h, bytes);
+}
+
+hsla_status hsla_csr_check(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col, int32_t *bad_row) {
+    if (bad_row) *bad_row = INT32_MAX;
+    if (n < 0 || nnz < 0 || nnz >= INT32_MAX || !row_ptr || (nnz > 0 && !col)) return HSLA_ERR_INVALID_ARG;
+    if (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz) {
+        if (bad_row) *bad_row = -1;
+        return HSLA_ERR_INVALID_CSR;
+    }
+    int64_t lower = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t d = -1;
+        if (!hsla::csr_row_ok(i, n, nnz, row_ptr, col, &d, &lower)) {
+            if (bad_row) *bad_row = i;
+            return HSLA_ERR_INVALID_CSR;
+        }
+    }
+    return HSLA_OK;
 }
 
 hsla_status hsla_pattern_create(hsla_handle *h, int32_t n, int64_t nnz, const int32_t *d_row_ptr,

@@ -39,6 +39,7 @@ struct RInfo {  // per-system result record (device)
     int32_t status;
     int32_t pad;
     double rel_residual, true_residual;
+    uint64_t t_begin, t_end;  // persistent kernels: device wall clock when the system was taken and finished
 };
 
 struct Args {
@@ -49,6 +50,7 @@ struct Args {
     const double *val, *b;
     double *x;
     double *r, *p, *q, *dinv;  // work vectors, concatenated like b
+    double *u, *w;             // single-reduction kernel: M^{-1} r and A u
     const int32_t *order;      // systems in queue order (nullptr: 0..B-1)
     int32_t *queue;            // next queue slot
     int32_t *bad;              // first invalid system (validation)
@@ -213,6 +215,7 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
         const int32_t qs = slot;
         __syncthreads();
         if (qs >= a.B) return;
+        const uint64_t t_begin = threadIdx.x == 0 ? wall_clock64() : 0;
         const int32_t s = a.order ? a.order[qs] : qs;
         const bool shared = a.shared_n >= 0;
         const int64_t r0 = shared ? (int64_t)s * a.shared_n : a.row_off[s];
@@ -346,6 +349,164 @@ __global__ __launch_bounds__(kRB) void k_ragged_pcg(Args a) {
             f.pad = 0;
             f.rel_residual = bn > 0 ? sqrt(rr) / bn : sqrt(rr);
             f.true_residual = accr[1] > 0 ? sqrt(accr[0]) / sqrt(accr[1]) : sqrt(accr[0]);
+            f.t_begin = t_begin;
+            f.t_end = wall_clock64();
+            a.info[s] = f;
+        }
+        __syncthreads();
+    }
+}
+
+// The same persistent launch with the single-reduction recurrence of
+// Chronopoulos and Gear (preconditioned: u = M^{-1} r, w = A u,
+// gamma = r.u, delta = w.u; beta = gamma / gamma_old,
+// alpha = gamma / (delta - beta gamma / alpha_old); p = u + beta p,
+// s = w + beta s, x += alpha p, r -= alpha s): per iteration one pass with
+// the SpMV and one workgroup reduction of gamma, delta and the previous
+// sweep's ||r||^2 (the stop test), then one vector pass -- against three
+// passes and two reductions in k_ragged_pcg.  `q` holds s.
+__global__ __launch_bounds__(kRB) void k_ragged_pcg_sr(Args a) {
+    __shared__ double sh[3 * kRW];
+    __shared__ double lds[kRW * kChunk];
+    __shared__ int32_t slot;
+    for (;;) {
+        if (threadIdx.x == 0) slot = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int32_t qs = slot;
+        __syncthreads();
+        if (qs >= a.B) return;
+        const uint64_t t_begin = threadIdx.x == 0 ? wall_clock64() : 0;
+        const int32_t s = a.order ? a.order[qs] : qs;
+        const bool shared = a.shared_n >= 0;
+        const int64_t r0 = shared ? (int64_t)s * a.shared_n : a.row_off[s];
+        const int32_t n = (int32_t)(shared ? a.shared_n : a.row_off[s + 1] - r0);
+        const int64_t k0 = shared ? (int64_t)s * a.shared_nnz : a.nnz_off[s];
+        const int32_t *rp = shared ? a.rp : a.rp + r0 + s;
+        const int32_t *col = shared ? a.col : a.col + k0;
+        const double *__restrict__ val = a.val + k0;
+        const double *__restrict__ b = a.b + r0;
+        double *__restrict__ x = a.x + r0;
+        double *__restrict__ r = a.r + r0;
+        double *__restrict__ p = a.p + r0;
+        double *__restrict__ sv = a.q + r0;
+        double *__restrict__ u = a.u + r0;
+        double *__restrict__ w = a.w + r0;
+        double *__restrict__ dinv = a.dinv + r0;
+        // set-up: x = 0, r = b, u = D^{-1} r
+        double acc1[1] = {0.0};
+        int bad_diag = 0, neg_diag = 0;
+        for (int32_t i = threadIdx.x; i < n; i += kRB) {
+            double d = 0.0;
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+                if (col[k] == i) d = val[k];
+            if (a.jacobi && d == 0.0) bad_diag = 1;
+            if (a.jacobi && d < 0.0) neg_diag = 1;
+            const double di = a.jacobi ? 1.0 / d : 1.0;
+            const double bi = b[i];
+            dinv[i] = di;
+            x[i] = 0.0;
+            r[i] = bi;
+            u[i] = di * bi;
+            acc1[0] += bi * bi;
+        }
+        double bd[2] = {(double)bad_diag, (double)neg_diag};
+        wg_sum<kRW, 2>(bd, sh);
+        wg_sum<kRW, 1>(acc1, sh);
+        const double bn = sqrt(acc1[0]);
+        double tol = a.rtol * bn;
+        if (a.atol > tol) tol = a.atol;
+        double rr = acc1[0];
+        int32_t status = HSLA_NOT_CONVERGED;
+        int64_t it = 0;
+        if (bd[0] > 0.0) {
+            status = HSLA_ERR_ZERO_DIAGONAL;
+        } else if (!isfinite(bn)) {
+            status = HSLA_ERR_NONFINITE;
+        } else if (sqrt(rr) <= tol) {
+            status = HSLA_OK;
+        } else if (bd[1] > 0.0) {
+            status = HSLA_BREAKDOWN;  // negative Jacobi diagonal: x stays 0
+        } else if (a.max_iter > 0) {
+            double gamma_old = 1.0, alpha_old = 1.0;
+            for (;;) {
+                __syncthreads();  // u of the last sweep complete
+                // w = A u with gamma = r.u, delta = w.u, and ||r||^2 of the last sweep
+                double acc3[3] = {0.0, 0.0, 0.0};
+                wg_spmv<kRW>(n, rp, col, val, u, lds, [&](int32_t i, double sum) {
+                    const double ri = r[i], ui = u[i];
+                    w[i] = sum;
+                    acc3[0] += ri * ui;
+                    acc3[1] += sum * ui;
+                    acc3[2] += ri * ri;
+                });
+                wg_sum<kRW, 3>(acc3, sh);
+                if (it > 0) {
+                    rr = acc3[2];
+                    const double rn = sqrt(rr);
+                    if (!isfinite(rn)) { status = HSLA_ERR_NONFINITE; break; }
+                    if (rn <= tol) { status = HSLA_OK; break; }
+                    if (it >= a.max_iter) break;
+                }
+                const double gamma = acc3[0], delta = acc3[1];
+                const double beta = it > 0 ? gamma / gamma_old : 0.0;
+                const double sigma = it > 0 ? delta - beta * gamma / alpha_old : delta;
+                if (!isfinite(sigma) || !isfinite(gamma)) { status = HSLA_ERR_NONFINITE; break; }
+                if (!(sigma > 0.0)) { status = HSLA_BREAKDOWN; break; }
+                const double alpha = gamma / sigma;
+                const bool first = it == 0;
+                for (int32_t i0 = threadIdx.x; i0 < n; i0 += 2 * kRB) {
+                    double xv[2], pv[2], sq[2], rv[2], uv[2], wv[2], dv[2];
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        const int32_t i = i0 + k * kRB;
+                        if (i < n) {
+                            xv[k] = x[i];
+                            pv[k] = first ? 0.0 : p[i];
+                            sq[k] = first ? 0.0 : sv[i];
+                            rv[k] = r[i];
+                            uv[k] = u[i];
+                            wv[k] = w[i];
+                            dv[k] = dinv[i];
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        const int32_t i = i0 + k * kRB;
+                        if (i < n) {
+                            const double pn = uv[k] + beta * pv[k];
+                            const double sn = wv[k] + beta * sq[k];
+                            const double rn = rv[k] - alpha * sn;
+                            p[i] = pn;
+                            sv[i] = sn;
+                            x[i] = xv[k] + alpha * pn;
+                            r[i] = rn;
+                            u[i] = dv[k] * rn;
+                        }
+                    }
+                }
+                gamma_old = gamma;
+                alpha_old = alpha;
+                ++it;
+            }
+        }
+        // true residual ||b - A x||
+        double accr[2] = {0.0, 0.0};
+        __syncthreads();
+        wg_spmv<kRW>(n, rp, col, val, x, lds, [&](int32_t i, double sum) {
+            const double e = b[i] - sum;
+            accr[0] += e * e;
+            accr[1] += b[i] * b[i];
+        });
+        wg_sum<kRW, 2>(accr, sh);
+        if (threadIdx.x == 0) {
+            RInfo f;
+            f.iters = it;
+            f.status = n == 0 ? HSLA_OK : status;
+            f.pad = 0;
+            f.rel_residual = bn > 0 ? sqrt(rr) / bn : sqrt(rr);
+            f.true_residual = accr[1] > 0 ? sqrt(accr[0]) / sqrt(accr[1]) : sqrt(accr[0]);
+            f.t_begin = t_begin;
+            f.t_end = wall_clock64();
             a.info[s] = f;
         }
         __syncthreads();
@@ -408,6 +569,7 @@ __global__ __launch_bounds__(kSB) void k_small_pcg(Args a) {
         const int32_t s = slot;
         __syncthreads();
         if (s >= a.B) return;
+        const uint64_t t_begin = threadIdx.x == 0 ? wall_clock64() : 0;
         const double *val = a.val + (int64_t)s * a.shared_nnz;
         const double *b = a.b + (int64_t)s * n;
         double *x = a.x + (int64_t)s * n;
@@ -590,6 +752,8 @@ __global__ __launch_bounds__(kSB) void k_small_pcg(Args a) {
             f.pad = 0;
             f.rel_residual = bn > 0 ? sqrt(rr) / bn : sqrt(rr);
             f.true_residual = accr[1] > 0 ? sqrt(accr[0]) / sqrt(accr[1]) : sqrt(accr[0]);
+            f.t_begin = t_begin;
+            f.t_end = wall_clock64();
             a.info[s] = f;
         }
         __syncthreads();
@@ -604,9 +768,12 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
                                   hipStream_t s, int small_rows = 0, int small_k = 0,
                                   bool single_reduction = false) {
     const int32_t B = a.B;
+    // the general kernel's single-reduction form keeps two more vectors
+    const bool sr_general = single_reduction && small_rows == 0;
+    const int nvec = sr_general ? 6 : 4;
     size_t bytes = 0;
     auto add = [&](size_t v) { bytes += (v + 255) / 256 * 256; };
-    add(sizeof(double) * 4 * (rows > 0 ? rows : 1));
+    add(sizeof(double) * nvec * (rows > 0 ? rows : 1));
     add(sizeof(int32_t) * B);
     add(sizeof(RInfo) * B);
     add(256);
@@ -619,11 +786,13 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
         off += (v + 255) / 256 * 256;
         return p;
     };
-    double *vec = (double *)take(sizeof(double) * 4 * (rows > 0 ? rows : 1));
+    double *vec = (double *)take(sizeof(double) * nvec * (rows > 0 ? rows : 1));
     a.r = vec;
     a.p = vec + rows;
     a.q = vec + 2 * rows;
     a.dinv = vec + 3 * rows;
+    a.u = sr_general ? vec + 4 * rows : nullptr;
+    a.w = sr_general ? vec + 5 * rows : nullptr;
     int32_t *dorder = (int32_t *)take(sizeof(int32_t) * B);
     a.order = order.empty() ? nullptr : dorder;
     a.info = (RInfo *)take(sizeof(RInfo) * B);
@@ -641,7 +810,8 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
     // every pointer the kernels dereference must be set (rows/entries > 0)
     const bool shared = a.shared_n >= 0;
     if (!a.rp || !a.queue || !a.bad || !a.info || (!shared && (!a.row_off || !a.nnz_off || !a.order)) ||
-        (rows > 0 && (!a.b || !a.x || !a.r || !a.p || !a.q || !a.dinv)) || (entries > 0 && (!a.col || !a.val)))
+        (rows > 0 && (!a.b || !a.x || !a.r || !a.p || !a.q || !a.dinv)) || (entries > 0 && (!a.col || !a.val)) ||
+        (sr_general && rows > 0 && (!a.u || !a.w)))
         return set_error(h, HSLA_ERR_INTERNAL, "persistent solve: unset kernel argument");
     if (!shared) {
         k_ragged_validate<<<std::min(B, 4096), 256, 0, s>>>(a);
@@ -670,6 +840,8 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
         SMALL_LAUNCH(true)
     } else if (small_rows > 0) {
         SMALL_LAUNCH(false)
+    } else if (sr_general) {
+        k_ragged_pcg_sr<<<gr, kRB, 0, s>>>(a);
     } else {
         k_ragged_pcg<<<gr, kRB, 0, s>>>(a);
     }
@@ -679,6 +851,9 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
     HSLA_HIP(h, hipMemcpyAsync(hi.data(), a.info, sizeof(RInfo) * B, hipMemcpyDeviceToHost, s));
     HSLA_HIP(h, hipStreamSynchronize(s));
     int worst = HSLA_OK;
+    uint64_t t0 = UINT64_MAX;
+    for (int i = 0; i < B; ++i) t0 = std::min(t0, hi[i].t_begin);
+    const double tick_ms = 1.0 / (double)h->dev.wall_khz;
     for (int i = 0; i < B; ++i) {
         const int sst = hi[i].status;
         if (sst < 0 || worst < 0)
@@ -686,9 +861,13 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
         else
             worst = std::max(worst, sst);
         if (infos) {
+            infos[i].t_start_ms = (double)(hi[i].t_begin - t0) * tick_ms;
+            infos[i].t_end_ms = (double)(hi[i].t_end - t0) * tick_ms;
+            infos[i].workgroups = small_rows > 0 ? gs : gr;
+            infos[i].reserved = 0;
             infos[i].iters = hi[i].iters;
             infos[i].status = sst;
-            infos[i].method = single_reduction && small_rows > 0 ? HSLA_METHOD_CG_SR : HSLA_METHOD_CG;
+            infos[i].method = single_reduction ? HSLA_METHOD_CG_SR : HSLA_METHOD_CG;
             infos[i].rel_residual = hi[i].rel_residual;
             infos[i].true_residual = hi[i].true_residual;
             infos[i].spmv_ms = 0.0;
@@ -966,6 +1145,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_fin_residual(Seg g) {
     const double rn = sqrt(st.rnorm2);
     f.rel_residual = st.bnorm > 0 ? rn / st.bnorm : rn;
     f.true_residual = tot[1] > 0 ? sqrt(tot[0]) / sqrt(tot[1]) : sqrt(tot[0]);
+    f.t_begin = f.t_end = 0;
     g.a.info[s] = f;
 }
 
@@ -1090,6 +1270,9 @@ static hsla_status run_segmented(hsla_handle *h, Args a, const hsla_opts &o, con
             infos[i].spmv_launches = 0;
             infos[i].spmv_form = 0;
             infos[i].spmv_paired = 0;
+            infos[i].t_start_ms = infos[i].t_end_ms = 0.0;
+            infos[i].workgroups = 0;
+            infos[i].reserved = 0;
         }
     }
     return (hsla_status)worst;
@@ -1181,7 +1364,7 @@ extern "C" hsla_status hsla_solve_ragged(hsla_handle *h, int32_t B, const int64_
     a.val = d_values;
     a.b = d_b;
     a.x = d_x;
-    if (!o.persistent || o.stall_window > 0 || (rows >= kSegMinRows && max_n > kSegMinN))
+    if (!o.persistent || o.stall_window > 0 || (o.persistent != 2 && rows >= kSegMinRows && max_n > kSegMinN))
         return run_segmented(h, a, o, ro, max_n, infos, s);
-    return run_persistent(h, a, o, rows, no[B], max_n, order, infos, s);
+    return run_persistent(h, a, o, rows, no[B], max_n, order, infos, s, 0, 0, o.method == HSLA_METHOD_CG_SR);
 }

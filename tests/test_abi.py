@@ -53,7 +53,7 @@ def test_host_only_entry_points(lib):
     o = _lib.Opts()
     lib.hsla_opts_default(ctypes.byref(o))
     assert o.rtol == 1e-8 and o.precond == 1 and o.method == 0 and o.use_graph == 1
-    assert ctypes.sizeof(_lib.Info) == 56
+    assert ctypes.sizeof(_lib.Info) == 80
 
 
 def test_struct_layout_matches_header(tmp_path):

@@ -448,6 +448,38 @@ def test_backward_memory_flat_in_iterations():
         _lib.use_torch_allocator(dev(), enable=False)
 
 
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_persistent_single_reduction(orc, precond):
+    """CG_SR in the general persistent kernel (shared-pattern mode, one
+    workgroup per system, one reduction per iteration): sampled systems
+    match the oracle's CG, the k-th iterate at a cap, breakdown, b = 0."""
+    m = 20
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m))
+    B = 300
+    r = np.random.default_rng(9)
+    V = np.stack([a.val] * B)
+    V[5] = -a.val  # not SPD: breakdown (Jacobi: negative diagonal)
+    bs = r.standard_normal((B, a.n))
+    bs[7] = 0.0
+    pat = pattern(a)
+    kw = dict(method="cg_sr", precond=precond, rtol=1e-12)
+    x, inf, st = _lib.solve(pat, t64(V), t64(bs), _lib.make_opts(**kw))
+    assert st == _lib.BREAKDOWN
+    assert all(f["spmv_form"] == "persistent" and f["method"] == "cg_sr" for f in inf)
+    assert inf[5]["status"] == _lib.BREAKDOWN
+    assert inf[7]["status"] == 0 and inf[7]["iters"] == 0 and not x[7].any()
+    for s in (0, 150, 299):
+        ref = orc.cg(a, bs[s], precond=precond, rtol=1e-12)
+        assert inf[s]["status"] == 0
+        assert rel(x[s].cpu().numpy(), ref.x) <= 1e-8
+        assert iters_close(inf[s]["iters"], ref.iters), (inf[s]["iters"], ref.iters)
+    for k in (1, 2, 7):
+        xk, ik, sk = _lib.solve(pat, t64(V), t64(bs), _lib.make_opts(max_iter=k, **kw))
+        refk = orc.cg(a, bs[0], precond=precond, rtol=1e-12, max_iter=k)
+        assert ik[0]["status"] == _lib.NOT_CONVERGED and ik[0]["iters"] == k
+        assert rel(xk[0].cpu().numpy(), refk.x) <= 1e-10, (k, rel(xk[0].cpu().numpy(), refk.x))
+
+
 def test_persistent_shared_mode_batch(orc):
     """A batch with one system per compute unit and more runs the general
     persistent kernel in shared-pattern mode (n > 4096): sampled systems
@@ -515,6 +547,12 @@ def test_cg_single_reduction_per_iteration(orc, fmt, precond):
     pat = pattern(a)
     pat.set_format(fmt)
     kw = dict(method="cg_sr", precond=precond, rtol=1e-12, persistent=False)
+    # leave NaN in the work vectors first: a CG solve whose SpMV meets a NaN
+    # value stops as non-finite after writing q = A p
+    bad = a.val.copy()
+    bad[1] = np.nan
+    with pytest.raises(_lib.HslaError):
+        solve(a, b, pat=pat, values=t64(bad), method="cg", precond="none", persistent=False)
     x, info, st = solve(a, b, pat=pat, **kw)
     ref = orc.cg(a, b, precond=precond, rtol=1e-12)
     assert st == 0 and info[0]["method"] == "cg_sr", info

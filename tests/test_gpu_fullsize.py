@@ -48,16 +48,30 @@ def test_diffusion3d_256_first_iterations(orc):
     _log("bicgstab", rel(x.cpu().numpy(), ref.x))
 
 
-def test_ragged_knn_full_sizes(orc):
-    """512 systems (64 distinct full-size k-NN Laplacians, each 8 times) in
-    one persistent launch: copies agree bitwise, sampled systems match the
-    oracle at rtol 1e-12, every system's FP64 residual meets the tolerance."""
+@pytest.mark.parametrize("persistent", [True, "force"])
+def test_ragged_knn_full_sizes(orc, persistent):
+    """512 systems (64 distinct full-size k-NN Laplacians, each 8 times):
+    with the default routing the batch (13M rows) runs on the segmented
+    per-iteration path; "force" runs it in one persistent launch.  Copies
+    agree bitwise, sampled systems match the oracle at rtol 1e-12, every
+    system's FP64 residual meets the tolerance; the persistent launch
+    reports when each workgroup took and finished its system."""
     distinct = [W.knn_system(s) for s in range(64)]
     systems = [distinct[i % 64] for i in range(512)]
     mats = [(t64(a.val), t32(a.row_ptr), t32(a.col)) for a, _ in distinct]
     L = hs.SparseCSRList([mats[i % 64] for i in range(512)])
-    xs, infos, st = L.solve([t64(b) for _, b in systems], rtol=1e-12)
+    xs, infos, st = L.solve([t64(b) for _, b in systems], rtol=1e-12, persistent=persistent)
     assert st == _lib.OK
+    if persistent == "force":
+        assert all(f["spmv_form"] == "persistent" for f in infos)
+        wg = infos[0]["workgroups"]
+        assert 0 < wg <= 512 and all(0.0 <= f["t_start_ms"] <= f["t_end_ms"] for f in infos)
+        busy = sum(f["t_end_ms"] - f["t_start_ms"] for f in infos)
+        wall = max(f["t_end_ms"] for f in infos)
+        _log("persistent knn: wall", wall, "ms, load balance", busy / (wg * wall))
+        assert 0.0 < busy / (wg * wall) <= 1.0 + 1e-9
+    else:
+        assert all(f["spmv_form"] != "persistent" for f in infos)
     for i in range(64, 512):
         assert torch.equal(xs[i], xs[i % 64])
         assert infos[i]["iters"] == infos[i % 64]["iters"]
@@ -68,6 +82,54 @@ def test_ragged_knn_full_sizes(orc):
         assert rel(xs[s].cpu().numpy(), ref.x) <= 1e-8
         assert iters_close(infos[s]["iters"], ref.iters)
         _log("knn", s, a.n, rel(xs[s].cpu().numpy(), ref.x))
+
+
+def _kappa_hat(ref):
+    """Condition number estimate of the preconditioned operator from CG's
+    coefficients: extreme eigenvalues of the Lanczos tridiagonal."""
+    al, be = ref.alphas, ref.betas
+    k = len(al)
+    d = 1.0 / al
+    d[1:] += be[:k - 1] / al[:k - 1]
+    e = np.sqrt(be[:k - 1]) / al[:k - 1]
+    ev = np.linalg.eigvalsh(np.diag(d) + np.diag(e, 1) + np.diag(e, -1))
+    return ev[-1] / ev[0]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("method", ["cg", "bicgstab"])
+def test_diffusion3d_256_full_solve(orc, method):
+    """The headline system (and its upwind variant under BiCGStab) solved to
+    rtol 1e-12 on the GPU in the configuration the benchmark times and by the
+    oracle on all host cores: ||x_gpu - x_oracle|| / ||x_oracle|| <= 1e-8,
+    iteration counts within max(2, 2%), and the reported true residual equal
+    to the oracle's ||b - A x_gpu|| / ||b||.  For CG the Lanczos estimate of
+    the preconditioned condition number is logged: the worst-case bound
+    kappa * 2e-12 on the difference of two rtol-1e-12 solutions."""
+    import os
+
+    a, b = W.diffusion3d_workload(256)
+    if method == "bicgstab":
+        a = a.with_values(W.diffusion3d_values(256, W.diffusion3d_kappa(256), velocity=10.0))
+    pat = pattern(a)
+    x, infos, st = _lib.solve(pat, t64(a.val), t64(b), _lib.make_opts(method=method, precond="jacobi", rtol=1e-12))
+    assert st == _lib.OK
+    x = x.cpu().numpy()
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    with orc.threads(threads):
+        if method == "cg":
+            ref = orc.cg(a, b, precond="jacobi", rtol=1e-12, history=True)
+        else:
+            ref = orc.bicgstab(a, b, precond="jacobi", rtol=1e-12)
+        tr = orc.residual_norm(a, b, x) / np.linalg.norm(b)
+    assert ref.status == 0
+    err = rel(x, ref.x)
+    kh = _kappa_hat(ref) if method == "cg" else float("nan")
+    _log(method, "gpu iters", infos[0]["iters"], "oracle iters", ref.iters, "rel diff", err, "kappa_hat", kh,
+         "true residual gpu", infos[0]["true_residual"], "oracle's", tr)
+    assert err <= 1e-8
+    assert iters_close(infos[0]["iters"], ref.iters)
+    assert abs(infos[0]["true_residual"] - tr) <= 1e-10 * tr
 
 
 def test_shared_pattern_96_adjoint_and_fd(orc):
@@ -162,7 +224,8 @@ def test_learned_fsai_256(orc):
     g0 = model.ghat(pat, V[:1].contiguous()).cpu().numpy().reshape(-1)
     a0 = pa.with_values(V[0].cpu().numpy())
     ref, _ = mpnn.forward(p64, a0, bf=True)
-    assert rel(g0, ref) <= 2e-2
+    _log("network forward vs oracle", rel(g0, ref))
+    assert rel(g0, ref) <= 1e-3  # relative Frobenius bound for the bf16 network
     G, GT = model.factors(pat, V)
     assert torch.isfinite(G).all()
     x, infos, st = _lib.solve(pat, V, bt, _lib.make_opts(method="cg", precond="fsai", rtol=1e-12, G=G, GT=GT))

@@ -54,8 +54,10 @@ def test_mpnn_forward_parity(m, B):
     for s in range(B):
         ref, _ = mpnn.forward(p32, a.with_values(V[s]), bf=True)
         assert g[s].shape == ref.shape
-        assert rel(g[s], ref) <= 2e-2, (s, rel(g[s], ref))
-        assert np.mean(np.abs(g[s] - ref) <= 1e-2 * (np.abs(ref) + 1e-2)) > 0.97
+        # the same bf16 cast points: only float32 vs float64 accumulation
+        # differs, so a cast rarely rounds the other way (measured ~1e-8)
+        assert rel(g[s], ref) <= 1e-5, (s, rel(g[s], ref))
+        assert np.max(np.abs(g[s] - ref)) <= 1e-4 * np.max(np.abs(ref))
 
 
 def test_mpnn_backward_parity():
@@ -76,7 +78,7 @@ def test_mpnn_backward_parity():
         for k in tot:
             tot[k] += gr[k]
     for k in tot:
-        assert rel(gd[k], tot[k]) <= 5e-2, (k, rel(gd[k], tot[k]))
+        assert rel(gd[k], tot[k]) <= 1e-4, (k, rel(gd[k], tot[k]))  # measured <= 2e-6
     # a second kept forward with another batch is required before another backward
     with pytest.raises(_lib.HslaError):
         _lib.mpnn_backward(pat, B + 1, torch.as_tensor(dg).to(dev()))

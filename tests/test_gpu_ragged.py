@@ -55,6 +55,30 @@ def test_ragged_knn_parity(orc, persistent):
 
 
 @pytest.mark.parametrize("persistent", [True, False])
+def test_ragged_single_reduction(orc, persistent):
+    """CG_SR on a ragged batch: the persistent launch runs the
+    single-reduction kernel (reported as cg_sr), the segmented path runs CG;
+    both match the oracle's CG."""
+    systems = [_knn(s, 100, 3000) for s in range(7)]
+    row_off = np.cumsum([0] + [a.n for a, _ in systems])
+    nnz_off = np.cumsum([0] + [a.nnz for a, _ in systems])
+    rp = np.concatenate([a.row_ptr for a, _ in systems])
+    col = np.concatenate([a.col for a, _ in systems])
+    val = np.concatenate([a.val for a, _ in systems])
+    b = np.concatenate([bb for _, bb in systems])
+    opts = _lib.make_opts(method="cg_sr", precond="jacobi", rtol=1e-12, persistent=persistent)
+    x, infos, st = _lib.solve_ragged(torch.as_tensor(row_off).to(dev()), torch.as_tensor(nnz_off).to(dev()),
+                                     t32(rp), t32(col), t64(val), t64(b), opts)
+    assert st == 0
+    x = x.cpu().numpy()
+    for s, ((a, bb), f) in enumerate(zip(systems, infos)):
+        assert f["method"] == ("cg_sr" if persistent else "cg")
+        ref = orc.cg(a, bb, precond="jacobi", rtol=1e-12)
+        assert rel(x[row_off[s]:row_off[s + 1]], ref.x) <= 1e-8
+        assert iters_close(f["iters"], ref.iters), (s, f["iters"], ref.iters)
+
+
+@pytest.mark.parametrize("persistent", [True, False])
 def test_ragged_rejects_invalid_system(persistent):
     a, b = _knn(0, 100, 200)
     c = a.col.copy()
