@@ -41,6 +41,8 @@ def _both(pat, fn):
     ("poisson2d_even", lambda: W.poisson2d(38), 5),
     ("diffusion3d_even", lambda: W.diffusion3d(14, W.diffusion3d_kappa(14)), 7),
     ("upwind_even", lambda: W.diffusion3d(12, W.diffusion3d_kappa(12), velocity=10.0), 7),
+    # odd offsets m - 1, m + 1 with even n
+    ("aniso9_even", lambda: W.aniso2d(30, 30.0, 0.7), 9),
 ])
 def test_stencil_spmv_bitwise(orc, name, make, nofs):
     a = make()
@@ -132,8 +134,12 @@ def test_stencil_adjoint_transpose():
     assert rel(l1.cpu().numpy(), dense) <= 1e-8
 
 
-def test_stencil_fsai(orc):
-    pa, slots = W.aniso_pattern(21)
+@pytest.mark.parametrize("m", [21, 22])
+def test_stencil_fsai(orc, m):
+    """FSAI-PCG with factors on the 9-point stencil's lower and upper
+    triangles (main diagonal at one end), odd and even n, against the
+    oracle with the same factor."""
+    pa, slots = W.aniso_pattern(m)
     a = pa.with_values(W.aniso_stencil(100.0, 0.4)[slots])
     ah = mpnn.scaled(a)
     rpL, colL, gh = orc.fsai(ah)
@@ -343,3 +349,43 @@ def test_paired_layout(orc, m, paired, method):
         refk = orc.cg(a, b, precond="jacobi", rtol=1e-14, max_iter=k)
         assert st == _lib.NOT_CONVERGED and fk[0]["iters"] == k
         assert rel(xk.cpu().numpy(), refk.x) <= 1e-12
+
+
+@pytest.mark.parametrize("m", [30, 29])
+@pytest.mark.parametrize("method", ["cg", "bicgstab"])
+def test_odd_offset_stencil(orc, m, method):
+    """The 9-point anisotropic stencil (offsets -m-1 .. m+1, odd ones beyond
+    -1/+1) keeps the two-rows-256-apart layout with row masks for even and
+    odd n (half copy of S A S for CG, full copy of A D^{-1} for BiCGStab);
+    the half-form SpMV is bitwise the CSR one; solves and CG's truncated
+    iterate match the oracle."""
+    paired = False
+    a = W.aniso2d(m, 50.0, 0.6)
+    pat = pattern(a)
+    assert pat.stencil == (True, 9)
+    r = np.random.default_rng(m)
+    X = r.standard_normal((2, a.n))
+    V = np.stack([a.val, 2.0 * a.val])  # symmetric: the half form
+    ys = {}
+    for fmt in ("diagonal", "csr"):
+        pat.set_format(fmt)
+        ys[fmt] = _lib.spmv(pat, t64(V), t64(X)).cpu().numpy()
+    pat.set_format("auto")
+    assert np.array_equal(ys["diagonal"], ys["csr"])
+    b = r.standard_normal(a.n)
+    if method == "bicgstab":
+        a = a.with_values(a.val * (1 + 0.05 * r.standard_normal(a.nnz)))
+    opts = _lib.make_opts(method=method, precond="jacobi", rtol=1e-12, persistent=False)
+    x, infos, st = _lib.solve(pat, t64(a.val), t64(b), opts)
+    assert st == _lib.OK and infos[0]["spmv_paired"] is paired
+    assert infos[0]["spmv_form"] == ("diagonal-half-unit" if method == "cg" else "diagonal-unit")
+    ref = orc.solve(a, b, method=method, precond="jacobi", rtol=1e-12)
+    assert rel(x.cpu().numpy(), ref.x) <= 1e-8
+    if method == "cg":
+        assert iters_close(infos[0]["iters"], ref.iters)
+        for k in (1, 7):
+            opts = _lib.make_opts(method="cg", precond="jacobi", rtol=1e-14, max_iter=k, persistent=False)
+            xk, fk, st = _lib.solve(pat, t64(a.val), t64(b), opts)
+            refk = orc.cg(a, b, precond="jacobi", rtol=1e-14, max_iter=k)
+            assert st == _lib.NOT_CONVERGED and fk[0]["iters"] == k
+            assert rel(xk.cpu().numpy(), refk.x) <= 1e-12
