@@ -303,10 +303,35 @@ namespace hsla {
 
 // Butterfly sum over the 64 lanes; every lane ends with the same value and
 // the association order is fixed, so the result is deterministic.
+// A DPP lane move of a double (both 32-bit halves with the same control);
+// rows left out by ROW_MASK keep `old`.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double old, double v) {
+    const uint64_t o = (uint64_t)__double_as_longlong(old), x = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)x, CTRL, ROW_MASK,
+                                                              0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(x >> 32),
+                                                              CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wavefront (all lanes active), in every lane.
+// A fixed tree of data-parallel-primitive moves (no LDS round trips): pairs,
+// quads, half rows and rows of 16 lanes (each lane ends with its row's sum),
+// then rows 0+1 and 2+3 (row broadcast 15), then all four (row broadcast
+// 31, into lane 63), which is read back into every lane.  The order is the
+// same on every call, so results are run-to-run deterministic.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    v += dpp_f64<0xB1>(0.0, v);        // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(0.0, v);        // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(0.0, v);       // row_half_mirror
+    v += dpp_f64<0x140>(0.0, v);       // row_mirror
+    v += dpp_f64<0x142, 0xa>(0.0, v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(0.0, v);  // row_bcast:31 into rows 2 and 3
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // Sum over the block of NV values; the result is valid in thread 0.

@@ -62,7 +62,10 @@ struct Args {
 
 // Workgroup (NW waves) sum of NV values in a fixed order; result in every
 // thread.
-template <int NW, int NV>
+// TAIL = false leaves out the closing barrier: the caller then guarantees
+// that `sh` is not written again before every wave has passed another
+// barrier (e.g. by alternating buffers between consecutive sums).
+template <int NW, int NV, bool TAIL = true>
 __device__ __forceinline__ void wg_sum(double (&v)[NV], double *sh) {
 #pragma unroll
     for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
@@ -79,7 +82,7 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV], double *sh) {
         for (int q = 0; q < NW; ++q) s += sh[j * NW + q];
         v[j] = s;
     }
-    __syncthreads();
+    if (TAIL) __syncthreads();
 }
 
 // y = A v for one system, by the whole workgroup (NW waves): wave w takes
@@ -760,13 +763,207 @@ __global__ __launch_bounds__(kSB) void k_small_pcg(Args a) {
     }
 }
 
+// Small systems with short rows (at most K = 5 entries, or K = 8 with
+// n <= 2048): the same recurrence as k_small_pcg (plain CG or Jacobi-PCG,
+// Algorithm "Distributed CG" on one workgroup) with the matrix itself held in
+// registers.  512 threads; thread t owns rows t + 512 j (R of them) and
+// keeps their column indices (two 16-bit indices per register, loaded once
+// per launch: the pattern is shared) and the current system's values
+// (loaded once per system), so an iteration reads nothing but the LDS copy
+// of p.  Each row adds its products in ascending column order, products
+// rounded before the add.
+constexpr int kRT = 512;
+constexpr int kRTW = kRT / kWave;
+
+template <int K>
+__device__ __forceinline__ double reg_row(const double (&vv)[K], const uint32_t (&cc)[(K + 1) / 2], int32_t len,
+                                          const double *v) {
+#pragma clang fp contract(off)
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (k < len) {
+            const uint32_t c = (cc[k / 2] >> (16 * (k & 1))) & 0xffffu;
+            const double prd = vv[k] * v[c];
+            sum = sum + prd;
+        }
+    return sum;
+}
+
+template <int R, int K>
+__global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
+    __shared__ double ps[kSmallMaxN];
+    __shared__ double xs[kSmallMaxN];  // x of the thread's own rows (keeps registers for the matrix)
+    __shared__ double sh[2][3 * kRTW];
+    __shared__ int32_t slot;
+    const int32_t n = (int32_t)a.shared_n;
+    // this thread's rows of the shared pattern
+    int32_t lo[R], len[R], dk[R];
+    uint32_t cc[R][(K + 1) / 2];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int32_t i = threadIdx.x + j * kRT;
+        lo[j] = 0;
+        len[j] = 0;
+        dk[j] = -1;
+#pragma unroll
+        for (int u = 0; u < (K + 1) / 2; ++u) cc[j][u] = 0u;
+        if (i < n) {
+            lo[j] = a.rp[i];
+            len[j] = a.rp[i + 1] - lo[j];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k < len[j]) {
+                    const int32_t c = a.col[lo[j] + k];
+                    cc[j][k / 2] |= (uint32_t)c << (16 * (k & 1));
+                    if (c == i) dk[j] = k;
+                }
+        }
+    }
+    for (;;) {
+        if (threadIdx.x == 0) slot = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int32_t s = slot;
+        __syncthreads();
+        if (s >= a.B) return;
+        const uint64_t t_begin = threadIdx.x == 0 ? wall_clock64() : 0;
+        const double *val = a.val + (int64_t)s * a.shared_nnz;
+        const double *b = a.b + (int64_t)s * n;
+        double *x = a.x + (int64_t)s * n;
+        double vv[R][K];
+        double rv[R], dv[R], pv[R], qv[R];
+        double acc3[3] = {0.0, 0.0, 0.0};
+        int bad_diag = 0, neg_diag = 0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int32_t i = threadIdx.x + j * kRT;
+#pragma unroll
+            for (int k = 0; k < K; ++k) vv[j][k] = k < len[j] ? val[lo[j] + k] : 0.0;
+            rv[j] = pv[j] = qv[j] = 0.0;
+            dv[j] = 1.0;
+            if (i < n) {
+                xs[i] = 0.0;
+                double d = 0.0;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (k == dk[j]) d = vv[j][k];
+                if (a.jacobi && d == 0.0) bad_diag = 1;
+                if (a.jacobi && d < 0.0) neg_diag = 1;
+                const double di = a.jacobi ? 1.0 / d : 1.0;
+                const double bi = b[i];
+                dv[j] = di;
+                rv[j] = bi;
+                pv[j] = di * bi;
+                ps[i] = pv[j];
+                acc3[0] += bi * bi;
+                acc3[1] += bi * bi;
+                acc3[2] += bi * (di * bi);
+            }
+        }
+        double bd[2] = {(double)bad_diag, (double)neg_diag};
+        wg_sum<kRTW, 2>(bd, sh[0]);
+        wg_sum<kRTW, 3>(acc3, sh[0]);
+        const double bn = sqrt(acc3[0]);
+        double tol = a.rtol * bn;
+        if (a.atol > tol) tol = a.atol;
+        double rho = acc3[2], rr = acc3[1];
+        int32_t status = HSLA_NOT_CONVERGED;
+        int64_t it = 0;
+        if (bd[0] > 0.0) {
+            status = HSLA_ERR_ZERO_DIAGONAL;
+        } else if (!isfinite(bn)) {
+            status = HSLA_ERR_NONFINITE;
+        } else if (sqrt(rr) <= tol) {
+            status = HSLA_OK;
+        } else if (bd[1] > 0.0) {
+            status = HSLA_BREAKDOWN;  // negative Jacobi diagonal: x stays 0
+        } else {
+            while (it < a.max_iter) {
+                // q = A p from the LDS copy of p, sigma = p.q
+                double acc1[1] = {0.0};
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    qv[j] = reg_row<K>(vv[j], cc[j], len[j], ps);
+                    acc1[0] += pv[j] * qv[j];
+                }
+                // sh[0] and sh[1] alternate, and every iteration ends with a
+                // barrier, so the sums need no closing barrier of their own
+                wg_sum<kRTW, 1, false>(acc1, sh[0]);
+                const double sigma = acc1[0];
+                if (!isfinite(sigma)) { status = HSLA_ERR_NONFINITE; break; }
+                if (!(sigma > 0.0)) { status = HSLA_BREAKDOWN; break; }
+                const double alpha = rho / sigma;
+                double acc2[2] = {0.0, 0.0};
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const int32_t i = threadIdx.x + j * kRT;
+                    if (i < n) xs[i] = xs[i] + alpha * pv[j];
+                    rv[j] = rv[j] - alpha * qv[j];
+                    acc2[0] += rv[j] * rv[j];
+                    acc2[1] += rv[j] * (dv[j] * rv[j]);
+                }
+                wg_sum<kRTW, 2, false>(acc2, sh[1]);
+                ++it;
+                rr = acc2[0];
+                const double rn = sqrt(rr);
+                if (!isfinite(rn)) { status = HSLA_ERR_NONFINITE; break; }
+                if (rn <= tol) { status = HSLA_OK; break; }
+                const double beta = acc2[1] / rho;
+                rho = acc2[1];
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const int32_t i = threadIdx.x + j * kRT;
+                    pv[j] = dv[j] * rv[j] + beta * pv[j];
+                    if (i < n) ps[i] = pv[j];
+                }
+                __syncthreads();
+            }
+        }
+        // x out, and the true residual ||b - A x|| from an LDS copy of x
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int32_t i = threadIdx.x + j * kRT;
+            if (i < n) {
+                x[i] = xs[i];
+                ps[i] = xs[i];
+            }
+        }
+        __syncthreads();
+        double accr[2] = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int32_t i = threadIdx.x + j * kRT;
+            if (i < n) {
+                const double bi = b[i];
+                const double e = bi - reg_row<K>(vv[j], cc[j], len[j], ps);
+                accr[0] += e * e;
+                accr[1] += bi * bi;
+            }
+        }
+        wg_sum<kRTW, 2>(accr, sh[0]);
+        if (threadIdx.x == 0) {
+            RInfo f;
+            f.iters = it;
+            f.status = status;
+            f.pad = 0;
+            f.rel_residual = bn > 0 ? sqrt(rr) / bn : sqrt(rr);
+            f.true_residual = accr[1] > 0 ? sqrt(accr[0]) / sqrt(accr[1]) : sqrt(accr[0]);
+            f.t_begin = t_begin;
+            f.t_end = wall_clock64();
+            a.info[s] = f;
+        }
+        __syncthreads();
+    }
+}
+
 // Carves the work vectors, launches the persistent kernel and returns the
 // per-system records.  `a` arrives with the system description set; `order`
 // (host, may be empty = identity) is the queue order.
 static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, int64_t rows, int64_t entries,
                                   int64_t max_n, const std::vector<int32_t> &order, hsla_info *infos,
                                   hipStream_t s, int small_rows = 0, int small_k = 0,
-                                  bool single_reduction = false) {
+                                  bool single_reduction = false, bool small_reg = false) {
     const int32_t B = a.B;
     // the general kernel's single-reduction form keeps two more vectors
     const bool sr_general = single_reduction && small_rows == 0;
@@ -836,7 +1033,22 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
         k_small_pcg<4, 8, SRV><<<gs, kSB, 0, s>>>(a);                        \
     else if (small_rows == 4)                                                \
         k_small_pcg<4, 16, SRV><<<gs, kSB, 0, s>>>(a);
-    if (small_rows > 0 && single_reduction) {
+    if (small_reg) {
+        if (small_k == 5 && small_rows == 1)
+            k_small_reg<1, 5><<<gs, kRT, 0, s>>>(a);
+        else if (small_k == 5 && small_rows == 2)
+            k_small_reg<2, 5><<<gs, kRT, 0, s>>>(a);
+        else if (small_k == 5 && small_rows == 4)
+            k_small_reg<4, 5><<<gs, kRT, 0, s>>>(a);
+        else if (small_k == 5)
+            k_small_reg<8, 5><<<gs, kRT, 0, s>>>(a);
+        else if (small_rows == 1)
+            k_small_reg<1, 8><<<gs, kRT, 0, s>>>(a);
+        else if (small_rows == 2)
+            k_small_reg<2, 8><<<gs, kRT, 0, s>>>(a);
+        else
+            k_small_reg<4, 8><<<gs, kRT, 0, s>>>(a);
+    } else if (small_rows > 0 && single_reduction) {
         SMALL_LAUNCH(true)
     } else if (small_rows > 0) {
         SMALL_LAUNCH(false)
@@ -1304,11 +1516,19 @@ hsla_status persistent_solve(hsla_handle *h, const hsla_pattern *p, int B, const
     a.b = b;
     a.x = x;
     int rows = 0, k = 0;
+    bool reg = false;
     if (p->n <= rg::kSmallMaxN && p->max_row <= rg::kSmallMaxRow) {
         rows = p->n <= rg::kSB ? 1 : p->n <= 2 * rg::kSB ? 2 : 4;
         k = p->max_row <= 8 ? 8 : 16;
+        // rows short enough to keep the matrix in registers (CG only)
+        if (!single_reduction && (p->max_row <= 5 || (p->max_row <= 8 && p->n <= 4 * rg::kRT))) {
+            reg = true;
+            k = p->max_row <= 5 ? 5 : 8;
+            rows = p->n <= rg::kRT ? 1 : p->n <= 2 * rg::kRT ? 2 : p->n <= 4 * rg::kRT ? 4 : 8;
+        }
     }
-    return rg::run_persistent(h, a, o, (int64_t)B * p->n, p->nnz, p->n, {}, infos, s, rows, k, single_reduction);
+    return rg::run_persistent(h, a, o, (int64_t)B * p->n, p->nnz, p->n, {}, infos, s, rows, k, single_reduction,
+                              reg);
 }
 
 }  // namespace hsla

@@ -158,6 +158,39 @@ def test_cg_poisson2d_parity(orc, precond, persistent):
     assert info[0]["true_residual"] <= 2e-12
 
 
+@pytest.mark.parametrize("make", [lambda: W.poisson2d(20), lambda: W.poisson2d(30), lambda: W.poisson2d(45),
+                                  lambda: W.poisson2d(64), lambda: W.diffusion3d(8, W.diffusion3d_kappa(8)),
+                                  lambda: W.diffusion3d(10, W.diffusion3d_kappa(10)),
+                                  lambda: W.diffusion3d(12, W.diffusion3d_kappa(12))],
+                         ids=["p20", "p30", "p45", "p64", "d8", "d10", "d12"])
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_small_systems_matrix_in_registers(orc, make, precond):
+    """Small systems with rows of at most 5 (n <= 4096) or 8 (n <= 2048)
+    entries run with the matrix held in registers, 1, 2, 4 or 8 rows per
+    thread: the oracle's solution and iteration count, the k-th iterate at a
+    cap, b = 0, and a batch member bitwise equal to its own solve."""
+    a = make()
+    r = np.random.default_rng(a.n)
+    b = r.standard_normal(a.n)
+    pat = pattern(a)
+    x, info, st = solve(a, b, pat=pat, method="cg", precond=precond, rtol=1e-12)
+    ref = orc.cg(a, b, precond=precond, rtol=1e-12)
+    assert st == 0 and info[0]["spmv_form"] == "persistent"
+    assert rel(x, ref.x) <= 1e-8
+    assert iters_close(info[0]["iters"], ref.iters), (info[0]["iters"], ref.iters)
+    assert info[0]["true_residual"] <= 5e-12
+    for k in (1, 5):
+        xk, ik, sk = solve(a, b, pat=pat, method="cg", precond=precond, rtol=1e-14, max_iter=k)
+        refk = orc.cg(a, b, precond=precond, rtol=1e-14, max_iter=k)
+        assert sk == _lib.NOT_CONVERGED and ik[0]["iters"] == k and rel(xk, refk.x) <= 1e-12
+    V = np.stack([a.val * 2.0, a.val])
+    Bm = np.stack([r.standard_normal(a.n), b])
+    X, infos, st = _lib.solve(pat, t64(V), t64(Bm), _lib.make_opts(method="cg", precond=precond, rtol=1e-12))
+    assert st == 0 and np.array_equal(X[1].cpu().numpy(), x)
+    x0, i0, st = solve(a, np.zeros(a.n), pat=pat, method="cg", precond=precond)
+    assert st == 0 and i0[0]["iters"] == 0 and not x0.any()
+
+
 @pytest.mark.parametrize("persistent", [True, False])
 def test_pcg_diffusion3d_parity(orc, persistent):
     """3D log-normal diffusion (the large workload's operator) at m = 24."""
