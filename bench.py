@@ -753,9 +753,15 @@ def run_learned(ctx, args, dev):
     gen = np.random.default_rng(0)
     model = learned.LearnedFSAI(seed=0, device=dev)
     ntr = st_train.shape[0]
+    # systems in a fresh random order each pass over the training set, each
+    # drawn once per pass (the default steps make exactly one pass)
+    order = []
 
     def sample(step):
-        idx = torch.as_tensor(gen.integers(0, ntr, args.train_batch)).to(dev)
+        nonlocal order
+        if len(order) < args.train_batch:
+            order = list(gen.permutation(ntr)) + order
+        idx = torch.as_tensor([order.pop() for _ in range(args.train_batch)]).to(dev)
         return learned.aniso_batch_values(sl, st_train[idx])
 
     _sync()
@@ -823,6 +829,7 @@ def run_learned(ctx, args, dev):
         "fell_back": int(fell), "status_learned": stl, "status_jacobi": stj, "autotune": tuning,
         "true_relative_residual_max_learned": rel_l, "true_relative_residual_max_jacobi": rel_j,
         "train_seconds": t_train, "train_steps": args.train_steps, "train_batch": args.train_batch,
+        "train_systems_seen": min(ntr, args.train_steps * args.train_batch),
         "train_probes": args.train_probes, "train_loss_first": float(np.mean(hist_loss[:5])),
         "train_loss_last": float(np.mean(hist_loss[-20:])), "iteration_histogram": hist, "mpnn_forward": mfma,
         **(oracle_learned(ctx, pa, args.oracle_aniso_systems) if not args.no_cpu_baseline else {}),
@@ -1225,7 +1232,7 @@ def main():
     ap.add_argument("--aniso-m", type=int, default=256)
     ap.add_argument("--train-systems", type=int, default=4096)
     ap.add_argument("--eval-systems", type=int, default=1024)
-    ap.add_argument("--train-steps", type=int, default=600)
+    ap.add_argument("--train-steps", type=int, default=1024, help="4096 systems / 4 per step: one pass")
     ap.add_argument("--train-batch", type=int, default=4)
     ap.add_argument("--train-probes", type=int, default=4)
     ap.add_argument("--train-lr", type=float, default=3e-3)

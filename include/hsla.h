@@ -272,6 +272,18 @@ typedef struct hsla_tune_state {
 } hsla_tune_state;
 hsla_status hsla_pattern_get_tuning(const hsla_pattern *p, hsla_tune_state *out);
 hsla_status hsla_pattern_set_tuning(hsla_pattern *p, const hsla_tune_state *in);
+/* A coloring of the pattern's columns in which two columns that share a
+ * row get different colors (greedy, columns in ascending order, each taking
+ * the smallest color free among the columns it shares a row with), so that
+ * a Jacobian with this sparsity pattern is recovered from one Jacobian-vector
+ * product per color: the product with the indicator of color c holds
+ * J_ij at row i for the one column j of color c in that row (the
+ * compression of Curtis, Powell and Reid).  d_color (int32[n], device,
+ * nullable) receives the colors, *ncolors (host) their number.  Used by the
+ * Newton solves with a general residual (Sec. "Adjoint Differentiation",
+ * paragraph "Nonlinear systems"). */
+hsla_status hsla_pattern_colors(hsla_handle *h, const hsla_pattern *p, int32_t *d_color, int32_t *ncolors,
+                                void *stream);
 /* Device copies of the transpose: row_ptr_T int32[n+1], col_T int32[nnz] and
  * src int32[nnz] with src[k'] = position in A of the entry stored at k' of
  * A^T (a bijection).  Host-visible only through the copy. */

@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import HslaError, Pattern
 
-__all__ = ["SparseCSR", "SparseCSRList", "SolveFn", "HslaError", "Pattern", "from_coo"]
+__all__ = ["SparseCSR", "SparseCSRList", "SolveFn", "SpMVFn", "HslaError", "Pattern", "from_coo"]
 
 
 class SolveFn(torch.autograd.Function):
@@ -60,6 +60,47 @@ class SolveFn(torch.autograd.Function):
         return (gA if want_gA else None), (gb if ctx.needs_input_grad[1] else None), None, None, None
 
 
+class SpMVFn(torch.autograd.Function):
+    """y = A(values) x, differentiable in reverse mode (dL/dvalues_k =
+    g[row(k)] x[col(k)] on the pattern, dL/dx = A^T g) and forward mode
+    (d y = A dx + A(d values) x), so that residuals built from it can be
+    differentiated with torch.autograd.forward_ad (the Jacobian products of
+    the general Newton solve) and torch.autograd.grad (its adjoint
+    gradient)."""
+
+    @staticmethod
+    def forward(values, x, A):
+        return _lib.spmv(A.pattern, values.detach(), x.detach().contiguous())
+
+    @staticmethod
+    def setup_context(ctx, inputs, output):
+        values, x, A = inputs
+        ctx.A = A
+        ctx.save_for_backward(values, x)
+        ctx.save_for_forward(values, x)
+
+    @staticmethod
+    def backward(ctx, g):
+        values, x = ctx.saved_tensors
+        A = ctx.A
+        g = g.contiguous()
+        gv = _lib.outer_on_pattern(A.pattern, -g, x.detach()) if ctx.needs_input_grad[0] else None
+        gx = A._transpose_mv(values.detach(), g) if ctx.needs_input_grad[1] else None
+        return gv, gx, None
+
+    @staticmethod
+    def jvp(ctx, dvalues, dx, _):
+        values, x = ctx.saved_tensors
+        A = ctx.A
+        out = None
+        if dx is not None:
+            out = _lib.spmv(A.pattern, values.detach(), dx.contiguous())
+        if dvalues is not None:
+            t = _lib.spmv(A.pattern, dvalues.contiguous(), x.detach().contiguous())
+            out = t if out is None else out + t
+        return out
+
+
 class SparseCSR:
     """A square sparse matrix (or a batch sharing one pattern) in CSR form.
 
@@ -91,6 +132,19 @@ class SparseCSR:
         return _lib.spmv(self.pattern, self.values.detach(), x)
 
     __matmul__ = matvec
+
+    def mv(self, x: torch.Tensor) -> torch.Tensor:
+        """y = A x, differentiable in the values and x (reverse and forward
+        mode; see SpMVFn)."""
+        return SpMVFn.apply(self.values, x, self)
+
+    def _transpose_mv(self, values: torch.Tensor, g: torch.Tensor) -> torch.Tensor:
+        """A^T g on the transpose pattern (built once per matrix)."""
+        if not hasattr(self, "_tpat"):
+            rpT, colT, src = self.pattern.transpose()
+            self._tpat = Pattern(rpT, colT)
+            self._tsrc = src.to(torch.int64)
+        return _lib.spmv(self._tpat, values[..., self._tsrc].contiguous(), g)
 
     def solve(self, b: torch.Tensor, *, rtol: float = 1e-8, atol: float = 0.0, method: str = "auto",
               precond: str = "jacobi", max_iter: int = 0, check_every: int = 0, graph: bool = True,

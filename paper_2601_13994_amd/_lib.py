@@ -36,7 +36,7 @@ EXPORTS = [
     "hsla_spmv", "hsla_solve", "hsla_solve_batched", "hsla_adjoint", "hsla_adjoint_batched",
     "hsla_outer_on_pattern", "hsla_residual_norms",
     "hsla_mpnn_num_params", "hsla_mpnn_forward", "hsla_mpnn_backward", "hsla_probe_loss", "hsla_adam_step",
-    "hsla_fsai_factors", "hsla_solve_ragged", "hsla_solve_noalloc", "hsla_csr_check",
+    "hsla_fsai_factors", "hsla_solve_ragged", "hsla_solve_noalloc", "hsla_csr_check", "hsla_pattern_colors",
 ]
 
 
@@ -158,6 +158,7 @@ def load() -> ctypes.CDLL:
         L.hsla_solve_ragged.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, P(Opts), P(Info), vp]
         L.hsla_solve_noalloc.argtypes = [vp, vp, i32, vp, vp, vp, P(Opts), P(Info), vp]
         L.hsla_csr_check.argtypes = [i32, i64, vp, vp, P(i32)]
+        L.hsla_pattern_colors.argtypes = [vp, vp, vp, P(i32), vp]
         _lib = L
     return _lib
 
@@ -377,6 +378,16 @@ class Pattern:
             st = load().hsla_pattern_transpose(self.h, self.p, ptr(rpT), ptr(colT), ptr(src), stream_ptr(self.device))
             check(st, self.h, "hsla_pattern_transpose")
         return rpT, colT[:self.nnz], src[:self.nnz]
+
+    def colors(self):
+        """(color int32 [n] on the device, number of colors): a column
+        coloring in which columns sharing a row differ (hsla_pattern_colors)."""
+        color = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+        nc = ctypes.c_int32()
+        with torch.cuda.device(self.device):
+            st = load().hsla_pattern_colors(self.h, self.p, ptr(color), ctypes.byref(nc), stream_ptr(self.device))
+            check(st, self.h, "hsla_pattern_colors")
+        return color[:self.n], nc.value
 
     def lower(self):
         """(row_ptr_L, col_L, pos) of the lower triangle incl. the diagonal

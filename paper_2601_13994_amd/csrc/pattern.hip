@@ -850,6 +850,53 @@ hsla_status hsla_pattern_lower(hsla_handle *h, const hsla_pattern *p, int32_t *d
     return HSLA_OK;
 }
 
+hsla_status hsla_pattern_colors(hsla_handle *h, const hsla_pattern *p, int32_t *d_color, int32_t *ncolors,
+                                void *stream) {
+    if (!h || !p || !ncolors) return hsla::set_error(h, HSLA_ERR_INVALID_ARG, "null handle, pattern or output");
+    hsla_status st = hsla::enter(h, (hipStream_t)stream);
+    if (st != HSLA_OK) return st;
+    hipStream_t s = h->stream;
+    const int32_t n = p->n;
+    const int64_t nnz = p->nnz;
+    std::vector<int32_t> rp((size_t)n + 1), col(nnz > 0 ? (size_t)nnz : 1);
+    HSLA_HIP(h, hipMemcpyAsync(rp.data(), p->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
+    if (nnz > 0) HSLA_HIP(h, hipMemcpyAsync(col.data(), p->col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
+    HSLA_HIP(h, hipStreamSynchronize(s));
+    // rows holding each column (counting sort)
+    std::vector<int32_t> cp((size_t)n + 1, 0), rows(nnz > 0 ? (size_t)nnz : 1);
+    for (int64_t k = 0; k < nnz; ++k) ++cp[col[k] + 1];
+    for (int32_t j = 0; j < n; ++j) cp[j + 1] += cp[j];
+    {
+        std::vector<int32_t> next(cp.begin(), cp.end() - 1);
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k) rows[next[col[k]]++] = i;
+    }
+    // greedy, columns in order: the smallest color no column sharing a row
+    // with column j has taken (mark[c] == j: taken)
+    std::vector<int32_t> color((size_t)n, -1), mark;
+    int32_t nc = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        for (int32_t t = cp[j]; t < cp[j + 1]; ++t) {
+            const int32_t i = rows[t];
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+                const int32_t c = color[col[k]];
+                if (c >= 0) mark[c] = j;
+            }
+        }
+        int32_t c = 0;
+        while (c < (int32_t)mark.size() && mark[c] == j) ++c;
+        if (c == (int32_t)mark.size()) mark.push_back(-1);
+        color[j] = c;
+        if (c + 1 > nc) nc = c + 1;
+    }
+    *ncolors = nc;
+    if (d_color && n > 0) {
+        HSLA_HIP(h, hipMemcpyAsync(d_color, color.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+        HSLA_HIP(h, hipStreamSynchronize(s));
+    }
+    return HSLA_OK;
+}
+
 hsla_status hsla_pattern_transpose(hsla_handle *h, const hsla_pattern *p, int32_t *d_row_ptr_T, int32_t *d_col_T,
                                    int32_t *d_src, void *stream) {
     if (!h || !p) return hsla::set_error(h, HSLA_ERR_INVALID_ARG, "null handle or pattern");

@@ -627,3 +627,27 @@ def test_cg_single_reduction_fsai_runs_cg(orc):
     assert st == 0 and info[0]["method"] == "cg"
     ref = orc.fsai_pcg(a, rpL, colL, G.cpu().numpy().astype(np.float64), b, rtol=1e-12)
     assert rel(x.cpu().numpy(), ref.x) <= 1e-8
+
+
+def _random_csr(n, density, seed):
+    rp, col = W.random_pattern(n, density, np.random.default_rng(seed))
+    return W.Csr(n, rp, col, np.ones(len(col)))
+
+
+@pytest.mark.parametrize("make", [lambda: W.poisson2d(17), lambda: W.diffusion3d(9), lambda: _random_csr(500, 0.02, 3)])
+def test_pattern_colors_separate_columns_sharing_a_row(make):
+    """hsla_pattern_colors: no two columns stored in the same row share a
+    color, and the greedy coloring uses at least the longest row's length
+    and few colors on stencils."""
+    a = make()
+    pat = pattern(a)
+    color, nc = pat.colors()
+    color = color.cpu().numpy()
+    assert color.shape == (a.n,) and color.min() >= 0 and color.max() == nc - 1
+    for i in range(a.n):
+        cs = color[a.col[a.row_ptr[i]:a.row_ptr[i + 1]]]
+        assert len(set(cs.tolist())) == len(cs)
+    longest = int(np.diff(a.row_ptr).max())
+    assert nc >= longest
+    if a.n in (17 * 17, 9 ** 3):
+        assert nc <= 2 * longest

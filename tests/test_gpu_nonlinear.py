@@ -91,3 +91,94 @@ def test_paper_fd_protocol():
     ef = np.linalg.norm(np.array(ff) - gf) / np.linalg.norm(gf)
     print("[nonlinear] fd", ea, ef, flush=True)
     assert ea <= 1e-5 and ef <= 1e-5
+
+
+# ---------------------------------------------------------------- general residuals
+
+def test_general_residual_cubic_with_parameter(orc):
+    """F(u; values, f, k) = A(values) u + k u^3 - f with k inside the
+    nonlinearity, solved by newton_solve_residual (Jacobian from colored
+    forward-mode products through SparseCSR.mv): u and the gradients w.r.t.
+    every stored value, f and k against the dense oracle."""
+    a, f, r = _problem(16, 8)
+    w = r.standard_normal(a.n)
+    vals = t64(a.val).requires_grad_(True)
+    ft = t64(f).requires_grad_(True)
+    kt = torch.tensor(0.8, dtype=torch.float64, device=dev(), requires_grad=True)
+    A = hs.SparseCSR(vals, t32(a.row_ptr), t32(a.col))
+
+    def res(u, v, ff, kk):
+        return A.with_values(v).mv(u) + kk * u ** 3 - ff
+
+    info = {}
+    u = nonlinear.newton_solve_residual(res, (vals, ft, kt), pattern=A.pattern, tol=1e-13, lin_rtol=1e-14,
+                                        info=info)
+    (t64(w) * u).sum().backward()
+    rows = torch.as_tensor(a.rows())
+    cols = torch.as_tensor(a.col.astype(np.int64))
+
+    def res_dense(uu, v, ff, kk):
+        Ad = torch.zeros(a.n, a.n, dtype=torch.float64).index_put((rows, cols), v)
+        return Ad @ uu + kk * uu ** 3 - ff
+
+    pc = (torch.as_tensor(a.val), torch.as_tensor(f), torch.tensor(0.8, dtype=torch.float64))
+    u_ref, its = ON.newton_general(res_dense, a.n, pc)
+    assert rel(u.detach().cpu().numpy(), u_ref) <= 1e-10
+    assert 5 <= info["colors"] <= 9 and info["newton_steps"] <= its + 1
+    (gv, gf, gk), _ = ON.gradients_general(res_dense, u_ref, pc, w)
+    assert rel(vals.grad.cpu().numpy(), gv) <= 1e-8
+    assert rel(ft.grad.cpu().numpy(), gf) <= 1e-8
+    assert abs(float(kt.grad) - float(gk)) <= 1e-8 * abs(float(gk))
+
+
+def test_general_residual_nonlinear_diffusion(orc):
+    """A residual with a nonsymmetric Jacobian on the 5-point pattern
+    (kappa depends on u on every face): u and dL/dkappa, dL/df against the
+    dense oracle; the Newton steps' linear solves run BiCGStab."""
+    from test_oracle_nonlinear import nl_diffusion
+
+    m = 14
+    pat_a = W.poisson2d(m)
+    r = np.random.default_rng(9)
+    kap = np.exp(0.3 * r.standard_normal(m * m))
+    f = 1.0 + 0.3 * r.standard_normal(m * m)
+    w = r.standard_normal(m * m)
+    kt = t64(kap).requires_grad_(True)
+    ft = t64(f).requires_grad_(True)
+    from gpu_common import pattern
+    pat = pattern(pat_a)
+
+    def res(u, kk, ff):
+        return nl_diffusion(u, kk, ff, m)
+
+    info = {}
+    u = nonlinear.newton_solve_residual(res, (kt, ft), pattern=pat, tol=1e-13, lin_rtol=1e-14, info=info)
+    (t64(w) * u).sum().backward()
+    pc = (torch.as_tensor(kap), torch.as_tensor(f))
+    u_ref, _ = ON.newton_general(lambda uu, a1, a2: nl_diffusion(uu, a1, a2, m), m * m, pc)
+    assert rel(u.detach().cpu().numpy(), u_ref) <= 1e-10
+    (gk, gf), _ = ON.gradients_general(lambda uu, a1, a2: nl_diffusion(uu, a1, a2, m), u_ref, pc, w)
+    assert rel(kt.grad.cpu().numpy(), gk) <= 1e-8
+    assert rel(ft.grad.cpu().numpy(), gf) <= 1e-8
+
+
+def test_general_residual_matches_semilinear_path():
+    """On F = A u + u^2 - f the general solve and the semilinear one agree:
+    u, dL/dA and dL/df."""
+    a, f, r = _problem(24, 10)
+    w = t64(r.standard_normal(a.n))
+    out = []
+    for general in (False, True):
+        vals = t64(a.val).requires_grad_(True)
+        ft = t64(f).requires_grad_(True)
+        A = hs.SparseCSR(vals, t32(a.row_ptr), t32(a.col))
+        if general:
+            u = nonlinear.newton_solve_residual(lambda uu, v, ff: A.with_values(v).mv(uu) + uu * uu - ff,
+                                                (vals, ft), pattern=A.pattern, tol=1e-13, lin_rtol=1e-14)
+        else:
+            u = nonlinear.newton_solve(A, ft, tol=1e-13, lin_rtol=1e-14)
+        (w * u).sum().backward()
+        out.append((u.detach().cpu().numpy(), vals.grad.cpu().numpy(), ft.grad.cpu().numpy()))
+    assert rel(out[1][0], out[0][0]) <= 1e-10
+    assert rel(out[1][1], out[0][1]) <= 1e-8
+    assert rel(out[1][2], out[0][2]) <= 1e-8
