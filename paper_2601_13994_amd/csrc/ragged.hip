@@ -790,34 +790,38 @@ __device__ __forceinline__ double reg_row(const double (&vv)[K], const uint32_t 
     return sum;
 }
 
-template <int R, int K>
+// SR: the single-reduction recurrence (as in k_small_pcg): s = A p is kept
+// in registers, r.u, (A u).u and r.r are one workgroup sum, and an iteration
+// has two barriers instead of three.
+template <int R, int K, bool SR>
 __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
     __shared__ double ps[kSmallMaxN];
     __shared__ double xs[kSmallMaxN];  // x of the thread's own rows (keeps registers for the matrix)
+    // SR at eight rows per thread: s = A p of the thread's own rows lives in
+    // LDS (in registers it would spill)
+    constexpr bool kSL = SR && R >= 8;
+    __shared__ double sl[kSL ? kSmallMaxN : 1];
+    __shared__ double dl[kSL ? kSmallMaxN : 1];  // and so does D^{-1}
     __shared__ double sh[2][3 * kRTW];
     __shared__ int32_t slot;
     const int32_t n = (int32_t)a.shared_n;
     // this thread's rows of the shared pattern
-    int32_t lo[R], len[R], dk[R];
+    // (row starts are re-read per system and the diagonal found in cc, so
+    // only the lengths and the packed columns stay in registers)
+    int32_t len[R];
     uint32_t cc[R][(K + 1) / 2];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int32_t i = threadIdx.x + j * kRT;
-        lo[j] = 0;
         len[j] = 0;
-        dk[j] = -1;
 #pragma unroll
         for (int u = 0; u < (K + 1) / 2; ++u) cc[j][u] = 0u;
         if (i < n) {
-            lo[j] = a.rp[i];
-            len[j] = a.rp[i + 1] - lo[j];
+            const int32_t lo = a.rp[i];
+            len[j] = a.rp[i + 1] - lo;
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                if (k < len[j]) {
-                    const int32_t c = a.col[lo[j] + k];
-                    cc[j][k / 2] |= (uint32_t)c << (16 * (k & 1));
-                    if (c == i) dk[j] = k;
-                }
+                if (k < len[j]) cc[j][k / 2] |= (uint32_t)a.col[lo + k] << (16 * (k & 1));
         }
     }
     for (;;) {
@@ -837,8 +841,9 @@ __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int32_t i = threadIdx.x + j * kRT;
+            const int32_t lo = i < n ? a.rp[i] : 0;
 #pragma unroll
-            for (int k = 0; k < K; ++k) vv[j][k] = k < len[j] ? val[lo[j] + k] : 0.0;
+            for (int k = 0; k < K; ++k) vv[j][k] = k < len[j] ? val[lo + k] : 0.0;
             rv[j] = pv[j] = qv[j] = 0.0;
             dv[j] = 1.0;
             if (i < n) {
@@ -846,12 +851,13 @@ __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
                 double d = 0.0;
 #pragma unroll
                 for (int k = 0; k < K; ++k)
-                    if (k == dk[j]) d = vv[j][k];
+                    if (k < len[j] && (int32_t)((cc[j][k / 2] >> (16 * (k & 1))) & 0xffffu) == i) d = vv[j][k];
                 if (a.jacobi && d == 0.0) bad_diag = 1;
                 if (a.jacobi && d < 0.0) neg_diag = 1;
                 const double di = a.jacobi ? 1.0 / d : 1.0;
                 const double bi = b[i];
                 dv[j] = di;
+                if constexpr (kSL) dl[i] = di;
                 rv[j] = bi;
                 pv[j] = di * bi;
                 ps[i] = pv[j];
@@ -877,6 +883,86 @@ __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
             status = HSLA_OK;
         } else if (bd[1] > 0.0) {
             status = HSLA_BREAKDOWN;  // negative Jacobi diagonal: x stays 0
+        } else if (SR) {
+            // u = D^{-1} r is p at the start (in LDS); w = A u, s = w
+            double gamma = rho, alpha = 0.0;
+            {
+                double d1[1] = {0.0};
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const int32_t i = threadIdx.x + j * kRT;
+                    const double wj = reg_row<K>(vv[j], cc[j], len[j], ps);
+                    if constexpr (kSL) {
+                        if (i < n) sl[i] = wj;
+                    } else {
+                        qv[j] = wj;
+                    }
+                    d1[0] += wj * pv[j];
+                }
+                wg_sum<kRTW, 1>(d1, sh[0]);
+                if (!isfinite(d1[0])) {
+                    status = HSLA_ERR_NONFINITE;
+                } else if (!(d1[0] > 0.0)) {
+                    status = HSLA_BREAKDOWN;
+                } else {
+                    alpha = gamma / d1[0];
+                }
+            }
+            while (status == HSLA_NOT_CONVERGED && it < a.max_iter) {
+                // x += alpha p, r -= alpha s, u = D^{-1} r (to LDS)
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const int32_t i = threadIdx.x + j * kRT;
+                    double sj;
+                    if constexpr (kSL) {
+                        sj = i < n ? sl[i] : 0.0;
+                    } else {
+                        sj = qv[j];
+                    }
+                    rv[j] = rv[j] - alpha * sj;
+                    if (i < n) {
+                        xs[i] = xs[i] + alpha * pv[j];
+                        ps[i] = (kSL ? dl[i] : dv[j]) * rv[j];
+                    }
+                }
+                ++it;
+                __syncthreads();
+                // w = A u; r.u, w.u, r.r in one sum (the barrier before the
+                // next update separates consecutive sums: no closing barrier)
+                double w[R];
+                double d3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const int32_t i = threadIdx.x + j * kRT;
+                    w[j] = reg_row<K>(vv[j], cc[j], len[j], ps);
+                    const double u = i < n ? ps[i] : 0.0;  // D^{-1} r of the own row
+                    d3[0] += rv[j] * u;
+                    d3[1] += w[j] * u;
+                    d3[2] += rv[j] * rv[j];
+                }
+                wg_sum<kRTW, 3, false>(d3, sh[it & 1]);
+                rr = d3[2];
+                const double rn = sqrt(rr);
+                if (!isfinite(rn) || !isfinite(d3[0]) || !isfinite(d3[1])) { status = HSLA_ERR_NONFINITE; break; }
+                if (rn <= tol) { status = HSLA_OK; break; }
+                const double beta = d3[0] / gamma;
+                const double curv = d3[1] - beta * d3[0] / alpha;
+                if (!(curv > 0.0)) { status = HSLA_BREAKDOWN; break; }
+                alpha = d3[0] / curv;
+                gamma = d3[0];
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    // u of the own rows is re-read from LDS rather than kept
+                    // live across the sum
+                    const int32_t i = threadIdx.x + j * kRT;
+                    pv[j] = (i < n ? ps[i] : 0.0) + beta * pv[j];
+                    if constexpr (kSL) {
+                        if (i < n) sl[i] = w[j] + beta * sl[i];
+                    } else {
+                        qv[j] = w[j] + beta * qv[j];
+                    }
+                }
+            }
         } else {
             while (it < a.max_iter) {
                 // q = A p from the LDS copy of p, sigma = p.q
@@ -1033,21 +1119,25 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
         k_small_pcg<4, 8, SRV><<<gs, kSB, 0, s>>>(a);                        \
     else if (small_rows == 4)                                                \
         k_small_pcg<4, 16, SRV><<<gs, kSB, 0, s>>>(a);
-    if (small_reg) {
-        if (small_k == 5 && small_rows == 1)
-            k_small_reg<1, 5><<<gs, kRT, 0, s>>>(a);
-        else if (small_k == 5 && small_rows == 2)
-            k_small_reg<2, 5><<<gs, kRT, 0, s>>>(a);
-        else if (small_k == 5 && small_rows == 4)
-            k_small_reg<4, 5><<<gs, kRT, 0, s>>>(a);
-        else if (small_k == 5)
-            k_small_reg<8, 5><<<gs, kRT, 0, s>>>(a);
-        else if (small_rows == 1)
-            k_small_reg<1, 8><<<gs, kRT, 0, s>>>(a);
-        else if (small_rows == 2)
-            k_small_reg<2, 8><<<gs, kRT, 0, s>>>(a);
-        else
-            k_small_reg<4, 8><<<gs, kRT, 0, s>>>(a);
+#define REG_LAUNCH(SRV)                                         \
+    if (small_k == 5 && small_rows == 1)                        \
+        k_small_reg<1, 5, SRV><<<gs, kRT, 0, s>>>(a);           \
+    else if (small_k == 5 && small_rows == 2)                   \
+        k_small_reg<2, 5, SRV><<<gs, kRT, 0, s>>>(a);           \
+    else if (small_k == 5 && small_rows == 4)                   \
+        k_small_reg<4, 5, SRV><<<gs, kRT, 0, s>>>(a);           \
+    else if (small_k == 5)                                      \
+        k_small_reg<8, 5, SRV><<<gs, kRT, 0, s>>>(a);           \
+    else if (small_rows == 1)                                   \
+        k_small_reg<1, 8, SRV><<<gs, kRT, 0, s>>>(a);           \
+    else if (small_rows == 2)                                   \
+        k_small_reg<2, 8, SRV><<<gs, kRT, 0, s>>>(a);           \
+    else                                                        \
+        k_small_reg<4, 8, SRV><<<gs, kRT, 0, s>>>(a);
+    if (small_reg && single_reduction) {
+        REG_LAUNCH(true)
+    } else if (small_reg) {
+        REG_LAUNCH(false)
     } else if (small_rows > 0 && single_reduction) {
         SMALL_LAUNCH(true)
     } else if (small_rows > 0) {
@@ -1058,6 +1148,7 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
         k_ragged_pcg<<<gr, kRB, 0, s>>>(a);
     }
 #undef SMALL_LAUNCH
+#undef REG_LAUNCH
     HSLA_HIP(h, hipGetLastError());
     std::vector<RInfo> hi(B);
     HSLA_HIP(h, hipMemcpyAsync(hi.data(), a.info, sizeof(RInfo) * B, hipMemcpyDeviceToHost, s));
@@ -1520,8 +1611,8 @@ hsla_status persistent_solve(hsla_handle *h, const hsla_pattern *p, int B, const
     if (p->n <= rg::kSmallMaxN && p->max_row <= rg::kSmallMaxRow) {
         rows = p->n <= rg::kSB ? 1 : p->n <= 2 * rg::kSB ? 2 : 4;
         k = p->max_row <= 8 ? 8 : 16;
-        // rows short enough to keep the matrix in registers (CG only)
-        if (!single_reduction && (p->max_row <= 5 || (p->max_row <= 8 && p->n <= 4 * rg::kRT))) {
+        // rows short enough to keep the matrix in registers
+        if (p->max_row <= 5 || (p->max_row <= 8 && p->n <= 4 * rg::kRT)) {
             reg = true;
             k = p->max_row <= 5 ? 5 : 8;
             rows = p->n <= rg::kRT ? 1 : p->n <= 2 * rg::kRT ? 2 : p->n <= 4 * rg::kRT ? 4 : 8;

@@ -164,30 +164,34 @@ def test_cg_poisson2d_parity(orc, precond, persistent):
                                   lambda: W.diffusion3d(12, W.diffusion3d_kappa(12))],
                          ids=["p20", "p30", "p45", "p64", "d8", "d10", "d12"])
 @pytest.mark.parametrize("precond", ["none", "jacobi"])
-def test_small_systems_matrix_in_registers(orc, make, precond):
+@pytest.mark.parametrize("method", ["cg", "cg_sr"])
+def test_small_systems_matrix_in_registers(orc, make, precond, method):
     """Small systems with rows of at most 5 (n <= 4096) or 8 (n <= 2048)
     entries run with the matrix held in registers, 1, 2, 4 or 8 rows per
-    thread: the oracle's solution and iteration count, the k-th iterate at a
-    cap, b = 0, and a batch member bitwise equal to its own solve."""
+    thread, by CG and by the single-reduction recurrence: the oracle's
+    solution and iteration count, the k-th iterate at a cap, breakdown on
+    -A, b = 0, and a batch member bitwise equal to its own solve."""
     a = make()
     r = np.random.default_rng(a.n)
     b = r.standard_normal(a.n)
     pat = pattern(a)
-    x, info, st = solve(a, b, pat=pat, method="cg", precond=precond, rtol=1e-12)
+    x, info, st = solve(a, b, pat=pat, method=method, precond=precond, rtol=1e-12)
     ref = orc.cg(a, b, precond=precond, rtol=1e-12)
-    assert st == 0 and info[0]["spmv_form"] == "persistent"
+    assert st == 0 and info[0]["spmv_form"] == "persistent" and info[0]["method"] == method
     assert rel(x, ref.x) <= 1e-8
     assert iters_close(info[0]["iters"], ref.iters), (info[0]["iters"], ref.iters)
     assert info[0]["true_residual"] <= 5e-12
     for k in (1, 5):
-        xk, ik, sk = solve(a, b, pat=pat, method="cg", precond=precond, rtol=1e-14, max_iter=k)
+        xk, ik, sk = solve(a, b, pat=pat, method=method, precond=precond, rtol=1e-14, max_iter=k)
         refk = orc.cg(a, b, precond=precond, rtol=1e-14, max_iter=k)
         assert sk == _lib.NOT_CONVERGED and ik[0]["iters"] == k and rel(xk, refk.x) <= 1e-12
-    V = np.stack([a.val * 2.0, a.val])
-    Bm = np.stack([r.standard_normal(a.n), b])
-    X, infos, st = _lib.solve(pat, t64(V), t64(Bm), _lib.make_opts(method="cg", precond=precond, rtol=1e-12))
-    assert st == 0 and np.array_equal(X[1].cpu().numpy(), x)
-    x0, i0, st = solve(a, np.zeros(a.n), pat=pat, method="cg", precond=precond)
+    V = np.stack([a.val * 2.0, a.val, -a.val])
+    Bm = np.stack([r.standard_normal(a.n), b, b])
+    X, infos, st = _lib.solve(pat, t64(V), t64(Bm), _lib.make_opts(method=method, precond=precond, rtol=1e-12))
+    assert st == _lib.BREAKDOWN and infos[2]["status"] == _lib.BREAKDOWN
+    assert infos[0]["status"] == 0 and infos[1]["status"] == 0
+    assert np.array_equal(X[1].cpu().numpy(), x)
+    x0, i0, st = solve(a, np.zeros(a.n), pat=pat, method=method, precond=precond)
     assert st == 0 and i0[0]["iters"] == 0 and not x0.any()
 
 
@@ -537,14 +541,15 @@ def test_persistent_shared_mode_batch(orc):
 
 
 @pytest.mark.parametrize("name,make", [
-    ("poisson64", lambda: W.poisson2d(64)),                 # 4 rows per thread, 5 entries
-    ("poisson30", lambda: W.poisson2d(30)),                 # 1 row per thread
-    ("poisson40", lambda: W.poisson2d(40)),                 # 2 rows per thread
-    ("aniso9", lambda: W.aniso2d(60, 50.0, 0.6)),           # 9 entries per row
+    ("poisson64", lambda: W.poisson2d(64)),                 # matrix in registers, 8 rows per thread
+    ("poisson30", lambda: W.poisson2d(30)),                 # in registers, 2 rows per thread
+    ("poisson40", lambda: W.poisson2d(40)),                 # in registers, 4 rows per thread
+    ("aniso9", lambda: W.aniso2d(60, 50.0, 0.6)),           # 9 entries per row: matrix streamed, K = 16
+    ("diff15", lambda: W.diffusion3d(15, W.diffusion3d_kappa(15))),  # n = 3375, 7 entries: streamed, K = 8
 ])
 @pytest.mark.parametrize("precond", ["none", "jacobi"])
 def test_cg_single_reduction_parity(orc, name, make, precond):
-    """CG_SR (the Chronopoulos-Gear recurrence in the small-system kernel)
+    """CG_SR (the Chronopoulos-Gear recurrence in the small-system kernels)
     against the oracle's Algorithm-1 CG: same solution, iteration counts
     within max(2, 2%), reported as CG_SR; capped and singular cases."""
     a = make()
