@@ -857,7 +857,7 @@ __device__ __forceinline__ void full_pair(const Stencil &sn, const double *__res
             v0[s] = 1.0;
             v1[s] = 1.0;
         } else {
-            const dpair t = *(const dpair *)(base + (UF && s > DS ? s - 1 : s) * kDiaChunk);
+            const dpair t = __builtin_nontemporal_load((const dpair *)(base + (UF && s > DS ? s - 1 : s) * kDiaChunk));
             v0[s] = t.x;
             v1[s] = t.y;
         }
@@ -973,8 +973,9 @@ __device__ __forceinline__ void spmv_dia_full(const Stencil &sn, const VT *__res
 
 // The half form's SpMV (see kSymNS): the same products as spmv_dia, added
 // in the same ascending diagonal order, so the result is bitwise that of the
-// full copy, the tiles and CSR.  The upper and main diagonals stream; the
-// lower ones are re-reads of the mirrored upper entries.  Along a pencil the
+// full copy, the tiles and CSR.  The upper and main diagonals stream
+// (nontemporal loads: each entry is read once per sweep); the lower ones are
+// re-reads of the mirrored upper entries.  Along a pencil the
 // previous plane's +o_max values are, in registers, this plane's -o_max
 // values, and x moves the same way: the previous plane's own x is this
 // plane's x at -o_max, and its x at +o_max is this plane's own x.  When o_max
@@ -1022,8 +1023,8 @@ __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restric
             v1[s] = VT(1);
             v2[s] = VT(1);
         } else if (s >= DS) {
-            v1[s] = base[(s - U0) * kDiaChunk];
-            v2[s] = base[(s - U0) * kDiaChunk + kBlock];
+            v1[s] = __builtin_nontemporal_load(&base[(s - U0) * kDiaChunk]);
+            v2[s] = __builtin_nontemporal_load(&base[(s - U0) * kDiaChunk + kBlock]);
         } else if (CONT && s == 0) {
             v1[s] = cy.v0;
             v2[s] = cy.v1;
@@ -1085,7 +1086,7 @@ __device__ __forceinline__ void sym_pair(const Stencil &sn, const VT *__restrict
             v0[s] = VT(1);
             v1[s] = VT(1);
         } else if (s >= DS) {
-            const dpair t = *(const dpair *)(base + (s - U0) * kDiaChunk);
+            const dpair t = __builtin_nontemporal_load((const dpair *)(base + (s - U0) * kDiaChunk));
             v0[s] = t.x;
             v1[s] = t.y;
         } else if (CONT && s == 0) {

@@ -237,7 +237,8 @@ def _grid7(nx, ny, nz, seed, keep=None):
 
 @pytest.mark.parametrize("shape,keep", [((32, 32, 37), None), ((32, 32, 37), 37788), ((512, 20, 1), None),
                                         ((16, 32, 29), 14500), ((64, 64, 21), 85000), ((37, 41, 1), None),
-                                        ((100, 30, 7), 20000)])
+                                        ((100, 30, 7), 20000), ((256, 16, 5), None), ((256, 16, 5), 18000),
+                                        ((256, 12, 4), None)])
 def test_half_form_spmv_bitwise(orc, shape, keep):
     """The symmetric half form (main + upper diagonals stored; pencil walk
     when the largest offset is a whole number of 512-row chunks, chunk walk
