@@ -91,8 +91,11 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV], double *sh) {
 // and each lane adds the products of its row in ascending order.  The next
 // block's row pointers, and the next chunk's values and column indices, are
 // loaded while the current block or chunk is processed.
-// epi(i, y_i) runs on the lane that owns row i.
-template <int NW, class Epi>
+// epi(i, y_i) runs on the lane that owns row i.  NT: the values and column
+// indices are read with nontemporal loads (a pass over a whole batch that
+// the caches cannot hold; the persistent kernels, which re-read one system's
+// matrix every iteration, keep the default policy).
+template <int NW, class Epi, bool NT = false>
 __device__ __forceinline__ void wg_spmv(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                         const double *__restrict__ val, const double *__restrict__ v, double *lds,
                                         Epi &&epi) {
@@ -127,8 +130,8 @@ __device__ __forceinline__ void wg_spmv(int32_t n, const int32_t *__restrict__ r
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int32_t e = e0 + u * kWave + lane;
-                vv[u] = e < e1 ? val[e] : 0.0;
-                cv[u] = e < e1 ? col[e] : 0;
+                vv[u] = e < e1 ? (NT ? __builtin_nontemporal_load(&val[e]) : val[e]) : 0.0;
+                cv[u] = e < e1 ? (NT ? __builtin_nontemporal_load(&col[e]) : col[e]) : 0;
             }
         }
         have = false;
@@ -145,8 +148,8 @@ __device__ __forceinline__ void wg_spmv(int32_t n, const int32_t *__restrict__ r
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int32_t e = ns + u * kWave + lane;
-                nv[u] = e < ne ? val[e] : 0.0;
-                nc[u] = e < ne ? col[e] : 0;
+                nv[u] = e < ne ? (NT ? __builtin_nontemporal_load(&val[e]) : val[e]) : 0.0;
+                nc[u] = e < ne ? (NT ? __builtin_nontemporal_load(&col[e]) : col[e]) : 0;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -1319,11 +1322,12 @@ __global__ __launch_bounds__(kBlock) void k_seg_spmv_dot(Seg g) {
     const double *p = a.p + k.r0;
     double *q = a.q + k.r0;
     double acc[1] = {0.0};
-    wg_spmv<kSegW>(k.hi - k.lo, k.rp + k.lo, a.col + k.k0, a.val + k.k0, p, lds, [&](int32_t i, double sum) {
+    auto epi = [&](int32_t i, double sum) {
         const int32_t row = k.lo + i;
-        q[row] = sum;
+        __builtin_nontemporal_store(sum, &q[row]);
         acc[0] += p[row] * sum;
-    });
+    };
+    wg_spmv<kSegW, decltype(epi) &, true>(k.hi - k.lo, k.rp + k.lo, a.col + k.k0, a.val + k.k0, p, lds, epi);
     seg_partial<1>(g, c, acc);
 }
 
@@ -1351,9 +1355,9 @@ __global__ __launch_bounds__(kBlock) void k_seg_update(Seg g) {
         for (int u = 0; u < 2; ++u) {
             const int32_t j = i + u * kBlock;
             if (j < k.hi) {
-                rv[u] = a.r[k.r0 + j];
-                qv[u] = a.q[k.r0 + j];
-                dv[u] = a.dinv[k.r0 + j];
+                rv[u] = __builtin_nontemporal_load(&a.r[k.r0 + j]);
+                qv[u] = __builtin_nontemporal_load(&a.q[k.r0 + j]);
+                dv[u] = __builtin_nontemporal_load(&a.dinv[k.r0 + j]);
             }
         }
 #pragma unroll
@@ -1361,7 +1365,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_update(Seg g) {
             const int32_t j = i + u * kBlock;
             if (j < k.hi) {
                 const double ri = rv[u] - alpha * qv[u];
-                a.r[k.r0 + j] = ri;
+                __builtin_nontemporal_store(ri, &a.r[k.r0 + j]);
                 acc[0] += ri * ri;
                 acc[1] += ri * (dv[u] * ri);
             }
@@ -1398,11 +1402,11 @@ __global__ __launch_bounds__(kBlock) void k_seg_direction(Seg g) {
         for (int u = 0; u < 2; ++u) {
             const int32_t j = i + u * kBlock;
             if (j < k.hi) {
-                xv[u] = a.x[k.r0 + j];
-                pv[u] = a.p[k.r0 + j];
+                xv[u] = __builtin_nontemporal_load(&a.x[k.r0 + j]);
+                pv[u] = __builtin_nontemporal_load(&a.p[k.r0 + j]);
                 if (!xonly) {
-                    rv[u] = a.r[k.r0 + j];
-                    dv[u] = a.dinv[k.r0 + j];
+                    rv[u] = __builtin_nontemporal_load(&a.r[k.r0 + j]);
+                    dv[u] = __builtin_nontemporal_load(&a.dinv[k.r0 + j]);
                 }
             }
         }
@@ -1410,8 +1414,8 @@ __global__ __launch_bounds__(kBlock) void k_seg_direction(Seg g) {
         for (int u = 0; u < 2; ++u) {
             const int32_t j = i + u * kBlock;
             if (j < k.hi) {
-                a.x[k.r0 + j] = xv[u] + alpha * pv[u];
-                if (!xonly) a.p[k.r0 + j] = dv[u] * rv[u] + beta * pv[u];
+                __builtin_nontemporal_store(xv[u] + alpha * pv[u], &a.x[k.r0 + j]);
+                if (!xonly) __builtin_nontemporal_store(dv[u] * rv[u] + beta * pv[u], &a.p[k.r0 + j]);
             }
         }
     }
