@@ -1232,8 +1232,8 @@ def main():
     ap.add_argument("--aniso-m", type=int, default=256)
     ap.add_argument("--train-systems", type=int, default=4096)
     ap.add_argument("--eval-systems", type=int, default=1024)
-    ap.add_argument("--train-steps", type=int, default=1024, help="4096 systems / 4 per step: one pass")
-    ap.add_argument("--train-batch", type=int, default=4)
+    ap.add_argument("--train-steps", type=int, default=256, help="4096 systems / 16 per step: one pass")
+    ap.add_argument("--train-batch", type=int, default=16)
     ap.add_argument("--train-probes", type=int, default=4)
     ap.add_argument("--train-lr", type=float, default=3e-3)
     ap.add_argument("--oracle-adj-systems", type=int, default=2, help="systems of the oracle's adjoint timing")
