@@ -395,7 +395,40 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
     }
     if args.csr_line:
         top["csr_path"] = run_diffusion_csr(pat, vals, bt, kw, n, nnz, args)
+    top["single_reduction"] = run_single_reduction(pat, vals, bt, kw, args, ms_step, iters)
     return top, iters
+
+
+# kernel launches per iteration of the per-iteration path: CG runs SpMV+dot,
+# alpha finalize, update, beta finalize, direction; the single-reduction
+# recurrence runs SpMV with both dots, one finalize, one vector sweep
+CG_LAUNCHES_PER_ITERATION, SR_LAUNCHES_PER_ITERATION = 5, 3
+
+
+def run_single_reduction(pat, vals, bt, kw, args, ms_cg, iters_cg, B=1):
+    """The same solve(s) with the single-reduction recurrence (CG_SR:
+    Chronopoulos and Gear), against the two-reduction schedule just timed."""
+    from paper_2601_13994_amd import _lib
+
+    opts = _lib.make_opts(**dict(kw, method="cg_sr"))
+    _lib.solve(pat, vals, bt, opts)
+    _sync()
+    t0 = time.perf_counter()
+    reps = max(1, args.sub_steps)
+    for _ in range(reps):
+        _, infos, st = _lib.solve(pat, vals, bt, opts)
+    _sync()
+    dt = (time.perf_counter() - t0) / reps
+    it = max(f["iters"] for f in infos)
+    return {
+        "method": infos[0]["method"], "status": st, "iterations_max": it,
+        "iterations_two_reduction": iters_cg, "ms_per_solve": dt * 1e3,
+        "ms_per_iteration": dt * 1e3 / max(it, 1),
+        "two_reduction_ms_per_iteration": ms_cg / max(iters_cg, 1),
+        "launches_per_iteration": SR_LAUNCHES_PER_ITERATION,
+        "two_reduction_launches_per_iteration": CG_LAUNCHES_PER_ITERATION,
+        "true_relative_residual_max": max(f["true_residual"] for f in infos), "systems": B, "reps": reps,
+    }
 
 
 def run_diffusion_csr(pat, vals, bt, kw, n, nnz, args):
@@ -691,6 +724,18 @@ def run_adjoint(ctx, args, dev):
     dt = (time.perf_counter() - t0) / args.sub_steps
     itf = np.array([f["iters"] for f in fi])
     itb = np.array([f["iters"] for f in bi])
+    # the forward solves alone, two-reduction CG against the single-reduction
+    # recurrence (the batch runs until its slowest system stops)
+    _lib.solve(pat, vals, bt, opts)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.sub_steps):
+        _lib.solve(pat, vals, bt, opts)
+    _sync()
+    t_fwd = (time.perf_counter() - t0) / args.sub_steps
+    sr = run_single_reduction(pat, vals, bt, dict(method="cg", precond="jacobi", rtol=1e-8), args,
+                              t_fwd * 1e3, int(itf.max()), B)
+    sr["two_reduction_ms_per_solve"] = t_fwd * 1e3
     # per system per iteration: the operator's values in the form used (the
     # row masks or CSR indices, shared by the batch, amortised over B) + 88n
     # (p gathered, q written: 16n; update and direction: 72n)
@@ -711,7 +756,7 @@ def run_adjoint(ctx, args, dev):
         "iterations_forward_mean": float(itf.mean()), "iterations_adjoint_mean": float(itb.mean()),
         "true_relative_residual_max": max(max(f["true_residual"] for f in fi), max(f["true_residual"] for f in bi)),
         "model_GBps": work / dt / 1e9, "model_frac_of_peak": work / dt / 1e9 / HBM_PEAK_GBPS,
-        "reps": args.sub_steps,
+        "reps": args.sub_steps, "forward_single_reduction": sr,
         **(oracle_adjoint(ctx, args.oracle_adj_systems) if not args.no_cpu_baseline else {}),
     }
 

@@ -770,26 +770,28 @@ __global__ __launch_bounds__(kSB) void k_small_pcg(Args a) {
 // n <= 2048): the same recurrence as k_small_pcg (plain CG or Jacobi-PCG,
 // Algorithm "Distributed CG" on one workgroup) with the matrix itself held in
 // registers.  512 threads; thread t owns rows t + 512 j (R of them) and
-// keeps their column indices (two 16-bit indices per register, loaded once
-// per launch: the pattern is shared) and the current system's values
-// (loaded once per system), so an iteration reads nothing but the LDS copy
-// of p.  Each row adds its products in ascending column order, products
-// rounded before the add.
+// keeps their columns (as LDS byte offsets, two 16-bit offsets per
+// register, loaded once per launch: the pattern is shared) and the current
+// system's values (loaded once per system), so an iteration reads nothing
+// but the LDS copy of p.  Each row adds its products in ascending column
+// order, products rounded before the add; the K - len slots past a row's
+// entries hold value 0 at offset 0, and their products (0 times a finite
+// p) leave the sum as it is, so the row loop has no branches.
 constexpr int kRT = 512;
 constexpr int kRTW = kRT / kWave;
+static_assert(kSmallMaxN * 8 <= 65536, "column byte offsets are packed in 16 bits");
 
 template <int K>
-__device__ __forceinline__ double reg_row(const double (&vv)[K], const uint32_t (&cc)[(K + 1) / 2], int32_t len,
+__device__ __forceinline__ double reg_row(const double (&vv)[K], const uint32_t (&cc)[(K + 1) / 2],
                                           const double *v) {
 #pragma clang fp contract(off)
     double sum = 0.0;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-        if (k < len) {
-            const uint32_t c = (cc[k / 2] >> (16 * (k & 1))) & 0xffffu;
-            const double prd = vv[k] * v[c];
-            sum = sum + prd;
-        }
+    for (int k = 0; k < K; ++k) {
+        const uint32_t off = (k & 1) ? cc[k / 2] >> 16 : cc[k / 2] & 0xffffu;
+        const double prd = vv[k] * *(const double *)((const char *)v + off);
+        sum = sum + prd;
+    }
     return sum;
 }
 
@@ -800,11 +802,7 @@ template <int R, int K, bool SR>
 __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
     __shared__ double ps[kSmallMaxN];
     __shared__ double xs[kSmallMaxN];  // x of the thread's own rows (keeps registers for the matrix)
-    // SR at eight rows per thread: s = A p of the thread's own rows lives in
-    // LDS (in registers it would spill)
-    constexpr bool kSL = SR && R >= 8;
-    __shared__ double sl[kSL ? kSmallMaxN : 1];
-    __shared__ double dl[kSL ? kSmallMaxN : 1];  // and so does D^{-1}
+    static_assert(!SR || R <= 4, "the single-reduction recurrence keeps s in registers: at most 4 rows");
     __shared__ double sh[2][3 * kRTW];
     __shared__ int32_t slot;
     const int32_t n = (int32_t)a.shared_n;
@@ -824,7 +822,7 @@ __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
             len[j] = a.rp[i + 1] - lo;
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                if (k < len[j]) cc[j][k / 2] |= (uint32_t)a.col[lo + k] << (16 * (k & 1));
+                if (k < len[j]) cc[j][k / 2] |= (uint32_t)a.col[lo + k] * 8u << (16 * (k & 1));
         }
     }
     for (;;) {
@@ -854,13 +852,12 @@ __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
                 double d = 0.0;
 #pragma unroll
                 for (int k = 0; k < K; ++k)
-                    if (k < len[j] && (int32_t)((cc[j][k / 2] >> (16 * (k & 1))) & 0xffffu) == i) d = vv[j][k];
+                    if (k < len[j] && (int32_t)((cc[j][k / 2] >> (16 * (k & 1))) & 0xffffu) == 8 * i) d = vv[j][k];
                 if (a.jacobi && d == 0.0) bad_diag = 1;
                 if (a.jacobi && d < 0.0) neg_diag = 1;
                 const double di = a.jacobi ? 1.0 / d : 1.0;
                 const double bi = b[i];
                 dv[j] = di;
-                if constexpr (kSL) dl[i] = di;
                 rv[j] = bi;
                 pv[j] = di * bi;
                 ps[i] = pv[j];
@@ -894,12 +891,8 @@ __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
                     const int32_t i = threadIdx.x + j * kRT;
-                    const double wj = reg_row<K>(vv[j], cc[j], len[j], ps);
-                    if constexpr (kSL) {
-                        if (i < n) sl[i] = wj;
-                    } else {
-                        qv[j] = wj;
-                    }
+                    const double wj = reg_row<K>(vv[j], cc[j], ps);
+                    qv[j] = wj;
                     d1[0] += wj * pv[j];
                 }
                 wg_sum<kRTW, 1>(d1, sh[0]);
@@ -916,16 +909,10 @@ __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
                     const int32_t i = threadIdx.x + j * kRT;
-                    double sj;
-                    if constexpr (kSL) {
-                        sj = i < n ? sl[i] : 0.0;
-                    } else {
-                        sj = qv[j];
-                    }
-                    rv[j] = rv[j] - alpha * sj;
+                    rv[j] = rv[j] - alpha * qv[j];
                     if (i < n) {
                         xs[i] = xs[i] + alpha * pv[j];
-                        ps[i] = (kSL ? dl[i] : dv[j]) * rv[j];
+                        ps[i] = dv[j] * rv[j];
                     }
                 }
                 ++it;
@@ -937,7 +924,7 @@ __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
                     const int32_t i = threadIdx.x + j * kRT;
-                    w[j] = reg_row<K>(vv[j], cc[j], len[j], ps);
+                    w[j] = reg_row<K>(vv[j], cc[j], ps);
                     const double u = i < n ? ps[i] : 0.0;  // D^{-1} r of the own row
                     d3[0] += rv[j] * u;
                     d3[1] += w[j] * u;
@@ -959,11 +946,7 @@ __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
                     // live across the sum
                     const int32_t i = threadIdx.x + j * kRT;
                     pv[j] = (i < n ? ps[i] : 0.0) + beta * pv[j];
-                    if constexpr (kSL) {
-                        if (i < n) sl[i] = w[j] + beta * sl[i];
-                    } else {
-                        qv[j] = w[j] + beta * qv[j];
-                    }
+                    qv[j] = w[j] + beta * qv[j];
                 }
             }
         } else {
@@ -972,7 +955,7 @@ __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
                 double acc1[1] = {0.0};
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
-                    qv[j] = reg_row<K>(vv[j], cc[j], len[j], ps);
+                    qv[j] = reg_row<K>(vv[j], cc[j], ps);
                     acc1[0] += pv[j] * qv[j];
                 }
                 // sh[0] and sh[1] alternate, and every iteration ends with a
@@ -1025,7 +1008,7 @@ __global__ __launch_bounds__(kRT) void k_small_reg(Args a) {
             const int32_t i = threadIdx.x + j * kRT;
             if (i < n) {
                 const double bi = b[i];
-                const double e = bi - reg_row<K>(vv[j], cc[j], len[j], ps);
+                const double e = bi - reg_row<K>(vv[j], cc[j], ps);
                 accr[0] += e * e;
                 accr[1] += bi * bi;
             }
@@ -1122,25 +1105,34 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
         k_small_pcg<4, 8, SRV><<<gs, kSB, 0, s>>>(a);                        \
     else if (small_rows == 4)                                                \
         k_small_pcg<4, 16, SRV><<<gs, kSB, 0, s>>>(a);
-#define REG_LAUNCH(SRV)                                         \
-    if (small_k == 5 && small_rows == 1)                        \
-        k_small_reg<1, 5, SRV><<<gs, kRT, 0, s>>>(a);           \
-    else if (small_k == 5 && small_rows == 2)                   \
-        k_small_reg<2, 5, SRV><<<gs, kRT, 0, s>>>(a);           \
-    else if (small_k == 5 && small_rows == 4)                   \
-        k_small_reg<4, 5, SRV><<<gs, kRT, 0, s>>>(a);           \
-    else if (small_k == 5)                                      \
-        k_small_reg<8, 5, SRV><<<gs, kRT, 0, s>>>(a);           \
-    else if (small_rows == 1)                                   \
-        k_small_reg<1, 8, SRV><<<gs, kRT, 0, s>>>(a);           \
-    else if (small_rows == 2)                                   \
-        k_small_reg<2, 8, SRV><<<gs, kRT, 0, s>>>(a);           \
-    else                                                        \
-        k_small_reg<4, 8, SRV><<<gs, kRT, 0, s>>>(a);
     if (small_reg && single_reduction) {
-        REG_LAUNCH(true)
+        if (small_k == 5 && small_rows == 1)
+            k_small_reg<1, 5, true><<<gs, kRT, 0, s>>>(a);
+        else if (small_k == 5 && small_rows == 2)
+            k_small_reg<2, 5, true><<<gs, kRT, 0, s>>>(a);
+        else if (small_k == 5)
+            k_small_reg<4, 5, true><<<gs, kRT, 0, s>>>(a);
+        else if (small_rows == 1)
+            k_small_reg<1, 8, true><<<gs, kRT, 0, s>>>(a);
+        else if (small_rows == 2)
+            k_small_reg<2, 8, true><<<gs, kRT, 0, s>>>(a);
+        else
+            k_small_reg<4, 8, true><<<gs, kRT, 0, s>>>(a);
     } else if (small_reg) {
-        REG_LAUNCH(false)
+        if (small_k == 5 && small_rows == 1)
+            k_small_reg<1, 5, false><<<gs, kRT, 0, s>>>(a);
+        else if (small_k == 5 && small_rows == 2)
+            k_small_reg<2, 5, false><<<gs, kRT, 0, s>>>(a);
+        else if (small_k == 5 && small_rows == 4)
+            k_small_reg<4, 5, false><<<gs, kRT, 0, s>>>(a);
+        else if (small_k == 5)
+            k_small_reg<8, 5, false><<<gs, kRT, 0, s>>>(a);
+        else if (small_rows == 1)
+            k_small_reg<1, 8, false><<<gs, kRT, 0, s>>>(a);
+        else if (small_rows == 2)
+            k_small_reg<2, 8, false><<<gs, kRT, 0, s>>>(a);
+        else
+            k_small_reg<4, 8, false><<<gs, kRT, 0, s>>>(a);
     } else if (small_rows > 0 && single_reduction) {
         SMALL_LAUNCH(true)
     } else if (small_rows > 0) {
@@ -1151,7 +1143,6 @@ static hsla_status run_persistent(hsla_handle *h, Args a, const hsla_opts &o, in
         k_ragged_pcg<<<gr, kRB, 0, s>>>(a);
     }
 #undef SMALL_LAUNCH
-#undef REG_LAUNCH
     HSLA_HIP(h, hipGetLastError());
     std::vector<RInfo> hi(B);
     HSLA_HIP(h, hipMemcpyAsync(hi.data(), a.info, sizeof(RInfo) * B, hipMemcpyDeviceToHost, s));
@@ -1615,8 +1606,11 @@ hsla_status persistent_solve(hsla_handle *h, const hsla_pattern *p, int B, const
     if (p->n <= rg::kSmallMaxN && p->max_row <= rg::kSmallMaxRow) {
         rows = p->n <= rg::kSB ? 1 : p->n <= 2 * rg::kSB ? 2 : 4;
         k = p->max_row <= 8 ? 8 : 16;
-        // rows short enough to keep the matrix in registers
-        if (p->max_row <= 5 || (p->max_row <= 8 && p->n <= 4 * rg::kRT)) {
+        // rows short enough to keep the matrix in registers (the
+        // single-reduction recurrence, which keeps s = A p there as well, at
+        // up to 4 rows per thread)
+        if ((p->max_row <= 5 || (p->max_row <= 8 && p->n <= 4 * rg::kRT)) &&
+            !(single_reduction && p->n > 4 * rg::kRT)) {
             reg = true;
             k = p->max_row <= 5 ? 5 : 8;
             rows = p->n <= rg::kRT ? 1 : p->n <= 2 * rg::kRT ? 2 : p->n <= 4 * rg::kRT ? 4 : 8;

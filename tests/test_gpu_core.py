@@ -168,9 +168,10 @@ def test_cg_poisson2d_parity(orc, precond, persistent):
 def test_small_systems_matrix_in_registers(orc, make, precond, method):
     """Small systems with rows of at most 5 (n <= 4096) or 8 (n <= 2048)
     entries run with the matrix held in registers, 1, 2, 4 or 8 rows per
-    thread, by CG and by the single-reduction recurrence: the oracle's
-    solution and iteration count, the k-th iterate at a cap, breakdown on
-    -A, b = 0, and a batch member bitwise equal to its own solve."""
+    thread, by CG and by the single-reduction recurrence (up to 4 rows per
+    thread; p64 runs it in the LDS kernel): the oracle's solution and
+    iteration count, the k-th iterate at a cap, breakdown on -A, b = 0, and
+    a batch member bitwise equal to its own solve."""
     a = make()
     r = np.random.default_rng(a.n)
     b = r.standard_normal(a.n)
