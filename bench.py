@@ -396,21 +396,28 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
     if args.csr_line:
         top["csr_path"] = run_diffusion_csr(pat, vals, bt, kw, n, nnz, args)
     top["single_reduction"] = run_single_reduction(pat, vals, bt, kw, args, ms_step, iters)
+    top["s_step"] = run_single_reduction(pat, vals, bt, kw, args, ms_step, iters, s_step=4)
     return top, iters
 
 
 # kernel launches per iteration of the per-iteration path: CG runs SpMV+dot,
 # alpha finalize, update, beta finalize, direction; the single-reduction
-# recurrence runs SpMV with both dots, one finalize, one vector sweep
+# recurrence runs SpMV with both dots, one finalize, one vector sweep;
+# s-step CG runs 2s - 1 basis SpMVs, the Gram pass, one finalize and the
+# recovery sweep per s steps
 CG_LAUNCHES_PER_ITERATION, SR_LAUNCHES_PER_ITERATION = 5, 3
 
 
-def run_single_reduction(pat, vals, bt, kw, args, ms_cg, iters_cg, B=1):
+def run_single_reduction(pat, vals, bt, kw, args, ms_cg, iters_cg, B=1, s_step=0):
     """The same solve(s) with the single-reduction recurrence (CG_SR:
-    Chronopoulos and Gear), against the two-reduction schedule just timed."""
+    Chronopoulos and Gear) or, with s_step, s-step CG (one Gram reduction
+    per s steps), against the two-reduction schedule just timed."""
     from paper_2601_13994_amd import _lib
 
-    opts = _lib.make_opts(**dict(kw, method="cg_sr"))
+    if s_step:
+        opts = _lib.make_opts(**dict(kw, method="cg_sstep", s_step=s_step, persistent=False))
+    else:
+        opts = _lib.make_opts(**dict(kw, method="cg_sr"))
     _lib.solve(pat, vals, bt, opts)
     _sync()
     t0 = time.perf_counter()
@@ -425,9 +432,10 @@ def run_single_reduction(pat, vals, bt, kw, args, ms_cg, iters_cg, B=1):
         "iterations_two_reduction": iters_cg, "ms_per_solve": dt * 1e3,
         "ms_per_iteration": dt * 1e3 / max(it, 1),
         "two_reduction_ms_per_iteration": ms_cg / max(iters_cg, 1),
-        "launches_per_iteration": SR_LAUNCHES_PER_ITERATION,
+        "launches_per_iteration": (2 * s_step + 2) / s_step if s_step else SR_LAUNCHES_PER_ITERATION,
         "two_reduction_launches_per_iteration": CG_LAUNCHES_PER_ITERATION,
         "true_relative_residual_max": max(f["true_residual"] for f in infos), "systems": B, "reps": reps,
+        **({"s": s_step} if s_step else {}),
     }
 
 

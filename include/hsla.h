@@ -64,12 +64,26 @@ typedef enum hsla_status {
  * the persistent kernels, shared-pattern and ragged (one workgroup
  * reduction and two passes per iteration instead of two and three); FSAI
  * and the segmented ragged path run it as CG.  hsla_info.method reports
- * which ran. */
+ * which ran.
+ *
+ * HSLA_METHOD_CG_SSTEP is s-step (communication-avoiding) CG, the other
+ * roadmap item of that appendix, in Carson and Demmel's formulation of the
+ * s-step method of Chronopoulos and Gear: per outer iteration 2s - 1 SpMVs
+ * build the Chebyshev basis on [0, 2] of the Krylov spaces of p and r
+ * (hsla_opts.s_step = s inner steps, 2..4), one pass forms their Gram
+ * matrices (the only reduction of the outer iteration), the s CG steps run
+ * on coordinate vectors, and one sweep recovers x, r and p.  In exact
+ * arithmetic its iterates are CG's.  It runs on the Jacobi-scaled operator
+ * (precond JACOBI only; other preconditioners are rejected), on the
+ * per-iteration kernels (never in a persistent launch) and without
+ * profiling; the stop test follows every inner step on the unscaled
+ * residual from the weighted Gram matrix. */
 typedef enum hsla_method {
     HSLA_METHOD_AUTO = 0,
     HSLA_METHOD_CG = 1,
     HSLA_METHOD_BICGSTAB = 2,
-    HSLA_METHOD_CG_SR = 3
+    HSLA_METHOD_CG_SR = 3,
+    HSLA_METHOD_CG_SSTEP = 4
 } hsla_method;
 typedef enum hsla_precond { HSLA_PRECOND_NONE = 0, HSLA_PRECOND_JACOBI = 1, HSLA_PRECOND_FSAI = 2 } hsla_precond;
 
@@ -101,6 +115,8 @@ typedef struct hsla_opts {
                             iteration where it had) stops with HSLA_STAGNATED, e.g. so that a
                             poor learned preconditioner gives way to Jacobi early.  Runs on the
                             per-iteration kernels (no persistent launch).  Default 0: off     */
+    int32_t s_step;      /* HSLA_METHOD_CG_SSTEP: inner steps per outer iteration, 2..4;
+                            default 4                                                        */
 } hsla_opts;
 
 /* Per-system result information. */

@@ -20,7 +20,7 @@ OK, NOT_CONVERGED, BREAKDOWN, FELL_BACK, STAGNATED = 0, 1, 2, 3, 4
 ERR_INVALID_ARG, ERR_INVALID_CSR, ERR_NONFINITE, ERR_HIP = -1, -2, -3, -4
 ERR_NO_MEMORY, ERR_ZERO_DIAGONAL, ERR_INTERNAL = -5, -6, -7
 
-METHODS = {"auto": 0, "cg": 1, "bicgstab": 2, "cg_sr": 3}
+METHODS = {"auto": 0, "cg": 1, "bicgstab": 2, "cg_sr": 3, "cg_sstep": 4}
 METHOD_NAMES = {v: k for k, v in METHODS.items()}
 PRECONDS = {"none": 0, "jacobi": 1, "fsai": 2}
 FORMATS = {"auto": 0, "csr": 1, "diagonal": 2}
@@ -53,7 +53,7 @@ class Opts(ctypes.Structure):
         ("max_iter", ctypes.c_int64), ("check_every", ctypes.c_int32),
         ("use_x0", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32),
         ("d_G", ctypes.c_void_p), ("d_GT", ctypes.c_void_p), ("persistent", ctypes.c_int32),
-        ("stall_window", ctypes.c_int32),
+        ("stall_window", ctypes.c_int32), ("s_step", ctypes.c_int32),
     ]
 
 
@@ -254,7 +254,8 @@ def need(t: torch.Tensor, dtype: torch.dtype, name: str, device: torch.device) -
 
 
 def make_opts(method="auto", precond="jacobi", rtol=1e-8, atol=0.0, max_iter=0, check_every=0,
-              x0=False, graph=True, profile=False, G=None, GT=None, persistent=True, stall_window=0) -> Opts:
+              x0=False, graph=True, profile=False, G=None, GT=None, persistent=True, stall_window=0,
+              s_step=4) -> Opts:
     o = Opts()
     load().hsla_opts_default(ctypes.byref(o))
     o.method = METHODS[method]
@@ -270,6 +271,7 @@ def make_opts(method="auto", precond="jacobi", rtol=1e-8, atol=0.0, max_iter=0, 
     o.d_GT = GT.data_ptr() if GT is not None else None
     o.persistent = 2 if persistent == "force" else int(bool(persistent))
     o.stall_window = int(stall_window or 0)
+    o.s_step = int(s_step)
     return o
 
 

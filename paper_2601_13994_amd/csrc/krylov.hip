@@ -60,6 +60,9 @@ struct Sys {
     SysState *st;       // [B]
     double *part;       // [B][3][G] block partials of the last producing kernel
     double *part2;      // [B][G] block partials of the single-reduction sweep (kept past the next SpMV)
+    // s-step CG: basis vectors past p and r ([2s-1][B][n]), Gram partials
+    // ([B][2 NG][G]) and the coordinates of x, r, p ([B][3][2s+1])
+    double *ssb, *ssp, *ssc;
 };
 
 #define SYS_OFFSETS(S, A)                                               \
@@ -741,6 +744,250 @@ __global__ __launch_bounds__(kBlock) void k_sr_sweep(Pat A, Sys S) {
     if (threadIdx.x == 0) S.part2[(int64_t)sidx * gridDim.x + blockIdx.x] = acc[0];
 }
 
+// ---------------------------------------------------------------------------
+// s-step CG: the communication-avoiding CG the paper names after Algorithm
+// "Distributed CG" (appendix "Distributed Conjugate Gradient and Halo
+// Exchange"), in Carson and Demmel's formulation of the s-step method of
+// Chronopoulos and Gear, on the Jacobi-scaled operator S A S (unit
+// diagonal).  One outer iteration: 2 SS - 1 SpMVs build the Chebyshev basis
+// on [0, 2] of the Krylov spaces of p (T_0..T_SS) and r (T_0..T_{SS-1});
+// one pass forms the Gram matrices Y^T Y and Y^T S^{-2} Y (the outer
+// iteration's only reduction); one finalize block per system takes SS CG
+// steps on coordinate vectors, with the stop test on the unscaled residual
+// after every step; one sweep recovers x, r and p from the basis.
+// ---------------------------------------------------------------------------
+template <int SS>
+struct SStep {
+    static constexpr int NB = 2 * SS + 1;         // basis vectors
+    static constexpr int NG = NB * (NB + 1) / 2;  // Gram entries, upper triangle by rows
+    static constexpr int NGT = 2 * NG;            // plain and S^{-2}-weighted
+};
+
+// Basis vector k: 0 = p, 1..SS = T_k(p), SS + 1 = r, SS + 2..2 SS =
+// T_{k-SS-1}(r); each a [B][n] array (Bn = B n).
+template <int SS>
+__device__ __forceinline__ const double *ss_vec(const Sys &S, int k, int64_t Bn) {
+    return k == 0 ? S.p : k == SS + 1 ? S.r : S.ssb + (int64_t)(k <= SS ? k - 1 : k - 2) * Bn;
+}
+
+// out = (A - I) in (first), else 2 (A - I) in - prev: one step of the
+// Chebyshev recurrence.
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_ss_basis(Pat A, Sys S, const double *in, const double *prev,
+                                                     double *out, int first) {
+    __shared__ double lds[kWavesPerBlock][kTileCap];
+    SYS_OFFSETS(S, A)
+    (void)part;
+    if (stopped(st)) return;
+    in += vo;
+    prev += vo;
+    out += vo;
+    if constexpr (NS > 0) {
+        spmv_A<NS>(A, S, sidx, in, lds[threadIdx.x / kWave], [&](int64_t row, double yv, double vrow) {
+            const double t = yv - vrow;
+            out[row] = first ? t : 2.0 * t - prev[row];
+        });
+    } else {
+        spmv_A<NS>(A, S, sidx, in, lds[threadIdx.x / kWave], [&](int64_t row, double yv) {
+            const double t = yv - in[row];
+            out[row] = first ? t : 2.0 * t - prev[row];
+        });
+    }
+}
+
+// Partials of the Gram matrices over the basis (entry (a, b), a <= b, at
+// a NB - a (a - 1) / 2 + b - a; the weighted ones NG further).
+template <int SS>
+__global__ __launch_bounds__(kBlock) void k_ss_gram(Pat A, Sys S) {
+    using Q = SStep<SS>;
+    const int sidx = blockIdx.y;
+    const int64_t n = A.n, vo = (int64_t)sidx * n, Bn = (int64_t)gridDim.y * n;
+    if (stopped(S.st[sidx])) return;
+    const double *y[Q::NB];
+#pragma unroll
+    for (int k = 0; k < Q::NB; ++k) y[k] = ss_vec<SS>(S, k, Bn) + vo;
+    const double *sc = S.dinv + vo;
+    double acc[Q::NGT];
+#pragma unroll
+    for (int g = 0; g < Q::NGT; ++g) acc[g] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        double v[Q::NB];
+#pragma unroll
+        for (int k = 0; k < Q::NB; ++k) v[k] = y[k][i];
+        const double si = sc[i];
+        const double wt = 1.0 / (si * si);  // r = S^{-1} r^: weight of the unscaled norm
+        int g = 0;
+#pragma unroll
+        for (int a = 0; a < Q::NB; ++a) {
+#pragma unroll
+            for (int b = a; b < Q::NB; ++b) {
+                const double pr = v[a] * v[b];
+                acc[g] += pr;
+                acc[Q::NG + g] += pr * wt;
+                ++g;
+            }
+        }
+    }
+    block_partial<Q::NGT>(acc, S.ssp + (int64_t)sidx * Q::NGT * gridDim.x);
+}
+
+// u^T M v for the packed symmetric M (tot + off), fixed order.
+template <int NB>
+__device__ __forceinline__ double ss_form(const double *tot, int off, const double (&u)[NB], const double (&v)[NB]) {
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        double row = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int lo = a < b ? a : b, hi = a < b ? b : a;
+            row += tot[off + lo * NB - lo * (lo - 1) / 2 + hi - lo] * v[b];
+        }
+        acc += u[a] * row;
+    }
+    return acc;
+}
+
+// out = B c: coordinates of A (Y c) (A T_0 = T_0 + T_1, A T_j = (T_{j-1} +
+// T_{j+1}) / 2 + T_j in each block; a block's last vector is never mapped).
+template <int SS>
+__device__ __forceinline__ void ss_bmul(const double (&c)[SStep<SS>::NB], double (&out)[SStep<SS>::NB]) {
+    constexpr int NB = SStep<SS>::NB;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) out[k] = 0.0;
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+        const int start = blk == 0 ? 0 : SS + 1, len = blk == 0 ? SS + 1 : SS;
+#pragma unroll
+        for (int j = 0; j + 1 < len; ++j) {
+            const int k = start + j;
+            const double v = c[k];
+            if (j == 0) {
+                out[k] += v;
+                out[k + 1] += v;
+            } else {
+                out[k - 1] += 0.5 * v;
+                out[k] += v;
+                out[k + 1] += 0.5 * v;
+            }
+        }
+    }
+}
+
+// The SS inner steps of one outer iteration, on coordinates (thread 0 of a
+// block per system); leaves the coordinates of x (increment), r and p.
+template <int SS>
+__global__ __launch_bounds__(kBlock) void k_fin_ss(Sys S, int G) {
+    using Q = SStep<SS>;
+    constexpr int NB = Q::NB;
+    const int sidx = blockIdx.x;
+    SysState &st = S.st[sidx];
+    if (stopped(st)) {
+        if (threadIdx.x == 0) st.xpend = 0;
+        return;
+    }
+    double tot[Q::NGT];
+    reduce_partials<Q::NGT>(S.ssp + (int64_t)sidx * Q::NGT * G, G, tot);
+    if (threadIdx.x != 0) return;
+    double pc[NB], rc[NB], xc[NB], bp[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) pc[k] = rc[k] = xc[k] = 0.0;
+    pc[0] = 1.0;
+    rc[SS + 1] = 1.0;
+    double rho = ss_form<NB>(tot, 0, rc, rc);
+    bool stop = false;
+#pragma unroll
+    for (int j = 0; j < SS; ++j) {
+        if (stop) break;
+        ss_bmul<SS>(pc, bp);
+        const double sigma = ss_form<NB>(tot, 0, pc, bp);
+        if (!isfinite(sigma)) {
+            st.status = HSLA_ERR_NONFINITE;
+            stop = true;
+            break;
+        }
+        if (!(sigma > 0.0)) {
+            st.status = HSLA_BREAKDOWN;
+            stop = true;
+            break;
+        }
+        const double alpha = rho / sigma;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            xc[k] = xc[k] + alpha * pc[k];
+            rc[k] = rc[k] - alpha * bp[k];
+        }
+        st.iters += 1;
+        const double rr = ss_form<NB>(tot, Q::NG, rc, rc);
+        st.rnorm2 = rr > 0.0 ? rr : 0.0;
+        if (!isfinite(rr)) {
+            st.status = HSLA_ERR_NONFINITE;
+            stop = true;
+        } else if (sqrt(st.rnorm2) <= st.tol) {
+            st.status = HSLA_OK;
+            stop = true;
+        } else if (st.iters >= st.max_iter) {
+            st.status = HSLA_NOT_CONVERGED;
+            stop = true;
+        } else {
+            const double rho_new = ss_form<NB>(tot, 0, rc, rc);
+            const double beta = rho_new / rho;
+            rho = rho_new;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) pc[k] = rc[k] + beta * pc[k];
+        }
+    }
+    if (stop) st.done = 1;
+    st.xpend = 1;  // this outer iteration's recovery sweep applies x (and r, p)
+    double *cf = S.ssc + (int64_t)sidx * 3 * NB;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        cf[k] = xc[k];
+        cf[NB + k] = rc[k];
+        cf[2 * NB + k] = pc[k];
+    }
+}
+
+// x += Y x_c; r = Y r_c, p = Y p_c (a system that stopped takes x only).
+template <int SS>
+__global__ __launch_bounds__(kBlock) void k_ss_recover(Pat A, Sys S) {
+    using Q = SStep<SS>;
+    constexpr int NB = Q::NB;
+    const int sidx = blockIdx.y;
+    const int64_t n = A.n, vo = (int64_t)sidx * n, Bn = (int64_t)gridDim.y * n;
+    const SysState &st = S.st[sidx];
+    if (st.done && !st.xpend) return;
+    const bool full = !st.done;
+    const double *cf = S.ssc + (int64_t)sidx * 3 * NB;
+    double xc[NB], rc[NB], pc[NB];
+    const double *y[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        xc[k] = cf[k];
+        rc[k] = cf[NB + k];
+        pc[k] = cf[2 * NB + k];
+        y[k] = ss_vec<SS>(S, k, Bn) + vo;
+    }
+    double *x = S.x + vo, *r = S.r + vo, *p = S.p + vo;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        double v[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) v[k] = y[k][i];
+        double xs = 0.0, rs = 0.0, ps = 0.0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            xs += xc[k] * v[k];
+            rs += rc[k] * v[k];
+            ps += pc[k] * v[k];
+        }
+        x[i] = x[i] + xs;
+        if (full) {
+            r[i] = rs;
+            p[i] = ps;
+        }
+    }
+}
+
 // The operator S A S of the scaled system on CSR values (tile form): each
 // entry times S_row S_col, the diagonal 1 by construction.
 __global__ __launch_bounds__(kBlock) void k_scale_sym(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
@@ -1373,6 +1620,7 @@ struct SolveCall {
     int nsA, nsF; // slot counts of the diagonal-major SpMV of A and of the FSAI factors (0: tiles)
     int Gs, Gf;   // blocks per system of the A-SpMV and FSAI kernels
     int sr;       // CG with the single-reduction recurrence (no or Jacobi preconditioner)
+    int ss;       // s-step CG: inner steps per outer iteration (0: off; Jacobi only)
 };
 
 
@@ -1384,7 +1632,39 @@ static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hip
     const dim3 gs(c.Gs, c.B), gfs(c.Gf, c.B), gv(c.Gv, c.B), gf(c.B);
     const int Gs = c.Gs, Gfs = c.Gf, Gv = c.Gv;
     for (int k = 0; k < iters; ++k) {
-        if (c.method == HSLA_METHOD_CG && c.sr) {
+        if (c.method == HSLA_METHOD_CG && c.ss) {
+            // one outer iteration (c.ss inner steps)
+            const Sys &S = c.S;
+            const int64_t Bn = (int64_t)c.B * c.A.n;
+            for (int blk = 0; blk < 2; ++blk) {
+                const double *v0 = blk == 0 ? S.p : S.r;
+                double *base = S.ssb + (blk == 0 ? 0 : (int64_t)c.ss * Bn);
+                const int len = blk == 0 ? c.ss + 1 : c.ss;
+                for (int j = 1; j < len; ++j) {
+                    const double *in = j == 1 ? v0 : base + (int64_t)(j - 2) * Bn;
+                    const double *prev = j == 1 ? v0 : j == 2 ? v0 : base + (int64_t)(j - 3) * Bn;
+                    double *out = base + (int64_t)(j - 1) * Bn;
+                    NS_LAUNCH_A(k_ss_basis, c.nsA, gs, c.A, c.S, in, prev, out, j == 1 ? 1 : 0);
+                }
+            }
+            switch (c.ss) {
+                case 2:
+                    k_ss_gram<2><<<gv, kBlock, 0, s>>>(c.A, c.S);
+                    k_fin_ss<2><<<gf, kBlock, 0, s>>>(c.S, Gv);
+                    k_ss_recover<2><<<gv, kBlock, 0, s>>>(c.A, c.S);
+                    break;
+                case 3:
+                    k_ss_gram<3><<<gv, kBlock, 0, s>>>(c.A, c.S);
+                    k_fin_ss<3><<<gf, kBlock, 0, s>>>(c.S, Gv);
+                    k_ss_recover<3><<<gv, kBlock, 0, s>>>(c.A, c.S);
+                    break;
+                default:
+                    k_ss_gram<4><<<gv, kBlock, 0, s>>>(c.A, c.S);
+                    k_fin_ss<4><<<gf, kBlock, 0, s>>>(c.S, Gv);
+                    k_ss_recover<4><<<gv, kBlock, 0, s>>>(c.A, c.S);
+                    break;
+            }
+        } else if (c.method == HSLA_METHOD_CG && c.sr) {
             if (ev) (void)hipEventRecord(ev[2 * k], s);
             NS_LAUNCH_A(k_sr_spmv_dot, c.nsA, gs, c.A, c.S);
             if (ev) (void)hipEventRecord(ev[2 * k + 1], s);
@@ -1539,15 +1819,19 @@ static hsla_status decide_half(hsla_handle *h, const hsla_pattern *p, const Pat 
 // Grid sizes, SpMV forms and workspace layout of one solve.
 struct Plan {
     int nvec, Gt, Gv, nsA, nsF, Gd, Gs, Gf, pencil;
-    size_t diaA, diaL, diaU, sval;
+    size_t diaA, diaL, diaU, sval, ssp, ssc;
     Layout lay;
 };
 
+// Gram partials per block of s-step CG (plain and weighted upper triangles).
+static int ss_partials(int ss) { return ss > 0 ? (2 * ss + 1) * (2 * ss + 2) : 0; }
+
 static Plan plan_solve(hsla_handle *h, const Tune &tn, const Pat &A, const FPat *L, const FPat *U, int B, int method,
-                       int pre) {
+                       int pre, int ss = 0) {
     Plan pl{};
     const int64_t n = A.n;
-    pl.nvec = method == HSLA_METHOD_CG ? 6 : 8;
+    // s-step CG keeps its 2 ss - 1 basis vectors past p and r after the six
+    pl.nvec = method == HSLA_METHOD_CG ? 6 + (ss > 0 ? 2 * ss - 1 : 0) : 8;
     // SpMV-based kernels: up to 16 blocks per CU; vector kernels: up to 8,
     // shared by the systems of a batch (fewer, longer-running blocks each)
     pl.Gt = grid_blocks(h, kWavesPerBlock, A.ntiles, B, tn.tile_cu);
@@ -1582,8 +1866,10 @@ static Plan plan_solve(hsla_handle *h, const Tune &tn, const Pat &A, const FPat 
     pl.diaL = pl.nsF ? sizeof(float) * (size_t)B * L->sn.nofs * drows : 0;
     pl.diaU = pl.nsF ? sizeof(float) * (size_t)B * U->sn.nofs * drows : 0;
     pl.sval = scaled && !pl.nsA ? sizeof(double) * (size_t)B * (size_t)A.nnz : 0;
+    pl.ssp = sizeof(double) * (size_t)ss_partials(ss) * pl.Gv * B;
+    pl.ssc = ss > 0 ? sizeof(double) * 3 * (2 * ss + 1) * (size_t)B : 0;
     const size_t extra = align_up(pl.diaA, 256) + align_up(pl.diaL, 256) + align_up(pl.diaU, 256) +
-                         align_up(pl.sval, 256);
+                         align_up(pl.sval, 256) + align_up(pl.ssp, 256) + align_up(pl.ssc, 256);
     const int Gmax = std::max(std::max(pl.Gt, pl.Gv), std::max(pl.Gd, pl.Gf));
     pl.lay = make_layout(B, n, pl.nvec, Gmax, extra);
     return pl;
@@ -1592,12 +1878,14 @@ static Plan plan_solve(hsla_handle *h, const Tune &tn, const Pat &A, const FPat 
 static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, const FPat *L, const FPat *U, int B,
                               const double *values,
                               const double *b, double *x, const hsla_opts &o, int method, hsla_info *infos,
-                              hipStream_t s, bool sr = false) {
+                              hipStream_t s, bool sr = false, int ss = 0) {
     const int64_t n = A.n;
     const int pre = o.precond == HSLA_PRECOND_NONE ? PRE_NONE : o.precond == HSLA_PRECOND_FSAI ? PRE_FSAI : PRE_JACOBI;
     if (method == HSLA_METHOD_BICGSTAB && pre == PRE_FSAI)
         return set_error(h, HSLA_ERR_INVALID_ARG, "FSAI preconditioning is for CG only");
-    const Plan pl = plan_solve(h, tn, A, L, U, B, method, pre);
+    if (ss > 0 && (method != HSLA_METHOD_CG || pre != PRE_JACOBI))
+        return set_error(h, HSLA_ERR_INVALID_ARG, "s-step CG runs on the Jacobi-scaled operator (precond JACOBI)");
+    const Plan pl = plan_solve(h, tn, A, L, U, B, method, pre, ss);
     const int nvec = pl.nvec, Gt = pl.Gt, Gv = pl.Gv, nsA = pl.nsA, nsF = pl.nsF, Gs = pl.Gs, Gf = pl.Gf;
     const size_t diaA = pl.diaA, diaL = pl.diaL;
     const Layout lay = pl.lay;
@@ -1621,6 +1909,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
     c.Gs = Gs;
     c.Gf = Gf;
     c.sr = sr && method == HSLA_METHOD_CG && (pre == PRE_NONE || pre == PRE_JACOBI);
+    c.ss = ss;
     Sys &S = c.S;
     S.val = values;
     S.b = b;
@@ -1633,7 +1922,9 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
     double **cg_slots[] = {&S.r, &S.p, &S.q, &S.dinv, &S.z, &S.w};
     double **bicg_slots[] = {&S.r, &S.p, &S.t, &S.dinv, &S.rh, &S.y, &S.v, &S.s};
     double ***slots = method == HSLA_METHOD_CG ? cg_slots : bicg_slots;
-    for (int k = 0; k < nvec; ++k) *slots[k] = vec + k * vs;
+    const int nslots = method == HSLA_METHOD_CG ? 6 : 8;
+    for (int k = 0; k < nslots && k < nvec; ++k) *slots[k] = vec + k * vs;
+    S.ssb = ss > 0 ? vec + 6 * vs : nullptr;
     S.aval = values;
     // right-Jacobi BiCGStab iterates on A D^{-1}: its values are scaled
     // below, once D^{-1} is known
@@ -1663,6 +1954,12 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             k_to_dia<float><<<dim3(Gv, B), kBlock, 0, s>>>((int32_t)n, U->rp, U->sn, U->nnz, U->val, du);
             c.L.dia = dl;
             c.U.dia = du;
+            ex += align_up(diaL, 256) + align_up(pl.diaU, 256);
+        }
+        if (ss > 0) {
+            S.ssp = (double *)ex;
+            ex += align_up(pl.ssp, 256);
+            S.ssc = (double *)ex;
         }
     }
     k_reset<<<1, kBlock, 0, s>>>(S.st, B, max_iter, o.stall_window > 0 ? o.stall_window : 0);
@@ -1716,7 +2013,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
     int chunk = o.check_every > 0 ? o.check_every : 8;
     const int chunk_cap = o.check_every > 0 ? o.check_every : 64;
     hipEvent_t *ev = nullptr;
-    if (o.profile) {
+    if (o.profile && !c.ss) {  // (s-step CG runs unprofiled)
         st = ensure_prof_events(h, chunk_cap > chunk ? chunk_cap : chunk);
         if (st != HSLA_OK) return st;
         ev = h->prof_ev;
@@ -1753,7 +2050,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
         if (chunk > chunk_cap) chunk = chunk_cap;
         st = run_chunk(h, c, chunk, o.use_graph != 0, s, ev);
         if (st != HSLA_OK) return st;
-        run += chunk;
+        run += (int64_t)chunk * (c.ss > 0 ? c.ss : 1);
         pending = chunk;
         if (chunk < chunk_cap) chunk *= 2;
     }
@@ -1781,7 +2078,7 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
             hsla_info &f = infos[i];
             f.iters = hs[i].iters;
             f.status = sst;
-            f.method = c.sr ? HSLA_METHOD_CG_SR : method;
+            f.method = c.ss ? HSLA_METHOD_CG_SSTEP : c.sr ? HSLA_METHOD_CG_SR : method;
             const double bn = hs[i].bnorm;
             const double rn = std::sqrt(hs[i].rnorm2);
             f.rel_residual = bn > 0 ? rn / bn : rn;
@@ -1838,8 +2135,10 @@ static hsla_status read_opts(hsla_handle *h, const hsla_opts *opts, hsla_opts *o
     else
         hsla_opts_default(o);
     if (!(o->rtol >= 0) || !(o->atol >= 0)) return set_error(h, HSLA_ERR_INVALID_ARG, "negative or NaN tolerance");
-    if (o->method < HSLA_METHOD_AUTO || o->method > HSLA_METHOD_CG_SR)
+    if (o->method < HSLA_METHOD_AUTO || o->method > HSLA_METHOD_CG_SSTEP)
         return set_error(h, HSLA_ERR_INVALID_ARG, "unknown method %d", o->method);
+    if (o->method == HSLA_METHOD_CG_SSTEP && (o->s_step < 2 || o->s_step > 4))
+        return set_error(h, HSLA_ERR_INVALID_ARG, "s_step must be 2, 3 or 4 (got %d)", o->s_step);
     if (o->precond < HSLA_PRECOND_NONE || o->precond > HSLA_PRECOND_FSAI)
         return set_error(h, HSLA_ERR_INVALID_ARG, "unknown preconditioner %d", o->precond);
     return HSLA_OK;
@@ -1868,7 +2167,8 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
     if (!values || !b || !x) return set_error(h, HSLA_ERR_INVALID_ARG, "null values, b or x");
     int method = o.method;
     const bool sr = method == HSLA_METHOD_CG_SR;  // single-reduction CG where it applies
-    if (sr) method = HSLA_METHOD_CG;
+    const int ss = method == HSLA_METHOD_CG_SSTEP ? o.s_step : 0;  // s-step CG (per-iteration kernels)
+    if (sr || ss) method = HSLA_METHOD_CG;
     int symv = -1;  // values symmetric: -1 not checked
     if (method == HSLA_METHOD_AUTO) {
         bool sym = false;
@@ -1877,7 +2177,7 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
         method = sym ? HSLA_METHOD_CG : HSLA_METHOD_BICGSTAB;
         symv = sym ? 1 : 0;
     }
-    if (o.persistent && persistent_eligible(h, p, B, method, o))
+    if (!ss && o.persistent && persistent_eligible(h, p, B, method, o))
         return persistent_solve(h, p, B, values, b, x, o, infos, s, sr);
     const Pat A = pat_of(p);
     FPat L{}, U{};
@@ -1889,7 +2189,7 @@ hsla_status solve_entry(hsla_handle *h, const hsla_pattern *p, int B, const doub
     Tune tn = tune_of(p);
     st = decide_half(h, p, A, B, values, symv, s, &tn);
     if (st != HSLA_OK) return st;
-    return solve_core(h, tn, A, &L, &U, B, values, b, x, o, method, infos, s, sr);
+    return solve_core(h, tn, A, &L, &U, B, values, b, x, o, method, infos, s, sr, ss);
 }
 
 // Eq. adjoint_linear: A^T lambda = gx, gb = lambda, gA = -lambda x^T on the
@@ -1917,8 +2217,9 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
     st = values_symmetric(h, p, B, values, s, &sym);
     if (st != HSLA_OK) return st;
     const bool sr = o.method == HSLA_METHOD_CG_SR;
+    const int ss = o.method == HSLA_METHOD_CG_SSTEP ? o.s_step : 0;
     const int method = o.method == HSLA_METHOD_AUTO ? (sym ? HSLA_METHOD_CG : HSLA_METHOD_BICGSTAB)
-                       : sr                         ? HSLA_METHOD_CG
+                       : sr || ss                   ? HSLA_METHOD_CG
                                                     : o.method;
     const int64_t n = p->n;
     double *lam = gb, *lam_own = nullptr, *valT = nullptr;
@@ -1929,13 +2230,13 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
     hsla_status res;
     if (sym) {
         const Pat A = pat_of(p);
-        if (o.persistent && persistent_eligible(h, p, B, method, o)) {
+        if (!ss && o.persistent && persistent_eligible(h, p, B, method, o)) {
             res = persistent_solve(h, p, B, values, gx, lam, o, infos, s, sr);
         } else {
             Tune tn = tune_of(p);
             res = decide_half(h, p, A, B, values, 1, s, &tn);
             if (res == HSLA_OK)
-                res = solve_core(h, tn, A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s, sr);
+                res = solve_core(h, tn, A, nullptr, nullptr, B, values, gx, lam, o, method, infos, s, sr, ss);
         }
     } else {
         if (dev_alloc(h, (void **)&valT, sizeof(double) * (size_t)B * (p->nnz > 0 ? p->nnz : 1)) != hipSuccess) {
@@ -1947,7 +2248,7 @@ hsla_status adjoint_entry(hsla_handle *h, const hsla_pattern *p, int B, const do
         if (blocks > 8192) blocks = 8192;
         if (tot > 0) k_gather_values<<<blocks, kBlock, 0, s>>>(p->nnz, B, values, p->srcT, valT);
         const Pat AT = pat_T_of(p);
-        res = solve_core(h, tune_of(p), AT, nullptr, nullptr, B, valT, gx, lam, o, method, infos, s, sr);
+        res = solve_core(h, tune_of(p), AT, nullptr, nullptr, B, valT, gx, lam, o, method, infos, s, sr, ss);
     }
     if (res >= 0 && gA) {
         int Gr = (int)((n + kBlock - 1) / kBlock);
@@ -1970,10 +2271,13 @@ hsla_status workspace_size(hsla_handle *h, const hsla_pattern *p, int B, const h
     FPat L{p->rpL, p->colL, p->metaL, p->ntilesL, p->nnz_lower, nullptr, p->use(p->stL)};
     FPat U{p->rpU, p->colU, p->metaU, p->ntilesU, p->nnz_lower, nullptr, p->use(p->stU)};
     size_t need = 0;
+    // the single-reduction and s-step recurrences are CG solves
+    const int om = o.method == HSLA_METHOD_CG_SR || o.method == HSLA_METHOD_CG_SSTEP ? HSLA_METHOD_CG : o.method;
+    const int ss = o.method == HSLA_METHOD_CG_SSTEP ? o.s_step : 0;
     for (int method : {HSLA_METHOD_CG, HSLA_METHOD_BICGSTAB}) {
-        if (o.method != HSLA_METHOD_AUTO && o.method != method) continue;
+        if (om != HSLA_METHOD_AUTO && om != method) continue;
         if (method == HSLA_METHOD_BICGSTAB && pre == PRE_FSAI) continue;
-        const Plan pl = plan_solve(h, tune_of(p), A, &L, &U, B, method, pre);
+        const Plan pl = plan_solve(h, tune_of(p), A, &L, &U, B, method, pre, method == HSLA_METHOD_CG ? ss : 0);
         need = std::max(need, pl.lay.total);
         if (o.persistent && persistent_eligible(h, p, B, method, o))
             need = std::max(need, sizeof(double) * 4 * (size_t)B * p->n + 1024 + 40 * (size_t)B);

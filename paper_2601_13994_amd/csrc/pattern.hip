@@ -644,6 +644,7 @@ void hsla_opts_default(hsla_opts *o) {
     o->use_graph = 1;
     o->persistent = 1;
     o->stall_window = 0;
+    o->s_step = 4;
 }
 
 const char *hsla_status_string(int st) {

@@ -619,6 +619,56 @@ def test_cg_single_reduction_per_iteration(orc, fmt, precond):
     assert st == 0 and i0[0]["iters"] == 0 and not x0.any()
 
 
+@pytest.mark.parametrize("s", [2, 3, 4])
+@pytest.mark.parametrize("fmt", ["auto", "csr"])
+def test_sstep_cg(orc, s, fmt):
+    """s-step CG (Chebyshev basis on [0, 2], one Gram reduction per s inner
+    steps) on the per-iteration kernels, diagonal-major and tile forms:
+    against the s-step oracle the solution at rtol 1e-10 and the iteration
+    count (within max(2, 2%)), against the oracle's Jacobi-PCG the solution,
+    the k-th iterate at k = s (an outer boundary) and s + 1 (inside an outer
+    step), graph replay bitwise equal to plain launches, a batch member
+    bitwise equal to its own solve, b = 0, and the rejected options."""
+    from oracle import sstep
+    m = 20
+    a = W.diffusion3d(m, W.diffusion3d_kappa(m))
+    r = np.random.default_rng(21)
+    b = r.standard_normal(a.n)
+    pat = pattern(a)
+    pat.set_format(fmt)
+    kw = dict(method="cg_sstep", precond="jacobi", s_step=s, persistent=False)
+    try:
+        x, info, st = solve(a, b, pat=pat, rtol=1e-10, **kw)
+        ref = sstep.sstep_cg(a, b, s=s, precond="jacobi", rtol=1e-10)
+        assert st == 0 and info[0]["method"] == "cg_sstep", info[0]
+        assert rel(x, ref.x) <= 1e-9
+        assert iters_close(info[0]["iters"], ref.iters), (info[0]["iters"], ref.iters)
+        assert info[0]["true_residual"] <= 2e-10
+        pcg = orc.cg(a, b, precond="jacobi", rtol=1e-10)
+        assert rel(x, pcg.x) <= 1e-8
+        xg, _, _ = solve(a, b, pat=pat, rtol=1e-10, graph=False, **kw)
+        assert np.array_equal(x, xg)
+        for k in (s, s + 1):
+            xk, ik, sk = solve(a, b, pat=pat, rtol=1e-14, max_iter=k, **kw)
+            refk = sstep.sstep_cg(a, b, s=s, precond="jacobi", rtol=1e-14, max_iter=k)
+            assert sk == _lib.NOT_CONVERGED and ik[0]["iters"] == k
+            assert rel(xk, refk.x) <= 1e-11, (k, rel(xk, refk.x))
+        V = np.stack([a.val, W.diffusion3d_values(m, W.diffusion3d_kappa(m, sample=1)), a.val])
+        bs = np.stack([r.standard_normal(a.n), b, b])
+        xb, ib, sb = _lib.solve(pat, t64(V), t64(bs), _lib.make_opts(rtol=1e-10, **kw))
+        assert sb == 0 and np.array_equal(xb[2].cpu().numpy(), x)
+        ref1 = sstep.sstep_cg(a.with_values(V[1]), b, s=s, precond="jacobi", rtol=1e-10)
+        assert rel(xb[1].cpu().numpy(), ref1.x) <= 1e-9
+        x0, i0, st0 = solve(a, np.zeros(a.n), pat=pat, **kw)
+        assert st0 == 0 and i0[0]["iters"] == 0 and not x0.any()
+    finally:
+        pat.set_format("auto")
+    with pytest.raises(_lib.HslaError):
+        solve(a, b, pat=pat, **dict(kw, precond="none"))
+    with pytest.raises(_lib.HslaError):
+        solve(a, b, pat=pat, **dict(kw, s_step=5))
+
+
 def test_cg_single_reduction_fsai_runs_cg(orc):
     """FSAI preconditioning keeps the two-reduction recurrence and says so."""
     from oracle import mpnn
