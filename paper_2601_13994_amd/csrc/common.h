@@ -838,7 +838,8 @@ __device__ __forceinline__ bool pairable(const Stencil &sn, int64_t n, const dou
 // One chunk of the full copy in the paired layout: rows r0 = 2t and r1 =
 // 2t + 1 of the chunk, one 16-byte load per stored diagonal and per x gather
 // at an even offset for both rows, the pair's own x as each other's -1 and
-// +1 neighbour.  Same products in the same order as spmv_dia_full, without
+// +1 neighbour, and x of rows r0 - 1 and r0 + 2 from the neighbouring lanes
+// (DPP).  Same products in the same order as spmv_dia_full, without
 // the row masks: an absent entry is stored as 0 and every gather row is
 // clamped into [0, n), so its product is 0 * (a finite x) and the add leaves
 // the sum as it was (up to the sign of a zero sum).
@@ -861,16 +862,26 @@ __device__ __forceinline__ void full_pair(const Stencil &sn, const double *__res
             v0[s] = t.x;
             v1[s] = t.y;
         }
-        if (s == DS - 1) {
-            x0[s] = x[clamp_row(r0 - 1, n)];
-        } else if (s == DS + 1) {
-            x1[s] = x[clamp_row(r0 + 2, n)];
+        if (s == DS - 1 || s == DS + 1) {  // the neighbouring lanes' rows, after the loop
+            x0[s] = x1[s] = 0.0;
         } else {
             const int64_t a = r0 + sn.ofs[s], pa = a < 0 ? 0 : a > n - 2 ? n - 2 : a;
             const dpair t = *(const dpair *)(x + pa);
             x0[s] = t.x;
             x1[s] = t.y;
         }
+    }
+    // x of rows r0 - 1 and r0 + 2 from the lanes below and above by DPP wave
+    // shifts (the wavefront's first and last lane read theirs)
+    {
+        const int lane = threadIdx.x & (kWave - 1);
+        double xe = 0.0;
+        if (lane == 0)
+            xe = x[clamp_row(r0 - 1, n)];
+        else if (lane == kWave - 1)
+            xe = x[clamp_row(r0 + 2, n)];
+        x0[DS - 1] = dpp_f64<0x138>(xe, x1[DS]);  // wave_shr:1, lane l <- l - 1
+        x1[DS + 1] = dpp_f64<0x130>(xe, x0[DS]);  // wave_shl:1, lane l <- l + 1
     }
     x1[DS - 1] = x0[DS];
     x0[DS + 1] = x1[DS];
@@ -985,7 +996,9 @@ __device__ __forceinline__ void spmv_dia_full(const Stencil &sn, const VT *__res
 // Two row layouts.  Paired (sym_pair): each thread takes two adjacent rows
 // r0 = 2t, r1 = 2t + 1 of the chunk, so that every stream and every gather
 // at an even offset is one 16-byte load for both rows, and the pair's own
-// entries and x are each other's -1 and +1 neighbours.  It needs the offsets
+// entries and x are each other's -1 and +1 neighbours; x of rows r0 - 1 and
+// r0 + 2 and row r0 - 1's +1 entry are the neighbouring lanes' own values,
+// moved by DPP (measured at 256^3: 134 -> 121 us per SpMV).  It needs the offsets
 // -1 and +1 beside the main diagonal, every other offset even, n even and x
 // 16-byte aligned: then a pair start clamped into [0, n - 2] reads exactly
 // the x of every row that has the entry.  It reads no row masks: an absent
@@ -1092,8 +1105,8 @@ __device__ __forceinline__ void sym_pair(const Stencil &sn, const VT *__restrict
         } else if (CONT && s == 0) {
             v0[s] = cy.v0;
             v1[s] = cy.v1;
-        } else if (s == DS - 1) {  // d = -1: row r1's entry mirrors row r0's +1 entry
-            v0[s] = r0 >= 1 ? dv[dia_index(r0 - 1, ms, NH)] : VT(0);
+        } else if (s == DS - 1) {  // d = -1: taken from the lane below after the loop
+            v0[s] = VT(0);
         } else {  // a mirror row above the first row holds no entry: 0
             const int64_t a = r0 + d, pa = a < 0 ? 0 : a > npad - 2 ? npad - 2 : a;
             const dpair t = *(const dpair *)(dv + dia_index(pa, ms, NH));
@@ -1106,16 +1119,31 @@ __device__ __forceinline__ void sym_pair(const Stencil &sn, const VT *__restrict
         } else if (CONT && s == DS) {
             x0[s] = cy.xown0;
             x1[s] = cy.xown1;
-        } else if (s == DS - 1) {
-            x0[s] = x[clamp_row(r0 - 1, n)];
-        } else if (s == DS + 1) {
-            x1[s] = x[clamp_row(r0 + 2, n)];
+        } else if (s == DS - 1 || s == DS + 1) {  // the neighbouring lanes' rows, after the loop
+            x0[s] = x1[s] = 0.0;
         } else {
             const int64_t a = r0 + d, pa = a < 0 ? 0 : a > n - 2 ? n - 2 : a;
             const dpair t = *(const dpair *)(x + pa);
             x0[s] = t.x;
             x1[s] = t.y;
         }
+    }
+    // Rows r0 - 1 and r0 + 2 belong to the lanes below and above: their x
+    // and row r0 - 1's +1 entry (the mirror of row r0's -1 entry) move by
+    // DPP wave shifts; the wavefront's first and last lane read theirs.
+    {
+        const int lane = threadIdx.x & (kWave - 1);
+        double xe = 0.0;
+        VT ve = VT(0);
+        if (lane == 0) {
+            xe = x[clamp_row(r0 - 1, n)];
+            ve = r0 >= 1 ? dv[dia_index(r0 - 1, NS - 1 - (DS - 1) - U0, NH)] : VT(0);
+        } else if (lane == kWave - 1) {
+            xe = x[clamp_row(r0 + 2, n)];
+        }
+        x0[DS - 1] = dpp_f64<0x138>(xe, x1[DS]);       // wave_shr:1, lane l <- l - 1
+        x1[DS + 1] = dpp_f64<0x130>(xe, x0[DS]);       // wave_shl:1, lane l <- l + 1
+        v0[DS - 1] = dpp_f64<0x138>(ve, v1[DS + 1]);
     }
     v1[DS - 1] = v0[DS + 1];
     x1[DS - 1] = x0[DS];
