@@ -1025,9 +1025,13 @@ __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restric
     const VT *__restrict__ base = dv + c * NH * kDiaChunk + threadIdx.x;
     VT v1[NS], v2[NS];
     double x1[NS], x2[NS];
+    // The thread's two rows are kBlock apart: at offset +kBlock row i's
+    // neighbour is row i2, at -kBlock row i2's is row i (x and the mirrored
+    // entry), so those come from the thread's own registers after the loop.
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int64_t d = sn.ofs[s];
+        const bool up = d == kBlock, dn = d == -kBlock && !(CONT && s == 0);
         // gather rows clamped into [0, n) rather than chosen by the mask, so
         // that no address waits for the mask load; the mask gates the adds
         const int64_t r1 = clamp_row(j1 + d, n);
@@ -1043,7 +1047,7 @@ __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restric
             v2[s] = cy.v1;
         } else {
             v1[s] = dv[dia_index(r1, NS - 1 - s - U0, NH)];
-            v2[s] = dv[dia_index(r2, NS - 1 - s - U0, NH)];
+            v2[s] = dn ? VT(0) : dv[dia_index(r2, NS - 1 - s - U0, NH)];
         }
         if (CONT && s == 0) {
             x1[s] = cy.xlo0;
@@ -1052,8 +1056,22 @@ __device__ __forceinline__ void sym_chunk(const Stencil &sn, const VT *__restric
             x1[s] = cy.xown0;
             x2[s] = cy.xown1;
         } else {
-            x1[s] = x[r1];
-            x2[s] = x[r2];
+            x1[s] = up ? 0.0 : x[r1];
+            x2[s] = dn ? 0.0 : x[r2];
+        }
+    }
+    {
+        VT vup = VT(0);  // row i's +kBlock entry: the mirror of row i2's -kBlock entry
+#pragma unroll
+        for (int s = DS; s < NS; ++s)
+            if (sn.ofs[s] == kBlock) vup = v1[s];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (sn.ofs[s] == kBlock) x1[s] = x2[DS];
+            if (sn.ofs[s] == -kBlock && !(CONT && s == 0)) {
+                x2[s] = x1[DS];
+                v2[s] = vup;
+            }
         }
     }
     double a1 = 0.0, a2 = 0.0;
