@@ -952,8 +952,28 @@ __device__ __forceinline__ void spmv_dia_full(const Stencil &sn, const VT *__res
                         v1[u] = __builtin_nontemporal_load(&base[si * kDiaChunk]);
                         v2[u] = __builtin_nontemporal_load(&base[si * kDiaChunk + kBlock]);
                     }
-                    x1[u] = x[o1 ? i + d : j1];
-                    x2[u] = x[o2 ? i2 + d : j2];
+                    // rows i and i2 are kBlock apart: at +kBlock row i's
+                    // neighbour is row i2, at -kBlock row i2's is row i
+                    // (their own x, taken below)
+                    const bool up = kExact && ds >= 0 && d == kBlock, dn = kExact && ds >= 0 && d == -kBlock;
+                    x1[u] = up ? 0.0 : x[o1 ? i + d : j1];
+                    x2[u] = dn ? 0.0 : x[o2 ? i2 + d : j2];
+                }
+                if constexpr (kExact) {
+                    if (ds >= 0) {
+                        double own1 = 0.0, own2 = 0.0;
+#pragma unroll
+                        for (int u = 0; u < kGroup; ++u)
+                            if (u == ds) {
+                                own1 = x1[u];
+                                own2 = x2[u];
+                            }
+#pragma unroll
+                        for (int u = 0; u < kGroup; ++u) {
+                            if (sn.ofs[u] == kBlock) x1[u] = own2;
+                            if (sn.ofs[u] == -kBlock) x2[u] = own1;
+                        }
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < kGroup; ++u) {
