@@ -204,12 +204,14 @@ def test_shared_pattern_96_adjoint_and_fd(orc):
     assert err <= 1e-6
 
 
-def test_single_reduction_96_batch(orc):
-    """The single-reduction recurrence on the per-iteration kernels over a
-    16-system batch on one 96^3 pattern (4 coefficient fields): a sampled
-    system against the oracle's CG (x to 1e-8 at rtol 1e-12, iterations
-    within max(2, 2%)), every system's FP64 residual, and each system's
-    iteration count within max(2, 2%) of the two-reduction CG's."""
+@pytest.mark.parametrize("method", ["cg_sr", "cg_sstep"])
+def test_single_reduction_96_batch(orc, method):
+    """The single-reduction and s-step (s = 4) recurrences on the
+    per-iteration kernels over a 16-system batch on one 96^3 pattern (4
+    coefficient fields): a sampled system against the oracle's CG (x to 1e-8
+    at rtol 1e-12, iterations within max(2, 2%)), every system's FP64
+    residual, and each system's iteration count within max(2, 2%) of the
+    two-reduction CG's."""
     m, B = 96, 16
     a0, V4, _, _ = W.shared_pattern_batch(m, 4)
     n = a0.n
@@ -218,8 +220,8 @@ def test_single_reduction_96_batch(orc):
     bs = np.stack([W.rng(4, 5, s).standard_normal(n) for s in range(B)])
     bt = t64(bs)
     kw = dict(precond="jacobi", rtol=1e-12, persistent=False)
-    x, fi, st = _lib.solve(pat, V, bt, _lib.make_opts(method="cg_sr", **kw))
-    assert st == _lib.OK and all(f["method"] == "cg_sr" for f in fi)
+    x, fi, st = _lib.solve(pat, V, bt, _lib.make_opts(method=method, **kw))
+    assert st == _lib.OK and all(f["method"] == method for f in fi)
     xc, ci, stc = _lib.solve(pat, V, bt, _lib.make_opts(method="cg", **kw))
     assert stc == _lib.OK
     assert all(iters_close(f["iters"], g["iters"]) for f, g in zip(fi, ci)), \
@@ -230,7 +232,7 @@ def test_single_reduction_96_batch(orc):
     ref = orc.cg(a0.with_values(V4[s % 4]), bs[s], precond="jacobi", rtol=1e-12)
     assert rel(x[s].cpu().numpy(), ref.x) <= 1e-8
     assert iters_close(fi[s]["iters"], ref.iters), (fi[s]["iters"], ref.iters)
-    _log("single reduction 96^3", fi[s]["iters"], ref.iters, rel(x[s].cpu().numpy(), ref.x))
+    _log(method, "96^3", fi[s]["iters"], ref.iters, rel(x[s].cpu().numpy(), ref.x))
 
 
 def test_learned_fsai_256(orc):
