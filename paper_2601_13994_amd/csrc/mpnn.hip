@@ -5,7 +5,7 @@
 //
 // Network (hidden 64, three message-passing layers, bf16 weights and
 // activations, fp32 accumulation; dense layers on the matrix cores with
-// v_mfma_f32_16x16x16_bf16):
+// gfx950's v_mfma_f32_16x16x32_bf16, K in steps of 32):
 //   f_k   = [a^_k, [j<i], [j>i], [j=i]],  a^_k = a_k / sqrt(a_ii a_jj)
 //   h0_i  = relu(sum_{k in row i} f_k W0 + b0)
 //   m_i   = sum_{k in row i} (f_k C_l) * h_{col k}            l = 1..3
@@ -26,7 +26,8 @@ namespace mp {
 
 constexpr int HID = 64, HEAD = 32, NF = 4, LAYERS = 3;
 constexpr int KH = 2 * HID + NF;  // 132 head inputs
-constexpr int KHP = 144;          // padded to 9 k-steps of 16
+constexpr int KHP = 160;          // padded to 5 k-steps of 32
+constexpr int KHT = 144;          // 9 row tiles of 16 cover the 132 inputs (weight gradient)
 
 // Packed fp32 parameter layout (master copy, Adam state, gradients).
 constexpr int OFF_W0 = 0, OFF_B0 = OFF_W0 + NF * HID;
@@ -39,8 +40,18 @@ constexpr int OFF_C2 = OFF_H2 + HEAD;
 constexpr int NPARAM = OFF_C2 + 1;
 __host__ __device__ constexpr int off_layer(int l) { return LAYER0 + (l - 1) * L_SIZE; }
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef short short8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// One 16x16x32 product on the matrix cores: lane (i, q) = (l % 16, l / 16)
+// brings A[i][8q + t] and B[8q + t][i] (t = 0..7) and holds
+// C[4q + t][i] (t = 0..3) of the accumulator.
+__device__ __forceinline__ float4_t mfma32(short8_t a, short8_t b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                   c, 0, 0, 0);
+}
+__device__ __forceinline__ short8_t ld8(const uint16_t *p) { return *reinterpret_cast<const short8_t *>(p); }
 
 // float -> bfloat16 bits, round to nearest even (NaN kept quiet).
 __device__ __forceinline__ uint16_t f2bf(float x) {
@@ -52,13 +63,14 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ __forceinline__ float rbf(float x) { return bf2f(f2bf(x)); }
 
-// Swizzled B operand of a K x N bf16 matrix for 16x16x16 MFMA: fragment
-// (ks, nt) holds, for lane l, B[16 ks + 4 (l/16) + t][16 nt + l%16], t = 0..3,
-// stored as 4 consecutive bf16 at ((ks * NT + nt) * 64 + l) * 4.
+// Swizzled B operand of a K x N bf16 matrix (K a multiple of 32) for the
+// 16x16x32 product: fragment (ks, nt) holds, for lane l,
+// B[32 ks + 8 (l/16) + t][16 nt + l%16], t = 0..7, stored as 8 consecutive
+// bf16 (one 16-byte load) at ((ks * NT + nt) * 64 + l) * 8.
 __device__ __forceinline__ void put_bfrag(uint16_t *dst, int NT, int k, int n, float v) {
-    const int ks = k / 16, kr = k % 16, q = kr / 4, t = kr % 4;
+    const int ks = k / 32, kr = k % 32, q = kr / 8, t = kr % 8;
     const int nt = n / 16, i = n % 16;
-    dst[((size_t)(ks * NT + nt) * 64 + q * 16 + i) * 4 + t] = f2bf(v);
+    dst[((size_t)(ks * NT + nt) * 64 + q * 16 + i) * 8 + t] = f2bf(v);
 }
 
 // Device copies of the weights derived from the fp32 master.
@@ -66,7 +78,7 @@ struct Weights {
     float *wq;        // [NPARAM] master with every matrix rounded to bf16
     uint16_t *Wf[3];  // W_l   as B fragments: K = 128, N = 64
     uint16_t *WTf[3]; // W_l^T as B fragments: K = 64,  N = 128
-    uint16_t *H1f;    // H1 (padded to K = 144) as B fragments, N = 32
+    uint16_t *H1f;    // H1 (padded to K = 160) as B fragments, N = 32
     uint16_t *H1Tf;   // H1^T restricted to its first 128 columns: K = 32, N = 128
 };
 
@@ -101,9 +113,10 @@ __global__ void k_mp_weights(const float *__restrict__ P, Weights w) {
 }
 
 // ---------------------------------------------------------------------------
-// Generic bf16 GEMM on the matrix cores: C[M x 16NT] = A[M x 16KS] B.
+// Generic bf16 GEMM on the matrix cores: C[M x 16NT] = A[M x 32KS] B.
 // A row r is the concatenation of A0[r][0:K0] and A1[r][0:K-K0] (bf16,
-// leading dimensions lda0/lda1, K0 a multiple of 16).  Each wave computes 16
+// leading dimensions lda0/lda1 multiples of 8, K0 a multiple of 8, so that
+// each lane's 8 operands are one aligned 16-byte load from one of them).  Each wave computes 16
 // rows; rows past M are clamped on load and skipped on store.  The epilogue
 // gets (row, col, accumulated value) for every valid element.
 // ---------------------------------------------------------------------------
@@ -122,14 +135,10 @@ __global__ __launch_bounds__(kBlock) void k_gemm(int64_t M, const uint16_t *__re
         for (int nt = 0; nt < NT; ++nt) acc[nt] = float4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const int k = ks * 16 + 4 * q;
-            const uint16_t *src = k < K0 ? A0 + ra * lda0 + k : A1 + ra * lda1 + (k - K0);
-            const short4_t a = *reinterpret_cast<const short4_t *>(src);
+            const int k = ks * 32 + 8 * q;
+            const short8_t a = ld8(k < K0 ? A0 + ra * lda0 + k : A1 + ra * lda1 + (k - K0));
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const short4_t b = *reinterpret_cast<const short4_t *>(Bf + ((size_t)(ks * NT + nt) * 64 + lane) * 4);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
-            }
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma32(a, ld8(Bf + ((size_t)(ks * NT + nt) * 64 + lane) * 8), acc[nt]);
         }
         epi(row0, q, i, acc);
     }
@@ -214,7 +223,8 @@ struct EpiHead {
 // ---------------------------------------------------------------------------
 // Weight gradients: C[K x N] += A^T B with A [M x K] (two column blocks as
 // in k_gemm) and B [M x N] (bf16).  Block b sums rows of its own contiguous
-// chunk with MFMA (A^T fragment: lane (i, q) holds A[m + 4q + t][16 kt + i])
+// chunk, 32 at a time, with MFMA (A^T fragment: lane (i, q) holds
+// A[m + 8q + t][16 kt + i], t = 0..7)
 // and writes a partial; k_sum_partials adds the partials in block order.
 // Wave w of the block owns output fragments f = w, w + 4, ... of the
 // (K/16) x (N/16) grid.
@@ -234,31 +244,32 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(int64_t M, const uint16_t *_
     float4_t acc[PER];
 #pragma unroll
     for (int f = 0; f < PER; ++f) acc[f] = float4_t{0.f, 0.f, 0.f, 0.f};
-    for (int64_t m = m_lo; m < m_hi; m += 16) {
-        short4_t av[KT], bv[NT];
+    // The wave's fragments share one column tile (NT divides the wave
+    // count), so it loads that B operand once per step and the A^T
+    // operand of each of its row tiles as it goes.
+    static_assert(kWavesPerBlock % NT == 0, "a wave's fragments must share their column tile");
+    const int nt = w % NT;
+    for (int64_t m = m_lo; m < m_hi; m += 32) {
+        short8_t bv;
 #pragma unroll
-        for (int kt = 0; kt < KT; ++kt) {
-            const int k = kt * 16 + i;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int64_t r = m + 4 * q + t;
-                uint16_t v = 0;
-                if (r < m_hi) v = k < K0 ? A0[r * lda0 + k] : A1[r * lda1 + (k - K0)];
-                av[kt][t] = (short)v;
-            }
-        }
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int64_t r = m + 4 * q + t;
-                bv[nt][t] = (short)(r < m_hi ? Bm[r * ldb + nt * 16 + i] : 0);
-            }
+        for (int t = 0; t < 8; ++t) {
+            const int64_t r = m + 8 * q + t;
+            bv[t] = (short)(r < m_hi ? Bm[r * ldb + nt * 16 + i] : 0);
         }
 #pragma unroll
         for (int f = 0; f < PER; ++f) {
             const int fr = w + f * kWavesPerBlock;
-            if (fr < NFRAG) acc[f] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[fr / NT], bv[fr % NT], acc[f], 0, 0, 0);
+            if (fr >= NFRAG) continue;
+            const int k = (fr / NT) * 16 + i;
+            short8_t av;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int64_t r = m + 8 * q + t;
+                uint16_t v = 0;
+                if (r < m_hi) v = k < K0 ? A0[r * lda0 + k] : A1[r * lda1 + (k - K0)];
+                av[t] = (short)v;
+            }
+            acc[f] = mfma32(av, bv, acc[f]);
         }
     }
     float *out = part + (size_t)blockIdx.x * (KT * 16) * (NT * 16);
@@ -427,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_mp_aggregate(Graph g, int B, const f
     }
 }
 
-// Head inputs x_k = [h3_i, h3_j, f_k, 0...] (bf16, 144 wide) for lower
+// Head inputs x_k = [h3_i, h3_j, f_k, 0...] (bf16, 160 wide) for lower
 // entries.  Four entries per wave, 16 lanes per entry, 8-byte copies.
 __global__ __launch_bounds__(kBlock) void k_mp_head_gather(Graph g, int B, const float *__restrict__ ah,
                                                            const uint16_t *__restrict__ h3, uint16_t *__restrict__ X) {
@@ -447,13 +458,17 @@ __global__ __launch_bounds__(kBlock) void k_mp_head_gather(Graph g, int B, const
         *reinterpret_cast<uint2 *>(x + HID + l16 * 4) = vj;
         float f[4];
         feats(g, ah + s * g.nnz, g.posL[kl], i, f);
-        x[2 * HID + l16] = l16 < NF ? f2bf(f[l16 < NF ? l16 : 0]) : (uint16_t)0;
+        // columns 128..159: the features, then zeros (two per lane)
+        const int c = 2 * l16;
+        const uint32_t lo = c < NF ? f2bf(f[c < NF ? c : 0]) : 0u;
+        const uint32_t hi = c + 1 < NF ? f2bf(f[c + 1 < NF ? c + 1 : 0]) : 0u;
+        *reinterpret_cast<uint32_t *>(x + 2 * HID + c) = lo | (hi << 16);
     }
 }
 
 // Inference head without the x_k buffer: the GEMM's A operand is fetched
 // straight from h3 (rows i and j of the entry) and the features, giving the
-// same bf16 operand values as k_mp_head_gather + k_gemm<9, 2>.
+// same bf16 operand values as k_mp_head_gather + k_gemm<5, 2>.
 __global__ __launch_bounds__(kBlock) void k_mp_head_fused(Graph g, int64_t M, const float *__restrict__ ah,
                                                           const uint16_t *__restrict__ h3,
                                                           const uint16_t *__restrict__ Bf, EpiHead epi) {
@@ -465,29 +480,26 @@ __global__ __launch_bounds__(kBlock) void k_mp_head_fused(Graph g, int64_t M, co
         if (ra >= M) ra = M - 1;
         const int64_t s = ra / g.nL, kl = ra - s * g.nL;
         const int32_t ni = g.rowL[kl], nj = g.colL[kl];
-        const uint16_t *hs = h3 + s * (int64_t)g.n * HID + 4 * q;
-        short4_t fa = short4_t{0, 0, 0, 0};
+        const uint16_t *hs = h3 + s * (int64_t)g.n * HID + 8 * q;
+        short8_t fa = short8_t{0, 0, 0, 0, 0, 0, 0, 0};
         if (q == 0) {
             float f[4];
             feats(g, ah + s * g.nnz, g.posL[kl], ni, f);
-            fa = short4_t{(short)f2bf(f[0]), (short)f2bf(f[1]), (short)f2bf(f[2]), (short)f2bf(f[3])};
+            fa = short8_t{(short)f2bf(f[0]), (short)f2bf(f[1]), (short)f2bf(f[2]), (short)f2bf(f[3]), 0, 0, 0, 0};
         }
         float4_t acc[2];
         acc[0] = acc[1] = float4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ks = 0; ks < 9; ++ks) {
-            short4_t a;
-            if (ks < 4)
-                a = *reinterpret_cast<const short4_t *>(hs + (int64_t)ni * HID + ks * 16);
-            else if (ks < 8)
-                a = *reinterpret_cast<const short4_t *>(hs + (int64_t)nj * HID + (ks - 4) * 16);
+        for (int ks = 0; ks < 5; ++ks) {
+            short8_t a;
+            if (ks < 2)
+                a = ld8(hs + (int64_t)ni * HID + ks * 32);
+            else if (ks < 4)
+                a = ld8(hs + (int64_t)nj * HID + (ks - 2) * 32);
             else
                 a = fa;
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                const short4_t b = *reinterpret_cast<const short4_t *>(Bf + ((size_t)(ks * 2 + nt) * 64 + lane) * 4);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
-            }
+            for (int nt = 0; nt < 2; ++nt) acc[nt] = mfma32(a, ld8(Bf + ((size_t)(ks * 2 + nt) * 64 + lane) * 8), acc[nt]);
         }
         epi(row0, q, i, acc);
     }
@@ -915,7 +927,7 @@ static hsla_status forward(hsla_handle *h, const hsla_pattern *p, int B, const d
         k_mp_aggregate<<<ga, kBlock, 0, s>>>(g, B, f.w.wq + off_layer(l) + L_C, f.ah32, f.h[l - 1], f.m[l - 1]);
         const int64_t M = B * n;
         EpiBiasReluBf16<4> epi{f.w.wq + off_layer(l) + L_B, f.h[l], M};
-        k_gemm<8, 4><<<nblocks((M + 15) / 16, kWavesPerBlock, 8192), kBlock, 0, s>>>(
+        k_gemm<4, 4><<<nblocks((M + 15) / 16, kWavesPerBlock, 8192), kBlock, 0, s>>>(
             M, f.h[l - 1], HID, f.m[l - 1], HID, HID, f.w.Wf[l - 1], epi);
     }
     if (keep) {
@@ -924,7 +936,7 @@ static hsla_status forward(hsla_handle *h, const hsla_pattern *p, int B, const d
                                                                                         f.X);
         const int64_t M = B * nL;
         EpiHead epi{f.w.wq, f.z, f.t, Ghat, p->isdiagL, nL, M};
-        k_gemm<9, 2><<<nblocks((M + 15) / 16, kWavesPerBlock, 8192), kBlock, 0, s>>>(M, f.X, KHP, f.X, KHP, KHP,
+        k_gemm<5, 2><<<nblocks((M + 15) / 16, kWavesPerBlock, 8192), kBlock, 0, s>>>(M, f.X, KHP, f.X, KHP, KHP,
                                                                                    f.w.H1f, epi);
     } else {
         const int64_t M = B * nL;
@@ -960,9 +972,9 @@ static hsla_status backward(hsla_handle *h, const hsla_pattern *p, int B, const 
     // head
     k_mp_head_bwd<<<NB_V, kBlock, 0, s>>>(g, ML, f.w.wq, dG, f.t, f.z, w.dz, w.part);
     sum_into(w.part, NB_V, 1, 2 * HEAD + 1, 1, grads + OFF_C1, s);
-    k_gemm_tn<9, 2><<<NB_TN, kBlock, 0, s>>>(ML, f.X, KHP, f.X, KHP, KHP, w.dz, HEAD, w.part);
-    sum_into(w.part, NB_TN, KHP, HEAD, KH, grads + OFF_H1, s);
-    k_gemm<2, 8><<<nblocks((ML + 15) / 16, kWavesPerBlock, 8192), kBlock, 0, s>>>(
+    k_gemm_tn<KHT / 16, 2><<<NB_TN, kBlock, 0, s>>>(ML, f.X, KHP, f.X, KHP, KHP, w.dz, HEAD, w.part);
+    sum_into(w.part, NB_TN, KHT, HEAD, KH, grads + OFF_H1, s);
+    k_gemm<1, 8><<<nblocks((ML + 15) / 16, kWavesPerBlock, 8192), kBlock, 0, s>>>(
         ML, w.dz, HEAD, w.dz, HEAD, HEAD, f.w.H1Tf, EpiStoreF32<8>{w.dX, ML});
     const int gw = nblocks(MN, kWavesPerBlock, 16384);
     k_mp_head_dh<<<gw, kBlock, 0, s>>>(g, B, w.dX, w.dh);
@@ -972,7 +984,7 @@ static hsla_status backward(hsla_handle *h, const hsla_pattern *p, int B, const 
         sum_into(w.part, NB_V, 1, HID, 1, grads + off_layer(l) + L_B, s);
         k_gemm_tn<8, 4><<<NB_TN, kBlock, 0, s>>>(MN, f.h[l - 1], HID, f.m[l - 1], HID, HID, w.dpre, HID, w.part);
         sum_into(w.part, NB_TN, 2 * HID, HID, 2 * HID, grads + off_layer(l) + L_W, s);
-        k_gemm<4, 8><<<nblocks((MN + 15) / 16, kWavesPerBlock, 8192), kBlock, 0, s>>>(
+        k_gemm<2, 8><<<nblocks((MN + 15) / 16, kWavesPerBlock, 8192), kBlock, 0, s>>>(
             MN, w.dpre, HID, w.dpre, HID, HID, f.w.WTf[l - 1], EpiStoreF32<8>{w.dhm, MN});
         k_mp_aggregate_bwd<<<NB_V, kBlock, 0, s>>>(g, B, f.w.wq + off_layer(l) + L_C, f.ah32, f.h[l - 1], w.dhm,
                                                    w.dh, w.part);
