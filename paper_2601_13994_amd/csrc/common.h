@@ -815,6 +815,15 @@ __device__ __forceinline__ void spmv_dia(const Stencil &sn, const VT *__restrict
 
 typedef double dpair __attribute__((ext_vector_type(2)));
 
+// An epilogue that derives from OwnRowsEpi reads per-row data of its own:
+// load_one(row) is issued when a step starts, together with the product's
+// loads, so that no second memory round trip follows the sum, and
+// one(row, y, loaded) finishes the row.  (Strided chunk layout of the full
+// copy; the tile walk calls it as epi(row, y).)
+struct OwnRowsEpi {};
+template <class Epi>
+constexpr bool own_rows_epi = std::is_base_of_v<OwnRowsEpi, std::remove_reference_t<Epi>>;
+
 __device__ __forceinline__ int64_t clamp_row(int64_t r, int64_t n) { return r < 0 ? 0 : r < n ? r : n - 1; }
 
 // Whether the paired row layout applies (see full_pair and sym_pair): 5, 7
@@ -914,7 +923,7 @@ __device__ __forceinline__ void spmv_dia_full(const Stencil &sn, const VT *__res
     static_assert(!UF || kExact, "the unit-diagonal copy has 5, 7 or 9 diagonals");
     constexpr int kGroup = kExact ? NS : 4;
     const ChunkWalk cw(dia_chunks(n));
-    if constexpr (kExact && std::is_same_v<VT, double>) {
+    if constexpr (kExact && std::is_same_v<VT, double> && !own_rows_epi<Epi>) {
         if (pairable<NS>(sn, n, x)) {
             for (int64_t c = cw.first; c < cw.hi; c += cw.stride) full_pair<NS, UF>(sn, dv, n, x, c, epi);
             return;
@@ -928,6 +937,14 @@ __device__ __forceinline__ void spmv_dia_full(const Stencil &sn, const VT *__res
         const int64_t i2 = i + kBlock;
         const bool one = i < n, two = i2 < n;
         const int64_t j1 = one ? i : 0, j2 = two ? i2 : 0;
+        [[maybe_unused]] auto own1 = [&] {
+            if constexpr (own_rows_epi<Epi>) return epi.load_one(j1);
+            else return 0;
+        }();
+        [[maybe_unused]] auto own2 = [&] {
+            if constexpr (own_rows_epi<Epi>) return epi.load_one(j2);
+            else return 0;
+        }();
         const uint32_t m1 = one ? (uint32_t)mask[i] : 0u;
         const uint32_t m2 = two ? (uint32_t)mask[i2] : 0u;
         const VT *__restrict__ base = dv + c * nst * kDiaChunk + threadIdx.x;
@@ -988,7 +1005,10 @@ __device__ __forceinline__ void spmv_dia_full(const Stencil &sn, const VT *__res
                 }
             }
         }
-        if constexpr (std::is_invocable_v<Epi, int64_t, double, double>) {
+        if constexpr (own_rows_epi<Epi>) {
+            if (one) epi.one(i, a1, own1);
+            if (two) epi.one(i2, a2, own2);
+        } else if constexpr (std::is_invocable_v<Epi, int64_t, double, double>) {
             if (ds < 0) {
                 c1 = x[j1];
                 c2 = x[j2];

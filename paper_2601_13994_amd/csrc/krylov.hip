@@ -459,9 +459,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_beta(Sys S, int G) {
 }
 
 // x += alpha p, then p = z + beta p with z = r (none, and Jacobi on the
-// scaled system) or the stored z (FSAI); a system that stopped in this
-// iteration takes only the x update.  XUP = false (the FSAI start, p = z):
-// no x update.
+// scaled system; FSAI runs its direction update inside the second half of
+// its apply); a system that stopped in this iteration takes only the x
+// update.  XUP = false: no x update.
 template <int PRE, bool XUP = true>
 __global__ __launch_bounds__(kBlock) void k_cg_direction(Pat A, Sys S) {
     SYS_OFFSETS(S, A)
@@ -1036,19 +1036,55 @@ __global__ __launch_bounds__(kBlock) void k_fsai_check(FPat L, Sys S, int32_t n)
     if (__syncthreads_or(bad ? 1 : 0) && threadIdx.x == 0) atomicOr(&S.st[sidx].bad_diag, 4);
 }
 
-// FSAI apply, second half: z = G^T w.
-template <int NS>
-__global__ __launch_bounds__(kBlock) void k_fsai_upper(Pat A, FPat U, Sys S) {
+// FSAI apply, second half, with CG's direction update: z = G^T w, then
+// x += alpha p and p = z + beta p row by row (z itself is never stored).
+// beta = (r.z)'/(r.z) is known by then: r.z = w.w comes from the first half.
+// XUP = false (the start, p = z): no x update.  A system that stopped with
+// its last x update pending takes only that.
+template <bool XUP>
+struct UpperDirEpi : OwnRowsEpi {
+    double *__restrict__ x;
+    double *__restrict__ p;
+    double alpha, beta;
+    struct One {
+        double x, p;
+    };
+    __device__ One load_one(int64_t i) const {
+        return {XUP ? __builtin_nontemporal_load(x + i) : 0.0, __builtin_nontemporal_load(p + i)};
+    }
+    __device__ void one(int64_t i, double z, const One &o) const {
+        if (XUP) st_nt(&x[i], o.x + alpha * o.p);
+        st_nt(&p[i], z + beta * o.p);
+    }
+    __device__ void operator()(int64_t i, double z) const { one(i, z, load_one(i)); }
+};
+
+template <int NS, bool XUP>
+__device__ __forceinline__ void fsai_upper_dir(const Pat &A, const FPat &U, const Sys &S) {
     __shared__ double lds[kWavesPerBlock][kTileCap];
     SYS_OFFSETS(S, A)
     (void)part;
-    if (stopped(st)) return;
-    const double *w = S.w + vo;
-    double *z = S.z + vo;
-    spmv_F<NS>(U, A.n, sidx, w, lds[threadIdx.x / kWave],
-               [&](int64_t row, double yv) {
-                   st_nt(&z[row], yv);
-               });
+    const bool xonly = stopped(st);
+    if (xonly && (!XUP || !st.xpend)) return;
+    double *x = S.x + vo;
+    double *p = S.p + vo;
+    const double alpha = st.alpha;
+    if (xonly) {
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * kBlock)
+            x[i] = x[i] + alpha * p[i];
+        return;
+    }
+    spmv_F<NS>(U, A.n, sidx, S.w + vo, lds[threadIdx.x / kWave], UpperDirEpi<XUP>{{}, x, p, alpha, st.beta});
+}
+
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_fsai_upper_dir(Pat A, FPat U, Sys S) {
+    fsai_upper_dir<NS, true>(A, U, S);
+}
+
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_fsai_upper_start(Pat A, FPat U, Sys S) {
+    fsai_upper_dir<NS, false>(A, U, S);
 }
 
 // Set-up: rho = r.z (p = z follows from beta = 0 and p = 0); iteration:
@@ -1693,9 +1729,8 @@ static void enqueue_iterations(const SolveCall &c, int iters, hipStream_t s, hip
                     k_cg_update<PRE_FSAI><<<gv, kBlock, 0, s>>>(c.A, c.S);
                     k_fin_beta<PRE_FSAI><<<gf, kBlock, 0, s>>>(c.S, Gv);
                     NS_LAUNCH(k_fsai_lower_dot, c.nsF, gfs, c.A, c.L, c.S);
-                    NS_LAUNCH(k_fsai_upper, c.nsF, gfs, c.A, c.U, c.S);
                     k_fin_fsai<<<gf, kBlock, 0, s>>>(c.S, Gfs, 0);
-                    k_cg_direction<PRE_FSAI><<<gv, kBlock, 0, s>>>(c.A, c.S);
+                    NS_LAUNCH(k_fsai_upper_dir, c.nsF, gfs, c.A, c.U, c.S);
                     break;
             }
         } else {
@@ -1989,9 +2024,8 @@ static hsla_status solve_core(hsla_handle *h, const Tune &tn, const Pat &A, cons
                 k_fsai_check<<<gv, kBlock, 0, s>>>(c.L, S, (int32_t)n);
                 k_fin_cg_init<PRE_FSAI><<<gf, kBlock, 0, s>>>(S, Gv, o.rtol, o.atol);
                 NS_LAUNCH(k_fsai_lower_dot, nsF, gfs, A, c.L, S);
-                NS_LAUNCH(k_fsai_upper, nsF, gfs, A, c.U, S);
                 k_fin_fsai<<<gf, kBlock, 0, s>>>(S, Gf, 1);
-                k_cg_direction<PRE_FSAI, false><<<gv, kBlock, 0, s>>>(A, S);
+                NS_LAUNCH(k_fsai_upper_start, nsF, gfs, A, c.U, S);
                 break;
         }
     } else {
