@@ -550,19 +550,42 @@ __global__ __launch_bounds__(kBlock) void k_mp_head_bwd(Graph g, int64_t M, cons
 // dh3_i = sum over lower entries k of row i of dX[k][0:64]
 //       + sum over lower entries k with column i of dX[k][64:128]
 // (the second sum walks row i of L^T, whose src gives the entry in L).
+// Four nodes per wave, 16 lanes per node, 4 channels per lane (16-byte
+// loads); each sum's entries are loaded 8 at a time and added in order.
 __global__ __launch_bounds__(kBlock) void k_mp_head_dh(Graph g, int B, const float *__restrict__ dX,
                                                        float *__restrict__ dh) {
-    const int c = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
+    const int c0 = (lane & 15) * 4;
     const int64_t total = (int64_t)B * g.n;
-    for (int64_t node = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; node < total;
-         node += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t node = wave * 4 + (lane >> 4); node < total; node += nwaves * 4) {
         const int64_t s = node / g.n;
         const int32_t i = (int32_t)(node - s * g.n);
-        const float *d = dX + s * g.nL * (2 * HID);
-        float acc = 0.f;
-        for (int32_t k = g.rpL[i]; k < g.rpL[i + 1]; ++k) acc += d[(int64_t)k * 2 * HID + c];
-        for (int32_t k = g.rpU[i]; k < g.rpU[i + 1]; ++k) acc += d[(int64_t)g.srcU[k] * 2 * HID + HID + c];
-        dh[node * HID + c] = acc;
+        const float *d = dX + s * g.nL * (2 * HID) + c0;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        auto walk = [&](int32_t lo, int32_t hi, const int32_t *src, int off) {
+            for (int32_t k0 = lo; k0 < hi; k0 += 8) {
+                float4 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (k0 + u < hi) {
+                        const int64_t e = src ? src[k0 + u] : k0 + u;
+                        v[u] = *reinterpret_cast<const float4 *>(d + e * 2 * HID + off);
+                    }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (k0 + u < hi) {
+                        acc[0] += v[u].x;
+                        acc[1] += v[u].y;
+                        acc[2] += v[u].z;
+                        acc[3] += v[u].w;
+                    }
+            }
+        };
+        walk(g.rpL[i], g.rpL[i + 1], nullptr, 0);
+        walk(g.rpU[i], g.rpU[i + 1], g.srcU, HID);
+        *reinterpret_cast<float4 *>(dh + node * HID + c0) = float4{acc[0], acc[1], acc[2], acc[3]};
     }
 }
 
@@ -590,81 +613,186 @@ __global__ __launch_bounds__(kBlock) void k_mp_relu_bwd(int64_t rows, const floa
 
 // Aggregation backward: dh_prev_j = dhm[j][0:64] + sum_{k: col k = j} gate_k *
 // dm_{row k}, walking row j of A^T; block partials of dC = sum_k f_k^T
-// (dm_{row k} * h_{col k}) (4 x 64).
+// (dm_{row k} * h_{col k}) (4 x 64).  Laid out like k_mp_aggregate: four
+// nodes per wave, 16 lanes per node, 4 channels per lane (16-byte loads of
+// dm); a row's transposed entries are loaded 8 at a time, then summed in
+// ascending order.  An entry of row j of A^T has column j in A, so its
+// features need only its row i and value.
 __global__ __launch_bounds__(kBlock) void k_mp_aggregate_bwd(Graph g, int B, const float *__restrict__ C,
                                                              const float *__restrict__ ah,
                                                              const uint16_t *__restrict__ hprev,
                                                              const float *__restrict__ dhm, float *__restrict__ dh_out,
                                                              float *__restrict__ part) {
     __shared__ float sh[kWavesPerBlock][NF * HID];
-    const int c = threadIdx.x & 63, w = threadIdx.x / kWave;
-    float Cc[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x / kWave;
+    const int c0 = (lane & 15) * 4;
+    float Cc[4][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) Cc[t] = C[t * HID + c];
-    float pC[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) Cc[t][u] = C[t * HID + c0 + u];
+    float pC[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pC[t][u] = 0.f;
     const int64_t total = (int64_t)B * g.n;
-    for (int64_t node = (int64_t)blockIdx.x * kWavesPerBlock + w; node < total; node += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t node = wave * 4 + (lane >> 4); node < total; node += nwaves * 4) {
         const int64_t s = node / g.n;
         const int32_t j = (int32_t)(node - s * g.n);
         const float *a = ah + s * g.nnz;
-        const float *dm = dhm + s * (int64_t)g.n * 2 * HID + HID;  // dm[row][c] at dm[row * 128 + c]
-        const float hj = bf2f(hprev[node * HID + c]);
-        float acc = dhm[node * 2 * HID + c];
-        for (int32_t kt = g.rpT[j]; kt < g.rpT[j + 1]; ++kt) {
-            const int32_t i = g.colT[kt];       // row of the entry in A
-            const int64_t k = g.srcT[kt];       // its position in A
-            float f[4];
-            feats(g, a, k, i, f);
-            const float dmi = dm[(int64_t)i * 2 * HID + c];
-            acc += (f[0] * Cc[0] + f[1] * Cc[1] + f[2] * Cc[2] + f[3] * Cc[3]) * dmi;
-            const float prod = dmi * hj;
+        const float *dm = dhm + s * (int64_t)g.n * 2 * HID + HID + c0;  // dm[row][c0..] at dm[row * 128]
+        const uint2 hv = *reinterpret_cast<const uint2 *>(hprev + node * HID + c0);
+        const float hj[4] = {bf2f((uint16_t)(hv.x & 0xffffu)), bf2f((uint16_t)(hv.x >> 16)),
+                             bf2f((uint16_t)(hv.y & 0xffffu)), bf2f((uint16_t)(hv.y >> 16))};
+        const float4 d0 = *reinterpret_cast<const float4 *>(dhm + node * 2 * HID + c0);
+        float acc[4] = {d0.x, d0.y, d0.z, d0.w};
+        const int32_t lo = g.rpT[j], hi = g.rpT[j + 1];
+        for (int32_t k0 = lo; k0 < hi; k0 += 8) {
+            int32_t ri[8];
+            float av[8];
+            float4 dv[8];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) pC[t] += f[t] * prod;
+            for (int u = 0; u < 8; ++u) {
+                ri[u] = j;
+                av[u] = 0.f;
+                if (k0 + u < hi) {
+                    ri[u] = g.colT[k0 + u];
+                    av[u] = a[g.srcT[k0 + u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < hi) dv[u] = *reinterpret_cast<const float4 *>(dm + (int64_t)ri[u] * 2 * HID);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (k0 + u < hi) {
+                    // features of entry (i, j): value, j < i, j > i, j = i
+                    const float f[4] = {av[u], j < ri[u] ? 1.f : 0.f, j > ri[u] ? 1.f : 0.f, j == ri[u] ? 1.f : 0.f};
+                    const float dmi[4] = {dv[u].x, dv[u].y, dv[u].z, dv[u].w};
+#pragma unroll
+                    for (int ch = 0; ch < 4; ++ch) {
+                        const float gate = f[0] * Cc[0][ch] + f[1] * Cc[1][ch] + f[2] * Cc[2][ch] + f[3] * Cc[3][ch];
+                        acc[ch] += gate * dmi[ch];
+                        const float prod = dmi[ch] * hj[ch];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) pC[t][ch] += f[t] * prod;
+                    }
+                }
+            }
         }
-        dh_out[node * HID + c] = acc;
+        *reinterpret_cast<float4 *>(dh_out + node * HID + c0) = float4{acc[0], acc[1], acc[2], acc[3]};
     }
+    // the four nodes of a wave share channels: lanes l, l + 16, l + 32, l + 48
+    // (fixed butterfly), then the waves of the block in order
 #pragma unroll
-    for (int t = 0; t < 4; ++t) sh[w][t * HID + c] = pC[t];
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pC[t][u] += __shfl_xor(pC[t][u], 16);
+            pC[t][u] += __shfl_xor(pC[t][u], 32);
+        }
+    if (lane < 16) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sh[w][t * HID + c0 + u] = pC[t][u];
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < NF * HID; e += blockDim.x) {
-        float s = 0.f;
-        for (int q = 0; q < kWavesPerBlock; ++q) s += sh[q][e];
-        part[(size_t)blockIdx.x * NF * HID + e] = s;
+        float sum = 0.f;
+        for (int q = 0; q < kWavesPerBlock; ++q) sum += sh[q][e];
+        part[(size_t)blockIdx.x * NF * HID + e] = sum;
     }
 }
 
 // Init backward: block partials of dW0 = sum_i s_i^T dpre0_i (4 x 64) and
-// db0 = sum dpre0 (64), dpre0 = bf16(dh0 * [h0 > 0]).
+// db0 = sum dpre0 (64), dpre0 = bf16(dh0 * [h0 > 0]).  Four nodes per wave,
+// 16 lanes per node, 4 channels per lane; a row's entries are loaded 8 at a
+// time and their features summed in order.
 __global__ __launch_bounds__(kBlock) void k_mp_init_bwd(Graph g, int B, const float *__restrict__ ah,
                                                         const uint16_t *__restrict__ h0, const float *__restrict__ dh0,
                                                         float *__restrict__ part) {
     __shared__ float sh[kWavesPerBlock][(NF + 1) * HID];
-    const int c = threadIdx.x & 63, w = threadIdx.x / kWave;
-    float pW[4] = {0.f, 0.f, 0.f, 0.f}, pb = 0.f;
+    const int lane = threadIdx.x & 63, w = threadIdx.x / kWave;
+    const int c0 = (lane & 15) * 4;
+    float pW[4][4], pb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        pb[u] = 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pW[t][u] = 0.f;
+    }
     const int64_t total = (int64_t)B * g.n;
-    for (int64_t node = (int64_t)blockIdx.x * kWavesPerBlock + w; node < total; node += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t node = wave * 4 + (lane >> 4); node < total; node += nwaves * 4) {
         const int64_t s = node / g.n;
         const int32_t i = (int32_t)(node - s * g.n);
-        const float dp = rbf(bf2f(h0[node * HID + c]) > 0.f ? dh0[node * HID + c] : 0.f);
+        const float *a = ah + s * g.nnz;
+        const uint2 hv = *reinterpret_cast<const uint2 *>(h0 + node * HID + c0);
+        const float4 dv = *reinterpret_cast<const float4 *>(dh0 + node * HID + c0);
+        const float hb[4] = {bf2f((uint16_t)(hv.x & 0xffffu)), bf2f((uint16_t)(hv.x >> 16)),
+                             bf2f((uint16_t)(hv.y & 0xffffu)), bf2f((uint16_t)(hv.y >> 16))};
+        const float dd[4] = {dv.x, dv.y, dv.z, dv.w};
         float sf[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int32_t k = g.rp[i]; k < g.rp[i + 1]; ++k) {
-            float f[4];
-            feats(g, ah + s * g.nnz, k, i, f);
+        const int32_t lo = g.rp[i], hi = g.rp[i + 1];
+        for (int32_t k0 = lo; k0 < hi; k0 += 8) {
+            int32_t cj[8];
+            float av[8];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) sf[t] += f[t];
+            for (int u = 0; u < 8; ++u) {
+                cj[u] = i;
+                av[u] = 0.f;
+                if (k0 + u < hi) {
+                    cj[u] = g.col[k0 + u];
+                    av[u] = a[k0 + u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < hi) {
+                    sf[0] += av[u];
+                    sf[1] += cj[u] < i ? 1.f : 0.f;
+                    sf[2] += cj[u] > i ? 1.f : 0.f;
+                    sf[3] += cj[u] == i ? 1.f : 0.f;
+                }
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) pW[t] += sf[t] * dp;
-        pb += dp;
-    }
+        for (int u = 0; u < 4; ++u) {
+            const float dp = rbf(hb[u] > 0.f ? dd[u] : 0.f);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) sh[w][t * HID + c] = pW[t];
-    sh[w][NF * HID + c] = pb;
+            for (int t = 0; t < 4; ++t) pW[t][u] += sf[t] * dp;
+            pb[u] += dp;
+        }
+    }
+    // the four nodes of a wave share channels (fixed butterfly), then the
+    // waves of the block in order
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        pb[u] += __shfl_xor(pb[u], 16);
+        pb[u] += __shfl_xor(pb[u], 32);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            pW[t][u] += __shfl_xor(pW[t][u], 16);
+            pW[t][u] += __shfl_xor(pW[t][u], 32);
+        }
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) sh[w][t * HID + c0 + u] = pW[t][u];
+            sh[w][NF * HID + c0 + u] = pb[u];
+        }
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < (NF + 1) * HID; e += blockDim.x) {
-        float s = 0.f;
-        for (int q = 0; q < kWavesPerBlock; ++q) s += sh[q][e];
-        part[(size_t)blockIdx.x * (NF + 1) * HID + e] = s;
+        float sum = 0.f;
+        for (int q = 0; q < kWavesPerBlock; ++q) sum += sh[q][e];
+        part[(size_t)blockIdx.x * (NF + 1) * HID + e] = sum;
     }
 }
 
@@ -976,8 +1104,7 @@ static hsla_status backward(hsla_handle *h, const hsla_pattern *p, int B, const 
     sum_into(w.part, NB_TN, KHT, HEAD, KH, grads + OFF_H1, s);
     k_gemm<1, 8><<<nblocks((ML + 15) / 16, kWavesPerBlock, 8192), kBlock, 0, s>>>(
         ML, w.dz, HEAD, w.dz, HEAD, HEAD, f.w.H1Tf, EpiStoreF32<8>{w.dX, ML});
-    const int gw = nblocks(MN, kWavesPerBlock, 16384);
-    k_mp_head_dh<<<gw, kBlock, 0, s>>>(g, B, w.dX, w.dh);
+    k_mp_head_dh<<<nblocks(MN, 4 * kWavesPerBlock, 16384), kBlock, 0, s>>>(g, B, w.dX, w.dh);
     // message-passing layers
     for (int l = LAYERS; l >= 1; --l) {
         k_mp_relu_bwd<<<NB_V, kBlock, 0, s>>>(MN, w.dh, f.h[l], w.dpre, w.part);
