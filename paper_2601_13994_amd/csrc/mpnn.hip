@@ -236,6 +236,13 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(int64_t M, const uint16_t *_
                                                     float *__restrict__ part) {
     constexpr int NFRAG = KT * NT;
     constexpr int PER = (NFRAG + kWavesPerBlock - 1) / kWavesPerBlock;
+    constexpr int KW = KT * 16, NW = NT * 16;  // columns of A and B the product uses
+    // 32 rows of A and B per step, staged with 16-byte coalesced loads; the
+    // MFMA operands (8 consecutive rows of one column per lane) are then
+    // read from LDS.  Rows padded by 8 elements: 16-byte aligned, and
+    // consecutive rows start on different banks.
+    __shared__ __attribute__((aligned(16))) uint16_t sa[32][KW + 8];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[32][NW + 8];
     const int lane = threadIdx.x & 63, i = lane & 15, q = lane >> 4, w = threadIdx.x / kWave;
     const int64_t chunk = (M + gridDim.x - 1) / gridDim.x;
     const int64_t m_lo = (int64_t)blockIdx.x * chunk;
@@ -245,17 +252,50 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(int64_t M, const uint16_t *_
 #pragma unroll
     for (int f = 0; f < PER; ++f) acc[f] = float4_t{0.f, 0.f, 0.f, 0.f};
     // The wave's fragments share one column tile (NT divides the wave
-    // count), so it loads that B operand once per step and the A^T
-    // operand of each of its row tiles as it goes.
+    // count), so its B operand is read once per step.
     static_assert(kWavesPerBlock % NT == 0, "a wave's fragments must share their column tile");
     const int nt = w % NT;
+    const short8_t zero8 = short8_t{0, 0, 0, 0, 0, 0, 0, 0};
+    // the next step's rows are loaded into registers while the current
+    // step's products run (a block has few waves to hide the latency with)
+    constexpr int EA = 32 * (KW / 8), EB = 32 * (NW / 8);
+    constexpr int RA = (EA + kBlock - 1) / kBlock, RB = (EB + kBlock - 1) / kBlock;
+    short8_t ra[RA], rb[RB];
+    auto fetch = [&](int64_t m) {
+#pragma unroll
+        for (int u = 0; u < RA; ++u) {
+            const int e = threadIdx.x + u * kBlock;
+            const int r = e / (KW / 8), k = (e % (KW / 8)) * 8;
+            const int64_t row = m + r;
+            ra[u] = zero8;
+            if (e < EA && row < m_hi) ra[u] = ld8(k < K0 ? A0 + row * lda0 + k : A1 + row * lda1 + (k - K0));
+        }
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            const int e = threadIdx.x + u * kBlock;
+            const int r = e / (NW / 8), k = (e % (NW / 8)) * 8;
+            const int64_t row = m + r;
+            rb[u] = zero8;
+            if (e < EB && row < m_hi) rb[u] = ld8(Bm + row * ldb + k);
+        }
+    };
+    if (m_lo < m_hi) fetch(m_lo);
     for (int64_t m = m_lo; m < m_hi; m += 32) {
+#pragma unroll
+        for (int u = 0; u < RA; ++u) {
+            const int e = threadIdx.x + u * kBlock;
+            if (e < EA) *reinterpret_cast<short8_t *>(&sa[e / (KW / 8)][(e % (KW / 8)) * 8]) = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            const int e = threadIdx.x + u * kBlock;
+            if (e < EB) *reinterpret_cast<short8_t *>(&sb[e / (NW / 8)][(e % (NW / 8)) * 8]) = rb[u];
+        }
+        __syncthreads();
+        if (m + 32 < m_hi) fetch(m + 32);
         short8_t bv;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int64_t r = m + 8 * q + t;
-            bv[t] = (short)(r < m_hi ? Bm[r * ldb + nt * 16 + i] : 0);
-        }
+        for (int t = 0; t < 8; ++t) bv[t] = (short)sb[8 * q + t][nt * 16 + i];
 #pragma unroll
         for (int f = 0; f < PER; ++f) {
             const int fr = w + f * kWavesPerBlock;
@@ -263,21 +303,17 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(int64_t M, const uint16_t *_
             const int k = (fr / NT) * 16 + i;
             short8_t av;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int64_t r = m + 8 * q + t;
-                uint16_t v = 0;
-                if (r < m_hi) v = k < K0 ? A0[r * lda0 + k] : A1[r * lda1 + (k - K0)];
-                av[t] = (short)v;
-            }
+            for (int t = 0; t < 8; ++t) av[t] = (short)sa[8 * q + t][k];
             acc[f] = mfma32(av, bv, acc[f]);
         }
+        __syncthreads();
     }
     float *out = part + (size_t)blockIdx.x * (KT * 16) * (NT * 16);
 #pragma unroll
     for (int f = 0; f < PER; ++f) {
         const int fr = w + f * kWavesPerBlock;
         if (fr >= NFRAG) continue;
-        const int kt = fr / NT, nt = fr % NT;
+        const int kt = fr / NT;
 #pragma unroll
         for (int t = 0; t < 4; ++t) out[(size_t)(kt * 16 + 4 * q + t) * (NT * 16) + nt * 16 + i] = acc[f][t];
     }
@@ -508,35 +544,59 @@ __global__ __launch_bounds__(kBlock) void k_mp_head_fused(Graph g, int64_t M, co
 // Head backward, per lower entry: dt = dg * (sigmoid(t) on the diagonal, 1
 // elsewhere), dz = bf16(dt H2 * [z > 0]); block partials laid out like the
 // parameters [c1 (32), H2 (32), c2]: dc1 = sum dz, dH2 = sum z dt, dc2 = sum dt.
+// Eight entries per wave, 8 lanes per entry, 4 channels per lane (8-byte
+// accesses of z and dz).
 __global__ __launch_bounds__(kBlock) void k_mp_head_bwd(Graph g, int64_t M, const float *__restrict__ wq,
                                                         const float *__restrict__ dg, const float *__restrict__ t,
                                                         const uint16_t *__restrict__ z, uint16_t *__restrict__ dz,
                                                         float *__restrict__ part) {
     __shared__ float sh[kWavesPerBlock][2 * HEAD + 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x / kWave;
-    const int c = lane & 31, half = lane >> 5;
-    float pH2 = 0.f, pc1 = 0.f, pc2 = 0.f;
-    const float H2c = wq[OFF_H2 + c];
-    for (int64_t e = ((int64_t)blockIdx.x * kWavesPerBlock + w) * 2 + half; e < M;
-         e += (int64_t)gridDim.x * kWavesPerBlock * 2) {
+    const int c0 = (lane & 7) * 4, sub = lane >> 3;
+    float H2c[4], pH2[4], pc1[4], pc2 = 0.f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        H2c[u] = wq[OFF_H2 + c0 + u];
+        pH2[u] = pc1[u] = 0.f;
+    }
+    for (int64_t e = ((int64_t)blockIdx.x * kWavesPerBlock + w) * 8 + sub; e < M;
+         e += (int64_t)gridDim.x * kWavesPerBlock * 8) {
         const bool d = g.isdiag[e % g.nL] != 0;
         const float tv = t[e];
         const float dt = d ? dg[e] / (1.f + expf(-tv)) : dg[e];
-        const float zz = bf2f(z[e * HEAD + c]);
-        const float dzz = zz > 0.f ? dt * H2c : 0.f;
-        const uint16_t db = f2bf(dzz);
-        dz[e * HEAD + c] = db;
-        pH2 += zz * dt;
-        pc1 += bf2f(db);
-        if (c == 0) pc2 += dt;
+        const uint2 zv = *reinterpret_cast<const uint2 *>(z + e * HEAD + c0);
+        const float zz[4] = {bf2f((uint16_t)(zv.x & 0xffffu)), bf2f((uint16_t)(zv.x >> 16)),
+                             bf2f((uint16_t)(zv.y & 0xffffu)), bf2f((uint16_t)(zv.y >> 16))};
+        uint16_t db[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            db[u] = f2bf(zz[u] > 0.f ? dt * H2c[u] : 0.f);
+            pH2[u] += zz[u] * dt;
+            pc1[u] += bf2f(db[u]);
+        }
+        uint2 o;
+        o.x = (uint32_t)db[0] | ((uint32_t)db[1] << 16);
+        o.y = (uint32_t)db[2] | ((uint32_t)db[3] << 16);
+        *reinterpret_cast<uint2 *>(dz + e * HEAD + c0) = o;
+        if ((lane & 7) == 0) pc2 += dt;
     }
-    // combine the two half-waves (fixed order), then waves in order
-    pH2 += __shfl_xor(pH2, 32);
-    pc1 += __shfl_xor(pc1, 32);
-    pc2 += __shfl_xor(pc2, 32);
-    if (lane < HEAD) {
-        sh[w][lane] = pc1;
-        sh[w][HEAD + lane] = pH2;
+    // the eight entries of a wave share channels (fixed butterfly), then
+    // the waves of the block in order
+#pragma unroll
+    for (int x = 8; x < 64; x *= 2) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pH2[u] += __shfl_xor(pH2[u], x);
+            pc1[u] += __shfl_xor(pc1[u], x);
+        }
+        pc2 += __shfl_xor(pc2, x);
+    }
+    if (lane < 8) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sh[w][c0 + u] = pc1[u];
+            sh[w][HEAD + c0 + u] = pH2[u];
+        }
     }
     if (lane == 0) sh[w][2 * HEAD] = pc2;
     __syncthreads();
