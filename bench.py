@@ -15,7 +15,7 @@ Prints one JSON line on stdout (progress goes to stderr):
              kernel streams / mean launch duration, durations from HIP events
              around every SpMV launch of profiled solves run right after the
              timed region (the timed solves replay graphs and carry no
-             events); survey_unit prices the same launches at the CSR SpMV
+             events); csr_unit prices the same launches at the CSR SpMV
              unit 12 nnz + 4(n+1) + 16n; traffic = FETCH_SIZE + WRITE_SIZE
              per launch from the committed rocprofv3 counter summary (null if
              the kernel source changed since the counters were taken)
@@ -289,7 +289,7 @@ def _profiled_spmv(pat, vals, bt, opts_kw, solves: int):
     return ms / max(launches, 1), launches, info
 
 
-def survey_spmv_bytes(n: int, nnz: int) -> int:
+def csr_unit_spmv_bytes(n: int, nnz: int) -> int:
     """The scope table's SpMV unit: CSR values, int32 column indices and row
     pointers, p gathered once and q written once."""
     return 12 * nnz + 4 * (n + 1) + 16 * n
@@ -331,7 +331,7 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
     form = form_of(pinfo, pat)
     bytes_launch = spmv_bytes(n, nnz, form, nofs)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    unit_bytes = survey_spmv_bytes(n, nnz)
+    unit_bytes = csr_unit_spmv_bytes(n, nnz)
     it_bytes = bytes_launch + 72 * n
     csr_it_bytes = pcg_iteration_bytes(n, nnz, 0)
     top = {
@@ -366,7 +366,7 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "launches_timed": launches,
             "launch_timing": (f"HIP events around every SpMV launch of {args.profile_solves} profiled solve(s) of "
                               "the same system run after the timed region"),
-            "survey_unit": {
+            "csr_unit": {
                 "bytes_per_launch": unit_bytes,
                 "achieved_GBps": unit_bytes / (avg_ms * 1e-3) / 1e9,
                 "frac": unit_bytes / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
@@ -389,8 +389,8 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
             "spmv_form": recs[-1]["spmv_form"],
             "setup_excluded_ms": {"pattern": ctx.get("setup_ms"), "autotune": tune_ms if tuning else None},
             "autotune": tuning,
-            "survey_bytes_per_iteration": csr_it_bytes,
-            "survey_equivalent_iteration_GBps": csr_it_bytes * iters / (ms_step * 1e-3) / 1e9,
+            "csr_unit_bytes_per_iteration": csr_it_bytes,
+            "csr_unit_equivalent_iteration_GBps": csr_it_bytes * iters / (ms_step * 1e-3) / 1e9,
         },
     }
     if args.csr_line:
@@ -461,7 +461,7 @@ def run_diffusion_csr(pat, vals, bt, kw, n, nnz, args):
     finally:
         pat.set_format("auto")
     it = infos[0]["iters"]
-    ub = survey_spmv_bytes(n, nnz)
+    ub = csr_unit_spmv_bytes(n, nnz)
     it_bytes = ub + 72 * n
     return {
         "workload": "the headline system with the CSR form forced (k_cg_spmv_dot<0>)",
