@@ -357,20 +357,25 @@ struct Graph {
 };
 
 // Scaled values a^ = a / sqrt(a_ii a_jj): fp64 (probe loss) and fp32 (features).
+// Sixteen lanes per node, one entry of its row per lane (rows longer than 16
+// take further turns), so that the column -> diagonal -> value loads of a
+// row's entries are in flight together.
 __global__ void k_mp_scale(Graph g, int B, const double *__restrict__ val, double *__restrict__ ah64,
                            float *__restrict__ ah32, int32_t *bad) {
+    const int l16 = threadIdx.x & 15;
     const int64_t total = (int64_t)B * g.n;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / 16);
+    for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16; e < total; e += groups) {
         const int64_t s = e / g.n;
         const int32_t i = (int32_t)(e - s * g.n);
         const double *v = val + s * g.nnz;
         const int32_t di = g.diag[i];
         const double aii = di >= 0 ? v[di] : 0.0;
         if (!(aii > 0.0)) {
-            *bad = 1;
+            if (l16 == 0) *bad = 1;
             continue;
         }
-        for (int32_t k = g.rp[i]; k < g.rp[i + 1]; ++k) {
+        for (int32_t k = g.rp[i] + l16; k < g.rp[i + 1]; k += 16) {
             const int32_t j = g.col[k];
             const int32_t dj = g.diag[j];
             const double ajj = dj >= 0 ? v[dj] : 0.0;
@@ -389,27 +394,56 @@ __device__ __forceinline__ void feats(const Graph &g, const float *ah, int64_t k
     f[3] = j == i ? 1.f : 0.f;
 }
 
-// h0 = relu(s W0 + b0), s_i = sum_{k in row i} f_k.  One wave per node, lane = channel.
+// h0 = relu(s W0 + b0), s_i = sum_{k in row i} f_k.  Four nodes per wave,
+// 16 lanes per node, 4 channels per lane; a row's entries are loaded 8 at
+// a time and their features summed in order.
 __global__ __launch_bounds__(kBlock) void k_mp_init(Graph g, int B, const float *__restrict__ wq,
                                                     const float *__restrict__ ah, uint16_t *__restrict__ h0) {
-    const int c = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
+    const int c0 = (lane & 15) * 4;
     const int64_t total = (int64_t)B * g.n;
-    for (int64_t node = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; node < total;
-         node += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t node = wave * 4 + (lane >> 4); node < total; node += nwaves * 4) {
         const int64_t s = node / g.n;
         const int32_t i = (int32_t)(node - s * g.n);
         const float *a = ah + s * g.nnz;
         float sf[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int32_t k = g.rp[i]; k < g.rp[i + 1]; ++k) {
-            float f[4];
-            feats(g, a, k, i, f);
+        const int32_t lo = g.rp[i], hi = g.rp[i + 1];
+        for (int32_t k0 = lo; k0 < hi; k0 += 8) {
+            int32_t cj[8];
+            float av[8];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) sf[t] += f[t];
+            for (int u = 0; u < 8; ++u) {
+                cj[u] = i;
+                av[u] = 0.f;
+                if (k0 + u < hi) {
+                    cj[u] = g.col[k0 + u];
+                    av[u] = a[k0 + u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < hi) {
+                    sf[0] += av[u];
+                    sf[1] += cj[u] < i ? 1.f : 0.f;
+                    sf[2] += cj[u] > i ? 1.f : 0.f;
+                    sf[3] += cj[u] == i ? 1.f : 0.f;
+                }
         }
-        float acc = wq[OFF_B0 + c];
+        uint16_t hb[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc += sf[t] * wq[OFF_W0 + t * HID + c];
-        h0[node * HID + c] = f2bf(fmaxf(acc, 0.f));
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u;
+            float acc = wq[OFF_B0 + c];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc += sf[t] * wq[OFF_W0 + t * HID + c];
+            hb[u] = f2bf(fmaxf(acc, 0.f));
+        }
+        uint2 out;
+        out.x = (uint32_t)hb[0] | ((uint32_t)hb[1] << 16);
+        out.y = (uint32_t)hb[2] | ((uint32_t)hb[3] << 16);
+        *reinterpret_cast<uint2 *>(h0 + node * HID + c0) = out;
     }
 }
 
@@ -1107,10 +1141,9 @@ static hsla_status forward(hsla_handle *h, const hsla_pattern *p, int B, const d
     const int64_t n = p->n, nL = p->nnz_lower;
     HSLA_HIP(h, hipMemsetAsync(f.bad, 0, sizeof(int32_t), s));
     k_mp_weights<<<64, kBlock, 0, s>>>(params, f.w);
-    k_mp_scale<<<nblocks(B * n, kBlock, 8192), kBlock, 0, s>>>(g, B, values, f.ah64, f.ah32, f.bad);
-    const int gw = nblocks(B * n, kWavesPerBlock, 16384);
+    k_mp_scale<<<nblocks(B * n, kBlock / 16, 16384), kBlock, 0, s>>>(g, B, values, f.ah64, f.ah32, f.bad);
     const int ga = nblocks(B * n, 4 * kWavesPerBlock, 16384);
-    k_mp_init<<<gw, kBlock, 0, s>>>(g, B, f.w.wq, f.ah32, f.h[0]);
+    k_mp_init<<<ga, kBlock, 0, s>>>(g, B, f.w.wq, f.ah32, f.h[0]);
     for (int l = 1; l <= LAYERS; ++l) {
         k_mp_aggregate<<<ga, kBlock, 0, s>>>(g, B, f.w.wq + off_layer(l) + L_C, f.ah32, f.h[l - 1], f.m[l - 1]);
         const int64_t M = B * n;
@@ -1236,7 +1269,7 @@ static hsla_status probe_loss(hsla_handle *h, const hsla_pattern *p, int B, cons
     int32_t *bad = bp.take<int32_t>(16);
     const Graph g = make_graph(p);
     HSLA_HIP(h, hipMemsetAsync(bad, 0, sizeof(int32_t), s));
-    k_mp_scale<<<nblocks(B * n, kBlock, 8192), kBlock, 0, s>>>(g, B, values, ah64, ah32, bad);
+    k_mp_scale<<<nblocks(B * n, kBlock / 16, 16384), kBlock, 0, s>>>(g, B, values, ah64, ah32, bad);
     k_perm_f64<<<nblocks(B * nnz, kBlock, 8192), kBlock, 0, s>>>(nnz, B, ah64, p->srcT, ahT);
     k_perm_f32<<<nblocks(B * nL, kBlock, 8192), kBlock, 0, s>>>(nL, B, Gh, p->srcU, GhT);
     const SpPat A{p->row_ptr, p->col, p->meta, p->ntiles, nnz};
