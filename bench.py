@@ -111,10 +111,10 @@ def form_text(form: str, nofs: int) -> str:
 
 def pcg_iteration_bytes(n: int, nnz: int, nofs: int) -> int:
     """Algorithmic bytes of one Jacobi-PCG iteration as scheduled here:
-    SpMV+dot on the scaled operator S A S, update (reads r q S, writes r:
-    32n), direction with the iteration's x update (reads r p x, writes p x:
-    40n)."""
-    return spmv_bytes(n, nnz, "diagonal" if nofs else "csr", nofs) + 72 * n
+    SpMV+dot on the scaled operator S A S, update (reads r q and the FP32
+    stop-test weights, writes r: 28n), direction with the iteration's x
+    update (reads r p x, writes p x: 40n)."""
+    return spmv_bytes(n, nnz, "diagonal" if nofs else "csr", nofs) + 68 * n
 
 
 def cpu_info() -> str:
@@ -332,7 +332,7 @@ def run_diffusion(ctx, args, dev, pat, vals, bt):
     bytes_launch = spmv_bytes(n, nnz, form, nofs)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     unit_bytes = csr_unit_spmv_bytes(n, nnz)
-    it_bytes = bytes_launch + 72 * n
+    it_bytes = bytes_launch + 68 * n  # update 28n, direction 40n
     csr_it_bytes = pcg_iteration_bytes(n, nnz, 0)
     top = {
         "metric": METRIC,
@@ -462,7 +462,7 @@ def run_diffusion_csr(pat, vals, bt, kw, n, nnz, args):
         pat.set_format("auto")
     it = infos[0]["iters"]
     ub = csr_unit_spmv_bytes(n, nnz)
-    it_bytes = ub + 72 * n
+    it_bytes = ub + 68 * n
     return {
         "workload": "the headline system with the CSR form forced (k_cg_spmv_dot<0>)",
         "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iterations": it, "status": st,
@@ -745,14 +745,14 @@ def run_adjoint(ctx, args, dev):
                               t_fwd * 1e3, int(itf.max()), B)
     sr["two_reduction_ms_per_solve"] = t_fwd * 1e3
     # per system per iteration: the operator's values in the form used (the
-    # row masks or CSR indices, shared by the batch, amortised over B) + 88n
-    # (p gathered, q written: 16n; update and direction: 72n)
+    # row masks or CSR indices, shared by the batch, amortised over B) + 84n
+    # (p gathered, q written: 16n; update and direction: 68n)
     form = form_of(fi[0], pat)
     nofs = pat.stencil[1]
     base = form.removesuffix("-paired")
     per_it = {"diagonal-half-unit": 8 * (nofs // 2) * n, "diagonal-half": 8 * (nofs // 2 + 1) * n,
               "diagonal": 8 * nofs * n,
-              "mask-tiles": 8 * nnz, "csr": 8 * nnz}[base] + 88 * n
+              "mask-tiles": 8 * nnz, "csr": 8 * nnz}[base] + 84 * n
     if not form.endswith("-paired"):
         per_it += (2 * n if form != "csr" else 4 * nnz + 4 * (n + 1)) / B
     work = float(per_it * (itf.sum() + itb.sum()) + B * (12 * nnz + 28 * n))

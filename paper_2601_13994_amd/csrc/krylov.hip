@@ -292,6 +292,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Pat A, Sys S, int use_x0) {
             if (a < 0.0) neg = true;
             const double si = a > 0.0 ? 1.0 / sqrt(a) : 1.0;
             S.dinv[vo + i] = si;
+            // the stop test's weights 1/S_i^2 = a_ii, in FP32 (z slot)
+            reinterpret_cast<float *>(S.z)[vo + i] = a > 0.0 ? (float)a : 1.0f;
             zi = si * ri;  // the scaled residual S r
             S.r[vo + i] = zi;
             S.x[vo + i] = use_x0 ? S.x[vo + i] / si : 0.0;
@@ -369,7 +371,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_alpha(Sys S, int G) {
 }
 
 // r -= alpha q; partials of r.r and r.z (Jacobi, scaled system: r holds
-// S r, so the unscaled r.r is the sum of (r_i / S_i)^2 and r.z = r.r of the
+// S r, so the unscaled r.r is the sum of r_i^2 / S_i^2 = r_i^2 a_ii, with
+// a_ii read as FP32 -- the norm only decides when to stop, and the 4-byte
+// weights take an eighth off the sweep's bytes -- and r.z = r.r of the
 // scaled vector).  x += alpha p of the same iteration is applied by the
 // direction kernel, which reads p anyway, so p is read once per iteration.
 template <int PRE>
@@ -379,63 +383,67 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Pat A, Sys S) {
     const double alpha = st.alpha;
     double *__restrict__ r = S.r + vo;
     const double *__restrict__ q = S.q + vo;
-    const double *__restrict__ dinv = S.dinv + vo;
+    const float *__restrict__ wt = reinterpret_cast<const float *>(S.z) + vo;
     double acc[2] = {0.0, 0.0};  // r.r, r.z
-    auto elem = [&](double rv, double qv, double dv) {
+    auto elem = [&](double rv, double qv, float wv) {
         const double ri = rv - alpha * qv;
         if (PRE == PRE_JACOBI) {
-            const double u = ri / dv;
-            acc[0] += u * u;
-            acc[1] += ri * ri;
+            const double rr = ri * ri;
+            acc[0] += rr * (double)wv;
+            acc[1] += rr;
         } else {
             acc[0] += ri * ri;
         }
         return ri;
     };
-    if (al16(r) && al16(q) && (PRE != PRE_JACOBI || al16(dinv))) {
-        const dpair one = {1.0, 1.0};
+    typedef float fpair __attribute__((ext_vector_type(2)));
+    if (al16(r) && al16(q) && (PRE != PRE_JACOBI || ((uintptr_t)wt & 7u) == 0)) {
+        const fpair one = {1.0f, 1.0f};
         PAIR_LOOP_BEGIN(A.n / 2)
-                dpair rv[2], qv[2], dv[2];
+                dpair rv[2], qv[2];
+                fpair wv[2];
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     const int64_t e = 2 * (i_ + j * S_);
                     rv[j] = ldp(r + e);
                     qv[j] = ldp(q + e);
-                    dv[j] = PRE == PRE_JACOBI ? ldp(dinv + e) : one;
+                    wv[j] = PRE == PRE_JACOBI ? __builtin_nontemporal_load((const fpair *)(wt + e)) : one;
                 }
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     dpair o;
-                    o.x = elem(rv[j].x, qv[j].x, dv[j].x);
-                    o.y = elem(rv[j].y, qv[j].y, dv[j].y);
+                    o.x = elem(rv[j].x, qv[j].x, wv[j].x);
+                    o.y = elem(rv[j].y, qv[j].y, wv[j].y);
                     stp(r + 2 * (i_ + j * S_), o);
                 }
         PAIR_LOOP_TAIL
                 const int64_t e = 2 * i_;
-                const dpair rv = ldp(r + e), qv = ldp(q + e), dv = PRE == PRE_JACOBI ? ldp(dinv + e) : one;
+                const dpair rv = ldp(r + e), qv = ldp(q + e);
+                const fpair wv = PRE == PRE_JACOBI ? __builtin_nontemporal_load((const fpair *)(wt + e)) : one;
                 dpair o;
-                o.x = elem(rv.x, qv.x, dv.x);
-                o.y = elem(rv.y, qv.y, dv.y);
+                o.x = elem(rv.x, qv.x, wv.x);
+                o.y = elem(rv.y, qv.y, wv.y);
                 stp(r + e, o);
         PAIR_LOOP_END
         if ((A.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
             const int64_t e = A.n - 1;
-            r[e] = elem(r[e], q[e], PRE == PRE_JACOBI ? dinv[e] : 1.0);
+            r[e] = elem(r[e], q[e], PRE == PRE_JACOBI ? wt[e] : 1.0f);
         }
     } else {
         GRID_LOOP_BEGIN(A.n)
-                double rv[4], qv[4], dv[4];
+                double rv[4], qv[4];
+                float wv[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int64_t e = i_ + j * S_;
                     rv[j] = r[e];
                     qv[j] = q[e];
-                    dv[j] = PRE == PRE_JACOBI ? dinv[e] : 1.0;
+                    wv[j] = PRE == PRE_JACOBI ? wt[e] : 1.0f;
                 }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) r[i_ + j * S_] = elem(rv[j], qv[j], dv[j]);
+                for (int j = 0; j < 4; ++j) r[i_ + j * S_] = elem(rv[j], qv[j], wv[j]);
         GRID_LOOP_TAIL
-                r[i_] = elem(r[i_], q[i_], PRE == PRE_JACOBI ? dinv[i_] : 1.0);
+                r[i_] = elem(r[i_], q[i_], PRE == PRE_JACOBI ? wt[i_] : 1.0f);
         GRID_LOOP_END
     }
     if (PRE == PRE_NONE) acc[1] = acc[0];
